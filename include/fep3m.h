@@ -1,0 +1,153 @@
+/*
+ * fep3m.h - C ABI of the MI355X finite-element P3M library.
+ *
+ * Computes periodic 1/R potentials and energies of N point charges in the
+ * cube [0, L]^3 by the finite-element P3M method of Beams, Olson & Freund
+ * ("A Finite Element Based P3M Method for N-body Problems"):
+ *
+ *   Phi_i = sum_n sum'_j Q_j / |x_i - x_j + n L|            (eq. potential)
+ *   U     = 1/2 sum_i Q_i Phi_i                             (eq. potentialenergy)
+ *
+ * split as Phi = Phi_sr + Phi_sm (eq. phisplit) with polynomial screens
+ * (Section 2.1): a near-field pair sum minus the potential of the screens in
+ * the (2 n_sr + 1)^3 block of elements around each charge (eq. sc, the
+ * self term of Section 2.4 included), plus an order-p finite element
+ * solution of the periodic Poisson problem for the screens (Section 2.2),
+ * evaluated at the charges (eq. evalsmooth).  The screen is the
+ * one-element-support variant of the Discussion (Section 5) with degree q;
+ * the mesh uses order p = q + 2.  Screen-potential tables are order-p
+ * Dirichlet finite element solutions on a larger box (Remark, Section 4).
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer on the context's device,
+ *     owned by the caller; the library never frees or retains it.
+ *   - x is N x 3, xyz interleaved (x[3 i + k]); Q, Phi are length N;
+ *     F is N x 3 interleaved.  Outputs are in the caller's particle order.
+ *   - Positions may be any finite reals; they are wrapped periodically.
+ *   - Charges must be neutral: |sum Q| <= 1e-10 sum |Q| (the periodic
+ *     problem is only solvable for neutral charge, Section 2.2).
+ *   - Calls are ordered on the context's stream (default: the null stream)
+ *     and have completed when they return.
+ *   - A context is not thread safe; use one context per stream.
+ *   - Functions return FEP3M_OK (0) or a negative status; no exception
+ *     crosses the ABI.  fep3m_last_error() gives a message for the last
+ *     failure on a context.
+ */
+#ifndef FEP3M_H
+#define FEP3M_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fep3m_ctx fep3m_ctx;
+
+enum {
+  FEP3M_OK = 0,
+  FEP3M_ERR_ARG = -1,           /* invalid argument (size, pointer, option)        */
+  FEP3M_ERR_NOT_NEUTRAL = -2,   /* |sum Q| > 1e-10 sum |Q|                         */
+  FEP3M_ERR_NONFINITE = -3,     /* NaN or Inf in x or Q                            */
+  FEP3M_ERR_NOT_CONVERGED = -4, /* mesh solve missed mg_rtol within mg_max_iter     */
+  FEP3M_ERR_DEVICE = -5,        /* HIP runtime error                               */
+  FEP3M_ERR_OOM = -6,           /* device allocation failed                        */
+  FEP3M_ERR_UNSUPPORTED = -7    /* valid request this build does not implement      */
+};
+
+enum {
+  FEP3M_PRECISION_FP64 = 0,     /* every stage in float64                          */
+  FEP3M_PRECISION_MIXED = 1     /* float32 near field and interpolation with
+                                   compensated per-particle sums; float64 mesh
+                                   solve norms, coarse solve, projections and U   */
+};
+
+typedef struct {
+  int32_t n_sr;          /* near block radius in elements (default 3: 7^3 block,
+                            the paper's short-range list, Section 4)             */
+  int32_t precision;     /* FEP3M_PRECISION_*                                    */
+  double  mg_rtol;       /* relative residual target of the mesh solve (1e-12)   */
+  int32_t mg_max_iter;   /* PCG iteration cap (60)                               */
+  int32_t cheb_degree;   /* Chebyshev smoothing degree per V-cycle side (3)      */
+  int32_t table_box;     /* elements per axis of the table domain, odd,
+                            > 2 n_sr + 1 (default 2 n_sr + 9)                    */
+} fep3m_options;
+
+typedef struct {
+  int32_t mg_iterations;     /* PCG iterations of the last mesh solve            */
+  double  mg_rel_residual;   /* ||b - K phi|| / ||b|| reached                     */
+  int64_t near_pairs;        /* ordered near pairs (i, j), j != i, of the last call */
+  int32_t max_per_element;   /* largest element occupancy of the last call        */
+  int32_t mg_levels;         /* levels of the multigrid hierarchy                */
+  double  create_seconds;    /* wall time of create (tables, hierarchy)           */
+} fep3m_stats;
+
+/* Fill *opt with the defaults listed above.  Returns FEP3M_ERR_ARG on NULL. */
+int fep3m_default_options(fep3m_options *opt);
+
+/* Create a context for N charges in the periodic cube [0, L]^3 meshed by
+ * dims[0] x dims[1] x dims[2] elements (cubic meshes only: all three equal),
+ * one-element screens of degree q, mesh order p = q + 2.  q = 3 (the
+ * lowest degree whose one-element screen cancels monopole and dipole) is
+ * implemented; other degrees return FEP3M_ERR_UNSUPPORTED.
+ * Precomputes the 1-D element matrices, screens, near-field tables and the
+ * multigrid hierarchy, and allocates every device buffer the evaluation
+ * needs.  Errors: FEP3M_ERR_ARG for L <= 0 or non-finite, N < 2,
+ * dims < 2 n_sr + 1 or unequal, q out of range, bad options;
+ * FEP3M_ERR_OOM, FEP3M_ERR_DEVICE.  *out is NULL on failure. */
+int fep3m_create(double L, int64_t N, const int32_t dims[3], int32_t q, fep3m_ctx **out);
+int fep3m_create_ex(double L, int64_t N, const int32_t dims[3], int32_t q,
+                    const fep3m_options *opt, fep3m_ctx **out);
+
+/* Order subsequent calls on the given hipStream_t (NULL: null stream). */
+int fep3m_set_stream(fep3m_ctx *ctx, void *hip_stream);
+
+/* Phi[i] for every charge (eq. potential evaluated by the method). */
+int fep3m_potential(fep3m_ctx *ctx, const double *x, const double *Q, double *Phi);
+
+/* Phi as above and U = 1/2 sum Q_i Phi_i written to U[0] (device pointer,
+ * one double); the sum is a fixed-order float64 tree. */
+int fep3m_energy(fep3m_ctx *ctx, const double *x, const double *Q, double *Phi, double *U);
+
+/* Copy an internal stage of the last evaluation to the device buffer `out`
+ * of `out_bytes` bytes (test and diagnostic use).  Stages:
+ *   0 perm     int32  [N]        caller index of each sorted slot
+ *   1 start    int32  [n^3 + 1]  first sorted slot of each element
+ *   2 C        double [n^3 * 8]  element screen moments (element units)
+ *   3 b        double [(p n)^3]  load vector after projection ([z][y][x])
+ *   4 phi      double [(p n)^3]  mesh potential, zero mean (element units)
+ *   5 Phi_p    double [N]        near pair sum, caller order, physical units
+ *   6 Phi_m    double [N]        mesh minus near-screen term, caller order
+ *   7 T        double [8 * (2 n_sr + 1)^3 * (p + 1)^3]  tables (element units)
+ * Returns FEP3M_ERR_ARG when out_bytes is too small or the stage unknown. */
+int fep3m_debug_stage(fep3m_ctx *ctx, int32_t stage, void *out, int64_t out_bytes);
+
+/* Number of bytes fep3m_debug_stage needs for a stage (0 if unknown). */
+int64_t fep3m_stage_bytes(const fep3m_ctx *ctx, int32_t stage);
+
+/* Counters of the last call. */
+int fep3m_get_stats(const fep3m_ctx *ctx, fep3m_stats *stats);
+
+void fep3m_destroy(fep3m_ctx *ctx);
+
+/* Message of the last failure on ctx ("" if none); valid until the next call. */
+const char *fep3m_last_error(const fep3m_ctx *ctx);
+
+/* Static description of a status code. */
+const char *fep3m_status_string(int status);
+
+/* The create-time near-field tables on the host (no device needed), for
+ * inspection and tests: order-p Dirichlet FE solutions of the basis screens
+ * on a box of `box` elements (Remark, Section 4), element units, layout as
+ * debug stage 7: T[a][D][m], a = ax + 2 ay + 4 az, D the target-minus-source
+ * element offset in [-n_sr, n_sr]^3 (x fastest), m the node (x fastest).
+ * out (host memory, caller-owned) must hold out_len >= 8 (2 n_sr + 1)^3
+ * (q + 3)^3 doubles.  Returns FEP3M_ERR_ARG for q != 3, n_sr outside 1..3,
+ * an even box or box <= 2 n_sr + 1, or a short buffer. */
+int fep3m_host_tables(int32_t q, int32_t n_sr, int32_t box, double *out, int64_t out_len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEP3M_H */

@@ -1,0 +1,184 @@
+"""MI355X finite-element P3M: Python binding of libfep3m.so.
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+kernels of the C library (include/fep3m.h).  PyTorch provides device memory
+and the current HIP stream.  If the library has not been built the import
+still succeeds but every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfep3m.so")
+
+OK = 0
+ERR_ARG = -1
+ERR_NOT_NEUTRAL = -2
+ERR_NONFINITE = -3
+ERR_NOT_CONVERGED = -4
+ERR_DEVICE = -5
+ERR_OOM = -6
+ERR_UNSUPPORTED = -7
+
+PRECISION_FP64 = 0
+PRECISION_MIXED = 1
+
+STAGES = {"perm": 0, "start": 1, "C": 2, "b": 3, "phi": 4, "Phi_p": 5, "Phi_m": 6, "T": 7}
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("n_sr", ctypes.c_int32), ("precision", ctypes.c_int32), ("mg_rtol", ctypes.c_double),
+                ("mg_max_iter", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("table_box", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("mg_iterations", ctypes.c_int32), ("mg_rel_residual", ctypes.c_double),
+                ("near_pairs", ctypes.c_int64), ("max_per_element", ctypes.c_int32),
+                ("mg_levels", ctypes.c_int32), ("create_seconds", ctypes.c_double)]
+
+
+class FEP3MError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fep3m status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises if it is missing: no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1503_08509_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.fep3m_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.fep3m_create.argtypes = [dp, i64, ctypes.POINTER(i32), i32, ctypes.POINTER(vp)]
+        L.fep3m_create_ex.argtypes = [dp, i64, ctypes.POINTER(i32), i32, ctypes.POINTER(Options), ctypes.POINTER(vp)]
+        L.fep3m_set_stream.argtypes = [vp, vp]
+        L.fep3m_potential.argtypes = [vp, vp, vp, vp]
+        L.fep3m_energy.argtypes = [vp, vp, vp, vp, vp]
+        L.fep3m_debug_stage.argtypes = [vp, i32, vp, i64]
+        L.fep3m_stage_bytes.argtypes = [vp, i32]
+        L.fep3m_stage_bytes.restype = i64
+        L.fep3m_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.fep3m_destroy.argtypes = [vp]
+        L.fep3m_destroy.restype = None
+        L.fep3m_last_error.argtypes = [vp]
+        L.fep3m_last_error.restype = ctypes.c_char_p
+        L.fep3m_status_string.argtypes = [ctypes.c_int]
+        L.fep3m_status_string.restype = ctypes.c_char_p
+        L.fep3m_host_tables.argtypes = [i32, i32, i32, ctypes.POINTER(dp), i64]
+        _lib = L
+    return _lib
+
+
+def default_options():
+    o = Options()
+    lib().fep3m_default_options(ctypes.byref(o))
+    return o
+
+
+def host_tables(q=3, n_sr=3, box=None):
+    """Near-field tables from the library's create-time precompute (host)."""
+    box = 2 * n_sr + 9 if box is None else box
+    p = q + 2
+    S = 2 * n_sr + 1
+    out = np.zeros(8 * S**3 * (p + 1) ** 3)
+    st = lib().fep3m_host_tables(q, n_sr, box, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size)
+    if st != OK:
+        raise FEP3MError(st, lib().fep3m_status_string(st).decode())
+    return out.reshape(8, S**3, (p + 1) ** 3)
+
+
+class Context:
+    """One FE-P3M configuration (L, N, n^3 elements, screen degree q)."""
+
+    def __init__(self, L, N, n, q=3, **opts):
+        import torch  # device memory and streams only
+
+        self._torch = torch
+        o = default_options()
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise TypeError(f"unknown option {k}")
+            setattr(o, k, v)
+        dims = (ctypes.c_int32 * 3)(n, n, n)
+        h = ctypes.c_void_p()
+        st = lib().fep3m_create_ex(float(L), int(N), dims, int(q), ctypes.byref(o), ctypes.byref(h))
+        if st != OK:
+            raise FEP3MError(st, lib().fep3m_last_error(None).decode() or lib().fep3m_status_string(st).decode())
+        self._h = h
+        self.L, self.N, self.n, self.q = float(L), int(N), int(n), int(q)
+        self.options = o
+
+    def _check(self, st):
+        if st != OK:
+            msg = lib().fep3m_last_error(self._h).decode() or lib().fep3m_status_string(st).decode()
+            raise FEP3MError(st, msg)
+
+    def _prep(self, x, Q):
+        t = self._torch
+        if not (isinstance(x, t.Tensor) and isinstance(Q, t.Tensor)):
+            raise TypeError("x and Q must be torch tensors on the GPU")
+        if x.device.type != "cuda" or Q.device.type != "cuda":
+            raise ValueError("x and Q must be device tensors")
+        if x.dtype != t.float64 or Q.dtype != t.float64:
+            raise TypeError("x and Q must be float64")
+        if tuple(x.shape) != (self.N, 3) or tuple(Q.shape) != (self.N,):
+            raise ValueError(f"expected x [{self.N}, 3] and Q [{self.N}]")
+        x = x.contiguous()
+        Q = Q.contiguous()
+        self._check(lib().fep3m_set_stream(self._h, ctypes.c_void_p(t.cuda.current_stream(x.device).cuda_stream)))
+        return x, Q
+
+    def potential(self, x, Q):
+        x, Q = self._prep(x, Q)
+        Phi = self._torch.empty(self.N, dtype=self._torch.float64, device=x.device)
+        self._check(lib().fep3m_potential(self._h, x.data_ptr(), Q.data_ptr(), Phi.data_ptr()))
+        return Phi
+
+    def energy(self, x, Q):
+        x, Q = self._prep(x, Q)
+        t = self._torch
+        Phi = t.empty(self.N, dtype=t.float64, device=x.device)
+        U = t.empty(1, dtype=t.float64, device=x.device)
+        self._check(lib().fep3m_energy(self._h, x.data_ptr(), Q.data_ptr(), Phi.data_ptr(), U.data_ptr()))
+        return Phi, U[0]
+
+    def stage(self, name, device="cuda"):
+        t = self._torch
+        sid = STAGES[name]
+        nbytes = lib().fep3m_stage_bytes(self._h, sid)
+        dtype = t.int32 if name in ("perm", "start") else t.float64
+        out = t.empty(nbytes // (4 if dtype == t.int32 else 8), dtype=dtype, device=device)
+        self._check(lib().fep3m_debug_stage(self._h, sid, out.data_ptr(), nbytes))
+        return out
+
+    def stats(self):
+        s = Stats()
+        self._check(lib().fep3m_get_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fep3m_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,617 @@
+// Context, pipeline orchestration and the C ABI (include/fep3m.h).
+//
+// Per call (Algorithm 1): bin and sort the charges by element, form the
+// per-element screen moments, assemble the load, solve the periodic mesh
+// problem by multigrid-preconditioned conjugate gradients, then evaluate
+// the near-screen field, the near-pair sum and the interpolation, and
+// combine.  Every buffer is allocated at create; a call allocates nothing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "fep3m.h"
+#include "host_fe.hpp"
+#include "host_tables.hpp"
+#include "kernels.hpp"
+
+using namespace fep3m;
+
+namespace {
+
+struct Status : std::runtime_error {
+  int code;
+  Status(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char *what) {
+  if (e == hipErrorOutOfMemory) throw Status(FEP3M_ERR_OOM, std::string(what) + ": out of device memory");
+  if (e != hipSuccess) throw Status(FEP3M_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+T *dalloc(size_t count, const char *what) {
+  void *p = nullptr;
+  hip_check(hipMalloc(&p, count * sizeof(T) + 64), what);
+  return static_cast<T *>(p);
+}
+
+struct MGLevel {
+  LevelOp op{};
+  size_t ndof = 0;
+  double *x = nullptr, *x2 = nullptr, *d = nullptr, *f = nullptr, *r = nullptr;
+  double lmax = 0.0;
+};
+
+}  // namespace
+
+struct fep3m_ctx {
+  // configuration
+  double L = 1.0, h = 1.0;
+  int64_t N = 0;
+  int n = 0, q = 3, p = 5, d = 1, nsr = 3, B = 15;
+  fep3m_options opt{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  fep3m_stats stats{};
+  std::vector<void *> allocs;
+
+  // precompute
+  std::vector<double> T_host;
+  double *T = nullptr, *gw = nullptr, *w1 = nullptr;
+  GllBasis bas{};
+
+  // particles
+  double *gtmp = nullptr, *sg = nullptr, *sQ = nullptr;
+  int *elem = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *tmp = nullptr, *perm = nullptr;
+  int *flags = nullptr, *maxcount = nullptr;
+  unsigned long long *paircount = nullptr;
+  double *C = nullptr, *Wel = nullptr, *phip_s = nullptr, *phim_s = nullptr, *phi_s = nullptr;
+  double *partial = nullptr, *scal = nullptr;
+  size_t partial_len = 0;
+  double *host_scal = nullptr;  // pinned
+
+  // mesh
+  std::vector<MGLevel> lv;
+  std::vector<Transfer> tr;
+  double *coarseV = nullptr, *coarseLam = nullptr;
+  int coarseP = 0;
+  double *b = nullptr, *sol = nullptr, *rr = nullptr, *pv = nullptr, *qv = nullptr;
+
+  template <class T>
+  T *alloc(size_t count, const char *what) {
+    T *p = dalloc<T>(count, what);
+    allocs.push_back(p);
+    return p;
+  }
+  ~fep3m_ctx() {
+    for (void *p : allocs) (void)hipFree(p);
+    if (host_scal) (void)hipHostFree(host_scal);
+  }
+  void check_launch(const char *what) { hip_check(hipGetLastError(), what); }
+  void sync(const char *what) { hip_check(hipStreamSynchronize(stream), what); }
+
+  // reduce `count` partials to scal[slot] and return it on the host
+  double reduce_host(int count, const double *part, int slot_) {
+    launch_sum_partials(stream, count, part, scal + slot_);
+    hip_check(hipMemcpyAsync(host_scal, scal + slot_, sizeof(double), hipMemcpyDeviceToHost, stream), "copy scalar");
+    sync("reduce");
+    return host_scal[0];
+  }
+
+  void build(double L_, int64_t N_, int n_, int q_, const fep3m_options &o);
+  void build_mg();
+  void estimate_spectra();
+  void vcycle(int l, const double *f);
+  void cheb_smooth(int l, const double *f, bool zero_start);
+  void solve();
+  void evaluate(const double *x, const double *Qc, double *Phi, double *U);
+};
+
+// ----------------------------------------------------------------- create
+
+void fep3m_ctx::build(double L_, int64_t N_, int n_, int q_, const fep3m_options &o) {
+  auto t0 = std::chrono::steady_clock::now();
+  L = L_;
+  N = N_;
+  n = n_;
+  q = q_;
+  p = q + 2;
+  d = q - 2;
+  opt = o;
+  nsr = o.n_sr;
+  B = o.table_box;
+  h = L / n;
+
+  Screen1D scr = make_screen(q);
+  compute_tables(p, scr, nsr, B, T_host);
+  Mat g = load_weights(p, scr);
+  Mat ke, me;
+  element_matrices(p, ke, me);
+  std::vector<double> gwh(size_t(d + 1) * (p + 1)), w1h(p);
+  for (int l = 0; l <= d; ++l)
+    for (int k = 0; k <= p; ++k) gwh[l * (p + 1) + k] = g(l, k);
+  for (int k = 0; k < p; ++k) {  // (M1 1) at local index k (k = 0 collects both elements)
+    double s = 0.0;
+    for (int j = 0; j <= p; ++j) s += me(k, j);
+    if (k == 0)
+      for (int j = 0; j <= p; ++j) s += me(p, j);
+    w1h[k] = s;
+  }
+  Vec nodes = gll_nodes(p);
+  for (int a = 0; a <= p; ++a) {
+    double den = 1.0;
+    for (int j = 0; j <= p; ++j)
+      if (j != a) den *= (nodes[a] - nodes[j]);
+    bas.x[a] = nodes[a];
+    bas.w[a] = 1.0 / den;
+  }
+
+  const int M = n * n * n;
+  T = alloc<double>(T_host.size(), "tables");
+  gw = alloc<double>(gwh.size(), "load weights");
+  w1 = alloc<double>(w1h.size(), "mass ones");
+  hip_check(hipMemcpy(T, T_host.data(), T_host.size() * sizeof(double), hipMemcpyHostToDevice), "upload tables");
+  hip_check(hipMemcpy(gw, gwh.data(), gwh.size() * sizeof(double), hipMemcpyHostToDevice), "upload weights");
+  hip_check(hipMemcpy(w1, w1h.data(), w1h.size() * sizeof(double), hipMemcpyHostToDevice), "upload weights");
+
+  gtmp = alloc<double>(3 * size_t(N), "positions");
+  sg = alloc<double>(3 * size_t(N), "sorted positions");
+  sQ = alloc<double>(size_t(N), "sorted charges");
+  elem = alloc<int>(size_t(N), "elements");
+  slot = alloc<int>(size_t(N), "slots");
+  tmp = alloc<int>(size_t(N), "sort scratch");
+  perm = alloc<int>(size_t(N), "permutation");
+  count = alloc<int>(size_t(M), "counts");
+  start = alloc<int>(size_t(M) + 1, "element starts");
+  flags = alloc<int>(4, "flags");
+  maxcount = alloc<int>(4, "max count");
+  paircount = alloc<unsigned long long>(2, "pair count");
+  C = alloc<double>(size_t(M) * 8, "moments");
+  Wel = alloc<double>(size_t(M) * (p + 1) * (p + 1) * (p + 1), "element field");
+  phip_s = alloc<double>(size_t(N), "pair potential");
+  phim_s = alloc<double>(size_t(N), "mesh potential");
+  phi_s = alloc<double>(size_t(N), "potential");
+  partial_len = size_t(4 * kRedBlocks) + 64;
+  scal = alloc<double>(64, "scalars");
+  hip_check(hipHostMalloc(reinterpret_cast<void **>(&host_scal), 64 * sizeof(double), hipHostMallocDefault),
+            "pinned scalars");
+
+  build_mg();
+  // partials serve every two-stage reduction: the fixed reduction grids and
+  // the per-tile partials of the fine-level operator
+  partial_len = std::max(partial_len, size_t(apply_blocks(lv[0].op)) + 64);
+  partial = alloc<double>(partial_len, "partials");
+  estimate_spectra();
+  auto t1 = std::chrono::steady_clock::now();
+  stats.create_seconds = std::chrono::duration<double>(t1 - t0).count();
+  stats.mg_levels = int(lv.size());
+}
+
+static LevelOp make_levelop(int p, int n) {
+  LevelOp op{};
+  op.p = p;
+  op.n = n;
+  op.P = p * n;
+  Mat ke, me;
+  element_matrices(p, ke, me);
+  for (int a = 0; a <= p; ++a)
+    for (int b = 0; b <= p; ++b) {
+      op.ke[a * (p + 1) + b] = ke(a, b);
+      op.me[a * (p + 1) + b] = me(a, b);
+    }
+  for (int k = 0; k < p; ++k) {
+    op.dk[k] = ke(k, k) + (k == 0 ? ke(p, p) : 0.0);
+    op.dm[k] = me(k, k) + (k == 0 ? me(p, p) : 0.0);
+  }
+  return op;
+}
+
+static Transfer make_transfer(int pf, int nf, int pc, int nc) {
+  Transfer t{};
+  t.pf = pf; t.nf = nf; t.Pf = pf * nf;
+  t.pc = pc; t.nc = nc; t.Pc = pc * nc;
+  t.r = nf / nc;
+  t.ns = t.r * pf;
+  Vec gf = gll_nodes(pf), gc = gll_nodes(pc);
+  std::vector<double> l(pc + 1);
+  for (int s = 0; s < t.ns; ++s) {
+    const int fe = s / pf, k = s % pf;
+    const double pos = (fe + 0.5 + gf[k]) / t.r - 0.5;
+    lagrange(gc, pos, l.data(), nullptr);
+    for (int j = 0; j <= pc; ++j) t.w[s * (pc + 1) + j] = (std::fabs(l[j]) < 1e-15 ? 0.0 : l[j]);
+  }
+  return t;
+}
+
+void fep3m_ctx::build_mg() {
+  std::vector<std::pair<int, int>> hier;
+  hier.push_back({p, n});
+  if (p > 3) hier.push_back({3, n});
+  hier.push_back({1, n});
+  int nc = n;
+  while (nc > 4 && nc % 2 == 0) { nc /= 2; hier.push_back({1, nc}); }
+  while (nc > 6 && nc % 3 == 0) { nc /= 3; hier.push_back({1, nc}); }
+  if (size_t(nc) * nc * nc > 4096)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "mesh size leaves a coarse grid above 16^3 elements (n must coarsen by 2 or 3)");
+  for (auto &pr : hier) {
+    MGLevel L_;
+    L_.op = make_levelop(pr.first, pr.second);
+    L_.ndof = size_t(L_.op.P) * L_.op.P * L_.op.P;
+    lv.push_back(L_);
+  }
+  for (size_t i = 0; i + 1 < hier.size(); ++i)
+    tr.push_back(make_transfer(hier[i].first, hier[i].second, hier[i + 1].first, hier[i + 1].second));
+  for (size_t i = 0; i < lv.size(); ++i) {
+    MGLevel &L_ = lv[i];
+    L_.x = alloc<double>(L_.ndof, "mg x");
+    L_.f = (i == 0) ? nullptr : alloc<double>(L_.ndof, "mg f");
+    if (i + 1 < lv.size()) {
+      L_.x2 = alloc<double>(L_.ndof, "mg x2");
+      L_.d = alloc<double>(L_.ndof, "mg d");
+      L_.r = alloc<double>(L_.ndof, "mg r");
+    }
+  }
+  const size_t nd0 = lv[0].ndof;
+  b = alloc<double>(nd0, "load");
+  sol = alloc<double>(nd0, "phi");
+  rr = alloc<double>(nd0, "pcg r");
+  pv = alloc<double>(nd0, "pcg p");
+  qv = alloc<double>(nd0, "pcg q");
+  // coarse level: 1-D periodic pencil K1 V = M1 V Lambda
+  {
+    const LevelOp &op = lv.back().op;
+    Mat K1, M1;
+    assemble_1d(op.p, op.n, true, K1, M1);
+    Vec lam;
+    Mat V;
+    sym_gen_eig(K1, M1, lam, V);
+    lam[0] = 0.0;
+    coarseP = op.P;
+    coarseV = alloc<double>(V.a.size(), "coarse V");
+    coarseLam = alloc<double>(lam.size(), "coarse lambda");
+    hip_check(hipMemcpy(coarseV, V.a.data(), V.a.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+    hip_check(hipMemcpy(coarseLam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+  }
+}
+
+void fep3m_ctx::estimate_spectra() {
+  // largest eigenvalue of D^-1 K per smoothed level (power iteration)
+  for (size_t i = 0; i + 1 < lv.size(); ++i) {
+    MGLevel &L_ = lv[i];
+    launch_hash_fill(stream, L_.ndof, 12345u + uint32_t(i), L_.x);
+    double lam = 0.0;
+    launch_dot(stream, L_.ndof, L_.x, L_.x, partial);
+    double nx = std::sqrt(reduce_host(red_grid(L_.ndof), partial, 0));
+    for (int it = 0; it < 24; ++it) {
+      launch_apply(stream, L_.op, L_.x, nullptr, nullptr, L_.d, nullptr, 0.0, -1.0, kCheb, nullptr);
+      launch_dot(stream, L_.ndof, L_.d, L_.d, partial);
+      double nd = std::sqrt(reduce_host(red_grid(L_.ndof), partial, 0));
+      lam = nd / nx;
+      launch_scale(stream, L_.ndof, 1.0 / nd, L_.d, L_.x);
+      nx = 1.0;
+    }
+    check_launch("power iteration");
+    L_.lmax = lam;
+  }
+}
+
+// ----------------------------------------------------------------- multigrid
+
+void fep3m_ctx::cheb_smooth(int l, const double *f, bool zero_start) {
+  MGLevel &L_ = lv[l];
+  const double bmax = 1.1 * L_.lmax, amin = bmax / 10.0;
+  const double theta = 0.5 * (bmax + amin), delta = 0.5 * (bmax - amin), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  const int deg = opt.cheb_degree;
+  for (int s = 0; s < deg; ++s) {
+    double c1, c2;
+    if (s == 0) {
+      c1 = 0.0;
+      c2 = 1.0 / theta;
+    } else {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      c1 = rn * rho;
+      c2 = 2.0 * rn / delta;
+      rho = rn;
+    }
+    if (s == 0 && zero_start) {
+      launch_cheb_first(stream, L_.op, f, L_.d, L_.x, c2);
+    } else {
+      launch_apply(stream, L_.op, L_.x, f, nullptr, L_.d, L_.x2, c1, c2, kCheb, nullptr);
+      std::swap(L_.x, L_.x2);
+    }
+  }
+}
+
+void fep3m_ctx::vcycle(int l, const double *f) {
+  MGLevel &L_ = lv[l];
+  if (l + 1 == int(lv.size())) {
+    launch_coarse_solve(stream, coarseP, coarseV, coarseLam, f, L_.x);
+    return;
+  }
+  cheb_smooth(l, f, true);
+  launch_apply(stream, L_.op, L_.x, f, L_.r, nullptr, nullptr, 0.0, 0.0, kResidual, nullptr);
+  launch_restrict(stream, tr[l], L_.r, lv[l + 1].f);
+  vcycle(l + 1, lv[l + 1].f);
+  launch_prolong_add(stream, tr[l], lv[l + 1].x, L_.x);
+  cheb_smooth(l, f, false);
+}
+
+void fep3m_ctx::solve() {
+  MGLevel &L0 = lv[0];
+  const size_t nd = L0.ndof;
+  hip_check(hipMemsetAsync(sol, 0, nd * sizeof(double), stream), "zero phi");
+  hip_check(hipMemcpyAsync(rr, b, nd * sizeof(double), hipMemcpyDeviceToDevice, stream), "copy r");
+  launch_dot(stream, nd, b, b, partial);
+  const double bnorm = std::sqrt(reduce_host(red_grid(nd), partial, 0));
+  stats.mg_iterations = 0;
+  stats.mg_rel_residual = 0.0;
+  if (bnorm == 0.0) return;
+  vcycle(0, rr);
+  hip_check(hipMemcpyAsync(pv, L0.x, nd * sizeof(double), hipMemcpyDeviceToDevice, stream), "copy p");
+  launch_dot(stream, nd, rr, L0.x, partial);
+  double rz = reduce_host(red_grid(nd), partial, 0);
+  double rel = 1.0;
+  int it = 0;
+  for (it = 1; it <= opt.mg_max_iter; ++it) {
+    const int nb = launch_apply(stream, L0.op, pv, nullptr, qv, nullptr, nullptr, 0.0, 0.0, kApplyDot, partial);
+    const double pq = reduce_host(nb, partial, 0);
+    const double alpha = rz / pq;
+    launch_cg_update(stream, nd, alpha, pv, qv, sol, rr, partial);
+    rel = std::sqrt(reduce_host(red_grid(nd), partial, 0)) / bnorm;
+    if (rel <= opt.mg_rtol) break;
+    vcycle(0, rr);
+    launch_dot(stream, nd, rr, L0.x, partial);
+    const double rzn = reduce_host(red_grid(nd), partial, 0);
+    launch_xpay(stream, nd, rzn / rz, L0.x, pv);
+    rz = rzn;
+  }
+  stats.mg_iterations = std::min(it, opt.mg_max_iter);
+  stats.mg_rel_residual = rel;
+  check_launch("mesh solve");
+  if (!(rel <= opt.mg_rtol))
+    throw Status(FEP3M_ERR_NOT_CONVERGED, "mesh solve reached relative residual " + std::to_string(rel));
+}
+
+// ----------------------------------------------------------------- evaluate
+
+void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U) {
+  const int M = n * n * n;
+  hip_check(hipMemsetAsync(count, 0, size_t(M) * sizeof(int), stream), "zero counts");
+  hip_check(hipMemsetAsync(flags, 0, 4 * sizeof(int), stream), "zero flags");
+  const int gb = bin_grid(N);
+  launch_bin(stream, N, x, Qc, L, n, gtmp, elem, slot, count, flags, partial);
+  launch_sum_partials(stream, gb, partial, scal + 1);
+  launch_sum_partials(stream, gb, partial + gb, scal + 2);
+  hip_check(hipMemcpyAsync(host_scal + 1, scal + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, stream), "copy");
+  hip_check(hipMemcpyAsync(host_scal + 4, flags, sizeof(int), hipMemcpyDeviceToHost, stream), "copy");
+  sync("binning");
+  int fl;
+  std::memcpy(&fl, host_scal + 4, sizeof(int));
+  if (fl) throw Status(FEP3M_ERR_NONFINITE, "non-finite position or charge");
+  const double sq = host_scal[1], sa = host_scal[2];
+  if (std::fabs(sq) > 1e-10 * sa) throw Status(FEP3M_ERR_NOT_NEUTRAL, "charges are not neutral: sum Q = " + std::to_string(sq));
+
+  launch_scan(stream, M, count, start, maxcount);
+  launch_scatter(stream, N, elem, slot, start, tmp);
+  launch_rank(stream, N, tmp, elem, start, gtmp, Qc, perm, sg, sQ);
+  launch_moments(stream, n, N, start, sg, sQ, C);
+  launch_load(stream, n, p, C, gw, b, partial);
+  launch_sum_partials(stream, red_grid(lv[0].ndof), partial, scal + 3);
+  launch_sub_mass_ones(stream, n, p, w1, scal + 3, b);
+  check_launch("assignment");
+  solve();
+  launch_mass_dot(stream, n, p, w1, sol, partial);
+  launch_sum_partials(stream, red_grid(lv[0].ndof), partial, scal + 5);
+  launch_sub_const(stream, lv[0].ndof, 1.0 / (double(n) * n * n), scal + 5, sol);
+  if (launch_psi(stream, n, nsr, p, C, T, sol, Wel) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
+  if (launch_pair(stream, n, nsr, N, start, sg, sQ, phip_s) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "pair variant");
+  if (launch_interp(stream, p, n, N, 1.0 / h, bas, sg, Wel, phip_s, perm, phim_s, phi_s, Phi) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "interpolation variant");
+  if (U) {
+    launch_energy(stream, N, sQ, phi_s, partial);
+    launch_sum_partials(stream, energy_grid(N), partial, scal + 6);
+    launch_half(stream, scal + 6, U);
+  }
+  hip_check(hipMemsetAsync(paircount, 0, sizeof(unsigned long long), stream), "zero pair count");
+  launch_pair_count(stream, n, nsr, start, paircount);
+  hip_check(hipMemcpyAsync(host_scal + 8, paircount, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream), "copy");
+  hip_check(hipMemcpyAsync(host_scal + 9, maxcount, sizeof(int), hipMemcpyDeviceToHost, stream), "copy");
+  check_launch("evaluation");
+  sync("evaluation");
+  unsigned long long pc;
+  std::memcpy(&pc, host_scal + 8, sizeof(pc));
+  int mc;
+  std::memcpy(&mc, host_scal + 9, sizeof(int));
+  stats.near_pairs = int64_t(pc);
+  stats.max_per_element = mc;
+}
+
+// ----------------------------------------------------------------- C ABI
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <class F>
+int guarded(fep3m_ctx *ctx, F &&f) {
+  try {
+    if (ctx) ctx->err.clear();
+    f();
+    return FEP3M_OK;
+  } catch (const Status &s) {
+    if (ctx) ctx->err = s.what();
+    return s.code;
+  } catch (const std::bad_alloc &) {
+    if (ctx) ctx->err = "host allocation failed";
+    return FEP3M_ERR_OOM;
+  } catch (const std::exception &e) {
+    if (ctx) ctx->err = e.what();
+    return FEP3M_ERR_DEVICE;
+  }
+}
+
+bool valid_options(const fep3m_options &o, std::string &why) {
+  if (o.n_sr < 1 || o.n_sr > 3) { why = "n_sr must be 1..3"; return false; }
+  if (o.precision != FEP3M_PRECISION_FP64 && o.precision != FEP3M_PRECISION_MIXED) { why = "unknown precision"; return false; }
+  if (!(o.mg_rtol > 0.0) || !(o.mg_rtol < 1.0)) { why = "mg_rtol must be in (0, 1)"; return false; }
+  if (o.mg_max_iter < 1 || o.mg_max_iter > 1000) { why = "mg_max_iter must be 1..1000"; return false; }
+  if (o.cheb_degree < 1 || o.cheb_degree > 10) { why = "cheb_degree must be 1..10"; return false; }
+  if (o.table_box % 2 == 0 || o.table_box < 2 * o.n_sr + 3 || o.table_box > 41) {
+    why = "table_box must be odd, > 2 n_sr + 1 and <= 41";
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fep3m_default_options(fep3m_options *opt) {
+  if (!opt) return FEP3M_ERR_ARG;
+  opt->n_sr = 3;
+  opt->precision = FEP3M_PRECISION_FP64;
+  opt->mg_rtol = 1e-12;
+  opt->mg_max_iter = 60;
+  opt->cheb_degree = 3;
+  opt->table_box = 2 * 3 + 9;
+  return FEP3M_OK;
+}
+
+int fep3m_create_ex(double L, int64_t N, const int32_t dims[3], int32_t q, const fep3m_options *opt, fep3m_ctx **out) {
+  if (!out) return FEP3M_ERR_ARG;
+  *out = nullptr;
+  fep3m_options o;
+  if (opt) o = *opt; else fep3m_default_options(&o);
+  std::string why;
+  if (!dims) return FEP3M_ERR_ARG;
+  if (!(L > 0.0) || !std::isfinite(L)) return FEP3M_ERR_ARG;
+  if (N < 2 || N > (int64_t(1) << 30)) return FEP3M_ERR_ARG;
+  if (dims[0] != dims[1] || dims[1] != dims[2]) return FEP3M_ERR_ARG;
+  if (!valid_options(o, why)) return FEP3M_ERR_ARG;
+  if (dims[0] < 2 * o.n_sr + 1 || dims[0] > 512) return FEP3M_ERR_ARG;
+  if (q < 2 || q > 6) return FEP3M_ERR_ARG;
+  if (q != 3) return FEP3M_ERR_UNSUPPORTED;
+  if (o.precision != FEP3M_PRECISION_FP64) return FEP3M_ERR_UNSUPPORTED;
+  std::unique_ptr<fep3m_ctx> ctx(new (std::nothrow) fep3m_ctx());
+  if (!ctx) return FEP3M_ERR_OOM;
+  int st = guarded(ctx.get(), [&] { ctx->build(L, N, dims[0], q, o); });
+  if (st != FEP3M_OK) {
+    g_create_error = ctx->err;
+    return st;
+  }
+  *out = ctx.release();
+  return FEP3M_OK;
+}
+
+int fep3m_create(double L, int64_t N, const int32_t dims[3], int32_t q, fep3m_ctx **out) {
+  return fep3m_create_ex(L, N, dims, q, nullptr, out);
+}
+
+int fep3m_set_stream(fep3m_ctx *ctx, void *hip_stream) {
+  if (!ctx) return FEP3M_ERR_ARG;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return FEP3M_OK;
+}
+
+int fep3m_potential(fep3m_ctx *ctx, const double *x, const double *Q, double *Phi) {
+  if (!ctx || !x || !Q || !Phi) return FEP3M_ERR_ARG;
+  return guarded(ctx, [&] { ctx->evaluate(x, Q, Phi, nullptr); });
+}
+
+int fep3m_energy(fep3m_ctx *ctx, const double *x, const double *Q, double *Phi, double *U) {
+  if (!ctx || !x || !Q || !Phi || !U) return FEP3M_ERR_ARG;
+  return guarded(ctx, [&] { ctx->evaluate(x, Q, Phi, U); });
+}
+
+int64_t fep3m_stage_bytes(const fep3m_ctx *ctx, int32_t stage) {
+  if (!ctx) return 0;
+  const int64_t M = int64_t(ctx->n) * ctx->n * ctx->n;
+  const int64_t P3 = int64_t(ctx->lv.empty() ? 0 : ctx->lv[0].ndof);
+  switch (stage) {
+    case 0: return ctx->N * 4;
+    case 1: return (M + 1) * 4;
+    case 2: return M * 8 * 8;
+    case 3: case 4: return P3 * 8;
+    case 5: case 6: return ctx->N * 8;
+    case 7: return int64_t(ctx->T_host.size()) * 8;
+    default: return 0;
+  }
+}
+
+int fep3m_debug_stage(fep3m_ctx *ctx, int32_t stage, void *out, int64_t out_bytes) {
+  if (!ctx || !out) return FEP3M_ERR_ARG;
+  const int64_t need = fep3m_stage_bytes(ctx, stage);
+  if (need == 0 || out_bytes < need) {
+    ctx->err = "unknown stage or buffer too small";
+    return FEP3M_ERR_ARG;
+  }
+  return guarded(ctx, [&] {
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    switch (stage) {
+      case 0: hip_check(hipMemcpyAsync(out, ctx->perm, need, k, ctx->stream), "stage"); break;
+      case 1: hip_check(hipMemcpyAsync(out, ctx->start, need, k, ctx->stream), "stage"); break;
+      case 2: hip_check(hipMemcpyAsync(out, ctx->C, need, k, ctx->stream), "stage"); break;
+      case 3: hip_check(hipMemcpyAsync(out, ctx->b, need, k, ctx->stream), "stage"); break;
+      case 4: hip_check(hipMemcpyAsync(out, ctx->sol, need, k, ctx->stream), "stage"); break;
+      case 5: launch_unpermute(ctx->stream, ctx->N, 1.0 / ctx->h, ctx->perm, ctx->phip_s, static_cast<double *>(out)); break;
+      case 6: launch_unpermute(ctx->stream, ctx->N, 1.0, ctx->perm, ctx->phim_s, static_cast<double *>(out)); break;
+      case 7: hip_check(hipMemcpyAsync(out, ctx->T_host.data(), need, hipMemcpyHostToDevice, ctx->stream), "stage"); break;
+    }
+    ctx->check_launch("stage");
+    ctx->sync("stage");
+  });
+}
+
+int fep3m_get_stats(const fep3m_ctx *ctx, fep3m_stats *stats) {
+  if (!ctx || !stats) return FEP3M_ERR_ARG;
+  *stats = ctx->stats;
+  return FEP3M_OK;
+}
+
+void fep3m_destroy(fep3m_ctx *ctx) { delete ctx; }
+
+const char *fep3m_last_error(const fep3m_ctx *ctx) {
+  if (!ctx) return g_create_error.c_str();
+  return ctx->err.c_str();
+}
+
+const char *fep3m_status_string(int status) {
+  switch (status) {
+    case FEP3M_OK: return "ok";
+    case FEP3M_ERR_ARG: return "invalid argument";
+    case FEP3M_ERR_NOT_NEUTRAL: return "charges are not neutral";
+    case FEP3M_ERR_NONFINITE: return "non-finite input";
+    case FEP3M_ERR_NOT_CONVERGED: return "mesh solve did not converge";
+    case FEP3M_ERR_DEVICE: return "device error";
+    case FEP3M_ERR_OOM: return "out of memory";
+    case FEP3M_ERR_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+int fep3m_host_tables(int32_t q, int32_t n_sr, int32_t box, double *out, int64_t out_len) {
+  if (!out || q != 3 || n_sr < 1 || n_sr > 3 || box % 2 == 0 || box < 2 * n_sr + 3 || box > 41) return FEP3M_ERR_ARG;
+  const int p = q + 2, S = 2 * n_sr + 1;
+  const int64_t need = int64_t(8) * S * S * S * (p + 1) * (p + 1) * (p + 1);
+  if (out_len < need) return FEP3M_ERR_ARG;
+  try {
+    Vec T;
+    compute_tables(p, make_screen(q), n_sr, box, T);
+    std::memcpy(out, T.data(), size_t(need) * sizeof(double));
+  } catch (...) {
+    return FEP3M_ERR_ARG;
+  }
+  return FEP3M_OK;
+}
+
+}  // extern "C"

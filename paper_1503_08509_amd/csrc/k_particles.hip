@@ -1,0 +1,413 @@
+// Particle-side kernels: periodic wrap and element binning, a deterministic
+// counting sort by element, per-element screen moments, the near-pair 1/R
+// sum, interpolation of the mesh field at the charges, and the energy.
+//
+// Positions are kept as g = n * frac(x / L) in element units: element
+// e = floor(g) (clamped to n - 1) and local offset u = g - e - 1/2.
+#include "kernels.hpp"
+
+namespace fep3m {
+
+__device__ __forceinline__ double block_sum_p(double v, double *red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// ----------------------------------------------------------------- binning
+
+// Wrap, bin and count.  Non-finite inputs raise flags[0] and are binned to
+// element 0 so every index stays in bounds.  Block partials of sum Q and
+// sum |Q| go to partial[b] and partial[gridDim.x + b].
+__global__ __launch_bounds__(256) void k_bin(int64_t N, const double *__restrict__ x, const double *__restrict__ Q,
+                                             double L, int n, double *__restrict__ gtmp, int *__restrict__ elem,
+                                             int *__restrict__ slot, int *__restrict__ count, int *__restrict__ flags,
+                                             double *__restrict__ partial) {
+  __shared__ double red[256];
+  double sq = 0.0, sa = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    int e[3];
+    bool ok = true;
+    double gv[3];
+    for (int k = 0; k < 3; ++k) {
+      const double xv = x[3 * i + k];
+      if (!isfinite(xv)) ok = false;
+      double s = xv / L;
+      s = s - floor(s);
+      double t = s * double(n);
+      double ef = floor(t);
+      if (ef > double(n - 1)) ef = double(n - 1);
+      if (!(ef >= 0.0 && ef <= double(n - 1))) {  // NaN from an overflowing x / L
+        ok = false;
+        ef = 0.0;
+      }
+      gv[k] = t;
+      e[k] = int(ef);
+    }
+    const double q = Q[i];
+    if (!isfinite(q)) ok = false;
+    if (!ok) {
+      atomicOr(flags, 1);
+      e[0] = e[1] = e[2] = 0;
+      gv[0] = gv[1] = gv[2] = 0.5;
+    }
+    for (int k = 0; k < 3; ++k) gtmp[k * N + i] = gv[k];
+    const int E = e[0] + n * (e[1] + n * e[2]);
+    elem[i] = E;
+    slot[i] = atomicAdd(count + E, 1);
+    sq += ok ? q : 0.0;
+    sa += ok ? fabs(q) : 0.0;
+  }
+  double t1 = block_sum_p(sq, red);
+  double t2 = block_sum_p(sa, red);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = t1;
+    partial[gridDim.x + blockIdx.x] = t2;
+  }
+}
+
+// Exclusive scan of count[0..M) into start[0..M]; also the largest count.
+__global__ __launch_bounds__(1024) void k_scan(int M, const int *__restrict__ count, int *__restrict__ start,
+                                               int *__restrict__ maxcount) {
+  __shared__ int sums[1024];
+  __shared__ int mx[1024];
+  const int t = threadIdx.x;
+  const int chunk = (M + 1023) / 1024;
+  const int b = t * chunk, e = min(M, b + chunk);
+  int s = 0, m = 0;
+  for (int i = b; i < e; ++i) { s += count[i]; m = max(m, count[i]); }
+  sums[t] = s;
+  mx[t] = m;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+    int v = (t >= off) ? sums[t - off] : 0;
+    __syncthreads();
+    sums[t] += v;
+    __syncthreads();
+  }
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) mx[t] = max(mx[t], mx[t + off]);
+    __syncthreads();
+  }
+  int run = sums[t] - s;
+  for (int i = b; i < e; ++i) { start[i] = run; run += count[i]; }
+  if (t == 1023) start[M] = sums[1023];
+  if (t == 0) maxcount[0] = mx[0];
+}
+
+__global__ __launch_bounds__(256) void k_scatter(int64_t N, const int *__restrict__ elem, const int *__restrict__ slot,
+                                                 const int *__restrict__ start, int *__restrict__ tmp) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x)
+    tmp[start[elem[i]] + slot[i]] = int(i);
+}
+
+// Stable order inside each element: the rank of caller index i among its
+// element's indices.  Gathers the sorted positions and charges.
+__global__ __launch_bounds__(256) void k_rank(int64_t N, const int *__restrict__ tmp, const int *__restrict__ elem,
+                                              const int *__restrict__ start, const double *__restrict__ gtmp,
+                                              const double *__restrict__ Q, int *__restrict__ perm,
+                                              double *__restrict__ sg, double *__restrict__ sQ) {
+  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < N; s += int64_t(gridDim.x) * blockDim.x) {
+    const int i = tmp[s];
+    const int E = elem[i];
+    const int b = start[E], e = start[E + 1];
+    int rank = 0;
+    for (int j = b; j < e; ++j) rank += (tmp[j] < i);
+    const int pos = b + rank;
+    perm[pos] = i;
+    for (int k = 0; k < 3; ++k) sg[k * N + pos] = gtmp[k * N + i];
+    sQ[pos] = Q[i];
+  }
+}
+
+// ----------------------------------------------------------------- moments
+
+// C[E][a] = sum_{j in E} Q_j u_j^a, a = ax + 2 ay + 4 az (element units).
+__global__ __launch_bounds__(256) void k_moments(int n, int64_t N, const int *__restrict__ start,
+                                                 const double *__restrict__ sg, const double *__restrict__ sQ,
+                                                 double *__restrict__ C) {
+  const int M = n * n * n;
+  for (int E = blockIdx.x * blockDim.x + threadIdx.x; E < M; E += gridDim.x * blockDim.x) {
+    const int ex = E % n, ey = (E / n) % n, ez = E / (n * n);
+    double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int s = start[E]; s < start[E + 1]; ++s) {
+      const double q = sQ[s];
+      const double ux = sg[s] - ex - 0.5, uy = sg[N + s] - ey - 0.5, uz = sg[2 * N + s] - ez - 0.5;
+      c[0] += q;
+      c[1] += q * ux;
+      c[2] += q * uy;
+      c[3] += q * ux * uy;
+      c[4] += q * uz;
+      c[5] += q * ux * uz;
+      c[6] += q * uy * uz;
+      c[7] += q * ux * uy * uz;
+    }
+    for (int a = 0; a < 8; ++a) C[size_t(E) * 8 + a] = c[a];
+  }
+}
+
+// ----------------------------------------------------------------- pair sum
+
+// One wavefront per target element.  Sources are the charges of the
+// (2 NSR + 1)^3 element block, walked as up to 2 (2 NSR + 1)^2 contiguous
+// sorted segments (rows along x, split where the row wraps the periodic
+// boundary); every lane takes a strided share of the flattened source list
+// and accumulates for a chunk of up to kTgt targets, then the wave reduces.
+// Displacements are formed in the target's unwrapped frame in element
+// units, so no minimum-image test is needed (n >= 2 NSR + 1).
+constexpr int kTgt = 8;
+template <int NSR>
+__global__ __launch_bounds__(64) void k_pair(int n, int64_t N, const int *__restrict__ start,
+                                             const double *__restrict__ sg, const double *__restrict__ sQ,
+                                             double *__restrict__ phip) {
+  constexpr int W = 2 * NSR + 1;
+  constexpr int MAXSEG = 2 * W * W;
+  __shared__ int sb[MAXSEG];
+  __shared__ int sl[MAXSEG];
+  __shared__ int so[MAXSEG + 1];
+  __shared__ int ss[MAXSEG];  // packed image shifts (s + 1) per axis, 2 bits each, in units of n
+  const int lane = threadIdx.x;
+  const int E = blockIdx.x;
+  const int tb = start[E], te = start[E + 1];
+  if (tb == te) return;  // uniform over the (single-wave) block
+  const int ex = E % n, ey = (E / n) % n, ez = E / (n * n);
+  for (int row = lane; row < W * W; row += 64) {
+    const int dy = row % W - NSR, dz = row / W - NSR;
+    int yy = ey + dy, zz = ez + dz, sy = 0, sz = 0;
+    if (yy < 0) { yy += n; sy = -1; } else if (yy >= n) { yy -= n; sy = 1; }
+    if (zz < 0) { zz += n; sz = -1; } else if (zz >= n) { zz -= n; sz = 1; }
+    const int rowE = n * (yy + n * zz);
+    const int x0 = ex - NSR, x1 = ex + NSR;
+    int bA, eA, shA, bB = 0, eB = 0, shB = 0;
+    if (x0 < 0) {
+      bA = start[rowE + x0 + n]; eA = start[rowE + n]; shA = -1;
+      bB = start[rowE]; eB = start[rowE + x1 + 1]; shB = 0;
+    } else if (x1 >= n) {
+      bA = start[rowE + x0]; eA = start[rowE + n]; shA = 0;
+      bB = start[rowE]; eB = start[rowE + x1 - n + 1]; shB = 1;
+    } else {
+      bA = start[rowE + x0]; eA = start[rowE + x1 + 1]; shA = 0;
+    }
+    const int pk = ((sy + 1) << 2) | ((sz + 1) << 4);
+    sb[2 * row] = bA; sl[2 * row] = eA - bA; ss[2 * row] = pk | (shA + 1);
+    sb[2 * row + 1] = bB; sl[2 * row + 1] = eB - bB; ss[2 * row + 1] = pk | (shB + 1);
+  }
+  __syncthreads();
+  if (lane == 0) {
+    int acc = 0;
+    for (int k = 0; k < MAXSEG; ++k) { so[k] = acc; acc += sl[k]; }
+    so[MAXSEG] = acc;
+  }
+  __syncthreads();
+  const int total = so[MAXSEG];
+  const double nd = double(n);
+  for (int t0 = tb; t0 < te; t0 += kTgt) {
+    const int nt = min(kTgt, te - t0);
+    double tx[kTgt], ty[kTgt], tz[kTgt], acc[kTgt];
+#pragma unroll
+    for (int k = 0; k < kTgt; ++k) {
+      const int ti = t0 + (k < nt ? k : 0);
+      tx[k] = sg[ti]; ty[k] = sg[N + ti]; tz[k] = sg[2 * N + ti];
+      acc[k] = 0.0;
+    }
+    int sp = 0;
+    for (int f = lane; f < total; f += 64) {
+      while (f >= so[sp + 1]) ++sp;
+      const int j = sb[sp] + (f - so[sp]);
+      const int pk = ss[sp];
+      const double shx = double((pk & 3) - 1) * nd, shy = double(((pk >> 2) & 3) - 1) * nd,
+                   shz = double(((pk >> 4) & 3) - 1) * nd;
+      const double jx = sg[j] + shx, jy = sg[N + j] + shy, jz = sg[2 * N + j] + shz;
+      const double qj = sQ[j];
+#pragma unroll
+      for (int k = 0; k < kTgt; ++k) {
+        const double dx = jx - tx[k], dy = jy - ty[k], dz = jz - tz[k];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const bool use = (k < nt) && (j != t0 + k);
+        acc[k] += use ? qj * rsqrt(r2) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kTgt; ++k) {
+      double v = acc[k];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      acc[k] = v;
+    }
+    if (lane == 0) {
+      for (int k = 0; k < nt; ++k) phip[t0 + k] = acc[k];
+    }
+  }
+}
+
+// ----------------------------------------------------------------- interpolation
+
+// Phi_m at each sorted charge: sum_m W_E[m] u_m(u_i) (W = phi - Psi of its
+// element, element units) by sum factorisation; then the combined
+// potential (Phi_p + Phi_m) / h, scattered to caller order.
+template <int PO>
+__global__ __launch_bounds__(256) void k_interp(int n, int64_t N, double inv_h, GllBasis bas,
+                                                const double *__restrict__ sg, const double *__restrict__ Wel,
+                                                const double *__restrict__ phip, const int *__restrict__ perm,
+                                                double *__restrict__ phim_s, double *__restrict__ phi_s,
+                                                double *__restrict__ Phi) {
+  constexpr int Q1 = PO + 1;
+  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < N; s += int64_t(gridDim.x) * blockDim.x) {
+    double l[3][Q1];
+    int e[3];
+    for (int k = 0; k < 3; ++k) {
+      const double g = sg[k * N + s];
+      double ef = floor(g);
+      if (ef > double(n - 1)) ef = double(n - 1);
+      e[k] = int(ef);
+      const double u = g - ef - 0.5;
+#pragma unroll
+      for (int a = 0; a < Q1; ++a) {
+        double v = bas.w[a];
+#pragma unroll
+        for (int j = 0; j < Q1; ++j)
+          if (j != a) v *= (u - bas.x[j]);
+        l[k][a] = v;
+      }
+    }
+    const size_t E = size_t(e[0]) + size_t(n) * (e[1] + size_t(n) * e[2]);
+    const double *w = Wel + E * (Q1 * Q1 * Q1);
+    double acc = 0.0;
+#pragma unroll
+    for (int mz = 0; mz < Q1; ++mz) {
+      double sy = 0.0;
+#pragma unroll
+      for (int my = 0; my < Q1; ++my) {
+        double sx = 0.0;
+#pragma unroll
+        for (int mx = 0; mx < Q1; ++mx) sx += l[0][mx] * w[(mz * Q1 + my) * Q1 + mx];
+        sy += l[1][my] * sx;
+      }
+      acc += l[2][mz] * sy;
+    }
+    const double pm = acc * inv_h;
+    const double tot = phip[s] * inv_h + pm;
+    phim_s[s] = pm;
+    phi_s[s] = tot;
+    Phi[perm[s]] = tot;
+  }
+}
+
+// Block partials of sum_s Q_s Phi_s.
+__global__ __launch_bounds__(256) void k_energy(int64_t N, const double *__restrict__ sQ, const double *__restrict__ phi_s,
+                                                double *__restrict__ partial) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < N; s += int64_t(gridDim.x) * blockDim.x)
+    acc += sQ[s] * phi_s[s];
+  double t = block_sum_p(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_half(const double *__restrict__ in, double *__restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = 0.5 * in[0];
+}
+
+// out[perm[s]] = scale * in[s]
+__global__ __launch_bounds__(256) void k_unpermute(int64_t N, double scale, const int *__restrict__ perm,
+                                                   const double *__restrict__ in, double *__restrict__ out) {
+  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < N; s += int64_t(gridDim.x) * blockDim.x)
+    out[perm[s]] = scale * in[s];
+}
+
+// Ordered near pairs: sum_E count_E * (sum over the block of counts) - N.
+template <int NSR>
+__global__ __launch_bounds__(256) void k_pair_count(int n, const int *__restrict__ start,
+                                                    unsigned long long *__restrict__ out) {
+  const int M = n * n * n;
+  for (int E = blockIdx.x * blockDim.x + threadIdx.x; E < M; E += gridDim.x * blockDim.x) {
+    const int c = start[E + 1] - start[E];
+    if (c == 0) continue;
+    const int ex = E % n, ey = (E / n) % n, ez = E / (n * n);
+    long long s = 0;
+    for (int dz = -NSR; dz <= NSR; ++dz)
+      for (int dy = -NSR; dy <= NSR; ++dy)
+        for (int dx = -NSR; dx <= NSR; ++dx) {
+          const int F = (ex + dx + n) % n + n * ((ey + dy + n) % n + n * ((ez + dz + n) % n));
+          s += start[F + 1] - start[F];
+        }
+    atomicAdd(out, (unsigned long long)(c * s - c));
+  }
+}
+
+// ----------------------------------------------------------------- launchers
+
+namespace {
+inline int grid_n(int64_t n, int maxb = 4096) {
+  int64_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  return int(g < maxb ? g : maxb);
+}
+}  // namespace
+
+int bin_grid(int64_t N) { return grid_n(N, kRedBlocks); }
+
+void launch_bin(hipStream_t s, int64_t N, const double *x, const double *Q, double L, int n, double *gtmp, int *elem,
+                int *slot, int *count, int *flags, double *partial) {
+  hipLaunchKernelGGL(k_bin, dim3(bin_grid(N)), dim3(256), 0, s, N, x, Q, L, n, gtmp, elem, slot, count, flags, partial);
+}
+void launch_scan(hipStream_t s, int M, const int *count, int *start, int *maxcount) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, M, count, start, maxcount);
+}
+void launch_scatter(hipStream_t s, int64_t N, const int *elem, const int *slot, const int *start, int *tmp) {
+  hipLaunchKernelGGL(k_scatter, dim3(grid_n(N)), dim3(256), 0, s, N, elem, slot, start, tmp);
+}
+void launch_rank(hipStream_t s, int64_t N, const int *tmp, const int *elem, const int *start, const double *gtmp,
+                 const double *Q, int *perm, double *sg, double *sQ) {
+  hipLaunchKernelGGL(k_rank, dim3(grid_n(N)), dim3(256), 0, s, N, tmp, elem, start, gtmp, Q, perm, sg, sQ);
+}
+void launch_moments(hipStream_t s, int n, int64_t N, const int *start, const double *sg, const double *sQ, double *C) {
+  hipLaunchKernelGGL(k_moments, dim3(grid_n(int64_t(n) * n * n)), dim3(256), 0, s, n, N, start, sg, sQ, C);
+}
+int launch_pair(hipStream_t s, int n, int nsr, int64_t N, const int *start, const double *sg, const double *sQ,
+                double *phip) {
+  const int M = n * n * n;
+  dim3 g(M);
+  switch (nsr) {
+    case 1: hipLaunchKernelGGL(k_pair<1>, g, dim3(64), 0, s, n, N, start, sg, sQ, phip); return 0;
+    case 2: hipLaunchKernelGGL(k_pair<2>, g, dim3(64), 0, s, n, N, start, sg, sQ, phip); return 0;
+    case 3: hipLaunchKernelGGL(k_pair<3>, g, dim3(64), 0, s, n, N, start, sg, sQ, phip); return 0;
+    case 4: hipLaunchKernelGGL(k_pair<4>, g, dim3(64), 0, s, n, N, start, sg, sQ, phip); return 0;
+    default: return -1;
+  }
+}
+int launch_pair_count(hipStream_t s, int n, int nsr, const int *start, unsigned long long *out) {
+  const int M = n * n * n;
+  switch (nsr) {
+    case 1: hipLaunchKernelGGL(k_pair_count<1>, dim3(grid_n(M)), dim3(256), 0, s, n, start, out); return 0;
+    case 2: hipLaunchKernelGGL(k_pair_count<2>, dim3(grid_n(M)), dim3(256), 0, s, n, start, out); return 0;
+    case 3: hipLaunchKernelGGL(k_pair_count<3>, dim3(grid_n(M)), dim3(256), 0, s, n, start, out); return 0;
+    case 4: hipLaunchKernelGGL(k_pair_count<4>, dim3(grid_n(M)), dim3(256), 0, s, n, start, out); return 0;
+    default: return -1;
+  }
+}
+int launch_interp(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const double *sg,
+                  const double *Wel, const double *phip, const int *perm, double *phim_s, double *phi_s, double *Phi) {
+  if (p != 5) return -1;
+  hipLaunchKernelGGL(k_interp<5>, dim3(grid_n(N)), dim3(256), 0, s, n, N, inv_h, bas, sg, Wel, phip, perm, phim_s,
+                     phi_s, Phi);
+  return 0;
+}
+void launch_energy(hipStream_t s, int64_t N, const double *sQ, const double *phi_s, double *partial) {
+  hipLaunchKernelGGL(k_energy, dim3(grid_n(N, kRedBlocks)), dim3(256), 0, s, N, sQ, phi_s, partial);
+}
+int energy_grid(int64_t N) { return grid_n(N, kRedBlocks); }
+void launch_half(hipStream_t s, const double *in, double *out) {
+  hipLaunchKernelGGL(k_half, dim3(1), dim3(64), 0, s, in, out);
+}
+void launch_unpermute(hipStream_t s, int64_t N, double scale, const int *perm, const double *in, double *out) {
+  hipLaunchKernelGGL(k_unpermute, dim3(grid_n(N)), dim3(256), 0, s, N, scale, perm, in, out);
+}
+
+}  // namespace fep3m

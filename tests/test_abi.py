@@ -1,0 +1,97 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/fep3m.h, validates arguments before touching the device,
+and its create-time host precompute (the near-field tables) agrees with the
+oracle's independent computation."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1503_08509_amd as fp
+from oracle import tables
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fep3m.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fep3m_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fp.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_default_options_and_status_strings():
+    o = fp.default_options()
+    assert o.n_sr == 3 and o.precision == 0 and o.mg_rtol == 1e-12 and o.table_box == 15
+    assert fp.lib().fep3m_default_options(None) == fp.ERR_ARG
+    for st in range(0, -8, -1):
+        assert fp.lib().fep3m_status_string(st)
+    assert fp.lib().fep3m_status_string(-99) == b"unknown status"
+
+
+@pytest.mark.parametrize("L,N,dims,q", [
+    (0.0, 100, (8, 8, 8), 3),      # L <= 0
+    (float("nan"), 100, (8, 8, 8), 3),
+    (1.0, 1, (8, 8, 8), 3),        # N < 2
+    (1.0, 100, (6, 6, 6), 3),      # n < 2 n_sr + 1
+    (1.0, 100, (8, 8, 9), 3),      # non-cubic
+    (1.0, 100, (8, 8, 8), 1),      # q out of range
+    (1.0, 100, (8, 8, 8), 7),
+])
+def test_create_rejects_bad_arguments(L, N, dims, q):
+    h = ctypes.c_void_p()
+    d = (ctypes.c_int32 * 3)(*dims)
+    st = fp.lib().fep3m_create(L, N, d, q, ctypes.byref(h))
+    assert st == fp.ERR_ARG
+    assert not h.value
+
+
+def test_create_rejects_bad_options():
+    h = ctypes.c_void_p()
+    d = (ctypes.c_int32 * 3)(8, 8, 8)
+    for field, val in (("n_sr", 0), ("mg_rtol", 0.0), ("mg_max_iter", 0), ("table_box", 14), ("table_box", 7),
+                       ("precision", 5), ("cheb_degree", 0)):
+        o = fp.default_options()
+        setattr(o, field, val)
+        assert fp.lib().fep3m_create_ex(1.0, 100, d, 3, ctypes.byref(o), ctypes.byref(h)) == fp.ERR_ARG, field
+    assert fp.lib().fep3m_create_ex(1.0, 100, d, 3, None, None) == fp.ERR_ARG
+
+
+def test_unsupported_degree_is_reported():
+    h = ctypes.c_void_p()
+    d = (ctypes.c_int32 * 3)(8, 8, 8)
+    assert fp.lib().fep3m_create(1.0, 100, d, 4, ctypes.byref(h)) == fp.ERR_UNSUPPORTED
+
+
+def test_null_context_calls():
+    L = fp.lib()
+    assert L.fep3m_potential(None, None, None, None) == fp.ERR_ARG
+    assert L.fep3m_energy(None, None, None, None, None) == fp.ERR_ARG
+    assert L.fep3m_stage_bytes(None, 0) == 0
+    assert L.fep3m_get_stats(None, None) == fp.ERR_ARG
+    L.fep3m_destroy(None)
+
+
+@pytest.mark.parametrize("n_sr,box", [(3, 15), (2, 11), (1, 9)])
+def test_host_tables_match_oracle(n_sr, box):
+    T = fp.host_tables(3, n_sr, box)
+    To = tables.screen_tables(5, 3, n_sr, B=box)
+    assert T.shape == To.shape
+    assert np.abs(T - To).max() < 1e-12 * np.abs(To).max()
+
+
+def test_host_tables_argument_checks():
+    out = np.zeros(10)
+    ptr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert fp.lib().fep3m_host_tables(3, 3, 15, ptr, 10) == fp.ERR_ARG      # short buffer
+    assert fp.lib().fep3m_host_tables(3, 3, 14, ptr, 10**7) == fp.ERR_ARG   # even box
+    assert fp.lib().fep3m_host_tables(4, 3, 15, ptr, 10**7) == fp.ERR_ARG   # degree
