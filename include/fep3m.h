@@ -82,6 +82,30 @@ typedef struct {
   double  create_seconds;    /* wall time of create (tables, hierarchy)           */
 } fep3m_stats;
 
+/* Profile slots: stages of one call, the fine-level operator launches, and
+ * the whole call.  `work` holds the algorithmic work of the slot: floating
+ * point operations for NEAR (2 * 8 * (p+1)^3 per target element and near
+ * offset) and PAIR (11 per ordered near pair), bytes that must cross HBM
+ * for FINE_APPLY (the vectors each launch reads and writes, 8 bytes per DOF
+ * each), 0 elsewhere. */
+enum {
+  FEP3M_PROF_SORT = 0,        /* wrap, bin, counting sort, gather          */
+  FEP3M_PROF_ASSIGN = 1,      /* element moments, load assembly, projection */
+  FEP3M_PROF_SOLVE = 2,       /* multigrid-PCG mesh solve and gauge        */
+  FEP3M_PROF_NEAR = 3,        /* near-screen field (one launch per call)    */
+  FEP3M_PROF_PAIR = 4,        /* near-pair sum (one launch per call)        */
+  FEP3M_PROF_INTERP = 5,      /* interpolation, combination, energy         */
+  FEP3M_PROF_FINE_APPLY = 6,  /* every fine-level operator launch           */
+  FEP3M_PROF_TOTAL = 7,       /* whole call                                 */
+  FEP3M_PROF_SLOTS = 8
+};
+
+typedef struct {
+  double  ms[FEP3M_PROF_SLOTS];     /* accumulated device time (hipEvents)     */
+  int64_t count[FEP3M_PROF_SLOTS];  /* calls (stage slots) or kernel launches  */
+  double  work[FEP3M_PROF_SLOTS];   /* accumulated algorithmic work (above)    */
+} fep3m_profile;
+
 /* Fill *opt with the defaults listed above.  Returns FEP3M_ERR_ARG on NULL. */
 int fep3m_default_options(fep3m_options *opt);
 
@@ -124,6 +148,14 @@ int fep3m_debug_stage(fep3m_ctx *ctx, int32_t stage, void *out, int64_t out_byte
 
 /* Number of bytes fep3m_debug_stage needs for a stage (0 if unknown). */
 int64_t fep3m_stage_bytes(const fep3m_ctx *ctx, int32_t stage);
+
+/* Turn per-stage device timing on (1) or off (0) and clear the profile.
+ * While on, every call records hipEvents on the context's stream around
+ * each stage and each fine-level operator launch. */
+int fep3m_set_profiling(fep3m_ctx *ctx, int32_t on);
+
+/* Accumulated profile since the last fep3m_set_profiling. */
+int fep3m_get_profile(const fep3m_ctx *ctx, fep3m_profile *prof);
 
 /* Counters of the last call. */
 int fep3m_get_stats(const fep3m_ctx *ctx, fep3m_stats *stats);

@@ -41,6 +41,13 @@ class Stats(ctypes.Structure):
                 ("mg_levels", ctypes.c_int32), ("create_seconds", ctypes.c_double)]
 
 
+PROF_SLOTS = ["sort", "assign", "solve", "near", "pair", "interp", "fine_apply", "total"]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("count", ctypes.c_int64 * 8), ("work", ctypes.c_double * 8)]
+
+
 class FEP3MError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"fep3m status {status}: {msg}")
@@ -74,6 +81,8 @@ def lib():
         L.fep3m_last_error.restype = ctypes.c_char_p
         L.fep3m_status_string.argtypes = [ctypes.c_int]
         L.fep3m_status_string.restype = ctypes.c_char_p
+        L.fep3m_set_profiling.argtypes = [vp, i32]
+        L.fep3m_get_profile.argtypes = [vp, ctypes.POINTER(Profile)]
         L.fep3m_host_tables.argtypes = [i32, i32, i32, ctypes.POINTER(dp), i64]
         _lib = L
     return _lib
@@ -165,6 +174,14 @@ class Context:
         s = Stats()
         self._check(lib().fep3m_get_stats(self._h, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def set_profiling(self, on=True):
+        self._check(lib().fep3m_set_profiling(self._h, 1 if on else 0))
+
+    def profile(self):
+        p = Profile()
+        self._check(lib().fep3m_get_profile(self._h, ctypes.byref(p)))
+        return {name: {"ms": p.ms[i], "count": p.count[i], "work": p.work[i]} for i, name in enumerate(PROF_SLOTS)}
 
     def close(self):
         if getattr(self, "_h", None):

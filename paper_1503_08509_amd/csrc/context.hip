@@ -43,6 +43,16 @@ T *dalloc(size_t count, const char *what) {
   return static_cast<T *>(p);
 }
 
+// Device-time profile (hipEvents on the context stream).
+struct Profiler {
+  bool on = false;
+  hipEvent_t stage_ev[2 * FEP3M_PROF_SLOTS] = {};
+  std::vector<hipEvent_t> kev;   // begin/end pairs for fine-level operator launches
+  std::vector<double> kwork;     // bytes of each recorded launch
+  int kused = 0;
+  fep3m_profile acc{};
+};
+
 struct MGLevel {
   LevelOp op{};
   size_t ndof = 0;
@@ -62,6 +72,7 @@ struct fep3m_ctx {
   std::string err;
   fep3m_stats stats{};
   std::vector<void *> allocs;
+  Profiler prof;
 
   // precompute
   std::vector<double> T_host;
@@ -92,6 +103,9 @@ struct fep3m_ctx {
     return p;
   }
   ~fep3m_ctx() {
+    for (hipEvent_t e : prof.stage_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : prof.kev) (void)hipEventDestroy(e);
     for (void *p : allocs) (void)hipFree(p);
     if (host_scal) (void)hipHostFree(host_scal);
   }
@@ -107,6 +121,24 @@ struct fep3m_ctx {
   }
 
   void build(double L_, int64_t N_, int n_, int q_, const fep3m_options &o);
+  void stage_mark(int slot, bool begin) {
+    if (prof.on) hip_check(hipEventRecord(prof.stage_ev[2 * slot + (begin ? 0 : 1)], stream), "event");
+  }
+  // fine-level operator launch, bracketed by events when profiling
+  int apply0(const double *x, const double *f, double *out, double *d, double *xo, double c1, double c2, int mode,
+             double *part) {
+    const bool rec = prof.on && prof.kused < int(prof.kev.size()) / 2;
+    if (rec) hip_check(hipEventRecord(prof.kev[2 * prof.kused], stream), "event");
+    const int nb = launch_apply(stream, lv[0].op, x, f, out, d, xo, c1, c2, mode, part);
+    if (rec) {
+      hip_check(hipEventRecord(prof.kev[2 * prof.kused + 1], stream), "event");
+      const double vec = mode == kCheb ? 5.0 : mode == kResidual ? 3.0 : 2.0;  // vectors read + written
+      prof.kwork[prof.kused] = vec * 8.0 * double(lv[0].ndof);
+      ++prof.kused;
+    }
+    return nb;
+  }
+  void profile_collect(bool energy);
   void build_mg();
   void estimate_spectra();
   void vcycle(int l, const double *f);
@@ -195,13 +227,22 @@ void fep3m_ctx::build(double L_, int64_t N_, int n_, int q_, const fep3m_options
   stats.mg_levels = int(lv.size());
 }
 
-static LevelOp make_levelop(int p, int n) {
+// Operator of a level whose elements are H fine elements wide: in fine
+// element units K1 scales as 1/H and M1 as H, so K = K1 M1 M1 + ... scales
+// as H (the coarse spaces are nested in the fine one, and the rediscretised
+// operator equals the Galerkin product P^T K P only with this scaling).
+static LevelOp make_levelop(int p, int n, double H) {
   LevelOp op{};
   op.p = p;
   op.n = n;
   op.P = p * n;
   Mat ke, me;
   element_matrices(p, ke, me);
+  for (int a = 0; a <= p; ++a)
+    for (int b = 0; b <= p; ++b) {
+      ke(a, b) /= H;
+      me(a, b) *= H;
+    }
   for (int a = 0; a <= p; ++a)
     for (int b = 0; b <= p; ++b) {
       op.ke[a * (p + 1) + b] = ke(a, b);
@@ -243,7 +284,7 @@ void fep3m_ctx::build_mg() {
     throw Status(FEP3M_ERR_UNSUPPORTED, "mesh size leaves a coarse grid above 16^3 elements (n must coarsen by 2 or 3)");
   for (auto &pr : hier) {
     MGLevel L_;
-    L_.op = make_levelop(pr.first, pr.second);
+    L_.op = make_levelop(pr.first, pr.second, double(n) / pr.second);
     L_.ndof = size_t(L_.op.P) * L_.op.P * L_.op.P;
     lv.push_back(L_);
   }
@@ -270,6 +311,9 @@ void fep3m_ctx::build_mg() {
     const LevelOp &op = lv.back().op;
     Mat K1, M1;
     assemble_1d(op.p, op.n, true, K1, M1);
+    const double H = double(n) / op.n;
+    for (double &v : K1.a) v /= H;
+    for (double &v : M1.a) v *= H;
     Vec lam;
     Mat V;
     sym_gen_eig(K1, M1, lam, V);
@@ -307,7 +351,7 @@ void fep3m_ctx::estimate_spectra() {
 
 void fep3m_ctx::cheb_smooth(int l, const double *f, bool zero_start) {
   MGLevel &L_ = lv[l];
-  const double bmax = 1.1 * L_.lmax, amin = bmax / 10.0;
+  const double bmax = 1.1 * L_.lmax, amin = bmax / 12.0;
   const double theta = 0.5 * (bmax + amin), delta = 0.5 * (bmax - amin), sigma = theta / delta;
   double rho = 1.0 / sigma;
   const int deg = opt.cheb_degree;
@@ -325,7 +369,8 @@ void fep3m_ctx::cheb_smooth(int l, const double *f, bool zero_start) {
     if (s == 0 && zero_start) {
       launch_cheb_first(stream, L_.op, f, L_.d, L_.x, c2);
     } else {
-      launch_apply(stream, L_.op, L_.x, f, nullptr, L_.d, L_.x2, c1, c2, kCheb, nullptr);
+      if (l == 0) apply0(L_.x, f, nullptr, L_.d, L_.x2, c1, c2, kCheb, nullptr);
+      else launch_apply(stream, L_.op, L_.x, f, nullptr, L_.d, L_.x2, c1, c2, kCheb, nullptr);
       std::swap(L_.x, L_.x2);
     }
   }
@@ -338,7 +383,8 @@ void fep3m_ctx::vcycle(int l, const double *f) {
     return;
   }
   cheb_smooth(l, f, true);
-  launch_apply(stream, L_.op, L_.x, f, L_.r, nullptr, nullptr, 0.0, 0.0, kResidual, nullptr);
+  if (l == 0) apply0(L_.x, f, L_.r, nullptr, nullptr, 0.0, 0.0, kResidual, nullptr);
+  else launch_apply(stream, L_.op, L_.x, f, L_.r, nullptr, nullptr, 0.0, 0.0, kResidual, nullptr);
   launch_restrict(stream, tr[l], L_.r, lv[l + 1].f);
   vcycle(l + 1, lv[l + 1].f);
   launch_prolong_add(stream, tr[l], lv[l + 1].x, L_.x);
@@ -362,7 +408,7 @@ void fep3m_ctx::solve() {
   double rel = 1.0;
   int it = 0;
   for (it = 1; it <= opt.mg_max_iter; ++it) {
-    const int nb = launch_apply(stream, L0.op, pv, nullptr, qv, nullptr, nullptr, 0.0, 0.0, kApplyDot, partial);
+    const int nb = apply0(pv, nullptr, qv, nullptr, nullptr, 0.0, 0.0, kApplyDot, partial);
     const double pq = reduce_host(nb, partial, 0);
     const double alpha = rz / pq;
     launch_cg_update(stream, nd, alpha, pv, qv, sol, rr, partial);
@@ -385,6 +431,9 @@ void fep3m_ctx::solve() {
 
 void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U) {
   const int M = n * n * n;
+  prof.kused = 0;
+  stage_mark(FEP3M_PROF_TOTAL, true);
+  stage_mark(FEP3M_PROF_SORT, true);
   hip_check(hipMemsetAsync(count, 0, size_t(M) * sizeof(int), stream), "zero counts");
   hip_check(hipMemsetAsync(flags, 0, 4 * sizeof(int), stream), "zero flags");
   const int gb = bin_grid(N);
@@ -403,17 +452,27 @@ void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double 
   launch_scan(stream, M, count, start, maxcount);
   launch_scatter(stream, N, elem, slot, start, tmp);
   launch_rank(stream, N, tmp, elem, start, gtmp, Qc, perm, sg, sQ);
+  stage_mark(FEP3M_PROF_SORT, false);
+  stage_mark(FEP3M_PROF_ASSIGN, true);
   launch_moments(stream, n, N, start, sg, sQ, C);
   launch_load(stream, n, p, C, gw, b, partial);
   launch_sum_partials(stream, red_grid(lv[0].ndof), partial, scal + 3);
   launch_sub_mass_ones(stream, n, p, w1, scal + 3, b);
   check_launch("assignment");
+  stage_mark(FEP3M_PROF_ASSIGN, false);
+  stage_mark(FEP3M_PROF_SOLVE, true);
   solve();
   launch_mass_dot(stream, n, p, w1, sol, partial);
   launch_sum_partials(stream, red_grid(lv[0].ndof), partial, scal + 5);
   launch_sub_const(stream, lv[0].ndof, 1.0 / (double(n) * n * n), scal + 5, sol);
+  stage_mark(FEP3M_PROF_SOLVE, false);
+  stage_mark(FEP3M_PROF_NEAR, true);
   if (launch_psi(stream, n, nsr, p, C, T, sol, Wel) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
+  stage_mark(FEP3M_PROF_NEAR, false);
+  stage_mark(FEP3M_PROF_PAIR, true);
   if (launch_pair(stream, n, nsr, N, start, sg, sQ, phip_s) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "pair variant");
+  stage_mark(FEP3M_PROF_PAIR, false);
+  stage_mark(FEP3M_PROF_INTERP, true);
   if (launch_interp(stream, p, n, N, 1.0 / h, bas, sg, Wel, phip_s, perm, phim_s, phi_s, Phi) != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "interpolation variant");
   if (U) {
@@ -421,6 +480,8 @@ void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double 
     launch_sum_partials(stream, energy_grid(N), partial, scal + 6);
     launch_half(stream, scal + 6, U);
   }
+  stage_mark(FEP3M_PROF_INTERP, false);
+  stage_mark(FEP3M_PROF_TOTAL, false);
   hip_check(hipMemsetAsync(paircount, 0, sizeof(unsigned long long), stream), "zero pair count");
   launch_pair_count(stream, n, nsr, start, paircount);
   hip_check(hipMemcpyAsync(host_scal + 8, paircount, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream), "copy");
@@ -433,6 +494,27 @@ void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double 
   std::memcpy(&mc, host_scal + 9, sizeof(int));
   stats.near_pairs = int64_t(pc);
   stats.max_per_element = mc;
+  if (prof.on) profile_collect(U != nullptr);
+}
+
+void fep3m_ctx::profile_collect(bool) {
+  for (int s = 0; s < FEP3M_PROF_SLOTS; ++s) {
+    if (s == FEP3M_PROF_FINE_APPLY) continue;
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, prof.stage_ev[2 * s], prof.stage_ev[2 * s + 1]), "elapsed");
+    prof.acc.ms[s] += ms;
+    prof.acc.count[s] += 1;
+  }
+  const double S = 2 * nsr + 1;
+  prof.acc.work[FEP3M_PROF_NEAR] += 2.0 * 8.0 * (p + 1) * (p + 1) * (p + 1) * S * S * S * double(n) * n * n;
+  prof.acc.work[FEP3M_PROF_PAIR] += 11.0 * double(stats.near_pairs);
+  for (int k = 0; k < prof.kused; ++k) {
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, prof.kev[2 * k], prof.kev[2 * k + 1]), "elapsed");
+    prof.acc.ms[FEP3M_PROF_FINE_APPLY] += ms;
+    prof.acc.count[FEP3M_PROF_FINE_APPLY] += 1;
+    prof.acc.work[FEP3M_PROF_FINE_APPLY] += prof.kwork[k];
+  }
 }
 
 // ----------------------------------------------------------------- C ABI
@@ -570,6 +652,26 @@ int fep3m_debug_stage(fep3m_ctx *ctx, int32_t stage, void *out, int64_t out_byte
     ctx->check_launch("stage");
     ctx->sync("stage");
   });
+}
+
+int fep3m_set_profiling(fep3m_ctx *ctx, int32_t on) {
+  if (!ctx) return FEP3M_ERR_ARG;
+  return guarded(ctx, [&] {
+    if (on && ctx->prof.kev.empty()) {
+      for (hipEvent_t &e : ctx->prof.stage_ev) hip_check(hipEventCreate(&e), "event create");
+      ctx->prof.kev.resize(2 * 512);
+      ctx->prof.kwork.resize(512);
+      for (hipEvent_t &e : ctx->prof.kev) hip_check(hipEventCreate(&e), "event create");
+    }
+    ctx->prof.on = on != 0;
+    ctx->prof.acc = fep3m_profile{};
+  });
+}
+
+int fep3m_get_profile(const fep3m_ctx *ctx, fep3m_profile *prof) {
+  if (!ctx || !prof) return FEP3M_ERR_ARG;
+  *prof = ctx->prof.acc;
+  return FEP3M_OK;
 }
 
 int fep3m_get_stats(const fep3m_ctx *ctx, fep3m_stats *stats) {

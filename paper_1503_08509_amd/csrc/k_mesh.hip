@@ -7,7 +7,7 @@
 //   K = K1 (x) M1 (x) M1 + M1 (x) K1 (x) M1 + M1 (x) M1 (x) K1
 // (the Galerkin stiffness of the tensor Q_p space on a uniform periodic
 // mesh, Section 2.2), applied as y = Kx (My Mz x) + Mx (Ky Mz x + My Kz x)
-// with banded 1-D passes on an LDS tile.
+// with banded 1-D passes over register columns of an LDS-staged tile.
 #include "kernels.hpp"
 
 namespace fep3m {
@@ -112,125 +112,158 @@ __global__ __launch_bounds__(256) void k_sub_const(size_t total, double invV, co
 
 // ----------------------------------------------------------------- operator
 
-template <int PO>
-__device__ __forceinline__ double diag_at(const LevelOp &op, int kx, int ky, int kz) {
-  return op.dk[kx] * op.dm[ky] * op.dm[kz] + op.dm[kx] * op.dk[ky] * op.dm[kz] + op.dm[kx] * op.dm[ky] * op.dk[kz];
+
+// Tiles of the fine level are handed to the 8 XCDs in contiguous chunks so
+// that neighbouring tiles (which re-read each other's halos) share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  if (nb % 8 != 0) return b;
+  return (b % 8) * (nb / 8) + b / 8;
 }
 
 template <int PO, int TE>
 struct ApplyShape {
   static constexpr int O = TE * PO;          // owned nodes per axis
   static constexpr int I = O + PO + 1;       // input nodes per axis (with halo)
-  static constexpr int NX = I * I * I;
-  static constexpr int NA = O * I * I;
-  static constexpr int NC = O * O * I;
-  static constexpr bool kReuse = 2 * NC <= NX;
-  static constexpr int LDS = NX + 2 * NA + (kReuse ? 0 : 2 * NC);
+  static constexpr int SA = I * I + 16;      // stride of one z-plane of A, B (bank padding)
+  static constexpr int RS = I + 1;           // row stride of C1, C2
+  static constexpr int SC = O * RS;          // plane stride of C1, C2
+  static constexpr int YS = O + 1;           // row stride of the output tile
+  static constexpr int LDS_AB = 2 * O * SA;
+  static constexpr int LDS_C = 2 * O * SC;
+  static constexpr int LDS_Y = O * O * YS;
+  static constexpr int LDS = LDS_AB > LDS_C + LDS_Y ? LDS_AB : LDS_C + LDS_Y;
+  static_assert(I * I <= 256 && O * I <= 256 && O * O <= 256, "tile columns must fit one pass of 256 threads");
 };
+
+// Banded 1-D element-assembled operator on a column held in registers:
+// out[o] = sum_j a[k][j] v[o + PO - k + j] (+ a[PO][j] v[o + j] for k = 0),
+// k = o mod PO, with v indexed from one element below the first output.
+// Every coefficient index is a compile-time constant, so the (wave-uniform)
+// coefficients come from scalar registers.
+template <int PO, int NOUT>
+__device__ __forceinline__ void band_apply(const double *__restrict__ a, const double (&v)[NOUT + PO + 1],
+                                           double (&out)[NOUT]) {
+  constexpr int Q1 = PO + 1;
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    const int k = o % PO;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < Q1; ++j) s += a[k * Q1 + j] * v[o + PO - k + j];
+    if (k == 0) {
+#pragma unroll
+      for (int j = 0; j < Q1; ++j) s += a[PO * Q1 + j] * v[o + j];
+    }
+    out[o] = s;
+  }
+}
 
 // One tile of TE^3 elements per block: y = K x on the owned nodes, then the
 // mode's epilogue.  The owned nodes of a tile are p*e + k, k < p, for its
 // elements; the inputs reach one element below and one node above.
+// Pass z: each thread streams one (x, y) column of the input from global
+// memory and writes A = Mz x, B = Kz x; pass y: one (z, x) column of A and B
+// gives C1 = My A and C2 = Ky A + My B; pass x: one (z, y) row of C1, C2
+// gives y = Kx C1 + Mx C2; the epilogue then walks the owned nodes x-fastest.
 template <int PO, int TE>
 __global__ __launch_bounds__(256) void k_apply(LevelOp op, const double *__restrict__ x,
                                                const double *__restrict__ f, double *__restrict__ out,
                                                double *__restrict__ dvec, double *__restrict__ xo, double c1,
                                                double c2, int mode, double *__restrict__ partial) {
   using S = ApplyShape<PO, TE>;
-  constexpr int O = S::O, I = S::I, Q1 = PO + 1;
+  constexpr int O = S::O, I = S::I;
   __shared__ double lds[S::LDS];
   __shared__ double red[256];
-  double *xs = lds;
-  double *A = lds + S::NX;
-  double *B = A + S::NA;
-  double *C1 = S::kReuse ? lds : B + S::NA;
-  double *C2 = C1 + S::NC;
+  double *A = lds;
+  double *B = lds + O * S::SA;
+  double *C1 = lds;
+  double *C2 = lds + O * S::SC;
+  double *Y = lds + 2 * O * S::SC;
   const int P = op.P;
   const int tiles = (op.n + TE - 1) / TE;
-  int t = blockIdx.x;
+  int t = xcd_tile(blockIdx.x, gridDim.x);
   const int tx = t % tiles;
   t /= tiles;
   const int ty = t % tiles;
   const int tz = t / tiles;
   const int ox0 = tx * O, oy0 = ty * O, oz0 = tz * O;
+  const int tid = threadIdx.x;
 
-  for (int li = threadIdx.x; li < S::NX; li += blockDim.x) {
-    const int lx = li % I, ly = (li / I) % I, lz = li / (I * I);
-    const int gx = wrapi(ox0 - PO + lx, P), gy = wrapi(oy0 - PO + ly, P), gz = wrapi(oz0 - PO + lz, P);
-    xs[li] = x[(size_t(gz) * P + gy) * P + gx];
+  // pass z
+  if (tid < I * I) {
+    const int lx = tid % I, ly = tid / I;
+    const int gx = wrapi(ox0 - PO + lx, P), gy = wrapi(oy0 - PO + ly, P);
+    double v[I];
+#pragma unroll
+    for (int z = 0; z < I; ++z) v[z] = x[(size_t(wrapi(oz0 - PO + z, P)) * P + gy) * P + gx];
+    double a[O], b[O];
+    band_apply<PO, O>(op.me, v, a);
+    band_apply<PO, O>(op.ke, v, b);
+#pragma unroll
+    for (int oz = 0; oz < O; ++oz) {
+      A[oz * S::SA + tid] = a[oz];
+      B[oz * S::SA + tid] = b[oz];
+    }
   }
   __syncthreads();
-  // z pass: A = Mz x, B = Kz x on owned z, all y, x
-  for (int li = threadIdx.x; li < S::NA; li += blockDim.x) {
-    const int lxy = li % (I * I), oz = li / (I * I);
-    const int k = oz % PO, lz = oz + PO;
-    double a = 0.0, b = 0.0;
+  // pass y
+  double c1v[O], c2v[O];
+  const bool act2 = tid < O * I;
+  const int oz2 = tid / I, lx2 = tid % I;
+  if (act2) {
+    double va[I], vb[I];
 #pragma unroll
-    for (int j = 0; j < Q1; ++j) {
-      const double v = xs[(lz - k + j) * I * I + lxy];
-      a += op.me[k * Q1 + j] * v;
-      b += op.ke[k * Q1 + j] * v;
+    for (int y = 0; y < I; ++y) {
+      va[y] = A[oz2 * S::SA + y * I + lx2];
+      vb[y] = B[oz2 * S::SA + y * I + lx2];
     }
-    if (k == 0) {
+    double t1[O], t2[O];
+    band_apply<PO, O>(op.me, va, c1v);
+    band_apply<PO, O>(op.ke, va, t1);
+    band_apply<PO, O>(op.me, vb, t2);
 #pragma unroll
-      for (int j = 0; j < Q1; ++j) {
-        const double v = xs[(lz - PO + j) * I * I + lxy];
-        a += op.me[PO * Q1 + j] * v;
-        b += op.ke[PO * Q1 + j] * v;
-      }
-    }
-    A[li] = a;
-    B[li] = b;
+    for (int o = 0; o < O; ++o) c2v[o] = t1[o] + t2[o];
   }
   __syncthreads();
-  // y pass: C1 = My A, C2 = Ky A + My B on owned z, y; all x
-  for (int li = threadIdx.x; li < S::NC; li += blockDim.x) {
-    const int lx = li % I, oy = (li / I) % O, oz = li / (I * O);
-    const int k = oy % PO, ly = oy + PO;
-    double c1v = 0.0, c2v = 0.0;
+  if (act2) {
 #pragma unroll
-    for (int j = 0; j < Q1; ++j) {
-      const int src = (oz * I + (ly - k + j)) * I + lx;
-      const double av = A[src], bv = B[src];
-      c1v += op.me[k * Q1 + j] * av;
-      c2v += op.ke[k * Q1 + j] * av + op.me[k * Q1 + j] * bv;
+    for (int oy = 0; oy < O; ++oy) {
+      C1[oz2 * S::SC + oy * S::RS + lx2] = c1v[oy];
+      C2[oz2 * S::SC + oy * S::RS + lx2] = c2v[oy];
     }
-    if (k == 0) {
-#pragma unroll
-      for (int j = 0; j < Q1; ++j) {
-        const int src = (oz * I + (ly - PO + j)) * I + lx;
-        const double av = A[src], bv = B[src];
-        c1v += op.me[PO * Q1 + j] * av;
-        c2v += op.ke[PO * Q1 + j] * av + op.me[PO * Q1 + j] * bv;
-      }
-    }
-    C1[li] = c1v;
-    C2[li] = c2v;
   }
   __syncthreads();
-  // x pass and epilogue on the owned nodes
+  // pass x
+  if (tid < O * O) {
+    const int oz = tid / O, oy = tid % O;
+    double v1[I], v2[I];
+#pragma unroll
+    for (int xx = 0; xx < I; ++xx) {
+      v1[xx] = C1[oz * S::SC + oy * S::RS + xx];
+      v2[xx] = C2[oz * S::SC + oy * S::RS + xx];
+    }
+    double y1[O], y2[O];
+    band_apply<PO, O>(op.ke, v1, y1);
+    band_apply<PO, O>(op.me, v2, y2);
+#pragma unroll
+    for (int ox = 0; ox < O; ++ox) Y[(oz * O + oy) * S::YS + ox] = y1[ox] + y2[ox];
+  }
+  __syncthreads();
+  // epilogue on the owned nodes, x fastest
   double acc = 0.0;
-  for (int li = threadIdx.x; li < O * O * O; li += blockDim.x) {
+  for (int li = tid; li < O * O * O; li += 256) {
     const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
     const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
-    const int k = ox % PO, lx = ox + PO;
-    double y = 0.0;
-    const int base = (oz * O + oy) * I;
-#pragma unroll
-    for (int j = 0; j < Q1; ++j) y += op.ke[k * Q1 + j] * C1[base + lx - k + j] + op.me[k * Q1 + j] * C2[base + lx - k + j];
-    if (k == 0) {
-#pragma unroll
-      for (int j = 0; j < Q1; ++j)
-        y += op.ke[PO * Q1 + j] * C1[base + lx - PO + j] + op.me[PO * Q1 + j] * C2[base + lx - PO + j];
-    }
     if (gx >= P || gy >= P || gz >= P) continue;
+    const double y = Y[(oz * O + oy) * S::YS + ox];
     const size_t g = (size_t(gz) * P + gy) * P + gx;
     if (mode == kApply) {
       out[g] = y;
     } else if (mode == kResidual) {
       out[g] = f[g] - y;
     } else if (mode == kCheb) {
-      const double D = diag_at<PO>(op, k, oy % PO, oz % PO);
+      const double D = op.dk[ox % PO] * op.dm[oy % PO] * op.dm[oz % PO] + op.dm[ox % PO] * op.dk[oy % PO] * op.dm[oz % PO] +
+                       op.dm[ox % PO] * op.dm[oy % PO] * op.dk[oz % PO];
       const double fv = f ? f[g] : 0.0;
       const double r = (fv - y) / D;
       const double dn = (c1 != 0.0 ? c1 * dvec[g] : 0.0) + c2 * r;
@@ -263,74 +296,170 @@ __global__ __launch_bounds__(256) void k_cheb_first(LevelOp op, const double *__
 
 // ----------------------------------------------------------------- transfers
 
-// Coarse value = sum over the fine nodes that reference the coarse node of
-// weight * fine value (restriction R = P^T, gather form).
+// Restriction R = P^T as three separable passes on a tile of TE^3 coarse
+// elements.  Along one axis, coarse node (e, j) collects the fine nodes s of
+// coarse element e with weight w[s][j] and, for the vertex j = 0, those of
+// element e - 1 with weight w[s][PC].  The tile reads the fine nodes of its
+// elements plus one coarse element below.
+template <int PF, int PC, int R, int TE>
+struct XferShape {
+  static constexpr int NS = R * PF;            // fine nodes per coarse element and axis
+  static constexpr int CO = PC * TE;           // owned coarse nodes per axis
+  static constexpr int NF = NS * (TE + 1);     // fine nodes read per axis (restriction)
+  static constexpr int CI = PC * TE + 1;       // coarse nodes read per axis (prolongation)
+  static constexpr int FO = NS * TE;           // owned fine nodes per axis (prolongation)
+};
+
+template <int PF, int PC, int R, int TE>
 __global__ __launch_bounds__(256) void k_restrict(Transfer tr, const double *__restrict__ rf, double *__restrict__ fc) {
-  const int Pc = tr.Pc, Pf = tr.Pf, pc = tr.pc, nc = tr.nc, ns = tr.ns, pf = tr.pf, r = tr.r;
-  const size_t total = size_t(Pc) * Pc * Pc;
-  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
-    const int gc[3] = {int(g % Pc), int((g / Pc) % Pc), int(g / (size_t(Pc) * Pc))};
-    int fidx[3][6 * kMaxP];
-    double fw[3][6 * kMaxP];
-    int cnt[3];
-    for (int a = 0; a < 3; ++a) {
-      const int e = gc[a] / pc, j = gc[a] % pc;
-      int c = 0;
-      for (int s = 0; s < ns; ++s) {
-        const double w = tr.w[s * (pc + 1) + j];
-        if (w != 0.0) { fidx[a][c] = (pf * r * e + s) % Pf; fw[a][c] = w; ++c; }
-      }
+  using S = XferShape<PF, PC, R, TE>;
+  constexpr int NS = S::NS, CO = S::CO, NF = S::NF, Q = PC + 1;
+  static_assert(NF * NF <= 256 && NF * CO <= 256 && CO * CO <= 256, "restriction tile too large");
+  __shared__ double G1[NF * NF * (CO + 1)];
+  __shared__ double G2[NF * CO * (CO + 1)];
+  const int Pf = tr.Pf, Pc = tr.Pc;
+  const int tiles = (tr.nc + TE - 1) / TE;
+  int t = blockIdx.x;
+  const int tx = t % tiles;
+  t /= tiles;
+  const int ty = t % tiles;
+  const int tz = t / tiles;
+  const int tid = threadIdx.x;
+  // fine index of the first node read: one coarse element below the tile
+  const int fx0 = NS * (tx * TE - 1), fy0 = NS * (ty * TE - 1), fz0 = NS * (tz * TE - 1);
+  // pass x: fine (z, y) row -> coarse x nodes
+  if (tid < NF * NF) {
+    const int fy = tid % NF, fz = tid / NF;
+    const double *row = rf + (size_t(wrapi(fz0 + fz, Pf)) * Pf + wrapi(fy0 + fy, Pf)) * Pf;
+    double v[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) v[i] = row[wrapi(fx0 + i, Pf)];
+#pragma unroll
+    for (int cx = 0; cx < CO; ++cx) {
+      const int ec = cx / PC, j = cx % PC;
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) s += tr.w[q * Q + j] * v[NS * (ec + 1) + q];
       if (j == 0) {
-        const int em = (e + nc - 1) % nc;
-        for (int s = 0; s < ns; ++s) {
-          const double w = tr.w[s * (pc + 1) + pc];
-          if (w != 0.0) { fidx[a][c] = (pf * r * em + s) % Pf; fw[a][c] = w; ++c; }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) s += tr.w[q * Q + PC] * v[NS * ec + q];
+      }
+      G1[(fz * NF + fy) * (CO + 1) + cx] = s;
+    }
+  }
+  __syncthreads();
+  // pass y: (fine z, coarse x) column -> coarse y nodes
+  if (tid < NF * CO) {
+    const int cx = tid % CO, fz = tid / CO;
+    double v[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) v[i] = G1[(fz * NF + i) * (CO + 1) + cx];
+#pragma unroll
+    for (int cy = 0; cy < CO; ++cy) {
+      const int ec = cy / PC, j = cy % PC;
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) s += tr.w[q * Q + j] * v[NS * (ec + 1) + q];
+      if (j == 0) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) s += tr.w[q * Q + PC] * v[NS * ec + q];
+      }
+      G2[(fz * CO + cy) * (CO + 1) + cx] = s;
+    }
+  }
+  __syncthreads();
+  // pass z: (coarse y, coarse x) column -> coarse z nodes, written out
+  if (tid < CO * CO) {
+    const int cx = tid % CO, cy = tid / CO;
+    double v[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) v[i] = G2[(i * CO + cy) * (CO + 1) + cx];
+    const int gx = tx * CO + cx, gy = ty * CO + cy;
+    if (gx < Pc && gy < Pc) {
+#pragma unroll
+      for (int cz = 0; cz < CO; ++cz) {
+        const int ec = cz / PC, j = cz % PC;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) s += tr.w[q * Q + j] * v[NS * (ec + 1) + q];
+        if (j == 0) {
+#pragma unroll
+          for (int q = 0; q < NS; ++q) s += tr.w[q * Q + PC] * v[NS * ec + q];
         }
+        const int gz = tz * CO + cz;
+        if (gz < Pc) fc[(size_t(gz) * Pc + gy) * Pc + gx] = s;
       }
-      cnt[a] = c;
     }
-    double acc = 0.0;
-    for (int iz = 0; iz < cnt[2]; ++iz) {
-      double sy = 0.0;
-      for (int iy = 0; iy < cnt[1]; ++iy) {
-        const double *row = rf + (size_t(fidx[2][iz]) * Pf + fidx[1][iy]) * Pf;
-        double sx = 0.0;
-        for (int ix = 0; ix < cnt[0]; ++ix) sx += fw[0][ix] * row[fidx[0][ix]];
-        sy += fw[1][iy] * sx;
-      }
-      acc += fw[2][iz] * sy;
-    }
-    fc[g] = acc;
   }
 }
 
-// xf += P ec: fine node value of the coarse FE function.
-__global__ __launch_bounds__(256) void k_prolong_add(Transfer tr, const double *__restrict__ ec, double *__restrict__ xf) {
-  const int Pc = tr.Pc, Pf = tr.Pf, pc = tr.pc, ns = tr.ns;
-  const size_t total = size_t(Pf) * Pf * Pf;
-  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
-    const int gf[3] = {int(g % Pf), int((g / Pf) % Pf), int(g / (size_t(Pf) * Pf))};
-    int ci[3][kMaxP + 1];
-    const double *wv[3];
-    for (int a = 0; a < 3; ++a) {
-      const int e = gf[a] / ns, s = gf[a] % ns;
-      wv[a] = tr.w + s * (pc + 1);
-      for (int j = 0; j <= pc; ++j) ci[a][j] = (pc * e + j) % Pc;
+// xf += P ec on a tile of TE^3 coarse elements: the fine nodes s of coarse
+// element e take sum_j w[s][j] ec[PC e + j] along each axis (three passes).
+template <int PF, int PC, int R, int TE>
+__global__ __launch_bounds__(256) void k_prolong_add(Transfer tr, const double *__restrict__ ec,
+                                                     double *__restrict__ xf) {
+  using S = XferShape<PF, PC, R, TE>;
+  constexpr int NS = S::NS, CI = S::CI, FO = S::FO, Q = PC + 1;
+  static_assert(CI * CI <= 256 && CI * FO <= 256 && FO * FO <= 256, "prolongation tile too large");
+  __shared__ double H1[CI * CI * (FO + 1)];
+  __shared__ double H2[CI * FO * (FO + 1)];
+  const int Pf = tr.Pf, Pc = tr.Pc;
+  const int tiles = (tr.nc + TE - 1) / TE;
+  int t = blockIdx.x;
+  const int tx = t % tiles;
+  t /= tiles;
+  const int ty = t % tiles;
+  const int tz = t / tiles;
+  const int tid = threadIdx.x;
+  const int cx0 = PC * TE * tx, cy0 = PC * TE * ty, cz0 = PC * TE * tz;
+  if (tid < CI * CI) {
+    const int cy = tid % CI, cz = tid / CI;
+    const double *row = ec + (size_t(wrapi(cz0 + cz, Pc)) * Pc + wrapi(cy0 + cy, Pc)) * Pc;
+    double v[CI];
+#pragma unroll
+    for (int i = 0; i < CI; ++i) v[i] = row[wrapi(cx0 + i, Pc)];
+#pragma unroll
+    for (int fx = 0; fx < FO; ++fx) {
+      const int e = fx / NS, s = fx % NS;
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) a += tr.w[s * Q + j] * v[PC * e + j];
+      H1[(cz * CI + cy) * (FO + 1) + fx] = a;
     }
-    double acc = 0.0;
-    for (int jz = 0; jz <= pc; ++jz) {
-      if (wv[2][jz] == 0.0) continue;
-      double sy = 0.0;
-      for (int jy = 0; jy <= pc; ++jy) {
-        if (wv[1][jy] == 0.0) continue;
-        const double *row = ec + (size_t(ci[2][jz]) * Pc + ci[1][jy]) * Pc;
-        double sx = 0.0;
-        for (int jx = 0; jx <= pc; ++jx) sx += wv[0][jx] * row[ci[0][jx]];
-        sy += wv[1][jy] * sx;
+  }
+  __syncthreads();
+  if (tid < CI * FO) {
+    const int fx = tid % FO, cz = tid / FO;
+    double v[CI];
+#pragma unroll
+    for (int i = 0; i < CI; ++i) v[i] = H1[(cz * CI + i) * (FO + 1) + fx];
+#pragma unroll
+    for (int fy = 0; fy < FO; ++fy) {
+      const int e = fy / NS, s = fy % NS;
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) a += tr.w[s * Q + j] * v[PC * e + j];
+      H2[(cz * FO + fy) * (FO + 1) + fx] = a;
+    }
+  }
+  __syncthreads();
+  if (tid < FO * FO) {
+    const int fx = tid % FO, fy = tid / FO;
+    double v[CI];
+#pragma unroll
+    for (int i = 0; i < CI; ++i) v[i] = H2[(i * FO + fy) * (FO + 1) + fx];
+    const int gx = NS * TE * tx + fx, gy = NS * TE * ty + fy;
+    if (gx < Pf && gy < Pf) {
+#pragma unroll
+      for (int fz = 0; fz < FO; ++fz) {
+        const int e = fz / NS, s = fz % NS;
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) a += tr.w[s * Q + j] * v[PC * e + j];
+        const int gz = NS * TE * tz + fz;
+        if (gz < Pf) xf[(size_t(gz) * Pf + gy) * Pf + gx] += a;
       }
-      acc += wv[2][jz] * sy;
     }
-    xf[g] += acc;
   }
 }
 
@@ -492,16 +621,16 @@ static int apply_impl(hipStream_t s, const LevelOp &op, const double *x, const d
 int launch_apply(hipStream_t s, const LevelOp &op, const double *x, const double *f, double *out, double *d,
                  double *xo, double c1, double c2, int mode, double *partial) {
   switch (op.p) {
-    case 1: return apply_impl<1, 8>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 1: return apply_impl<1, 14>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
     case 2: return apply_impl<2, 4>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
-    case 3: return apply_impl<3, 3>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 3: return apply_impl<3, 4>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
     case 5: return apply_impl<5, 2>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
     default: return -1;
   }
 }
 
 int apply_blocks(const LevelOp &op) {
-  int TE = op.p == 1 ? 8 : op.p == 2 ? 4 : op.p == 3 ? 3 : 2;
+  int TE = op.p == 1 ? 14 : op.p == 2 ? 4 : op.p == 3 ? 4 : 2;
   int tiles = (op.n + TE - 1) / TE;
   return tiles * tiles * tiles;
 }
@@ -510,13 +639,37 @@ void launch_cheb_first(hipStream_t s, const LevelOp &op, const double *f, double
   const size_t tot = size_t(op.P) * op.P * op.P;
   hipLaunchKernelGGL(k_cheb_first, dim3(grid_for(tot)), dim3(256), 0, s, op, f, d, x, c2);
 }
+template <int PF, int PC, int R, int TE>
+static void restrict_impl(hipStream_t s, const Transfer &tr, const double *in, double *out) {
+  const int tiles = (tr.nc + TE - 1) / TE;
+  hipLaunchKernelGGL((k_restrict<PF, PC, R, TE>), dim3(tiles * tiles * tiles), dim3(256), 0, s, tr, in, out);
+}
+template <int PF, int PC, int R, int TE>
+static void prolong_impl(hipStream_t s, const Transfer &tr, const double *in, double *out) {
+  const int tiles = (tr.nc + TE - 1) / TE;
+  hipLaunchKernelGGL((k_prolong_add<PF, PC, R, TE>), dim3(tiles * tiles * tiles), dim3(256), 0, s, tr, in, out);
+}
+
+// Supported transfers: p 5 -> 3 and 3 -> 1 on one mesh, Q1 coarsening by 2 or 3.
+int launch_transfer(hipStream_t s, const Transfer &tr, const double *in, double *out, bool restrict_) {
+  if (tr.pf == 5 && tr.pc == 3 && tr.r == 1) {
+    if (restrict_) restrict_impl<5, 3, 1, 2>(s, tr, in, out); else prolong_impl<5, 3, 1, 3>(s, tr, in, out);
+  } else if (tr.pf == 3 && tr.pc == 1 && tr.r == 1) {
+    if (restrict_) restrict_impl<3, 1, 1, 4>(s, tr, in, out); else prolong_impl<3, 1, 1, 5>(s, tr, in, out);
+  } else if (tr.pf == 1 && tr.pc == 1 && tr.r == 2) {
+    if (restrict_) restrict_impl<1, 1, 2, 7>(s, tr, in, out); else prolong_impl<1, 1, 2, 8>(s, tr, in, out);
+  } else if (tr.pf == 1 && tr.pc == 1 && tr.r == 3) {
+    if (restrict_) restrict_impl<1, 1, 3, 4>(s, tr, in, out); else prolong_impl<1, 1, 3, 5>(s, tr, in, out);
+  } else {
+    return -1;
+  }
+  return 0;
+}
 void launch_restrict(hipStream_t s, const Transfer &tr, const double *rf, double *fc) {
-  const size_t tot = size_t(tr.Pc) * tr.Pc * tr.Pc;
-  hipLaunchKernelGGL(k_restrict, dim3(grid_for(tot)), dim3(256), 0, s, tr, rf, fc);
+  launch_transfer(s, tr, rf, fc, true);
 }
 void launch_prolong_add(hipStream_t s, const Transfer &tr, const double *ec, double *xf) {
-  const size_t tot = size_t(tr.Pf) * tr.Pf * tr.Pf;
-  hipLaunchKernelGGL(k_prolong_add, dim3(grid_for(tot)), dim3(256), 0, s, tr, ec, xf);
+  launch_transfer(s, tr, ec, xf, false);
 }
 void launch_coarse_solve(hipStream_t s, int Pn, const double *V, const double *lam, const double *f, double *x) {
   hipLaunchKernelGGL(k_coarse_solve, dim3(1), dim3(256), 0, s, Pn, V, lam, f, x);

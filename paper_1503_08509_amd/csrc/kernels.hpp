@@ -45,6 +45,7 @@ int launch_apply(hipStream_t s, const LevelOp &op, const double *x, const double
                  double *xo, double c1, double c2, int mode, double *partial);
 int apply_blocks(const LevelOp &op);
 void launch_cheb_first(hipStream_t s, const LevelOp &op, const double *f, double *d, double *x, double c2);
+int launch_transfer(hipStream_t s, const Transfer &tr, const double *in, double *out, bool restrict_);
 void launch_restrict(hipStream_t s, const Transfer &tr, const double *rf, double *fc);
 void launch_prolong_add(hipStream_t s, const Transfer &tr, const double *ec, double *xf);
 void launch_coarse_solve(hipStream_t s, int Pn, const double *V, const double *lam, const double *f, double *x);
