@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--workload", default="uniform-1M-n64")
     ap.add_argument("--cpu-sample", type=int, default=1500, help="oracle target sample for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain device copy of 256 MiB (FETCH_SIZE/WRITE_SIZE calibration) and exit")
     return ap.parse_args()
 
 
@@ -100,6 +102,14 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        a = torch.empty(2**25, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        torch.cuda.synchronize()
+        c = a.clone()          # one copy kernel: reads and writes 2^25 doubles = 256 MiB each way
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": 2**25 * 8, "check": float(c[0].item())}))
+        return
 
     import paper_1503_08509_amd as fp
     import workloads

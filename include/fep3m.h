@@ -66,7 +66,7 @@ typedef struct {
   int32_t n_sr;          /* near block radius in elements (default 3: 7^3 block,
                             the paper's short-range list, Section 4)             */
   int32_t precision;     /* FEP3M_PRECISION_*                                    */
-  double  mg_rtol;       /* relative residual target of the mesh solve (1e-12)   */
+  double  mg_rtol;       /* relative residual target of the mesh solve (1e-10)   */
   int32_t mg_max_iter;   /* PCG iteration cap (60)                               */
   int32_t cheb_degree;   /* Chebyshev smoothing degree per V-cycle side (3)      */
   int32_t table_box;     /* elements per axis of the table domain, odd,
@@ -78,14 +78,16 @@ typedef struct {
   double  mg_rel_residual;   /* ||b - K phi|| / ||b|| reached                     */
   int64_t near_pairs;        /* ordered near pairs (i, j), j != i, of the last call */
   int32_t max_per_element;   /* largest element occupancy of the last call        */
+  int32_t adj_iterations;    /* PCG iterations of the second (adjoint) mesh solve */
   int32_t mg_levels;         /* levels of the multigrid hierarchy                */
   double  create_seconds;    /* wall time of create (tables, hierarchy)           */
 } fep3m_stats;
 
 /* Profile slots: stages of one call, the fine-level operator launches, and
  * the whole call.  `work` holds the algorithmic work of the slot: floating
- * point operations for NEAR (2 * 8 * (p+1)^3 per target element and near
- * offset) and PAIR (11 per ordered near pair), bytes that must cross HBM
+ * point operations for NEAR and ADJ_NEAR (2 * 8 * (p+1)^3 per element and
+ * near offset) and PAIR (11 per ordered near pair, 20 when forces are
+ * accumulated in the same pass), bytes that must cross HBM
  * for FINE_APPLY (the vectors each launch reads and writes, 8 bytes per DOF
  * each), 0 elsewhere. */
 enum {
@@ -97,7 +99,10 @@ enum {
   FEP3M_PROF_INTERP = 5,      /* interpolation, combination, energy         */
   FEP3M_PROF_FINE_APPLY = 6,  /* every fine-level operator launch           */
   FEP3M_PROF_TOTAL = 7,       /* whole call                                 */
-  FEP3M_PROF_SLOTS = 8
+  FEP3M_PROF_ADJ_SOLVE = 8,   /* forces: deposit, assembly, second mesh solve */
+  FEP3M_PROF_ADJ_NEAR = 9,    /* forces: moment adjoint (transposed near field) */
+  FEP3M_PROF_FORCES = 10,     /* forces: per-charge gradient and dU/dQ      */
+  FEP3M_PROF_SLOTS = 11
 };
 
 typedef struct {
@@ -132,6 +137,20 @@ int fep3m_potential(fep3m_ctx *ctx, const double *x, const double *Q, double *Ph
 /* Phi as above and U = 1/2 sum Q_i Phi_i written to U[0] (device pointer,
  * one double); the sum is a fixed-order float64 tree. */
 int fep3m_energy(fep3m_ctx *ctx, const double *x, const double *Q, double *Phi, double *U);
+
+/* Energy and forces (spec extension; the paper evaluates potentials
+ * only, Section 5).  U[0] = 1/2 sum Q_i Phi_i as in fep3m_energy, and the
+ * exact gradient of that discrete energy: F[3 i + k] = -dU/dx_ik (the
+ * near-pair term is recomputed in the pair pass, the mesh terms come from a
+ * deposit of the charges on the order-p basis, a second mesh solve and the
+ * transposed near-screen correlation).  The method's operators are not
+ * symmetric (no exact momentum conservation, Section 5), so sum_i F_i is
+ * not exactly zero and dU/dQ differs from Phi; U is discontinuous where a
+ * charge crosses an element face, and F is the gradient inside elements.
+ * Phi (length N) and dUdQ (length N) may be NULL.  All device pointers. */
+int fep3m_energy_forces(fep3m_ctx *ctx, const double *x, const double *Q, double *U, double *F);
+int fep3m_energy_forces_ex(fep3m_ctx *ctx, const double *x, const double *Q, double *Phi, double *U,
+                           double *F, double *dUdQ);
 
 /* Copy an internal stage of the last evaluation to the device buffer `out`
  * of `out_bytes` bytes (test and diagnostic use).  Stages:

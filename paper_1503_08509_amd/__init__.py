@@ -38,14 +38,16 @@ class Options(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("mg_iterations", ctypes.c_int32), ("mg_rel_residual", ctypes.c_double),
                 ("near_pairs", ctypes.c_int64), ("max_per_element", ctypes.c_int32),
+                ("adj_iterations", ctypes.c_int32),
                 ("mg_levels", ctypes.c_int32), ("create_seconds", ctypes.c_double)]
 
 
-PROF_SLOTS = ["sort", "assign", "solve", "near", "pair", "interp", "fine_apply", "total"]
+PROF_SLOTS = ["sort", "assign", "solve", "near", "pair", "interp", "fine_apply", "total",
+              "adj_solve", "adj_near", "forces"]
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("count", ctypes.c_int64 * 8), ("work", ctypes.c_double * 8)]
+    _fields_ = [("ms", ctypes.c_double * 11), ("count", ctypes.c_int64 * 11), ("work", ctypes.c_double * 11)]
 
 
 class FEP3MError(RuntimeError):
@@ -71,6 +73,8 @@ def lib():
         L.fep3m_set_stream.argtypes = [vp, vp]
         L.fep3m_potential.argtypes = [vp, vp, vp, vp]
         L.fep3m_energy.argtypes = [vp, vp, vp, vp, vp]
+        L.fep3m_energy_forces.argtypes = [vp, vp, vp, vp, vp]
+        L.fep3m_energy_forces_ex.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.fep3m_debug_stage.argtypes = [vp, i32, vp, i64]
         L.fep3m_stage_bytes.argtypes = [vp, i32]
         L.fep3m_stage_bytes.restype = i64
@@ -160,6 +164,24 @@ class Context:
         U = t.empty(1, dtype=t.float64, device=x.device)
         self._check(lib().fep3m_energy(self._h, x.data_ptr(), Q.data_ptr(), Phi.data_ptr(), U.data_ptr()))
         return Phi, U[0]
+
+    def energy_forces(self, x, Q, dUdQ=False, Phi=False):
+        """U (0-d), F [N,3] = -dU/dx and optionally dU/dQ [N] and Phi [N]."""
+        x, Q = self._prep(x, Q)
+        t = self._torch
+        U = t.empty(1, dtype=t.float64, device=x.device)
+        F = t.empty((self.N, 3), dtype=t.float64, device=x.device)
+        g = t.empty(self.N, dtype=t.float64, device=x.device) if dUdQ else None
+        P = t.empty(self.N, dtype=t.float64, device=x.device) if Phi else None
+        self._check(lib().fep3m_energy_forces_ex(self._h, x.data_ptr(), Q.data_ptr(),
+                                                 P.data_ptr() if P is not None else None, U.data_ptr(),
+                                                 F.data_ptr(), g.data_ptr() if g is not None else None))
+        out = {"U": U[0], "F": F}
+        if dUdQ:
+            out["dUdQ"] = g
+        if Phi:
+            out["Phi"] = P
+        return out
 
     def stage(self, name, device="cuda"):
         t = self._torch

@@ -95,6 +95,8 @@ struct fep3m_ctx {
   double *coarseV = nullptr, *coarseLam = nullptr;
   int coarseP = 0;
   double *b = nullptr, *sol = nullptr, *rr = nullptr, *pv = nullptr, *qv = nullptr;
+  // adjoint
+  double *gE = nullptr, *Gv = nullptr, *lam = nullptr, *Aadj = nullptr, *fpair = nullptr, *Phi_int = nullptr;
 
   template <class T>
   T *alloc(size_t count, const char *what) {
@@ -125,14 +127,15 @@ struct fep3m_ctx {
     if (prof.on) hip_check(hipEventRecord(prof.stage_ev[2 * slot + (begin ? 0 : 1)], stream), "event");
   }
   // fine-level operator launch, bracketed by events when profiling
-  int apply0(const double *x, const double *f, double *out, double *d, double *xo, double c1, double c2, int mode,
-             double *part) {
+  int apply0(const double *x, const double *f, double *out, const double *d, double *xo, double c1, double c2,
+             int mode, double *part) {
     const bool rec = prof.on && prof.kused < int(prof.kev.size()) / 2;
     if (rec) hip_check(hipEventRecord(prof.kev[2 * prof.kused], stream), "event");
     const int nb = launch_apply(stream, lv[0].op, x, f, out, d, xo, c1, c2, mode, part);
     if (rec) {
       hip_check(hipEventRecord(prof.kev[2 * prof.kused + 1], stream), "event");
-      const double vec = mode == kCheb ? 5.0 : mode == kResidual ? 3.0 : 2.0;  // vectors read + written
+      // vectors read + written: x, f, x_prev (when c1 != 0) and x_new; x, f, r; x, Kx
+      const double vec = mode == kCheb ? (c1 != 0.0 ? 4.0 : 3.0) : mode == kResidual ? 3.0 : 2.0;
       prof.kwork[prof.kused] = vec * 8.0 * double(lv[0].ndof);
       ++prof.kused;
     }
@@ -143,8 +146,10 @@ struct fep3m_ctx {
   void estimate_spectra();
   void vcycle(int l, const double *f);
   void cheb_smooth(int l, const double *f, bool zero_start);
-  void solve();
-  void evaluate(const double *x, const double *Qc, double *Phi, double *U);
+  void solve(const double *rhs, double *out);
+  void mesh_solve(double *rhs, double *out);
+  void evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F = nullptr,
+                double *dUdQ = nullptr);
 };
 
 // ----------------------------------------------------------------- create
@@ -301,6 +306,12 @@ void fep3m_ctx::build_mg() {
     }
   }
   const size_t nd0 = lv[0].ndof;
+  gE = alloc<double>(size_t(n) * n * n * (p + 1) * (p + 1) * (p + 1), "deposit");
+  Gv = alloc<double>(nd0, "adjoint load");
+  lam = alloc<double>(nd0, "adjoint potential");
+  Aadj = alloc<double>(size_t(n) * n * n * 8, "moment adjoint");
+  fpair = alloc<double>(3 * size_t(N), "pair forces");
+  Phi_int = alloc<double>(size_t(N), "potential (caller order)");
   b = alloc<double>(nd0, "load");
   sol = alloc<double>(nd0, "phi");
   rr = alloc<double>(nd0, "pcg r");
@@ -335,7 +346,7 @@ void fep3m_ctx::estimate_spectra() {
     launch_dot(stream, L_.ndof, L_.x, L_.x, partial);
     double nx = std::sqrt(reduce_host(red_grid(L_.ndof), partial, 0));
     for (int it = 0; it < 24; ++it) {
-      launch_apply(stream, L_.op, L_.x, nullptr, nullptr, L_.d, nullptr, 0.0, -1.0, kCheb, nullptr);
+      launch_apply(stream, L_.op, L_.x, nullptr, L_.d, nullptr, nullptr, 0.0, 0.0, kDinvApply, nullptr);
       launch_dot(stream, L_.ndof, L_.d, L_.d, partial);
       double nd = std::sqrt(reduce_host(red_grid(L_.ndof), partial, 0));
       lam = nd / nx;
@@ -367,10 +378,11 @@ void fep3m_ctx::cheb_smooth(int l, const double *f, bool zero_start) {
       rho = rn;
     }
     if (s == 0 && zero_start) {
-      launch_cheb_first(stream, L_.op, f, L_.d, L_.x, c2);
+      launch_cheb_first(stream, L_.op, f, L_.x2, L_.x, c2);   // x = c2 D^-1 f, x_prev (x2) = 0
     } else {
-      if (l == 0) apply0(L_.x, f, nullptr, L_.d, L_.x2, c1, c2, kCheb, nullptr);
-      else launch_apply(stream, L_.op, L_.x, f, nullptr, L_.d, L_.x2, c1, c2, kCheb, nullptr);
+      // x2 holds x_prev on entry and receives x_new; then the two swap
+      if (l == 0) apply0(L_.x, f, nullptr, L_.x2, L_.x2, c1, c2, kCheb, nullptr);
+      else launch_apply(stream, L_.op, L_.x, f, nullptr, L_.x2, L_.x2, c1, c2, kCheb, nullptr);
       std::swap(L_.x, L_.x2);
     }
   }
@@ -391,12 +403,13 @@ void fep3m_ctx::vcycle(int l, const double *f) {
   cheb_smooth(l, f, false);
 }
 
-void fep3m_ctx::solve() {
+// PCG on K out = rhs (rhs compatible), preconditioned by one V-cycle.
+void fep3m_ctx::solve(const double *rhs, double *sol) {
   MGLevel &L0 = lv[0];
   const size_t nd = L0.ndof;
-  hip_check(hipMemsetAsync(sol, 0, nd * sizeof(double), stream), "zero phi");
-  hip_check(hipMemcpyAsync(rr, b, nd * sizeof(double), hipMemcpyDeviceToDevice, stream), "copy r");
-  launch_dot(stream, nd, b, b, partial);
+  hip_check(hipMemsetAsync(sol, 0, nd * sizeof(double), stream), "zero solution");
+  hip_check(hipMemcpyAsync(rr, rhs, nd * sizeof(double), hipMemcpyDeviceToDevice, stream), "copy r");
+  launch_dot(stream, nd, rhs, rhs, partial);
   const double bnorm = std::sqrt(reduce_host(red_grid(nd), partial, 0));
   stats.mg_iterations = 0;
   stats.mg_rel_residual = 0.0;
@@ -427,9 +440,17 @@ void fep3m_ctx::solve() {
     throw Status(FEP3M_ERR_NOT_CONVERGED, "mesh solve reached relative residual " + std::to_string(rel));
 }
 
+// Gauge-fixed periodic solve: out = K^+ rhs with int out = 0.
+void fep3m_ctx::mesh_solve(double *rhs, double *out) {
+  solve(rhs, out);
+  launch_mass_dot(stream, n, p, w1, out, partial);
+  launch_sum_partials(stream, red_grid(lv[0].ndof), partial, scal + 5);
+  launch_sub_const(stream, lv[0].ndof, 1.0 / (double(n) * n * n), scal + 5, out);
+}
+
 // ----------------------------------------------------------------- evaluate
 
-void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U) {
+void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ) {
   const int M = n * n * n;
   prof.kused = 0;
   stage_mark(FEP3M_PROF_TOTAL, true);
@@ -461,16 +482,16 @@ void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double 
   check_launch("assignment");
   stage_mark(FEP3M_PROF_ASSIGN, false);
   stage_mark(FEP3M_PROF_SOLVE, true);
-  solve();
-  launch_mass_dot(stream, n, p, w1, sol, partial);
-  launch_sum_partials(stream, red_grid(lv[0].ndof), partial, scal + 5);
-  launch_sub_const(stream, lv[0].ndof, 1.0 / (double(n) * n * n), scal + 5, sol);
+  mesh_solve(b, sol);
+  const int fwd_iters = stats.mg_iterations;
+  const double fwd_rel = stats.mg_rel_residual;
   stage_mark(FEP3M_PROF_SOLVE, false);
   stage_mark(FEP3M_PROF_NEAR, true);
   if (launch_psi(stream, n, nsr, p, C, T, sol, Wel) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
   stage_mark(FEP3M_PROF_NEAR, false);
   stage_mark(FEP3M_PROF_PAIR, true);
-  if (launch_pair(stream, n, nsr, N, start, sg, sQ, phip_s) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "pair variant");
+  if (launch_pair(stream, n, nsr, N, start, sg, sQ, phip_s, F ? fpair : nullptr) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "pair variant");
   stage_mark(FEP3M_PROF_PAIR, false);
   stage_mark(FEP3M_PROF_INTERP, true);
   if (launch_interp(stream, p, n, N, 1.0 / h, bas, sg, Wel, phip_s, perm, phim_s, phi_s, Phi) != 0)
@@ -481,6 +502,26 @@ void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double 
     launch_half(stream, scal + 6, U);
   }
   stage_mark(FEP3M_PROF_INTERP, false);
+  if (F) {
+    // reverse pass: deposit, second mesh solve, moment adjoint, forces
+    stage_mark(FEP3M_PROF_ADJ_SOLVE, true);
+    launch_deposit(stream, p, n, N, bas, start, sg, sQ, gE);
+    launch_assemble(stream, p, n, gE, Gv, partial);
+    launch_sum_partials(stream, red_grid(lv[0].ndof), partial, scal + 7);
+    launch_sub_mass_ones(stream, n, p, w1, scal + 7, Gv);
+    mesh_solve(Gv, lam);
+    stage_mark(FEP3M_PROF_ADJ_SOLVE, false);
+    stage_mark(FEP3M_PROF_ADJ_NEAR, true);
+    if (launch_adj_moments(stream, p, n, nsr, gE, T, lam, gw, Aadj) != 0)
+      throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
+    stage_mark(FEP3M_PROF_ADJ_NEAR, false);
+    stage_mark(FEP3M_PROF_FORCES, true);
+    launch_forces(stream, p, n, N, 1.0 / h, bas, sg, sQ, Wel, Aadj, fpair, phip_s, phim_s, perm, F, dUdQ);
+    stage_mark(FEP3M_PROF_FORCES, false);
+    stats.adj_iterations = stats.mg_iterations;
+    stats.mg_iterations = fwd_iters;
+    stats.mg_rel_residual = fwd_rel;
+  }
   stage_mark(FEP3M_PROF_TOTAL, false);
   hip_check(hipMemsetAsync(paircount, 0, sizeof(unsigned long long), stream), "zero pair count");
   launch_pair_count(stream, n, nsr, start, paircount);
@@ -494,12 +535,13 @@ void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double 
   std::memcpy(&mc, host_scal + 9, sizeof(int));
   stats.near_pairs = int64_t(pc);
   stats.max_per_element = mc;
-  if (prof.on) profile_collect(U != nullptr);
+  if (prof.on) profile_collect(F != nullptr);
 }
 
-void fep3m_ctx::profile_collect(bool) {
+void fep3m_ctx::profile_collect(bool forces) {
   for (int s = 0; s < FEP3M_PROF_SLOTS; ++s) {
     if (s == FEP3M_PROF_FINE_APPLY) continue;
+    if (!forces && (s == FEP3M_PROF_ADJ_SOLVE || s == FEP3M_PROF_ADJ_NEAR || s == FEP3M_PROF_FORCES)) continue;
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, prof.stage_ev[2 * s], prof.stage_ev[2 * s + 1]), "elapsed");
     prof.acc.ms[s] += ms;
@@ -507,7 +549,9 @@ void fep3m_ctx::profile_collect(bool) {
   }
   const double S = 2 * nsr + 1;
   prof.acc.work[FEP3M_PROF_NEAR] += 2.0 * 8.0 * (p + 1) * (p + 1) * (p + 1) * S * S * S * double(n) * n * n;
-  prof.acc.work[FEP3M_PROF_PAIR] += 11.0 * double(stats.near_pairs);
+  prof.acc.work[FEP3M_PROF_PAIR] += (forces ? 20.0 : 11.0) * double(stats.near_pairs);
+  if (forces)
+    prof.acc.work[FEP3M_PROF_ADJ_NEAR] += 2.0 * 8.0 * (p + 1) * (p + 1) * (p + 1) * S * S * S * double(n) * n * n;
   for (int k = 0; k < prof.kused; ++k) {
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, prof.kev[2 * k], prof.kev[2 * k + 1]), "elapsed");
@@ -562,7 +606,7 @@ int fep3m_default_options(fep3m_options *opt) {
   if (!opt) return FEP3M_ERR_ARG;
   opt->n_sr = 3;
   opt->precision = FEP3M_PRECISION_FP64;
-  opt->mg_rtol = 1e-12;
+  opt->mg_rtol = 1e-10;
   opt->mg_max_iter = 60;
   opt->cheb_degree = 3;
   opt->table_box = 2 * 3 + 9;
@@ -613,6 +657,16 @@ int fep3m_potential(fep3m_ctx *ctx, const double *x, const double *Q, double *Ph
 int fep3m_energy(fep3m_ctx *ctx, const double *x, const double *Q, double *Phi, double *U) {
   if (!ctx || !x || !Q || !Phi || !U) return FEP3M_ERR_ARG;
   return guarded(ctx, [&] { ctx->evaluate(x, Q, Phi, U); });
+}
+
+int fep3m_energy_forces_ex(fep3m_ctx *ctx, const double *x, const double *Q, double *Phi, double *U, double *F,
+                           double *dUdQ) {
+  if (!ctx || !x || !Q || !U || !F) return FEP3M_ERR_ARG;
+  return guarded(ctx, [&] { ctx->evaluate(x, Q, Phi ? Phi : ctx->Phi_int, U, F, dUdQ); });
+}
+
+int fep3m_energy_forces(fep3m_ctx *ctx, const double *x, const double *Q, double *U, double *F) {
+  return fep3m_energy_forces_ex(ctx, x, Q, nullptr, U, F, nullptr);
 }
 
 int64_t fep3m_stage_bytes(const fep3m_ctx *ctx, int32_t stage) {

@@ -36,8 +36,9 @@ struct Transfer {
 enum ApplyMode : int {
   kApply = 0,      // out = K x
   kResidual = 1,   // out = f - K x
-  kCheb = 2,       // d = c1 d + c2 D^-1 (f - K x); xo = x + d
-  kApplyDot = 3    // out = K x, block partial of x . (K x)
+  kCheb = 2,       // xo = x + c1 (x - xprev) + c2 D^-1 (f - K x)   (xo may alias xprev)
+  kApplyDot = 3,   // out = K x, block partial of x . (K x)
+  kDinvApply = 4   // out = D^-1 K x
 };
 
 }  // namespace fep3m

@@ -1,0 +1,310 @@
+// Adjoint (reverse) pass of the discrete energy U = 1/2 sum Q_i Phi_i:
+// forces F = -dU/dx and dU/dQ.  In element units (g = x / h, U_hat = h U):
+//
+//   g_E[m]   = sum_{i in E} Q_i u_m(u_i)                    (charge deposit)
+//   G        = assembled g; lambda = gauge(K^+ compat(G))   (second mesh solve)
+//   A[E][a]  = 4 pi <lambda_E, G_a> - sum_D <g_{E+D}, T_a[D]>
+//   dU_hat/dg_i = Q_i sum_j Q_j (g_j - g_i)/r^3              (pair part)
+//               + 1/2 Q_i [ sum_m W_E[m] grad u_m(u_i) + sum_a A[E][a] grad u^a ]
+//   dU_hat/dQ_i = Phi_p + 1/2 Phi_m + 1/2 sum_a A[E][a] u_i^a
+//
+// with W_E = phi_E - Psi_E from the forward pass; F = -(1/h^2) dU_hat/dg.
+// The operators are not symmetric (the paper notes the lack of exact
+// momentum conservation), so dU/dQ differs from Phi.
+#include "kernels.hpp"
+
+namespace fep3m {
+
+__device__ __forceinline__ double block_sum_a(double v, double *red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// g_E[m] for one element per block: thread m sums over the element's charges.
+template <int PO>
+__global__ __launch_bounds__(256) void k_deposit(int n, int64_t N, GllBasis bas, const int *__restrict__ start,
+                                                 const double *__restrict__ sg, const double *__restrict__ sQ,
+                                                 double *__restrict__ gE) {
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
+  const int E = blockIdx.x;
+  const int m = threadIdx.x;
+  if (m >= NM) return;
+  const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
+  const int ex = E % n, ey = (E / n) % n, ez = E / (n * n);
+  double acc = 0.0;
+  for (int s = start[E]; s < start[E + 1]; ++s) {
+    const double ux = sg[s] - ex - 0.5, uy = sg[N + s] - ey - 0.5, uz = sg[2 * N + s] - ez - 0.5;
+    double lx = bas.w[mx], ly = bas.w[my], lz = bas.w[mz];
+#pragma unroll
+    for (int j = 0; j < Q1; ++j) {
+      if (j != mx) lx *= ux - bas.x[j];
+      if (j != my) ly *= uy - bas.x[j];
+      if (j != mz) lz *= uz - bas.x[j];
+    }
+    acc += sQ[s] * lx * ly * lz;
+  }
+  gE[size_t(E) * NM + m] = acc;
+}
+
+// G at each global node: sum of the owning elements' g values (gather form),
+// with block partials of sum G for the compatibility projection.
+template <int PO>
+__global__ __launch_bounds__(256) void k_assemble(int n, const double *__restrict__ gE, double *__restrict__ G,
+                                                  double *__restrict__ partial) {
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
+  __shared__ double red[256];
+  const int P = PO * n;
+  const size_t total = size_t(P) * P * P;
+  double acc = 0.0;
+  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
+    const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
+    int ex[2], kx[2], ey[2], ky[2], ez[2], kz[2];
+    int nx = 1, ny = 1, nz = 1;
+    ex[0] = gx / PO; kx[0] = gx % PO;
+    ey[0] = gy / PO; ky[0] = gy % PO;
+    ez[0] = gz / PO; kz[0] = gz % PO;
+    if (kx[0] == 0) { ex[1] = (ex[0] + n - 1) % n; kx[1] = PO; nx = 2; }
+    if (ky[0] == 0) { ey[1] = (ey[0] + n - 1) % n; ky[1] = PO; ny = 2; }
+    if (kz[0] == 0) { ez[1] = (ez[0] + n - 1) % n; kz[1] = PO; nz = 2; }
+    double s = 0.0;
+    for (int iz = 0; iz < nz; ++iz)
+      for (int iy = 0; iy < ny; ++iy)
+        for (int ix = 0; ix < nx; ++ix) {
+          const size_t E = size_t(ex[ix]) + size_t(n) * (ey[iy] + size_t(n) * ez[iz]);
+          s += gE[E * NM + (kz[iz] * Q1 + ky[iy]) * Q1 + kx[ix]];
+        }
+    G[g] = s;
+    acc += s;
+  }
+  double t = block_sum_a(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// A[E][a] = 4 pi <lambda_E, G_a> - sum_D <g_{E+D}, T_a[D]>.
+// Block = 4 x 4 x 4 brick of elements E; thread = 4 elements (a row along x)
+// x 8 moments, for one lane of a 16-node chunk; the deposits of the source
+// slab (fixed D_z) and the tables of the chunk are staged in LDS; the 16
+// node lanes are reduced at the end.
+template <int NSR, int PO>
+__global__ __launch_bounds__(256) void k_adj_moments(int n, const double *__restrict__ gE,
+                                                     const double *__restrict__ T, const double *__restrict__ lam,
+                                                     const double *__restrict__ gw, double *__restrict__ Aout) {
+  constexpr int BS = 4, H = BS + 2 * NSR, S = 2 * NSR + 1, ND = S * S * S;
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
+  constexpr int MC = 16;                         // nodes per chunk
+  constexpr int NCH = (NM + MC - 1) / MC;
+  constexpr int SLAB = BS * H * H;               // source elements of one D_z
+  __shared__ double Gs[MC * SLAB];               // [m][lz][hy][hx]
+  __shared__ double Ts[S * S * MC * 8];          // [Dyx][m][a]
+  const int bricks = (n + BS - 1) / BS;
+  int b = blockIdx.x;
+  const int bx = b % bricks;
+  b /= bricks;
+  const int by = b % bricks;
+  const int bz = b / bricks;
+  const int x0 = bx * BS, y0 = by * BS, z0 = bz * BS;
+  const int tid = threadIdx.x;
+  const int ml = tid % MC, eg = tid / MC;        // node lane, element group (16 rows)
+  const int ly = eg % BS, lz = eg / BS;          // the row: elements (0..3, ly, lz)
+  double acc[4][8];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) acc[e][a] = 0.0;
+
+  for (int Dz = -NSR; Dz <= NSR; ++Dz) {
+    for (int ch = 0; ch < NCH; ++ch) {
+      __syncthreads();
+      for (int i = tid; i < MC * SLAB; i += 256) {
+        const int h = i % SLAB, mm = i / SLAB;
+        const int m = ch * MC + mm;
+        const int hx = h % H, hy = (h / H) % H, hz = h / (H * H);
+        const int ex = (x0 - NSR + hx + 2 * n) % n, ey = (y0 - NSR + hy + 2 * n) % n;
+        const int ez = (z0 + hz + Dz + 2 * n) % n;
+        Gs[i] = m < NM ? gE[(size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NM + m] : 0.0;
+      }
+      for (int i = tid; i < S * S * MC * 8; i += 256) {
+        const int a = i % 8, mm = (i / 8) % MC, dyx = i / (8 * MC);
+        const int Dx = dyx % S - NSR, Dy = dyx / S - NSR;
+        const int m = ch * MC + mm;
+        const int iD = (Dx + NSR) + S * ((Dy + NSR) + S * (Dz + NSR));
+        Ts[i] = m < NM ? T[(size_t(a) * ND + iD) * NM + m] : 0.0;
+      }
+      __syncthreads();
+      for (int dyx = 0; dyx < S * S; ++dyx) {
+        const int Dx = dyx % S - NSR, Dy = dyx / S - NSR;
+        double tv[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) tv[a] = Ts[(dyx * MC + ml) * 8 + a];
+        const double *gr = Gs + ml * SLAB + (lz * H + (ly + Dy + NSR)) * H + (Dx + NSR);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double gv = gr[e];
+#pragma unroll
+          for (int a = 0; a < 8; ++a) acc[e][a] += tv[a] * gv;
+        }
+      }
+    }
+  }
+  // reduce the node lanes (xor shuffles within groups of 16 lanes)
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      double v = acc[e][a];
+      for (int off = MC / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      acc[e][a] = v;
+    }
+  // lane 0 of each row group parks the 32 sums in LDS (static indices)
+  __syncthreads();
+  double *red = Gs;  // [64 elements][8 moments], element = lx + 4 (ly + 4 lz)
+  if (ml == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int a = 0; a < 8; ++a) red[(e + 4 * eg) * 8 + a] = acc[e][a];
+  }
+  __syncthreads();
+  if (tid >= 64) return;
+  // thread tid finishes brick element tid: A = 4 pi <lambda_E, G_a> - sum
+  const int ex = x0 + (tid % 4), ey = y0 + ((tid / 4) % 4), ez = z0 + tid / 16;
+  if (ex >= n || ey >= n || ez >= n) return;
+  const int P = PO * n;
+  double a1[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int m = 0; m < NM; ++m) {
+    const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
+    const int gx = (PO * ex + mx) % P, gy = (PO * ey + my) % P, gz = (PO * ez + mz) % P;
+    const double lv = lam[(size_t(gz) * P + gy) * P + gx];
+    const double gx0 = gw[mx], gx1 = gw[Q1 + mx], gy0 = gw[my], gy1 = gw[Q1 + my], gz0 = gw[mz], gz1 = gw[Q1 + mz];
+    a1[0] += lv * gx0 * gy0 * gz0;
+    a1[1] += lv * gx1 * gy0 * gz0;
+    a1[2] += lv * gx0 * gy1 * gz0;
+    a1[3] += lv * gx1 * gy1 * gz0;
+    a1[4] += lv * gx0 * gy0 * gz1;
+    a1[5] += lv * gx1 * gy0 * gz1;
+    a1[6] += lv * gx0 * gy1 * gz1;
+    a1[7] += lv * gx1 * gy1 * gz1;
+  }
+  const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) Aout[E * 8 + a] = 4.0 * M_PI * a1[a] - red[tid * 8 + a];
+}
+
+// Forces and dU/dQ per sorted charge, scattered to caller order.
+template <int PO>
+__global__ __launch_bounds__(256) void k_forces(int n, int64_t N, double inv_h, GllBasis bas,
+                                                const double *__restrict__ sg, const double *__restrict__ sQ,
+                                                const double *__restrict__ Wel, const double *__restrict__ Aadj,
+                                                const double *__restrict__ fpair, const double *__restrict__ phip,
+                                                const double *__restrict__ phim_s, const int *__restrict__ perm,
+                                                double *__restrict__ F, double *__restrict__ dUdQ) {
+  constexpr int Q1 = PO + 1;
+  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < N; s += int64_t(gridDim.x) * blockDim.x) {
+    double l[3][Q1], dl[3][Q1], u[3];
+    int e[3];
+    for (int k = 0; k < 3; ++k) {
+      const double g = sg[k * N + s];
+      double ef = floor(g);
+      if (ef > double(n - 1)) ef = double(n - 1);
+      e[k] = int(ef);
+      u[k] = g - ef - 0.5;
+#pragma unroll
+      for (int a = 0; a < Q1; ++a) {
+        double v = bas.w[a], dv = 0.0;
+#pragma unroll
+        for (int j = 0; j < Q1; ++j) {
+          if (j == a) continue;
+          dv = dv * (u[k] - bas.x[j]) + v;   // product rule, running
+          v *= (u[k] - bas.x[j]);
+        }
+        l[k][a] = v;
+        dl[k][a] = dv;
+      }
+    }
+    const size_t E = size_t(e[0]) + size_t(n) * (e[1] + size_t(n) * e[2]);
+    const double *w = Wel + E * (Q1 * Q1 * Q1);
+    double gxs = 0.0, gys = 0.0, gzs = 0.0;
+#pragma unroll
+    for (int mz = 0; mz < Q1; ++mz) {
+      double sy_ll = 0.0, sy_dl = 0.0, sy_ld = 0.0;
+#pragma unroll
+      for (int my = 0; my < Q1; ++my) {
+        double rl = 0.0, rd = 0.0;
+#pragma unroll
+        for (int mx = 0; mx < Q1; ++mx) {
+          const double wv = w[(mz * Q1 + my) * Q1 + mx];
+          rl += l[0][mx] * wv;
+          rd += dl[0][mx] * wv;
+        }
+        sy_ll += l[1][my] * rl;   // x value, y value
+        sy_dl += l[1][my] * rd;   // x deriv, y value
+        sy_ld += dl[1][my] * rl;  // x value, y deriv
+      }
+      gxs += l[2][mz] * sy_dl;
+      gys += l[2][mz] * sy_ld;
+      gzs += dl[2][mz] * sy_ll;
+    }
+    const double *A = Aadj + E * 8;
+    const double ux = u[0], uy = u[1], uz = u[2];
+    // grad of u^a, a = ax + 2 ay + 4 az, each exponent 0 or 1
+    const double ax = A[1] + A[3] * uy + A[5] * uz + A[7] * uy * uz;
+    const double ay = A[2] + A[3] * ux + A[6] * uz + A[7] * ux * uz;
+    const double az = A[4] + A[5] * ux + A[6] * uy + A[7] * ux * uy;
+    const double au = A[0] + A[1] * ux + A[2] * uy + A[3] * ux * uy + A[4] * uz + A[5] * ux * uz + A[6] * uy * uz +
+                      A[7] * ux * uy * uz;
+    const double q = sQ[s];
+    const double s2 = inv_h * inv_h;
+    const int i = perm[s];
+    F[3 * size_t(i) + 0] = -s2 * (q * fpair[s] + 0.5 * q * (gxs + ax));
+    F[3 * size_t(i) + 1] = -s2 * (q * fpair[N + s] + 0.5 * q * (gys + ay));
+    F[3 * size_t(i) + 2] = -s2 * (q * fpair[2 * N + s] + 0.5 * q * (gzs + az));
+    if (dUdQ) dUdQ[i] = inv_h * phip[s] + 0.5 * phim_s[s] + 0.5 * inv_h * au;
+  }
+}
+
+// ----------------------------------------------------------------- launchers
+
+int launch_deposit(hipStream_t s, int p, int n, int64_t N, const GllBasis &bas, const int *start, const double *sg,
+                   const double *sQ, double *gE) {
+  if (p != 5) return -1;
+  hipLaunchKernelGGL(k_deposit<5>, dim3(n * n * n), dim3(256), 0, s, n, N, bas, start, sg, sQ, gE);
+  return 0;
+}
+int launch_assemble(hipStream_t s, int p, int n, const double *gE, double *G, double *partial) {
+  if (p != 5) return -1;
+  const size_t tot = size_t(p * n) * (p * n) * (p * n);
+  hipLaunchKernelGGL(k_assemble<5>, dim3(red_grid(tot)), dim3(256), 0, s, n, gE, G, partial);
+  return 0;
+}
+int launch_adj_moments(hipStream_t s, int p, int n, int nsr, const double *gE, const double *T, const double *lam,
+                       const double *gw, double *A) {
+  if (p != 5) return -1;
+  const int bricks = (n + 3) / 4;
+  dim3 g(bricks * bricks * bricks);
+  switch (nsr) {
+    case 1: hipLaunchKernelGGL((k_adj_moments<1, 5>), g, dim3(256), 0, s, n, gE, T, lam, gw, A); return 0;
+    case 2: hipLaunchKernelGGL((k_adj_moments<2, 5>), g, dim3(256), 0, s, n, gE, T, lam, gw, A); return 0;
+    case 3: hipLaunchKernelGGL((k_adj_moments<3, 5>), g, dim3(256), 0, s, n, gE, T, lam, gw, A); return 0;
+    default: return -1;
+  }
+}
+int launch_forces(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const double *sg,
+                  const double *sQ, const double *Wel, const double *A, const double *fpair, const double *phip,
+                  const double *phim_s, const int *perm, double *F, double *dUdQ) {
+  if (p != 5) return -1;
+  int64_t gb = (N + 255) / 256;
+  if (gb > 4096) gb = 4096;
+  hipLaunchKernelGGL(k_forces<5>, dim3(int(gb)), dim3(256), 0, s, n, N, inv_h, bas, sg, sQ, Wel, A, fpair, phip,
+                     phim_s, perm, F, dUdQ);
+  return 0;
+}
+
+}  // namespace fep3m

@@ -12,10 +12,8 @@
 
 namespace fep3m {
 
-__device__ __forceinline__ int wrapi(int i, int P) {
-  int r = i % P;
-  return r < 0 ? r + P : r;
-}
+// Periodic wrap of an index known to lie in [-P, 2P).
+__device__ __forceinline__ int wrapi(int i, int P) { return i < 0 ? i + P : (i >= P ? i - P : i); }
 
 __device__ __forceinline__ double block_sum(double v, double *red) {
   // Fixed-shape tree over the block (deterministic).
@@ -113,11 +111,31 @@ __global__ __launch_bounds__(256) void k_sub_const(size_t total, double invV, co
 // ----------------------------------------------------------------- operator
 
 
-// Tiles of the fine level are handed to the 8 XCDs in contiguous chunks so
-// that neighbouring tiles (which re-read each other's halos) share an L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-  if (nb % 8 != 0) return b;
-  return (b % 8) * (nb / 8) + b / 8;
+// Tile order.  Workgroups are dispatched round-robin over the 8 XCDs, each
+// with its own L2.  When the tile grid splits into octants of power-of-two
+// edge, XCD x takes octant x and walks it in Morton order, so the tiles that
+// re-read each other's halos run close together in time on one L2;
+// otherwise the order is linear (x fastest).
+__device__ __forceinline__ int compact_bits(int v) {  // every third bit
+  v &= 0x09249249;
+  v = (v ^ (v >> 2)) & 0x030c30c3;
+  v = (v ^ (v >> 4)) & 0x0300f00f;
+  v = (v ^ (v >> 8)) & 0xff0000ff;
+  v = (v ^ (v >> 16)) & 0x000003ff;
+  return v;
+}
+__device__ __forceinline__ void tile_coords(int b, int tiles, int &tx, int &ty, int &tz) {
+  const int half = tiles >> 1;
+  if ((tiles & 1) == 0 && half > 0 && (half & (half - 1)) == 0) {
+    const int xcd = b & 7, idx = b >> 3;
+    tx = compact_bits(idx) + half * (xcd & 1);
+    ty = compact_bits(idx >> 1) + half * ((xcd >> 1) & 1);
+    tz = compact_bits(idx >> 2) + half * (xcd >> 2);
+  } else {
+    tx = b % tiles;
+    ty = (b / tiles) % tiles;
+    tz = b / (tiles * tiles);
+  }
 }
 
 template <int PO, int TE>
@@ -158,6 +176,15 @@ __device__ __forceinline__ void band_apply(const double *__restrict__ a, const d
   }
 }
 
+template <int PO, int NOUT>
+__device__ __forceinline__ void band_apply_acc(const double *__restrict__ a, const double (&v)[NOUT + PO + 1],
+                                               double (&out)[NOUT]) {
+  double t[NOUT];
+  band_apply<PO, NOUT>(a, v, t);
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) out[o] += t[o];
+}
+
 // One tile of TE^3 elements per block: y = K x on the owned nodes, then the
 // mode's epilogue.  The owned nodes of a tile are p*e + k, k < p, for its
 // elements; the inputs reach one element below and one node above.
@@ -168,12 +195,13 @@ __device__ __forceinline__ void band_apply(const double *__restrict__ a, const d
 template <int PO, int TE>
 __global__ __launch_bounds__(256) void k_apply(LevelOp op, const double *__restrict__ x,
                                                const double *__restrict__ f, double *__restrict__ out,
-                                               double *__restrict__ dvec, double *__restrict__ xo, double c1,
-                                               double c2, int mode, double *__restrict__ partial) {
+                                               const double *xprev, double *xo, double c1, double c2, int mode,
+                                               double *__restrict__ partial) {
   using S = ApplyShape<PO, TE>;
   constexpr int O = S::O, I = S::I;
-  __shared__ double lds[S::LDS];
-  __shared__ double red[256];
+  __shared__ double lds[S::LDS];         // A, B; then C1, C2, Y; last the dot-product tree
+  __shared__ double invd[PO * PO * PO];  // 1 / diag(K) by local node index
+  __shared__ double Xo[O * O * O];       // x on the owned nodes (from the z-pass columns)
   double *A = lds;
   double *B = lds + O * S::SA;
   double *C1 = lds;
@@ -181,13 +209,32 @@ __global__ __launch_bounds__(256) void k_apply(LevelOp op, const double *__restr
   double *Y = lds + 2 * O * S::SC;
   const int P = op.P;
   const int tiles = (op.n + TE - 1) / TE;
-  int t = xcd_tile(blockIdx.x, gridDim.x);
-  const int tx = t % tiles;
-  t /= tiles;
-  const int ty = t % tiles;
-  const int tz = t / tiles;
+  int tx, ty, tz;
+  tile_coords(blockIdx.x, tiles, tx, ty, tz);
   const int ox0 = tx * O, oy0 = ty * O, oz0 = tz * O;
   const int tid = threadIdx.x;
+
+  // Epilogue operands of this thread's owned nodes, fetched now so their
+  // latency hides behind the three passes.
+  constexpr int NIT = (O * O * O + 255) / 256;
+  const bool need_f = (mode == kResidual) || (mode == kCheb);
+  const bool need_d = (mode == kCheb) && (c1 != 0.0);
+  for (int i = tid; i < PO * PO * PO; i += 256) {
+    const int kx = i % PO, ky = (i / PO) % PO, kz = i / (PO * PO);
+    invd[i] = 1.0 / (op.dk[kx] * op.dm[ky] * op.dm[kz] + op.dm[kx] * op.dk[ky] * op.dm[kz] +
+                     op.dm[kx] * op.dm[ky] * op.dk[kz]);
+  }
+  double pf_f[NIT], pf_d[NIT];
+#pragma unroll
+  for (int r = 0; r < NIT; ++r) {
+    const int li = tid + 256 * r;
+    const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
+    const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
+    const bool ok = li < O * O * O && gx < P && gy < P && gz < P;
+    const size_t g = ok ? (size_t(gz) * P + gy) * P + gx : 0;
+    pf_f[r] = (ok && need_f) ? f[g] : 0.0;
+    pf_d[r] = (ok && need_d) ? xprev[g] : 0.0;
+  }
 
   // pass z
   if (tid < I * I) {
@@ -196,14 +243,17 @@ __global__ __launch_bounds__(256) void k_apply(LevelOp op, const double *__restr
     double v[I];
 #pragma unroll
     for (int z = 0; z < I; ++z) v[z] = x[(size_t(wrapi(oz0 - PO + z, P)) * P + gy) * P + gx];
-    double a[O], b[O];
-    band_apply<PO, O>(op.me, v, a);
-    band_apply<PO, O>(op.ke, v, b);
+    if (lx >= PO && lx < PO + O && ly >= PO && ly < PO + O) {
 #pragma unroll
-    for (int oz = 0; oz < O; ++oz) {
-      A[oz * S::SA + tid] = a[oz];
-      B[oz * S::SA + tid] = b[oz];
+      for (int oz = 0; oz < O; ++oz) Xo[(oz * O + (ly - PO)) * O + (lx - PO)] = v[oz + PO];
     }
+    double a[O];
+    band_apply<PO, O>(op.me, v, a);
+#pragma unroll
+    for (int oz = 0; oz < O; ++oz) A[oz * S::SA + tid] = a[oz];
+    band_apply<PO, O>(op.ke, v, a);
+#pragma unroll
+    for (int oz = 0; oz < O; ++oz) B[oz * S::SA + tid] = a[oz];
   }
   __syncthreads();
   // pass y
@@ -211,18 +261,14 @@ __global__ __launch_bounds__(256) void k_apply(LevelOp op, const double *__restr
   const bool act2 = tid < O * I;
   const int oz2 = tid / I, lx2 = tid % I;
   if (act2) {
-    double va[I], vb[I];
+    double v[I];
 #pragma unroll
-    for (int y = 0; y < I; ++y) {
-      va[y] = A[oz2 * S::SA + y * I + lx2];
-      vb[y] = B[oz2 * S::SA + y * I + lx2];
-    }
-    double t1[O], t2[O];
-    band_apply<PO, O>(op.me, va, c1v);
-    band_apply<PO, O>(op.ke, va, t1);
-    band_apply<PO, O>(op.me, vb, t2);
+    for (int y = 0; y < I; ++y) v[y] = A[oz2 * S::SA + y * I + lx2];
+    band_apply<PO, O>(op.me, v, c1v);
+    band_apply<PO, O>(op.ke, v, c2v);
 #pragma unroll
-    for (int o = 0; o < O; ++o) c2v[o] = t1[o] + t2[o];
+    for (int y = 0; y < I; ++y) v[y] = B[oz2 * S::SA + y * I + lx2];
+    band_apply_acc<PO, O>(op.me, v, c2v);
   }
   __syncthreads();
   if (act2) {
@@ -236,61 +282,56 @@ __global__ __launch_bounds__(256) void k_apply(LevelOp op, const double *__restr
   // pass x
   if (tid < O * O) {
     const int oz = tid / O, oy = tid % O;
-    double v1[I], v2[I];
+    double v[I], yv[O];
 #pragma unroll
-    for (int xx = 0; xx < I; ++xx) {
-      v1[xx] = C1[oz * S::SC + oy * S::RS + xx];
-      v2[xx] = C2[oz * S::SC + oy * S::RS + xx];
-    }
-    double y1[O], y2[O];
-    band_apply<PO, O>(op.ke, v1, y1);
-    band_apply<PO, O>(op.me, v2, y2);
+    for (int xx = 0; xx < I; ++xx) v[xx] = C1[oz * S::SC + oy * S::RS + xx];
+    band_apply<PO, O>(op.ke, v, yv);
 #pragma unroll
-    for (int ox = 0; ox < O; ++ox) Y[(oz * O + oy) * S::YS + ox] = y1[ox] + y2[ox];
+    for (int xx = 0; xx < I; ++xx) v[xx] = C2[oz * S::SC + oy * S::RS + xx];
+    band_apply_acc<PO, O>(op.me, v, yv);
+#pragma unroll
+    for (int ox = 0; ox < O; ++ox) Y[(oz * O + oy) * S::YS + ox] = yv[ox];
   }
   __syncthreads();
   // epilogue on the owned nodes, x fastest
   double acc = 0.0;
-  for (int li = tid; li < O * O * O; li += 256) {
+#pragma unroll
+  for (int r = 0; r < NIT; ++r) {
+    const int li = tid + 256 * r;
     const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
     const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
-    if (gx >= P || gy >= P || gz >= P) continue;
-    const double y = Y[(oz * O + oy) * S::YS + ox];
+    const bool ok = li < O * O * O && gx < P && gy < P && gz < P;
+    const int lc = ok ? li : 0;
+    const int cx = lc % O, cy = (lc / O) % O, cz = lc / (O * O);
+    const double y = Y[(cz * O + cy) * S::YS + cx];
+    const double xv = Xo[lc];
+    const double rr = (pf_f[r] - y) * invd[(ox % PO) + PO * ((oy % PO) + PO * (oz % PO))];
     const size_t g = (size_t(gz) * P + gy) * P + gx;
-    if (mode == kApply) {
-      out[g] = y;
-    } else if (mode == kResidual) {
-      out[g] = f[g] - y;
-    } else if (mode == kCheb) {
-      const double D = op.dk[ox % PO] * op.dm[oy % PO] * op.dm[oz % PO] + op.dm[ox % PO] * op.dk[oy % PO] * op.dm[oz % PO] +
-                       op.dm[ox % PO] * op.dm[oy % PO] * op.dk[oz % PO];
-      const double fv = f ? f[g] : 0.0;
-      const double r = (fv - y) / D;
-      const double dn = (c1 != 0.0 ? c1 * dvec[g] : 0.0) + c2 * r;
-      dvec[g] = dn;
-      if (xo) xo[g] = x[g] + dn;
-    } else {  // kApplyDot
-      out[g] = y;
-      acc += x[g] * y;
+    if (ok) {
+      if (mode == kApply) out[g] = y;
+      else if (mode == kResidual) out[g] = pf_f[r] - y;
+      else if (mode == kCheb) xo[g] = xv + c1 * (xv - pf_d[r]) + c2 * rr;  // may overwrite x_prev
+      else if (mode == kDinvApply) out[g] = -rr;                            // f = 0 here: -rr = D^-1 K x
+      else { out[g] = y; acc += xv * y; }
     }
   }
   if (mode == kApplyDot) {
-    double s = block_sum(acc, red);
+    __syncthreads();  // every thread is done with Y before the tree reuses it
+    double s = block_sum(acc, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
   }
 }
 
-// First Chebyshev step from a zero iterate: x = d = c2 D^-1 f.
+// First Chebyshev step from a zero iterate: x = c2 D^-1 f, and x_prev = 0.
 __global__ __launch_bounds__(256) void k_cheb_first(LevelOp op, const double *__restrict__ f,
-                                                    double *__restrict__ d, double *__restrict__ x, double c2) {
+                                                    double *__restrict__ xprev, double *__restrict__ x, double c2) {
   const int P = op.P, p = op.p;
   const size_t total = size_t(P) * P * P;
   for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
     const int kx = int(g % P) % p, ky = int((g / P) % P) % p, kz = int(g / (size_t(P) * P)) % p;
     const double D = op.dk[kx] * op.dm[ky] * op.dm[kz] + op.dm[kx] * op.dk[ky] * op.dm[kz] + op.dm[kx] * op.dm[ky] * op.dk[kz];
-    const double v = c2 * f[g] / D;
-    d[g] = v;
-    x[g] = v;
+    x[g] = c2 * f[g] / D;
+    xprev[g] = 0.0;
   }
 }
 
@@ -310,13 +351,33 @@ struct XferShape {
   static constexpr int FO = NS * TE;           // owned fine nodes per axis (prolongation)
 };
 
+// 1-D restriction of a register column v (fine nodes of the tile, from one
+// coarse element below) to the CO owned coarse nodes.
+template <int PC, int NS, int CO, int NF>
+__device__ __forceinline__ void restrict_col(const double *__restrict__ w, const double (&v)[NF], double (&o)[CO]) {
+  constexpr int Q = PC + 1;
+#pragma unroll
+  for (int c = 0; c < CO; ++c) {
+    const int ec = c / PC, j = c % PC;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) s += w[q * Q + j] * v[NS * (ec + 1) + q];
+    if (j == 0) {
+#pragma unroll
+      for (int q = 0; q < NS; ++q) s += w[q * Q + PC] * v[NS * ec + q];
+    }
+    o[c] = s;
+  }
+}
+
 template <int PF, int PC, int R, int TE>
 __global__ __launch_bounds__(256) void k_restrict(Transfer tr, const double *__restrict__ rf, double *__restrict__ fc) {
   using S = XferShape<PF, PC, R, TE>;
-  constexpr int NS = S::NS, CO = S::CO, NF = S::NF, Q = PC + 1;
+  constexpr int NS = S::NS, CO = S::CO, NF = S::NF;
   static_assert(NF * NF <= 256 && NF * CO <= 256 && CO * CO <= 256, "restriction tile too large");
-  __shared__ double G1[NF * NF * (CO + 1)];
-  __shared__ double G2[NF * CO * (CO + 1)];
+  __shared__ double G1[CO * NF * (NF + 1)];   // [cz][fy][fx]
+  __shared__ double G2[CO * CO * (NF + 1)];   // [cz][cy][fx]
+  __shared__ double Out[CO * CO * CO];        // [cz][cy][cx]
   const int Pf = tr.Pf, Pc = tr.Pc;
   const int tiles = (tr.nc + TE - 1) / TE;
   int t = blockIdx.x;
@@ -325,84 +386,70 @@ __global__ __launch_bounds__(256) void k_restrict(Transfer tr, const double *__r
   const int ty = t % tiles;
   const int tz = t / tiles;
   const int tid = threadIdx.x;
-  // fine index of the first node read: one coarse element below the tile
   const int fx0 = NS * (tx * TE - 1), fy0 = NS * (ty * TE - 1), fz0 = NS * (tz * TE - 1);
-  // pass x: fine (z, y) row -> coarse x nodes
-  if (tid < NF * NF) {
-    const int fy = tid % NF, fz = tid / NF;
-    const double *row = rf + (size_t(wrapi(fz0 + fz, Pf)) * Pf + wrapi(fy0 + fy, Pf)) * Pf;
-    double v[NF];
+  if (tid < NF * NF) {  // pass z: one fine (x, y) column per thread, lanes along x
+    const int fx = tid % NF, fy = tid / NF;
+    const int gx = wrapi(fx0 + fx, Pf), gy = wrapi(fy0 + fy, Pf);
+    double v[NF], o[CO];
 #pragma unroll
-    for (int i = 0; i < NF; ++i) v[i] = row[wrapi(fx0 + i, Pf)];
+    for (int i = 0; i < NF; ++i) v[i] = rf[(size_t(wrapi(fz0 + i, Pf)) * Pf + gy) * Pf + gx];
+    restrict_col<PC, NS, CO, NF>(tr.w, v, o);
 #pragma unroll
-    for (int cx = 0; cx < CO; ++cx) {
-      const int ec = cx / PC, j = cx % PC;
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < NS; ++q) s += tr.w[q * Q + j] * v[NS * (ec + 1) + q];
-      if (j == 0) {
-#pragma unroll
-        for (int q = 0; q < NS; ++q) s += tr.w[q * Q + PC] * v[NS * ec + q];
-      }
-      G1[(fz * NF + fy) * (CO + 1) + cx] = s;
-    }
+    for (int c = 0; c < CO; ++c) G1[(c * NF + fy) * (NF + 1) + fx] = o[c];
   }
   __syncthreads();
-  // pass y: (fine z, coarse x) column -> coarse y nodes
-  if (tid < NF * CO) {
-    const int cx = tid % CO, fz = tid / CO;
-    double v[NF];
+  if (tid < CO * NF) {  // pass y
+    const int fx = tid % NF, cz = tid / NF;
+    double v[NF], o[CO];
 #pragma unroll
-    for (int i = 0; i < NF; ++i) v[i] = G1[(fz * NF + i) * (CO + 1) + cx];
+    for (int i = 0; i < NF; ++i) v[i] = G1[(cz * NF + i) * (NF + 1) + fx];
+    restrict_col<PC, NS, CO, NF>(tr.w, v, o);
 #pragma unroll
-    for (int cy = 0; cy < CO; ++cy) {
-      const int ec = cy / PC, j = cy % PC;
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < NS; ++q) s += tr.w[q * Q + j] * v[NS * (ec + 1) + q];
-      if (j == 0) {
-#pragma unroll
-        for (int q = 0; q < NS; ++q) s += tr.w[q * Q + PC] * v[NS * ec + q];
-      }
-      G2[(fz * CO + cy) * (CO + 1) + cx] = s;
-    }
+    for (int c = 0; c < CO; ++c) G2[(cz * CO + c) * (NF + 1) + fx] = o[c];
   }
   __syncthreads();
-  // pass z: (coarse y, coarse x) column -> coarse z nodes, written out
-  if (tid < CO * CO) {
-    const int cx = tid % CO, cy = tid / CO;
-    double v[NF];
+  if (tid < CO * CO) {  // pass x
+    const int cy = tid % CO, cz = tid / CO;
+    double v[NF], o[CO];
 #pragma unroll
-    for (int i = 0; i < NF; ++i) v[i] = G2[(i * CO + cy) * (CO + 1) + cx];
-    const int gx = tx * CO + cx, gy = ty * CO + cy;
-    if (gx < Pc && gy < Pc) {
+    for (int i = 0; i < NF; ++i) v[i] = G2[(cz * CO + cy) * (NF + 1) + i];
+    restrict_col<PC, NS, CO, NF>(tr.w, v, o);
 #pragma unroll
-      for (int cz = 0; cz < CO; ++cz) {
-        const int ec = cz / PC, j = cz % PC;
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < NS; ++q) s += tr.w[q * Q + j] * v[NS * (ec + 1) + q];
-        if (j == 0) {
-#pragma unroll
-          for (int q = 0; q < NS; ++q) s += tr.w[q * Q + PC] * v[NS * ec + q];
-        }
-        const int gz = tz * CO + cz;
-        if (gz < Pc) fc[(size_t(gz) * Pc + gy) * Pc + gx] = s;
-      }
-    }
+    for (int c = 0; c < CO; ++c) Out[(cz * CO + cy) * CO + c] = o[c];
+  }
+  __syncthreads();
+  for (int li = tid; li < CO * CO * CO; li += 256) {
+    const int cx = li % CO, cy = (li / CO) % CO, cz = li / (CO * CO);
+    const int gx = tx * CO + cx, gy = ty * CO + cy, gz = tz * CO + cz;
+    if (gx < Pc && gy < Pc && gz < Pc) fc[(size_t(gz) * Pc + gy) * Pc + gx] = Out[li];
   }
 }
 
-// xf += P ec on a tile of TE^3 coarse elements: the fine nodes s of coarse
-// element e take sum_j w[s][j] ec[PC e + j] along each axis (three passes).
+// 1-D prolongation of a coarse register column (CI nodes from the tile's
+// first coarse node) to the FO owned fine nodes.
+template <int PC, int NS, int CI, int FO>
+__device__ __forceinline__ void prolong_col(const double *__restrict__ w, const double (&v)[CI], double (&o)[FO]) {
+  constexpr int Q = PC + 1;
+#pragma unroll
+  for (int f = 0; f < FO; ++f) {
+    const int e = f / NS, s = f % NS;
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) a += w[s * Q + j] * v[PC * e + j];
+    o[f] = a;
+  }
+}
+
+// xf += P ec on a tile of TE^3 coarse elements (three separable passes).
 template <int PF, int PC, int R, int TE>
 __global__ __launch_bounds__(256) void k_prolong_add(Transfer tr, const double *__restrict__ ec,
                                                      double *__restrict__ xf) {
   using S = XferShape<PF, PC, R, TE>;
-  constexpr int NS = S::NS, CI = S::CI, FO = S::FO, Q = PC + 1;
+  constexpr int NS = S::NS, CI = S::CI, FO = S::FO;
   static_assert(CI * CI <= 256 && CI * FO <= 256 && FO * FO <= 256, "prolongation tile too large");
-  __shared__ double H1[CI * CI * (FO + 1)];
-  __shared__ double H2[CI * FO * (FO + 1)];
+  __shared__ double H1[FO * CI * (CI + 1)];   // [fz][cy][cx]
+  __shared__ double H2[FO * FO * (CI + 1)];   // [fz][fy][cx]
+  __shared__ double Out[FO * FO * FO];        // [fz][fy][fx]
   const int Pf = tr.Pf, Pc = tr.Pc;
   const int tiles = (tr.nc + TE - 1) / TE;
   int t = blockIdx.x;
@@ -412,54 +459,53 @@ __global__ __launch_bounds__(256) void k_prolong_add(Transfer tr, const double *
   const int tz = t / tiles;
   const int tid = threadIdx.x;
   const int cx0 = PC * TE * tx, cy0 = PC * TE * ty, cz0 = PC * TE * tz;
-  if (tid < CI * CI) {
-    const int cy = tid % CI, cz = tid / CI;
-    const double *row = ec + (size_t(wrapi(cz0 + cz, Pc)) * Pc + wrapi(cy0 + cy, Pc)) * Pc;
-    double v[CI];
+  constexpr int NIT = (FO * FO * FO + 255) / 256;
+  double pf[NIT];  // fine values to update, fetched before the passes
 #pragma unroll
-    for (int i = 0; i < CI; ++i) v[i] = row[wrapi(cx0 + i, Pc)];
+  for (int r = 0; r < NIT; ++r) {
+    const int li = tid + 256 * r;
+    const int fx = li % FO, fy = (li / FO) % FO, fz = li / (FO * FO);
+    const int gx = NS * TE * tx + fx, gy = NS * TE * ty + fy, gz = NS * TE * tz + fz;
+    const bool ok = li < FO * FO * FO && gx < Pf && gy < Pf && gz < Pf;
+    pf[r] = ok ? xf[(size_t(gz) * Pf + gy) * Pf + gx] : 0.0;
+  }
+  if (tid < CI * CI) {  // pass z
+    const int cx = tid % CI, cy = tid / CI;
+    const int gx = wrapi(cx0 + cx, Pc), gy = wrapi(cy0 + cy, Pc);
+    double v[CI], o[FO];
 #pragma unroll
-    for (int fx = 0; fx < FO; ++fx) {
-      const int e = fx / NS, s = fx % NS;
-      double a = 0.0;
+    for (int i = 0; i < CI; ++i) v[i] = ec[(size_t(wrapi(cz0 + i, Pc)) * Pc + gy) * Pc + gx];
+    prolong_col<PC, NS, CI, FO>(tr.w, v, o);
 #pragma unroll
-      for (int j = 0; j < Q; ++j) a += tr.w[s * Q + j] * v[PC * e + j];
-      H1[(cz * CI + cy) * (FO + 1) + fx] = a;
-    }
+    for (int f = 0; f < FO; ++f) H1[(f * CI + cy) * (CI + 1) + cx] = o[f];
   }
   __syncthreads();
-  if (tid < CI * FO) {
-    const int fx = tid % FO, cz = tid / FO;
-    double v[CI];
+  if (tid < FO * CI) {  // pass y
+    const int cx = tid % CI, fz = tid / CI;
+    double v[CI], o[FO];
 #pragma unroll
-    for (int i = 0; i < CI; ++i) v[i] = H1[(cz * CI + i) * (FO + 1) + fx];
+    for (int i = 0; i < CI; ++i) v[i] = H1[(fz * CI + i) * (CI + 1) + cx];
+    prolong_col<PC, NS, CI, FO>(tr.w, v, o);
 #pragma unroll
-    for (int fy = 0; fy < FO; ++fy) {
-      const int e = fy / NS, s = fy % NS;
-      double a = 0.0;
-#pragma unroll
-      for (int j = 0; j < Q; ++j) a += tr.w[s * Q + j] * v[PC * e + j];
-      H2[(cz * FO + fy) * (FO + 1) + fx] = a;
-    }
+    for (int f = 0; f < FO; ++f) H2[(fz * FO + f) * (CI + 1) + cx] = o[f];
   }
   __syncthreads();
-  if (tid < FO * FO) {
-    const int fx = tid % FO, fy = tid / FO;
-    double v[CI];
+  if (tid < FO * FO) {  // pass x
+    const int fy = tid % FO, fz = tid / FO;
+    double v[CI], o[FO];
 #pragma unroll
-    for (int i = 0; i < CI; ++i) v[i] = H2[(i * FO + fy) * (FO + 1) + fx];
-    const int gx = NS * TE * tx + fx, gy = NS * TE * ty + fy;
-    if (gx < Pf && gy < Pf) {
+    for (int i = 0; i < CI; ++i) v[i] = H2[(fz * FO + fy) * (CI + 1) + i];
+    prolong_col<PC, NS, CI, FO>(tr.w, v, o);
 #pragma unroll
-      for (int fz = 0; fz < FO; ++fz) {
-        const int e = fz / NS, s = fz % NS;
-        double a = 0.0;
+    for (int f = 0; f < FO; ++f) Out[(fz * FO + fy) * FO + f] = o[f];
+  }
+  __syncthreads();
 #pragma unroll
-        for (int j = 0; j < Q; ++j) a += tr.w[s * Q + j] * v[PC * e + j];
-        const int gz = NS * TE * tz + fz;
-        if (gz < Pf) xf[(size_t(gz) * Pf + gy) * Pf + gx] += a;
-      }
-    }
+  for (int r = 0; r < NIT; ++r) {
+    const int li = tid + 256 * r;
+    const int fx = li % FO, fy = (li / FO) % FO, fz = li / (FO * FO);
+    const int gx = NS * TE * tx + fx, gy = NS * TE * ty + fy, gz = NS * TE * tz + fz;
+    if (li < FO * FO * FO && gx < Pf && gy < Pf && gz < Pf) xf[(size_t(gz) * Pf + gy) * Pf + gx] = pf[r] + Out[li];
   }
 }
 
@@ -610,32 +656,33 @@ void launch_sub_const(hipStream_t s, size_t total, double invV, const double *sc
 }
 
 template <int PO, int TE>
-static int apply_impl(hipStream_t s, const LevelOp &op, const double *x, const double *f, double *out, double *d,
-                      double *xo, double c1, double c2, int mode, double *partial) {
+static int apply_impl(hipStream_t s, const LevelOp &op, const double *x, const double *f, double *out,
+                      const double *d, double *xo, double c1, double c2, int mode, double *partial) {
   const int tiles = (op.n + TE - 1) / TE;
   const int nb = tiles * tiles * tiles;
   hipLaunchKernelGGL((k_apply<PO, TE>), dim3(nb), dim3(256), 0, s, op, x, f, out, d, xo, c1, c2, mode, partial);
   return nb;
 }
 
-int launch_apply(hipStream_t s, const LevelOp &op, const double *x, const double *f, double *out, double *d,
-                 double *xo, double c1, double c2, int mode, double *partial) {
+int launch_apply(hipStream_t s, const LevelOp &op, const double *x, const double *f, double *out,
+                 const double *d, double *xo, double c1, double c2, int mode, double *partial) {
   switch (op.p) {
-    case 1: return apply_impl<1, 14>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 1: return apply_impl<1, 8>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
     case 2: return apply_impl<2, 4>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
-    case 3: return apply_impl<3, 4>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 3: return apply_impl<3, 3>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
     case 5: return apply_impl<5, 2>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
     default: return -1;
   }
 }
 
 int apply_blocks(const LevelOp &op) {
-  int TE = op.p == 1 ? 14 : op.p == 2 ? 4 : op.p == 3 ? 4 : 2;
+  int TE = op.p == 1 ? 8 : op.p == 2 ? 4 : op.p == 3 ? 3 : 2;
   int tiles = (op.n + TE - 1) / TE;
   return tiles * tiles * tiles;
 }
 
 void launch_cheb_first(hipStream_t s, const LevelOp &op, const double *f, double *d, double *x, double c2) {
+  // d receives x_prev = 0
   const size_t tot = size_t(op.P) * op.P * op.P;
   hipLaunchKernelGGL(k_cheb_first, dim3(grid_for(tot)), dim3(256), 0, s, op, f, d, x, c2);
 }
@@ -653,7 +700,7 @@ static void prolong_impl(hipStream_t s, const Transfer &tr, const double *in, do
 // Supported transfers: p 5 -> 3 and 3 -> 1 on one mesh, Q1 coarsening by 2 or 3.
 int launch_transfer(hipStream_t s, const Transfer &tr, const double *in, double *out, bool restrict_) {
   if (tr.pf == 5 && tr.pc == 3 && tr.r == 1) {
-    if (restrict_) restrict_impl<5, 3, 1, 2>(s, tr, in, out); else prolong_impl<5, 3, 1, 3>(s, tr, in, out);
+    if (restrict_) restrict_impl<5, 3, 1, 2>(s, tr, in, out); else prolong_impl<5, 3, 1, 2>(s, tr, in, out);
   } else if (tr.pf == 3 && tr.pc == 1 && tr.r == 1) {
     if (restrict_) restrict_impl<3, 1, 1, 4>(s, tr, in, out); else prolong_impl<3, 1, 1, 5>(s, tr, in, out);
   } else if (tr.pf == 1 && tr.pc == 1 && tr.r == 2) {

@@ -7,29 +7,39 @@
 // screens of every element in E's near block (D = 0 is the self term).  The
 // kernel writes W_E = phi_E - Psi_E, the field the charges of E interpolate.
 //
-// Block = a 4 x 4 x 4 brick of target elements and 8 wavefronts: lane l of
-// every wave owns target element l of the brick, wave w owns the 27 nodes
-// m = 27 w .. 27 w + 26.  The moments C of the brick's halo
-// ((4 + 2 NSR)^3 elements) sit in LDS; the tables are streamed through LDS
-// one offset D at a time and read as wave-uniform broadcasts, so every table
-// value fetched from L2 feeds 64 target elements.
+// Work decomposition (a dense contraction over (D, a) with an implicit,
+// gathered left operand):
+//   block  = a 4 x 4 x 4 brick of target elements,
+//   thread = 8 target elements (a 2 x 2 x 2 sub-brick) x 8 nodes m, held as
+//            64 float64 accumulators; 216 of 256 threads compute,
+//   tables T[.][D][.] (8 x 216 values per offset) stream through a double
+//            LDS buffer, prefetched one offset ahead into registers, one
+//            barrier per offset; every table value fetched from L2 serves the
+//            brick's 64 elements,
+//   moments C of the source elements sit in LDS as one z-slab per D_z.
 #include "kernels.hpp"
 
 namespace fep3m {
 
 template <int NSR, int PO>
-__global__ __launch_bounds__(512) void k_psi(int n, const double *__restrict__ C, const double *__restrict__ T,
+__global__ __launch_bounds__(256) void k_psi(int n, const double *__restrict__ C, const double *__restrict__ T,
                                              const double *__restrict__ phi, double *__restrict__ Wel) {
   constexpr int BS = 4;                       // brick edge (elements)
-  constexpr int H = BS + 2 * NSR;             // halo edge
-  constexpr int H3 = H * H * H;
+  constexpr int H = BS + 2 * NSR;             // halo edge in x and y
   constexpr int S = 2 * NSR + 1;
   constexpr int ND = S * S * S;
   constexpr int Q1 = PO + 1;
-  constexpr int NM = Q1 * Q1 * Q1;            // 216 for p = 5
-  constexpr int MW = (NM + 7) / 8;            // nodes per wave
-  __shared__ double Cs[8 * H3];
-  __shared__ double Ts[8 * NM];
+  constexpr int NM = Q1 * Q1 * Q1;            // nodes per element (216 for p = 5)
+  constexpr int MT = 8;                       // nodes per thread
+  constexpr int NGM = NM / MT;                // node groups
+  constexpr int NTHR = 8 * NGM;               // computing threads
+  constexpr int TV = 8 * NM;                  // table values per offset
+  constexpr int TPF = (TV + 255) / 256;       // prefetch registers per thread
+  constexpr int SLAB = BS * H * H;            // one z-slab of the halo
+  static_assert(NM % MT == 0 && NTHR <= 256, "thread tile");
+  __shared__ __align__(16) double Ts[2][TV];
+  __shared__ __align__(16) double Cs[8 * SLAB];
+
   const int bricks = (n + BS - 1) / BS;
   int b = blockIdx.x;
   const int bx = b % bricks;
@@ -37,49 +47,96 @@ __global__ __launch_bounds__(512) void k_psi(int n, const double *__restrict__ C
   const int by = b % bricks;
   const int bz = b / bricks;
   const int x0 = bx * BS, y0 = by * BS, z0 = bz * BS;
-  for (int h = threadIdx.x; h < H3; h += blockDim.x) {
-    const int hx = h % H, hy = (h / H) % H, hz = h / (H * H);
-    const int ex = (x0 - NSR + hx + 2 * n) % n, ey = (y0 - NSR + hy + 2 * n) % n, ez = (z0 - NSR + hz + 2 * n) % n;
-    const double *c = C + (size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * 8;
+  const int tid = threadIdx.x;
+  const bool comp = tid < NTHR;
+  const int ge = tid % 8, gm = tid / 8;
+  const int ex0 = 2 * (ge & 1), ey0 = 2 * ((ge >> 1) & 1), ez0 = 2 * (ge >> 2);
+  const int m0 = gm * MT;
+
+  double acc[8][MT];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) Cs[a * H3 + h] = c[a];
+  for (int e = 0; e < 8; ++e)
+#pragma unroll
+    for (int j = 0; j < MT; ++j) acc[e][j] = 0.0;
+
+  // table values of offset 0 into buffer 0
+  for (int i = tid; i < TV; i += 256) {
+    const int a = i / NM, m = i % NM;
+    Ts[0][i] = T[(size_t(a) * ND + 0) * NM + m];
   }
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lx = lane % BS, ly = (lane / BS) % BS, lz = lane / (BS * BS);
-  const int m0 = wave * MW;
-  double acc[MW];
-#pragma unroll
-  for (int j = 0; j < MW; ++j) acc[j] = 0.0;
-  for (int iD = 0; iD < ND; ++iD) {
+  int iD = 0;
+  for (int Dz = -NSR; Dz <= NSR; ++Dz) {
+    // stage the moments of the source slab for this D_z: target layer lz
+    // reads halo layer lz - Dz + NSR
     __syncthreads();
-    for (int i = threadIdx.x; i < 8 * NM; i += blockDim.x) {
-      const int a = i / NM, m = i % NM;
-      Ts[i] = T[(size_t(a) * ND + iD) * NM + m];
+    for (int h = tid; h < SLAB; h += 256) {
+      const int hx = h % H, hy = (h / H) % H, lz = h / (H * H);
+      const int ex = (x0 - NSR + hx + 2 * n) % n, ey = (y0 - NSR + hy + 2 * n) % n;
+      const int ez = (z0 + lz - Dz + 2 * n) % n;
+      const double *c = C + (size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * 8;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) Cs[a * SLAB + h] = c[a];
     }
     __syncthreads();
-    const int Dx = iD % S - NSR, Dy = (iD / S) % S - NSR, Dz = iD / (S * S) - NSR;
-    const int h = (lx - Dx + NSR) + H * ((ly - Dy + NSR) + H * (lz - Dz + NSR));
+    for (int Dyx = 0; Dyx < S * S; ++Dyx, ++iD) {
+      const int Dx = Dyx % S - NSR, Dy = Dyx / S - NSR;
+      const int cur = iD & 1;
+      // prefetch the next offset's tables into registers
+      double tp[TPF];
+      const bool more = iD + 1 < ND;
+      if (more) {
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const double c = Cs[a * H3 + h];
-      const double *t = Ts + a * NM + m0;
+        for (int r = 0; r < TPF; ++r) {
+          const int i = tid + 256 * r;
+          if (i < TV) {
+            const int a = i / NM, m = i % NM;
+            tp[r] = T[(size_t(a) * ND + iD + 1) * NM + m];
+          }
+        }
+      }
+      if (comp) {
+        const double *tb = Ts[cur];
 #pragma unroll
-      for (int j = 0; j < MW; ++j)
-        if (m0 + j < NM) acc[j] += t[j] * c;
+        for (int a = 0; a < 8; ++a) {
+          double tv[MT];
+#pragma unroll
+          for (int j = 0; j < MT; ++j) tv[j] = tb[a * NM + m0 + j];
+          double cv[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int lx = ex0 + (e & 1), ly = ey0 + ((e >> 1) & 1), lz = ez0 + (e >> 2);
+            cv[e] = Cs[a * SLAB + (lz * H + (ly - Dy + NSR)) * H + (lx - Dx + NSR)];
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+#pragma unroll
+            for (int j = 0; j < MT; ++j) acc[e][j] += tv[j] * cv[e];
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int r = 0; r < TPF; ++r) {
+          const int i = tid + 256 * r;
+          if (i < TV) Ts[cur ^ 1][i] = tp[r];
+        }
+      }
+      __syncthreads();
     }
   }
-  const int ex = x0 + lx, ey = y0 + ly, ez = z0 + lz;
-  if (ex >= n || ey >= n || ez >= n) return;
+  if (!comp) return;
   const int P = PO * n;
-  const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
 #pragma unroll
-  for (int j = 0; j < MW; ++j) {
-    const int m = m0 + j;
-    if (m >= NM) break;
-    const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
-    const int gx = (PO * ex + mx) % P, gy = (PO * ey + my) % P, gz = (PO * ez + mz) % P;
-    Wel[E * NM + m] = phi[(size_t(gz) * P + gy) * P + gx] - acc[j];
+  for (int e = 0; e < 8; ++e) {
+    const int ex = x0 + ex0 + (e & 1), ey = y0 + ey0 + ((e >> 1) & 1), ez = z0 + ez0 + (e >> 2);
+    if (ex >= n || ey >= n || ez >= n) continue;
+    const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
+#pragma unroll
+    for (int j = 0; j < MT; ++j) {
+      const int m = m0 + j;
+      const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
+      const int gx = (PO * ex + mx) % P, gy = (PO * ey + my) % P, gz = (PO * ez + mz) % P;
+      Wel[E * NM + m] = phi[(size_t(gz) * P + gy) * P + gx] - acc[e][j];
+    }
   }
 }
 
@@ -88,9 +145,9 @@ int launch_psi(hipStream_t s, int n, int nsr, int p, const double *C, const doub
   const int bricks = (n + 3) / 4;
   dim3 g(bricks * bricks * bricks);
   switch (nsr) {
-    case 1: hipLaunchKernelGGL((k_psi<1, 5>), g, dim3(512), 0, s, n, C, T, phi, Wel); return 0;
-    case 2: hipLaunchKernelGGL((k_psi<2, 5>), g, dim3(512), 0, s, n, C, T, phi, Wel); return 0;
-    case 3: hipLaunchKernelGGL((k_psi<3, 5>), g, dim3(512), 0, s, n, C, T, phi, Wel); return 0;
+    case 1: hipLaunchKernelGGL((k_psi<1, 5>), g, dim3(256), 0, s, n, C, T, phi, Wel); return 0;
+    case 2: hipLaunchKernelGGL((k_psi<2, 5>), g, dim3(256), 0, s, n, C, T, phi, Wel); return 0;
+    case 3: hipLaunchKernelGGL((k_psi<3, 5>), g, dim3(256), 0, s, n, C, T, phi, Wel); return 0;
     default: return -1;
   }
 }

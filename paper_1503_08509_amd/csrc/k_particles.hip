@@ -162,11 +162,13 @@ __global__ __launch_bounds__(256) void k_moments(int n, int64_t N, const int *__
 // and accumulates for a chunk of up to kTgt targets, then the wave reduces.
 // Displacements are formed in the target's unwrapped frame in element
 // units, so no minimum-image test is needed (n >= 2 NSR + 1).
+// With FORCE the same pass also accumulates sum_j Q_j (g_j - g_i) / r^3
+// (fpair, 3 x N sorted), the pair part of dU/dg_i divided by Q_i.
 constexpr int kTgt = 8;
-template <int NSR>
+template <int NSR, bool FORCE>
 __global__ __launch_bounds__(64) void k_pair(int n, int64_t N, const int *__restrict__ start,
                                              const double *__restrict__ sg, const double *__restrict__ sQ,
-                                             double *__restrict__ phip) {
+                                             double *__restrict__ phip, double *__restrict__ fpair) {
   constexpr int W = 2 * NSR + 1;
   constexpr int MAXSEG = 2 * W * W;
   __shared__ int sb[MAXSEG];
@@ -210,12 +212,13 @@ __global__ __launch_bounds__(64) void k_pair(int n, int64_t N, const int *__rest
   const double nd = double(n);
   for (int t0 = tb; t0 < te; t0 += kTgt) {
     const int nt = min(kTgt, te - t0);
-    double tx[kTgt], ty[kTgt], tz[kTgt], acc[kTgt];
+    double tx[kTgt], ty[kTgt], tz[kTgt], acc[kTgt], fx[kTgt], fy[kTgt], fz[kTgt];
 #pragma unroll
     for (int k = 0; k < kTgt; ++k) {
       const int ti = t0 + (k < nt ? k : 0);
       tx[k] = sg[ti]; ty[k] = sg[N + ti]; tz[k] = sg[2 * N + ti];
       acc[k] = 0.0;
+      fx[k] = fy[k] = fz[k] = 0.0;
     }
     int sp = 0;
     for (int f = lane; f < total; f += 64) {
@@ -231,7 +234,15 @@ __global__ __launch_bounds__(64) void k_pair(int n, int64_t N, const int *__rest
         const double dx = jx - tx[k], dy = jy - ty[k], dz = jz - tz[k];
         const double r2 = dx * dx + dy * dy + dz * dz;
         const bool use = (k < nt) && (j != t0 + k);
-        acc[k] += use ? qj * rsqrt(r2) : 0.0;
+        const double ri = rsqrt(r2);
+        const double qr = use ? qj * ri : 0.0;
+        acc[k] += qr;
+        if (FORCE) {
+          const double qr3 = qr * (use ? ri * ri : 0.0);  // the skipped self pair has ri = inf
+          fx[k] += qr3 * dx;
+          fy[k] += qr3 * dy;
+          fz[k] += qr3 * dz;
+        }
       }
     }
 #pragma unroll
@@ -239,9 +250,25 @@ __global__ __launch_bounds__(64) void k_pair(int n, int64_t N, const int *__rest
       double v = acc[k];
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
       acc[k] = v;
+      if (FORCE) {
+        double a = fx[k], b = fy[k], c = fz[k];
+        for (int off = 32; off > 0; off >>= 1) {
+          a += __shfl_xor(a, off, 64);
+          b += __shfl_xor(b, off, 64);
+          c += __shfl_xor(c, off, 64);
+        }
+        fx[k] = a; fy[k] = b; fz[k] = c;
+      }
     }
     if (lane == 0) {
-      for (int k = 0; k < nt; ++k) phip[t0 + k] = acc[k];
+      for (int k = 0; k < nt; ++k) {
+        phip[t0 + k] = acc[k];
+        if (FORCE) {
+          fpair[t0 + k] = fx[k];
+          fpair[N + t0 + k] = fy[k];
+          fpair[2 * N + t0 + k] = fz[k];
+        }
+      }
     }
   }
 }
@@ -370,15 +397,20 @@ void launch_rank(hipStream_t s, int64_t N, const int *tmp, const int *elem, cons
 void launch_moments(hipStream_t s, int n, int64_t N, const int *start, const double *sg, const double *sQ, double *C) {
   hipLaunchKernelGGL(k_moments, dim3(grid_n(int64_t(n) * n * n)), dim3(256), 0, s, n, N, start, sg, sQ, C);
 }
+template <int NSR>
+static void pair_impl(hipStream_t s, int n, int64_t N, const int *start, const double *sg, const double *sQ,
+                      double *phip, double *fpair) {
+  dim3 g(n * n * n);
+  if (fpair) hipLaunchKernelGGL((k_pair<NSR, true>), g, dim3(64), 0, s, n, N, start, sg, sQ, phip, fpair);
+  else hipLaunchKernelGGL((k_pair<NSR, false>), g, dim3(64), 0, s, n, N, start, sg, sQ, phip, fpair);
+}
 int launch_pair(hipStream_t s, int n, int nsr, int64_t N, const int *start, const double *sg, const double *sQ,
-                double *phip) {
-  const int M = n * n * n;
-  dim3 g(M);
+                double *phip, double *fpair) {
   switch (nsr) {
-    case 1: hipLaunchKernelGGL(k_pair<1>, g, dim3(64), 0, s, n, N, start, sg, sQ, phip); return 0;
-    case 2: hipLaunchKernelGGL(k_pair<2>, g, dim3(64), 0, s, n, N, start, sg, sQ, phip); return 0;
-    case 3: hipLaunchKernelGGL(k_pair<3>, g, dim3(64), 0, s, n, N, start, sg, sQ, phip); return 0;
-    case 4: hipLaunchKernelGGL(k_pair<4>, g, dim3(64), 0, s, n, N, start, sg, sQ, phip); return 0;
+    case 1: pair_impl<1>(s, n, N, start, sg, sQ, phip, fpair); return 0;
+    case 2: pair_impl<2>(s, n, N, start, sg, sQ, phip, fpair); return 0;
+    case 3: pair_impl<3>(s, n, N, start, sg, sQ, phip, fpair); return 0;
+    case 4: pair_impl<4>(s, n, N, start, sg, sQ, phip, fpair); return 0;
     default: return -1;
   }
 }

@@ -23,13 +23,23 @@ void launch_rank(hipStream_t s, int64_t N, const int *tmp, const int *elem, cons
                  const double *Q, int *perm, double *sg, double *sQ);
 void launch_moments(hipStream_t s, int n, int64_t N, const int *start, const double *sg, const double *sQ, double *C);
 int launch_pair(hipStream_t s, int n, int nsr, int64_t N, const int *start, const double *sg, const double *sQ,
-                double *phip);
+                double *phip, double *fpair);
 int launch_pair_count(hipStream_t s, int n, int nsr, const int *start, unsigned long long *out);
 int launch_interp(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const double *sg,
                   const double *Wel, const double *phip, const int *perm, double *phim_s, double *phi_s, double *Phi);
 void launch_energy(hipStream_t s, int64_t N, const double *sQ, const double *phi_s, double *partial);
 void launch_half(hipStream_t s, const double *in, double *out);
 void launch_unpermute(hipStream_t s, int64_t N, double scale, const int *perm, const double *in, double *out);
+
+// adjoint (k_adjoint.hip)
+int launch_deposit(hipStream_t s, int p, int n, int64_t N, const GllBasis &bas, const int *start, const double *sg,
+                   const double *sQ, double *gE);
+int launch_assemble(hipStream_t s, int p, int n, const double *gE, double *G, double *partial);
+int launch_adj_moments(hipStream_t s, int p, int n, int nsr, const double *gE, const double *T, const double *lam,
+                       const double *gw, double *A);
+int launch_forces(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const double *sg,
+                  const double *sQ, const double *Wel, const double *A, const double *fpair, const double *phip,
+                  const double *phim_s, const int *perm, double *F, double *dUdQ);
 
 // near field (k_near.hip)
 int launch_psi(hipStream_t s, int n, int nsr, int p, const double *C, const double *T, const double *phi, double *Wel);
@@ -41,10 +51,10 @@ void launch_sum_partials(hipStream_t s, int count, const double *partial, double
 void launch_sub_mass_ones(hipStream_t s, int n, int p, const double *w1, const double *scal, double *v);
 void launch_mass_dot(hipStream_t s, int n, int p, const double *w1, const double *v, double *partial);
 void launch_sub_const(hipStream_t s, size_t total, double invV, const double *scal, double *v);
-int launch_apply(hipStream_t s, const LevelOp &op, const double *x, const double *f, double *out, double *d,
-                 double *xo, double c1, double c2, int mode, double *partial);
+int launch_apply(hipStream_t s, const LevelOp &op, const double *x, const double *f, double *out,
+                 const double *xprev, double *xo, double c1, double c2, int mode, double *partial);
 int apply_blocks(const LevelOp &op);
-void launch_cheb_first(hipStream_t s, const LevelOp &op, const double *f, double *d, double *x, double c2);
+void launch_cheb_first(hipStream_t s, const LevelOp &op, const double *f, double *xprev, double *x, double c2);
 int launch_transfer(hipStream_t s, const Transfer &tr, const double *in, double *out, bool restrict_);
 void launch_restrict(hipStream_t s, const Transfer &tr, const double *rf, double *fc);
 void launch_prolong_add(hipStream_t s, const Transfer &tr, const double *ec, double *xf);

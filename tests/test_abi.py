@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_default_options_and_status_strings():
     o = fp.default_options()
-    assert o.n_sr == 3 and o.precision == 0 and o.mg_rtol == 1e-12 and o.table_box == 15
+    assert o.n_sr == 3 and o.precision == 0 and o.mg_rtol == 1e-10 and o.table_box == 15
     assert fp.lib().fep3m_default_options(None) == fp.ERR_ARG
     for st in range(0, -8, -1):
         assert fp.lib().fep3m_status_string(st)

@@ -40,7 +40,7 @@ def test_config1_stage_parity(torch):
     x, Q = workloads.make("uniform-1k-n8")
     L, n = 1.0, 8
     ref = fep3m.run(x, Q, fep3m.Params(L=L, n=n), stages=True)
-    ctx, Phi, U = _gpu(torch, x, Q, L, n)
+    ctx, Phi, U = _gpu(torch, x, Q, L, n, mg_rtol=1e-13)     # tight solve: stages exact
     order, start = _stable_order(ref["e_lin"], n)
     np.testing.assert_array_equal(ctx.stage("perm").cpu().numpy(), order)
     np.testing.assert_array_equal(ctx.stage("start").cpu().numpy(), start)
@@ -57,7 +57,7 @@ def test_config1_stage_parity(torch):
     assert _rel_rms(Phi, ref["Phi"]) < 1e-6
     assert abs(U - ref["U"]) < 1e-6 * abs(ref["U"])
     st = ctx.stats()
-    assert st["mg_rel_residual"] <= 1e-12
+    assert st["mg_rel_residual"] <= 1e-13
     counts = np.diff(start)
     assert st["max_per_element"] == counts.max()
 
@@ -119,8 +119,8 @@ def test_config2_sampled_parity(torch):
     rng = np.random.default_rng(7)
     tgt = np.sort(rng.choice(len(Q), 400, replace=False))
     ref = fep3m.run(x, Q, fep3m.Params(L=L, n=n), targets=tgt, stages=True)
-    phi = ctx.stage("phi").cpu().numpy()
-    assert np.abs(phi - ref["phi"].ravel()).max() < 1e-9 * np.abs(ref["phi"]).max()
+    phi = ctx.stage("phi").cpu().numpy()                       # default solve tolerance 1e-10
+    assert np.abs(phi - ref["phi"].ravel()).max() < 1e-7 * np.abs(ref["phi"]).max()
     assert _rel_rms(Phi[tgt], ref["Phi"]) < 1e-6
     # every charge: the energy is consistent with the returned potentials
     assert abs(U - 0.5 * float(np.sum(Q * Phi))) < 1e-10 * abs(U)
