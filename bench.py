@@ -1,10 +1,13 @@
 #!/usr/bin/env python3
 """Benchmark of the FE-P3M hot path on one MI355X.
 
-One step = one full evaluation through the C ABI (bin and sort, moments,
-load, multigrid-PCG mesh solve, near-screen field, near-pair sum,
-interpolation, energy) on device-resident synthetic inputs.  Prints one
-JSON line: pair interactions/s of the whole step, the step time, the
+One step = one full energy + force evaluation through the C ABI (bin and
+sort, moments, load, multigrid-PCG mesh solve, near-screen field, near-pair
+sum with pair forces, interpolation, energy; then the reverse pass: charge
+deposit, second mesh solve, transposed near-screen correlation, forces) on
+device-resident synthetic inputs.  Prints one JSON line: pair
+interactions/s of the whole step, the step time (the N = 1e6 energy+force
+time on the default workload), the
 roofline position of the dominant kernel (device time from hipEvents the
 library records on its stream), and the FP64 oracle's throughput on a
 bounded sample of the same workload, timed on this host's cores.
@@ -31,43 +34,56 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="uniform-1M-n64")
-    ap.add_argument("--cpu-sample", type=int, default=1500, help="oracle target sample for the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=1000, help="oracle target sample for the CPU baseline")
+    ap.add_argument("--outputs", choices=["forces", "energy"], default="forces",
+                    help="forces: U and F (the metric's energy+force step); energy: Phi and U")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 256 MiB (FETCH_SIZE/WRITE_SIZE calibration) and exit")
     return ap.parse_args()
 
 
-def cpu_baseline(x, Q, w, sample, Phi_gpu):
-    """The oracle, stage by stage as fep3m.run orders them, on this host:
-    the mesh side in full, the per-charge side for `sample` targets, scaled
-    to all N charges."""
+def cpu_baseline(x, Q, w, sample, F_gpu):
+    """The FP64 oracle's energy + force evaluation, stage by stage in the
+    order the oracle computes it, on this host: every mesh-side stage in full
+    (binning, moments, load, exact periodic solve; charge deposit, assembly,
+    exact adjoint solve), the per-charge stages (near-screen field, moment
+    adjoint, interpolation and its gradient, near pairs and pair forces) for
+    `sample` charges, scaled to all N."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
-    from oracle import fep3m as ofe, mesh, screens, tables
+    from oracle import adjoint as oadj, fep3m as ofe, mesh, screens, tables
 
     P = ofe.Params(L=w.L, n=w.n)
-    n, p, q = P.n, P.p, P.q
+    n, p, q, d, h = P.n, P.p, P.q, P.d, P.h
     t0 = time.perf_counter()
     T = tables.screen_tables(p, q, P.n_sr, P.B, P.table_bc)
     t_tables = time.perf_counter() - t0
     t0 = time.perf_counter()
     e, e_lin, u = ofe.bin_particles(x, P.L, n)
-    C = screens.element_moments(e_lin, u, Q, n**3, P.d)
+    C = screens.element_moments(e_lin, u, Q, n**3, d)
     b = mesh.project_compatible(mesh.load_vector(C, n, p, q), p, n)
     phi = mesh.solve_periodic(b, p, n)
     phi = phi - mesh.mean_value(phi, p, n)
+    gE = oadj.element_deposit(e_lin, u, Q, n, p)
+    G = mesh.project_compatible(oadj.assemble(gE, n, p), p, n)
+    lam = mesh.solve_periodic(G, p, n)
+    lam = lam - mesh.mean_value(lam, p, n)
     t_fixed = time.perf_counter() - t0
     rng = np.random.default_rng(0)
     tgt = np.sort(rng.choice(len(Q), min(sample, len(Q)), replace=False))
     t0 = time.perf_counter()
     uel, inv = np.unique(e_lin[tgt], return_inverse=True)
-    phiE = ofe.element_phi(phi, p, n, uel)
-    PsiE = ofe.near_field(C, T, n, P.n_sr, uel)
-    Phi_m = np.sum((phiE - PsiE)[inv] * ofe.basis_values(p, u[tgt]), axis=1)
+    W = ofe.element_phi(phi, p, n, uel) - ofe.near_field(C, T, n, P.n_sr, uel)
+    A = oadj.moment_adjoint(lam, gE, T, n, p, q, P.n_sr, uel)
+    ut, Qt = u[tgt], Q[tgt]
+    mesh_grad = 0.5 * Qt[:, None] * (np.einsum("nkm,nm->nk", oadj.basis_gradients(p, ut), W[inv])
+                                     + np.einsum("nka,na->nk", oadj.monomial_gradients(ut, d), A[inv]))
+    Phi_m = np.sum(W[inv] * ofe.basis_values(p, ut), axis=1)
     Phi_p = ofe.pair_potential(e, e_lin, u, Q, n, P.n_sr, tgt)
-    Phi_s = (Phi_p + Phi_m) / P.h
+    dUp = oadj.pair_forces(e, e_lin, u, Q, n, P.n_sr, tgt)
+    F_s = -(dUp + mesh_grad) / h**2
     t_tgt = time.perf_counter() - t0
     t_step = t_fixed + t_tgt * len(Q) / len(tgt)
     counts = np.bincount(e_lin, minlength=n**3).reshape(n, n, n)
@@ -78,19 +94,20 @@ def cpu_baseline(x, Q, w, sample, Phi_gpu):
             for dx in r:
                 block += np.roll(counts, (dz, dy, dx), axis=(0, 1, 2))
     pairs = float(np.sum(counts * block) - len(Q))
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    err = float(np.linalg.norm(Phi_gpu[tgt] - Phi_s) / np.linalg.norm(Phi_s))
+    threads = max([dd.get("num_threads", 1) for dd in threadpool_info()] + [1])
+    err = float(np.linalg.norm(F_gpu[tgt] - F_s) / np.linalg.norm(F_s))
+    del Phi_m, Phi_p
     return {
         "value": pairs / t_step,
         "unit": "pair interactions/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"mesh side in full ({t_fixed:.1f} s: bin, moments, load, exact periodic solve), "
-                   f"per-charge side for {len(tgt)} of {len(Q)} charges ({t_tgt:.1f} s), scaled to all charges; "
-                   f"tables precomputed once ({t_tables:.1f} s, excluded); BLAS threads={threads}, "
-                   f"per-charge loops single-threaded"),
+        "sample": (f"energy+forces; mesh side in full ({t_fixed:.1f} s: binning, moments, load, exact periodic "
+                   f"solve, charge deposit, assembly, exact adjoint solve), per-charge side for {len(tgt)} of "
+                   f"{len(Q)} charges ({t_tgt:.1f} s), scaled to all charges; tables precomputed once "
+                   f"({t_tables:.1f} s, excluded); BLAS threads={threads}, per-charge loops single-threaded"),
         "step_seconds_extrapolated": t_step,
-        "gpu_vs_oracle_rel_rms_on_sample": err,
+        "gpu_vs_oracle_force_rel_rms_on_sample": err,
     }
 
 
@@ -120,14 +137,23 @@ def main():
     tx = torch.from_numpy(x).to(dev)
     tQ = torch.from_numpy(Q).to(dev)
     ctx = fp.Context(w.L, w.N, w.n)
+    forces = args.outputs == "forces"
+
+    def step():
+        if forces:
+            o = ctx.energy_forces(tx, tQ)
+            return o["U"], o["F"]
+        Phi_, U_ = ctx.energy(tx, tQ)
+        return U_, None
+
     for _ in range(args.warmup):
-        ctx.energy(tx, tQ)
+        step()
     torch.cuda.synchronize()
     ctx.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        Phi, U = ctx.energy(tx, tQ)
+        U, F = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
@@ -153,6 +179,8 @@ def main():
     kernels = {"k_psi (near-screen field)": kern("near", "alu"),
                "k_pair (near-pair sum)": kern("pair", "alu"),
                "k_apply p=5 (fine-level operator)": kern("fine_apply", "hbm")}
+    if forces:
+        kernels["k_adj_moments (transposed near field)"] = kern("adj_near", "alu")
     dominant = max(kernels, key=lambda k: (kernels[k]["avg_launch_ms"] * kernels[k]["launches_per_step"])
                    if kernels[k] else -1)
     roof = dict(kernels[dominant])
@@ -171,17 +199,21 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "N": w.N, "elements": f"{w.n}^3", "L": w.L, "screen": "one-element q=3",
-                   "mesh_order": 5, "near_block": "7^3", "outputs": "Phi, U", "precision": "fp64",
-                   "near_pairs_per_step": pairs},
+                   "mesh_order": 5, "near_block": "7^3", "outputs": "U, F" if forces else "Phi, U",
+                   "precision": "fp64", "mg_rtol": ctx.options.mg_rtol, "near_pairs_per_step": pairs},
         "roofline": roof,
         "kernels": kernels,
         "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if k != "fine_apply"},
         "mg_iterations": st["mg_iterations"],
+        "adj_mg_iterations": st["adj_iterations"] if forces else None,
         "mg_rel_residual": st["mg_rel_residual"],
         "U": float(U.item()),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x, Q, w, args.cpu_sample, Phi.cpu().numpy())
+        if forces:
+            out["cpu_baseline"] = cpu_baseline(x, Q, w, args.cpu_sample, F.cpu().numpy())
+        else:
+            out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
 
 

@@ -77,16 +77,17 @@ def assemble(gE, n, p):
     return out
 
 
-def moment_adjoint(lam, gE, T, n, p, q, n_sr):
-    """A[E][a] = 4 pi <lambda_E, G_a> - sum_D <g_{E+D}, T_a[D]>."""
+def moment_adjoint(lam, gE, T, n, p, q, n_sr, elems=None):
+    """A[E][a] = 4 pi <lambda_E, G_a> - sum_D <g_{E+D}, T_a[D]> for the given
+    elements (default: all)."""
     d = q - 2
     g = screens.load_weights(p, q)
     A_exp = screens.moment_exponents(d)
-    lamE = fep3m.element_phi(lam, p, n, np.arange(n**3))
+    E = np.arange(n**3) if elems is None else np.asarray(elems)
+    lamE = fep3m.element_phi(lam, p, n, E)
     Gs = np.stack([np.einsum("k,j,i->kji", g[az], g[ay], g[ax]).ravel() for (ax, ay, az) in A_exp])
     A1 = 4.0 * math.pi * lamE @ Gs.T
     A2 = np.zeros_like(A1)
-    E = np.arange(n**3)
     ex, ey, ez = E % n, (E // n) % n, E // (n * n)
     for iD, (Dx, Dy, Dz) in enumerate(tables.offsets(n_sr)):
         src = ((ex + Dx) % n) + n * (((ey + Dy) % n) + n * ((ez + Dz) % n))
@@ -94,14 +95,17 @@ def moment_adjoint(lam, gE, T, n, p, q, n_sr):
     return A1 - A2
 
 
-def pair_forces(e, e_lin, u, Q, n, n_sr):
-    """dU_p/dg_i (element units) for every charge."""
+def pair_forces(e, e_lin, u, Q, n, n_sr, targets=None):
+    """dU_p/dg_i (element units) for the target charges (default: all)."""
     order = np.argsort(e_lin, kind="stable")
     counts = np.bincount(e_lin, minlength=n**3)
     start = np.concatenate([[0], np.cumsum(counts)])
-    out = np.zeros((len(Q), 3))
-    for E in np.unique(e_lin):
-        ti = order[start[E]:start[E + 1]]
+    targets = np.arange(len(Q)) if targets is None else np.asarray(targets)
+    out = np.zeros((len(targets), 3))
+    tgt_e = e_lin[targets]
+    for E in np.unique(tgt_e):
+        sel = np.nonzero(tgt_e == E)[0]
+        ti = targets[sel]
         ex, ey, ez = E % n, (E // n) % n, E // (n * n)
         srcs, shifts = [], []
         for (Dx, Dy, Dz) in tables.offsets(n_sr):
@@ -116,31 +120,40 @@ def pair_forces(e, e_lin, u, Q, n, n_sr):
         self_mask = js[None, :] == ti[:, None]
         r[self_mask] = np.inf
         w = Q[ti][:, None] * Q[js][None, :] / r**3
-        out[ti] = np.einsum("ij,ijk->ik", w, dvec)
+        out[sel] = np.einsum("ij,ijk->ik", w, dvec)
     return out
 
 
-def energy_forces(x, Q, params: fep3m.Params):
-    """U, F (N,3) and dU/dQ (N) of the discrete method, plus Phi."""
+def energy_forces(x, Q, params: fep3m.Params, targets=None):
+    """U, F (N,3) and dU/dQ (N) of the discrete method, plus Phi.  With
+    `targets`, Phi, F and dU/dQ are evaluated for those charges only (the
+    mesh solves and deposits still cover every charge) and U is omitted."""
     x = np.asarray(x, dtype=np.float64)
     Q = np.asarray(Q, dtype=np.float64)
     n, p, q, d, h = params.n, params.p, params.q, params.d, params.h
-    fw = fep3m.run(x, Q, params, stages=True)
+    all_targets = targets is None
+    tgt = np.arange(len(Q)) if all_targets else np.asarray(targets)
+    fw = fep3m.run(x, Q, params, targets=None if all_targets else tgt, stages=True)
     e, e_lin, u, C, phi = fw["e"], fw["e_lin"], fw["u"], fw["C"], fw["phi"]
     T = tables.screen_tables(p, q, params.n_sr, params.B, params.table_bc)
-    allE = np.arange(n**3)
-    W = fep3m.element_phi(phi, p, n, allE) - fep3m.near_field(C, T, n, params.n_sr, allE)
+    uel, inv = np.unique(e_lin[tgt], return_inverse=True)
+    W = fep3m.element_phi(phi, p, n, uel) - fep3m.near_field(C, T, n, params.n_sr, uel)
     gE = element_deposit(e_lin, u, Q, n, p)
     G = mesh.project_compatible(assemble(gE, n, p), p, n)
     lam = mesh.solve_periodic(G, p, n)
     lam = lam - mesh.mean_value(lam, p, n)
-    A = moment_adjoint(lam, gE, T, n, p, q, params.n_sr)
-    grad_v = basis_gradients(p, u)                       # (N,3,M)
-    grad_a = monomial_gradients(u, d)                    # (N,3,8)
-    mesh_grad = 0.5 * Q[:, None] * (np.einsum("nkm,nm->nk", grad_v, W[e_lin])
-                                     + np.einsum("nka,na->nk", grad_a, A[e_lin]))
-    dUp = pair_forces(e, e_lin, u, Q, n, params.n_sr)
+    A = moment_adjoint(lam, gE, T, n, p, q, params.n_sr, uel)
+    ut = u[tgt]
+    Qt = Q[tgt]
+    grad_v = basis_gradients(p, ut)                      # (T,3,M)
+    grad_a = monomial_gradients(ut, d)                   # (T,3,8)
+    mesh_grad = 0.5 * Qt[:, None] * (np.einsum("nkm,nm->nk", grad_v, W[inv])
+                                     + np.einsum("nka,na->nk", grad_a, A[inv]))
+    dUp = pair_forces(e, e_lin, u, Q, n, params.n_sr, tgt)
     F = -(dUp + mesh_grad) / h**2
-    mono = np.prod(u[:, None, :] ** screens.moment_exponents(d)[None, :, :], axis=2)
-    dUdQ = (fw["Phi_p"] * h + 0.5 * fw["Phi_m"] * h + 0.5 * np.sum(A[e_lin] * mono, axis=1)) / h
-    return {"U": fw["U"], "Phi": fw["Phi"], "F": F, "dUdQ": dUdQ, "A": A, "lam": lam, "gE": gE}
+    mono = np.prod(ut[:, None, :] ** screens.moment_exponents(d)[None, :, :], axis=2)
+    dUdQ = (fw["Phi_p"] * h + 0.5 * fw["Phi_m"] * h + 0.5 * np.sum(A[inv] * mono, axis=1)) / h
+    out = {"Phi": fw["Phi"], "F": F, "dUdQ": dUdQ, "A": A, "lam": lam, "gE": gE}
+    if all_targets:
+        out["U"] = fw["U"]
+    return out

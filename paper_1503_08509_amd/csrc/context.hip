@@ -76,7 +76,7 @@ struct fep3m_ctx {
 
   // precompute
   std::vector<double> T_host;
-  double *T = nullptr, *gw = nullptr, *w1 = nullptr;
+  double *T = nullptr, *Tt = nullptr, *gw = nullptr, *w1 = nullptr;
   GllBasis bas{};
 
   // particles
@@ -196,6 +196,15 @@ void fep3m_ctx::build(double L_, int64_t N_, int n_, int q_, const fep3m_options
   gw = alloc<double>(gwh.size(), "load weights");
   w1 = alloc<double>(w1h.size(), "mass ones");
   hip_check(hipMemcpy(T, T_host.data(), T_host.size() * sizeof(double), hipMemcpyHostToDevice), "upload tables");
+  {  // transposed copy Tt[D][m][a] for the reverse pass
+    const size_t ND = size_t(2 * nsr + 1) * (2 * nsr + 1) * (2 * nsr + 1), NM = size_t(p + 1) * (p + 1) * (p + 1);
+    std::vector<double> tt(T_host.size());
+    for (size_t a = 0; a < 8; ++a)
+      for (size_t iD = 0; iD < ND; ++iD)
+        for (size_t m = 0; m < NM; ++m) tt[(iD * NM + m) * 8 + a] = T_host[(a * ND + iD) * NM + m];
+    Tt = alloc<double>(tt.size(), "transposed tables");
+    hip_check(hipMemcpy(Tt, tt.data(), tt.size() * sizeof(double), hipMemcpyHostToDevice), "upload tables");
+  }
   hip_check(hipMemcpy(gw, gwh.data(), gwh.size() * sizeof(double), hipMemcpyHostToDevice), "upload weights");
   hip_check(hipMemcpy(w1, w1h.data(), w1h.size() * sizeof(double), hipMemcpyHostToDevice), "upload weights");
 
@@ -512,7 +521,7 @@ void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double 
     mesh_solve(Gv, lam);
     stage_mark(FEP3M_PROF_ADJ_SOLVE, false);
     stage_mark(FEP3M_PROF_ADJ_NEAR, true);
-    if (launch_adj_moments(stream, p, n, nsr, gE, T, lam, gw, Aadj) != 0)
+    if (launch_adj_moments(stream, p, n, nsr, gE, Tt, lam, gw, Aadj) != 0)
       throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
     stage_mark(FEP3M_PROF_ADJ_NEAR, false);
     stage_mark(FEP3M_PROF_FORCES, true);

@@ -89,98 +89,98 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const double *__restric
 }
 
 // A[E][a] = 4 pi <lambda_E, G_a> - sum_D <g_{E+D}, T_a[D]>.
-// Block = 4 x 4 x 4 brick of elements E; thread = 4 elements (a row along x)
-// x 8 moments, for one lane of a 16-node chunk; the deposits of the source
-// slab (fixed D_z) and the tables of the chunk are staged in LDS; the 16
-// node lanes are reduced at the end.
+// The second term is the transpose of the near-screen field: per element a
+// contraction over (D, m) with only 8 outputs, so the block's output is
+// small and the reduction is split over node lanes:
+//   block  = an 8 x 4 x 4 brick of elements E, 256 threads,
+//   thread = the 8 elements of one x-row of the brick x 8 moments (64
+//            float64 accumulators) for one lane of a 16-node chunk,
+//   deposits g of the source slab (fixed D_z, one node chunk) are staged in
+//            LDS with a padded element stride; the tables are read from a
+//            transposed copy Tt[D][m][a] (8 contiguous moments per node),
+//   the 16 node lanes are reduced with shuffles at the end.
 template <int NSR, int PO>
-__global__ __launch_bounds__(256) void k_adj_moments(int n, const double *__restrict__ gE,
-                                                     const double *__restrict__ T, const double *__restrict__ lam,
+__global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__restrict__ gE,
+                                                     const double *__restrict__ Tt, const double *__restrict__ lam,
                                                      const double *__restrict__ gw, double *__restrict__ Aout) {
-  constexpr int BS = 4, H = BS + 2 * NSR, S = 2 * NSR + 1, ND = S * S * S;
+  constexpr int BX = 8, BY = 4, BZ = 4;
+  constexpr int HX = BX + 2 * NSR, HY = BY + 2 * NSR, S = 2 * NSR + 1;
   constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
-  constexpr int MC = 16;                         // nodes per chunk
+  constexpr int MC = 16, MS = MC + 1;            // nodes per chunk, padded stride
   constexpr int NCH = (NM + MC - 1) / MC;
-  constexpr int SLAB = BS * H * H;               // source elements of one D_z
-  __shared__ double Gs[MC * SLAB];               // [m][lz][hy][hx]
-  __shared__ double Ts[S * S * MC * 8];          // [Dyx][m][a]
-  const int bricks = (n + BS - 1) / BS;
+  constexpr int SLAB = BZ * HY * HX;             // source elements of one D_z
+  __shared__ double Gs[SLAB * MS];               // [lz][hy][hx][m]
+  const int bx_n = (n + BX - 1) / BX, by_n = (n + BY - 1) / BY;
   int b = blockIdx.x;
-  const int bx = b % bricks;
-  b /= bricks;
-  const int by = b % bricks;
-  const int bz = b / bricks;
-  const int x0 = bx * BS, y0 = by * BS, z0 = bz * BS;
+  const int bx = b % bx_n;
+  b /= bx_n;
+  const int by = b % by_n;
+  const int bz = b / by_n;
+  const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
   const int tid = threadIdx.x;
-  const int ml = tid % MC, eg = tid / MC;        // node lane, element group (16 rows)
-  const int ly = eg % BS, lz = eg / BS;          // the row: elements (0..3, ly, lz)
-  double acc[4][8];
+  const int ml = tid % MC, eg = tid / MC;        // node lane, row (16 rows)
+  const int ly = eg % BY, lz = eg / BY;
+  double acc[BX][8];
 #pragma unroll
-  for (int e = 0; e < 4; ++e)
+  for (int e = 0; e < BX; ++e)
 #pragma unroll
     for (int a = 0; a < 8; ++a) acc[e][a] = 0.0;
 
   for (int Dz = -NSR; Dz <= NSR; ++Dz) {
     for (int ch = 0; ch < NCH; ++ch) {
       __syncthreads();
-      for (int i = tid; i < MC * SLAB; i += 256) {
-        const int h = i % SLAB, mm = i / SLAB;
+      for (int i = tid; i < MC * SLAB; i += 256) {   // lanes walk nodes: contiguous loads
+        const int mm = i % MC, h = i / MC;
         const int m = ch * MC + mm;
-        const int hx = h % H, hy = (h / H) % H, hz = h / (H * H);
+        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
         const int ex = (x0 - NSR + hx + 2 * n) % n, ey = (y0 - NSR + hy + 2 * n) % n;
         const int ez = (z0 + hz + Dz + 2 * n) % n;
-        Gs[i] = m < NM ? gE[(size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NM + m] : 0.0;
-      }
-      for (int i = tid; i < S * S * MC * 8; i += 256) {
-        const int a = i % 8, mm = (i / 8) % MC, dyx = i / (8 * MC);
-        const int Dx = dyx % S - NSR, Dy = dyx / S - NSR;
-        const int m = ch * MC + mm;
-        const int iD = (Dx + NSR) + S * ((Dy + NSR) + S * (Dz + NSR));
-        Ts[i] = m < NM ? T[(size_t(a) * ND + iD) * NM + m] : 0.0;
+        Gs[h * MS + mm] = m < NM ? gE[(size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NM + m] : 0.0;
       }
       __syncthreads();
+      const int m = ch * MC + ml;
+      const bool mv = m < NM;
       for (int dyx = 0; dyx < S * S; ++dyx) {
         const int Dx = dyx % S - NSR, Dy = dyx / S - NSR;
+        const int iD = (Dx + NSR) + S * ((Dy + NSR) + S * (Dz + NSR));
         double tv[8];
+        const double *tp = Tt + (size_t(iD) * NM + (mv ? m : 0)) * 8;
 #pragma unroll
-        for (int a = 0; a < 8; ++a) tv[a] = Ts[(dyx * MC + ml) * 8 + a];
-        const double *gr = Gs + ml * SLAB + (lz * H + (ly + Dy + NSR)) * H + (Dx + NSR);
+        for (int a = 0; a < 8; ++a) tv[a] = mv ? tp[a] : 0.0;
+        const double *gr = Gs + ((lz * HY + (ly + Dy + NSR)) * HX + (Dx + NSR)) * MS + ml;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const double gv = gr[e];
+        for (int e = 0; e < BX; ++e) {
+          const double gv = gr[e * MS];
 #pragma unroll
           for (int a = 0; a < 8; ++a) acc[e][a] += tv[a] * gv;
         }
       }
     }
   }
-  // reduce the node lanes (xor shuffles within groups of 16 lanes)
 #pragma unroll
-  for (int e = 0; e < 4; ++e)
+  for (int e = 0; e < BX; ++e)
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       double v = acc[e][a];
       for (int off = MC / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
       acc[e][a] = v;
     }
-  // lane 0 of each row group parks the 32 sums in LDS (static indices)
   __syncthreads();
-  double *red = Gs;  // [64 elements][8 moments], element = lx + 4 (ly + 4 lz)
+  double *red = Gs;  // [128 elements][8 moments], element = lx + BX (ly + BY lz)
   if (ml == 0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < BX; ++e)
 #pragma unroll
-      for (int a = 0; a < 8; ++a) red[(e + 4 * eg) * 8 + a] = acc[e][a];
+      for (int a = 0; a < 8; ++a) red[(e + BX * eg) * 8 + a] = acc[e][a];
   }
   __syncthreads();
-  if (tid >= 64) return;
-  // thread tid finishes brick element tid: A = 4 pi <lambda_E, G_a> - sum
-  const int ex = x0 + (tid % 4), ey = y0 + ((tid / 4) % 4), ez = z0 + tid / 16;
+  if (tid >= BX * BY * BZ) return;
+  const int ex = x0 + tid % BX, ey = y0 + (tid / BX) % BY, ez = z0 + tid / (BX * BY);
   if (ex >= n || ey >= n || ez >= n) return;
   const int P = PO * n;
   double a1[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int m = 0; m < NM; ++m) {
-    const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
+  for (int mm = 0; mm < NM; ++mm) {
+    const int mx = mm % Q1, my = (mm / Q1) % Q1, mz = mm / (Q1 * Q1);
     const int gx = (PO * ex + mx) % P, gy = (PO * ey + my) % P, gz = (PO * ez + mz) % P;
     const double lv = lam[(size_t(gz) * P + gy) * P + gx];
     const double gx0 = gw[mx], gx1 = gw[Q1 + mx], gy0 = gw[my], gy1 = gw[Q1 + my], gz0 = gw[mz], gz1 = gw[Q1 + mz];
@@ -284,15 +284,15 @@ int launch_assemble(hipStream_t s, int p, int n, const double *gE, double *G, do
   hipLaunchKernelGGL(k_assemble<5>, dim3(red_grid(tot)), dim3(256), 0, s, n, gE, G, partial);
   return 0;
 }
-int launch_adj_moments(hipStream_t s, int p, int n, int nsr, const double *gE, const double *T, const double *lam,
+int launch_adj_moments(hipStream_t s, int p, int n, int nsr, const double *gE, const double *Tt, const double *lam,
                        const double *gw, double *A) {
   if (p != 5) return -1;
-  const int bricks = (n + 3) / 4;
-  dim3 g(bricks * bricks * bricks);
+  const int bxn = (n + 7) / 8, byn = (n + 3) / 4;
+  dim3 g(bxn * byn * byn);
   switch (nsr) {
-    case 1: hipLaunchKernelGGL((k_adj_moments<1, 5>), g, dim3(256), 0, s, n, gE, T, lam, gw, A); return 0;
-    case 2: hipLaunchKernelGGL((k_adj_moments<2, 5>), g, dim3(256), 0, s, n, gE, T, lam, gw, A); return 0;
-    case 3: hipLaunchKernelGGL((k_adj_moments<3, 5>), g, dim3(256), 0, s, n, gE, T, lam, gw, A); return 0;
+    case 1: hipLaunchKernelGGL((k_adj_moments<1, 5>), g, dim3(256), 0, s, n, gE, Tt, lam, gw, A); return 0;
+    case 2: hipLaunchKernelGGL((k_adj_moments<2, 5>), g, dim3(256), 0, s, n, gE, Tt, lam, gw, A); return 0;
+    case 3: hipLaunchKernelGGL((k_adj_moments<3, 5>), g, dim3(256), 0, s, n, gE, Tt, lam, gw, A); return 0;
     default: return -1;
   }
 }

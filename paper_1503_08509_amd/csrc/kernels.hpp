@@ -35,7 +35,7 @@ void launch_unpermute(hipStream_t s, int64_t N, double scale, const int *perm, c
 int launch_deposit(hipStream_t s, int p, int n, int64_t N, const GllBasis &bas, const int *start, const double *sg,
                    const double *sQ, double *gE);
 int launch_assemble(hipStream_t s, int p, int n, const double *gE, double *G, double *partial);
-int launch_adj_moments(hipStream_t s, int p, int n, int nsr, const double *gE, const double *T, const double *lam,
+int launch_adj_moments(hipStream_t s, int p, int n, int nsr, const double *gE, const double *Tt, const double *lam,
                        const double *gw, double *A);
 int launch_forces(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const double *sg,
                   const double *sQ, const double *Wel, const double *A, const double *fpair, const double *phip,
