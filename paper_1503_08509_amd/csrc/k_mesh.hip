@@ -185,20 +185,50 @@ __device__ __forceinline__ void band_apply_acc(const double *__restrict__ a, con
   for (int o = 0; o < NOUT; ++o) out[o] += t[o];
 }
 
-// One tile of TE^3 elements per block: y = K x on the owned nodes, then the
-// mode's epilogue.  The owned nodes of a tile are p*e + k, k < p, for its
-// elements; the inputs reach one element below and one node above.
-// Pass z: each thread streams one (x, y) column of the input from global
-// memory and writes A = Mz x, B = Kz x; pass y: one (z, x) column of A and B
-// gives C1 = My A and C2 = Ky A + My B; pass x: one (z, y) row of C1, C2
-// gives y = Kx C1 + Mx C2; the epilogue then walks the owned nodes x-fastest.
-template <int PO, int TE>
+// Barrier for LDS hand-offs only: waits for LDS traffic, leaves global
+// loads in flight (the next tile's prefetch crosses it).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The it-th of the TPB tiles handled by block b (Morton order inside each
+// XCD's octant when the grid allows it, else linear).  False past the end.
+__device__ __forceinline__ bool block_tile(int b, int it, int tpb, int tiles, int &tx, int &ty, int &tz) {
+  const int half = tiles >> 1;
+  if ((tiles & 1) == 0 && half > 0 && (half & (half - 1)) == 0 && (half * half * half) % tpb == 0) {
+    const int xcd = b & 7, idx = (b >> 3) * tpb + it;
+    tx = compact_bits(idx) + half * (xcd & 1);
+    ty = compact_bits(idx >> 1) + half * ((xcd >> 1) & 1);
+    tz = compact_bits(idx >> 2) + half * (xcd >> 2);
+    return true;
+  }
+  const int t = b * tpb + it;
+  if (t >= tiles * tiles * tiles) return false;
+  tx = t % tiles;
+  ty = (t / tiles) % tiles;
+  tz = t / (tiles * tiles);
+  return true;
+}
+
+// TPB tiles of TE^3 elements per block: y = K x on the owned nodes of each
+// tile, then the mode's epilogue.  The owned nodes of a tile are p*e + k,
+// k < p, for its elements; the inputs reach one element below and one node
+// above.  Pass z: each thread streams one (x, y) column of the input from
+// global memory and writes A = Mz x, B = Kz x; pass y: one (z, x) column of A
+// and B gives C1 = My A and C2 = Ky A + My B; pass x: one (z, y) row of C1,
+// C2 gives y = Kx C1 + Mx C2; the epilogue walks the owned nodes x-fastest.
+// The next tile's column and epilogue operands are fetched while the
+// current tile runs its LDS passes.
+template <int PO, int TE, int TPB>
 __global__ __launch_bounds__(256) void k_apply(LevelOp op, const double *__restrict__ x,
                                                const double *__restrict__ f, double *__restrict__ out,
                                                const double *xprev, double *xo, double c1, double c2, int mode,
                                                double *__restrict__ partial) {
   using S = ApplyShape<PO, TE>;
   constexpr int O = S::O, I = S::I;
+  constexpr int NIT = (O * O * O + 255) / 256;
   __shared__ double lds[S::LDS];         // A, B; then C1, C2, Y; last the dot-product tree
   __shared__ double invd[PO * PO * PO];  // 1 / diag(K) by local node index
   __shared__ double Xo[O * O * O];       // x on the owned nodes (from the z-pass columns)
@@ -209,14 +239,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelOp op, const double *__restr
   double *Y = lds + 2 * O * S::SC;
   const int P = op.P;
   const int tiles = (op.n + TE - 1) / TE;
-  int tx, ty, tz;
-  tile_coords(blockIdx.x, tiles, tx, ty, tz);
-  const int ox0 = tx * O, oy0 = ty * O, oz0 = tz * O;
   const int tid = threadIdx.x;
-
-  // Epilogue operands of this thread's owned nodes, fetched now so their
-  // latency hides behind the three passes.
-  constexpr int NIT = (O * O * O + 255) / 256;
   const bool need_f = (mode == kResidual) || (mode == kCheb);
   const bool need_d = (mode == kCheb) && (c1 != 0.0);
   for (int i = tid; i < PO * PO * PO; i += 256) {
@@ -224,99 +247,121 @@ __global__ __launch_bounds__(256) void k_apply(LevelOp op, const double *__restr
     invd[i] = 1.0 / (op.dk[kx] * op.dm[ky] * op.dm[kz] + op.dm[kx] * op.dk[ky] * op.dm[kz] +
                      op.dm[kx] * op.dm[ky] * op.dk[kz]);
   }
-  double pf_f[NIT], pf_d[NIT];
+  // global inputs of one tile: this thread's z-column and epilogue operands
+  auto fetch = [&](int tx, int ty, int tz, double (&v)[I], double (&ff)[NIT], double (&fd)[NIT]) {
+    const int ox0 = tx * O, oy0 = ty * O, oz0 = tz * O;
+    if (tid < I * I) {
+      const int lx = tid % I, ly = tid / I;
+      const int gx = wrapi(ox0 - PO + lx, P), gy = wrapi(oy0 - PO + ly, P);
 #pragma unroll
-  for (int r = 0; r < NIT; ++r) {
-    const int li = tid + 256 * r;
-    const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
-    const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
-    const bool ok = li < O * O * O && gx < P && gy < P && gz < P;
-    const size_t g = ok ? (size_t(gz) * P + gy) * P + gx : 0;
-    pf_f[r] = (ok && need_f) ? f[g] : 0.0;
-    pf_d[r] = (ok && need_d) ? xprev[g] : 0.0;
-  }
-
-  // pass z
-  if (tid < I * I) {
-    const int lx = tid % I, ly = tid / I;
-    const int gx = wrapi(ox0 - PO + lx, P), gy = wrapi(oy0 - PO + ly, P);
-    double v[I];
-#pragma unroll
-    for (int z = 0; z < I; ++z) v[z] = x[(size_t(wrapi(oz0 - PO + z, P)) * P + gy) * P + gx];
-    if (lx >= PO && lx < PO + O && ly >= PO && ly < PO + O) {
-#pragma unroll
-      for (int oz = 0; oz < O; ++oz) Xo[(oz * O + (ly - PO)) * O + (lx - PO)] = v[oz + PO];
+      for (int z = 0; z < I; ++z) v[z] = x[(size_t(wrapi(oz0 - PO + z, P)) * P + gy) * P + gx];
     }
-    double a[O];
-    band_apply<PO, O>(op.me, v, a);
 #pragma unroll
-    for (int oz = 0; oz < O; ++oz) A[oz * S::SA + tid] = a[oz];
-    band_apply<PO, O>(op.ke, v, a);
-#pragma unroll
-    for (int oz = 0; oz < O; ++oz) B[oz * S::SA + tid] = a[oz];
-  }
-  __syncthreads();
-  // pass y
-  double c1v[O], c2v[O];
-  const bool act2 = tid < O * I;
-  const int oz2 = tid / I, lx2 = tid % I;
-  if (act2) {
-    double v[I];
-#pragma unroll
-    for (int y = 0; y < I; ++y) v[y] = A[oz2 * S::SA + y * I + lx2];
-    band_apply<PO, O>(op.me, v, c1v);
-    band_apply<PO, O>(op.ke, v, c2v);
-#pragma unroll
-    for (int y = 0; y < I; ++y) v[y] = B[oz2 * S::SA + y * I + lx2];
-    band_apply_acc<PO, O>(op.me, v, c2v);
-  }
-  __syncthreads();
-  if (act2) {
-#pragma unroll
-    for (int oy = 0; oy < O; ++oy) {
-      C1[oz2 * S::SC + oy * S::RS + lx2] = c1v[oy];
-      C2[oz2 * S::SC + oy * S::RS + lx2] = c2v[oy];
+    for (int r = 0; r < NIT; ++r) {
+      const int li = tid + 256 * r;
+      const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
+      const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
+      const bool ok = li < O * O * O && gx < P && gy < P && gz < P;
+      const size_t g = ok ? (size_t(gz) * P + gy) * P + gx : 0;
+      ff[r] = (ok && need_f) ? f[g] : 0.0;
+      fd[r] = (ok && need_d) ? xprev[g] : 0.0;
     }
-  }
-  __syncthreads();
-  // pass x
-  if (tid < O * O) {
-    const int oz = tid / O, oy = tid % O;
-    double v[I], yv[O];
-#pragma unroll
-    for (int xx = 0; xx < I; ++xx) v[xx] = C1[oz * S::SC + oy * S::RS + xx];
-    band_apply<PO, O>(op.ke, v, yv);
-#pragma unroll
-    for (int xx = 0; xx < I; ++xx) v[xx] = C2[oz * S::SC + oy * S::RS + xx];
-    band_apply_acc<PO, O>(op.me, v, yv);
-#pragma unroll
-    for (int ox = 0; ox < O; ++ox) Y[(oz * O + oy) * S::YS + ox] = yv[ox];
-  }
-  __syncthreads();
-  // epilogue on the owned nodes, x fastest
+  };
+  int tx = 0, ty = 0, tz = 0;
+  bool valid = block_tile(blockIdx.x, 0, TPB, tiles, tx, ty, tz);
+  double v[I], pf_f[NIT], pf_d[NIT];
+  if (valid) fetch(tx, ty, tz, v, pf_f, pf_d);
   double acc = 0.0;
+  for (int it = 0; it < TPB && valid; ++it) {
+    const int ox0 = tx * O, oy0 = ty * O, oz0 = tz * O;
+    int ntx = 0, nty = 0, ntz = 0;
+    const bool nvalid = (it + 1 < TPB) && block_tile(blockIdx.x, it + 1, TPB, tiles, ntx, nty, ntz);
+    double vn[I], nf[NIT], nd[NIT];
+    if (nvalid) fetch(ntx, nty, ntz, vn, nf, nd);
+    // pass z
+    if (tid < I * I) {
+      const int lx = tid % I, ly = tid / I;
+      if (lx >= PO && lx < PO + O && ly >= PO && ly < PO + O) {
 #pragma unroll
-  for (int r = 0; r < NIT; ++r) {
-    const int li = tid + 256 * r;
-    const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
-    const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
-    const bool ok = li < O * O * O && gx < P && gy < P && gz < P;
-    const int lc = ok ? li : 0;
-    const int cx = lc % O, cy = (lc / O) % O, cz = lc / (O * O);
-    const double y = Y[(cz * O + cy) * S::YS + cx];
-    const double xv = Xo[lc];
-    const double rr = (pf_f[r] - y) * invd[(ox % PO) + PO * ((oy % PO) + PO * (oz % PO))];
-    const size_t g = (size_t(gz) * P + gy) * P + gx;
-    if (ok) {
-      if (mode == kApply) out[g] = y;
-      else if (mode == kResidual) out[g] = pf_f[r] - y;
-      else if (mode == kCheb) xo[g] = xv + c1 * (xv - pf_d[r]) + c2 * rr;  // may overwrite x_prev
-      else if (mode == kDinvApply) out[g] = -rr;                            // f = 0 here: -rr = D^-1 K x
-      else { out[g] = y; acc += xv * y; }
+        for (int oz = 0; oz < O; ++oz) Xo[(oz * O + (ly - PO)) * O + (lx - PO)] = v[oz + PO];
+      }
+      double a[O];
+      band_apply<PO, O>(op.me, v, a);
+#pragma unroll
+      for (int oz = 0; oz < O; ++oz) A[oz * S::SA + tid] = a[oz];
+      band_apply<PO, O>(op.ke, v, a);
+#pragma unroll
+      for (int oz = 0; oz < O; ++oz) B[oz * S::SA + tid] = a[oz];
     }
+    lds_barrier();
+    // pass y
+    double c1v[O], c2v[O];
+    const bool act2 = tid < O * I;
+    const int oz2 = tid / I, lx2 = tid % I;
+    if (act2) {
+      double w[I];
+#pragma unroll
+      for (int y = 0; y < I; ++y) w[y] = A[oz2 * S::SA + y * I + lx2];
+      band_apply<PO, O>(op.me, w, c1v);
+      band_apply<PO, O>(op.ke, w, c2v);
+#pragma unroll
+      for (int y = 0; y < I; ++y) w[y] = B[oz2 * S::SA + y * I + lx2];
+      band_apply_acc<PO, O>(op.me, w, c2v);
+    }
+    lds_barrier();
+    if (act2) {
+#pragma unroll
+      for (int oy = 0; oy < O; ++oy) {
+        C1[oz2 * S::SC + oy * S::RS + lx2] = c1v[oy];
+        C2[oz2 * S::SC + oy * S::RS + lx2] = c2v[oy];
+      }
+    }
+    lds_barrier();
+    // pass x
+    if (tid < O * O) {
+      const int oz = tid / O, oy = tid % O;
+      double w[I], yv[O];
+#pragma unroll
+      for (int xx = 0; xx < I; ++xx) w[xx] = C1[oz * S::SC + oy * S::RS + xx];
+      band_apply<PO, O>(op.ke, w, yv);
+#pragma unroll
+      for (int xx = 0; xx < I; ++xx) w[xx] = C2[oz * S::SC + oy * S::RS + xx];
+      band_apply_acc<PO, O>(op.me, w, yv);
+#pragma unroll
+      for (int ox = 0; ox < O; ++ox) Y[(oz * O + oy) * S::YS + ox] = yv[ox];
+    }
+    lds_barrier();
+    // epilogue on the owned nodes, x fastest
+#pragma unroll
+    for (int r = 0; r < NIT; ++r) {
+      const int li = tid + 256 * r;
+      const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
+      const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
+      const bool ok = li < O * O * O && gx < P && gy < P && gz < P;
+      const int lc = ok ? li : 0;
+      const int cx = lc % O, cy = (lc / O) % O, cz = lc / (O * O);
+      const double y = Y[(cz * O + cy) * S::YS + cx];
+      const double xv = Xo[lc];
+      const double rr = (pf_f[r] - y) * invd[(ox % PO) + PO * ((oy % PO) + PO * (oz % PO))];
+      const size_t g = (size_t(gz) * P + gy) * P + gx;
+      if (ok) {
+        if (mode == kApply) out[g] = y;
+        else if (mode == kResidual) out[g] = pf_f[r] - y;
+        else if (mode == kCheb) xo[g] = xv + c1 * (xv - pf_d[r]) + c2 * rr;  // may overwrite x_prev
+        else if (mode == kDinvApply) out[g] = -rr;                            // f = 0: -rr = D^-1 K x
+        else { out[g] = y; acc += xv * y; }
+      }
+    }
+    lds_barrier();  // LDS free for the next tile
+#pragma unroll
+    for (int z = 0; z < I; ++z) v[z] = vn[z];
+#pragma unroll
+    for (int r = 0; r < NIT; ++r) { pf_f[r] = nf[r]; pf_d[r] = nd[r]; }
+    tx = ntx; ty = nty; tz = ntz;
+    valid = nvalid;
   }
   if (mode == kApplyDot) {
-    __syncthreads();  // every thread is done with Y before the tree reuses it
+    __syncthreads();
     double s = block_sum(acc, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
   }
@@ -655,12 +700,18 @@ void launch_sub_const(hipStream_t s, size_t total, double invV, const double *sc
   hipLaunchKernelGGL(k_sub_const, dim3(grid_for(total)), dim3(256), 0, s, total, invV, scal, v);
 }
 
+// Tiles per block.  One: with several tiles per block the prefetch registers
+// lower occupancy more than the overlap gains (measured).
+static inline int apply_tpb(int) { return 1; }
+
 template <int PO, int TE>
 static int apply_impl(hipStream_t s, const LevelOp &op, const double *x, const double *f, double *out,
                       const double *d, double *xo, double c1, double c2, int mode, double *partial) {
   const int tiles = (op.n + TE - 1) / TE;
-  const int nb = tiles * tiles * tiles;
-  hipLaunchKernelGGL((k_apply<PO, TE>), dim3(nb), dim3(256), 0, s, op, x, f, out, d, xo, c1, c2, mode, partial);
+  const int nt = tiles * tiles * tiles;
+  const int tpb = apply_tpb(tiles);
+  const int nb = (nt + tpb - 1) / tpb;
+  hipLaunchKernelGGL((k_apply<PO, TE, 1>), dim3(nb), dim3(256), 0, s, op, x, f, out, d, xo, c1, c2, mode, partial);
   return nb;
 }
 
@@ -678,7 +729,8 @@ int launch_apply(hipStream_t s, const LevelOp &op, const double *x, const double
 int apply_blocks(const LevelOp &op) {
   int TE = op.p == 1 ? 8 : op.p == 2 ? 4 : op.p == 3 ? 3 : 2;
   int tiles = (op.n + TE - 1) / TE;
-  return tiles * tiles * tiles;
+  const int tpb = apply_tpb(tiles);
+  return (tiles * tiles * tiles + tpb - 1) / tpb;
 }
 
 void launch_cheb_first(hipStream_t s, const LevelOp &op, const double *f, double *d, double *x, double c2) {
