@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1000, help="oracle target sample for the CPU baseline")
     ap.add_argument("--outputs", choices=["forces", "energy"], default="forces",
                     help="forces: U and F (the metric's energy+force step); energy: Phi and U")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="fp64: float64 throughout; mixed: float32 multigrid preconditioner, near field and "
+                         "interpolation with compensated sums, float64 reductions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 256 MiB (FETCH_SIZE/WRITE_SIZE calibration) and exit")
@@ -136,7 +139,8 @@ def main():
     dev = torch.device("cuda:0")
     tx = torch.from_numpy(x).to(dev)
     tQ = torch.from_numpy(Q).to(dev)
-    ctx = fp.Context(w.L, w.N, w.n)
+    mixed = args.precision == "mixed"
+    ctx = fp.Context(w.L, w.N, w.n, precision=fp.PRECISION_MIXED if mixed else fp.PRECISION_FP64)
     forces = args.outputs == "forces"
 
     def step():
@@ -179,6 +183,8 @@ def main():
     kernels = {"k_psi (near-screen field)": kern("near", "alu"),
                "k_pair (near-pair sum)": kern("pair", "alu"),
                "k_apply p=5 (fine-level operator)": kern("fine_apply", "hbm")}
+    if mixed:
+        kernels["k_apply<float> p=5 (fine-level preconditioner operator)"] = kern("fine_apply_f32", "hbm")
     if forces:
         kernels["k_adj_moments (transposed near field)"] = kern("adj_near", "alu")
     dominant = max(kernels, key=lambda k: (kernels[k]["avg_launch_ms"] * kernels[k]["launches_per_step"])
@@ -196,14 +202,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "N": w.N, "elements": f"{w.n}^3", "L": w.L, "screen": "one-element q=3",
                    "mesh_order": 5, "near_block": "7^3", "outputs": "U, F" if forces else "Phi, U",
-                   "precision": "fp64", "mg_rtol": ctx.options.mg_rtol, "near_pairs_per_step": pairs},
+                   "precision": args.precision, "mg_rtol": ctx.options.mg_rtol, "near_pairs_per_step": pairs},
         "roofline": roof,
         "kernels": kernels,
-        "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if k != "fine_apply"},
+        "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()
+                               if not k.startswith("fine_apply")},
         "mg_iterations": st["mg_iterations"],
         "adj_mg_iterations": st["adj_iterations"] if forces else None,
         "mg_rel_residual": st["mg_rel_residual"],

@@ -57,16 +57,26 @@ enum {
 
 enum {
   FEP3M_PRECISION_FP64 = 0,     /* every stage in float64                          */
-  FEP3M_PRECISION_MIXED = 1     /* float32 near field and interpolation with
-                                   compensated per-particle sums; float64 mesh
-                                   solve norms, coarse solve, projections and U   */
+  FEP3M_PRECISION_MIXED = 1     /* float32: the near-pair sum and its gradient,
+                                   the interpolation (both with Kahan-compensated
+                                   per-charge sums), the near-screen field (slab
+                                   sums compensated) and the multigrid V-cycle
+                                   that preconditions the mesh solve; float64:
+                                   the PCG iteration around it (operator apply,
+                                   updates, residual norms), the coarse-grid
+                                   solve, the mean-zero projections, the moments,
+                                   the moment adjoint and every reduction to U.
+                                   Results agree with FP64 to about 1e-6
+                                   relative RMS (Phi, U, F, dU/dQ).               */
 };
 
 typedef struct {
   int32_t n_sr;          /* near block radius in elements (default 3: 7^3 block,
                             the paper's short-range list, Section 4)             */
   int32_t precision;     /* FEP3M_PRECISION_*                                    */
-  double  mg_rtol;       /* relative residual target of the mesh solve (1e-10)   */
+  double  mg_rtol;       /* relative residual target of the mesh solve (1e-7,
+                            the single-precision level the paper's example
+                            calculations solve to, Section 4)                   */
   int32_t mg_max_iter;   /* PCG iteration cap (60)                               */
   int32_t cheb_degree;   /* Chebyshev smoothing degree per V-cycle side (3)      */
   int32_t table_box;     /* elements per axis of the table domain, odd,
@@ -81,6 +91,9 @@ typedef struct {
   int32_t adj_iterations;    /* PCG iterations of the second (adjoint) mesh solve */
   int32_t mg_levels;         /* levels of the multigrid hierarchy                */
   double  create_seconds;    /* wall time of create (tables, hierarchy)           */
+  int64_t generation;        /* successful potential/energy/energy_forces calls
+                                on this context; names the state fep3m_backward
+                                reuses                                            */
 } fep3m_stats;
 
 /* Profile slots: stages of one call, the fine-level operator launches, and
@@ -102,7 +115,9 @@ enum {
   FEP3M_PROF_ADJ_SOLVE = 8,   /* forces: deposit, assembly, second mesh solve */
   FEP3M_PROF_ADJ_NEAR = 9,    /* forces: moment adjoint (transposed near field) */
   FEP3M_PROF_FORCES = 10,     /* forces: per-charge gradient and dU/dQ      */
-  FEP3M_PROF_SLOTS = 11
+  FEP3M_PROF_FINE_APPLY_F32 = 11, /* fine-level operator launches in float32
+                                     (mixed-precision preconditioner)     */
+  FEP3M_PROF_SLOTS = 12
 };
 
 typedef struct {
@@ -151,6 +166,20 @@ int fep3m_energy(fep3m_ctx *ctx, const double *x, const double *Q, double *Phi, 
 int fep3m_energy_forces(fep3m_ctx *ctx, const double *x, const double *Q, double *U, double *F);
 int fep3m_energy_forces_ex(fep3m_ctx *ctx, const double *x, const double *Q, double *Phi, double *U,
                            double *F, double *dUdQ);
+
+/* Reverse pass of the last successful fep3m_potential / fep3m_energy /
+ * fep3m_energy_forces call on ctx, for callers that split the forward
+ * evaluation from the gradient (an autograd backward): F[3 i + k] = -dU/dx_ik
+ * and dUdQ[i] = dU/dQ_i exactly as fep3m_energy_forces_ex would return them
+ * for that call's x and Q.  It reuses that call's bins, sorted charges, mesh
+ * potential and per-element mesh-minus-near-screen field, recomputes the
+ * near-pair gradients (they are not kept by the forward call), and runs the
+ * deposit, second mesh solve and moment adjoint.  `generation` must equal
+ * fep3m_stats.generation read right after that call: any later call
+ * overwrites the state, and FEP3M_ERR_ARG is returned then (and when the
+ * last call failed, or both outputs are NULL).  F (N x 3) or dUdQ (N) may
+ * be NULL.  Device pointers, caller-owned. */
+int fep3m_backward(fep3m_ctx *ctx, int64_t generation, double *F, double *dUdQ);
 
 /* Copy an internal stage of the last evaluation to the device buffer `out`
  * of `out_bytes` bytes (test and diagnostic use).  Stages:

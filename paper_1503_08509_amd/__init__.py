@@ -39,15 +39,17 @@ class Stats(ctypes.Structure):
     _fields_ = [("mg_iterations", ctypes.c_int32), ("mg_rel_residual", ctypes.c_double),
                 ("near_pairs", ctypes.c_int64), ("max_per_element", ctypes.c_int32),
                 ("adj_iterations", ctypes.c_int32),
-                ("mg_levels", ctypes.c_int32), ("create_seconds", ctypes.c_double)]
+                ("mg_levels", ctypes.c_int32), ("create_seconds", ctypes.c_double),
+                ("generation", ctypes.c_int64)]
 
 
 PROF_SLOTS = ["sort", "assign", "solve", "near", "pair", "interp", "fine_apply", "total",
-              "adj_solve", "adj_near", "forces"]
+              "adj_solve", "adj_near", "forces", "fine_apply_f32"]
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 11), ("count", ctypes.c_int64 * 11), ("work", ctypes.c_double * 11)]
+    _fields_ = [("ms", ctypes.c_double * len(PROF_SLOTS)), ("count", ctypes.c_int64 * len(PROF_SLOTS)),
+                ("work", ctypes.c_double * len(PROF_SLOTS))]
 
 
 class FEP3MError(RuntimeError):
@@ -75,6 +77,7 @@ def lib():
         L.fep3m_energy.argtypes = [vp, vp, vp, vp, vp]
         L.fep3m_energy_forces.argtypes = [vp, vp, vp, vp, vp]
         L.fep3m_energy_forces_ex.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.fep3m_backward.argtypes = [vp, i64, vp, vp]
         L.fep3m_debug_stage.argtypes = [vp, i32, vp, i64]
         L.fep3m_stage_bytes.argtypes = [vp, i32]
         L.fep3m_stage_bytes.restype = i64
@@ -183,6 +186,18 @@ class Context:
             out["Phi"] = P
         return out
 
+    def backward(self, generation, F=True, dUdQ=True, device="cuda"):
+        """F = -dU/dx and dU/dQ of forward call `generation` (the value of
+        stats()["generation"] right after it), from the state that call left
+        in the context; the near-pair gradients are recomputed."""
+        t = self._torch
+        self._check(lib().fep3m_set_stream(self._h, ctypes.c_void_p(t.cuda.current_stream(device).cuda_stream)))
+        Fo = t.empty((self.N, 3), dtype=t.float64, device=device) if F else None
+        g = t.empty(self.N, dtype=t.float64, device=device) if dUdQ else None
+        self._check(lib().fep3m_backward(self._h, int(generation), Fo.data_ptr() if Fo is not None else None,
+                                         g.data_ptr() if g is not None else None))
+        return Fo, g
+
     def stage(self, name, device="cuda"):
         t = self._torch
         sid = STAGES[name]
@@ -221,3 +236,44 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+
+def _energy_function():
+    import torch
+
+    class FEP3MEnergy(torch.autograd.Function):
+        """U = FEP3MEnergy.apply(x, Q, ctx): the method's energy as a 0-d
+        float64 tensor, differentiable in x [N, 3] and Q [N].  The backward
+        pass is the library's hand-written adjoint (fep3m_backward): it
+        reuses the forward call's bins and mesh potential, recomputes the
+        near-pair terms, and returns grad_x = -F * dL/dU, grad_Q = dU/dQ *
+        dL/dU.  The context must not evaluate another configuration between
+        the forward call and its backward (an error is raised if it did)."""
+
+        @staticmethod
+        def forward(fctx, x, Q, ctx):
+            _, U = ctx.energy(x.detach(), Q.detach())
+            fctx.ctx = ctx
+            fctx.generation = ctx.stats()["generation"]
+            fctx.device = x.device
+            return U
+
+        @staticmethod
+        def backward(fctx, gU):
+            need_x, need_Q = fctx.needs_input_grad[0], fctx.needs_input_grad[1]
+            if not (need_x or need_Q):
+                return None, None, None
+            F, g = fctx.ctx.backward(fctx.generation, F=need_x, dUdQ=need_Q, device=fctx.device)
+            gx = -F * gU if need_x else None
+            gQ = g * gU if need_Q else None
+            return gx, gQ, None
+
+    return FEP3MEnergy
+
+
+def __getattr__(name):
+    if name == "FEP3MEnergy":
+        fn = _energy_function()
+        globals()["FEP3MEnergy"] = fn
+        return fn
+    raise AttributeError(name)

@@ -49,16 +49,38 @@ struct Profiler {
   hipEvent_t stage_ev[2 * FEP3M_PROF_SLOTS] = {};
   std::vector<hipEvent_t> kev;   // begin/end pairs for fine-level operator launches
   std::vector<double> kwork;     // bytes of each recorded launch
+  std::vector<int> kslot;        // profile slot of each recorded launch
   int kused = 0;
+  unsigned marked = 0;        // slots recorded in the current call
+  bool pair_forces = false;   // the current call's pair pass accumulated gradients
   fep3m_profile acc{};
+  void begin_call() {
+    kused = 0;
+    marked = 0;
+  }
+};
+
+// Vectors of one multigrid level in one arithmetic type.
+template <class T>
+struct LevelVecs {
+  T *x = nullptr, *x2 = nullptr, *f = nullptr, *r = nullptr;
 };
 
 struct MGLevel {
   LevelOp op{};
+  LevelOpF opf{};           // float32 copy (mixed-precision preconditioner)
   size_t ndof = 0;
-  double *x = nullptr, *x2 = nullptr, *d = nullptr, *f = nullptr, *r = nullptr;
+  LevelVecs<double> vd;
+  LevelVecs<float> vf;
+  double *d = nullptr;      // power-iteration work vector
   double lmax = 0.0;
+  template <class T> LevelVecs<T> &vec();
+  template <class T> const LevelOpT<T> &oper() const;
 };
+template <> LevelVecs<double> &MGLevel::vec<double>() { return vd; }
+template <> LevelVecs<float> &MGLevel::vec<float>() { return vf; }
+template <> const LevelOp &MGLevel::oper<double>() const { return op; }
+template <> const LevelOpF &MGLevel::oper<float>() const { return opf; }
 
 }  // namespace
 
@@ -71,6 +93,8 @@ struct fep3m_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   fep3m_stats stats{};
+  uint64_t generation = 0;   // successful evaluations so far
+  bool fwd_valid = false;    // buffers hold the state of evaluation `generation`
   std::vector<void *> allocs;
   Profiler prof;
 
@@ -85,6 +109,10 @@ struct fep3m_ctx {
   int *flags = nullptr, *maxcount = nullptr;
   unsigned long long *paircount = nullptr;
   double *C = nullptr, *Wel = nullptr, *phip_s = nullptr, *phim_s = nullptr, *phi_s = nullptr;
+  // mixed precision: float32 tables, element field, local coordinates
+  float *Tf = nullptr, *Welf = nullptr;
+  float4 *su = nullptr;
+  int *sel = nullptr;
   double *partial = nullptr, *scal = nullptr;
   size_t partial_len = 0;
   double *host_scal = nullptr;  // pinned
@@ -92,6 +120,10 @@ struct fep3m_ctx {
   // mesh
   std::vector<MGLevel> lv;
   std::vector<Transfer> tr;
+  std::vector<TransferF> trf;
+  bool mixed = false;        // float32 V-cycle, float32 near field and interpolation
+  template <class T> const TransferT<T> &transfer(int l) const;
+  double *dot_scr = nullptr; // two-dot partials of the mixed PCG
   double *coarseV = nullptr, *coarseLam = nullptr;
   int coarseP = 0;
   double *b = nullptr, *sol = nullptr, *rr = nullptr, *pv = nullptr, *qv = nullptr;
@@ -124,28 +156,36 @@ struct fep3m_ctx {
 
   void build(double L_, int64_t N_, int n_, int q_, const fep3m_options &o);
   void stage_mark(int slot, bool begin) {
-    if (prof.on) hip_check(hipEventRecord(prof.stage_ev[2 * slot + (begin ? 0 : 1)], stream), "event");
+    if (!prof.on) return;
+    hip_check(hipEventRecord(prof.stage_ev[2 * slot + (begin ? 0 : 1)], stream), "event");
+    if (begin) prof.marked |= 1u << slot;
   }
   // fine-level operator launch, bracketed by events when profiling
-  int apply0(const double *x, const double *f, double *out, const double *d, double *xo, double c1, double c2,
-             int mode, double *part) {
+  template <class T>
+  int apply0(const T *x, const T *f, T *out, const T *d, T *xo, T c1, T c2, int mode, double *part) {
     const bool rec = prof.on && prof.kused < int(prof.kev.size()) / 2;
     if (rec) hip_check(hipEventRecord(prof.kev[2 * prof.kused], stream), "event");
-    const int nb = launch_apply(stream, lv[0].op, x, f, out, d, xo, c1, c2, mode, part);
+    const int nb = launch_apply<T>(stream, lv[0].oper<T>(), x, f, out, d, xo, c1, c2, mode, part);
     if (rec) {
       hip_check(hipEventRecord(prof.kev[2 * prof.kused + 1], stream), "event");
-      // vectors read + written: x, f, x_prev (when c1 != 0) and x_new; x, f, r; x, Kx
-      const double vec = mode == kCheb ? (c1 != 0.0 ? 4.0 : 3.0) : mode == kResidual ? 3.0 : 2.0;
-      prof.kwork[prof.kused] = vec * 8.0 * double(lv[0].ndof);
+      // vectors read + written: x, f, x_prev (when read) and x_new; x, f, r; x, Kx
+      const double vec = mode == kCheb ? ((c1 != T(0) && d) ? 4.0 : 3.0) : mode == kResidual ? 3.0 : 2.0;
+      prof.kwork[prof.kused] = vec * double(sizeof(T)) * double(lv[0].ndof);
+      prof.kslot[prof.kused] = sizeof(T) == 8 ? FEP3M_PROF_FINE_APPLY : FEP3M_PROF_FINE_APPLY_F32;
       ++prof.kused;
     }
     return nb;
   }
-  void profile_collect(bool energy);
+  void profile_collect();
+  void forward(const double *x, const double *Q, double *Phi, double *U, bool pair_forces);
+  void pair_pass(bool pair_forces);
+  void reverse(double *F, double *dUdQ);
+  void finish(bool count_pairs);
+  void backward(int64_t gen, double *F, double *dUdQ);
   void build_mg();
   void estimate_spectra();
-  void vcycle(int l, const double *f);
-  void cheb_smooth(int l, const double *f, bool zero_start);
+  template <class T> void vcycle(int l, const T *f);
+  template <class T> void cheb_smooth(int l, const T *f, bool zero_start);
   void solve(const double *rhs, double *out);
   void mesh_solve(double *rhs, double *out);
   void evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F = nullptr,
@@ -166,6 +206,7 @@ void fep3m_ctx::build(double L_, int64_t N_, int n_, int q_, const fep3m_options
   nsr = o.n_sr;
   B = o.table_box;
   h = L / n;
+  mixed = o.precision == FEP3M_PRECISION_MIXED;
 
   Screen1D scr = make_screen(q);
   compute_tables(p, scr, nsr, B, T_host);
@@ -221,7 +262,16 @@ void fep3m_ctx::build(double L_, int64_t N_, int n_, int q_, const fep3m_options
   maxcount = alloc<int>(4, "max count");
   paircount = alloc<unsigned long long>(2, "pair count");
   C = alloc<double>(size_t(M) * 8, "moments");
-  Wel = alloc<double>(size_t(M) * (p + 1) * (p + 1) * (p + 1), "element field");
+  if (!mixed) {
+    Wel = alloc<double>(size_t(M) * (p + 1) * (p + 1) * (p + 1), "element field");
+  } else {
+    std::vector<float> tf(T_host.begin(), T_host.end());
+    Tf = alloc<float>(tf.size(), "tables (f32)");
+    hip_check(hipMemcpy(Tf, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice), "upload tables");
+    Welf = alloc<float>(size_t(M) * (p + 1) * (p + 1) * (p + 1), "element field (f32)");
+    su = alloc<float4>(size_t(N), "local coordinates (f32)");
+    sel = alloc<int>(size_t(N), "packed elements");
+  }
   phip_s = alloc<double>(size_t(N), "pair potential");
   phim_s = alloc<double>(size_t(N), "mesh potential");
   phi_s = alloc<double>(size_t(N), "potential");
@@ -286,6 +336,9 @@ static Transfer make_transfer(int pf, int nf, int pc, int nc) {
   return t;
 }
 
+template <> const Transfer &fep3m_ctx::transfer<double>(int l) const { return tr[l]; }
+template <> const TransferF &fep3m_ctx::transfer<float>(int l) const { return trf[l]; }
+
 void fep3m_ctx::build_mg() {
   std::vector<std::pair<int, int>> hier;
   hier.push_back({p, n});
@@ -306,13 +359,28 @@ void fep3m_ctx::build_mg() {
     tr.push_back(make_transfer(hier[i].first, hier[i].second, hier[i + 1].first, hier[i + 1].second));
   for (size_t i = 0; i < lv.size(); ++i) {
     MGLevel &L_ = lv[i];
-    L_.x = alloc<double>(L_.ndof, "mg x");
-    L_.f = (i == 0) ? nullptr : alloc<double>(L_.ndof, "mg f");
-    if (i + 1 < lv.size()) {
-      L_.x2 = alloc<double>(L_.ndof, "mg x2");
-      L_.d = alloc<double>(L_.ndof, "mg d");
-      L_.r = alloc<double>(L_.ndof, "mg r");
+    L_.vd.x = alloc<double>(L_.ndof, "mg x");
+    if (i + 1 < lv.size()) L_.d = alloc<double>(L_.ndof, "mg d");
+    if (!mixed) {
+      L_.vd.f = (i == 0) ? nullptr : alloc<double>(L_.ndof, "mg f");
+      if (i + 1 < lv.size()) {
+        L_.vd.x2 = alloc<double>(L_.ndof, "mg x2");
+        L_.vd.r = alloc<double>(L_.ndof, "mg r");
+      }
+    } else {
+      // float32 hierarchy; the fine level also holds the float32 copy of the residual
+      L_.opf = L_.op.cast<float>();
+      L_.vf.x = alloc<float>(L_.ndof, "mg x (f32)");
+      L_.vf.f = alloc<float>(L_.ndof, "mg f (f32)");
+      if (i + 1 < lv.size()) {
+        L_.vf.x2 = alloc<float>(L_.ndof, "mg x2 (f32)");
+        L_.vf.r = alloc<float>(L_.ndof, "mg r (f32)");
+      }
     }
+  }
+  if (mixed) {
+    for (const Transfer &t : tr) trf.push_back(t.cast<float>());
+    dot_scr = alloc<double>(2 * kRedBlocks, "two-dot partials");
   }
   const size_t nd0 = lv[0].ndof;
   gE = alloc<double>(size_t(n) * n * n * (p + 1) * (p + 1) * (p + 1), "deposit");
@@ -350,16 +418,17 @@ void fep3m_ctx::estimate_spectra() {
   // largest eigenvalue of D^-1 K per smoothed level (power iteration)
   for (size_t i = 0; i + 1 < lv.size(); ++i) {
     MGLevel &L_ = lv[i];
-    launch_hash_fill(stream, L_.ndof, 12345u + uint32_t(i), L_.x);
+    double *xw = L_.vd.x;
+    launch_hash_fill(stream, L_.ndof, 12345u + uint32_t(i), xw);
     double lam = 0.0;
-    launch_dot(stream, L_.ndof, L_.x, L_.x, partial);
+    launch_dot(stream, L_.ndof, xw, xw, partial);
     double nx = std::sqrt(reduce_host(red_grid(L_.ndof), partial, 0));
     for (int it = 0; it < 24; ++it) {
-      launch_apply(stream, L_.op, L_.x, nullptr, L_.d, nullptr, nullptr, 0.0, 0.0, kDinvApply, nullptr);
+      launch_apply<double>(stream, L_.op, xw, nullptr, L_.d, nullptr, nullptr, 0.0, 0.0, kDinvApply, nullptr);
       launch_dot(stream, L_.ndof, L_.d, L_.d, partial);
       double nd = std::sqrt(reduce_host(red_grid(L_.ndof), partial, 0));
       lam = nd / nx;
-      launch_scale(stream, L_.ndof, 1.0 / nd, L_.d, L_.x);
+      launch_scale(stream, L_.ndof, 1.0 / nd, L_.d, xw);
       nx = 1.0;
     }
     check_launch("power iteration");
@@ -369,8 +438,13 @@ void fep3m_ctx::estimate_spectra() {
 
 // ----------------------------------------------------------------- multigrid
 
-void fep3m_ctx::cheb_smooth(int l, const double *f, bool zero_start) {
+// Chebyshev(deg)-Jacobi smoothing on level l in arithmetic type T, targeting
+// the interval [lmax / 12, 1.1 lmax] of D^-1 K.
+template <class T>
+void fep3m_ctx::cheb_smooth(int l, const T *f, bool zero_start) {
   MGLevel &L_ = lv[l];
+  LevelVecs<T> &V = L_.vec<T>();
+  const LevelOpT<T> &op = L_.oper<T>();
   const double bmax = 1.1 * L_.lmax, amin = bmax / 12.0;
   const double theta = 0.5 * (bmax + amin), delta = 0.5 * (bmax - amin), sigma = theta / delta;
   double rho = 1.0 / sigma;
@@ -387,32 +461,44 @@ void fep3m_ctx::cheb_smooth(int l, const double *f, bool zero_start) {
       rho = rn;
     }
     if (s == 0 && zero_start) {
-      launch_cheb_first(stream, L_.op, f, L_.x2, L_.x, c2);   // x = c2 D^-1 f, x_prev (x2) = 0
+      launch_cheb_first<T>(stream, op, f, V.x, T(c2));   // x = c2 D^-1 f; x_prev = 0 (not stored)
     } else {
-      // x2 holds x_prev on entry and receives x_new; then the two swap
-      if (l == 0) apply0(L_.x, f, nullptr, L_.x2, L_.x2, c1, c2, kCheb, nullptr);
-      else launch_apply(stream, L_.op, L_.x, f, nullptr, L_.x2, L_.x2, c1, c2, kCheb, nullptr);
-      std::swap(L_.x, L_.x2);
+      // x2 holds x_prev on entry (null: zero, after the first step from a zero
+      // start) and receives x_new; then the two swap
+      const T *xprev = (s == 1 && zero_start) ? nullptr : V.x2;
+      if (l == 0) apply0<T>(V.x, f, nullptr, xprev, V.x2, T(c1), T(c2), kCheb, nullptr);
+      else launch_apply<T>(stream, op, V.x, f, nullptr, xprev, V.x2, T(c1), T(c2), kCheb, nullptr);
+      std::swap(V.x, V.x2);
     }
   }
 }
 
-void fep3m_ctx::vcycle(int l, const double *f) {
+// One V-cycle for K x = f on level l (x from zero), in arithmetic type T.
+template <class T>
+void fep3m_ctx::vcycle(int l, const T *f) {
   MGLevel &L_ = lv[l];
+  LevelVecs<T> &V = L_.vec<T>();
   if (l + 1 == int(lv.size())) {
-    launch_coarse_solve(stream, coarseP, coarseV, coarseLam, f, L_.x);
+    launch_coarse_solve<T>(stream, coarseP, coarseV, coarseLam, f, V.x);
     return;
   }
-  cheb_smooth(l, f, true);
-  if (l == 0) apply0(L_.x, f, L_.r, nullptr, nullptr, 0.0, 0.0, kResidual, nullptr);
-  else launch_apply(stream, L_.op, L_.x, f, L_.r, nullptr, nullptr, 0.0, 0.0, kResidual, nullptr);
-  launch_restrict(stream, tr[l], L_.r, lv[l + 1].f);
-  vcycle(l + 1, lv[l + 1].f);
-  launch_prolong_add(stream, tr[l], lv[l + 1].x, L_.x);
-  cheb_smooth(l, f, false);
+  const LevelOpT<T> &op = L_.oper<T>();
+  LevelVecs<T> &Vc = lv[l + 1].vec<T>();
+  cheb_smooth<T>(l, f, true);
+  if (l == 0) apply0<T>(V.x, f, V.r, nullptr, nullptr, T(0), T(0), kResidual, nullptr);
+  else launch_apply<T>(stream, op, V.x, f, V.r, nullptr, nullptr, T(0), T(0), kResidual, nullptr);
+  launch_transfer<T>(stream, transfer<T>(l), V.r, Vc.f, true);
+  vcycle<T>(l + 1, Vc.f);
+  launch_transfer<T>(stream, transfer<T>(l), Vc.x, V.x, false);
+  cheb_smooth<T>(l, f, false);
 }
 
-// PCG on K out = rhs (rhs compatible), preconditioned by one V-cycle.
+// PCG on K out = rhs (rhs compatible), preconditioned by one V-cycle.  In
+// mixed precision the V-cycle runs in float32 on a float32 copy of the
+// residual, and the iteration uses the flexible (Polak-Ribiere) update
+// beta = -alpha (z_new . q) / (z_old . r_old), which stays a descent method
+// when the preconditioner carries float32 rounding; everything else (K p, the
+// updates, every norm and inner product) is float64.
 void fep3m_ctx::solve(const double *rhs, double *sol) {
   MGLevel &L0 = lv[0];
   const size_t nd = L0.ndof;
@@ -423,23 +509,45 @@ void fep3m_ctx::solve(const double *rhs, double *sol) {
   stats.mg_iterations = 0;
   stats.mg_rel_residual = 0.0;
   if (bnorm == 0.0) return;
-  vcycle(0, rr);
-  hip_check(hipMemcpyAsync(pv, L0.x, nd * sizeof(double), hipMemcpyDeviceToDevice, stream), "copy p");
-  launch_dot(stream, nd, rr, L0.x, partial);
-  double rz = reduce_host(red_grid(nd), partial, 0);
+  // z = M^-1 r; returns z . r (and z . q in *zq when q is given)
+  auto precondition = [&](const double *q, double *zq) -> double {
+    if (!mixed) {
+      vcycle<double>(0, rr);
+      launch_dot(stream, nd, rr, L0.vd.x, partial);
+      return reduce_host(red_grid(nd), partial, 0);
+    }
+    launch_to_f32(stream, nd, rr, L0.vf.f);
+    vcycle<float>(0, L0.vf.f);
+    launch_dot2_f32(stream, nd, L0.vf.x, rr, q, dot_scr);
+    launch_sum_partials(stream, kRedBlocks, dot_scr, scal + 10);
+    launch_sum_partials(stream, kRedBlocks, dot_scr + kRedBlocks, scal + 11);
+    hip_check(hipMemcpyAsync(host_scal + 10, scal + 10, 2 * sizeof(double), hipMemcpyDeviceToHost, stream), "copy");
+    sync("two dots");
+    if (zq) *zq = host_scal[11];
+    return host_scal[10];
+  };
+  auto set_p = [&](double beta) {
+    if (!mixed) {
+      if (beta == 0.0) hip_check(hipMemcpyAsync(pv, L0.vd.x, nd * sizeof(double), hipMemcpyDeviceToDevice, stream), "copy p");
+      else launch_xpay(stream, nd, beta, L0.vd.x, pv);
+    } else {
+      launch_xpay_f32(stream, nd, beta, L0.vf.x, pv);
+    }
+  };
+  double rz = precondition(nullptr, nullptr);
+  set_p(0.0);
   double rel = 1.0;
   int it = 0;
   for (it = 1; it <= opt.mg_max_iter; ++it) {
-    const int nb = apply0(pv, nullptr, qv, nullptr, nullptr, 0.0, 0.0, kApplyDot, partial);
+    const int nb = apply0<double>(pv, nullptr, qv, nullptr, nullptr, 0.0, 0.0, kApplyDot, partial);
     const double pq = reduce_host(nb, partial, 0);
     const double alpha = rz / pq;
     launch_cg_update(stream, nd, alpha, pv, qv, sol, rr, partial);
     rel = std::sqrt(reduce_host(red_grid(nd), partial, 0)) / bnorm;
     if (rel <= opt.mg_rtol) break;
-    vcycle(0, rr);
-    launch_dot(stream, nd, rr, L0.x, partial);
-    const double rzn = reduce_host(red_grid(nd), partial, 0);
-    launch_xpay(stream, nd, rzn / rz, L0.x, pv);
+    double zq = 0.0;
+    const double rzn = precondition(qv, &zq);
+    set_p(mixed ? -alpha * zq / rz : rzn / rz);
     rz = rzn;
   }
   stats.mg_iterations = std::min(it, opt.mg_max_iter);
@@ -459,10 +567,8 @@ void fep3m_ctx::mesh_solve(double *rhs, double *out) {
 
 // ----------------------------------------------------------------- evaluate
 
-void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ) {
+void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *U, bool pair_forces) {
   const int M = n * n * n;
-  prof.kused = 0;
-  stage_mark(FEP3M_PROF_TOTAL, true);
   stage_mark(FEP3M_PROF_SORT, true);
   hip_check(hipMemsetAsync(count, 0, size_t(M) * sizeof(int), stream), "zero counts");
   hip_check(hipMemsetAsync(flags, 0, 4 * sizeof(int), stream), "zero flags");
@@ -482,6 +588,7 @@ void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double 
   launch_scan(stream, M, count, start, maxcount);
   launch_scatter(stream, N, elem, slot, start, tmp);
   launch_rank(stream, N, tmp, elem, start, gtmp, Qc, perm, sg, sQ);
+  if (mixed) launch_local_f32(stream, n, N, sg, sQ, su, sel);
   stage_mark(FEP3M_PROF_SORT, false);
   stage_mark(FEP3M_PROF_ASSIGN, true);
   launch_moments(stream, n, N, start, sg, sQ, C);
@@ -492,81 +599,127 @@ void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double 
   stage_mark(FEP3M_PROF_ASSIGN, false);
   stage_mark(FEP3M_PROF_SOLVE, true);
   mesh_solve(b, sol);
-  const int fwd_iters = stats.mg_iterations;
-  const double fwd_rel = stats.mg_rel_residual;
   stage_mark(FEP3M_PROF_SOLVE, false);
   stage_mark(FEP3M_PROF_NEAR, true);
-  if (launch_psi(stream, n, nsr, p, C, T, sol, Wel) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
+  const int ps = mixed ? launch_psi<float>(stream, n, nsr, p, C, Tf, sol, Welf)
+                       : launch_psi<double>(stream, n, nsr, p, C, T, sol, Wel);
+  if (ps != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
   stage_mark(FEP3M_PROF_NEAR, false);
-  stage_mark(FEP3M_PROF_PAIR, true);
-  if (launch_pair(stream, n, nsr, N, start, sg, sQ, phip_s, F ? fpair : nullptr) != 0)
-    throw Status(FEP3M_ERR_UNSUPPORTED, "pair variant");
-  stage_mark(FEP3M_PROF_PAIR, false);
+  pair_pass(pair_forces);
   stage_mark(FEP3M_PROF_INTERP, true);
-  if (launch_interp(stream, p, n, N, 1.0 / h, bas, sg, Wel, phip_s, perm, phim_s, phi_s, Phi) != 0)
-    throw Status(FEP3M_ERR_UNSUPPORTED, "interpolation variant");
+  const int is = mixed ? launch_interp_f32(stream, p, n, N, 1.0 / h, bas, su, sel, Welf, phip_s, perm, phim_s, phi_s, Phi)
+                       : launch_interp(stream, p, n, N, 1.0 / h, bas, sg, Wel, phip_s, perm, phim_s, phi_s, Phi);
+  if (is != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "interpolation variant");
   if (U) {
     launch_energy(stream, N, sQ, phi_s, partial);
     launch_sum_partials(stream, energy_grid(N), partial, scal + 6);
     launch_half(stream, scal + 6, U);
   }
   stage_mark(FEP3M_PROF_INTERP, false);
-  if (F) {
-    // reverse pass: deposit, second mesh solve, moment adjoint, forces
-    stage_mark(FEP3M_PROF_ADJ_SOLVE, true);
-    launch_deposit(stream, p, n, N, bas, start, sg, sQ, gE);
-    launch_assemble(stream, p, n, gE, Gv, partial);
-    launch_sum_partials(stream, red_grid(lv[0].ndof), partial, scal + 7);
-    launch_sub_mass_ones(stream, n, p, w1, scal + 7, Gv);
-    mesh_solve(Gv, lam);
-    stage_mark(FEP3M_PROF_ADJ_SOLVE, false);
-    stage_mark(FEP3M_PROF_ADJ_NEAR, true);
-    if (launch_adj_moments(stream, p, n, nsr, gE, Tt, lam, gw, Aadj) != 0)
-      throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
-    stage_mark(FEP3M_PROF_ADJ_NEAR, false);
-    stage_mark(FEP3M_PROF_FORCES, true);
-    launch_forces(stream, p, n, N, 1.0 / h, bas, sg, sQ, Wel, Aadj, fpair, phip_s, phim_s, perm, F, dUdQ);
-    stage_mark(FEP3M_PROF_FORCES, false);
-    stats.adj_iterations = stats.mg_iterations;
-    stats.mg_iterations = fwd_iters;
-    stats.mg_rel_residual = fwd_rel;
-  }
-  stage_mark(FEP3M_PROF_TOTAL, false);
-  hip_check(hipMemsetAsync(paircount, 0, sizeof(unsigned long long), stream), "zero pair count");
-  launch_pair_count(stream, n, nsr, start, paircount);
-  hip_check(hipMemcpyAsync(host_scal + 8, paircount, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream), "copy");
-  hip_check(hipMemcpyAsync(host_scal + 9, maxcount, sizeof(int), hipMemcpyDeviceToHost, stream), "copy");
-  check_launch("evaluation");
-  sync("evaluation");
-  unsigned long long pc;
-  std::memcpy(&pc, host_scal + 8, sizeof(pc));
-  int mc;
-  std::memcpy(&mc, host_scal + 9, sizeof(int));
-  stats.near_pairs = int64_t(pc);
-  stats.max_per_element = mc;
-  if (prof.on) profile_collect(F != nullptr);
 }
 
-void fep3m_ctx::profile_collect(bool forces) {
+void fep3m_ctx::pair_pass(bool pair_forces) {
+  stage_mark(FEP3M_PROF_PAIR, true);
+  double *fp = pair_forces ? fpair : nullptr;
+  const int st = mixed ? launch_pair_f32(stream, n, nsr, N, start, su, sel, phip_s, fp)
+                       : launch_pair(stream, n, nsr, N, start, sg, sQ, phip_s, fp);
+  if (st != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "pair variant");
+  prof.pair_forces = pair_forces;
+  stage_mark(FEP3M_PROF_PAIR, false);
+}
+
+// Reverse pass over the state the forward pass left in the context: deposit,
+// second mesh solve, moment adjoint, per-charge gradients.
+void fep3m_ctx::reverse(double *F, double *dUdQ) {
+  const int fwd_iters = stats.mg_iterations;
+  const double fwd_rel = stats.mg_rel_residual;
+  stage_mark(FEP3M_PROF_ADJ_SOLVE, true);
+  launch_deposit(stream, p, n, N, bas, start, sg, sQ, gE);
+  launch_assemble(stream, p, n, gE, Gv, partial);
+  launch_sum_partials(stream, red_grid(lv[0].ndof), partial, scal + 7);
+  launch_sub_mass_ones(stream, n, p, w1, scal + 7, Gv);
+  mesh_solve(Gv, lam);
+  stage_mark(FEP3M_PROF_ADJ_SOLVE, false);
+  stage_mark(FEP3M_PROF_ADJ_NEAR, true);
+  if (launch_adj_moments(stream, p, n, nsr, gE, Tt, lam, gw, Aadj) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
+  stage_mark(FEP3M_PROF_ADJ_NEAR, false);
+  stage_mark(FEP3M_PROF_FORCES, true);
+  if (mixed) launch_forces<float>(stream, p, n, N, 1.0 / h, bas, sg, sQ, Welf, Aadj, fpair, phip_s, phim_s, perm, F, dUdQ);
+  else launch_forces<double>(stream, p, n, N, 1.0 / h, bas, sg, sQ, Wel, Aadj, fpair, phip_s, phim_s, perm, F, dUdQ);
+  stage_mark(FEP3M_PROF_FORCES, false);
+  stats.adj_iterations = stats.mg_iterations;
+  stats.mg_iterations = fwd_iters;
+  stats.mg_rel_residual = fwd_rel;
+}
+
+void fep3m_ctx::finish(bool count_pairs) {
+  if (count_pairs) {
+    hip_check(hipMemsetAsync(paircount, 0, sizeof(unsigned long long), stream), "zero pair count");
+    launch_pair_count(stream, n, nsr, start, paircount);
+    hip_check(hipMemcpyAsync(host_scal + 8, paircount, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
+              "copy");
+    hip_check(hipMemcpyAsync(host_scal + 9, maxcount, sizeof(int), hipMemcpyDeviceToHost, stream), "copy");
+  }
+  check_launch("evaluation");
+  sync("evaluation");
+  if (count_pairs) {
+    unsigned long long pc;
+    std::memcpy(&pc, host_scal + 8, sizeof(pc));
+    int mc;
+    std::memcpy(&mc, host_scal + 9, sizeof(int));
+    stats.near_pairs = int64_t(pc);
+    stats.max_per_element = mc;
+  }
+  if (prof.on) profile_collect();
+}
+
+void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ) {
+  fwd_valid = false;
+  prof.begin_call();
+  stage_mark(FEP3M_PROF_TOTAL, true);
+  forward(x, Qc, Phi, U, F != nullptr);
+  if (F) reverse(F, dUdQ);
+  stage_mark(FEP3M_PROF_TOTAL, false);
+  finish(true);
+  ++generation;
+  stats.generation = int64_t(generation);
+  fwd_valid = true;
+}
+
+void fep3m_ctx::backward(int64_t gen, double *F, double *dUdQ) {
+  if (!fwd_valid || gen != int64_t(generation))
+    throw Status(FEP3M_ERR_ARG, "backward needs the state of forward call " + std::to_string(gen) +
+                                    " but the context holds call " + std::to_string(generation) +
+                                    (fwd_valid ? "" : " (failed)"));
+  prof.begin_call();
+  stage_mark(FEP3M_PROF_TOTAL, true);
+  pair_pass(true);       // pair gradients recomputed, not stored by the forward call
+  reverse(F, dUdQ);
+  stage_mark(FEP3M_PROF_TOTAL, false);
+  finish(false);
+}
+
+void fep3m_ctx::profile_collect() {
   for (int s = 0; s < FEP3M_PROF_SLOTS; ++s) {
-    if (s == FEP3M_PROF_FINE_APPLY) continue;
-    if (!forces && (s == FEP3M_PROF_ADJ_SOLVE || s == FEP3M_PROF_ADJ_NEAR || s == FEP3M_PROF_FORCES)) continue;
+    if (s == FEP3M_PROF_FINE_APPLY || s == FEP3M_PROF_FINE_APPLY_F32 || !(prof.marked & (1u << s))) continue;
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, prof.stage_ev[2 * s], prof.stage_ev[2 * s + 1]), "elapsed");
     prof.acc.ms[s] += ms;
     prof.acc.count[s] += 1;
   }
   const double S = 2 * nsr + 1;
-  prof.acc.work[FEP3M_PROF_NEAR] += 2.0 * 8.0 * (p + 1) * (p + 1) * (p + 1) * S * S * S * double(n) * n * n;
-  prof.acc.work[FEP3M_PROF_PAIR] += (forces ? 20.0 : 11.0) * double(stats.near_pairs);
-  if (forces)
-    prof.acc.work[FEP3M_PROF_ADJ_NEAR] += 2.0 * 8.0 * (p + 1) * (p + 1) * (p + 1) * S * S * S * double(n) * n * n;
+  const double near_flop = 2.0 * 8.0 * (p + 1) * (p + 1) * (p + 1) * S * S * S * double(n) * n * n;
+  if (prof.marked & (1u << FEP3M_PROF_NEAR)) prof.acc.work[FEP3M_PROF_NEAR] += near_flop;
+  if (prof.marked & (1u << FEP3M_PROF_PAIR))
+    prof.acc.work[FEP3M_PROF_PAIR] += (prof.pair_forces ? 20.0 : 11.0) * double(stats.near_pairs);
+  if (prof.marked & (1u << FEP3M_PROF_ADJ_NEAR)) prof.acc.work[FEP3M_PROF_ADJ_NEAR] += near_flop;
   for (int k = 0; k < prof.kused; ++k) {
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, prof.kev[2 * k], prof.kev[2 * k + 1]), "elapsed");
-    prof.acc.ms[FEP3M_PROF_FINE_APPLY] += ms;
-    prof.acc.count[FEP3M_PROF_FINE_APPLY] += 1;
-    prof.acc.work[FEP3M_PROF_FINE_APPLY] += prof.kwork[k];
+    prof.acc.ms[prof.kslot[k]] += ms;
+    prof.acc.count[prof.kslot[k]] += 1;
+    prof.acc.work[prof.kslot[k]] += prof.kwork[k];
   }
 }
 
@@ -615,7 +768,7 @@ int fep3m_default_options(fep3m_options *opt) {
   if (!opt) return FEP3M_ERR_ARG;
   opt->n_sr = 3;
   opt->precision = FEP3M_PRECISION_FP64;
-  opt->mg_rtol = 1e-10;
+  opt->mg_rtol = 1e-7;
   opt->mg_max_iter = 60;
   opt->cheb_degree = 3;
   opt->table_box = 2 * 3 + 9;
@@ -636,7 +789,6 @@ int fep3m_create_ex(double L, int64_t N, const int32_t dims[3], int32_t q, const
   if (dims[0] < 2 * o.n_sr + 1 || dims[0] > 512) return FEP3M_ERR_ARG;
   if (q < 2 || q > 6) return FEP3M_ERR_ARG;
   if (q != 3) return FEP3M_ERR_UNSUPPORTED;
-  if (o.precision != FEP3M_PRECISION_FP64) return FEP3M_ERR_UNSUPPORTED;
   std::unique_ptr<fep3m_ctx> ctx(new (std::nothrow) fep3m_ctx());
   if (!ctx) return FEP3M_ERR_OOM;
   int st = guarded(ctx.get(), [&] { ctx->build(L, N, dims[0], q, o); });
@@ -676,6 +828,11 @@ int fep3m_energy_forces_ex(fep3m_ctx *ctx, const double *x, const double *Q, dou
 
 int fep3m_energy_forces(fep3m_ctx *ctx, const double *x, const double *Q, double *U, double *F) {
   return fep3m_energy_forces_ex(ctx, x, Q, nullptr, U, F, nullptr);
+}
+
+int fep3m_backward(fep3m_ctx *ctx, int64_t generation, double *F, double *dUdQ) {
+  if (!ctx || (!F && !dUdQ)) return FEP3M_ERR_ARG;
+  return guarded(ctx, [&] { ctx->backward(generation, F, dUdQ); });
 }
 
 int64_t fep3m_stage_bytes(const fep3m_ctx *ctx, int32_t stage) {
@@ -724,6 +881,7 @@ int fep3m_set_profiling(fep3m_ctx *ctx, int32_t on) {
       for (hipEvent_t &e : ctx->prof.stage_ev) hip_check(hipEventCreate(&e), "event create");
       ctx->prof.kev.resize(2 * 512);
       ctx->prof.kwork.resize(512);
+      ctx->prof.kslot.resize(512);
       for (hipEvent_t &e : ctx->prof.kev) hip_check(hipEventCreate(&e), "event create");
     }
     ctx->prof.on = on != 0;

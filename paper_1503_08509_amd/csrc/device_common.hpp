@@ -11,27 +11,51 @@ constexpr int kMaxP = 6;           // largest element order handled by the kerne
 constexpr int kRedBlocks = 1024;   // fixed block count of every two-stage reduction
 constexpr int kRedThreads = 256;
 
-// 1-D element operator of one multigrid level, passed by value.
-struct LevelOp {
+// 1-D element operator of one multigrid level, passed by value, in the
+// arithmetic type T of the kernels that apply it.
+template <class T>
+struct LevelOpT {
   int p;                 // element order
   int n;                 // elements per axis (periodic)
   int P;                 // DOFs per axis = p * n
-  double ke[(kMaxP + 1) * (kMaxP + 1)];  // element stiffness, row-major (p+1)^2
-  double me[(kMaxP + 1) * (kMaxP + 1)];  // element mass
-  double dk[kMaxP];      // diagonal of assembled K1 at local index k (k = 0: vertex)
-  double dm[kMaxP];      // diagonal of assembled M1
+  T ke[(kMaxP + 1) * (kMaxP + 1)];  // element stiffness, row-major (p+1)^2
+  T me[(kMaxP + 1) * (kMaxP + 1)];  // element mass
+  T dk[kMaxP];           // diagonal of assembled K1 at local index k (k = 0: vertex)
+  T dm[kMaxP];           // diagonal of assembled M1
+
+  template <class U>
+  LevelOpT<U> cast() const {
+    LevelOpT<U> o{};
+    o.p = p; o.n = n; o.P = P;
+    for (int i = 0; i < (kMaxP + 1) * (kMaxP + 1); ++i) { o.ke[i] = U(ke[i]); o.me[i] = U(me[i]); }
+    for (int i = 0; i < kMaxP; ++i) { o.dk[i] = U(dk[i]); o.dm[i] = U(dm[i]); }
+    return o;
+  }
 };
+using LevelOp = LevelOpT<double>;
+using LevelOpF = LevelOpT<float>;
 
 // Prolongation weights from a coarse level (pc, nc) to a fine level (pf, nf):
 // fine nodes inside one coarse element are numbered s = 0 .. r*pf - 1
 // (r = nf / nc); w[s * (pc+1) + j] is coarse basis j at fine node s.
-struct Transfer {
+template <class T>
+struct TransferT {
   int pf, nf, Pf;
   int pc, nc, Pc;
   int r;                  // fine elements per coarse element per axis
   int ns;                 // r * pf
-  double w[3 * kMaxP * (kMaxP + 1)];   // ns <= 3 * kMaxP
+  T w[3 * kMaxP * (kMaxP + 1)];   // ns <= 3 * kMaxP
+
+  template <class U>
+  TransferT<U> cast() const {
+    TransferT<U> o{};
+    o.pf = pf; o.nf = nf; o.Pf = Pf; o.pc = pc; o.nc = nc; o.Pc = Pc; o.r = r; o.ns = ns;
+    for (int i = 0; i < 3 * kMaxP * (kMaxP + 1); ++i) o.w[i] = U(w[i]);
+    return o;
+  }
 };
+using Transfer = TransferT<double>;
+using TransferF = TransferT<float>;
 
 enum ApplyMode : int {
   kApply = 0,      // out = K x

@@ -199,10 +199,10 @@ __global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__r
 }
 
 // Forces and dU/dQ per sorted charge, scattered to caller order.
-template <int PO>
+template <int PO, class WT>
 __global__ __launch_bounds__(256) void k_forces(int n, int64_t N, double inv_h, GllBasis bas,
                                                 const double *__restrict__ sg, const double *__restrict__ sQ,
-                                                const double *__restrict__ Wel, const double *__restrict__ Aadj,
+                                                const WT *__restrict__ Wel, const double *__restrict__ Aadj,
                                                 const double *__restrict__ fpair, const double *__restrict__ phip,
                                                 const double *__restrict__ phim_s, const int *__restrict__ perm,
                                                 double *__restrict__ F, double *__restrict__ dUdQ) {
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void k_forces(int n, int64_t N, double inv_h, 
       }
     }
     const size_t E = size_t(e[0]) + size_t(n) * (e[1] + size_t(n) * e[2]);
-    const double *w = Wel + E * (Q1 * Q1 * Q1);
+    const WT *w = Wel + E * (Q1 * Q1 * Q1);
     double gxs = 0.0, gys = 0.0, gzs = 0.0;
 #pragma unroll
     for (int mz = 0; mz < Q1; ++mz) {
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_forces(int n, int64_t N, double inv_h, 
         double rl = 0.0, rd = 0.0;
 #pragma unroll
         for (int mx = 0; mx < Q1; ++mx) {
-          const double wv = w[(mz * Q1 + my) * Q1 + mx];
+          const double wv = double(w[(mz * Q1 + my) * Q1 + mx]);
           rl += l[0][mx] * wv;
           rd += dl[0][mx] * wv;
         }
@@ -263,9 +263,11 @@ __global__ __launch_bounds__(256) void k_forces(int n, int64_t N, double inv_h, 
     const double q = sQ[s];
     const double s2 = inv_h * inv_h;
     const int i = perm[s];
-    F[3 * size_t(i) + 0] = -s2 * (q * fpair[s] + 0.5 * q * (gxs + ax));
-    F[3 * size_t(i) + 1] = -s2 * (q * fpair[N + s] + 0.5 * q * (gys + ay));
-    F[3 * size_t(i) + 2] = -s2 * (q * fpair[2 * N + s] + 0.5 * q * (gzs + az));
+    if (F) {
+      F[3 * size_t(i) + 0] = -s2 * (q * fpair[s] + 0.5 * q * (gxs + ax));
+      F[3 * size_t(i) + 1] = -s2 * (q * fpair[N + s] + 0.5 * q * (gys + ay));
+      F[3 * size_t(i) + 2] = -s2 * (q * fpair[2 * N + s] + 0.5 * q * (gzs + az));
+    }
     if (dUdQ) dUdQ[i] = inv_h * phip[s] + 0.5 * phim_s[s] + 0.5 * inv_h * au;
   }
 }
@@ -296,15 +298,22 @@ int launch_adj_moments(hipStream_t s, int p, int n, int nsr, const double *gE, c
     default: return -1;
   }
 }
+template <class WT>
 int launch_forces(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const double *sg,
-                  const double *sQ, const double *Wel, const double *A, const double *fpair, const double *phip,
+                  const double *sQ, const WT *Wel, const double *A, const double *fpair, const double *phip,
                   const double *phim_s, const int *perm, double *F, double *dUdQ) {
   if (p != 5) return -1;
   int64_t gb = (N + 255) / 256;
   if (gb > 4096) gb = 4096;
-  hipLaunchKernelGGL(k_forces<5>, dim3(int(gb)), dim3(256), 0, s, n, N, inv_h, bas, sg, sQ, Wel, A, fpair, phip,
-                     phim_s, perm, F, dUdQ);
+  hipLaunchKernelGGL((k_forces<5, WT>), dim3(int(gb)), dim3(256), 0, s, n, N, inv_h, bas, sg, sQ, Wel, A, fpair,
+                     phip, phim_s, perm, F, dUdQ);
   return 0;
 }
+template int launch_forces<double>(hipStream_t, int, int, int64_t, double, const GllBasis &, const double *,
+                                   const double *, const double *, const double *, const double *, const double *,
+                                   const double *, const int *, double *, double *);
+template int launch_forces<float>(hipStream_t, int, int, int64_t, double, const GllBasis &, const double *,
+                                  const double *, const float *, const double *, const double *, const double *,
+                                  const double *, const int *, double *, double *);
 
 }  // namespace fep3m

@@ -158,14 +158,13 @@ struct ApplyShape {
 // k = o mod PO, with v indexed from one element below the first output.
 // Every coefficient index is a compile-time constant, so the (wave-uniform)
 // coefficients come from scalar registers.
-template <int PO, int NOUT>
-__device__ __forceinline__ void band_apply(const double *__restrict__ a, const double (&v)[NOUT + PO + 1],
-                                           double (&out)[NOUT]) {
+template <int PO, int NOUT, class T>
+__device__ __forceinline__ void band_apply(const T *__restrict__ a, const T (&v)[NOUT + PO + 1], T (&out)[NOUT]) {
   constexpr int Q1 = PO + 1;
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
     const int k = o % PO;
-    double s = 0.0;
+    T s = T(0);
 #pragma unroll
     for (int j = 0; j < Q1; ++j) s += a[k * Q1 + j] * v[o + PO - k + j];
     if (k == 0) {
@@ -176,207 +175,161 @@ __device__ __forceinline__ void band_apply(const double *__restrict__ a, const d
   }
 }
 
-template <int PO, int NOUT>
-__device__ __forceinline__ void band_apply_acc(const double *__restrict__ a, const double (&v)[NOUT + PO + 1],
-                                               double (&out)[NOUT]) {
-  double t[NOUT];
+template <int PO, int NOUT, class T>
+__device__ __forceinline__ void band_apply_acc(const T *__restrict__ a, const T (&v)[NOUT + PO + 1], T (&out)[NOUT]) {
+  T t[NOUT];
   band_apply<PO, NOUT>(a, v, t);
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) out[o] += t[o];
 }
 
-// Barrier for LDS hand-offs only: waits for LDS traffic, leaves global
-// loads in flight (the next tile's prefetch crosses it).
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// The it-th of the TPB tiles handled by block b (Morton order inside each
-// XCD's octant when the grid allows it, else linear).  False past the end.
-__device__ __forceinline__ bool block_tile(int b, int it, int tpb, int tiles, int &tx, int &ty, int &tz) {
-  const int half = tiles >> 1;
-  if ((tiles & 1) == 0 && half > 0 && (half & (half - 1)) == 0 && (half * half * half) % tpb == 0) {
-    const int xcd = b & 7, idx = (b >> 3) * tpb + it;
-    tx = compact_bits(idx) + half * (xcd & 1);
-    ty = compact_bits(idx >> 1) + half * ((xcd >> 1) & 1);
-    tz = compact_bits(idx >> 2) + half * (xcd >> 2);
-    return true;
-  }
-  const int t = b * tpb + it;
-  if (t >= tiles * tiles * tiles) return false;
-  tx = t % tiles;
-  ty = (t / tiles) % tiles;
-  tz = t / (tiles * tiles);
-  return true;
-}
-
-// TPB tiles of TE^3 elements per block: y = K x on the owned nodes of each
-// tile, then the mode's epilogue.  The owned nodes of a tile are p*e + k,
-// k < p, for its elements; the inputs reach one element below and one node
-// above.  Pass z: each thread streams one (x, y) column of the input from
-// global memory and writes A = Mz x, B = Kz x; pass y: one (z, x) column of A
-// and B gives C1 = My A and C2 = Ky A + My B; pass x: one (z, y) row of C1,
-// C2 gives y = Kx C1 + Mx C2; the epilogue walks the owned nodes x-fastest.
-// The next tile's column and epilogue operands are fetched while the
-// current tile runs its LDS passes.
-template <int PO, int TE, int TPB>
-__global__ __launch_bounds__(256) void k_apply(LevelOp op, const double *__restrict__ x,
-                                               const double *__restrict__ f, double *__restrict__ out,
-                                               const double *xprev, double *xo, double c1, double c2, int mode,
+// One tile of TE^3 elements per block: y = K x on the owned nodes, then the
+// mode's epilogue.  The owned nodes of a tile are p*e + k, k < p, for its
+// elements; the inputs reach one element below and one node above.
+// Pass z: each thread streams one (x, y) column of the input from global
+// memory and writes A = Mz x, B = Kz x; pass y: one (z, x) column of A and B
+// gives C1 = My A and C2 = Ky A + My B; pass x: one (z, y) row of C1, C2
+// gives y = Kx C1 + Mx C2; the epilogue then walks the owned nodes x-fastest.
+template <class T, int PO, int TE>
+__global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restrict__ x, const T *__restrict__ f,
+                                               T *__restrict__ out, const T *xprev, T *xo, T c1, T c2, int mode,
                                                double *__restrict__ partial) {
   using S = ApplyShape<PO, TE>;
   constexpr int O = S::O, I = S::I;
-  constexpr int NIT = (O * O * O + 255) / 256;
-  __shared__ double lds[S::LDS];         // A, B; then C1, C2, Y; last the dot-product tree
-  __shared__ double invd[PO * PO * PO];  // 1 / diag(K) by local node index
-  __shared__ double Xo[O * O * O];       // x on the owned nodes (from the z-pass columns)
-  double *A = lds;
-  double *B = lds + O * S::SA;
-  double *C1 = lds;
-  double *C2 = lds + O * S::SC;
-  double *Y = lds + 2 * O * S::SC;
+  static_assert(S::LDS * sizeof(T) >= 256 * sizeof(double), "the dot-product tree reuses the tile");
+  __shared__ __align__(16) T lds[S::LDS];  // A, B; then C1, C2, Y; last the dot-product tree
+  __shared__ T invd[PO * PO * PO];         // 1 / diag(K) by local node index
+  __shared__ T Xo[O * O * O];              // x on the owned nodes (from the z-pass columns)
+  T *A = lds;
+  T *B = lds + O * S::SA;
+  T *C1 = lds;
+  T *C2 = lds + O * S::SC;
+  T *Y = lds + 2 * O * S::SC;
   const int P = op.P;
   const int tiles = (op.n + TE - 1) / TE;
+  int tx, ty, tz;
+  tile_coords(blockIdx.x, tiles, tx, ty, tz);
+  const int ox0 = tx * O, oy0 = ty * O, oz0 = tz * O;
   const int tid = threadIdx.x;
+
+  // Epilogue operands of this thread's owned nodes, fetched now so their
+  // latency hides behind the three passes.
+  constexpr int NIT = (O * O * O + 255) / 256;
   const bool need_f = (mode == kResidual) || (mode == kCheb);
-  const bool need_d = (mode == kCheb) && (c1 != 0.0);
+  const bool need_d = (mode == kCheb) && (c1 != T(0)) && (xprev != nullptr);   // null x_prev reads as zero
   for (int i = tid; i < PO * PO * PO; i += 256) {
     const int kx = i % PO, ky = (i / PO) % PO, kz = i / (PO * PO);
-    invd[i] = 1.0 / (op.dk[kx] * op.dm[ky] * op.dm[kz] + op.dm[kx] * op.dk[ky] * op.dm[kz] +
-                     op.dm[kx] * op.dm[ky] * op.dk[kz]);
+    invd[i] = T(1) / (op.dk[kx] * op.dm[ky] * op.dm[kz] + op.dm[kx] * op.dk[ky] * op.dm[kz] +
+                      op.dm[kx] * op.dm[ky] * op.dk[kz]);
   }
-  // global inputs of one tile: this thread's z-column and epilogue operands
-  auto fetch = [&](int tx, int ty, int tz, double (&v)[I], double (&ff)[NIT], double (&fd)[NIT]) {
-    const int ox0 = tx * O, oy0 = ty * O, oz0 = tz * O;
-    if (tid < I * I) {
-      const int lx = tid % I, ly = tid / I;
-      const int gx = wrapi(ox0 - PO + lx, P), gy = wrapi(oy0 - PO + ly, P);
+  T pf_f[NIT], pf_d[NIT];
 #pragma unroll
-      for (int z = 0; z < I; ++z) v[z] = x[(size_t(wrapi(oz0 - PO + z, P)) * P + gy) * P + gx];
-    }
+  for (int r = 0; r < NIT; ++r) {
+    const int li = tid + 256 * r;
+    const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
+    const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
+    const bool ok = li < O * O * O && gx < P && gy < P && gz < P;
+    const size_t g = ok ? (size_t(gz) * P + gy) * P + gx : 0;
+    pf_f[r] = (ok && need_f) ? f[g] : T(0);
+    pf_d[r] = (ok && need_d) ? xprev[g] : T(0);
+  }
+
+  // pass z
+  if (tid < I * I) {
+    const int lx = tid % I, ly = tid / I;
+    const int gx = wrapi(ox0 - PO + lx, P), gy = wrapi(oy0 - PO + ly, P);
+    T v[I];
 #pragma unroll
-    for (int r = 0; r < NIT; ++r) {
-      const int li = tid + 256 * r;
-      const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
-      const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
-      const bool ok = li < O * O * O && gx < P && gy < P && gz < P;
-      const size_t g = ok ? (size_t(gz) * P + gy) * P + gx : 0;
-      ff[r] = (ok && need_f) ? f[g] : 0.0;
-      fd[r] = (ok && need_d) ? xprev[g] : 0.0;
+    for (int z = 0; z < I; ++z) v[z] = x[(size_t(wrapi(oz0 - PO + z, P)) * P + gy) * P + gx];
+    if (lx >= PO && lx < PO + O && ly >= PO && ly < PO + O) {
+#pragma unroll
+      for (int oz = 0; oz < O; ++oz) Xo[(oz * O + (ly - PO)) * O + (lx - PO)] = v[oz + PO];
     }
-  };
-  int tx = 0, ty = 0, tz = 0;
-  bool valid = block_tile(blockIdx.x, 0, TPB, tiles, tx, ty, tz);
-  double v[I], pf_f[NIT], pf_d[NIT];
-  if (valid) fetch(tx, ty, tz, v, pf_f, pf_d);
+    T a[O];
+    band_apply<PO, O>(op.me, v, a);
+#pragma unroll
+    for (int oz = 0; oz < O; ++oz) A[oz * S::SA + tid] = a[oz];
+    band_apply<PO, O>(op.ke, v, a);
+#pragma unroll
+    for (int oz = 0; oz < O; ++oz) B[oz * S::SA + tid] = a[oz];
+  }
+  __syncthreads();
+  // pass y
+  T c1v[O], c2v[O];
+  const bool act2 = tid < O * I;
+  const int oz2 = tid / I, lx2 = tid % I;
+  if (act2) {
+    T v[I];
+#pragma unroll
+    for (int y = 0; y < I; ++y) v[y] = A[oz2 * S::SA + y * I + lx2];
+    band_apply<PO, O>(op.me, v, c1v);
+    band_apply<PO, O>(op.ke, v, c2v);
+#pragma unroll
+    for (int y = 0; y < I; ++y) v[y] = B[oz2 * S::SA + y * I + lx2];
+    band_apply_acc<PO, O>(op.me, v, c2v);
+  }
+  __syncthreads();
+  if (act2) {
+#pragma unroll
+    for (int oy = 0; oy < O; ++oy) {
+      C1[oz2 * S::SC + oy * S::RS + lx2] = c1v[oy];
+      C2[oz2 * S::SC + oy * S::RS + lx2] = c2v[oy];
+    }
+  }
+  __syncthreads();
+  // pass x
+  if (tid < O * O) {
+    const int oz = tid / O, oy = tid % O;
+    T v[I], yv[O];
+#pragma unroll
+    for (int xx = 0; xx < I; ++xx) v[xx] = C1[oz * S::SC + oy * S::RS + xx];
+    band_apply<PO, O>(op.ke, v, yv);
+#pragma unroll
+    for (int xx = 0; xx < I; ++xx) v[xx] = C2[oz * S::SC + oy * S::RS + xx];
+    band_apply_acc<PO, O>(op.me, v, yv);
+#pragma unroll
+    for (int ox = 0; ox < O; ++ox) Y[(oz * O + oy) * S::YS + ox] = yv[ox];
+  }
+  __syncthreads();
+  // epilogue on the owned nodes, x fastest
   double acc = 0.0;
-  for (int it = 0; it < TPB && valid; ++it) {
-    const int ox0 = tx * O, oy0 = ty * O, oz0 = tz * O;
-    int ntx = 0, nty = 0, ntz = 0;
-    const bool nvalid = (it + 1 < TPB) && block_tile(blockIdx.x, it + 1, TPB, tiles, ntx, nty, ntz);
-    double vn[I], nf[NIT], nd[NIT];
-    if (nvalid) fetch(ntx, nty, ntz, vn, nf, nd);
-    // pass z
-    if (tid < I * I) {
-      const int lx = tid % I, ly = tid / I;
-      if (lx >= PO && lx < PO + O && ly >= PO && ly < PO + O) {
 #pragma unroll
-        for (int oz = 0; oz < O; ++oz) Xo[(oz * O + (ly - PO)) * O + (lx - PO)] = v[oz + PO];
-      }
-      double a[O];
-      band_apply<PO, O>(op.me, v, a);
-#pragma unroll
-      for (int oz = 0; oz < O; ++oz) A[oz * S::SA + tid] = a[oz];
-      band_apply<PO, O>(op.ke, v, a);
-#pragma unroll
-      for (int oz = 0; oz < O; ++oz) B[oz * S::SA + tid] = a[oz];
+  for (int r = 0; r < NIT; ++r) {
+    const int li = tid + 256 * r;
+    const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
+    const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
+    const bool ok = li < O * O * O && gx < P && gy < P && gz < P;
+    const int lc = ok ? li : 0;
+    const int cx = lc % O, cy = (lc / O) % O, cz = lc / (O * O);
+    const T y = Y[(cz * O + cy) * S::YS + cx];
+    const T xv = Xo[lc];
+    const T rr = (pf_f[r] - y) * invd[(ox % PO) + PO * ((oy % PO) + PO * (oz % PO))];
+    const size_t g = (size_t(gz) * P + gy) * P + gx;
+    if (ok) {
+      if (mode == kApply) out[g] = y;
+      else if (mode == kResidual) out[g] = pf_f[r] - y;
+      else if (mode == kCheb) xo[g] = xv + c1 * (xv - pf_d[r]) + c2 * rr;  // may overwrite x_prev
+      else if (mode == kDinvApply) out[g] = -rr;                            // f = 0 here: -rr = D^-1 K x
+      else { out[g] = y; acc += double(xv) * double(y); }
     }
-    lds_barrier();
-    // pass y
-    double c1v[O], c2v[O];
-    const bool act2 = tid < O * I;
-    const int oz2 = tid / I, lx2 = tid % I;
-    if (act2) {
-      double w[I];
-#pragma unroll
-      for (int y = 0; y < I; ++y) w[y] = A[oz2 * S::SA + y * I + lx2];
-      band_apply<PO, O>(op.me, w, c1v);
-      band_apply<PO, O>(op.ke, w, c2v);
-#pragma unroll
-      for (int y = 0; y < I; ++y) w[y] = B[oz2 * S::SA + y * I + lx2];
-      band_apply_acc<PO, O>(op.me, w, c2v);
-    }
-    lds_barrier();
-    if (act2) {
-#pragma unroll
-      for (int oy = 0; oy < O; ++oy) {
-        C1[oz2 * S::SC + oy * S::RS + lx2] = c1v[oy];
-        C2[oz2 * S::SC + oy * S::RS + lx2] = c2v[oy];
-      }
-    }
-    lds_barrier();
-    // pass x
-    if (tid < O * O) {
-      const int oz = tid / O, oy = tid % O;
-      double w[I], yv[O];
-#pragma unroll
-      for (int xx = 0; xx < I; ++xx) w[xx] = C1[oz * S::SC + oy * S::RS + xx];
-      band_apply<PO, O>(op.ke, w, yv);
-#pragma unroll
-      for (int xx = 0; xx < I; ++xx) w[xx] = C2[oz * S::SC + oy * S::RS + xx];
-      band_apply_acc<PO, O>(op.me, w, yv);
-#pragma unroll
-      for (int ox = 0; ox < O; ++ox) Y[(oz * O + oy) * S::YS + ox] = yv[ox];
-    }
-    lds_barrier();
-    // epilogue on the owned nodes, x fastest
-#pragma unroll
-    for (int r = 0; r < NIT; ++r) {
-      const int li = tid + 256 * r;
-      const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
-      const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
-      const bool ok = li < O * O * O && gx < P && gy < P && gz < P;
-      const int lc = ok ? li : 0;
-      const int cx = lc % O, cy = (lc / O) % O, cz = lc / (O * O);
-      const double y = Y[(cz * O + cy) * S::YS + cx];
-      const double xv = Xo[lc];
-      const double rr = (pf_f[r] - y) * invd[(ox % PO) + PO * ((oy % PO) + PO * (oz % PO))];
-      const size_t g = (size_t(gz) * P + gy) * P + gx;
-      if (ok) {
-        if (mode == kApply) out[g] = y;
-        else if (mode == kResidual) out[g] = pf_f[r] - y;
-        else if (mode == kCheb) xo[g] = xv + c1 * (xv - pf_d[r]) + c2 * rr;  // may overwrite x_prev
-        else if (mode == kDinvApply) out[g] = -rr;                            // f = 0: -rr = D^-1 K x
-        else { out[g] = y; acc += xv * y; }
-      }
-    }
-    lds_barrier();  // LDS free for the next tile
-#pragma unroll
-    for (int z = 0; z < I; ++z) v[z] = vn[z];
-#pragma unroll
-    for (int r = 0; r < NIT; ++r) { pf_f[r] = nf[r]; pf_d[r] = nd[r]; }
-    tx = ntx; ty = nty; tz = ntz;
-    valid = nvalid;
   }
   if (mode == kApplyDot) {
-    __syncthreads();
-    double s = block_sum(acc, lds);
+    __syncthreads();  // every thread is done with Y before the tree reuses it
+    double s = block_sum(acc, reinterpret_cast<double *>(lds));
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
   }
 }
 
-// First Chebyshev step from a zero iterate: x = c2 D^-1 f, and x_prev = 0.
-__global__ __launch_bounds__(256) void k_cheb_first(LevelOp op, const double *__restrict__ f,
-                                                    double *__restrict__ xprev, double *__restrict__ x, double c2) {
+// First Chebyshev step from a zero iterate: x = c2 D^-1 f (the next step
+// reads its zero x_prev as a null pointer).
+template <class T>
+__global__ __launch_bounds__(256) void k_cheb_first(LevelOpT<T> op, const T *__restrict__ f, T *__restrict__ x, T c2) {
   const int P = op.P, p = op.p;
   const size_t total = size_t(P) * P * P;
   for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
     const int kx = int(g % P) % p, ky = int((g / P) % P) % p, kz = int(g / (size_t(P) * P)) % p;
-    const double D = op.dk[kx] * op.dm[ky] * op.dm[kz] + op.dm[kx] * op.dk[ky] * op.dm[kz] + op.dm[kx] * op.dm[ky] * op.dk[kz];
+    const T D = op.dk[kx] * op.dm[ky] * op.dm[kz] + op.dm[kx] * op.dk[ky] * op.dm[kz] + op.dm[kx] * op.dm[ky] * op.dk[kz];
     x[g] = c2 * f[g] / D;
-    xprev[g] = 0.0;
   }
 }
 
@@ -398,13 +351,13 @@ struct XferShape {
 
 // 1-D restriction of a register column v (fine nodes of the tile, from one
 // coarse element below) to the CO owned coarse nodes.
-template <int PC, int NS, int CO, int NF>
-__device__ __forceinline__ void restrict_col(const double *__restrict__ w, const double (&v)[NF], double (&o)[CO]) {
+template <int PC, int NS, int CO, int NF, class T>
+__device__ __forceinline__ void restrict_col(const T *__restrict__ w, const T (&v)[NF], T (&o)[CO]) {
   constexpr int Q = PC + 1;
 #pragma unroll
   for (int c = 0; c < CO; ++c) {
     const int ec = c / PC, j = c % PC;
-    double s = 0.0;
+    T s = T(0);
 #pragma unroll
     for (int q = 0; q < NS; ++q) s += w[q * Q + j] * v[NS * (ec + 1) + q];
     if (j == 0) {
@@ -415,14 +368,14 @@ __device__ __forceinline__ void restrict_col(const double *__restrict__ w, const
   }
 }
 
-template <int PF, int PC, int R, int TE>
-__global__ __launch_bounds__(256) void k_restrict(Transfer tr, const double *__restrict__ rf, double *__restrict__ fc) {
+template <class T, int PF, int PC, int R, int TE>
+__global__ __launch_bounds__(256) void k_restrict(TransferT<T> tr, const T *__restrict__ rf, T *__restrict__ fc) {
   using S = XferShape<PF, PC, R, TE>;
   constexpr int NS = S::NS, CO = S::CO, NF = S::NF;
   static_assert(NF * NF <= 256 && NF * CO <= 256 && CO * CO <= 256, "restriction tile too large");
-  __shared__ double G1[CO * NF * (NF + 1)];   // [cz][fy][fx]
-  __shared__ double G2[CO * CO * (NF + 1)];   // [cz][cy][fx]
-  __shared__ double Out[CO * CO * CO];        // [cz][cy][cx]
+  __shared__ T G1[CO * NF * (NF + 1)];   // [cz][fy][fx]
+  __shared__ T G2[CO * CO * (NF + 1)];   // [cz][cy][fx]
+  __shared__ T Out[CO * CO * CO];        // [cz][cy][cx]
   const int Pf = tr.Pf, Pc = tr.Pc;
   const int tiles = (tr.nc + TE - 1) / TE;
   int t = blockIdx.x;
@@ -435,7 +388,7 @@ __global__ __launch_bounds__(256) void k_restrict(Transfer tr, const double *__r
   if (tid < NF * NF) {  // pass z: one fine (x, y) column per thread, lanes along x
     const int fx = tid % NF, fy = tid / NF;
     const int gx = wrapi(fx0 + fx, Pf), gy = wrapi(fy0 + fy, Pf);
-    double v[NF], o[CO];
+    T v[NF], o[CO];
 #pragma unroll
     for (int i = 0; i < NF; ++i) v[i] = rf[(size_t(wrapi(fz0 + i, Pf)) * Pf + gy) * Pf + gx];
     restrict_col<PC, NS, CO, NF>(tr.w, v, o);
@@ -445,7 +398,7 @@ __global__ __launch_bounds__(256) void k_restrict(Transfer tr, const double *__r
   __syncthreads();
   if (tid < CO * NF) {  // pass y
     const int fx = tid % NF, cz = tid / NF;
-    double v[NF], o[CO];
+    T v[NF], o[CO];
 #pragma unroll
     for (int i = 0; i < NF; ++i) v[i] = G1[(cz * NF + i) * (NF + 1) + fx];
     restrict_col<PC, NS, CO, NF>(tr.w, v, o);
@@ -455,7 +408,7 @@ __global__ __launch_bounds__(256) void k_restrict(Transfer tr, const double *__r
   __syncthreads();
   if (tid < CO * CO) {  // pass x
     const int cy = tid % CO, cz = tid / CO;
-    double v[NF], o[CO];
+    T v[NF], o[CO];
 #pragma unroll
     for (int i = 0; i < NF; ++i) v[i] = G2[(cz * CO + cy) * (NF + 1) + i];
     restrict_col<PC, NS, CO, NF>(tr.w, v, o);
@@ -472,13 +425,13 @@ __global__ __launch_bounds__(256) void k_restrict(Transfer tr, const double *__r
 
 // 1-D prolongation of a coarse register column (CI nodes from the tile's
 // first coarse node) to the FO owned fine nodes.
-template <int PC, int NS, int CI, int FO>
-__device__ __forceinline__ void prolong_col(const double *__restrict__ w, const double (&v)[CI], double (&o)[FO]) {
+template <int PC, int NS, int CI, int FO, class T>
+__device__ __forceinline__ void prolong_col(const T *__restrict__ w, const T (&v)[CI], T (&o)[FO]) {
   constexpr int Q = PC + 1;
 #pragma unroll
   for (int f = 0; f < FO; ++f) {
     const int e = f / NS, s = f % NS;
-    double a = 0.0;
+    T a = T(0);
 #pragma unroll
     for (int j = 0; j < Q; ++j) a += w[s * Q + j] * v[PC * e + j];
     o[f] = a;
@@ -486,15 +439,14 @@ __device__ __forceinline__ void prolong_col(const double *__restrict__ w, const 
 }
 
 // xf += P ec on a tile of TE^3 coarse elements (three separable passes).
-template <int PF, int PC, int R, int TE>
-__global__ __launch_bounds__(256) void k_prolong_add(Transfer tr, const double *__restrict__ ec,
-                                                     double *__restrict__ xf) {
+template <class T, int PF, int PC, int R, int TE>
+__global__ __launch_bounds__(256) void k_prolong_add(TransferT<T> tr, const T *__restrict__ ec, T *__restrict__ xf) {
   using S = XferShape<PF, PC, R, TE>;
   constexpr int NS = S::NS, CI = S::CI, FO = S::FO;
   static_assert(CI * CI <= 256 && CI * FO <= 256 && FO * FO <= 256, "prolongation tile too large");
-  __shared__ double H1[FO * CI * (CI + 1)];   // [fz][cy][cx]
-  __shared__ double H2[FO * FO * (CI + 1)];   // [fz][fy][cx]
-  __shared__ double Out[FO * FO * FO];        // [fz][fy][fx]
+  __shared__ T H1[FO * CI * (CI + 1)];   // [fz][cy][cx]
+  __shared__ T H2[FO * FO * (CI + 1)];   // [fz][fy][cx]
+  __shared__ T Out[FO * FO * FO];        // [fz][fy][fx]
   const int Pf = tr.Pf, Pc = tr.Pc;
   const int tiles = (tr.nc + TE - 1) / TE;
   int t = blockIdx.x;
@@ -505,19 +457,19 @@ __global__ __launch_bounds__(256) void k_prolong_add(Transfer tr, const double *
   const int tid = threadIdx.x;
   const int cx0 = PC * TE * tx, cy0 = PC * TE * ty, cz0 = PC * TE * tz;
   constexpr int NIT = (FO * FO * FO + 255) / 256;
-  double pf[NIT];  // fine values to update, fetched before the passes
+  T pf[NIT];  // fine values to update, fetched before the passes
 #pragma unroll
   for (int r = 0; r < NIT; ++r) {
     const int li = tid + 256 * r;
     const int fx = li % FO, fy = (li / FO) % FO, fz = li / (FO * FO);
     const int gx = NS * TE * tx + fx, gy = NS * TE * ty + fy, gz = NS * TE * tz + fz;
     const bool ok = li < FO * FO * FO && gx < Pf && gy < Pf && gz < Pf;
-    pf[r] = ok ? xf[(size_t(gz) * Pf + gy) * Pf + gx] : 0.0;
+    pf[r] = ok ? xf[(size_t(gz) * Pf + gy) * Pf + gx] : T(0);
   }
   if (tid < CI * CI) {  // pass z
     const int cx = tid % CI, cy = tid / CI;
     const int gx = wrapi(cx0 + cx, Pc), gy = wrapi(cy0 + cy, Pc);
-    double v[CI], o[FO];
+    T v[CI], o[FO];
 #pragma unroll
     for (int i = 0; i < CI; ++i) v[i] = ec[(size_t(wrapi(cz0 + i, Pc)) * Pc + gy) * Pc + gx];
     prolong_col<PC, NS, CI, FO>(tr.w, v, o);
@@ -527,7 +479,7 @@ __global__ __launch_bounds__(256) void k_prolong_add(Transfer tr, const double *
   __syncthreads();
   if (tid < FO * CI) {  // pass y
     const int cx = tid % CI, fz = tid / CI;
-    double v[CI], o[FO];
+    T v[CI], o[FO];
 #pragma unroll
     for (int i = 0; i < CI; ++i) v[i] = H1[(fz * CI + i) * (CI + 1) + cx];
     prolong_col<PC, NS, CI, FO>(tr.w, v, o);
@@ -537,7 +489,7 @@ __global__ __launch_bounds__(256) void k_prolong_add(Transfer tr, const double *
   __syncthreads();
   if (tid < FO * FO) {  // pass x
     const int fy = tid % FO, fz = tid / FO;
-    double v[CI], o[FO];
+    T v[CI], o[FO];
 #pragma unroll
     for (int i = 0; i < CI; ++i) v[i] = H2[(fz * FO + fy) * (CI + 1) + i];
     prolong_col<PC, NS, CI, FO>(tr.w, v, o);
@@ -560,8 +512,9 @@ __global__ __launch_bounds__(256) void k_prolong_add(Transfer tr, const double *
 // x = (V (x) V (x) V) diag(1 / (l_i + l_j + l_k)) (V (x) V (x) V)^T f with the
 // constant mode (l = 0) dropped.  One block; nc^3 <= kCoarseMax.
 constexpr int kCoarseMax = 4096;
+template <class T>
 __global__ __launch_bounds__(256) void k_coarse_solve(int Pn, const double *__restrict__ V, const double *__restrict__ lam,
-                                                      const double *__restrict__ f, double *__restrict__ x) {
+                                                      const T *__restrict__ f, T *__restrict__ x) {
   __shared__ double a[kCoarseMax];
   __shared__ double b[kCoarseMax];
   const int N3 = Pn * Pn * Pn;
@@ -609,7 +562,7 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int Pn, const double *__re
     const int ix = i % Pn, rest = i - ix;
     double s = 0.0;
     for (int c = 0; c < Pn; ++c) s += V[ix * Pn + c] * b[rest + c];
-    x[i] = s;
+    x[i] = T(s);
   }
 }
 
@@ -661,6 +614,39 @@ __global__ __launch_bounds__(256) void k_hash_fill(size_t n, uint32_t seed, doub
   }
 }
 
+// Mixed precision: the float64 PCG hands its residual to a float32 V-cycle
+// and takes the preconditioned residual back.
+__global__ __launch_bounds__(256) void k_to_f32(size_t n, const double *__restrict__ a, float *__restrict__ b) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    b[i] = float(a[i]);
+}
+
+// Block partials of z.r (first kRedBlocks slots) and z.q (next kRedBlocks),
+// float64 sums of a float32 z.
+__global__ __launch_bounds__(256) void k_dot2_f32(size_t n, const float *__restrict__ z, const double *__restrict__ r,
+                                                  const double *__restrict__ q, double *__restrict__ partial) {
+  __shared__ double red[256];
+  double a = 0.0, b = 0.0;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+    const double zi = double(z[i]);
+    a += zi * r[i];
+    if (q) b += zi * q[i];
+  }
+  const double ta = block_sum(a, red);
+  const double tb = block_sum(b, red);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = ta;
+    partial[gridDim.x + blockIdx.x] = tb;
+  }
+}
+
+// p = z + beta p (p = z when beta == 0: p is not read), z float32.
+__global__ __launch_bounds__(256) void k_xpay_f32(size_t n, double beta, const float *__restrict__ z,
+                                                  double *__restrict__ p) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    p[i] = beta == 0.0 ? double(z[i]) : double(z[i]) + beta * p[i];
+}
+
 // Second stage of every reduction: one block sums `count` partials in a
 // fixed order into out[0].
 __global__ __launch_bounds__(256) void k_sum_partials(int count, const double *__restrict__ partial, double *__restrict__ out) {
@@ -700,28 +686,23 @@ void launch_sub_const(hipStream_t s, size_t total, double invV, const double *sc
   hipLaunchKernelGGL(k_sub_const, dim3(grid_for(total)), dim3(256), 0, s, total, invV, scal, v);
 }
 
-// Tiles per block.  One: with several tiles per block the prefetch registers
-// lower occupancy more than the overlap gains (measured).
-static inline int apply_tpb(int) { return 1; }
-
-template <int PO, int TE>
-static int apply_impl(hipStream_t s, const LevelOp &op, const double *x, const double *f, double *out,
-                      const double *d, double *xo, double c1, double c2, int mode, double *partial) {
+template <class T, int PO, int TE>
+static int apply_impl(hipStream_t s, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *d, T *xo, T c1,
+                      T c2, int mode, double *partial) {
   const int tiles = (op.n + TE - 1) / TE;
-  const int nt = tiles * tiles * tiles;
-  const int tpb = apply_tpb(tiles);
-  const int nb = (nt + tpb - 1) / tpb;
-  hipLaunchKernelGGL((k_apply<PO, TE, 1>), dim3(nb), dim3(256), 0, s, op, x, f, out, d, xo, c1, c2, mode, partial);
+  const int nb = tiles * tiles * tiles;
+  hipLaunchKernelGGL((k_apply<T, PO, TE>), dim3(nb), dim3(256), 0, s, op, x, f, out, d, xo, c1, c2, mode, partial);
   return nb;
 }
 
-int launch_apply(hipStream_t s, const LevelOp &op, const double *x, const double *f, double *out,
-                 const double *d, double *xo, double c1, double c2, int mode, double *partial) {
+template <class T>
+int launch_apply(hipStream_t s, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *d, T *xo, T c1, T c2,
+                 int mode, double *partial) {
   switch (op.p) {
-    case 1: return apply_impl<1, 8>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
-    case 2: return apply_impl<2, 4>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
-    case 3: return apply_impl<3, 3>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
-    case 5: return apply_impl<5, 2>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 1: return apply_impl<T, 1, 8>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 2: return apply_impl<T, 2, 4>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 3: return apply_impl<T, 3, 3>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 5: return apply_impl<T, 5, 2>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
     default: return -1;
   }
 }
@@ -729,49 +710,64 @@ int launch_apply(hipStream_t s, const LevelOp &op, const double *x, const double
 int apply_blocks(const LevelOp &op) {
   int TE = op.p == 1 ? 8 : op.p == 2 ? 4 : op.p == 3 ? 3 : 2;
   int tiles = (op.n + TE - 1) / TE;
-  const int tpb = apply_tpb(tiles);
-  return (tiles * tiles * tiles + tpb - 1) / tpb;
+  return tiles * tiles * tiles;
 }
 
-void launch_cheb_first(hipStream_t s, const LevelOp &op, const double *f, double *d, double *x, double c2) {
-  // d receives x_prev = 0
+template <class T>
+void launch_cheb_first(hipStream_t s, const LevelOpT<T> &op, const T *f, T *x, T c2) {
   const size_t tot = size_t(op.P) * op.P * op.P;
-  hipLaunchKernelGGL(k_cheb_first, dim3(grid_for(tot)), dim3(256), 0, s, op, f, d, x, c2);
+  hipLaunchKernelGGL(k_cheb_first<T>, dim3(grid_for(tot)), dim3(256), 0, s, op, f, x, c2);
 }
-template <int PF, int PC, int R, int TE>
-static void restrict_impl(hipStream_t s, const Transfer &tr, const double *in, double *out) {
+template <class T, int PF, int PC, int R, int TE>
+static void restrict_impl(hipStream_t s, const TransferT<T> &tr, const T *in, T *out) {
   const int tiles = (tr.nc + TE - 1) / TE;
-  hipLaunchKernelGGL((k_restrict<PF, PC, R, TE>), dim3(tiles * tiles * tiles), dim3(256), 0, s, tr, in, out);
+  hipLaunchKernelGGL((k_restrict<T, PF, PC, R, TE>), dim3(tiles * tiles * tiles), dim3(256), 0, s, tr, in, out);
 }
-template <int PF, int PC, int R, int TE>
-static void prolong_impl(hipStream_t s, const Transfer &tr, const double *in, double *out) {
+template <class T, int PF, int PC, int R, int TE>
+static void prolong_impl(hipStream_t s, const TransferT<T> &tr, const T *in, T *out) {
   const int tiles = (tr.nc + TE - 1) / TE;
-  hipLaunchKernelGGL((k_prolong_add<PF, PC, R, TE>), dim3(tiles * tiles * tiles), dim3(256), 0, s, tr, in, out);
+  hipLaunchKernelGGL((k_prolong_add<T, PF, PC, R, TE>), dim3(tiles * tiles * tiles), dim3(256), 0, s, tr, in, out);
 }
 
 // Supported transfers: p 5 -> 3 and 3 -> 1 on one mesh, Q1 coarsening by 2 or 3.
-int launch_transfer(hipStream_t s, const Transfer &tr, const double *in, double *out, bool restrict_) {
+template <class T>
+int launch_transfer(hipStream_t s, const TransferT<T> &tr, const T *in, T *out, bool restrict_) {
   if (tr.pf == 5 && tr.pc == 3 && tr.r == 1) {
-    if (restrict_) restrict_impl<5, 3, 1, 2>(s, tr, in, out); else prolong_impl<5, 3, 1, 2>(s, tr, in, out);
+    if (restrict_) restrict_impl<T, 5, 3, 1, 2>(s, tr, in, out); else prolong_impl<T, 5, 3, 1, 2>(s, tr, in, out);
   } else if (tr.pf == 3 && tr.pc == 1 && tr.r == 1) {
-    if (restrict_) restrict_impl<3, 1, 1, 4>(s, tr, in, out); else prolong_impl<3, 1, 1, 5>(s, tr, in, out);
+    if (restrict_) restrict_impl<T, 3, 1, 1, 4>(s, tr, in, out); else prolong_impl<T, 3, 1, 1, 5>(s, tr, in, out);
   } else if (tr.pf == 1 && tr.pc == 1 && tr.r == 2) {
-    if (restrict_) restrict_impl<1, 1, 2, 7>(s, tr, in, out); else prolong_impl<1, 1, 2, 8>(s, tr, in, out);
+    if (restrict_) restrict_impl<T, 1, 1, 2, 7>(s, tr, in, out); else prolong_impl<T, 1, 1, 2, 8>(s, tr, in, out);
   } else if (tr.pf == 1 && tr.pc == 1 && tr.r == 3) {
-    if (restrict_) restrict_impl<1, 1, 3, 4>(s, tr, in, out); else prolong_impl<1, 1, 3, 5>(s, tr, in, out);
+    if (restrict_) restrict_impl<T, 1, 1, 3, 4>(s, tr, in, out); else prolong_impl<T, 1, 1, 3, 5>(s, tr, in, out);
   } else {
     return -1;
   }
   return 0;
 }
-void launch_restrict(hipStream_t s, const Transfer &tr, const double *rf, double *fc) {
-  launch_transfer(s, tr, rf, fc, true);
+template <class T>
+void launch_coarse_solve(hipStream_t s, int Pn, const double *V, const double *lam, const T *f, T *x) {
+  hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(256), 0, s, Pn, V, lam, f, x);
 }
-void launch_prolong_add(hipStream_t s, const Transfer &tr, const double *ec, double *xf) {
-  launch_transfer(s, tr, ec, xf, false);
+
+#define FEP3M_MESH_INSTANTIATE(T)                                                                              \
+  template int launch_apply<T>(hipStream_t, const LevelOpT<T> &, const T *, const T *, T *, const T *, T *, T, \
+                               T, int, double *);                                                              \
+  template void launch_cheb_first<T>(hipStream_t, const LevelOpT<T> &, const T *, T *, T);                     \
+  template int launch_transfer<T>(hipStream_t, const TransferT<T> &, const T *, T *, bool);                    \
+  template void launch_coarse_solve<T>(hipStream_t, int, const double *, const double *, const T *, T *);
+FEP3M_MESH_INSTANTIATE(double)
+FEP3M_MESH_INSTANTIATE(float)
+#undef FEP3M_MESH_INSTANTIATE
+
+void launch_to_f32(hipStream_t s, size_t n, const double *a, float *b) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(256), 0, s, n, a, b);
 }
-void launch_coarse_solve(hipStream_t s, int Pn, const double *V, const double *lam, const double *f, double *x) {
-  hipLaunchKernelGGL(k_coarse_solve, dim3(1), dim3(256), 0, s, Pn, V, lam, f, x);
+void launch_dot2_f32(hipStream_t s, size_t n, const float *z, const double *r, const double *q, double *partial) {
+  hipLaunchKernelGGL(k_dot2_f32, dim3(kRedBlocks), dim3(256), 0, s, n, z, r, q, partial);
+}
+void launch_xpay_f32(hipStream_t s, size_t n, double beta, const float *z, double *p) {
+  hipLaunchKernelGGL(k_xpay_f32, dim3(grid_for(n)), dim3(256), 0, s, n, beta, z, p);
 }
 void launch_dot(hipStream_t s, size_t n, const double *a, const double *b, double *partial) {
   hipLaunchKernelGGL(k_dot, dim3(grid_for(n)), dim3(256), 0, s, n, a, b, partial);

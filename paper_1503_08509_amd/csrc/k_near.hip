@@ -17,13 +17,22 @@
 //            barrier per offset; every table value fetched from L2 serves the
 //            brick's 64 elements,
 //   moments C of the source elements sit in LDS as one z-slab per D_z.
+//
+// The arithmetic type T is double, or float for the mixed-precision path:
+// then the tables and moments are float32, each D_z slab (8 (2 NSR + 1)^2
+// products per output) is summed into a float32 partial, and the seven slab
+// partials are added with Kahan compensation; phi stays float64 and W is
+// written as float32.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace fep3m {
 
-template <int NSR, int PO>
-__global__ __launch_bounds__(256) void k_psi(int n, const double *__restrict__ C, const double *__restrict__ T,
-                                             const double *__restrict__ phi, double *__restrict__ Wel) {
+template <int NSR, int PO, class T>
+__global__ __launch_bounds__(256, 2) void k_psi(int n, const double *__restrict__ C, const T *__restrict__ Tab,
+                                             const double *__restrict__ phi, T *__restrict__ Wel) {
+  constexpr bool kComp = std::is_same<T, float>::value;   // compensated slab sums
   constexpr int BS = 4;                       // brick edge (elements)
   constexpr int H = BS + 2 * NSR;             // halo edge in x and y
   constexpr int S = 2 * NSR + 1;
@@ -37,8 +46,8 @@ __global__ __launch_bounds__(256) void k_psi(int n, const double *__restrict__ C
   constexpr int TPF = (TV + 255) / 256;       // prefetch registers per thread
   constexpr int SLAB = BS * H * H;            // one z-slab of the halo
   static_assert(NM % MT == 0 && NTHR <= 256, "thread tile");
-  __shared__ __align__(16) double Ts[2][TV];
-  __shared__ __align__(16) double Cs[8 * SLAB];
+  __shared__ __align__(16) T Ts[2][TV];
+  __shared__ __align__(16) T Cs[8 * SLAB];
 
   const int bricks = (n + BS - 1) / BS;
   int b = blockIdx.x;
@@ -53,16 +62,20 @@ __global__ __launch_bounds__(256) void k_psi(int n, const double *__restrict__ C
   const int ex0 = 2 * (ge & 1), ey0 = 2 * ((ge >> 1) & 1), ez0 = 2 * (ge >> 2);
   const int m0 = gm * MT;
 
-  double acc[8][MT];
+  T acc[8][MT];                       // slab partial (float) or the whole sum (double)
+  T tot[kComp ? 8 : 1][MT], cmp[kComp ? 8 : 1][MT];   // Kahan total and compensation (float)
 #pragma unroll
   for (int e = 0; e < 8; ++e)
 #pragma unroll
-    for (int j = 0; j < MT; ++j) acc[e][j] = 0.0;
+    for (int j = 0; j < MT; ++j) {
+      acc[e][j] = T(0);
+      if (kComp) { tot[e][j] = T(0); cmp[e][j] = T(0); }
+    }
 
   // table values of offset 0 into buffer 0
   for (int i = tid; i < TV; i += 256) {
     const int a = i / NM, m = i % NM;
-    Ts[0][i] = T[(size_t(a) * ND + 0) * NM + m];
+    Ts[0][i] = Tab[(size_t(a) * ND + 0) * NM + m];
   }
   int iD = 0;
   for (int Dz = -NSR; Dz <= NSR; ++Dz) {
@@ -75,14 +88,14 @@ __global__ __launch_bounds__(256) void k_psi(int n, const double *__restrict__ C
       const int ez = (z0 + lz - Dz + 2 * n) % n;
       const double *c = C + (size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * 8;
 #pragma unroll
-      for (int a = 0; a < 8; ++a) Cs[a * SLAB + h] = c[a];
+      for (int a = 0; a < 8; ++a) Cs[a * SLAB + h] = T(c[a]);
     }
     __syncthreads();
     for (int Dyx = 0; Dyx < S * S; ++Dyx, ++iD) {
       const int Dx = Dyx % S - NSR, Dy = Dyx / S - NSR;
       const int cur = iD & 1;
       // prefetch the next offset's tables into registers
-      double tp[TPF];
+      T tp[TPF];
       const bool more = iD + 1 < ND;
       if (more) {
 #pragma unroll
@@ -90,18 +103,18 @@ __global__ __launch_bounds__(256) void k_psi(int n, const double *__restrict__ C
           const int i = tid + 256 * r;
           if (i < TV) {
             const int a = i / NM, m = i % NM;
-            tp[r] = T[(size_t(a) * ND + iD + 1) * NM + m];
+            tp[r] = Tab[(size_t(a) * ND + iD + 1) * NM + m];
           }
         }
       }
       if (comp) {
-        const double *tb = Ts[cur];
+        const T *tb = Ts[cur];
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
-          double tv[MT];
+          T tv[MT];
 #pragma unroll
           for (int j = 0; j < MT; ++j) tv[j] = tb[a * NM + m0 + j];
-          double cv[8];
+          T cv[8];
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             const int lx = ex0 + (e & 1), ly = ey0 + ((e >> 1) & 1), lz = ez0 + (e >> 2);
@@ -122,6 +135,18 @@ __global__ __launch_bounds__(256) void k_psi(int n, const double *__restrict__ C
       }
       __syncthreads();
     }
+    if (kComp) {   // fold this slab's partial into the compensated total
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int j = 0; j < MT; ++j) {
+          const T y = acc[e][j] - cmp[e][j];
+          const T t = tot[e][j] + y;
+          cmp[e][j] = (t - tot[e][j]) - y;
+          tot[e][j] = t;
+          acc[e][j] = T(0);
+        }
+    }
   }
   if (!comp) return;
   const int P = PO * n;
@@ -135,21 +160,25 @@ __global__ __launch_bounds__(256) void k_psi(int n, const double *__restrict__ C
       const int m = m0 + j;
       const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
       const int gx = (PO * ex + mx) % P, gy = (PO * ey + my) % P, gz = (PO * ez + mz) % P;
-      Wel[E * NM + m] = phi[(size_t(gz) * P + gy) * P + gx] - acc[e][j];
+      const double psi = kComp ? double(tot[e][j]) - double(cmp[e][j]) : double(acc[e][j]);
+      Wel[E * NM + m] = T(phi[(size_t(gz) * P + gy) * P + gx] - psi);
     }
   }
 }
 
-int launch_psi(hipStream_t s, int n, int nsr, int p, const double *C, const double *T, const double *phi, double *Wel) {
+template <class T>
+int launch_psi(hipStream_t s, int n, int nsr, int p, const double *C, const T *Tab, const double *phi, T *Wel) {
   if (p != 5) return -1;
   const int bricks = (n + 3) / 4;
   dim3 g(bricks * bricks * bricks);
   switch (nsr) {
-    case 1: hipLaunchKernelGGL((k_psi<1, 5>), g, dim3(256), 0, s, n, C, T, phi, Wel); return 0;
-    case 2: hipLaunchKernelGGL((k_psi<2, 5>), g, dim3(256), 0, s, n, C, T, phi, Wel); return 0;
-    case 3: hipLaunchKernelGGL((k_psi<3, 5>), g, dim3(256), 0, s, n, C, T, phi, Wel); return 0;
+    case 1: hipLaunchKernelGGL((k_psi<1, 5, T>), g, dim3(256), 0, s, n, C, Tab, phi, Wel); return 0;
+    case 2: hipLaunchKernelGGL((k_psi<2, 5, T>), g, dim3(256), 0, s, n, C, Tab, phi, Wel); return 0;
+    case 3: hipLaunchKernelGGL((k_psi<3, 5, T>), g, dim3(256), 0, s, n, C, Tab, phi, Wel); return 0;
     default: return -1;
   }
 }
+template int launch_psi<double>(hipStream_t, int, int, int, const double *, const double *, const double *, double *);
+template int launch_psi<float>(hipStream_t, int, int, int, const double *, const float *, const double *, float *);
 
 }  // namespace fep3m

@@ -5,6 +5,7 @@
 // Positions are kept as g = n * frac(x / L) in element units: element
 // e = floor(g) (clamped to n - 1) and local offset u = g - e - 1/2.
 #include "kernels.hpp"
+#include "pair_segments.hpp"
 
 namespace fep3m {
 
@@ -169,46 +170,12 @@ template <int NSR, bool FORCE>
 __global__ __launch_bounds__(64) void k_pair(int n, int64_t N, const int *__restrict__ start,
                                              const double *__restrict__ sg, const double *__restrict__ sQ,
                                              double *__restrict__ phip, double *__restrict__ fpair) {
-  constexpr int W = 2 * NSR + 1;
-  constexpr int MAXSEG = 2 * W * W;
-  __shared__ int sb[MAXSEG];
-  __shared__ int sl[MAXSEG];
-  __shared__ int so[MAXSEG + 1];
-  __shared__ int ss[MAXSEG];  // packed image shifts (s + 1) per axis, 2 bits each, in units of n
+  __shared__ PairSegments<NSR> seg;
   const int lane = threadIdx.x;
   const int E = blockIdx.x;
   const int tb = start[E], te = start[E + 1];
   if (tb == te) return;  // uniform over the (single-wave) block
-  const int ex = E % n, ey = (E / n) % n, ez = E / (n * n);
-  for (int row = lane; row < W * W; row += 64) {
-    const int dy = row % W - NSR, dz = row / W - NSR;
-    int yy = ey + dy, zz = ez + dz, sy = 0, sz = 0;
-    if (yy < 0) { yy += n; sy = -1; } else if (yy >= n) { yy -= n; sy = 1; }
-    if (zz < 0) { zz += n; sz = -1; } else if (zz >= n) { zz -= n; sz = 1; }
-    const int rowE = n * (yy + n * zz);
-    const int x0 = ex - NSR, x1 = ex + NSR;
-    int bA, eA, shA, bB = 0, eB = 0, shB = 0;
-    if (x0 < 0) {
-      bA = start[rowE + x0 + n]; eA = start[rowE + n]; shA = -1;
-      bB = start[rowE]; eB = start[rowE + x1 + 1]; shB = 0;
-    } else if (x1 >= n) {
-      bA = start[rowE + x0]; eA = start[rowE + n]; shA = 0;
-      bB = start[rowE]; eB = start[rowE + x1 - n + 1]; shB = 1;
-    } else {
-      bA = start[rowE + x0]; eA = start[rowE + x1 + 1]; shA = 0;
-    }
-    const int pk = ((sy + 1) << 2) | ((sz + 1) << 4);
-    sb[2 * row] = bA; sl[2 * row] = eA - bA; ss[2 * row] = pk | (shA + 1);
-    sb[2 * row + 1] = bB; sl[2 * row + 1] = eB - bB; ss[2 * row + 1] = pk | (shB + 1);
-  }
-  __syncthreads();
-  if (lane == 0) {
-    int acc = 0;
-    for (int k = 0; k < MAXSEG; ++k) { so[k] = acc; acc += sl[k]; }
-    so[MAXSEG] = acc;
-  }
-  __syncthreads();
-  const int total = so[MAXSEG];
+  const int total = build_segments<NSR>(seg, E, n, start, lane, 64);
   const double nd = double(n);
   for (int t0 = tb; t0 < te; t0 += kTgt) {
     const int nt = min(kTgt, te - t0);
@@ -222,11 +189,11 @@ __global__ __launch_bounds__(64) void k_pair(int n, int64_t N, const int *__rest
     }
     int sp = 0;
     for (int f = lane; f < total; f += 64) {
-      while (f >= so[sp + 1]) ++sp;
-      const int j = sb[sp] + (f - so[sp]);
-      const int pk = ss[sp];
-      const double shx = double((pk & 3) - 1) * nd, shy = double(((pk >> 2) & 3) - 1) * nd,
-                   shz = double(((pk >> 4) & 3) - 1) * nd;
+      while (f >= seg.so[sp + 1]) ++sp;
+      const int j = seg.sb[sp] + (f - seg.so[sp]);
+      const int pk = seg.ss[sp];
+      const double shx = double(seg.shift(pk, 0)) * nd, shy = double(seg.shift(pk, 1)) * nd,
+                   shz = double(seg.shift(pk, 2)) * nd;
       const double jx = sg[j] + shx, jy = sg[N + j] + shy, jz = sg[2 * N + j] + shz;
       const double qj = sQ[j];
 #pragma unroll

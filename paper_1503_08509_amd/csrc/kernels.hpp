@@ -31,18 +31,31 @@ void launch_energy(hipStream_t s, int64_t N, const double *sQ, const double *phi
 void launch_half(hipStream_t s, const double *in, double *out);
 void launch_unpermute(hipStream_t s, int64_t N, double scale, const int *perm, const double *in, double *out);
 
+// mixed precision (k_mixed.hip): float32 local coordinates and charges
+// (su = {ux, uy, uz, Q}), packed elements sel = ex | ey << 10 | ez << 20
+void launch_local_f32(hipStream_t s, int n, int64_t N, const double *sg, const double *sQ, float4 *su, int *sel);
+int launch_pair_f32(hipStream_t s, int n, int nsr, int64_t N, const int *start, const float4 *su, const int *sel,
+                    double *phip, double *fpair);
+int launch_interp_f32(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const float4 *su,
+                      const int *sel, const float *Wel, const double *phip, const int *perm, double *phim_s,
+                      double *phi_s, double *Phi);
+
 // adjoint (k_adjoint.hip)
 int launch_deposit(hipStream_t s, int p, int n, int64_t N, const GllBasis &bas, const int *start, const double *sg,
                    const double *sQ, double *gE);
 int launch_assemble(hipStream_t s, int p, int n, const double *gE, double *G, double *partial);
 int launch_adj_moments(hipStream_t s, int p, int n, int nsr, const double *gE, const double *Tt, const double *lam,
                        const double *gw, double *A);
+// W of the forward pass in float64, or float32 on the mixed-precision path
+template <class WT>
 int launch_forces(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const double *sg,
-                  const double *sQ, const double *Wel, const double *A, const double *fpair, const double *phip,
+                  const double *sQ, const WT *Wel, const double *A, const double *fpair, const double *phip,
                   const double *phim_s, const int *perm, double *F, double *dUdQ);
 
 // near field (k_near.hip)
-int launch_psi(hipStream_t s, int n, int nsr, int p, const double *C, const double *T, const double *phi, double *Wel);
+// T = double, or float (float32 tables, compensated slab sums, float32 W)
+template <class T>
+int launch_psi(hipStream_t s, int n, int nsr, int p, const double *C, const T *Tab, const double *phi, T *Wel);
 
 // mesh (k_mesh.hip)
 int red_grid(size_t n);
@@ -51,14 +64,22 @@ void launch_sum_partials(hipStream_t s, int count, const double *partial, double
 void launch_sub_mass_ones(hipStream_t s, int n, int p, const double *w1, const double *scal, double *v);
 void launch_mass_dot(hipStream_t s, int n, int p, const double *w1, const double *v, double *partial);
 void launch_sub_const(hipStream_t s, size_t total, double invV, const double *scal, double *v);
-int launch_apply(hipStream_t s, const LevelOp &op, const double *x, const double *f, double *out,
-                 const double *xprev, double *xo, double c1, double c2, int mode, double *partial);
+// Multigrid kernels in the arithmetic type T (double, or float for the
+// mixed-precision preconditioner); instantiated for both in k_mesh.hip.
+template <class T>
+int launch_apply(hipStream_t s, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *xprev, T *xo, T c1,
+                 T c2, int mode, double *partial);
 int apply_blocks(const LevelOp &op);
-void launch_cheb_first(hipStream_t s, const LevelOp &op, const double *f, double *xprev, double *x, double c2);
-int launch_transfer(hipStream_t s, const Transfer &tr, const double *in, double *out, bool restrict_);
-void launch_restrict(hipStream_t s, const Transfer &tr, const double *rf, double *fc);
-void launch_prolong_add(hipStream_t s, const Transfer &tr, const double *ec, double *xf);
-void launch_coarse_solve(hipStream_t s, int Pn, const double *V, const double *lam, const double *f, double *x);
+template <class T>
+void launch_cheb_first(hipStream_t s, const LevelOpT<T> &op, const T *f, T *x, T c2);
+template <class T>
+int launch_transfer(hipStream_t s, const TransferT<T> &tr, const T *in, T *out, bool restrict_);
+template <class T>
+void launch_coarse_solve(hipStream_t s, int Pn, const double *V, const double *lam, const T *f, T *x);
+void launch_to_f32(hipStream_t s, size_t n, const double *a, float *b);
+// partial[0, kRedBlocks): block sums of z.r; partial[kRedBlocks, 2 kRedBlocks): z.q (0 if q is null)
+void launch_dot2_f32(hipStream_t s, size_t n, const float *z, const double *r, const double *q, double *partial);
+void launch_xpay_f32(hipStream_t s, size_t n, double beta, const float *z, double *p);
 void launch_dot(hipStream_t s, size_t n, const double *a, const double *b, double *partial);
 void launch_cg_update(hipStream_t s, size_t n, double alpha, const double *p, const double *q, double *x, double *r,
                       double *partial);

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_default_options_and_status_strings():
     o = fp.default_options()
-    assert o.n_sr == 3 and o.precision == 0 and o.mg_rtol == 1e-10 and o.table_box == 15
+    assert o.n_sr == 3 and o.precision == 0 and o.mg_rtol == 1e-7 and o.table_box == 15
     assert fp.lib().fep3m_default_options(None) == fp.ERR_ARG
     for st in range(0, -8, -1):
         assert fp.lib().fep3m_status_string(st)
@@ -78,7 +78,23 @@ def test_null_context_calls():
     assert L.fep3m_energy(None, None, None, None, None) == fp.ERR_ARG
     assert L.fep3m_stage_bytes(None, 0) == 0
     assert L.fep3m_get_stats(None, None) == fp.ERR_ARG
+    assert L.fep3m_backward(None, 0, None, None) == fp.ERR_ARG
     L.fep3m_destroy(None)
+
+
+@pytest.mark.parametrize("cname,mirror", [("fep3m_stats", "Stats"), ("fep3m_options", "Options")])
+def test_structs_match_header(cname, mirror):
+    """The binding's ctypes mirrors have the header's fields in order."""
+    src = open(os.path.join(ROOT, "include", "fep3m.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\} " + cname + ";", src).group(1)
+    fields = re.findall(r"\b(\w+);", body)
+    assert fields == [f for f, _ in getattr(fp, mirror)._fields_]
+
+
+def test_energy_function_is_an_autograd_function():
+    import torch
+    assert issubclass(fp.FEP3MEnergy, torch.autograd.Function)
 
 
 @pytest.mark.parametrize("n_sr,box", [(3, 15), (2, 11), (1, 9)])

@@ -88,3 +88,39 @@ def test_dUdQ_neutral_directions(torch):
         Up = float(ctx.energy(tx, torch.from_numpy(Qp).cuda())[1].item())
         Um = float(ctx.energy(tx, torch.from_numpy(Qm).cuda())[1].item())
         assert abs((Up - Um) / (2 * eps) - (g[i] - g[j])) < 1e-5 * max(1.0, abs(g[i] - g[j]))
+
+
+def test_autograd_function_matches_energy_forces(torch):
+    """FEP3MEnergy's backward (reused forward state, recomputed pair terms)
+    returns exactly the fused energy+force call's -F and dU/dQ."""
+    x, Q = workloads.make("uniform-1k-n8")
+    ctx = fp.Context(1.0, len(Q), 8)
+    tx = torch.from_numpy(x).cuda().requires_grad_(True)
+    tQ = torch.from_numpy(Q).cuda().requires_grad_(True)
+    U = fp.FEP3MEnergy.apply(tx, tQ, ctx)
+    (2.0 * U).backward()
+    ref = ctx.energy_forces(tx.detach(), tQ.detach(), dUdQ=True)
+    assert float(U.item()) == float(ref["U"].item())
+    np.testing.assert_array_equal(tx.grad.cpu().numpy(), -2.0 * ref["F"].cpu().numpy())
+    np.testing.assert_array_equal(tQ.grad.cpu().numpy(), 2.0 * ref["dUdQ"].cpu().numpy())
+
+
+def test_autograd_single_input_and_stale_state(torch):
+    x, Q = workloads.make("uniform-1k-n8")
+    ctx = fp.Context(1.0, len(Q), 8)
+    tQ = torch.from_numpy(Q).cuda()
+    tx = torch.from_numpy(x).cuda().requires_grad_(True)
+    U = fp.FEP3MEnergy.apply(tx, tQ, ctx)
+    (gx,) = torch_autograd_grad(torch, U, [tx])
+    F = ctx.energy_forces(tx.detach(), tQ)["F"]
+    np.testing.assert_array_equal(gx.cpu().numpy(), -F.cpu().numpy())
+    # a later evaluation on the same context invalidates the earlier forward state
+    U1 = fp.FEP3MEnergy.apply(tx, tQ, ctx)
+    ctx.energy(tx.detach(), tQ)
+    with pytest.raises(fp.FEP3MError) as ei:
+        U1.backward()
+    assert ei.value.status == fp.ERR_ARG
+
+
+def torch_autograd_grad(torch, out, inputs):
+    return torch.autograd.grad(out, inputs)

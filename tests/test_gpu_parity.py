@@ -103,7 +103,7 @@ def test_small_and_ragged(torch, case):
                       [-0.125, 0.5, 0.625], [0.3, 0.7, 0.9], [0.5, 0.5, 0.5]])
         Q = np.array([1.0, -1.0, 0.5, -0.5, 2.0, -2.0])
     ref = fep3m.run(x, Q, fep3m.Params(L=L, n=n), stages=True)
-    ctx, Phi, U = _gpu(torch, x, Q, L, n)
+    ctx, Phi, U = _gpu(torch, x, Q, L, n, mg_rtol=1e-12)
     order, start = _stable_order(ref["e_lin"], n)
     np.testing.assert_array_equal(ctx.stage("perm").cpu().numpy(), order)
     assert _rel_rms(Phi, ref["Phi"]) < 1e-8
@@ -119,8 +119,8 @@ def test_config2_sampled_parity(torch):
     rng = np.random.default_rng(7)
     tgt = np.sort(rng.choice(len(Q), 400, replace=False))
     ref = fep3m.run(x, Q, fep3m.Params(L=L, n=n), targets=tgt, stages=True)
-    phi = ctx.stage("phi").cpu().numpy()                       # default solve tolerance 1e-10
-    assert np.abs(phi - ref["phi"].ravel()).max() < 1e-7 * np.abs(ref["phi"]).max()
+    phi = ctx.stage("phi").cpu().numpy()         # default solve tolerance (relative residual 1e-7)
+    assert np.abs(phi - ref["phi"].ravel()).max() < 5e-7 * np.abs(ref["phi"]).max()
     assert _rel_rms(Phi[tgt], ref["Phi"]) < 1e-6
     # every charge: the energy is consistent with the returned potentials
     assert abs(U - 0.5 * float(np.sum(Q * Phi))) < 1e-10 * abs(U)
@@ -128,8 +128,9 @@ def test_config2_sampled_parity(torch):
 
 def test_mesh_aligned_translation_invariance(torch):
     x, Q = workloads.make("uniform-1k-n8")
-    _, P1, U1 = _gpu(torch, x, Q, 1.0, 8)
-    _, P2, U2 = _gpu(torch, x + np.array([2, -3, 5]) / 8.0, Q, 1.0, 8)
+    # the multigrid hierarchy is not shift-equivariant: compare tight solves
+    _, P1, U1 = _gpu(torch, x, Q, 1.0, 8, mg_rtol=1e-13)
+    _, P2, U2 = _gpu(torch, x + np.array([2, -3, 5]) / 8.0, Q, 1.0, 8, mg_rtol=1e-13)
     assert np.abs(P1 - P2).max() < 1e-10 * np.abs(P1).max()
 
 
@@ -144,7 +145,7 @@ def test_repeatable_bitwise(torch):
 
 def test_error_paths(torch):
     x, Q = workloads.uniform(64, seed=1)
-    ctx = fp.Context(1.0, 64, 8)
+    ctx = fp.Context(1.0, 64, 8, mg_rtol=1e-12)
     tx = torch.from_numpy(x).cuda()
     with pytest.raises(fp.FEP3MError) as ei:
         ctx.potential(tx, torch.from_numpy(Q + 0.1).cuda())
