@@ -90,26 +90,33 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const double *__restric
 
 // A[E][a] = 4 pi <lambda_E, G_a> - sum_D <g_{E+D}, T_a[D]>.
 // The second term is the transpose of the near-screen field: per element a
-// contraction over (D, m) with only 8 outputs, so the block's output is
-// small and the reduction is split over node lanes:
-//   block  = an 8 x 4 x 4 brick of elements E, 256 threads,
-//   thread = the 8 elements of one x-row of the brick x 8 moments (64
-//            float64 accumulators) for one lane of a 16-node chunk,
-//   deposits g of the source slab (fixed D_z, one node chunk) are staged in
-//            LDS with a padded element stride; the tables are read from a
-//            transposed copy Tt[D][m][a] (8 contiguous moments per node),
-//   the 16 node lanes are reduced with shuffles at the end.
+// contraction over (D, m) with only 8 outputs, so the reduction over nodes m
+// is split across lanes:
+//   block  = an 8 x 4 x 4 brick of target elements, 256 threads,
+//   thread = the 8 elements of one x-row of the brick x 4 of the 8 moments
+//            (32 float64 accumulators) for one lane of an 8-node chunk,
+//   phase  = one (D_z, node chunk): the deposits g of the source slab and the
+//            tables of the 49 offsets of that D_z (transposed copy
+//            Tt[D][m][a], the chunk's nodes) are staged in LDS; per D_y a
+//            thread loads the 2 NSR + 8 sources its row sees into registers
+//            once and slides over D_x,
+//   the 8 node lanes are reduced with shuffles at the end.
 template <int NSR, int PO>
-__global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__restrict__ gE,
+__global__ __launch_bounds__(256) void k_adj_moments(int n, const double *__restrict__ gE,
                                                      const double *__restrict__ Tt, const double *__restrict__ lam,
                                                      const double *__restrict__ gw, double *__restrict__ Aout) {
   constexpr int BX = 8, BY = 4, BZ = 4;
   constexpr int HX = BX + 2 * NSR, HY = BY + 2 * NSR, S = 2 * NSR + 1;
   constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
-  constexpr int MC = 16, MS = MC + 1;            // nodes per chunk, padded stride
+  constexpr int MC = 8, MS = MC + 1;             // nodes per chunk, padded stride
   constexpr int NCH = (NM + MC - 1) / MC;
   constexpr int SLAB = BZ * HY * HX;             // source elements of one D_z
+  constexpr int AH = 4;                          // moments per thread
+  constexpr int TS = S * S * MC * 8;             // staged table values per phase
+  static_assert(MC * BY * BZ * (8 / AH) == 256, "thread map");
+  static_assert(BX * BY * BZ * 8 <= SLAB * MS, "reduction reuses the slab");
   __shared__ double Gs[SLAB * MS];               // [lz][hy][hx][m]
+  __shared__ __align__(16) double Ts[TS];        // [D_y D_x][m][a]
   const int bx_n = (n + BX - 1) / BX, by_n = (n + BY - 1) / BY;
   int b = blockIdx.x;
   const int bx = b % bx_n;
@@ -118,13 +125,13 @@ __global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__r
   const int bz = b / by_n;
   const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
   const int tid = threadIdx.x;
-  const int ml = tid % MC, eg = tid / MC;        // node lane, row (16 rows)
-  const int ly = eg % BY, lz = eg / BY;
-  double acc[BX][8];
+  const int ml = tid % MC, ah = (tid / MC) & 1, row = tid / (2 * MC);
+  const int ly = row % BY, lz = row / BY;
+  double acc[BX][AH];
 #pragma unroll
   for (int e = 0; e < BX; ++e)
 #pragma unroll
-    for (int a = 0; a < 8; ++a) acc[e][a] = 0.0;
+    for (int a = 0; a < AH; ++a) acc[e][a] = 0.0;
 
   for (int Dz = -NSR; Dz <= NSR; ++Dz) {
     for (int ch = 0; ch < NCH; ++ch) {
@@ -137,22 +144,34 @@ __global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__r
         const int ez = (z0 + hz + Dz + 2 * n) % n;
         Gs[h * MS + mm] = m < NM ? gE[(size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NM + m] : 0.0;
       }
+      for (int i = tid; i < TS; i += 256) {   // 64 contiguous values per offset
+        const int a = i % 8, mm = (i / 8) % MC, dyx = i / (8 * MC);
+        const int m = ch * MC + mm;
+        const int iD = dyx + S * S * (Dz + NSR);
+        Ts[i] = m < NM ? Tt[(size_t(iD) * NM + m) * 8 + a] : 0.0;
+      }
       __syncthreads();
-      const int m = ch * MC + ml;
-      const bool mv = m < NM;
-      for (int dyx = 0; dyx < S * S; ++dyx) {
-        const int Dx = dyx % S - NSR, Dy = dyx / S - NSR;
-        const int iD = (Dx + NSR) + S * ((Dy + NSR) + S * (Dz + NSR));
-        double tv[8];
-        const double *tp = Tt + (size_t(iD) * NM + (mv ? m : 0)) * 8;
+#pragma unroll 1
+      for (int Dy = -NSR; Dy <= NSR; ++Dy) {
+        // the x-row of sources this thread's 8 targets see at every D_x:
+        // target e, offset D_x reads window position e + D_x + NSR
+        double win[HX];
+        const double *gr = Gs + ((lz * HY + (ly + Dy + NSR)) * HX) * MS + ml;
 #pragma unroll
-        for (int a = 0; a < 8; ++a) tv[a] = mv ? tp[a] : 0.0;
-        const double *gr = Gs + ((lz * HY + (ly + Dy + NSR)) * HX + (Dx + NSR)) * MS + ml;
+        for (int hx = 0; hx < HX; ++hx) win[hx] = gr[hx * MS];
 #pragma unroll
-        for (int e = 0; e < BX; ++e) {
-          const double gv = gr[e * MS];
+        for (int Dx = -NSR; Dx <= NSR; ++Dx) {
+          const int dyx = (Dx + NSR) + S * (Dy + NSR);
+          const double *tp = Ts + (dyx * MC + ml) * 8 + ah * AH;
+          double tv[AH];
 #pragma unroll
-          for (int a = 0; a < 8; ++a) acc[e][a] += tv[a] * gv;
+          for (int a = 0; a < AH; ++a) tv[a] = tp[a];
+#pragma unroll
+          for (int e = 0; e < BX; ++e) {
+            const double gv = win[e + Dx + NSR];
+#pragma unroll
+            for (int a = 0; a < AH; ++a) acc[e][a] += tv[a] * gv;
+          }
         }
       }
     }
@@ -160,18 +179,18 @@ __global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__r
 #pragma unroll
   for (int e = 0; e < BX; ++e)
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
+    for (int a = 0; a < AH; ++a) {
       double v = acc[e][a];
       for (int off = MC / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
       acc[e][a] = v;
     }
   __syncthreads();
-  double *red = Gs;  // [128 elements][8 moments], element = lx + BX (ly + BY lz)
+  double *red = Gs;  // [BX BY BZ elements][8 moments], element = lx + BX (ly + BY lz)
   if (ml == 0) {
 #pragma unroll
     for (int e = 0; e < BX; ++e)
 #pragma unroll
-      for (int a = 0; a < 8; ++a) red[(e + BX * eg) * 8 + a] = acc[e][a];
+      for (int a = 0; a < AH; ++a) red[(e + BX * row) * 8 + ah * AH + a] = acc[e][a];
   }
   __syncthreads();
   if (tid >= BX * BY * BZ) return;
@@ -289,8 +308,8 @@ int launch_assemble(hipStream_t s, int p, int n, const double *gE, double *G, do
 int launch_adj_moments(hipStream_t s, int p, int n, int nsr, const double *gE, const double *Tt, const double *lam,
                        const double *gw, double *A) {
   if (p != 5) return -1;
-  const int bxn = (n + 7) / 8, byn = (n + 3) / 4;
-  dim3 g(bxn * byn * byn);
+  const int bxn = (n + 7) / 8, byn = (n + 3) / 4, bzn = (n + 3) / 4;
+  dim3 g(bxn * byn * bzn);
   switch (nsr) {
     case 1: hipLaunchKernelGGL((k_adj_moments<1, 5>), g, dim3(256), 0, s, n, gE, Tt, lam, gw, A); return 0;
     case 2: hipLaunchKernelGGL((k_adj_moments<2, 5>), g, dim3(256), 0, s, n, gE, Tt, lam, gw, A); return 0;

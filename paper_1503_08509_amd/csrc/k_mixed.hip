@@ -50,11 +50,72 @@ __global__ __launch_bounds__(256) void k_local_f32(int n, int64_t N, const doubl
 }
 
 // Near-pair sum, one wavefront per target element as in the float64 kernel:
-// each lane walks a strided share of the block's sources for up to kTgtF
-// targets, accumulating sum_j Q_j / r_ij (and, with FORCE, sum_j Q_j d_ij /
+// each lane walks a strided share of the block's sources for a chunk of up
+// to 8 targets, accumulating sum_j Q_j / r_ij (and, with FORCE, sum_j Q_j d_ij /
 // r_ij^3) in float32 with Kahan compensation; the lanes' compensated sums
 // are combined in float64.
-constexpr int kTgtF = 8;
+template <int NSR, bool FORCE, int NT>
+__device__ __forceinline__ void pair_chunk_f32(const PairSegments<NSR> &seg, int total, int lane, int64_t N, int t0,
+                                               int nt, int n, int ex, int ey, int ez, const float4 *__restrict__ su,
+                                               const int *__restrict__ sel, double *__restrict__ phip,
+                                               double *__restrict__ fpair) {
+  float tx[NT], ty[NT], tz[NT];
+  float ps[NT], pc[NT];
+  float fs[3][NT], fc[3][NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const float4 t = su[t0 + (k < nt ? k : 0)];
+    tx[k] = t.x; ty[k] = t.y; tz[k] = t.z;
+    ps[k] = pc[k] = 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fs[d][k] = fc[d][k] = 0.f;
+  }
+  int sp = 0;
+  for (int f = lane; f < total; f += 64) {
+    while (f >= seg.so[sp + 1]) ++sp;
+    const int j = seg.sb[sp] + (f - seg.so[sp]);
+    const int pk = seg.ss[sp];
+    const int pe = sel[j];
+    const float4 s = su[j];
+    // source position relative to the target element centre (element units)
+    const float jx = float((pe & 1023) + seg.shift(pk, 0) * n - ex) + s.x;
+    const float jy = float(((pe >> 10) & 1023) + seg.shift(pk, 1) * n - ey) + s.y;
+    const float jz = float((pe >> 20) + seg.shift(pk, 2) * n - ez) + s.z;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      const float dx = jx - tx[k], dy = jy - ty[k], dz = jz - tz[k];
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      const bool use = (k < nt) && (j != t0 + k);
+      const float ri = use ? rsqrtf(r2) : 0.f;   // the skipped self pair has r = 0
+      const float qr = s.w * ri;
+      kahan_add(ps[k], pc[k], qr);
+      if (FORCE) {
+        const float qr3 = qr * ri * ri;
+        kahan_add(fs[0][k], fc[0][k], qr3 * dx);
+        kahan_add(fs[1][k], fc[1][k], qr3 * dy);
+        kahan_add(fs[2][k], fc[2][k], qr3 * dz);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const double p = wave_sum(double(ps[k]) - double(pc[k]));
+    double g[3] = {0.0, 0.0, 0.0};
+    if (FORCE) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) g[d] = wave_sum(double(fs[d][k]) - double(fc[d][k]));
+    }
+    if (lane == 0 && k < nt) {
+      phip[t0 + k] = p;
+      if (FORCE) {
+        fpair[t0 + k] = g[0];
+        fpair[N + t0 + k] = g[1];
+        fpair[2 * N + t0 + k] = g[2];
+      }
+    }
+  }
+}
+
 template <int NSR, bool FORCE>
 __global__ __launch_bounds__(64) void k_pair_f32(int n, int64_t N, const int *__restrict__ start,
                                                  const float4 *__restrict__ su, const int *__restrict__ sel,
@@ -66,62 +127,17 @@ __global__ __launch_bounds__(64) void k_pair_f32(int n, int64_t N, const int *__
   if (tb == te) return;  // uniform over the (single-wave) block
   const int total = build_segments<NSR>(seg, E, n, start, lane, 64);
   const int ex = E % n, ey = (E / n) % n, ez = E / (n * n);
-  for (int t0 = tb; t0 < te; t0 += kTgtF) {
-    const int nt = min(kTgtF, te - t0);
-    float tx[kTgtF], ty[kTgtF], tz[kTgtF];
-    float ps[kTgtF], pc[kTgtF];
-    float fs[3][kTgtF], fc[3][kTgtF];
-#pragma unroll
-    for (int k = 0; k < kTgtF; ++k) {
-      const float4 t = su[t0 + (k < nt ? k : 0)];
-      tx[k] = t.x; ty[k] = t.y; tz[k] = t.z;
-      ps[k] = pc[k] = 0.f;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) fs[d][k] = fc[d][k] = 0.f;
-    }
-    int sp = 0;
-    for (int f = lane; f < total; f += 64) {
-      while (f >= seg.so[sp + 1]) ++sp;
-      const int j = seg.sb[sp] + (f - seg.so[sp]);
-      const int pk = seg.ss[sp];
-      const int pe = sel[j];
-      const float4 s = su[j];
-      // source position relative to the target element centre (element units)
-      const float jx = float((pe & 1023) + seg.shift(pk, 0) * n - ex) + s.x;
-      const float jy = float(((pe >> 10) & 1023) + seg.shift(pk, 1) * n - ey) + s.y;
-      const float jz = float((pe >> 20) + seg.shift(pk, 2) * n - ez) + s.z;
-#pragma unroll
-      for (int k = 0; k < kTgtF; ++k) {
-        const float dx = jx - tx[k], dy = jy - ty[k], dz = jz - tz[k];
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const bool use = (k < nt) && (j != t0 + k);
-        const float ri = use ? rsqrtf(r2) : 0.f;   // the skipped self pair has r = 0
-        const float qr = s.w * ri;
-        kahan_add(ps[k], pc[k], qr);
-        if (FORCE) {
-          const float qr3 = qr * ri * ri;
-          kahan_add(fs[0][k], fc[0][k], qr3 * dx);
-          kahan_add(fs[1][k], fc[1][k], qr3 * dy);
-          kahan_add(fs[2][k], fc[2][k], qr3 * dz);
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kTgtF; ++k) {
-      const double p = wave_sum(double(ps[k]) - double(pc[k]));
-      double g[3] = {0.0, 0.0, 0.0};
-      if (FORCE) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) g[d] = wave_sum(double(fs[d][k]) - double(fc[d][k]));
-      }
-      if (lane == 0 && k < nt) {
-        phip[t0 + k] = p;
-        if (FORCE) {
-          fpair[t0 + k] = g[0];
-          fpair[N + t0 + k] = g[1];
-          fpair[2 * N + t0 + k] = g[2];
-        }
-      }
+  for (int t0 = tb; t0 < te;) {   // chunk widths 8, 4, 2 as in the float64 kernel
+    const int rem = te - t0;
+    if (rem > 4) {
+      pair_chunk_f32<NSR, FORCE, 8>(seg, total, lane, N, t0, min(rem, 8), n, ex, ey, ez, su, sel, phip, fpair);
+      t0 += 8;
+    } else if (rem > 2) {
+      pair_chunk_f32<NSR, FORCE, 4>(seg, total, lane, N, t0, rem, n, ex, ey, ez, su, sel, phip, fpair);
+      t0 += 4;
+    } else {
+      pair_chunk_f32<NSR, FORCE, 2>(seg, total, lane, N, t0, rem, n, ex, ey, ez, su, sel, phip, fpair);
+      t0 += 2;
     }
   }
 }

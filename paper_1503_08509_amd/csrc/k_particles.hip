@@ -160,12 +160,79 @@ __global__ __launch_bounds__(256) void k_moments(int n, int64_t N, const int *__
 // (2 NSR + 1)^3 element block, walked as up to 2 (2 NSR + 1)^2 contiguous
 // sorted segments (rows along x, split where the row wraps the periodic
 // boundary); every lane takes a strided share of the flattened source list
-// and accumulates for a chunk of up to kTgt targets, then the wave reduces.
+// and accumulates for a chunk of up to 8 targets, then the wave reduces.
 // Displacements are formed in the target's unwrapped frame in element
 // units, so no minimum-image test is needed (n >= 2 NSR + 1).
 // With FORCE the same pass also accumulates sum_j Q_j (g_j - g_i) / r^3
 // (fpair, 3 x N sorted), the pair part of dU/dg_i divided by Q_i.
-constexpr int kTgt = 8;
+// One chunk of nt <= NT targets starting at sorted slot t0: every lane
+// walks its strided share of the block's sources and accumulates for all NT
+// targets in registers; the wave then reduces.
+template <int NSR, bool FORCE, int NT>
+__device__ __forceinline__ void pair_chunk(const PairSegments<NSR> &seg, int total, int lane, int64_t N, int t0,
+                                           int nt, double nd, const double *__restrict__ sg,
+                                           const double *__restrict__ sQ, double *__restrict__ phip,
+                                           double *__restrict__ fpair) {
+  double tx[NT], ty[NT], tz[NT], acc[NT], fx[NT], fy[NT], fz[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const int ti = t0 + (k < nt ? k : 0);
+    tx[k] = sg[ti]; ty[k] = sg[N + ti]; tz[k] = sg[2 * N + ti];
+    acc[k] = 0.0;
+    fx[k] = fy[k] = fz[k] = 0.0;
+  }
+  int sp = 0;
+  for (int f = lane; f < total; f += 64) {
+    while (f >= seg.so[sp + 1]) ++sp;
+    const int j = seg.sb[sp] + (f - seg.so[sp]);
+    const int pk = seg.ss[sp];
+    const double shx = double(seg.shift(pk, 0)) * nd, shy = double(seg.shift(pk, 1)) * nd,
+                 shz = double(seg.shift(pk, 2)) * nd;
+    const double jx = sg[j] + shx, jy = sg[N + j] + shy, jz = sg[2 * N + j] + shz;
+    const double qj = sQ[j];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      const double dx = jx - tx[k], dy = jy - ty[k], dz = jz - tz[k];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const bool use = (k < nt) && (j != t0 + k);
+      const double ri = rsqrt(r2);
+      const double qr = use ? qj * ri : 0.0;
+      acc[k] += qr;
+      if (FORCE) {
+        const double qr3 = qr * (use ? ri * ri : 0.0);  // the skipped self pair has ri = inf
+        fx[k] += qr3 * dx;
+        fy[k] += qr3 * dy;
+        fz[k] += qr3 * dz;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    double v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    acc[k] = v;
+    if (FORCE) {
+      double a = fx[k], b = fy[k], c = fz[k];
+      for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+        c += __shfl_xor(c, off, 64);
+      }
+      fx[k] = a; fy[k] = b; fz[k] = c;
+    }
+  }
+  if (lane == 0) {
+    for (int k = 0; k < nt; ++k) {
+      phip[t0 + k] = acc[k];
+      if (FORCE) {
+        fpair[t0 + k] = fx[k];
+        fpair[N + t0 + k] = fy[k];
+        fpair[2 * N + t0 + k] = fz[k];
+      }
+    }
+  }
+}
+
 template <int NSR, bool FORCE>
 __global__ __launch_bounds__(64) void k_pair(int n, int64_t N, const int *__restrict__ start,
                                              const double *__restrict__ sg, const double *__restrict__ sQ,
@@ -177,70 +244,22 @@ __global__ __launch_bounds__(64) void k_pair(int n, int64_t N, const int *__rest
   if (tb == te) return;  // uniform over the (single-wave) block
   const int total = build_segments<NSR>(seg, E, n, start, lane, 64);
   const double nd = double(n);
-  for (int t0 = tb; t0 < te; t0 += kTgt) {
-    const int nt = min(kTgt, te - t0);
-    double tx[kTgt], ty[kTgt], tz[kTgt], acc[kTgt], fx[kTgt], fy[kTgt], fz[kTgt];
-#pragma unroll
-    for (int k = 0; k < kTgt; ++k) {
-      const int ti = t0 + (k < nt ? k : 0);
-      tx[k] = sg[ti]; ty[k] = sg[N + ti]; tz[k] = sg[2 * N + ti];
-      acc[k] = 0.0;
-      fx[k] = fy[k] = fz[k] = 0.0;
-    }
-    int sp = 0;
-    for (int f = lane; f < total; f += 64) {
-      while (f >= seg.so[sp + 1]) ++sp;
-      const int j = seg.sb[sp] + (f - seg.so[sp]);
-      const int pk = seg.ss[sp];
-      const double shx = double(seg.shift(pk, 0)) * nd, shy = double(seg.shift(pk, 1)) * nd,
-                   shz = double(seg.shift(pk, 2)) * nd;
-      const double jx = sg[j] + shx, jy = sg[N + j] + shy, jz = sg[2 * N + j] + shz;
-      const double qj = sQ[j];
-#pragma unroll
-      for (int k = 0; k < kTgt; ++k) {
-        const double dx = jx - tx[k], dy = jy - ty[k], dz = jz - tz[k];
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        const bool use = (k < nt) && (j != t0 + k);
-        const double ri = rsqrt(r2);
-        const double qr = use ? qj * ri : 0.0;
-        acc[k] += qr;
-        if (FORCE) {
-          const double qr3 = qr * (use ? ri * ri : 0.0);  // the skipped self pair has ri = inf
-          fx[k] += qr3 * dx;
-          fy[k] += qr3 * dy;
-          fz[k] += qr3 * dz;
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kTgt; ++k) {
-      double v = acc[k];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      acc[k] = v;
-      if (FORCE) {
-        double a = fx[k], b = fy[k], c = fz[k];
-        for (int off = 32; off > 0; off >>= 1) {
-          a += __shfl_xor(a, off, 64);
-          b += __shfl_xor(b, off, 64);
-          c += __shfl_xor(c, off, 64);
-        }
-        fx[k] = a; fy[k] = b; fz[k] = c;
-      }
-    }
-    if (lane == 0) {
-      for (int k = 0; k < nt; ++k) {
-        phip[t0 + k] = acc[k];
-        if (FORCE) {
-          fpair[t0 + k] = fx[k];
-          fpair[N + t0 + k] = fy[k];
-          fpair[2 * N + t0 + k] = fz[k];
-        }
-      }
+  // chunk width per pass: 8 while more than 4 targets remain, then 4 or 2,
+  // so that sparsely occupied elements do not compute empty target slots
+  for (int t0 = tb; t0 < te;) {
+    const int rem = te - t0;
+    if (rem > 4) {
+      pair_chunk<NSR, FORCE, 8>(seg, total, lane, N, t0, min(rem, 8), nd, sg, sQ, phip, fpair);
+      t0 += 8;
+    } else if (rem > 2) {
+      pair_chunk<NSR, FORCE, 4>(seg, total, lane, N, t0, rem, nd, sg, sQ, phip, fpair);
+      t0 += 4;
+    } else {
+      pair_chunk<NSR, FORCE, 2>(seg, total, lane, N, t0, rem, nd, sg, sQ, phip, fpair);
+      t0 += 2;
     }
   }
 }
-
-// ----------------------------------------------------------------- interpolation
 
 // Phi_m at each sorted charge: sum_m W_E[m] u_m(u_i) (W = phi - Psi of its
 // element, element units) by sum factorisation; then the combined
