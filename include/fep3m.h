@@ -143,6 +143,20 @@ int fep3m_create(double L, int64_t N, const int32_t dims[3], int32_t q, fep3m_ct
 int fep3m_create_ex(double L, int64_t N, const int32_t dims[3], int32_t q,
                     const fep3m_options *opt, fep3m_ctx **out);
 
+/* A batch of nconf independent configurations that share L, the mesh and
+ * the options (spec extension: many small systems in one pass).
+ * Configuration b holds N_per_conf[b] >= 2 charges; every array argument of
+ * the evaluation calls concatenates the configurations in order (x is
+ * (sum N) x 3, Phi, Q and dUdQ have sum N entries, F (sum N) x 3), and U
+ * receives nconf energies, U[b] for configuration b.  Each configuration
+ * must be neutral on its own.  Every kernel launch covers all
+ * configurations; the mesh solves of all configurations iterate together
+ * and each stops changing once its own residual reaches mg_rtol.
+ * 1 <= nconf <= 1024, nconf * dims^3 <= 2^28.  fep3m_create_ex is the
+ * nconf = 1 case.  Errors as fep3m_create_ex. */
+int fep3m_create_batch(double L, int32_t nconf, const int64_t *N_per_conf, const int32_t dims[3], int32_t q,
+                       const fep3m_options *opt, fep3m_ctx **out);
+
 /* Order subsequent calls on the given hipStream_t (NULL: null stream). */
 int fep3m_set_stream(fep3m_ctx *ctx, void *hip_stream);
 
@@ -150,7 +164,8 @@ int fep3m_set_stream(fep3m_ctx *ctx, void *hip_stream);
 int fep3m_potential(fep3m_ctx *ctx, const double *x, const double *Q, double *Phi);
 
 /* Phi as above and U = 1/2 sum Q_i Phi_i written to U[0] (device pointer,
- * one double); the sum is a fixed-order float64 tree. */
+ * one double per configuration of a batch); the sum is a fixed-order
+ * float64 tree. */
 int fep3m_energy(fep3m_ctx *ctx, const double *x, const double *Q, double *Phi, double *U);
 
 /* Energy and forces (spec extension; the paper evaluates potentials

@@ -72,6 +72,8 @@ def lib():
         L.fep3m_default_options.argtypes = [ctypes.POINTER(Options)]
         L.fep3m_create.argtypes = [dp, i64, ctypes.POINTER(i32), i32, ctypes.POINTER(vp)]
         L.fep3m_create_ex.argtypes = [dp, i64, ctypes.POINTER(i32), i32, ctypes.POINTER(Options), ctypes.POINTER(vp)]
+        L.fep3m_create_batch.argtypes = [dp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32), i32,
+                                         ctypes.POINTER(Options), ctypes.POINTER(vp)]
         L.fep3m_set_stream.argtypes = [vp, vp]
         L.fep3m_potential.argtypes = [vp, vp, vp, vp]
         L.fep3m_energy.argtypes = [vp, vp, vp, vp, vp]
@@ -114,7 +116,12 @@ def host_tables(q=3, n_sr=3, box=None):
 
 
 class Context:
-    """One FE-P3M configuration (L, N, n^3 elements, screen degree q)."""
+    """FE-P3M on n^3 elements of the periodic cube of side L, screen degree q.
+
+    N is the number of charges, or a sequence of counts for a batch of
+    independent configurations evaluated together (arrays then concatenate
+    the configurations in order, and energies come back one per
+    configuration)."""
 
     def __init__(self, L, N, n, q=3, **opts):
         import torch  # device memory and streams only
@@ -127,11 +134,20 @@ class Context:
             setattr(o, k, v)
         dims = (ctypes.c_int32 * 3)(n, n, n)
         h = ctypes.c_void_p()
-        st = lib().fep3m_create_ex(float(L), int(N), dims, int(q), ctypes.byref(o), ctypes.byref(h))
+        self.batch = not np.isscalar(N)
+        counts = [int(v) for v in N] if self.batch else [int(N)]
+        if self.batch:
+            arr = (ctypes.c_int64 * len(counts))(*counts)
+            st = lib().fep3m_create_batch(float(L), len(counts), arr, dims, int(q), ctypes.byref(o), ctypes.byref(h))
+        else:
+            st = lib().fep3m_create_ex(float(L), counts[0], dims, int(q), ctypes.byref(o), ctypes.byref(h))
         if st != OK:
             raise FEP3MError(st, lib().fep3m_last_error(None).decode() or lib().fep3m_status_string(st).decode())
         self._h = h
-        self.L, self.N, self.n, self.q = float(L), int(N), int(n), int(q)
+        self.counts = counts
+        self.offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        self.nconf = len(counts)
+        self.L, self.N, self.n, self.q = float(L), int(sum(counts)), int(n), int(q)
         self.options = o
 
     def _check(self, st):
@@ -161,25 +177,27 @@ class Context:
         return Phi
 
     def energy(self, x, Q):
+        """Phi [N] and U (0-d; [nconf] for a batch)."""
         x, Q = self._prep(x, Q)
         t = self._torch
         Phi = t.empty(self.N, dtype=t.float64, device=x.device)
-        U = t.empty(1, dtype=t.float64, device=x.device)
+        U = t.empty(self.nconf, dtype=t.float64, device=x.device)
         self._check(lib().fep3m_energy(self._h, x.data_ptr(), Q.data_ptr(), Phi.data_ptr(), U.data_ptr()))
-        return Phi, U[0]
+        return Phi, (U if self.batch else U[0])
 
     def energy_forces(self, x, Q, dUdQ=False, Phi=False):
-        """U (0-d), F [N,3] = -dU/dx and optionally dU/dQ [N] and Phi [N]."""
+        """U (0-d; [nconf] for a batch), F [N,3] = -dU/dx and optionally
+        dU/dQ [N] and Phi [N]."""
         x, Q = self._prep(x, Q)
         t = self._torch
-        U = t.empty(1, dtype=t.float64, device=x.device)
+        U = t.empty(self.nconf, dtype=t.float64, device=x.device)
         F = t.empty((self.N, 3), dtype=t.float64, device=x.device)
         g = t.empty(self.N, dtype=t.float64, device=x.device) if dUdQ else None
         P = t.empty(self.N, dtype=t.float64, device=x.device) if Phi else None
         self._check(lib().fep3m_energy_forces_ex(self._h, x.data_ptr(), Q.data_ptr(),
                                                  P.data_ptr() if P is not None else None, U.data_ptr(),
                                                  F.data_ptr(), g.data_ptr() if g is not None else None))
-        out = {"U": U[0], "F": F}
+        out = {"U": U if self.batch else U[0], "F": F}
         if dUdQ:
             out["dUdQ"] = g
         if Phi:
@@ -243,7 +261,8 @@ def _energy_function():
 
     class FEP3MEnergy(torch.autograd.Function):
         """U = FEP3MEnergy.apply(x, Q, ctx): the method's energy as a 0-d
-        float64 tensor, differentiable in x [N, 3] and Q [N].  The backward
+        float64 tensor (one entry per configuration of a batch context),
+        differentiable in x [N, 3] and Q [N].  The backward
         pass is the library's hand-written adjoint (fep3m_backward): it
         reuses the forward call's bins and mesh potential, recomputes the
         near-pair terms, and returns grad_x = -F * dL/dU, grad_Q = dU/dQ *
@@ -263,8 +282,11 @@ def _energy_function():
             need_x, need_Q = fctx.needs_input_grad[0], fctx.needs_input_grad[1]
             if not (need_x or need_Q):
                 return None, None, None
-            F, g = fctx.ctx.backward(fctx.generation, F=need_x, dUdQ=need_Q, device=fctx.device)
-            gx = -F * gU if need_x else None
+            ctx = fctx.ctx
+            F, g = ctx.backward(fctx.generation, F=need_x, dUdQ=need_Q, device=fctx.device)
+            if ctx.batch:   # dL/dU_b applies to the charges of configuration b
+                gU = gU.repeat_interleave(torch.tensor(ctx.counts, device=gU.device))
+            gx = -F * (gU[:, None] if ctx.batch else gU) if need_x else None
             gQ = g * gU if need_Q else None
             return gx, gQ, None
 

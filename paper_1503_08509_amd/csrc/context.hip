@@ -84,10 +84,28 @@ template <> const LevelOpF &MGLevel::oper<float>() const { return opf; }
 
 }  // namespace
 
+// Per-configuration scalar slots (nb values each).
+enum CfgScalar : int {
+  kCsQ = 0,        // sum Q
+  kCsQabs = 1,     // sum |Q|
+  kCsLoad = 2,     // sum b (compatibility projection of the load)
+  kCsInt = 3,      // integral of the last mesh solution (gauge)
+  kCsEnergy = 4,   // sum Q Phi
+  kCsAdjLoad = 5,  // sum G (compatibility projection of the deposit)
+  kCsPcg = 6,      // 10 PCG scalars from here
+  kCsSlots = 16
+};
+
 struct fep3m_ctx {
   // configuration
   double L = 1.0, h = 1.0;
-  int64_t N = 0;
+  int64_t N = 0;                // charges in the whole batch
+  int nb = 1;                   // independent configurations (same mesh and parameters)
+  std::vector<int> off_h;       // first charge of each configuration (nb + 1 entries)
+  int *off_d = nullptr;
+  double *cs = nullptr, *host_cs = nullptr;   // per-configuration scalars (device, pinned mirror)
+  PcgScalars pcs{};
+  double *cfgs(int slot) const { return cs + size_t(slot) * nb; }
   int n = 0, q = 3, p = 5, d = 1, nsr = 3, B = 15;
   fep3m_options opt{};
   hipStream_t stream = nullptr;
@@ -142,6 +160,7 @@ struct fep3m_ctx {
     for (hipEvent_t e : prof.kev) (void)hipEventDestroy(e);
     for (void *p : allocs) (void)hipFree(p);
     if (host_scal) (void)hipHostFree(host_scal);
+    if (host_cs) (void)hipHostFree(host_cs);
   }
   void check_launch(const char *what) { hip_check(hipGetLastError(), what); }
   void sync(const char *what) { hip_check(hipStreamSynchronize(stream), what); }
@@ -154,7 +173,7 @@ struct fep3m_ctx {
     return host_scal[0];
   }
 
-  void build(double L_, int64_t N_, int n_, int q_, const fep3m_options &o);
+  void build(double L_, const std::vector<int64_t> &Ns, int n_, int q_, const fep3m_options &o);
   void stage_mark(int slot, bool begin) {
     if (!prof.on) return;
     hip_check(hipEventRecord(prof.stage_ev[2 * slot + (begin ? 0 : 1)], stream), "event");
@@ -165,16 +184,16 @@ struct fep3m_ctx {
   int apply0(const T *x, const T *f, T *out, const T *d, T *xo, T c1, T c2, int mode, double *part) {
     const bool rec = prof.on && prof.kused < int(prof.kev.size()) / 2;
     if (rec) hip_check(hipEventRecord(prof.kev[2 * prof.kused], stream), "event");
-    const int nb = launch_apply<T>(stream, lv[0].oper<T>(), x, f, out, d, xo, c1, c2, mode, part);
+    const int K = launch_apply<T>(stream, nb, lv[0].oper<T>(), x, f, out, d, xo, c1, c2, mode, part);
     if (rec) {
       hip_check(hipEventRecord(prof.kev[2 * prof.kused + 1], stream), "event");
       // vectors read + written: x, f, x_prev (when read) and x_new; x, f, r; x, Kx
       const double vec = mode == kCheb ? ((c1 != T(0) && d) ? 4.0 : 3.0) : mode == kResidual ? 3.0 : 2.0;
-      prof.kwork[prof.kused] = vec * double(sizeof(T)) * double(lv[0].ndof);
+      prof.kwork[prof.kused] = vec * double(sizeof(T)) * double(lv[0].ndof) * nb;
       prof.kslot[prof.kused] = sizeof(T) == 8 ? FEP3M_PROF_FINE_APPLY : FEP3M_PROF_FINE_APPLY_F32;
       ++prof.kused;
     }
-    return nb;
+    return K;
   }
   void profile_collect();
   void forward(const double *x, const double *Q, double *Phi, double *U, bool pair_forces);
@@ -194,10 +213,13 @@ struct fep3m_ctx {
 
 // ----------------------------------------------------------------- create
 
-void fep3m_ctx::build(double L_, int64_t N_, int n_, int q_, const fep3m_options &o) {
+void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_, const fep3m_options &o) {
   auto t0 = std::chrono::steady_clock::now();
   L = L_;
-  N = N_;
+  nb = int(Ns.size());
+  off_h.assign(1, 0);
+  for (int64_t v : Ns) off_h.push_back(off_h.back() + int(v));
+  N = off_h.back();
   n = n_;
   q = q_;
   p = q + 2;
@@ -233,6 +255,15 @@ void fep3m_ctx::build(double L_, int64_t N_, int n_, int q_, const fep3m_options
   }
 
   const int M = n * n * n;
+  off_d = alloc<int>(off_h.size(), "configuration offsets");
+  hip_check(hipMemcpy(off_d, off_h.data(), off_h.size() * sizeof(int), hipMemcpyHostToDevice), "upload offsets");
+  cs = alloc<double>(size_t(kCsSlots) * nb, "configuration scalars");
+  hip_check(hipHostMalloc(reinterpret_cast<void **>(&host_cs), size_t(kCsSlots) * nb * sizeof(double),
+                          hipHostMallocDefault), "pinned configuration scalars");
+  {
+    double **slots[] = {&pcs.bn2, &pcs.rz, &pcs.rzn, &pcs.pq, &pcs.rr, &pcs.zq, &pcs.alpha, &pcs.beta, &pcs.act, &pcs.rel};
+    for (int k = 0; k < 10; ++k) *slots[k] = cfgs(kCsPcg + k);
+  }
   T = alloc<double>(T_host.size(), "tables");
   gw = alloc<double>(gwh.size(), "load weights");
   w1 = alloc<double>(w1h.size(), "mass ones");
@@ -256,19 +287,19 @@ void fep3m_ctx::build(double L_, int64_t N_, int n_, int q_, const fep3m_options
   slot = alloc<int>(size_t(N), "slots");
   tmp = alloc<int>(size_t(N), "sort scratch");
   perm = alloc<int>(size_t(N), "permutation");
-  count = alloc<int>(size_t(M), "counts");
-  start = alloc<int>(size_t(M) + 1, "element starts");
+  count = alloc<int>(size_t(nb) * M, "counts");
+  start = alloc<int>(size_t(nb) * M + 1, "element starts");
   flags = alloc<int>(4, "flags");
   maxcount = alloc<int>(4, "max count");
   paircount = alloc<unsigned long long>(2, "pair count");
-  C = alloc<double>(size_t(M) * 8, "moments");
+  C = alloc<double>(size_t(nb) * M * 8, "moments");
   if (!mixed) {
-    Wel = alloc<double>(size_t(M) * (p + 1) * (p + 1) * (p + 1), "element field");
+    Wel = alloc<double>(size_t(nb) * M * (p + 1) * (p + 1) * (p + 1), "element field");
   } else {
     std::vector<float> tf(T_host.begin(), T_host.end());
     Tf = alloc<float>(tf.size(), "tables (f32)");
     hip_check(hipMemcpy(Tf, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice), "upload tables");
-    Welf = alloc<float>(size_t(M) * (p + 1) * (p + 1) * (p + 1), "element field (f32)");
+    Welf = alloc<float>(size_t(nb) * M * (p + 1) * (p + 1) * (p + 1), "element field (f32)");
     su = alloc<float4>(size_t(N), "local coordinates (f32)");
     sel = alloc<int>(size_t(N), "packed elements");
   }
@@ -283,7 +314,7 @@ void fep3m_ctx::build(double L_, int64_t N_, int n_, int q_, const fep3m_options
   build_mg();
   // partials serve every two-stage reduction: the fixed reduction grids and
   // the per-tile partials of the fine-level operator
-  partial_len = std::max(partial_len, size_t(apply_blocks(lv[0].op)) + 64);
+  partial_len = std::max(partial_len, size_t(nb) * apply_blocks(lv[0].op) + 64);
   partial = alloc<double>(partial_len, "partials");
   estimate_spectra();
   auto t1 = std::chrono::steady_clock::now();
@@ -359,22 +390,23 @@ void fep3m_ctx::build_mg() {
     tr.push_back(make_transfer(hier[i].first, hier[i].second, hier[i + 1].first, hier[i + 1].second));
   for (size_t i = 0; i < lv.size(); ++i) {
     MGLevel &L_ = lv[i];
-    L_.vd.x = alloc<double>(L_.ndof, "mg x");
+    const size_t nv = L_.ndof * nb;   // one block of the level per configuration
+    L_.vd.x = alloc<double>(nv, "mg x");
     if (i + 1 < lv.size()) L_.d = alloc<double>(L_.ndof, "mg d");
     if (!mixed) {
-      L_.vd.f = (i == 0) ? nullptr : alloc<double>(L_.ndof, "mg f");
+      L_.vd.f = (i == 0) ? nullptr : alloc<double>(nv, "mg f");
       if (i + 1 < lv.size()) {
-        L_.vd.x2 = alloc<double>(L_.ndof, "mg x2");
-        L_.vd.r = alloc<double>(L_.ndof, "mg r");
+        L_.vd.x2 = alloc<double>(nv, "mg x2");
+        L_.vd.r = alloc<double>(nv, "mg r");
       }
     } else {
       // float32 hierarchy; the fine level also holds the float32 copy of the residual
       L_.opf = L_.op.cast<float>();
-      L_.vf.x = alloc<float>(L_.ndof, "mg x (f32)");
-      L_.vf.f = alloc<float>(L_.ndof, "mg f (f32)");
+      L_.vf.x = alloc<float>(nv, "mg x (f32)");
+      L_.vf.f = alloc<float>(nv, "mg f (f32)");
       if (i + 1 < lv.size()) {
-        L_.vf.x2 = alloc<float>(L_.ndof, "mg x2 (f32)");
-        L_.vf.r = alloc<float>(L_.ndof, "mg r (f32)");
+        L_.vf.x2 = alloc<float>(nv, "mg x2 (f32)");
+        L_.vf.r = alloc<float>(nv, "mg r (f32)");
       }
     }
   }
@@ -382,11 +414,11 @@ void fep3m_ctx::build_mg() {
     for (const Transfer &t : tr) trf.push_back(t.cast<float>());
     dot_scr = alloc<double>(2 * kRedBlocks, "two-dot partials");
   }
-  const size_t nd0 = lv[0].ndof;
-  gE = alloc<double>(size_t(n) * n * n * (p + 1) * (p + 1) * (p + 1), "deposit");
+  const size_t nd0 = lv[0].ndof * nb;
+  gE = alloc<double>(size_t(nb) * n * n * n * (p + 1) * (p + 1) * (p + 1), "deposit");
   Gv = alloc<double>(nd0, "adjoint load");
   lam = alloc<double>(nd0, "adjoint potential");
-  Aadj = alloc<double>(size_t(n) * n * n * 8, "moment adjoint");
+  Aadj = alloc<double>(size_t(nb) * n * n * n * 8, "moment adjoint");
   fpair = alloc<double>(3 * size_t(N), "pair forces");
   Phi_int = alloc<double>(size_t(N), "potential (caller order)");
   b = alloc<double>(nd0, "load");
@@ -421,12 +453,11 @@ void fep3m_ctx::estimate_spectra() {
     double *xw = L_.vd.x;
     launch_hash_fill(stream, L_.ndof, 12345u + uint32_t(i), xw);
     double lam = 0.0;
-    launch_dot(stream, L_.ndof, xw, xw, partial);
-    double nx = std::sqrt(reduce_host(red_grid(L_.ndof), partial, 0));
+    // every configuration has the same operator: iterate on configuration 0
+    double nx = std::sqrt(reduce_host(launch_dot(stream, 1, L_.ndof, xw, xw, partial), partial, 0));
     for (int it = 0; it < 24; ++it) {
-      launch_apply<double>(stream, L_.op, xw, nullptr, L_.d, nullptr, nullptr, 0.0, 0.0, kDinvApply, nullptr);
-      launch_dot(stream, L_.ndof, L_.d, L_.d, partial);
-      double nd = std::sqrt(reduce_host(red_grid(L_.ndof), partial, 0));
+      launch_apply<double>(stream, 1, L_.op, xw, nullptr, L_.d, nullptr, nullptr, 0.0, 0.0, kDinvApply, nullptr);
+      double nd = std::sqrt(reduce_host(launch_dot(stream, 1, L_.ndof, L_.d, L_.d, partial), partial, 0));
       lam = nd / nx;
       launch_scale(stream, L_.ndof, 1.0 / nd, L_.d, xw);
       nx = 1.0;
@@ -461,13 +492,13 @@ void fep3m_ctx::cheb_smooth(int l, const T *f, bool zero_start) {
       rho = rn;
     }
     if (s == 0 && zero_start) {
-      launch_cheb_first<T>(stream, op, f, V.x, T(c2));   // x = c2 D^-1 f; x_prev = 0 (not stored)
+      launch_cheb_first<T>(stream, nb, op, f, V.x, T(c2));   // x = c2 D^-1 f; x_prev = 0 (not stored)
     } else {
       // x2 holds x_prev on entry (null: zero, after the first step from a zero
       // start) and receives x_new; then the two swap
       const T *xprev = (s == 1 && zero_start) ? nullptr : V.x2;
       if (l == 0) apply0<T>(V.x, f, nullptr, xprev, V.x2, T(c1), T(c2), kCheb, nullptr);
-      else launch_apply<T>(stream, op, V.x, f, nullptr, xprev, V.x2, T(c1), T(c2), kCheb, nullptr);
+      else launch_apply<T>(stream, nb, op, V.x, f, nullptr, xprev, V.x2, T(c1), T(c2), kCheb, nullptr);
       std::swap(V.x, V.x2);
     }
   }
@@ -479,141 +510,144 @@ void fep3m_ctx::vcycle(int l, const T *f) {
   MGLevel &L_ = lv[l];
   LevelVecs<T> &V = L_.vec<T>();
   if (l + 1 == int(lv.size())) {
-    launch_coarse_solve<T>(stream, coarseP, coarseV, coarseLam, f, V.x);
+    launch_coarse_solve<T>(stream, nb, coarseP, coarseV, coarseLam, f, V.x);
     return;
   }
   const LevelOpT<T> &op = L_.oper<T>();
   LevelVecs<T> &Vc = lv[l + 1].vec<T>();
   cheb_smooth<T>(l, f, true);
   if (l == 0) apply0<T>(V.x, f, V.r, nullptr, nullptr, T(0), T(0), kResidual, nullptr);
-  else launch_apply<T>(stream, op, V.x, f, V.r, nullptr, nullptr, T(0), T(0), kResidual, nullptr);
-  launch_transfer<T>(stream, transfer<T>(l), V.r, Vc.f, true);
+  else launch_apply<T>(stream, nb, op, V.x, f, V.r, nullptr, nullptr, T(0), T(0), kResidual, nullptr);
+  launch_transfer<T>(stream, nb, transfer<T>(l), V.r, Vc.f, true);
   vcycle<T>(l + 1, Vc.f);
-  launch_transfer<T>(stream, transfer<T>(l), Vc.x, V.x, false);
+  launch_transfer<T>(stream, nb, transfer<T>(l), Vc.x, V.x, false);
   cheb_smooth<T>(l, f, false);
 }
 
-// PCG on K out = rhs (rhs compatible), preconditioned by one V-cycle.  In
-// mixed precision the V-cycle runs in float32 on a float32 copy of the
-// residual, and the iteration uses the flexible (Polak-Ribiere) update
-// beta = -alpha (z_new . q) / (z_old . r_old), which stays a descent method
-// when the preconditioner carries float32 rounding; everything else (K p, the
+// PCG on K out = rhs (rhs compatible), preconditioned by one V-cycle, for
+// every configuration of the batch at once: the scalars of each
+// configuration live on the device (one thread per configuration updates
+// them) and a configuration that has converged keeps alpha = beta = 0, so
+// its iterate no longer changes while the others finish.  The host reads
+// the nb relative residuals once per iteration.  In mixed precision the
+// V-cycle runs in float32 on a float32 copy of the residual, and the
+// iteration uses the flexible (Polak-Ribiere) update beta = -alpha
+// (z_new . q) / (z_old . r_old), which stays a descent method when the
+// preconditioner carries float32 rounding; everything else (K p, the
 // updates, every norm and inner product) is float64.
 void fep3m_ctx::solve(const double *rhs, double *sol) {
   MGLevel &L0 = lv[0];
-  const size_t nd = L0.ndof;
+  const size_t per = L0.ndof, nd = per * nb;
   hip_check(hipMemsetAsync(sol, 0, nd * sizeof(double), stream), "zero solution");
   hip_check(hipMemcpyAsync(rr, rhs, nd * sizeof(double), hipMemcpyDeviceToDevice, stream), "copy r");
-  launch_dot(stream, nd, rhs, rhs, partial);
-  const double bnorm = std::sqrt(reduce_host(red_grid(nd), partial, 0));
-  stats.mg_iterations = 0;
-  stats.mg_rel_residual = 0.0;
-  if (bnorm == 0.0) return;
-  // z = M^-1 r; returns z . r (and z . q in *zq when q is given)
-  auto precondition = [&](const double *q, double *zq) -> double {
+  launch_sum_partials(stream, launch_dot(stream, nb, per, rhs, rhs, partial), partial, pcs.bn2, nb);
+  // z = M^-1 r; rzn = z . r (and zq = z . q when q is given)
+  auto precondition = [&](const double *q) {
     if (!mixed) {
       vcycle<double>(0, rr);
-      launch_dot(stream, nd, rr, L0.vd.x, partial);
-      return reduce_host(red_grid(nd), partial, 0);
-    }
-    launch_to_f32(stream, nd, rr, L0.vf.f);
-    vcycle<float>(0, L0.vf.f);
-    launch_dot2_f32(stream, nd, L0.vf.x, rr, q, dot_scr);
-    launch_sum_partials(stream, kRedBlocks, dot_scr, scal + 10);
-    launch_sum_partials(stream, kRedBlocks, dot_scr + kRedBlocks, scal + 11);
-    hip_check(hipMemcpyAsync(host_scal + 10, scal + 10, 2 * sizeof(double), hipMemcpyDeviceToHost, stream), "copy");
-    sync("two dots");
-    if (zq) *zq = host_scal[11];
-    return host_scal[10];
-  };
-  auto set_p = [&](double beta) {
-    if (!mixed) {
-      if (beta == 0.0) hip_check(hipMemcpyAsync(pv, L0.vd.x, nd * sizeof(double), hipMemcpyDeviceToDevice, stream), "copy p");
-      else launch_xpay(stream, nd, beta, L0.vd.x, pv);
+      launch_sum_partials(stream, launch_dot(stream, nb, per, rr, L0.vd.x, partial), partial, pcs.rzn, nb);
     } else {
-      launch_xpay_f32(stream, nd, beta, L0.vf.x, pv);
+      launch_to_f32(stream, nd, rr, L0.vf.f);
+      vcycle<float>(0, L0.vf.f);
+      const int K = launch_dot2_f32(stream, nb, per, L0.vf.x, rr, q, dot_scr);
+      launch_sum_partials(stream, K, dot_scr, pcs.rzn, nb);
+      launch_sum_partials(stream, K, dot_scr + size_t(nb) * K, pcs.zq, nb);
     }
   };
-  double rz = precondition(nullptr, nullptr);
-  set_p(0.0);
-  double rel = 1.0;
+  auto set_p = [&] {   // p = z + beta p
+    if (!mixed) launch_xpay(stream, nb, per, pcs.beta, L0.vd.x, pv);
+    else launch_xpay_f32(stream, nb, per, pcs.beta, L0.vf.x, pv);
+  };
+  precondition(nullptr);
+  launch_pcg_scalars(stream, nb, kPcgStart, 0.0, pcs);   // act = (b != 0), beta = 0, rz = z . r
+  set_p();
+  double relmax = 0.0;
   int it = 0;
   for (it = 1; it <= opt.mg_max_iter; ++it) {
-    const int nb = apply0<double>(pv, nullptr, qv, nullptr, nullptr, 0.0, 0.0, kApplyDot, partial);
-    const double pq = reduce_host(nb, partial, 0);
-    const double alpha = rz / pq;
-    launch_cg_update(stream, nd, alpha, pv, qv, sol, rr, partial);
-    rel = std::sqrt(reduce_host(red_grid(nd), partial, 0)) / bnorm;
-    if (rel <= opt.mg_rtol) break;
-    double zq = 0.0;
-    const double rzn = precondition(qv, &zq);
-    set_p(mixed ? -alpha * zq / rz : rzn / rz);
-    rz = rzn;
+    const int Ka = apply0<double>(pv, nullptr, qv, nullptr, nullptr, 0.0, 0.0, kApplyDot, partial);
+    launch_sum_partials(stream, Ka, partial, pcs.pq, nb);
+    launch_pcg_scalars(stream, nb, kPcgAlpha, 0.0, pcs);
+    launch_sum_partials(stream, launch_cg_update(stream, nb, per, pcs.alpha, pv, qv, sol, rr, partial), partial,
+                        pcs.rr, nb);
+    launch_pcg_scalars(stream, nb, kPcgResid, opt.mg_rtol, pcs);
+    hip_check(hipMemcpyAsync(host_cs, pcs.rel, nb * sizeof(double), hipMemcpyDeviceToHost, stream), "copy residuals");
+    sync("mesh solve residual");
+    relmax = 0.0;
+    for (int bb = 0; bb < nb; ++bb) relmax = std::max(relmax, host_cs[bb]);
+    if (relmax <= opt.mg_rtol) break;
+    precondition(qv);
+    launch_pcg_scalars(stream, nb, mixed ? kPcgBetaPR : kPcgBeta, 0.0, pcs);
+    set_p();
   }
   stats.mg_iterations = std::min(it, opt.mg_max_iter);
-  stats.mg_rel_residual = rel;
+  stats.mg_rel_residual = relmax;
   check_launch("mesh solve");
-  if (!(rel <= opt.mg_rtol))
-    throw Status(FEP3M_ERR_NOT_CONVERGED, "mesh solve reached relative residual " + std::to_string(rel));
+  if (!(relmax <= opt.mg_rtol))
+    throw Status(FEP3M_ERR_NOT_CONVERGED, "mesh solve reached relative residual " + std::to_string(relmax));
 }
 
 // Gauge-fixed periodic solve: out = K^+ rhs with int out = 0.
 void fep3m_ctx::mesh_solve(double *rhs, double *out) {
   solve(rhs, out);
-  launch_mass_dot(stream, n, p, w1, out, partial);
-  launch_sum_partials(stream, red_grid(lv[0].ndof), partial, scal + 5);
-  launch_sub_const(stream, lv[0].ndof, 1.0 / (double(n) * n * n), scal + 5, out);
+  launch_mass_dot(stream, nb, n, p, w1, out, partial);
+  launch_sum_partials(stream, seg_blocks(nb, lv[0].ndof), partial, cfgs(kCsInt), nb);
+  launch_sub_const(stream, nb, lv[0].ndof, 1.0 / (double(n) * n * n), cfgs(kCsInt), out);
 }
 
 // ----------------------------------------------------------------- evaluate
 
 void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *U, bool pair_forces) {
-  const int M = n * n * n;
+  const int MT = nb * n * n * n;
   stage_mark(FEP3M_PROF_SORT, true);
-  hip_check(hipMemsetAsync(count, 0, size_t(M) * sizeof(int), stream), "zero counts");
+  hip_check(hipMemsetAsync(count, 0, size_t(MT) * sizeof(int), stream), "zero counts");
   hip_check(hipMemsetAsync(flags, 0, 4 * sizeof(int), stream), "zero flags");
-  const int gb = bin_grid(N);
-  launch_bin(stream, N, x, Qc, L, n, gtmp, elem, slot, count, flags, partial);
-  launch_sum_partials(stream, gb, partial, scal + 1);
-  launch_sum_partials(stream, gb, partial + gb, scal + 2);
-  hip_check(hipMemcpyAsync(host_scal + 1, scal + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, stream), "copy");
+  const int gb = launch_bin(stream, nb, off_d, N, x, Qc, L, n, gtmp, elem, slot, count, flags, partial);
+  launch_sum_partials(stream, gb, partial, cfgs(kCsQ), nb);
+  launch_sum_partials(stream, gb, partial + size_t(nb) * gb, cfgs(kCsQabs), nb);
+  hip_check(hipMemcpyAsync(host_cs, cs, 2 * size_t(nb) * sizeof(double), hipMemcpyDeviceToHost, stream), "copy");
   hip_check(hipMemcpyAsync(host_scal + 4, flags, sizeof(int), hipMemcpyDeviceToHost, stream), "copy");
   sync("binning");
   int fl;
   std::memcpy(&fl, host_scal + 4, sizeof(int));
   if (fl) throw Status(FEP3M_ERR_NONFINITE, "non-finite position or charge");
-  const double sq = host_scal[1], sa = host_scal[2];
-  if (std::fabs(sq) > 1e-10 * sa) throw Status(FEP3M_ERR_NOT_NEUTRAL, "charges are not neutral: sum Q = " + std::to_string(sq));
+  for (int bb = 0; bb < nb; ++bb) {
+    const double sq = host_cs[kCsQ * nb + bb], sa = host_cs[kCsQabs * nb + bb];
+    if (std::fabs(sq) > 1e-10 * sa)
+      throw Status(FEP3M_ERR_NOT_NEUTRAL, "charges are not neutral: sum Q = " + std::to_string(sq) +
+                                              (nb > 1 ? " in configuration " + std::to_string(bb) : std::string()));
+  }
 
-  launch_scan(stream, M, count, start, maxcount);
+  launch_scan(stream, MT, count, start, maxcount);
   launch_scatter(stream, N, elem, slot, start, tmp);
   launch_rank(stream, N, tmp, elem, start, gtmp, Qc, perm, sg, sQ);
   if (mixed) launch_local_f32(stream, n, N, sg, sQ, su, sel);
   stage_mark(FEP3M_PROF_SORT, false);
   stage_mark(FEP3M_PROF_ASSIGN, true);
-  launch_moments(stream, n, N, start, sg, sQ, C);
-  launch_load(stream, n, p, C, gw, b, partial);
-  launch_sum_partials(stream, red_grid(lv[0].ndof), partial, scal + 3);
-  launch_sub_mass_ones(stream, n, p, w1, scal + 3, b);
+  launch_moments(stream, nb, n, N, start, sg, sQ, C);
+  launch_load(stream, nb, n, p, C, gw, b, partial);
+  launch_sum_partials(stream, seg_blocks(nb, lv[0].ndof), partial, cfgs(kCsLoad), nb);
+  launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsLoad), b);
   check_launch("assignment");
   stage_mark(FEP3M_PROF_ASSIGN, false);
   stage_mark(FEP3M_PROF_SOLVE, true);
   mesh_solve(b, sol);
   stage_mark(FEP3M_PROF_SOLVE, false);
   stage_mark(FEP3M_PROF_NEAR, true);
-  const int ps = mixed ? launch_psi<float>(stream, n, nsr, p, C, Tf, sol, Welf)
-                       : launch_psi<double>(stream, n, nsr, p, C, T, sol, Wel);
+  const int ps = mixed ? launch_psi<float>(stream, nb, n, nsr, p, C, Tf, sol, Welf)
+                       : launch_psi<double>(stream, nb, n, nsr, p, C, T, sol, Wel);
   if (ps != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
   stage_mark(FEP3M_PROF_NEAR, false);
   pair_pass(pair_forces);
   stage_mark(FEP3M_PROF_INTERP, true);
-  const int is = mixed ? launch_interp_f32(stream, p, n, N, 1.0 / h, bas, su, sel, Welf, phip_s, perm, phim_s, phi_s, Phi)
-                       : launch_interp(stream, p, n, N, 1.0 / h, bas, sg, Wel, phip_s, perm, phim_s, phi_s, Phi);
+  const int is = mixed ? launch_interp_f32(stream, nb, off_d, p, n, N, 1.0 / h, bas, su, sel, Welf, phip_s, perm,
+                                           phim_s, phi_s, Phi)
+                       : launch_interp(stream, nb, off_d, p, n, N, 1.0 / h, bas, sg, Wel, phip_s, perm, phim_s, phi_s,
+                                       Phi);
   if (is != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "interpolation variant");
   if (U) {
-    launch_energy(stream, N, sQ, phi_s, partial);
-    launch_sum_partials(stream, energy_grid(N), partial, scal + 6);
-    launch_half(stream, scal + 6, U);
+    const int Ke = launch_energy(stream, nb, off_d, N, sQ, phi_s, partial);
+    launch_sum_partials(stream, Ke, partial, cfgs(kCsEnergy), nb);
+    launch_half(stream, nb, cfgs(kCsEnergy), U);
   }
   stage_mark(FEP3M_PROF_INTERP, false);
 }
@@ -621,8 +655,8 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
 void fep3m_ctx::pair_pass(bool pair_forces) {
   stage_mark(FEP3M_PROF_PAIR, true);
   double *fp = pair_forces ? fpair : nullptr;
-  const int st = mixed ? launch_pair_f32(stream, n, nsr, N, start, su, sel, phip_s, fp)
-                       : launch_pair(stream, n, nsr, N, start, sg, sQ, phip_s, fp);
+  const int st = mixed ? launch_pair_f32(stream, nb, n, nsr, N, start, su, sel, phip_s, fp)
+                       : launch_pair(stream, nb, n, nsr, N, start, sg, sQ, phip_s, fp);
   if (st != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "pair variant");
   prof.pair_forces = pair_forces;
   stage_mark(FEP3M_PROF_PAIR, false);
@@ -634,19 +668,23 @@ void fep3m_ctx::reverse(double *F, double *dUdQ) {
   const int fwd_iters = stats.mg_iterations;
   const double fwd_rel = stats.mg_rel_residual;
   stage_mark(FEP3M_PROF_ADJ_SOLVE, true);
-  launch_deposit(stream, p, n, N, bas, start, sg, sQ, gE);
-  launch_assemble(stream, p, n, gE, Gv, partial);
-  launch_sum_partials(stream, red_grid(lv[0].ndof), partial, scal + 7);
-  launch_sub_mass_ones(stream, n, p, w1, scal + 7, Gv);
+  launch_deposit(stream, nb, p, n, N, bas, start, sg, sQ, gE);
+  launch_assemble(stream, nb, p, n, gE, Gv, partial);
+  launch_sum_partials(stream, seg_blocks(nb, lv[0].ndof), partial, cfgs(kCsAdjLoad), nb);
+  launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsAdjLoad), Gv);
   mesh_solve(Gv, lam);
   stage_mark(FEP3M_PROF_ADJ_SOLVE, false);
   stage_mark(FEP3M_PROF_ADJ_NEAR, true);
-  if (launch_adj_moments(stream, p, n, nsr, gE, Tt, lam, gw, Aadj) != 0)
+  if (launch_adj_moments(stream, nb, p, n, nsr, gE, Tt, lam, gw, Aadj) != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
   stage_mark(FEP3M_PROF_ADJ_NEAR, false);
   stage_mark(FEP3M_PROF_FORCES, true);
-  if (mixed) launch_forces<float>(stream, p, n, N, 1.0 / h, bas, sg, sQ, Welf, Aadj, fpair, phip_s, phim_s, perm, F, dUdQ);
-  else launch_forces<double>(stream, p, n, N, 1.0 / h, bas, sg, sQ, Wel, Aadj, fpair, phip_s, phim_s, perm, F, dUdQ);
+  if (mixed)
+    launch_forces<float>(stream, nb, off_d, p, n, N, 1.0 / h, bas, sg, sQ, Welf, Aadj, fpair, phip_s, phim_s, perm, F,
+                         dUdQ);
+  else
+    launch_forces<double>(stream, nb, off_d, p, n, N, 1.0 / h, bas, sg, sQ, Wel, Aadj, fpair, phip_s, phim_s, perm, F,
+                          dUdQ);
   stage_mark(FEP3M_PROF_FORCES, false);
   stats.adj_iterations = stats.mg_iterations;
   stats.mg_iterations = fwd_iters;
@@ -656,7 +694,7 @@ void fep3m_ctx::reverse(double *F, double *dUdQ) {
 void fep3m_ctx::finish(bool count_pairs) {
   if (count_pairs) {
     hip_check(hipMemsetAsync(paircount, 0, sizeof(unsigned long long), stream), "zero pair count");
-    launch_pair_count(stream, n, nsr, start, paircount);
+    launch_pair_count(stream, nb, n, nsr, start, paircount);
     hip_check(hipMemcpyAsync(host_scal + 8, paircount, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
               "copy");
     hip_check(hipMemcpyAsync(host_scal + 9, maxcount, sizeof(int), hipMemcpyDeviceToHost, stream), "copy");
@@ -709,7 +747,7 @@ void fep3m_ctx::profile_collect() {
     prof.acc.count[s] += 1;
   }
   const double S = 2 * nsr + 1;
-  const double near_flop = 2.0 * 8.0 * (p + 1) * (p + 1) * (p + 1) * S * S * S * double(n) * n * n;
+  const double near_flop = 2.0 * 8.0 * (p + 1) * (p + 1) * (p + 1) * S * S * S * double(n) * n * n * nb;
   if (prof.marked & (1u << FEP3M_PROF_NEAR)) prof.acc.work[FEP3M_PROF_NEAR] += near_flop;
   if (prof.marked & (1u << FEP3M_PROF_PAIR))
     prof.acc.work[FEP3M_PROF_PAIR] += (prof.pair_forces ? 20.0 : 11.0) * double(stats.near_pairs);
@@ -775,7 +813,10 @@ int fep3m_default_options(fep3m_options *opt) {
   return FEP3M_OK;
 }
 
-int fep3m_create_ex(double L, int64_t N, const int32_t dims[3], int32_t q, const fep3m_options *opt, fep3m_ctx **out) {
+namespace {
+
+int create_common(double L, const std::vector<int64_t> &Ns, const int32_t dims[3], int32_t q,
+                  const fep3m_options *opt, fep3m_ctx **out) {
   if (!out) return FEP3M_ERR_ARG;
   *out = nullptr;
   fep3m_options o;
@@ -783,21 +824,41 @@ int fep3m_create_ex(double L, int64_t N, const int32_t dims[3], int32_t q, const
   std::string why;
   if (!dims) return FEP3M_ERR_ARG;
   if (!(L > 0.0) || !std::isfinite(L)) return FEP3M_ERR_ARG;
-  if (N < 2 || N > (int64_t(1) << 30)) return FEP3M_ERR_ARG;
+  if (Ns.empty() || Ns.size() > 1024) return FEP3M_ERR_ARG;
+  int64_t total = 0;
+  for (int64_t v : Ns) {
+    if (v < 2 || v > (int64_t(1) << 30)) return FEP3M_ERR_ARG;
+    total += v;
+  }
+  if (total > (int64_t(1) << 30)) return FEP3M_ERR_ARG;
   if (dims[0] != dims[1] || dims[1] != dims[2]) return FEP3M_ERR_ARG;
+  if (int64_t(Ns.size()) * dims[0] * dims[0] * dims[0] > (int64_t(1) << 28)) return FEP3M_ERR_ARG;
   if (!valid_options(o, why)) return FEP3M_ERR_ARG;
   if (dims[0] < 2 * o.n_sr + 1 || dims[0] > 512) return FEP3M_ERR_ARG;
   if (q < 2 || q > 6) return FEP3M_ERR_ARG;
   if (q != 3) return FEP3M_ERR_UNSUPPORTED;
   std::unique_ptr<fep3m_ctx> ctx(new (std::nothrow) fep3m_ctx());
   if (!ctx) return FEP3M_ERR_OOM;
-  int st = guarded(ctx.get(), [&] { ctx->build(L, N, dims[0], q, o); });
+  int st = guarded(ctx.get(), [&] { ctx->build(L, Ns, dims[0], q, o); });
   if (st != FEP3M_OK) {
     g_create_error = ctx->err;
     return st;
   }
   *out = ctx.release();
   return FEP3M_OK;
+}
+
+}  // namespace
+
+int fep3m_create_ex(double L, int64_t N, const int32_t dims[3], int32_t q, const fep3m_options *opt, fep3m_ctx **out) {
+  return create_common(L, std::vector<int64_t>{N}, dims, q, opt, out);
+}
+
+int fep3m_create_batch(double L, int32_t nconf, const int64_t *N_per_conf, const int32_t dims[3], int32_t q,
+                       const fep3m_options *opt, fep3m_ctx **out) {
+  if (out) *out = nullptr;
+  if (!N_per_conf || nconf < 1 || nconf > 1024) return FEP3M_ERR_ARG;
+  return create_common(L, std::vector<int64_t>(N_per_conf, N_per_conf + nconf), dims, q, opt, out);
 }
 
 int fep3m_create(double L, int64_t N, const int32_t dims[3], int32_t q, fep3m_ctx **out) {
@@ -837,8 +898,8 @@ int fep3m_backward(fep3m_ctx *ctx, int64_t generation, double *F, double *dUdQ) 
 
 int64_t fep3m_stage_bytes(const fep3m_ctx *ctx, int32_t stage) {
   if (!ctx) return 0;
-  const int64_t M = int64_t(ctx->n) * ctx->n * ctx->n;
-  const int64_t P3 = int64_t(ctx->lv.empty() ? 0 : ctx->lv[0].ndof);
+  const int64_t M = int64_t(ctx->n) * ctx->n * ctx->n * ctx->nb;
+  const int64_t P3 = int64_t(ctx->lv.empty() ? 0 : ctx->lv[0].ndof) * ctx->nb;
   switch (stage) {
     case 0: return ctx->N * 4;
     case 1: return (M + 1) * 4;

@@ -57,6 +57,28 @@ struct TransferT {
 using Transfer = TransferT<double>;
 using TransferF = TransferT<float>;
 
+// Batches: nb independent configurations that share the mesh and the
+// method's parameters.  Element ids are configuration-major (b * n^3 + e),
+// mesh vectors are nb consecutive P^3 blocks, and the charges of
+// configuration b occupy caller (and sorted) indices off[b] .. off[b+1]-1.
+// Per-configuration reductions use K blocks per configuration: block
+// (b, k) = blockIdx b * K + k strides over configuration b's range.
+__device__ __forceinline__ int cfg_of(const int *__restrict__ off, int nb, int64_t i) {
+  int lo = 0, hi = nb;   // off[lo] <= i < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Device arrays (nb values each) of the per-configuration PCG scalars.
+struct PcgScalars {
+  double *bn2, *rz, *rzn, *pq, *rr, *zq, *alpha, *beta, *act, *rel;
+};
+
+enum PcgStep : int { kPcgStart = 0, kPcgAlpha = 1, kPcgResid = 2, kPcgBeta = 3, kPcgBetaPR = 4 };
+
 enum ApplyMode : int {
   kApply = 0,      // out = K x
   kResidual = 1,   // out = f - K x

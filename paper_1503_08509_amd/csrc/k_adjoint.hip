@@ -34,11 +34,12 @@ __global__ __launch_bounds__(256) void k_deposit(int n, int64_t N, GllBasis bas,
                                                  const double *__restrict__ sg, const double *__restrict__ sQ,
                                                  double *__restrict__ gE) {
   constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
-  const int E = blockIdx.x;
+  const int E = blockIdx.x;   // element of the whole batch; local coordinates below
   const int m = threadIdx.x;
   if (m >= NM) return;
   const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
-  const int ex = E % n, ey = (E / n) % n, ez = E / (n * n);
+  const int El = E % (n * n * n);
+  const int ex = El % n, ey = (El / n) % n, ez = El / (n * n);
   double acc = 0.0;
   for (int s = start[E]; s < start[E + 1]; ++s) {
     const double ux = sg[s] - ex - 0.5, uy = sg[N + s] - ey - 0.5, uz = sg[2 * N + s] - ez - 0.5;
@@ -55,16 +56,20 @@ __global__ __launch_bounds__(256) void k_deposit(int n, int64_t N, GllBasis bas,
 }
 
 // G at each global node: sum of the owning elements' g values (gather form),
-// with block partials of sum G for the compatibility projection.
+// with per-configuration block partials (K blocks per configuration) of
+// sum G for the compatibility projection.
 template <int PO>
-__global__ __launch_bounds__(256) void k_assemble(int n, const double *__restrict__ gE, double *__restrict__ G,
-                                                  double *__restrict__ partial) {
+__global__ __launch_bounds__(256) void k_assemble(int n, int K, const double *__restrict__ gEall,
+                                                  double *__restrict__ Gall, double *__restrict__ partial) {
   constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
   __shared__ double red[256];
   const int P = PO * n;
   const size_t total = size_t(P) * P * P;
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const double *gE = gEall + size_t(cfg) * n * n * n * NM;
+  double *G = Gall + size_t(cfg) * total;
   double acc = 0.0;
-  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
+  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < total; g += size_t(K) * blockDim.x) {
     const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
     int ex[2], kx[2], ey[2], ky[2], ez[2], kz[2];
     int nx = 1, ny = 1, nz = 1;
@@ -117,8 +122,15 @@ __global__ __launch_bounds__(256) void k_adj_moments(int n, const double *__rest
   static_assert(BX * BY * BZ * 8 <= SLAB * MS, "reduction reuses the slab");
   __shared__ double Gs[SLAB * MS];               // [lz][hy][hx][m]
   __shared__ __align__(16) double Ts[TS];        // [D_y D_x][m][a]
-  const int bx_n = (n + BX - 1) / BX, by_n = (n + BY - 1) / BY;
-  int b = blockIdx.x;
+  const int bx_n = (n + BX - 1) / BX, by_n = (n + BY - 1) / BY, bz_n = (n + BZ - 1) / BZ;
+  {  // configuration of this brick
+    const int cfg = blockIdx.x / (bx_n * by_n * bz_n);
+    const size_t M = size_t(n) * n * n, P = size_t(PO) * n;
+    gE += size_t(cfg) * M * NM;
+    lam += size_t(cfg) * P * P * P;
+    Aout += size_t(cfg) * M * 8;
+  }
+  int b = blockIdx.x % (bx_n * by_n * bz_n);
   const int bx = b % bx_n;
   b /= bx_n;
   const int by = b % by_n;
@@ -219,7 +231,8 @@ __global__ __launch_bounds__(256) void k_adj_moments(int n, const double *__rest
 
 // Forces and dU/dQ per sorted charge, scattered to caller order.
 template <int PO, class WT>
-__global__ __launch_bounds__(256) void k_forces(int n, int64_t N, double inv_h, GllBasis bas,
+__global__ __launch_bounds__(256) void k_forces(int n, int64_t N, int nb, const int *__restrict__ off, double inv_h,
+                                                GllBasis bas,
                                                 const double *__restrict__ sg, const double *__restrict__ sQ,
                                                 const WT *__restrict__ Wel, const double *__restrict__ Aadj,
                                                 const double *__restrict__ fpair, const double *__restrict__ phip,
@@ -248,7 +261,7 @@ __global__ __launch_bounds__(256) void k_forces(int n, int64_t N, double inv_h, 
         dl[k][a] = dv;
       }
     }
-    const size_t E = size_t(e[0]) + size_t(n) * (e[1] + size_t(n) * e[2]);
+    const size_t E = size_t(cfg_of(off, nb, s)) * n * n * n + size_t(e[0]) + size_t(n) * (e[1] + size_t(n) * e[2]);
     const WT *w = Wel + E * (Q1 * Q1 * Q1);
     double gxs = 0.0, gys = 0.0, gzs = 0.0;
 #pragma unroll
@@ -293,23 +306,24 @@ __global__ __launch_bounds__(256) void k_forces(int n, int64_t N, double inv_h, 
 
 // ----------------------------------------------------------------- launchers
 
-int launch_deposit(hipStream_t s, int p, int n, int64_t N, const GllBasis &bas, const int *start, const double *sg,
-                   const double *sQ, double *gE) {
+int launch_deposit(hipStream_t s, int nb, int p, int n, int64_t N, const GllBasis &bas, const int *start,
+                   const double *sg, const double *sQ, double *gE) {
   if (p != 5) return -1;
-  hipLaunchKernelGGL(k_deposit<5>, dim3(n * n * n), dim3(256), 0, s, n, N, bas, start, sg, sQ, gE);
+  hipLaunchKernelGGL(k_deposit<5>, dim3(nb * n * n * n), dim3(256), 0, s, n, N, bas, start, sg, sQ, gE);
   return 0;
 }
-int launch_assemble(hipStream_t s, int p, int n, const double *gE, double *G, double *partial) {
+int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, double *G, double *partial) {
   if (p != 5) return -1;
-  const size_t tot = size_t(p * n) * (p * n) * (p * n);
-  hipLaunchKernelGGL(k_assemble<5>, dim3(red_grid(tot)), dim3(256), 0, s, n, gE, G, partial);
+  const size_t per = size_t(p * n) * (p * n) * (p * n);
+  const int K = seg_blocks(nb, per);
+  hipLaunchKernelGGL(k_assemble<5>, dim3(nb * K), dim3(256), 0, s, n, K, gE, G, partial);
   return 0;
 }
-int launch_adj_moments(hipStream_t s, int p, int n, int nsr, const double *gE, const double *Tt, const double *lam,
-                       const double *gw, double *A) {
+int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, const double *gE, const double *Tt,
+                       const double *lam, const double *gw, double *A) {
   if (p != 5) return -1;
   const int bxn = (n + 7) / 8, byn = (n + 3) / 4, bzn = (n + 3) / 4;
-  dim3 g(bxn * byn * bzn);
+  dim3 g(nb * bxn * byn * bzn);
   switch (nsr) {
     case 1: hipLaunchKernelGGL((k_adj_moments<1, 5>), g, dim3(256), 0, s, n, gE, Tt, lam, gw, A); return 0;
     case 2: hipLaunchKernelGGL((k_adj_moments<2, 5>), g, dim3(256), 0, s, n, gE, Tt, lam, gw, A); return 0;
@@ -318,21 +332,21 @@ int launch_adj_moments(hipStream_t s, int p, int n, int nsr, const double *gE, c
   }
 }
 template <class WT>
-int launch_forces(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const double *sg,
-                  const double *sQ, const WT *Wel, const double *A, const double *fpair, const double *phip,
-                  const double *phim_s, const int *perm, double *F, double *dUdQ) {
+int launch_forces(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h, const GllBasis &bas,
+                  const double *sg, const double *sQ, const WT *Wel, const double *A, const double *fpair,
+                  const double *phip, const double *phim_s, const int *perm, double *F, double *dUdQ) {
   if (p != 5) return -1;
   int64_t gb = (N + 255) / 256;
   if (gb > 4096) gb = 4096;
-  hipLaunchKernelGGL((k_forces<5, WT>), dim3(int(gb)), dim3(256), 0, s, n, N, inv_h, bas, sg, sQ, Wel, A, fpair,
-                     phip, phim_s, perm, F, dUdQ);
+  hipLaunchKernelGGL((k_forces<5, WT>), dim3(int(gb)), dim3(256), 0, s, n, N, nb, off, inv_h, bas, sg, sQ, Wel, A,
+                     fpair, phip, phim_s, perm, F, dUdQ);
   return 0;
 }
-template int launch_forces<double>(hipStream_t, int, int, int64_t, double, const GllBasis &, const double *,
+template int launch_forces<double>(hipStream_t, int, const int *, int, int, int64_t, double, const GllBasis &,
                                    const double *, const double *, const double *, const double *, const double *,
-                                   const double *, const int *, double *, double *);
-template int launch_forces<float>(hipStream_t, int, int, int64_t, double, const GllBasis &, const double *,
-                                  const double *, const float *, const double *, const double *, const double *,
-                                  const double *, const int *, double *, double *);
+                                   const double *, const double *, const int *, double *, double *);
+template int launch_forces<float>(hipStream_t, int, const int *, int, int, int64_t, double, const GllBasis &,
+                                  const double *, const double *, const float *, const double *, const double *,
+                                  const double *, const double *, const int *, double *, double *);
 
 }  // namespace fep3m

@@ -33,15 +33,19 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 
 // b at node (gz, gy, gx): 4 pi sum over the 1..8 elements owning the node of
 // sum_a C[E][a] g[ax][kx] g[ay][ky] g[az][kz] (gather form, no atomics),
-// with block partial sums of b for the compatibility projection.
-__global__ __launch_bounds__(256) void k_load(int n, int p, const double *__restrict__ C,
-                                              const double *__restrict__ gw, double *__restrict__ b,
+// with per-configuration block partial sums of b (K blocks per
+// configuration) for the compatibility projection.
+__global__ __launch_bounds__(256) void k_load(int n, int p, int K, const double *__restrict__ Call,
+                                              const double *__restrict__ gw, double *__restrict__ ball,
                                               double *__restrict__ partial) {
   __shared__ double red[256];
   const int P = p * n;
   const size_t total = size_t(P) * P * P;
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const double *C = Call + size_t(cfg) * n * n * n * 8;
+  double *b = ball + size_t(cfg) * total;
   double acc = 0.0;
-  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
+  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < total; g += size_t(K) * blockDim.x) {
     const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
     int ex[2], kx[2], ey[2], ky[2], ez[2], kz[2];
     int nx = 1, ny = 1, nz = 1;
@@ -71,28 +75,33 @@ __global__ __launch_bounds__(256) void k_load(int n, int p, const double *__rest
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// v -= s * w1[kx] w1[ky] w1[kz] with s = scal[0] / V  (V = n^3 in element
-// units): subtracts the uniform-background multiple of M 1.  Used on the
-// load (compatibility) with scal = sum b.
-__global__ __launch_bounds__(256) void k_sub_mass_ones(int n, int p, const double *__restrict__ w1,
-                                                       const double *__restrict__ scal, double *__restrict__ v) {
+// v -= s * w1[kx] w1[ky] w1[kz] with s = scal[b] / V  (V = n^3 in element
+// units) on configuration b: subtracts the uniform-background multiple of
+// M 1.  Used on the load (compatibility) with scal = sum b.
+__global__ __launch_bounds__(256) void k_sub_mass_ones(int n, int p, int K, const double *__restrict__ w1,
+                                                       const double *__restrict__ scal, double *__restrict__ vall) {
   const int P = p * n;
   const size_t total = size_t(P) * P * P;
-  const double s = scal[0] / (double(n) * n * n);
-  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  double *v = vall + size_t(cfg) * total;
+  const double s = scal[cfg] / (double(n) * n * n);
+  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < total; g += size_t(K) * blockDim.x) {
     const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
     v[g] -= s * w1[gx % p] * w1[gy % p] * w1[gz % p];
   }
 }
 
-// Block partials of (M 1)^T v = sum w1 w1 w1 v (the integral of the FE field).
-__global__ __launch_bounds__(256) void k_mass_dot(int n, int p, const double *__restrict__ w1,
-                                                  const double *__restrict__ v, double *__restrict__ partial) {
+// Per-configuration block partials of (M 1)^T v = sum w1 w1 w1 v (the
+// integral of the FE field).
+__global__ __launch_bounds__(256) void k_mass_dot(int n, int p, int K, const double *__restrict__ w1,
+                                                  const double *__restrict__ vall, double *__restrict__ partial) {
   __shared__ double red[256];
   const int P = p * n;
   const size_t total = size_t(P) * P * P;
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const double *v = vall + size_t(cfg) * total;
   double acc = 0.0;
-  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
+  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < total; g += size_t(K) * blockDim.x) {
     const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
     acc += w1[gx % p] * w1[gy % p] * w1[gz % p] * v[g];
   }
@@ -100,12 +109,13 @@ __global__ __launch_bounds__(256) void k_mass_dot(int n, int p, const double *__
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// v -= scal[0] / V (constant shift; fixes int phi = 0).
-__global__ __launch_bounds__(256) void k_sub_const(size_t total, double invV, const double *__restrict__ scal,
-                                                   double *__restrict__ v) {
-  const double s = scal[0] * invV;
-  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x)
-    v[g] -= s;
+// v -= scal[b] / V on configuration b (constant shift; fixes int phi = 0).
+__global__ __launch_bounds__(256) void k_sub_const(size_t per, int K, double invV, const double *__restrict__ scal,
+                                                   double *__restrict__ vall) {
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  double *v = vall + size_t(cfg) * per;
+  const double s = scal[cfg] * invV;
+  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < per; g += size_t(K) * blockDim.x) v[g] -= s;
 }
 
 // ----------------------------------------------------------------- operator
@@ -207,8 +217,17 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
   T *Y = lds + 2 * O * S::SC;
   const int P = op.P;
   const int tiles = (op.n + TE - 1) / TE;
+  {  // configuration of this tile: every vector moves to its block
+    const int tiles3 = tiles * tiles * tiles;
+    const size_t off = size_t(blockIdx.x / tiles3) * P * P * P;
+    x += off;
+    if (f) f += off;
+    if (out) out += off;
+    if (xprev) xprev += off;
+    if (xo) xo += off;
+  }
   int tx, ty, tz;
-  tile_coords(blockIdx.x, tiles, tx, ty, tz);
+  tile_coords(blockIdx.x % (tiles * tiles * tiles), tiles, tx, ty, tz);
   const int ox0 = tx * O, oy0 = ty * O, oz0 = tz * O;
   const int tid = threadIdx.x;
 
@@ -323,10 +342,14 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
 // First Chebyshev step from a zero iterate: x = c2 D^-1 f (the next step
 // reads its zero x_prev as a null pointer).
 template <class T>
-__global__ __launch_bounds__(256) void k_cheb_first(LevelOpT<T> op, const T *__restrict__ f, T *__restrict__ x, T c2) {
+__global__ __launch_bounds__(256) void k_cheb_first(LevelOpT<T> op, int K, const T *__restrict__ fall,
+                                                    T *__restrict__ xall, T c2) {
   const int P = op.P, p = op.p;
   const size_t total = size_t(P) * P * P;
-  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const T *f = fall + size_t(cfg) * total;
+  T *x = xall + size_t(cfg) * total;
+  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < total; g += size_t(K) * blockDim.x) {
     const int kx = int(g % P) % p, ky = int((g / P) % P) % p, kz = int(g / (size_t(P) * P)) % p;
     const T D = op.dk[kx] * op.dm[ky] * op.dm[kz] + op.dm[kx] * op.dk[ky] * op.dm[kz] + op.dm[kx] * op.dm[ky] * op.dk[kz];
     x[g] = c2 * f[g] / D;
@@ -378,7 +401,10 @@ __global__ __launch_bounds__(256) void k_restrict(TransferT<T> tr, const T *__re
   __shared__ T Out[CO * CO * CO];        // [cz][cy][cx]
   const int Pf = tr.Pf, Pc = tr.Pc;
   const int tiles = (tr.nc + TE - 1) / TE;
-  int t = blockIdx.x;
+  const int cfg = blockIdx.x / (tiles * tiles * tiles);
+  rf += size_t(cfg) * Pf * Pf * Pf;
+  fc += size_t(cfg) * Pc * Pc * Pc;
+  int t = blockIdx.x % (tiles * tiles * tiles);
   const int tx = t % tiles;
   t /= tiles;
   const int ty = t % tiles;
@@ -449,7 +475,10 @@ __global__ __launch_bounds__(256) void k_prolong_add(TransferT<T> tr, const T *_
   __shared__ T Out[FO * FO * FO];        // [fz][fy][fx]
   const int Pf = tr.Pf, Pc = tr.Pc;
   const int tiles = (tr.nc + TE - 1) / TE;
-  int t = blockIdx.x;
+  const int cfg = blockIdx.x / (tiles * tiles * tiles);
+  ec += size_t(cfg) * Pc * Pc * Pc;
+  xf += size_t(cfg) * Pf * Pf * Pf;
+  int t = blockIdx.x % (tiles * tiles * tiles);
   const int tx = t % tiles;
   t /= tiles;
   const int ty = t % tiles;
@@ -518,6 +547,8 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int Pn, const double *__re
   __shared__ double a[kCoarseMax];
   __shared__ double b[kCoarseMax];
   const int N3 = Pn * Pn * Pn;
+  f += size_t(blockIdx.x) * N3;   // one block per configuration
+  x += size_t(blockIdx.x) * N3;
   for (int i = threadIdx.x; i < N3; i += blockDim.x) a[i] = f[i];
   __syncthreads();
   // b = V^T along x
@@ -568,23 +599,33 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int Pn, const double *__re
 
 // ----------------------------------------------------------------- vectors
 
-__global__ __launch_bounds__(256) void k_dot(size_t n, const double *__restrict__ a, const double *__restrict__ b,
-                                             double *__restrict__ partial) {
+// Per-configuration vector kernels: configuration b = blockIdx / K owns
+// entries [b per, (b + 1) per); block partials land at partial[blockIdx].
+__global__ __launch_bounds__(256) void k_dot(size_t per, int K, const double *__restrict__ a,
+                                             const double *__restrict__ b, double *__restrict__ partial) {
   __shared__ double red[256];
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  a += size_t(cfg) * per;
+  b += size_t(cfg) * per;
   double acc = 0.0;
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+  for (size_t i = size_t(kb) * blockDim.x + threadIdx.x; i < per; i += size_t(K) * blockDim.x)
     acc += a[i] * b[i];
   double t = block_sum(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// x += alpha p; r -= alpha q; partial of r.r
-__global__ __launch_bounds__(256) void k_cg_update(size_t n, double alpha, const double *__restrict__ p,
-                                                   const double *__restrict__ q, double *__restrict__ x,
-                                                   double *__restrict__ r, double *__restrict__ partial) {
+// x += alpha_b p; r -= alpha_b q; partial of r.r
+__global__ __launch_bounds__(256) void k_cg_update(size_t per, int K, const double *__restrict__ alphas,
+                                                   const double *__restrict__ p, const double *__restrict__ q,
+                                                   double *__restrict__ x, double *__restrict__ r,
+                                                   double *__restrict__ partial) {
   __shared__ double red[256];
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const size_t o = size_t(cfg) * per;
+  p += o; q += o; x += o; r += o;
+  const double alpha = alphas[cfg];
   double acc = 0.0;
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+  for (size_t i = size_t(kb) * blockDim.x + threadIdx.x; i < per; i += size_t(K) * blockDim.x) {
     x[i] += alpha * p[i];
     const double rv = r[i] - alpha * q[i];
     r[i] = rv;
@@ -594,10 +635,15 @@ __global__ __launch_bounds__(256) void k_cg_update(size_t n, double alpha, const
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// p = z + beta p
-__global__ __launch_bounds__(256) void k_xpay(size_t n, double beta, const double *__restrict__ z, double *__restrict__ p) {
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
-    p[i] = z[i] + beta * p[i];
+// p = z + beta_b p (p = z when beta_b == 0: p is not read)
+__global__ __launch_bounds__(256) void k_xpay(size_t per, int K, const double *__restrict__ betas,
+                                              const double *__restrict__ z, double *__restrict__ p) {
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  z += size_t(cfg) * per;
+  p += size_t(cfg) * per;
+  const double beta = betas[cfg];
+  for (size_t i = size_t(kb) * blockDim.x + threadIdx.x; i < per; i += size_t(K) * blockDim.x)
+    p[i] = beta == 0.0 ? z[i] : z[i] + beta * p[i];
 }
 
 __global__ __launch_bounds__(256) void k_scale(size_t n, double s, const double *__restrict__ a, double *__restrict__ b) {
@@ -621,13 +667,19 @@ __global__ __launch_bounds__(256) void k_to_f32(size_t n, const double *__restri
     b[i] = float(a[i]);
 }
 
-// Block partials of z.r (first kRedBlocks slots) and z.q (next kRedBlocks),
-// float64 sums of a float32 z.
-__global__ __launch_bounds__(256) void k_dot2_f32(size_t n, const float *__restrict__ z, const double *__restrict__ r,
-                                                  const double *__restrict__ q, double *__restrict__ partial) {
+// Block partials of z.r (first gridDim slots) and z.q (next gridDim),
+// float64 sums of a float32 z, per configuration.
+__global__ __launch_bounds__(256) void k_dot2_f32(size_t per, int K, const float *__restrict__ z,
+                                                  const double *__restrict__ r, const double *__restrict__ q,
+                                                  double *__restrict__ partial) {
   __shared__ double red[256];
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const size_t o = size_t(cfg) * per;
+  z += o;
+  r += o;
+  if (q) q += o;
   double a = 0.0, b = 0.0;
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
+  for (size_t i = size_t(kb) * blockDim.x + threadIdx.x; i < per; i += size_t(K) * blockDim.x) {
     const double zi = double(z[i]);
     a += zi * r[i];
     if (q) b += zi * q[i];
@@ -640,21 +692,59 @@ __global__ __launch_bounds__(256) void k_dot2_f32(size_t n, const float *__restr
   }
 }
 
-// p = z + beta p (p = z when beta == 0: p is not read), z float32.
-__global__ __launch_bounds__(256) void k_xpay_f32(size_t n, double beta, const float *__restrict__ z,
-                                                  double *__restrict__ p) {
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+// p = z + beta_b p (p = z when beta_b == 0: p is not read), z float32.
+__global__ __launch_bounds__(256) void k_xpay_f32(size_t per, int K, const double *__restrict__ betas,
+                                                  const float *__restrict__ z, double *__restrict__ p) {
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  z += size_t(cfg) * per;
+  p += size_t(cfg) * per;
+  const double beta = betas[cfg];
+  for (size_t i = size_t(kb) * blockDim.x + threadIdx.x; i < per; i += size_t(K) * blockDim.x)
     p[i] = beta == 0.0 ? double(z[i]) : double(z[i]) + beta * p[i];
 }
 
-// Second stage of every reduction: one block sums `count` partials in a
-// fixed order into out[0].
-__global__ __launch_bounds__(256) void k_sum_partials(int count, const double *__restrict__ partial, double *__restrict__ out) {
+// PCG scalars, one thread per configuration, on arrays of nb values:
+//   kPcgStart  act = (bn2 > 0); beta = 0; rz = rzn
+//   kPcgAlpha  alpha = act ? rz / pq : 0
+//   kPcgResid  rel = sqrt(rr) / sqrt(bn2) (0 if bn2 = 0); act &= rel > rtol
+//   kPcgBeta   beta = act ? rzn / rz : 0; rz = rzn
+//   kPcgBetaPR beta = act ? -alpha zq / rz : 0; rz = rzn (flexible form)
+__global__ __launch_bounds__(64) void k_pcg_scalars(int nb, int step, double rtol, PcgScalars s) {
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    switch (step) {
+      case kPcgStart:
+        s.act[b] = s.bn2[b] > 0.0 ? 1.0 : 0.0;
+        s.beta[b] = 0.0;
+        s.rz[b] = s.rzn[b];
+        break;
+      case kPcgAlpha: s.alpha[b] = s.act[b] != 0.0 ? s.rz[b] / s.pq[b] : 0.0; break;
+      case kPcgResid: {
+        const double rel = s.bn2[b] > 0.0 ? sqrt(s.rr[b]) / sqrt(s.bn2[b]) : 0.0;
+        s.rel[b] = rel;
+        if (!(rel > rtol)) s.act[b] = 0.0;
+        break;
+      }
+      case kPcgBeta:
+        s.beta[b] = s.act[b] != 0.0 ? s.rzn[b] / s.rz[b] : 0.0;
+        s.rz[b] = s.rzn[b];
+        break;
+      default:
+        s.beta[b] = s.act[b] != 0.0 ? -s.alpha[b] * s.zq[b] / s.rz[b] : 0.0;
+        s.rz[b] = s.rzn[b];
+        break;
+    }
+  }
+}
+
+// Second stage of every reduction: block b sums the K partials of
+// configuration b in a fixed order into out[b].
+__global__ __launch_bounds__(256) void k_sum_partials(int K, const double *__restrict__ partial, double *__restrict__ out) {
   __shared__ double red[256];
+  partial += size_t(blockIdx.x) * K;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += partial[i];
+  for (int i = threadIdx.x; i < K; i += blockDim.x) acc += partial[i];
   double t = block_sum(acc, red);
-  if (threadIdx.x == 0) out[0] = t;
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 // ----------------------------------------------------------------- launchers
@@ -666,43 +756,55 @@ inline int grid_for(size_t n) {
 }
 }  // namespace
 
-void launch_load(hipStream_t s, int n, int p, const double *C, const double *gw, double *b, double *partial) {
-  const size_t tot = size_t(p * n) * (p * n) * (p * n);
-  hipLaunchKernelGGL(k_load, dim3(grid_for(tot)), dim3(256), 0, s, n, p, C, gw, b, partial);
+int seg_blocks(int nb, size_t per) {
+  const size_t cap = nb >= kRedBlocks ? 1 : size_t(kRedBlocks / nb);
+  size_t g = (per + 255) / 256;
+  if (g < 1) g = 1;
+  return int(g < cap ? g : cap);
 }
 int red_grid(size_t n) { return grid_for(n); }
-void launch_sum_partials(hipStream_t s, int count, const double *partial, double *out) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, count, partial, out);
+
+void launch_load(hipStream_t s, int nb, int n, int p, const double *C, const double *gw, double *b, double *partial) {
+  const size_t per = size_t(p * n) * (p * n) * (p * n);
+  const int K = seg_blocks(nb, per);
+  hipLaunchKernelGGL(k_load, dim3(nb * K), dim3(256), 0, s, n, p, K, C, gw, b, partial);
 }
-void launch_sub_mass_ones(hipStream_t s, int n, int p, const double *w1, const double *scal, double *v) {
-  const size_t tot = size_t(p * n) * (p * n) * (p * n);
-  hipLaunchKernelGGL(k_sub_mass_ones, dim3(grid_for(tot)), dim3(256), 0, s, n, p, w1, scal, v);
+void launch_sum_partials(hipStream_t s, int K, const double *partial, double *out, int nb) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(nb), dim3(256), 0, s, K, partial, out);
 }
-void launch_mass_dot(hipStream_t s, int n, int p, const double *w1, const double *v, double *partial) {
-  const size_t tot = size_t(p * n) * (p * n) * (p * n);
-  hipLaunchKernelGGL(k_mass_dot, dim3(grid_for(tot)), dim3(256), 0, s, n, p, w1, v, partial);
+void launch_sub_mass_ones(hipStream_t s, int nb, int n, int p, const double *w1, const double *scal, double *v) {
+  const size_t per = size_t(p * n) * (p * n) * (p * n);
+  const int K = seg_blocks(nb, per);
+  hipLaunchKernelGGL(k_sub_mass_ones, dim3(nb * K), dim3(256), 0, s, n, p, K, w1, scal, v);
 }
-void launch_sub_const(hipStream_t s, size_t total, double invV, const double *scal, double *v) {
-  hipLaunchKernelGGL(k_sub_const, dim3(grid_for(total)), dim3(256), 0, s, total, invV, scal, v);
+void launch_mass_dot(hipStream_t s, int nb, int n, int p, const double *w1, const double *v, double *partial) {
+  const size_t per = size_t(p * n) * (p * n) * (p * n);
+  const int K = seg_blocks(nb, per);
+  hipLaunchKernelGGL(k_mass_dot, dim3(nb * K), dim3(256), 0, s, n, p, K, w1, v, partial);
+}
+void launch_sub_const(hipStream_t s, int nb, size_t per, double invV, const double *scal, double *v) {
+  const int K = seg_blocks(nb, per);
+  hipLaunchKernelGGL(k_sub_const, dim3(nb * K), dim3(256), 0, s, per, K, invV, scal, v);
 }
 
 template <class T, int PO, int TE>
-static int apply_impl(hipStream_t s, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *d, T *xo, T c1,
-                      T c2, int mode, double *partial) {
+static int apply_impl(hipStream_t s, int nb, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *d, T *xo,
+                      T c1, T c2, int mode, double *partial) {
   const int tiles = (op.n + TE - 1) / TE;
-  const int nb = tiles * tiles * tiles;
-  hipLaunchKernelGGL((k_apply<T, PO, TE>), dim3(nb), dim3(256), 0, s, op, x, f, out, d, xo, c1, c2, mode, partial);
-  return nb;
+  const int K = tiles * tiles * tiles;
+  hipLaunchKernelGGL((k_apply<T, PO, TE>), dim3(nb * K), dim3(256), 0, s, op, x, f, out, d, xo, c1, c2, mode,
+                     partial);
+  return K;
 }
 
 template <class T>
-int launch_apply(hipStream_t s, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *d, T *xo, T c1, T c2,
-                 int mode, double *partial) {
+int launch_apply(hipStream_t s, int nb, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *d, T *xo,
+                 T c1, T c2, int mode, double *partial) {
   switch (op.p) {
-    case 1: return apply_impl<T, 1, 8>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
-    case 2: return apply_impl<T, 2, 4>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
-    case 3: return apply_impl<T, 3, 3>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
-    case 5: return apply_impl<T, 5, 2>(s, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 1: return apply_impl<T, 1, 8>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 2: return apply_impl<T, 2, 4>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 3: return apply_impl<T, 3, 3>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 5: return apply_impl<T, 5, 2>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial);
     default: return -1;
   }
 }
@@ -714,48 +816,54 @@ int apply_blocks(const LevelOp &op) {
 }
 
 template <class T>
-void launch_cheb_first(hipStream_t s, const LevelOpT<T> &op, const T *f, T *x, T c2) {
-  const size_t tot = size_t(op.P) * op.P * op.P;
-  hipLaunchKernelGGL(k_cheb_first<T>, dim3(grid_for(tot)), dim3(256), 0, s, op, f, x, c2);
+void launch_cheb_first(hipStream_t s, int nb, const LevelOpT<T> &op, const T *f, T *x, T c2) {
+  const size_t per = size_t(op.P) * op.P * op.P;
+  const int K = seg_blocks(nb, per);
+  hipLaunchKernelGGL(k_cheb_first<T>, dim3(nb * K), dim3(256), 0, s, op, K, f, x, c2);
 }
 template <class T, int PF, int PC, int R, int TE>
-static void restrict_impl(hipStream_t s, const TransferT<T> &tr, const T *in, T *out) {
+static void restrict_impl(hipStream_t s, int nb, const TransferT<T> &tr, const T *in, T *out) {
   const int tiles = (tr.nc + TE - 1) / TE;
-  hipLaunchKernelGGL((k_restrict<T, PF, PC, R, TE>), dim3(tiles * tiles * tiles), dim3(256), 0, s, tr, in, out);
+  hipLaunchKernelGGL((k_restrict<T, PF, PC, R, TE>), dim3(nb * tiles * tiles * tiles), dim3(256), 0, s, tr, in, out);
 }
 template <class T, int PF, int PC, int R, int TE>
-static void prolong_impl(hipStream_t s, const TransferT<T> &tr, const T *in, T *out) {
+static void prolong_impl(hipStream_t s, int nb, const TransferT<T> &tr, const T *in, T *out) {
   const int tiles = (tr.nc + TE - 1) / TE;
-  hipLaunchKernelGGL((k_prolong_add<T, PF, PC, R, TE>), dim3(tiles * tiles * tiles), dim3(256), 0, s, tr, in, out);
+  hipLaunchKernelGGL((k_prolong_add<T, PF, PC, R, TE>), dim3(nb * tiles * tiles * tiles), dim3(256), 0, s, tr, in,
+                     out);
 }
 
 // Supported transfers: p 5 -> 3 and 3 -> 1 on one mesh, Q1 coarsening by 2 or 3.
 template <class T>
-int launch_transfer(hipStream_t s, const TransferT<T> &tr, const T *in, T *out, bool restrict_) {
+int launch_transfer(hipStream_t s, int nb, const TransferT<T> &tr, const T *in, T *out, bool restrict_) {
   if (tr.pf == 5 && tr.pc == 3 && tr.r == 1) {
-    if (restrict_) restrict_impl<T, 5, 3, 1, 2>(s, tr, in, out); else prolong_impl<T, 5, 3, 1, 2>(s, tr, in, out);
+    if (restrict_) restrict_impl<T, 5, 3, 1, 2>(s, nb, tr, in, out);
+    else prolong_impl<T, 5, 3, 1, 2>(s, nb, tr, in, out);
   } else if (tr.pf == 3 && tr.pc == 1 && tr.r == 1) {
-    if (restrict_) restrict_impl<T, 3, 1, 1, 4>(s, tr, in, out); else prolong_impl<T, 3, 1, 1, 5>(s, tr, in, out);
+    if (restrict_) restrict_impl<T, 3, 1, 1, 4>(s, nb, tr, in, out);
+    else prolong_impl<T, 3, 1, 1, 5>(s, nb, tr, in, out);
   } else if (tr.pf == 1 && tr.pc == 1 && tr.r == 2) {
-    if (restrict_) restrict_impl<T, 1, 1, 2, 7>(s, tr, in, out); else prolong_impl<T, 1, 1, 2, 8>(s, tr, in, out);
+    if (restrict_) restrict_impl<T, 1, 1, 2, 7>(s, nb, tr, in, out);
+    else prolong_impl<T, 1, 1, 2, 8>(s, nb, tr, in, out);
   } else if (tr.pf == 1 && tr.pc == 1 && tr.r == 3) {
-    if (restrict_) restrict_impl<T, 1, 1, 3, 4>(s, tr, in, out); else prolong_impl<T, 1, 1, 3, 5>(s, tr, in, out);
+    if (restrict_) restrict_impl<T, 1, 1, 3, 4>(s, nb, tr, in, out);
+    else prolong_impl<T, 1, 1, 3, 5>(s, nb, tr, in, out);
   } else {
     return -1;
   }
   return 0;
 }
 template <class T>
-void launch_coarse_solve(hipStream_t s, int Pn, const double *V, const double *lam, const T *f, T *x) {
-  hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(256), 0, s, Pn, V, lam, f, x);
+void launch_coarse_solve(hipStream_t s, int nb, int Pn, const double *V, const double *lam, const T *f, T *x) {
+  hipLaunchKernelGGL(k_coarse_solve<T>, dim3(nb), dim3(256), 0, s, Pn, V, lam, f, x);
 }
 
-#define FEP3M_MESH_INSTANTIATE(T)                                                                              \
-  template int launch_apply<T>(hipStream_t, const LevelOpT<T> &, const T *, const T *, T *, const T *, T *, T, \
-                               T, int, double *);                                                              \
-  template void launch_cheb_first<T>(hipStream_t, const LevelOpT<T> &, const T *, T *, T);                     \
-  template int launch_transfer<T>(hipStream_t, const TransferT<T> &, const T *, T *, bool);                    \
-  template void launch_coarse_solve<T>(hipStream_t, int, const double *, const double *, const T *, T *);
+#define FEP3M_MESH_INSTANTIATE(T)                                                                                   \
+  template int launch_apply<T>(hipStream_t, int, const LevelOpT<T> &, const T *, const T *, T *, const T *, T *, T, \
+                               T, int, double *);                                                                   \
+  template void launch_cheb_first<T>(hipStream_t, int, const LevelOpT<T> &, const T *, T *, T);                     \
+  template int launch_transfer<T>(hipStream_t, int, const TransferT<T> &, const T *, T *, bool);                    \
+  template void launch_coarse_solve<T>(hipStream_t, int, int, const double *, const double *, const T *, T *);
 FEP3M_MESH_INSTANTIATE(double)
 FEP3M_MESH_INSTANTIATE(float)
 #undef FEP3M_MESH_INSTANTIATE
@@ -763,21 +871,33 @@ FEP3M_MESH_INSTANTIATE(float)
 void launch_to_f32(hipStream_t s, size_t n, const double *a, float *b) {
   hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(256), 0, s, n, a, b);
 }
-void launch_dot2_f32(hipStream_t s, size_t n, const float *z, const double *r, const double *q, double *partial) {
-  hipLaunchKernelGGL(k_dot2_f32, dim3(kRedBlocks), dim3(256), 0, s, n, z, r, q, partial);
+int launch_dot2_f32(hipStream_t s, int nb, size_t per, const float *z, const double *r, const double *q,
+                    double *partial) {
+  const int K = seg_blocks(nb, per);
+  hipLaunchKernelGGL(k_dot2_f32, dim3(nb * K), dim3(256), 0, s, per, K, z, r, q, partial);
+  return K;
 }
-void launch_xpay_f32(hipStream_t s, size_t n, double beta, const float *z, double *p) {
-  hipLaunchKernelGGL(k_xpay_f32, dim3(grid_for(n)), dim3(256), 0, s, n, beta, z, p);
+void launch_xpay_f32(hipStream_t s, int nb, size_t per, const double *betas, const float *z, double *p) {
+  const int K = seg_blocks(nb, per);
+  hipLaunchKernelGGL(k_xpay_f32, dim3(nb * K), dim3(256), 0, s, per, K, betas, z, p);
 }
-void launch_dot(hipStream_t s, size_t n, const double *a, const double *b, double *partial) {
-  hipLaunchKernelGGL(k_dot, dim3(grid_for(n)), dim3(256), 0, s, n, a, b, partial);
+void launch_pcg_scalars(hipStream_t s, int nb, int step, double rtol, const PcgScalars &sc) {
+  hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(64), 0, s, nb, step, rtol, sc);
 }
-void launch_cg_update(hipStream_t s, size_t n, double alpha, const double *p, const double *q, double *x, double *r,
-                      double *partial) {
-  hipLaunchKernelGGL(k_cg_update, dim3(grid_for(n)), dim3(256), 0, s, n, alpha, p, q, x, r, partial);
+int launch_dot(hipStream_t s, int nb, size_t per, const double *a, const double *b, double *partial) {
+  const int K = seg_blocks(nb, per);
+  hipLaunchKernelGGL(k_dot, dim3(nb * K), dim3(256), 0, s, per, K, a, b, partial);
+  return K;
 }
-void launch_xpay(hipStream_t s, size_t n, double beta, const double *z, double *p) {
-  hipLaunchKernelGGL(k_xpay, dim3(grid_for(n)), dim3(256), 0, s, n, beta, z, p);
+int launch_cg_update(hipStream_t s, int nb, size_t per, const double *alphas, const double *p, const double *q,
+                     double *x, double *r, double *partial) {
+  const int K = seg_blocks(nb, per);
+  hipLaunchKernelGGL(k_cg_update, dim3(nb * K), dim3(256), 0, s, per, K, alphas, p, q, x, r, partial);
+  return K;
+}
+void launch_xpay(hipStream_t s, int nb, size_t per, const double *betas, const double *z, double *p) {
+  const int K = seg_blocks(nb, per);
+  hipLaunchKernelGGL(k_xpay, dim3(nb * K), dim3(256), 0, s, per, K, betas, z, p);
 }
 void launch_scale(hipStream_t s, size_t n, double sc, const double *a, double *b) {
   hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(256), 0, s, n, sc, a, b);

@@ -125,8 +125,9 @@ __global__ __launch_bounds__(64) void k_pair_f32(int n, int64_t N, const int *__
   const int E = blockIdx.x;
   const int tb = start[E], te = start[E + 1];
   if (tb == te) return;  // uniform over the (single-wave) block
-  const int total = build_segments<NSR>(seg, E, n, start, lane, 64);
-  const int ex = E % n, ey = (E / n) % n, ez = E / (n * n);
+  const int M = n * n * n, El = E % M;
+  const int total = build_segments<NSR>(seg, El, n, start + (E / M) * M, lane, 64);
+  const int ex = El % n, ey = (El / n) % n, ez = El / (n * n);
   for (int t0 = tb; t0 < te;) {   // chunk widths 8, 4, 2 as in the float64 kernel
     const int rem = te - t0;
     if (rem > 4) {
@@ -146,7 +147,8 @@ __global__ __launch_bounds__(64) void k_pair_f32(int n, int64_t N, const int *__
 // factorisation in float32 (the outer sum compensated), combined with the
 // pair term in float64 and scattered to caller order.
 template <int PO>
-__global__ __launch_bounds__(256) void k_interp_f32(int n, int64_t N, double inv_h, GllBasis bas,
+__global__ __launch_bounds__(256) void k_interp_f32(int n, int64_t N, int nb, const int *__restrict__ off,
+                                                    double inv_h, GllBasis bas,
                                                     const float4 *__restrict__ su, const int *__restrict__ sel,
                                                     const float *__restrict__ Wel, const double *__restrict__ phip,
                                                     const int *__restrict__ perm, double *__restrict__ phim_s,
@@ -170,7 +172,8 @@ __global__ __launch_bounds__(256) void k_interp_f32(int n, int64_t N, double inv
           if (j != a) v *= (u[k] - bx[j]);
         l[k][a] = v;
       }
-    const size_t E = size_t(pe & 1023) + size_t(n) * (((pe >> 10) & 1023) + size_t(n) * (pe >> 20));
+    const size_t E = size_t(cfg_of(off, nb, s)) * n * n * n + size_t(pe & 1023) +
+                     size_t(n) * (((pe >> 10) & 1023) + size_t(n) * (pe >> 20));
     const float *w = Wel + E * (Q1 * Q1 * Q1);
     float acc = 0.f, comp = 0.f;
 #pragma unroll
@@ -208,30 +211,30 @@ void launch_local_f32(hipStream_t s, int n, int64_t N, const double *sg, const d
 }
 
 template <int NSR>
-static void pair_f32_impl(hipStream_t s, int n, int64_t N, const int *start, const float4 *su, const int *sel,
+static void pair_f32_impl(hipStream_t s, int nb, int n, int64_t N, const int *start, const float4 *su, const int *sel,
                           double *phip, double *fpair) {
-  dim3 g(n * n * n);
+  dim3 g(nb * n * n * n);
   if (fpair) hipLaunchKernelGGL((k_pair_f32<NSR, true>), g, dim3(64), 0, s, n, N, start, su, sel, phip, fpair);
   else hipLaunchKernelGGL((k_pair_f32<NSR, false>), g, dim3(64), 0, s, n, N, start, su, sel, phip, fpair);
 }
-int launch_pair_f32(hipStream_t s, int n, int nsr, int64_t N, const int *start, const float4 *su, const int *sel,
-                    double *phip, double *fpair) {
+int launch_pair_f32(hipStream_t s, int nb, int n, int nsr, int64_t N, const int *start, const float4 *su,
+                    const int *sel, double *phip, double *fpair) {
   if (n > 1024) return -1;   // packed element coordinates hold 10 bits per axis
   switch (nsr) {
-    case 1: pair_f32_impl<1>(s, n, N, start, su, sel, phip, fpair); return 0;
-    case 2: pair_f32_impl<2>(s, n, N, start, su, sel, phip, fpair); return 0;
-    case 3: pair_f32_impl<3>(s, n, N, start, su, sel, phip, fpair); return 0;
-    case 4: pair_f32_impl<4>(s, n, N, start, su, sel, phip, fpair); return 0;
+    case 1: pair_f32_impl<1>(s, nb, n, N, start, su, sel, phip, fpair); return 0;
+    case 2: pair_f32_impl<2>(s, nb, n, N, start, su, sel, phip, fpair); return 0;
+    case 3: pair_f32_impl<3>(s, nb, n, N, start, su, sel, phip, fpair); return 0;
+    case 4: pair_f32_impl<4>(s, nb, n, N, start, su, sel, phip, fpair); return 0;
     default: return -1;
   }
 }
 
-int launch_interp_f32(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const float4 *su,
-                      const int *sel, const float *Wel, const double *phip, const int *perm, double *phim_s,
-                      double *phi_s, double *Phi) {
+int launch_interp_f32(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h,
+                      const GllBasis &bas, const float4 *su, const int *sel, const float *Wel, const double *phip,
+                      const int *perm, double *phim_s, double *phi_s, double *Phi) {
   if (p != 5) return -1;
-  hipLaunchKernelGGL(k_interp_f32<5>, dim3(grid_m(N)), dim3(256), 0, s, n, N, inv_h, bas, su, sel, Wel, phip, perm,
-                     phim_s, phi_s, Phi);
+  hipLaunchKernelGGL(k_interp_f32<5>, dim3(grid_m(N)), dim3(256), 0, s, n, N, nb, off, inv_h, bas, su, sel, Wel,
+                     phip, perm, phim_s, phi_s, Phi);
   return 0;
 }
 

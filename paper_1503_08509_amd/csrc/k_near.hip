@@ -50,7 +50,14 @@ __global__ __launch_bounds__(256, 2) void k_psi(int n, const double *__restrict_
   __shared__ __align__(16) T Cs[8 * SLAB];
 
   const int bricks = (n + BS - 1) / BS;
-  int b = blockIdx.x;
+  {  // configuration of this brick
+    const int cfg = blockIdx.x / (bricks * bricks * bricks);
+    const size_t M = size_t(n) * n * n, P = size_t(PO) * n;
+    C += size_t(cfg) * M * 8;
+    phi += size_t(cfg) * P * P * P;
+    Wel += size_t(cfg) * M * NM;
+  }
+  int b = blockIdx.x % (bricks * bricks * bricks);
   const int bx = b % bricks;
   b /= bricks;
   const int by = b % bricks;
@@ -167,10 +174,10 @@ __global__ __launch_bounds__(256, 2) void k_psi(int n, const double *__restrict_
 }
 
 template <class T>
-int launch_psi(hipStream_t s, int n, int nsr, int p, const double *C, const T *Tab, const double *phi, T *Wel) {
+int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, const double *C, const T *Tab, const double *phi, T *Wel) {
   if (p != 5) return -1;
   const int bricks = (n + 3) / 4;
-  dim3 g(bricks * bricks * bricks);
+  dim3 g(nb * bricks * bricks * bricks);
   switch (nsr) {
     case 1: hipLaunchKernelGGL((k_psi<1, 5, T>), g, dim3(256), 0, s, n, C, Tab, phi, Wel); return 0;
     case 2: hipLaunchKernelGGL((k_psi<2, 5, T>), g, dim3(256), 0, s, n, C, Tab, phi, Wel); return 0;
@@ -178,7 +185,9 @@ int launch_psi(hipStream_t s, int n, int nsr, int p, const double *C, const T *T
     default: return -1;
   }
 }
-template int launch_psi<double>(hipStream_t, int, int, int, const double *, const double *, const double *, double *);
-template int launch_psi<float>(hipStream_t, int, int, int, const double *, const float *, const double *, float *);
+template int launch_psi<double>(hipStream_t, int, int, int, int, const double *, const double *, const double *,
+                                double *);
+template int launch_psi<float>(hipStream_t, int, int, int, int, const double *, const float *, const double *,
+                               float *);
 
 }  // namespace fep3m

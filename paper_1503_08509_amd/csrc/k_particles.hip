@@ -24,16 +24,22 @@ __device__ __forceinline__ double block_sum_p(double v, double *red) {
 
 // ----------------------------------------------------------------- binning
 
-// Wrap, bin and count.  Non-finite inputs raise flags[0] and are binned to
+// Wrap, bin and count; K blocks per configuration, block (b, k) over the
+// charges off[b] .. off[b+1]-1, which fall in elements b n^3 + e.
+// Non-finite inputs raise flags[0] and are binned to the configuration's
 // element 0 so every index stays in bounds.  Block partials of sum Q and
-// sum |Q| go to partial[b] and partial[gridDim.x + b].
-__global__ __launch_bounds__(256) void k_bin(int64_t N, const double *__restrict__ x, const double *__restrict__ Q,
-                                             double L, int n, double *__restrict__ gtmp, int *__restrict__ elem,
+// sum |Q| go to partial[blockIdx] and partial[gridDim.x + blockIdx].
+__global__ __launch_bounds__(256) void k_bin(int64_t N, int K, const int *__restrict__ off,
+                                             const double *__restrict__ x, const double *__restrict__ Q, double L,
+                                             int n, double *__restrict__ gtmp, int *__restrict__ elem,
                                              int *__restrict__ slot, int *__restrict__ count, int *__restrict__ flags,
                                              double *__restrict__ partial) {
   __shared__ double red[256];
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const int64_t hi = off[cfg + 1];
+  const int base = cfg * n * n * n;
   double sq = 0.0, sa = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+  for (int64_t i = off[cfg] + int64_t(kb) * blockDim.x + threadIdx.x; i < hi; i += int64_t(K) * blockDim.x) {
     int e[3];
     bool ok = true;
     double gv[3];
@@ -60,7 +66,7 @@ __global__ __launch_bounds__(256) void k_bin(int64_t N, const double *__restrict
       gv[0] = gv[1] = gv[2] = 0.5;
     }
     for (int k = 0; k < 3; ++k) gtmp[k * N + i] = gv[k];
-    const int E = e[0] + n * (e[1] + n * e[2]);
+    const int E = base + e[0] + n * (e[1] + n * e[2]);
     elem[i] = E;
     slot[i] = atomicAdd(count + E, 1);
     sq += ok ? q : 0.0;
@@ -131,12 +137,13 @@ __global__ __launch_bounds__(256) void k_rank(int64_t N, const int *__restrict__
 // ----------------------------------------------------------------- moments
 
 // C[E][a] = sum_{j in E} Q_j u_j^a, a = ax + 2 ay + 4 az (element units).
-__global__ __launch_bounds__(256) void k_moments(int n, int64_t N, const int *__restrict__ start,
+__global__ __launch_bounds__(256) void k_moments(int n, int MT, int64_t N, const int *__restrict__ start,
                                                  const double *__restrict__ sg, const double *__restrict__ sQ,
                                                  double *__restrict__ C) {
   const int M = n * n * n;
-  for (int E = blockIdx.x * blockDim.x + threadIdx.x; E < M; E += gridDim.x * blockDim.x) {
-    const int ex = E % n, ey = (E / n) % n, ez = E / (n * n);
+  for (int E = blockIdx.x * blockDim.x + threadIdx.x; E < MT; E += gridDim.x * blockDim.x) {
+    const int El = E % M;
+    const int ex = El % n, ey = (El / n) % n, ez = El / (n * n);
     double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int s = start[E]; s < start[E + 1]; ++s) {
       const double q = sQ[s];
@@ -242,7 +249,8 @@ __global__ __launch_bounds__(64) void k_pair(int n, int64_t N, const int *__rest
   const int E = blockIdx.x;
   const int tb = start[E], te = start[E + 1];
   if (tb == te) return;  // uniform over the (single-wave) block
-  const int total = build_segments<NSR>(seg, E, n, start, lane, 64);
+  const int M = n * n * n;
+  const int total = build_segments<NSR>(seg, E % M, n, start + (E / M) * M, lane, 64);
   const double nd = double(n);
   // chunk width per pass: 8 while more than 4 targets remain, then 4 or 2,
   // so that sparsely occupied elements do not compute empty target slots
@@ -265,8 +273,9 @@ __global__ __launch_bounds__(64) void k_pair(int n, int64_t N, const int *__rest
 // element, element units) by sum factorisation; then the combined
 // potential (Phi_p + Phi_m) / h, scattered to caller order.
 template <int PO>
-__global__ __launch_bounds__(256) void k_interp(int n, int64_t N, double inv_h, GllBasis bas,
-                                                const double *__restrict__ sg, const double *__restrict__ Wel,
+__global__ __launch_bounds__(256) void k_interp(int n, int64_t N, int nb, const int *__restrict__ off, double inv_h,
+                                                GllBasis bas, const double *__restrict__ sg,
+                                                const double *__restrict__ Wel,
                                                 const double *__restrict__ phip, const int *__restrict__ perm,
                                                 double *__restrict__ phim_s, double *__restrict__ phi_s,
                                                 double *__restrict__ Phi) {
@@ -289,7 +298,7 @@ __global__ __launch_bounds__(256) void k_interp(int n, int64_t N, double inv_h, 
         l[k][a] = v;
       }
     }
-    const size_t E = size_t(e[0]) + size_t(n) * (e[1] + size_t(n) * e[2]);
+    const size_t E = size_t(cfg_of(off, nb, s)) * n * n * n + size_t(e[0]) + size_t(n) * (e[1] + size_t(n) * e[2]);
     const double *w = Wel + E * (Q1 * Q1 * Q1);
     double acc = 0.0;
 #pragma unroll
@@ -312,19 +321,22 @@ __global__ __launch_bounds__(256) void k_interp(int n, int64_t N, double inv_h, 
   }
 }
 
-// Block partials of sum_s Q_s Phi_s.
-__global__ __launch_bounds__(256) void k_energy(int64_t N, const double *__restrict__ sQ, const double *__restrict__ phi_s,
-                                                double *__restrict__ partial) {
+// Per-configuration block partials of sum_s Q_s Phi_s (K blocks per
+// configuration over its sorted slots off[b] .. off[b+1]-1).
+__global__ __launch_bounds__(256) void k_energy(int K, const int *__restrict__ off, const double *__restrict__ sQ,
+                                                const double *__restrict__ phi_s, double *__restrict__ partial) {
   __shared__ double red[256];
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const int64_t hi = off[cfg + 1];
   double acc = 0.0;
-  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < N; s += int64_t(gridDim.x) * blockDim.x)
+  for (int64_t s = off[cfg] + int64_t(kb) * blockDim.x + threadIdx.x; s < hi; s += int64_t(K) * blockDim.x)
     acc += sQ[s] * phi_s[s];
   double t = block_sum_p(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(256) void k_half(const double *__restrict__ in, double *__restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = 0.5 * in[0];
+__global__ __launch_bounds__(256) void k_half(int nb, const double *__restrict__ in, double *__restrict__ out) {
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) out[b] = 0.5 * in[b];
 }
 
 // out[perm[s]] = scale * in[s]
@@ -336,18 +348,19 @@ __global__ __launch_bounds__(256) void k_unpermute(int64_t N, double scale, cons
 
 // Ordered near pairs: sum_E count_E * (sum over the block of counts) - N.
 template <int NSR>
-__global__ __launch_bounds__(256) void k_pair_count(int n, const int *__restrict__ start,
+__global__ __launch_bounds__(256) void k_pair_count(int n, int MT, const int *__restrict__ start,
                                                     unsigned long long *__restrict__ out) {
   const int M = n * n * n;
-  for (int E = blockIdx.x * blockDim.x + threadIdx.x; E < M; E += gridDim.x * blockDim.x) {
+  for (int E = blockIdx.x * blockDim.x + threadIdx.x; E < MT; E += gridDim.x * blockDim.x) {
     const int c = start[E + 1] - start[E];
     if (c == 0) continue;
-    const int ex = E % n, ey = (E / n) % n, ez = E / (n * n);
+    const int base = (E / M) * M, El = E % M;
+    const int ex = El % n, ey = (El / n) % n, ez = El / (n * n);
     long long s = 0;
     for (int dz = -NSR; dz <= NSR; ++dz)
       for (int dy = -NSR; dy <= NSR; ++dy)
         for (int dx = -NSR; dx <= NSR; ++dx) {
-          const int F = (ex + dx + n) % n + n * ((ey + dy + n) % n + n * ((ez + dz + n) % n));
+          const int F = base + (ex + dx + n) % n + n * ((ey + dy + n) % n + n * ((ez + dz + n) % n));
           s += start[F + 1] - start[F];
         }
     atomicAdd(out, (unsigned long long)(c * s - c));
@@ -364,11 +377,14 @@ inline int grid_n(int64_t n, int maxb = 4096) {
 }
 }  // namespace
 
-int bin_grid(int64_t N) { return grid_n(N, kRedBlocks); }
+int bin_grid(int64_t N, int nb) { return seg_blocks(nb, size_t((N + nb - 1) / nb)); }
 
-void launch_bin(hipStream_t s, int64_t N, const double *x, const double *Q, double L, int n, double *gtmp, int *elem,
-                int *slot, int *count, int *flags, double *partial) {
-  hipLaunchKernelGGL(k_bin, dim3(bin_grid(N)), dim3(256), 0, s, N, x, Q, L, n, gtmp, elem, slot, count, flags, partial);
+int launch_bin(hipStream_t s, int nb, const int *off, int64_t N, const double *x, const double *Q, double L, int n,
+               double *gtmp, int *elem, int *slot, int *count, int *flags, double *partial) {
+  const int K = bin_grid(N, nb);
+  hipLaunchKernelGGL(k_bin, dim3(nb * K), dim3(256), 0, s, N, K, off, x, Q, L, n, gtmp, elem, slot, count, flags,
+                     partial);
+  return K;
 }
 void launch_scan(hipStream_t s, int M, const int *count, int *start, int *maxcount) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, M, count, start, maxcount);
@@ -380,49 +396,55 @@ void launch_rank(hipStream_t s, int64_t N, const int *tmp, const int *elem, cons
                  const double *Q, int *perm, double *sg, double *sQ) {
   hipLaunchKernelGGL(k_rank, dim3(grid_n(N)), dim3(256), 0, s, N, tmp, elem, start, gtmp, Q, perm, sg, sQ);
 }
-void launch_moments(hipStream_t s, int n, int64_t N, const int *start, const double *sg, const double *sQ, double *C) {
-  hipLaunchKernelGGL(k_moments, dim3(grid_n(int64_t(n) * n * n)), dim3(256), 0, s, n, N, start, sg, sQ, C);
+void launch_moments(hipStream_t s, int nb, int n, int64_t N, const int *start, const double *sg, const double *sQ,
+                    double *C) {
+  const int MT = nb * n * n * n;
+  hipLaunchKernelGGL(k_moments, dim3(grid_n(MT)), dim3(256), 0, s, n, MT, N, start, sg, sQ, C);
 }
 template <int NSR>
-static void pair_impl(hipStream_t s, int n, int64_t N, const int *start, const double *sg, const double *sQ,
+static void pair_impl(hipStream_t s, int nb, int n, int64_t N, const int *start, const double *sg, const double *sQ,
                       double *phip, double *fpair) {
-  dim3 g(n * n * n);
+  dim3 g(nb * n * n * n);
   if (fpair) hipLaunchKernelGGL((k_pair<NSR, true>), g, dim3(64), 0, s, n, N, start, sg, sQ, phip, fpair);
   else hipLaunchKernelGGL((k_pair<NSR, false>), g, dim3(64), 0, s, n, N, start, sg, sQ, phip, fpair);
 }
-int launch_pair(hipStream_t s, int n, int nsr, int64_t N, const int *start, const double *sg, const double *sQ,
+int launch_pair(hipStream_t s, int nb, int n, int nsr, int64_t N, const int *start, const double *sg, const double *sQ,
                 double *phip, double *fpair) {
   switch (nsr) {
-    case 1: pair_impl<1>(s, n, N, start, sg, sQ, phip, fpair); return 0;
-    case 2: pair_impl<2>(s, n, N, start, sg, sQ, phip, fpair); return 0;
-    case 3: pair_impl<3>(s, n, N, start, sg, sQ, phip, fpair); return 0;
-    case 4: pair_impl<4>(s, n, N, start, sg, sQ, phip, fpair); return 0;
+    case 1: pair_impl<1>(s, nb, n, N, start, sg, sQ, phip, fpair); return 0;
+    case 2: pair_impl<2>(s, nb, n, N, start, sg, sQ, phip, fpair); return 0;
+    case 3: pair_impl<3>(s, nb, n, N, start, sg, sQ, phip, fpair); return 0;
+    case 4: pair_impl<4>(s, nb, n, N, start, sg, sQ, phip, fpair); return 0;
     default: return -1;
   }
 }
-int launch_pair_count(hipStream_t s, int n, int nsr, const int *start, unsigned long long *out) {
-  const int M = n * n * n;
+int launch_pair_count(hipStream_t s, int nb, int n, int nsr, const int *start, unsigned long long *out) {
+  const int MT = nb * n * n * n;
   switch (nsr) {
-    case 1: hipLaunchKernelGGL(k_pair_count<1>, dim3(grid_n(M)), dim3(256), 0, s, n, start, out); return 0;
-    case 2: hipLaunchKernelGGL(k_pair_count<2>, dim3(grid_n(M)), dim3(256), 0, s, n, start, out); return 0;
-    case 3: hipLaunchKernelGGL(k_pair_count<3>, dim3(grid_n(M)), dim3(256), 0, s, n, start, out); return 0;
-    case 4: hipLaunchKernelGGL(k_pair_count<4>, dim3(grid_n(M)), dim3(256), 0, s, n, start, out); return 0;
+    case 1: hipLaunchKernelGGL(k_pair_count<1>, dim3(grid_n(MT)), dim3(256), 0, s, n, MT, start, out); return 0;
+    case 2: hipLaunchKernelGGL(k_pair_count<2>, dim3(grid_n(MT)), dim3(256), 0, s, n, MT, start, out); return 0;
+    case 3: hipLaunchKernelGGL(k_pair_count<3>, dim3(grid_n(MT)), dim3(256), 0, s, n, MT, start, out); return 0;
+    case 4: hipLaunchKernelGGL(k_pair_count<4>, dim3(grid_n(MT)), dim3(256), 0, s, n, MT, start, out); return 0;
     default: return -1;
   }
 }
-int launch_interp(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const double *sg,
-                  const double *Wel, const double *phip, const int *perm, double *phim_s, double *phi_s, double *Phi) {
+int launch_interp(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h, const GllBasis &bas,
+                  const double *sg, const double *Wel, const double *phip, const int *perm, double *phim_s,
+                  double *phi_s, double *Phi) {
   if (p != 5) return -1;
-  hipLaunchKernelGGL(k_interp<5>, dim3(grid_n(N)), dim3(256), 0, s, n, N, inv_h, bas, sg, Wel, phip, perm, phim_s,
-                     phi_s, Phi);
+  hipLaunchKernelGGL(k_interp<5>, dim3(grid_n(N)), dim3(256), 0, s, n, N, nb, off, inv_h, bas, sg, Wel, phip, perm,
+                     phim_s, phi_s, Phi);
   return 0;
 }
-void launch_energy(hipStream_t s, int64_t N, const double *sQ, const double *phi_s, double *partial) {
-  hipLaunchKernelGGL(k_energy, dim3(grid_n(N, kRedBlocks)), dim3(256), 0, s, N, sQ, phi_s, partial);
+int launch_energy(hipStream_t s, int nb, const int *off, int64_t N, const double *sQ, const double *phi_s,
+                  double *partial) {
+  const int K = energy_grid(N, nb);
+  hipLaunchKernelGGL(k_energy, dim3(nb * K), dim3(256), 0, s, K, off, sQ, phi_s, partial);
+  return K;
 }
-int energy_grid(int64_t N) { return grid_n(N, kRedBlocks); }
-void launch_half(hipStream_t s, const double *in, double *out) {
-  hipLaunchKernelGGL(k_half, dim3(1), dim3(64), 0, s, in, out);
+int energy_grid(int64_t N, int nb) { return seg_blocks(nb, size_t((N + nb - 1) / nb)); }
+void launch_half(hipStream_t s, int nb, const double *in, double *out) {
+  hipLaunchKernelGGL(k_half, dim3(1), dim3(256), 0, s, nb, in, out);
 }
 void launch_unpermute(hipStream_t s, int64_t N, double scale, const int *perm, const double *in, double *out) {
   hipLaunchKernelGGL(k_unpermute, dim3(grid_n(N)), dim3(256), 0, s, N, scale, perm, in, out);

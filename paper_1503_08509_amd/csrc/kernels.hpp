@@ -12,78 +12,89 @@ struct GllBasis {
   double w[kMaxP + 1];
 };
 
-// particles (k_particles.hip)
-int bin_grid(int64_t N);
-int energy_grid(int64_t N);
-void launch_bin(hipStream_t s, int64_t N, const double *x, const double *Q, double L, int n, double *gtmp, int *elem,
-                int *slot, int *count, int *flags, double *partial);
+// particles (k_particles.hip).  nb configurations: charges of configuration
+// b are caller (and sorted) indices off[b] .. off[b+1]-1 (off on the device)
+// and fall in elements b n^3 .. (b+1) n^3 - 1.
+int bin_grid(int64_t N, int nb);
+int energy_grid(int64_t N, int nb);
+int launch_bin(hipStream_t s, int nb, const int *off, int64_t N, const double *x, const double *Q, double L, int n,
+               double *gtmp, int *elem, int *slot, int *count, int *flags, double *partial);
 void launch_scan(hipStream_t s, int M, const int *count, int *start, int *maxcount);
 void launch_scatter(hipStream_t s, int64_t N, const int *elem, const int *slot, const int *start, int *tmp);
 void launch_rank(hipStream_t s, int64_t N, const int *tmp, const int *elem, const int *start, const double *gtmp,
                  const double *Q, int *perm, double *sg, double *sQ);
-void launch_moments(hipStream_t s, int n, int64_t N, const int *start, const double *sg, const double *sQ, double *C);
-int launch_pair(hipStream_t s, int n, int nsr, int64_t N, const int *start, const double *sg, const double *sQ,
+void launch_moments(hipStream_t s, int nb, int n, int64_t N, const int *start, const double *sg, const double *sQ,
+                    double *C);
+int launch_pair(hipStream_t s, int nb, int n, int nsr, int64_t N, const int *start, const double *sg, const double *sQ,
                 double *phip, double *fpair);
-int launch_pair_count(hipStream_t s, int n, int nsr, const int *start, unsigned long long *out);
-int launch_interp(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const double *sg,
-                  const double *Wel, const double *phip, const int *perm, double *phim_s, double *phi_s, double *Phi);
-void launch_energy(hipStream_t s, int64_t N, const double *sQ, const double *phi_s, double *partial);
-void launch_half(hipStream_t s, const double *in, double *out);
+int launch_pair_count(hipStream_t s, int nb, int n, int nsr, const int *start, unsigned long long *out);
+int launch_interp(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h, const GllBasis &bas,
+                  const double *sg, const double *Wel, const double *phip, const int *perm, double *phim_s,
+                  double *phi_s, double *Phi);
+int launch_energy(hipStream_t s, int nb, const int *off, int64_t N, const double *sQ, const double *phi_s,
+                  double *partial);
+void launch_half(hipStream_t s, int nb, const double *in, double *out);
 void launch_unpermute(hipStream_t s, int64_t N, double scale, const int *perm, const double *in, double *out);
 
 // mixed precision (k_mixed.hip): float32 local coordinates and charges
 // (su = {ux, uy, uz, Q}), packed elements sel = ex | ey << 10 | ez << 20
 void launch_local_f32(hipStream_t s, int n, int64_t N, const double *sg, const double *sQ, float4 *su, int *sel);
-int launch_pair_f32(hipStream_t s, int n, int nsr, int64_t N, const int *start, const float4 *su, const int *sel,
-                    double *phip, double *fpair);
-int launch_interp_f32(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const float4 *su,
-                      const int *sel, const float *Wel, const double *phip, const int *perm, double *phim_s,
-                      double *phi_s, double *Phi);
+int launch_pair_f32(hipStream_t s, int nb, int n, int nsr, int64_t N, const int *start, const float4 *su,
+                    const int *sel, double *phip, double *fpair);
+int launch_interp_f32(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h,
+                      const GllBasis &bas, const float4 *su, const int *sel, const float *Wel, const double *phip,
+                      const int *perm, double *phim_s, double *phi_s, double *Phi);
 
 // adjoint (k_adjoint.hip)
-int launch_deposit(hipStream_t s, int p, int n, int64_t N, const GllBasis &bas, const int *start, const double *sg,
-                   const double *sQ, double *gE);
-int launch_assemble(hipStream_t s, int p, int n, const double *gE, double *G, double *partial);
-int launch_adj_moments(hipStream_t s, int p, int n, int nsr, const double *gE, const double *Tt, const double *lam,
-                       const double *gw, double *A);
+int launch_deposit(hipStream_t s, int nb, int p, int n, int64_t N, const GllBasis &bas, const int *start,
+                   const double *sg, const double *sQ, double *gE);
+int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, double *G, double *partial);
+int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, const double *gE, const double *Tt,
+                       const double *lam, const double *gw, double *A);
 // W of the forward pass in float64, or float32 on the mixed-precision path
 template <class WT>
-int launch_forces(hipStream_t s, int p, int n, int64_t N, double inv_h, const GllBasis &bas, const double *sg,
-                  const double *sQ, const WT *Wel, const double *A, const double *fpair, const double *phip,
-                  const double *phim_s, const int *perm, double *F, double *dUdQ);
+int launch_forces(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h, const GllBasis &bas,
+                  const double *sg, const double *sQ, const WT *Wel, const double *A, const double *fpair,
+                  const double *phip, const double *phim_s, const int *perm, double *F, double *dUdQ);
 
 // near field (k_near.hip)
 // T = double, or float (float32 tables, compensated slab sums, float32 W)
 template <class T>
-int launch_psi(hipStream_t s, int n, int nsr, int p, const double *C, const T *Tab, const double *phi, T *Wel);
+int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, const double *C, const T *Tab, const double *phi, T *Wel);
 
-// mesh (k_mesh.hip)
+// mesh (k_mesh.hip).  nb configurations; per-configuration reductions
+// write nb * K block partials (K = seg_blocks(nb, per) unless a launcher
+// returns its own K) that launch_sum_partials folds into out[0 .. nb).
 int red_grid(size_t n);
-void launch_load(hipStream_t s, int n, int p, const double *C, const double *gw, double *b, double *partial);
-void launch_sum_partials(hipStream_t s, int count, const double *partial, double *out);
-void launch_sub_mass_ones(hipStream_t s, int n, int p, const double *w1, const double *scal, double *v);
-void launch_mass_dot(hipStream_t s, int n, int p, const double *w1, const double *v, double *partial);
-void launch_sub_const(hipStream_t s, size_t total, double invV, const double *scal, double *v);
+int seg_blocks(int nb, size_t per);
+void launch_load(hipStream_t s, int nb, int n, int p, const double *C, const double *gw, double *b, double *partial);
+void launch_sum_partials(hipStream_t s, int K, const double *partial, double *out, int nb = 1);
+void launch_sub_mass_ones(hipStream_t s, int nb, int n, int p, const double *w1, const double *scal, double *v);
+void launch_mass_dot(hipStream_t s, int nb, int n, int p, const double *w1, const double *v, double *partial);
+void launch_sub_const(hipStream_t s, int nb, size_t per, double invV, const double *scal, double *v);
 // Multigrid kernels in the arithmetic type T (double, or float for the
 // mixed-precision preconditioner); instantiated for both in k_mesh.hip.
+// launch_apply returns its blocks per configuration (the K of kApplyDot).
 template <class T>
-int launch_apply(hipStream_t s, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *xprev, T *xo, T c1,
-                 T c2, int mode, double *partial);
+int launch_apply(hipStream_t s, int nb, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *xprev, T *xo,
+                 T c1, T c2, int mode, double *partial);
 int apply_blocks(const LevelOp &op);
 template <class T>
-void launch_cheb_first(hipStream_t s, const LevelOpT<T> &op, const T *f, T *x, T c2);
+void launch_cheb_first(hipStream_t s, int nb, const LevelOpT<T> &op, const T *f, T *x, T c2);
 template <class T>
-int launch_transfer(hipStream_t s, const TransferT<T> &tr, const T *in, T *out, bool restrict_);
+int launch_transfer(hipStream_t s, int nb, const TransferT<T> &tr, const T *in, T *out, bool restrict_);
 template <class T>
-void launch_coarse_solve(hipStream_t s, int Pn, const double *V, const double *lam, const T *f, T *x);
+void launch_coarse_solve(hipStream_t s, int nb, int Pn, const double *V, const double *lam, const T *f, T *x);
 void launch_to_f32(hipStream_t s, size_t n, const double *a, float *b);
-// partial[0, kRedBlocks): block sums of z.r; partial[kRedBlocks, 2 kRedBlocks): z.q (0 if q is null)
-void launch_dot2_f32(hipStream_t s, size_t n, const float *z, const double *r, const double *q, double *partial);
-void launch_xpay_f32(hipStream_t s, size_t n, double beta, const float *z, double *p);
-void launch_dot(hipStream_t s, size_t n, const double *a, const double *b, double *partial);
-void launch_cg_update(hipStream_t s, size_t n, double alpha, const double *p, const double *q, double *x, double *r,
-                      double *partial);
-void launch_xpay(hipStream_t s, size_t n, double beta, const double *z, double *p);
+// partial[0, nb K): block sums of z.r; partial[nb K, 2 nb K): z.q (0 if q is null); returns K
+int launch_dot2_f32(hipStream_t s, int nb, size_t per, const float *z, const double *r, const double *q,
+                    double *partial);
+void launch_xpay_f32(hipStream_t s, int nb, size_t per, const double *betas, const float *z, double *p);
+void launch_pcg_scalars(hipStream_t s, int nb, int step, double rtol, const PcgScalars &sc);
+int launch_dot(hipStream_t s, int nb, size_t per, const double *a, const double *b, double *partial);
+int launch_cg_update(hipStream_t s, int nb, size_t per, const double *alphas, const double *p, const double *q,
+                     double *x, double *r, double *partial);
+void launch_xpay(hipStream_t s, int nb, size_t per, const double *betas, const double *z, double *p);
 void launch_scale(hipStream_t s, size_t n, double sc, const double *a, double *b);
 void launch_hash_fill(hipStream_t s, size_t n, uint32_t seed, double *v);
 

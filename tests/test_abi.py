@@ -72,6 +72,21 @@ def test_unsupported_degree_is_reported():
     assert fp.lib().fep3m_create(1.0, 100, d, 4, ctypes.byref(h)) == fp.ERR_UNSUPPORTED
 
 
+def test_create_batch_rejects_bad_arguments():
+    L = fp.lib()
+    d = (ctypes.c_int32 * 3)(8, 8, 8)
+    h = ctypes.c_void_p()
+    good = (ctypes.c_int64 * 2)(10, 20)
+    assert L.fep3m_create_batch(1.0, 0, good, d, 3, None, ctypes.byref(h)) == fp.ERR_ARG
+    assert L.fep3m_create_batch(1.0, 2, None, d, 3, None, ctypes.byref(h)) == fp.ERR_ARG
+    assert L.fep3m_create_batch(1.0, 2, (ctypes.c_int64 * 2)(10, 1), d, 3, None, ctypes.byref(h)) == fp.ERR_ARG
+    assert L.fep3m_create_batch(1.0, 1025, (ctypes.c_int64 * 1025)(*([10] * 1025)), d, 3, None,
+                                ctypes.byref(h)) == fp.ERR_ARG
+    big = (ctypes.c_int32 * 3)(512, 512, 512)     # 3 x 512^3 elements exceed 2^28
+    assert L.fep3m_create_batch(1.0, 3, (ctypes.c_int64 * 3)(10, 20, 30), big, 3, None, ctypes.byref(h)) == fp.ERR_ARG
+    assert h.value is None
+
+
 def test_null_context_calls():
     L = fp.lib()
     assert L.fep3m_potential(None, None, None, None) == fp.ERR_ARG

@@ -1,0 +1,123 @@
+"""Batched evaluation: many independent configurations of uneven N in one
+context (every kernel launch covers all of them).  Each configuration of a
+batch must reproduce its own single-configuration evaluation, and the
+oracle."""
+import numpy as np
+import pytest
+
+import paper_1503_08509_amd as fp
+import workloads
+from oracle import adjoint, fep3m
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available()
+    return _t
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _uneven(seed, counts):
+    rng = np.random.default_rng(seed)
+    xs, Qs = [], []
+    for N in counts:
+        x = rng.random((N, 3))
+        Q = rng.uniform(-1, 1, N)
+        Q -= Q.mean()
+        xs.append(x)
+        Qs.append(Q)
+    return xs, Qs
+
+
+@pytest.mark.parametrize("precision", [fp.PRECISION_FP64, fp.PRECISION_MIXED])
+def test_batch_matches_single_configurations(torch, precision):
+    counts = [300, 17, 1000, 2, 64]
+    xs, Qs = _uneven(5, counts)
+    n = 8
+    bctx = fp.Context(1.0, counts, n, mg_rtol=1e-12, precision=precision)
+    tx = torch.from_numpy(np.concatenate(xs)).cuda()
+    tQ = torch.from_numpy(np.concatenate(Qs)).cuda()
+    out = bctx.energy_forces(tx, tQ, dUdQ=True, Phi=True)
+    assert tuple(out["U"].shape) == (len(counts),)
+    off = bctx.offsets
+    for b, N in enumerate(counts):
+        ctx = fp.Context(1.0, N, n, mg_rtol=1e-12, precision=precision)
+        ref = ctx.energy_forces(torch.from_numpy(xs[b]).cuda(), torch.from_numpy(Qs[b]).cuda(), dUdQ=True, Phi=True)
+        sl = slice(off[b], off[b + 1])
+        for k in ("Phi", "F", "dUdQ"):
+            assert _rel(out[k][sl].cpu().numpy(), ref[k].cpu().numpy()) < 1e-10, (b, k)
+        assert abs(float(out["U"][b]) - float(ref["U"])) < 1e-10 * abs(float(ref["U"])), b
+
+
+def test_batch_against_oracle(torch):
+    counts = [200, 50, 120]
+    xs, Qs = _uneven(6, counts)
+    n = 8
+    bctx = fp.Context(1.0, counts, n, mg_rtol=1e-13)
+    out = bctx.energy_forces(torch.from_numpy(np.concatenate(xs)).cuda(),
+                             torch.from_numpy(np.concatenate(Qs)).cuda(), dUdQ=True, Phi=True)
+    off = bctx.offsets
+    for b in range(len(counts)):
+        ref = adjoint.energy_forces(xs[b], Qs[b], fep3m.Params(L=1.0, n=n))
+        sl = slice(off[b], off[b + 1])
+        assert _rel(out["Phi"][sl].cpu().numpy(), ref["Phi"]) < 1e-10
+        assert _rel(out["F"][sl].cpu().numpy(), ref["F"]) < 1e-9
+        assert _rel(out["dUdQ"][sl].cpu().numpy(), ref["dUdQ"]) < 1e-9
+        assert abs(float(out["U"][b]) - ref["U"]) < 1e-10 * abs(ref["U"])
+
+
+def test_batch_64_configurations_sampled(torch):
+    """64 configurations, N log-uniform in [2000, 64000], 16^3 each, default
+    tolerance: a sample of configurations against single-configuration runs
+    and the whole batch's pair count against the per-configuration sums."""
+    xs, Qs = workloads.batch()
+    counts = [len(q) for q in Qs]
+    bctx = fp.Context(1.0, counts, 16)
+    out = bctx.energy_forces(torch.from_numpy(np.concatenate(xs)).cuda(),
+                             torch.from_numpy(np.concatenate(Qs)).cuda(), Phi=True)
+    off = bctx.offsets
+    pairs = 0
+    for b in range(len(counts)):
+        ctx = fp.Context(1.0, counts[b], 16)
+        if b % 9 == 0:
+            ref = ctx.energy_forces(torch.from_numpy(xs[b]).cuda(), torch.from_numpy(Qs[b]).cuda(), Phi=True)
+            sl = slice(off[b], off[b + 1])
+            assert _rel(out["Phi"][sl].cpu().numpy(), ref["Phi"].cpu().numpy()) < 1e-6
+            assert _rel(out["F"][sl].cpu().numpy(), ref["F"].cpu().numpy()) < 1e-6
+        else:
+            ctx.potential(torch.from_numpy(xs[b]).cuda(), torch.from_numpy(Qs[b]).cuda())
+        pairs += ctx.stats()["near_pairs"]
+        ctx.close()
+    assert bctx.stats()["near_pairs"] == pairs
+
+
+def test_batch_neutrality_is_per_configuration(torch):
+    counts = [10, 12]
+    xs, Qs = _uneven(7, counts)
+    Qs[0] = Qs[0] + 0.1          # configuration 0 charged, configuration 1 neutral ...
+    Qs[1] = Qs[1] - 10 * 0.1 / 12  # ... while the batch as a whole is neutral
+    bctx = fp.Context(1.0, counts, 8)
+    with pytest.raises(fp.FEP3MError) as ei:
+        bctx.potential(torch.from_numpy(np.concatenate(xs)).cuda(), torch.from_numpy(np.concatenate(Qs)).cuda())
+    assert ei.value.status == fp.ERR_NOT_NEUTRAL
+
+
+def test_batch_autograd(torch):
+    counts = [40, 25]
+    xs, Qs = _uneven(8, counts)
+    bctx = fp.Context(1.0, counts, 8)
+    tx = torch.from_numpy(np.concatenate(xs)).cuda().requires_grad_(True)
+    tQ = torch.from_numpy(np.concatenate(Qs)).cuda().requires_grad_(True)
+    U = fp.FEP3MEnergy.apply(tx, tQ, bctx)
+    w = torch.tensor([1.5, -2.0], dtype=torch.float64, device="cuda")
+    (U * w).sum().backward()
+    ref = bctx.energy_forces(tx.detach(), tQ.detach(), dUdQ=True)
+    scale = np.repeat([1.5, -2.0], counts)
+    np.testing.assert_allclose(tx.grad.cpu().numpy(), -ref["F"].cpu().numpy() * scale[:, None], rtol=0, atol=0)
+    np.testing.assert_allclose(tQ.grad.cpu().numpy(), ref["dUdQ"].cpu().numpy() * scale, rtol=0, atol=0)
