@@ -81,6 +81,12 @@ typedef struct {
   int32_t cheb_degree;   /* Chebyshev smoothing degree per V-cycle side (3)      */
   int32_t table_box;     /* elements per axis of the table domain, odd,
                             > 2 n_sr + 1 (default 2 n_sr + 9)                    */
+  int32_t autotune;      /* 1 (default): the first evaluation times the pair
+                            sum's work decompositions (one wave per element;
+                            persistent waves over a queue of target chunks of
+                            several sizes and grid sizes) and keeps the
+                            fastest; 0: one wave per element.  Every variant
+                            gives bit-identical results.                        */
 } fep3m_options;
 
 typedef struct {
@@ -94,6 +100,12 @@ typedef struct {
   int64_t generation;        /* successful potential/energy/energy_forces calls
                                 on this context; names the state fep3m_backward
                                 reuses                                            */
+  int32_t pair_variant;      /* pair-sum decomposition in use: 0 one wave per
+                                element, 1 persistent waves over a work queue     */
+  int32_t pair_item_targets; /* targets per work item (variant 1)                 */
+  int32_t pair_waves;        /* persistent waves launched (variant 1)             */
+  double  tune_ms_best;      /* device time of the chosen variant when tuned      */
+  double  tune_ms_default;   /* device time of one wave per element when tuned    */
 } fep3m_stats;
 
 /* Profile slots: stages of one call, the fine-level operator launches, and

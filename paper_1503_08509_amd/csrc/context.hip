@@ -145,6 +145,17 @@ struct fep3m_ctx {
   double *coarseV = nullptr, *coarseLam = nullptr;
   int coarseP = 0;
   double *b = nullptr, *sol = nullptr, *rr = nullptr, *pv = nullptr, *qv = nullptr;
+  // pair-sum work decomposition (autotuned): kind 0 one wave per element,
+  // kind 1 persistent waves over items of `titem` targets
+  struct PairPlan {
+    int kind = 0, titem = 0, waves = 0;
+  };
+  PairPlan plan;
+  bool tuned = false;
+  int items_titem = -1;         // item size the current work list was built for
+  int cus = 256;                // compute units of the device
+  int *nit = nullptr, *item_start = nullptr, *icounter = nullptr, *iscan_max = nullptr;
+  int2 *items = nullptr;
   // adjoint
   double *gE = nullptr, *Gv = nullptr, *lam = nullptr, *Aadj = nullptr, *fpair = nullptr, *Phi_int = nullptr;
 
@@ -198,6 +209,8 @@ struct fep3m_ctx {
   void profile_collect();
   void forward(const double *x, const double *Q, double *Phi, double *U, bool pair_forces);
   void pair_pass(bool pair_forces);
+  int pair_launch(const PairPlan &pl, bool pair_forces);
+  void tune_pairs(bool pair_forces);
   void reverse(double *F, double *dUdQ);
   void finish(bool count_pairs);
   void backward(int64_t gen, double *F, double *dUdQ);
@@ -302,6 +315,18 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
     Welf = alloc<float>(size_t(nb) * M * (p + 1) * (p + 1) * (p + 1), "element field (f32)");
     su = alloc<float4>(size_t(N), "local coordinates (f32)");
     sel = alloc<int>(size_t(N), "packed elements");
+  }
+  nit = alloc<int>(size_t(nb) * M + 1, "items per element");
+  item_start = alloc<int>(size_t(nb) * M + 1, "item starts");
+  items = alloc<int2>(size_t(N), "pair work items");
+  icounter = alloc<int>(4, "item counter");
+  iscan_max = alloc<int>(4, "item scan max");
+  {
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "device");
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, dev), "device properties");
+    cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   }
   phip_s = alloc<double>(size_t(N), "pair potential");
   phim_s = alloc<double>(size_t(N), "mesh potential");
@@ -620,6 +645,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   launch_scan(stream, MT, count, start, maxcount);
   launch_scatter(stream, N, elem, slot, start, tmp);
   launch_rank(stream, N, tmp, elem, start, gtmp, Qc, perm, sg, sQ);
+  items_titem = -1;   // the pair work list follows this call's element starts
   if (mixed) launch_local_f32(stream, n, N, sg, sQ, su, sel);
   stage_mark(FEP3M_PROF_SORT, false);
   stage_mark(FEP3M_PROF_ASSIGN, true);
@@ -652,14 +678,66 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   stage_mark(FEP3M_PROF_INTERP, false);
 }
 
-void fep3m_ctx::pair_pass(bool pair_forces) {
-  stage_mark(FEP3M_PROF_PAIR, true);
+int fep3m_ctx::pair_launch(const PairPlan &pl, bool pair_forces) {
   double *fp = pair_forces ? fpair : nullptr;
-  const int st = mixed ? launch_pair_f32(stream, nb, n, nsr, N, start, su, sel, phip_s, fp)
-                       : launch_pair(stream, nb, n, nsr, N, start, sg, sQ, phip_s, fp);
-  if (st != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "pair variant");
+  if (pl.kind == 0)
+    return mixed ? launch_pair_f32(stream, nb, n, nsr, N, start, su, sel, phip_s, fp)
+                 : launch_pair(stream, nb, n, nsr, N, start, sg, sQ, phip_s, fp);
+  const int MT = nb * n * n * n;
+  if (items_titem != pl.titem) {
+    launch_items(stream, MT, pl.titem, start, nit, item_start, iscan_max, items);
+    items_titem = pl.titem;
+  }
+  return mixed ? launch_pair_queue_f32(stream, pl.waves, n, nsr, N, start, items, item_start + MT, icounter, pl.titem,
+                                       su, sel, phip_s, fp)
+               : launch_pair_queue(stream, pl.waves, n, nsr, N, start, items, item_start + MT, icounter, pl.titem, sg,
+                                   sQ, phip_s, fp);
+}
+
+// Time each candidate decomposition of the pair sum on this call's data and
+// keep the fastest.  The candidates produce identical results, so the
+// outputs of the last one timed are the call's outputs.
+void fep3m_ctx::tune_pairs(bool pair_forces) {
+  std::vector<PairPlan> cand;
+  cand.push_back(PairPlan{0, 0, 0});
+  for (int titem : {8, 32, 64})
+    for (int per_cu : {16, 32}) cand.push_back(PairPlan{1, titem, per_cu * cus});
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "event");
+  hip_check(hipEventCreate(&e1), "event");
+  double best = 1e300, dflt = 0.0;
+  PairPlan pick = cand[0];
+  for (const PairPlan &pl : cand) {
+    if (pl.kind == 1 && items_titem != pl.titem) {   // list construction is not part of the timing
+      launch_items(stream, nb * n * n * n, pl.titem, start, nit, item_start, iscan_max, items);
+      items_titem = pl.titem;
+    }
+    hip_check(hipEventRecord(e0, stream), "event");
+    if (pair_launch(pl, pair_forces) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "pair variant");
+    hip_check(hipEventRecord(e1, stream), "event");
+    hip_check(hipEventSynchronize(e1), "tuning");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+    if (pl.kind == 0) dflt = ms;
+    if (ms < best) { best = ms; pick = pl; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  plan = pick;
+  tuned = true;
+  stats.tune_ms_best = best;
+  stats.tune_ms_default = dflt;
+}
+
+void fep3m_ctx::pair_pass(bool pair_forces) {
+  if (opt.autotune && !tuned && !prof.on) tune_pairs(pair_forces);
+  stage_mark(FEP3M_PROF_PAIR, true);
+  if (pair_launch(plan, pair_forces) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "pair variant");
   prof.pair_forces = pair_forces;
   stage_mark(FEP3M_PROF_PAIR, false);
+  stats.pair_variant = plan.kind;
+  stats.pair_item_targets = plan.titem;
+  stats.pair_waves = plan.waves;
 }
 
 // Reverse pass over the state the forward pass left in the context: deposit,
@@ -791,6 +869,7 @@ bool valid_options(const fep3m_options &o, std::string &why) {
   if (!(o.mg_rtol > 0.0) || !(o.mg_rtol < 1.0)) { why = "mg_rtol must be in (0, 1)"; return false; }
   if (o.mg_max_iter < 1 || o.mg_max_iter > 1000) { why = "mg_max_iter must be 1..1000"; return false; }
   if (o.cheb_degree < 1 || o.cheb_degree > 10) { why = "cheb_degree must be 1..10"; return false; }
+  if (o.autotune != 0 && o.autotune != 1) { why = "autotune must be 0 or 1"; return false; }
   if (o.table_box % 2 == 0 || o.table_box < 2 * o.n_sr + 3 || o.table_box > 41) {
     why = "table_box must be odd, > 2 n_sr + 1 and <= 41";
     return false;
@@ -810,6 +889,7 @@ int fep3m_default_options(fep3m_options *opt) {
   opt->mg_max_iter = 60;
   opt->cheb_degree = 3;
   opt->table_box = 2 * 3 + 9;
+  opt->autotune = 1;
   return FEP3M_OK;
 }
 

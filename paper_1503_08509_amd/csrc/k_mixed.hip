@@ -143,6 +143,44 @@ __global__ __launch_bounds__(64) void k_pair_f32(int n, int64_t N, const int *__
   }
 }
 
+// Load-balanced form over the work items of k_pair_queue (same items).
+template <int NSR, bool FORCE>
+__global__ __launch_bounds__(64) void k_pair_queue_f32(int n, int64_t N, const int *__restrict__ start,
+                                                       const int2 *__restrict__ items, const int *__restrict__ nitems,
+                                                       int *__restrict__ counter, int titem,
+                                                       const float4 *__restrict__ su, const int *__restrict__ sel,
+                                                       double *__restrict__ phip, double *__restrict__ fpair) {
+  __shared__ PairSegments<NSR> seg;
+  __shared__ int cur;
+  const int lane = threadIdx.x;
+  const int total_items = *nitems;
+  const int M = n * n * n;
+  for (;;) {
+    if (lane == 0) cur = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = cur;
+    if (it >= total_items) break;   // uniform over the wave
+    const int2 w = items[it];
+    const int E = w.x, El = E % M, te = min(w.y + titem, start[E + 1]);
+    const int total = build_segments<NSR>(seg, El, n, start + (E / M) * M, lane, 64);
+    const int ex = El % n, ey = (El / n) % n, ez = El / (n * n);
+    for (int t0 = w.y; t0 < te;) {
+      const int rem = te - t0;
+      if (rem > 4) {
+        pair_chunk_f32<NSR, FORCE, 8>(seg, total, lane, N, t0, min(rem, 8), n, ex, ey, ez, su, sel, phip, fpair);
+        t0 += 8;
+      } else if (rem > 2) {
+        pair_chunk_f32<NSR, FORCE, 4>(seg, total, lane, N, t0, rem, n, ex, ey, ez, su, sel, phip, fpair);
+        t0 += 4;
+      } else {
+        pair_chunk_f32<NSR, FORCE, 2>(seg, total, lane, N, t0, rem, n, ex, ey, ez, su, sel, phip, fpair);
+        t0 += 2;
+      }
+    }
+    __syncthreads();   // the segment list and cur are rewritten for the next item
+  }
+}
+
 // Phi_m at each sorted charge from the float32 W of its element by sum
 // factorisation in float32 (the outer sum compensated), combined with the
 // pair term in float64 and scattered to caller order.
@@ -225,6 +263,31 @@ int launch_pair_f32(hipStream_t s, int nb, int n, int nsr, int64_t N, const int 
     case 2: pair_f32_impl<2>(s, nb, n, N, start, su, sel, phip, fpair); return 0;
     case 3: pair_f32_impl<3>(s, nb, n, N, start, su, sel, phip, fpair); return 0;
     case 4: pair_f32_impl<4>(s, nb, n, N, start, su, sel, phip, fpair); return 0;
+    default: return -1;
+  }
+}
+
+template <int NSR>
+static void pair_queue_f32_impl(hipStream_t s, int waves, int n, int64_t N, const int *start, const int2 *items,
+                                const int *nitems, int *counter, int titem, const float4 *su, const int *sel,
+                                double *phip, double *fpair) {
+  if (fpair)
+    hipLaunchKernelGGL((k_pair_queue_f32<NSR, true>), dim3(waves), dim3(64), 0, s, n, N, start, items, nitems,
+                       counter, titem, su, sel, phip, fpair);
+  else
+    hipLaunchKernelGGL((k_pair_queue_f32<NSR, false>), dim3(waves), dim3(64), 0, s, n, N, start, items, nitems,
+                       counter, titem, su, sel, phip, fpair);
+}
+int launch_pair_queue_f32(hipStream_t s, int waves, int n, int nsr, int64_t N, const int *start, const int2 *items,
+                          const int *nitems, int *counter, int titem, const float4 *su, const int *sel, double *phip,
+                          double *fpair) {
+  if (n > 1024) return -1;
+  launch_fill_int(s, 1, 0, counter);
+  switch (nsr) {
+    case 1: pair_queue_f32_impl<1>(s, waves, n, N, start, items, nitems, counter, titem, su, sel, phip, fpair); return 0;
+    case 2: pair_queue_f32_impl<2>(s, waves, n, N, start, items, nitems, counter, titem, su, sel, phip, fpair); return 0;
+    case 3: pair_queue_f32_impl<3>(s, waves, n, N, start, items, nitems, counter, titem, su, sel, phip, fpair); return 0;
+    case 4: pair_queue_f32_impl<4>(s, waves, n, N, start, items, nitems, counter, titem, su, sel, phip, fpair); return 0;
     default: return -1;
   }
 }

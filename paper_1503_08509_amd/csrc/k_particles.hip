@@ -269,6 +269,64 @@ __global__ __launch_bounds__(64) void k_pair(int n, int64_t N, const int *__rest
   }
 }
 
+// Load-balanced form: work items (element, first target) of up to `titem`
+// targets each, taken from a shared counter by persistent one-wave blocks
+// until the list is exhausted (every wave reaches the exit test).  Heavy
+// elements split into several items; per-target arithmetic is the same as
+// in k_pair, so the results are identical.
+__global__ __launch_bounds__(256) void k_items_count(int MT, int titem, const int *__restrict__ start,
+                                                     int *__restrict__ nit) {
+  for (int E = blockIdx.x * blockDim.x + threadIdx.x; E < MT; E += gridDim.x * blockDim.x)
+    nit[E] = (start[E + 1] - start[E] + titem - 1) / titem;
+}
+__global__ __launch_bounds__(256) void k_items_fill(int MT, int titem, const int *__restrict__ start,
+                                                    const int *__restrict__ item_start, int2 *__restrict__ items) {
+  for (int E = blockIdx.x * blockDim.x + threadIdx.x; E < MT; E += gridDim.x * blockDim.x) {
+    const int b = item_start[E], k = item_start[E + 1] - b;
+    for (int j = 0; j < k; ++j) items[b + j] = make_int2(E, start[E] + j * titem);
+  }
+}
+__global__ __launch_bounds__(64) void k_fill_int(int count, int value, int *__restrict__ p) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = value;
+}
+
+template <int NSR, bool FORCE>
+__global__ __launch_bounds__(64) void k_pair_queue(int n, int64_t N, const int *__restrict__ start,
+                                                   const int2 *__restrict__ items, const int *__restrict__ nitems,
+                                                   int *__restrict__ counter, int titem,
+                                                   const double *__restrict__ sg, const double *__restrict__ sQ,
+                                                   double *__restrict__ phip, double *__restrict__ fpair) {
+  __shared__ PairSegments<NSR> seg;
+  __shared__ int cur;
+  const int lane = threadIdx.x;
+  const int total_items = *nitems;
+  const int M = n * n * n;
+  const double nd = double(n);
+  for (;;) {
+    if (lane == 0) cur = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = cur;
+    if (it >= total_items) break;   // uniform over the wave
+    const int2 w = items[it];
+    const int E = w.x, te = min(w.y + titem, start[E + 1]);
+    const int total = build_segments<NSR>(seg, E % M, n, start + (E / M) * M, lane, 64);
+    for (int t0 = w.y; t0 < te;) {
+      const int rem = te - t0;
+      if (rem > 4) {
+        pair_chunk<NSR, FORCE, 8>(seg, total, lane, N, t0, min(rem, 8), nd, sg, sQ, phip, fpair);
+        t0 += 8;
+      } else if (rem > 2) {
+        pair_chunk<NSR, FORCE, 4>(seg, total, lane, N, t0, rem, nd, sg, sQ, phip, fpair);
+        t0 += 4;
+      } else {
+        pair_chunk<NSR, FORCE, 2>(seg, total, lane, N, t0, rem, nd, sg, sQ, phip, fpair);
+        t0 += 2;
+      }
+    }
+    __syncthreads();   // the segment list and cur are rewritten for the next item
+  }
+}
+
 // Phi_m at each sorted charge: sum_m W_E[m] u_m(u_i) (W = phi - Psi of its
 // element, element units) by sum factorisation; then the combined
 // potential (Phi_p + Phi_m) / h, scattered to caller order.
@@ -415,6 +473,42 @@ int launch_pair(hipStream_t s, int nb, int n, int nsr, int64_t N, const int *sta
     case 2: pair_impl<2>(s, nb, n, N, start, sg, sQ, phip, fpair); return 0;
     case 3: pair_impl<3>(s, nb, n, N, start, sg, sQ, phip, fpair); return 0;
     case 4: pair_impl<4>(s, nb, n, N, start, sg, sQ, phip, fpair); return 0;
+    default: return -1;
+  }
+}
+// Work list of items of up to `titem` targets; nit (MT + 1 ints) and
+// item_start (MT + 1 ints) are scratch, items holds up to N entries, and
+// item_start[MT] receives the item count.
+void launch_items(hipStream_t s, int MT, int titem, const int *start, int *nit, int *item_start, int *scan_max,
+                  int2 *items) {
+  hipLaunchKernelGGL(k_items_count, dim3(grid_n(MT)), dim3(256), 0, s, MT, titem, start, nit);
+  launch_scan(s, MT, nit, item_start, scan_max);
+  hipLaunchKernelGGL(k_items_fill, dim3(grid_n(MT)), dim3(256), 0, s, MT, titem, start, item_start, items);
+}
+void launch_fill_int(hipStream_t s, int count, int value, int *p) {
+  hipLaunchKernelGGL(k_fill_int, dim3((count + 63) / 64 < 1024 ? (count + 63) / 64 : 1024), dim3(64), 0, s, count,
+                     value, p);
+}
+template <int NSR>
+static void pair_queue_impl(hipStream_t s, int waves, int n, int64_t N, const int *start, const int2 *items,
+                            const int *nitems, int *counter, int titem, const double *sg, const double *sQ,
+                            double *phip, double *fpair) {
+  if (fpair)
+    hipLaunchKernelGGL((k_pair_queue<NSR, true>), dim3(waves), dim3(64), 0, s, n, N, start, items, nitems, counter,
+                       titem, sg, sQ, phip, fpair);
+  else
+    hipLaunchKernelGGL((k_pair_queue<NSR, false>), dim3(waves), dim3(64), 0, s, n, N, start, items, nitems, counter,
+                       titem, sg, sQ, phip, fpair);
+}
+int launch_pair_queue(hipStream_t s, int waves, int n, int nsr, int64_t N, const int *start, const int2 *items,
+                      const int *nitems, int *counter, int titem, const double *sg, const double *sQ, double *phip,
+                      double *fpair) {
+  launch_fill_int(s, 1, 0, counter);
+  switch (nsr) {
+    case 1: pair_queue_impl<1>(s, waves, n, N, start, items, nitems, counter, titem, sg, sQ, phip, fpair); return 0;
+    case 2: pair_queue_impl<2>(s, waves, n, N, start, items, nitems, counter, titem, sg, sQ, phip, fpair); return 0;
+    case 3: pair_queue_impl<3>(s, waves, n, N, start, items, nitems, counter, titem, sg, sQ, phip, fpair); return 0;
+    case 4: pair_queue_impl<4>(s, waves, n, N, start, items, nitems, counter, titem, sg, sQ, phip, fpair); return 0;
     default: return -1;
   }
 }

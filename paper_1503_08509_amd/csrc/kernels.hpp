@@ -28,6 +28,15 @@ void launch_moments(hipStream_t s, int nb, int n, int64_t N, const int *start, c
 int launch_pair(hipStream_t s, int nb, int n, int nsr, int64_t N, const int *start, const double *sg, const double *sQ,
                 double *phip, double *fpair);
 int launch_pair_count(hipStream_t s, int nb, int n, int nsr, const int *start, unsigned long long *out);
+// Load-balanced pair sums: a work list of (element, first target) items of
+// up to titem targets (item_start[MT] = item count; items up to N entries),
+// consumed by `waves` persistent one-wave blocks through *counter.
+void launch_items(hipStream_t s, int MT, int titem, const int *start, int *nit, int *item_start, int *scan_max,
+                  int2 *items);
+void launch_fill_int(hipStream_t s, int count, int value, int *p);
+int launch_pair_queue(hipStream_t s, int waves, int n, int nsr, int64_t N, const int *start, const int2 *items,
+                      const int *nitems, int *counter, int titem, const double *sg, const double *sQ, double *phip,
+                      double *fpair);
 int launch_interp(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h, const GllBasis &bas,
                   const double *sg, const double *Wel, const double *phip, const int *perm, double *phim_s,
                   double *phi_s, double *Phi);
@@ -41,6 +50,9 @@ void launch_unpermute(hipStream_t s, int64_t N, double scale, const int *perm, c
 void launch_local_f32(hipStream_t s, int n, int64_t N, const double *sg, const double *sQ, float4 *su, int *sel);
 int launch_pair_f32(hipStream_t s, int nb, int n, int nsr, int64_t N, const int *start, const float4 *su,
                     const int *sel, double *phip, double *fpair);
+int launch_pair_queue_f32(hipStream_t s, int waves, int n, int nsr, int64_t N, const int *start, const int2 *items,
+                          const int *nitems, int *counter, int titem, const float4 *su, const int *sel, double *phip,
+                          double *fpair);
 int launch_interp_f32(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h,
                       const GllBasis &bas, const float4 *su, const int *sel, const float *Wel, const double *phip,
                       const int *perm, double *phim_s, double *phi_s, double *Phi);
