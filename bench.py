@@ -41,6 +41,8 @@ def parse():
                     help="fp64: float64 throughout; mixed: float32 multigrid preconditioner, near field and "
                          "interpolation with compensated sums, float64 reductions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the mixed-precision, clustered and batched measurements reported beside the FP64 line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 256 MiB (FETCH_SIZE/WRITE_SIZE calibration) and exit")
     return ap.parse_args()
@@ -114,13 +116,179 @@ def cpu_baseline(x, Q, w, sample, F_gpu):
     }
 
 
+BATCH_WORKLOAD = "batch-64-n16"
+
+# Kernel -> (profile summary holding its measured HBM traffic, sources whose
+# hash the summary records).  The summary's figure is used only while those
+# sources are unchanged; otherwise traffic is reported as null.
+TRAFFIC_FILES = {
+    "k_apply p=5 (fine-level operator)": ("k_apply_p5_fp64", ["paper_1503_08509_amd/csrc/k_mesh.hip",
+                                                               "paper_1503_08509_amd/csrc/device_common.hpp"]),
+    "k_adj_moments (transposed near field)": ("k_adj_moments_fp64", ["paper_1503_08509_amd/csrc/k_adjoint.hip",
+                                                                     "paper_1503_08509_amd/csrc/device_common.hpp"]),
+    "k_psi (near-screen field)": ("k_psi_fp64", ["paper_1503_08509_amd/csrc/k_near.hip",
+                                                 "paper_1503_08509_amd/csrc/device_common.hpp"]),
+}
+
+
+def source_hash(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, workload):
+    """Calibrated HBM traffic per launch (GB) of `kernel` on `workload` from
+    profiles/traffic_<tag>_<workload>.txt (FETCH_SIZE and WRITE_SIZE of
+    rocprofv3 --pmc runs scaled by the same counters on a plain copy), or
+    None when no such summary exists or its kernel sources have changed."""
+    if kernel not in TRAFFIC_FILES:
+        return None
+    tag, srcs = TRAFFIC_FILES[kernel]
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != source_hash(srcs):
+        return None
+    try:
+        return float(fields["hbm_gb_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def load_workload(name):
+    """(label, L, counts, n, x, Q): one configuration, or the batch of 64
+    independent 16^3 configurations with N log-uniform in [2000, 64000]."""
+    import numpy as np
+
+    import workloads
+
+    if name == BATCH_WORKLOAD:
+        xs, Qs = workloads.batch()
+        return name, 1.0, [len(q) for q in Qs], 16, np.concatenate(xs), np.concatenate(Qs)
+    w = workloads.WORKLOADS[name]
+    x, Q = workloads.make(w)
+    return name, w.L, [w.N], w.n, x, Q
+
+
+def kernel_rooflines(prof, steps, mixed):
+    def kern(slot, bound):
+        s = prof[slot]
+        if s["count"] == 0 or s["ms"] <= 0:
+            return None
+        sec = s["ms"] * 1e-3
+        if bound == "hbm":
+            ach = s["work"] / sec / 1e9
+            return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": ach / PEAK_HBM_GBS, "traffic": None,
+                    "avg_launch_ms": s["ms"] / s["count"], "launches_per_step": s["count"] / steps}
+        ach = s["work"] / sec / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
+                "avg_launch_ms": s["ms"] / s["count"], "launches_per_step": s["count"] / steps}
+
+    kernels = {"k_psi (near-screen field)": kern("near", "alu"),
+               "k_pair (near-pair sum)": kern("pair", "alu"),
+               "k_apply p=5 (fine-level operator)": kern("fine_apply", "hbm"),
+               "k_adj_moments (transposed near field)": kern("adj_near", "alu")}
+    if mixed:
+        kernels["k_apply<float> p=5 (fine-level preconditioner operator)"] = kern("fine_apply_f32", "hbm")
+    return {k: v for k, v in kernels.items() if v}
+
+
+def measure(name, precision, steps, warmup, forces=True):
+    """Run `warmup` + `steps` evaluations of one workload; device-resident
+    inputs; returns timings, per-stage device times, kernel rooflines, the
+    outputs of the last step (host copies) and the context statistics."""
+    import numpy as np
+    import torch
+
+    import paper_1503_08509_amd as fp
+
+    label, L, counts, n, x, Q = load_workload(name)
+    mixed = precision == "mixed"
+    dev = torch.device("cuda:0")
+    tx = torch.from_numpy(x).to(dev)
+    tQ = torch.from_numpy(Q).to(dev)
+    ctx = fp.Context(L, counts if len(counts) > 1 else counts[0], n,
+                     precision=fp.PRECISION_MIXED if mixed else fp.PRECISION_FP64)
+
+    def step():
+        if forces:
+            return ctx.energy_forces(tx, tQ, Phi=True)
+        Phi_, U_ = ctx.energy(tx, tQ)
+        return {"U": U_, "Phi": Phi_}
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / steps
+    st = ctx.stats()
+    prof = ctx.profile()
+    res = {
+        "workload": label, "precision": precision, "counts": counts, "n": n, "L": L, "ms_per_step": ms,
+        "pairs": st["near_pairs"], "value": st["near_pairs"] / (ms * 1e-3), "stats": st,
+        "kernels": kernel_rooflines(prof, steps, mixed),
+        "stages_ms_per_step": {k: v["ms"] / steps for k, v in prof.items() if not k.startswith("fine_apply")},
+        "out": {k: v.detach().cpu().numpy() for k, v in out.items()},
+        "x": x, "Q": Q, "mg_rtol": ctx.options.mg_rtol,
+    }
+    ctx.close()
+    return res
+
+
+def _rel_rms(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def variant_summary(r, ref=None):
+    import numpy as np
+    k = r["kernels"]
+    dom = max(k, key=lambda s: k[s]["avg_launch_ms"] * k[s]["launches_per_step"])
+    v = {"ms_per_step": r["ms_per_step"], "value": r["value"], "unit": "pair interactions/s",
+         "near_pairs_per_step": r["pairs"], "configurations": len(r["counts"]),
+         "N": int(sum(r["counts"])), "elements": f"{r['n']}^3",
+         "pair_kernel_ms": r["stages_ms_per_step"]["pair"],
+         "pair_interactions_per_s_pair_kernel": r["pairs"] / (r["stages_ms_per_step"]["pair"] * 1e-3),
+         "dominant_kernel": dom, "dominant_frac": k[dom]["frac"], "dominant_bound": k[dom]["bound"],
+         "kernel_fracs": {s: round(k[s]["frac"], 4) for s in k},
+         "mg_iterations": r["stats"]["mg_iterations"], "adj_mg_iterations": r["stats"]["adj_iterations"],
+         "pair_variant": {"kind": "queue" if r["stats"]["pair_variant"] else "element",
+                          "item_targets": r["stats"]["pair_item_targets"], "waves": r["stats"]["pair_waves"],
+                          "tuned_ms": r["stats"]["tune_ms_best"], "element_ms": r["stats"]["tune_ms_default"]}}
+    if ref is not None:
+        v["accuracy_vs_fp64"] = {
+            "Phi_rel_rms": _rel_rms(r["out"]["Phi"], ref["out"]["Phi"]),
+            "F_rel_rms": _rel_rms(r["out"]["F"], ref["out"]["F"]),
+            "U_rel": float(np.abs(r["out"]["U"] - ref["out"]["U"]).max() / np.abs(ref["out"]["U"]).max()),
+        }
+    return v
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    import numpy as np
+    import numpy as np  # noqa: F401
     import torch
 
     if args.copy_calibration:
@@ -131,94 +299,65 @@ def main():
         print(json.dumps({"copy_bytes_each_way": 2**25 * 8, "check": float(c[0].item())}))
         return
 
-    import paper_1503_08509_amd as fp
-    import workloads
-
-    w = workloads.WORKLOADS[args.workload]
-    x, Q = workloads.make(w)
-    dev = torch.device("cuda:0")
-    tx = torch.from_numpy(x).to(dev)
-    tQ = torch.from_numpy(Q).to(dev)
-    mixed = args.precision == "mixed"
-    ctx = fp.Context(w.L, w.N, w.n, precision=fp.PRECISION_MIXED if mixed else fp.PRECISION_FP64)
     forces = args.outputs == "forces"
-
-    def step():
-        if forces:
-            o = ctx.energy_forces(tx, tQ)
-            return o["U"], o["F"]
-        Phi_, U_ = ctx.energy(tx, tQ)
-        return U_, None
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        U, F = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    st = ctx.stats()
-    prof = ctx.profile()
-    pairs = st["near_pairs"]
-
-    def kern(slot, bound):
-        s = prof[slot]
-        if s["count"] == 0 or s["ms"] <= 0:
-            return None
-        sec = s["ms"] * 1e-3
-        if bound == "hbm":
-            ach = s["work"] / sec / 1e9
-            return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": ach / PEAK_HBM_GBS, "traffic": None,
-                    "avg_launch_ms": s["ms"] / s["count"], "launches_per_step": s["count"] / args.steps}
-        ach = s["work"] / sec / 1e12
-        return {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
-                "avg_launch_ms": s["ms"] / s["count"], "launches_per_step": s["count"] / args.steps}
-
-    kernels = {"k_psi (near-screen field)": kern("near", "alu"),
-               "k_pair (near-pair sum)": kern("pair", "alu"),
-               "k_apply p=5 (fine-level operator)": kern("fine_apply", "hbm")}
-    if mixed:
-        kernels["k_apply<float> p=5 (fine-level preconditioner operator)"] = kern("fine_apply_f32", "hbm")
-    if forces:
-        kernels["k_adj_moments (transposed near field)"] = kern("adj_near", "alu")
-    dominant = max(kernels, key=lambda k: (kernels[k]["avg_launch_ms"] * kernels[k]["launches_per_step"])
-                   if kernels[k] else -1)
+    r = measure(args.workload, args.precision, args.steps, args.warmup, forces)
+    mixed = args.precision == "mixed"
+    kernels = r["kernels"]
+    dominant = max(kernels, key=lambda k: kernels[k]["avg_launch_ms"] * kernels[k]["launches_per_step"])
     roof = dict(kernels[dominant])
     roof["kernel"] = dominant
+    roof["traffic"] = traffic_for(dominant, r["workload"]) if not mixed else None
+    roof["traffic_unit"] = "GB per launch (calibrated FETCH_SIZE + WRITE_SIZE)"
+    if roof["bound"] == "hbm":
+        roof["algorithmic_gb_per_launch"] = roof["achieved"] * roof["avg_launch_ms"] * 1e-3
+    st = r["stats"]
     out = {
         "metric": METRIC,
-        "value": pairs / (ms * 1e-3),
+        "value": r["value"],
         "unit": "pair interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "N": w.N, "elements": f"{w.n}^3", "L": w.L, "screen": "one-element q=3",
-                   "mesh_order": 5, "near_block": "7^3", "outputs": "U, F" if forces else "Phi, U",
-                   "precision": args.precision, "mg_rtol": ctx.options.mg_rtol, "near_pairs_per_step": pairs},
+        "config": {"workload": r["workload"], "N": int(sum(r["counts"])), "configurations": len(r["counts"]),
+                   "elements": f"{r['n']}^3", "L": r["L"], "screen": "one-element q=3", "mesh_order": 5,
+                   "near_block": "7^3", "outputs": "U, F" if forces else "Phi, U", "precision": args.precision,
+                   "mg_rtol": r["mg_rtol"], "near_pairs_per_step": r["pairs"]},
         "roofline": roof,
         "kernels": kernels,
-        "stages_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()
-                               if not k.startswith("fine_apply")},
+        "stages_ms_per_step": r["stages_ms_per_step"],
         "mg_iterations": st["mg_iterations"],
         "adj_mg_iterations": st["adj_iterations"] if forces else None,
         "mg_rel_residual": st["mg_rel_residual"],
-        "U": float(U.item()),
+        "pair_variant": variant_summary(r)["pair_variant"],
+        "U": [float(u) for u in np.atleast_1d(r["out"]["U"])][:4],
     }
+    if not args.no_variants and forces and args.workload == "uniform-1M-n64" and not mixed:
+        variants = {}
+        m = measure("uniform-1M-n64", "mixed", 3, 1)
+        variants["mixed uniform-1M-n64"] = variant_summary(m, r)
+        del m
+        c64 = measure("clustered-1M-n64", "fp64", 3, 1)
+        variants["fp64 clustered-1M-n64"] = variant_summary(c64)
+        cm = measure("clustered-1M-n64", "mixed", 3, 1)
+        variants["mixed clustered-1M-n64"] = variant_summary(cm, c64)
+        del c64, cm
+        b64 = measure(BATCH_WORKLOAD, "fp64", 3, 1)
+        variants["fp64 " + BATCH_WORKLOAD] = variant_summary(b64)
+        bm = measure(BATCH_WORKLOAD, "mixed", 3, 1)
+        variants["mixed " + BATCH_WORKLOAD] = variant_summary(bm, b64)
+        del b64, bm
+        out["variants"] = variants
     if not args.no_cpu_baseline:
-        if forces:
-            out["cpu_baseline"] = cpu_baseline(x, Q, w, args.cpu_sample, F.cpu().numpy())
+        if forces and len(r["counts"]) == 1:
+            import workloads
+            out["cpu_baseline"] = cpu_baseline(r["x"], r["Q"], workloads.WORKLOADS[r["workload"]], args.cpu_sample,
+                                               r["out"]["F"])
         else:
             out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -72,6 +72,16 @@ __device__ __forceinline__ int cfg_of(const int *__restrict__ off, int nb, int64
   return lo;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  For a grid of `total` blocks walking a linear (x fastest) order of
+// tiles, give XCD k the k-th contiguous eighth of that order, so the tiles
+// resident together on one XCD are spatial neighbours that share halo data
+// in its L2.  Identity when total is not a multiple of 8.
+__device__ __forceinline__ int xcd_linear(int b, int total) {
+  if (total % 8) return b;
+  return (b & 7) * (total >> 3) + (b >> 3);
+}
+
 // Device arrays (nb values each) of the per-configuration PCG scalars.
 struct PcgScalars {
   double *bn2, *rz, *rzn, *pq, *rr, *zq, *alpha, *beta, *act, *rel;

@@ -123,14 +123,15 @@ __global__ __launch_bounds__(256) void k_adj_moments(int n, const double *__rest
   __shared__ double Gs[SLAB * MS];               // [lz][hy][hx][m]
   __shared__ __align__(16) double Ts[TS];        // [D_y D_x][m][a]
   const int bx_n = (n + BX - 1) / BX, by_n = (n + BY - 1) / BY, bz_n = (n + BZ - 1) / BZ;
+  const int lin = xcd_linear(blockIdx.x, gridDim.x);
   {  // configuration of this brick
-    const int cfg = blockIdx.x / (bx_n * by_n * bz_n);
+    const int cfg = lin / (bx_n * by_n * bz_n);
     const size_t M = size_t(n) * n * n, P = size_t(PO) * n;
     gE += size_t(cfg) * M * NM;
     lam += size_t(cfg) * P * P * P;
     Aout += size_t(cfg) * M * 8;
   }
-  int b = blockIdx.x % (bx_n * by_n * bz_n);
+  int b = lin % (bx_n * by_n * bz_n);
   const int bx = b % bx_n;
   b /= bx_n;
   const int by = b % by_n;

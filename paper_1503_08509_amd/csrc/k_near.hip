@@ -50,14 +50,15 @@ __global__ __launch_bounds__(256, 2) void k_psi(int n, const double *__restrict_
   __shared__ __align__(16) T Cs[8 * SLAB];
 
   const int bricks = (n + BS - 1) / BS;
+  const int lin = xcd_linear(blockIdx.x, gridDim.x);
   {  // configuration of this brick
-    const int cfg = blockIdx.x / (bricks * bricks * bricks);
+    const int cfg = lin / (bricks * bricks * bricks);
     const size_t M = size_t(n) * n * n, P = size_t(PO) * n;
     C += size_t(cfg) * M * 8;
     phi += size_t(cfg) * P * P * P;
     Wel += size_t(cfg) * M * NM;
   }
-  int b = blockIdx.x % (bricks * bricks * bricks);
+  int b = lin % (bricks * bricks * bricks);
   const int bx = b % bricks;
   b /= bricks;
   const int by = b % bricks;
