@@ -205,7 +205,7 @@ def kernel_rooflines(prof, steps, mixed):
     return {k: v for k, v in kernels.items() if v}
 
 
-def measure(name, precision, steps, warmup, forces=True):
+def measure(name, precision, steps, warmup, forces=True, graph=False):
     """Run `warmup` + `steps` evaluations of one workload; device-resident
     inputs; returns timings, per-stage device times, kernel rooflines, the
     outputs of the last step (host copies) and the context statistics."""
@@ -220,7 +220,7 @@ def measure(name, precision, steps, warmup, forces=True):
     tx = torch.from_numpy(x).to(dev)
     tQ = torch.from_numpy(Q).to(dev)
     ctx = fp.Context(L, counts if len(counts) > 1 else counts[0], n,
-                     precision=fp.PRECISION_MIXED if mixed else fp.PRECISION_FP64)
+                     precision=fp.PRECISION_MIXED if mixed else fp.PRECISION_FP64, use_graph=1 if graph else 0)
 
     def step():
         if forces:
@@ -231,7 +231,8 @@ def measure(name, precision, steps, warmup, forces=True):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    ctx.set_profiling(True)
+    if not graph:   # graph replays are timed by wall clock only (no per-stage events)
+        ctx.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -261,18 +262,20 @@ def _rel_rms(a, b):
 def variant_summary(r, ref=None):
     import numpy as np
     k = r["kernels"]
-    dom = max(k, key=lambda s: k[s]["avg_launch_ms"] * k[s]["launches_per_step"])
     v = {"ms_per_step": r["ms_per_step"], "value": r["value"], "unit": "pair interactions/s",
          "near_pairs_per_step": r["pairs"], "configurations": len(r["counts"]),
          "N": int(sum(r["counts"])), "elements": f"{r['n']}^3",
-         "pair_kernel_ms": r["stages_ms_per_step"]["pair"],
-         "pair_interactions_per_s_pair_kernel": r["pairs"] / (r["stages_ms_per_step"]["pair"] * 1e-3),
-         "dominant_kernel": dom, "dominant_frac": k[dom]["frac"], "dominant_bound": k[dom]["bound"],
-         "kernel_fracs": {s: round(k[s]["frac"], 4) for s in k},
+         "graph_replays": r["stats"]["graph_replays"],
          "mg_iterations": r["stats"]["mg_iterations"], "adj_mg_iterations": r["stats"]["adj_iterations"],
          "pair_variant": {"kind": "queue" if r["stats"]["pair_variant"] else "element",
                           "item_targets": r["stats"]["pair_item_targets"], "waves": r["stats"]["pair_waves"],
                           "tuned_ms": r["stats"]["tune_ms_best"], "element_ms": r["stats"]["tune_ms_default"]}}
+    if k:
+        dom = max(k, key=lambda s: k[s]["avg_launch_ms"] * k[s]["launches_per_step"])
+        v.update({"pair_kernel_ms": r["stages_ms_per_step"]["pair"],
+                  "pair_interactions_per_s_pair_kernel": r["pairs"] / (r["stages_ms_per_step"]["pair"] * 1e-3),
+                  "dominant_kernel": dom, "dominant_frac": k[dom]["frac"], "dominant_bound": k[dom]["bound"],
+                  "kernel_fracs": {s: round(k[s]["frac"], 4) for s in k}})
     if ref is not None:
         v["accuracy_vs_fp64"] = {
             "Phi_rel_rms": _rel_rms(r["out"]["Phi"], ref["out"]["Phi"]),
@@ -351,7 +354,14 @@ def main():
         variants["fp64 " + BATCH_WORKLOAD] = variant_summary(b64)
         bm = measure(BATCH_WORKLOAD, "mixed", 3, 1)
         variants["mixed " + BATCH_WORKLOAD] = variant_summary(bm, b64)
-        del b64, bm
+        bg = measure(BATCH_WORKLOAD, "fp64", 3, 2, graph=True)
+        variants["fp64 " + BATCH_WORKLOAD + " hipGraph"] = variant_summary(bg, b64)
+        bmg = measure(BATCH_WORKLOAD, "mixed", 3, 2, graph=True)
+        variants["mixed " + BATCH_WORKLOAD + " hipGraph"] = variant_summary(bmg, b64)
+        del b64, bm, bg, bmg
+        ug = measure("uniform-1M-n64", "fp64", 3, 2, graph=True)
+        variants["fp64 uniform-1M-n64 hipGraph"] = variant_summary(ug, r)
+        del ug
         out["variants"] = variants
     if not args.no_cpu_baseline:
         if forces and len(r["counts"]) == 1:

@@ -87,6 +87,20 @@ typedef struct {
                             several sizes and grid sizes) and keeps the
                             fastest; 0: one wave per element.  Every variant
                             gives bit-identical results.                        */
+  int32_t use_graph;     /* 1: run each evaluation as one captured hipGraph
+                            replay on an internal stream ordered after the
+                            caller's stream, on context copies of the inputs
+                            and outputs (copied in and out around the replay).
+                            The graph is captured after an eager call and
+                            reused while the same outputs are requested; each
+                            mesh solve runs the iteration
+                            count of that eager call (a configuration that
+                            converges earlier stops changing), and after each
+                            replay the input checks and the final residuals are
+                            read back: a replay that falls short of mg_rtol is
+                            redone eagerly and the graph captured again.
+                            Results are identical to eager calls.  0 (default):
+                            eager launches.  Not used while profiling is on.  */
 } fep3m_options;
 
 typedef struct {
@@ -106,6 +120,7 @@ typedef struct {
   int32_t pair_waves;        /* persistent waves launched (variant 1)             */
   double  tune_ms_best;      /* device time of the chosen variant when tuned      */
   double  tune_ms_default;   /* device time of one wave per element when tuned    */
+  int64_t graph_replays;     /* evaluations served by a graph replay (use_graph)  */
 } fep3m_stats;
 
 /* Profile slots: stages of one call, the fine-level operator launches, and

@@ -33,7 +33,7 @@ STAGES = {"perm": 0, "start": 1, "C": 2, "b": 3, "phi": 4, "Phi_p": 5, "Phi_m": 
 class Options(ctypes.Structure):
     _fields_ = [("n_sr", ctypes.c_int32), ("precision", ctypes.c_int32), ("mg_rtol", ctypes.c_double),
                 ("mg_max_iter", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("table_box", ctypes.c_int32),
-                ("autotune", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -43,7 +43,8 @@ class Stats(ctypes.Structure):
                 ("mg_levels", ctypes.c_int32), ("create_seconds", ctypes.c_double),
                 ("generation", ctypes.c_int64), ("pair_variant", ctypes.c_int32),
                 ("pair_item_targets", ctypes.c_int32), ("pair_waves", ctypes.c_int32),
-                ("tune_ms_best", ctypes.c_double), ("tune_ms_default", ctypes.c_double)]
+                ("tune_ms_best", ctypes.c_double), ("tune_ms_default", ctypes.c_double),
+                ("graph_replays", ctypes.c_int64)]
 
 
 PROF_SLOTS = ["sort", "assign", "solve", "near", "pair", "interp", "fine_apply", "total",

@@ -93,7 +93,9 @@ enum CfgScalar : int {
   kCsEnergy = 4,   // sum Q Phi
   kCsAdjLoad = 5,  // sum G (compatibility projection of the deposit)
   kCsPcg = 6,      // 10 PCG scalars from here
-  kCsSlots = 16
+  kCsFwdRel = 16,  // final relative residual of the forward mesh solve
+  kCsAdjRel = 17,  // final relative residual of the adjoint mesh solve
+  kCsSlots = 18
 };
 
 struct fep3m_ctx {
@@ -152,6 +154,19 @@ struct fep3m_ctx {
   };
   PairPlan plan;
   bool tuned = false;
+  // graph mode: the whole evaluation captured once per set of argument
+  // pointers on an internal stream, then replayed
+  hipStream_t gstream = nullptr;
+  // the graph reads and writes context buffers; callers' arrays are copied
+  // in before and out after each replay
+  double *gx = nullptr, *gQ = nullptr, *gPhi = nullptr, *gU = nullptr, *gF = nullptr, *gD = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_ready = false, capturing = false;
+  int gmask = -1;               // outputs the captured graph produces (Phi, U, F, dUdQ bits)
+  int cap_iters[2] = {0, 0};    // PCG iterations of the forward and adjoint solves in the graph
+  int64_t replays = 0;
   int items_titem = -1;         // item size the current work list was built for
   int cus = 256;                // compute units of the device
   int *nit = nullptr, *item_start = nullptr, *icounter = nullptr, *iscan_max = nullptr;
@@ -172,6 +187,11 @@ struct fep3m_ctx {
     for (void *p : allocs) (void)hipFree(p);
     if (host_scal) (void)hipHostFree(host_scal);
     if (host_cs) (void)hipHostFree(host_cs);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (gstream) (void)hipStreamDestroy(gstream);
   }
   void check_launch(const char *what) { hip_check(hipGetLastError(), what); }
   void sync(const char *what) { hip_check(hipStreamSynchronize(stream), what); }
@@ -213,13 +233,27 @@ struct fep3m_ctx {
   void tune_pairs(bool pair_forces);
   void reverse(double *F, double *dUdQ);
   void finish(bool count_pairs);
+  void check_inputs() {   // flags and per-configuration charge sums, already on the host
+    int fl;
+    std::memcpy(&fl, host_scal + 4, sizeof(int));
+    if (fl) throw Status(FEP3M_ERR_NONFINITE, "non-finite position or charge");
+    for (int bb = 0; bb < nb; ++bb) {
+      const double sq = host_cs[kCsQ * nb + bb], sa = host_cs[kCsQabs * nb + bb];
+      if (std::fabs(sq) > 1e-10 * sa)
+        throw Status(FEP3M_ERR_NOT_NEUTRAL, "charges are not neutral: sum Q = " + std::to_string(sq) +
+                                                (nb > 1 ? " in configuration " + std::to_string(bb) : std::string()));
+    }
+  }
   void backward(int64_t gen, double *F, double *dUdQ);
   void build_mg();
   void estimate_spectra();
   template <class T> void vcycle(int l, const T *f);
   template <class T> void cheb_smooth(int l, const T *f, bool zero_start);
-  void solve(const double *rhs, double *out);
-  void mesh_solve(double *rhs, double *out);
+  void solve(const double *rhs, double *out, int which);
+  void mesh_solve(double *rhs, double *out, int which);
+  void run_once(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ);
+  void finish_host();
+  void evaluate_graph(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ);
   void evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F = nullptr,
                 double *dUdQ = nullptr);
 };
@@ -560,11 +594,11 @@ void fep3m_ctx::vcycle(int l, const T *f) {
 // (z_new . q) / (z_old . r_old), which stays a descent method when the
 // preconditioner carries float32 rounding; everything else (K p, the
 // updates, every norm and inner product) is float64.
-void fep3m_ctx::solve(const double *rhs, double *sol) {
+void fep3m_ctx::solve(const double *rhs, double *sol, int which) {
   MGLevel &L0 = lv[0];
   const size_t per = L0.ndof, nd = per * nb;
-  hip_check(hipMemsetAsync(sol, 0, nd * sizeof(double), stream), "zero solution");
-  hip_check(hipMemcpyAsync(rr, rhs, nd * sizeof(double), hipMemcpyDeviceToDevice, stream), "copy r");
+  launch_fill_f64(stream, nd, 0.0, sol);
+  launch_copy_f64(stream, nd, rhs, rr);
   launch_sum_partials(stream, launch_dot(stream, nb, per, rhs, rhs, partial), partial, pcs.bn2, nb);
   // z = M^-1 r; rzn = z . r (and zq = z . q when q is given)
   auto precondition = [&](const double *q) {
@@ -586,6 +620,12 @@ void fep3m_ctx::solve(const double *rhs, double *sol) {
   precondition(nullptr);
   launch_pcg_scalars(stream, nb, kPcgStart, 0.0, pcs);   // act = (b != 0), beta = 0, rz = z . r
   set_p();
+  // Eagerly, the host reads the residuals after every iteration and stops
+  // once all configurations have converged.  Under graph capture the loop
+  // runs the iteration count of the eager call it was captured after; the
+  // residuals are checked after each replay (a configuration that converged
+  // earlier does not change in the extra iterations).
+  const int fixed = capturing ? cap_iters[which] : 0;
   double relmax = 0.0;
   int it = 0;
   for (it = 1; it <= opt.mg_max_iter; ++it) {
@@ -595,25 +635,32 @@ void fep3m_ctx::solve(const double *rhs, double *sol) {
     launch_sum_partials(stream, launch_cg_update(stream, nb, per, pcs.alpha, pv, qv, sol, rr, partial), partial,
                         pcs.rr, nb);
     launch_pcg_scalars(stream, nb, kPcgResid, opt.mg_rtol, pcs);
-    hip_check(hipMemcpyAsync(host_cs, pcs.rel, nb * sizeof(double), hipMemcpyDeviceToHost, stream), "copy residuals");
-    sync("mesh solve residual");
-    relmax = 0.0;
-    for (int bb = 0; bb < nb; ++bb) relmax = std::max(relmax, host_cs[bb]);
-    if (relmax <= opt.mg_rtol) break;
+    if (capturing) {
+      if (it >= fixed) break;
+    } else {
+      hip_check(hipMemcpyAsync(host_cs, pcs.rel, nb * sizeof(double), hipMemcpyDeviceToHost, stream),
+                "copy residuals");
+      sync("mesh solve residual");
+      relmax = 0.0;
+      for (int bb = 0; bb < nb; ++bb) relmax = std::max(relmax, host_cs[bb]);
+      if (relmax <= opt.mg_rtol) break;
+    }
     precondition(qv);
     launch_pcg_scalars(stream, nb, mixed ? kPcgBetaPR : kPcgBeta, 0.0, pcs);
     set_p();
   }
+  launch_copy_f64(stream, nb, pcs.rel, cfgs(which ? kCsAdjRel : kCsFwdRel));
+  check_launch("mesh solve");
+  if (capturing) return;
   stats.mg_iterations = std::min(it, opt.mg_max_iter);
   stats.mg_rel_residual = relmax;
-  check_launch("mesh solve");
   if (!(relmax <= opt.mg_rtol))
     throw Status(FEP3M_ERR_NOT_CONVERGED, "mesh solve reached relative residual " + std::to_string(relmax));
 }
 
 // Gauge-fixed periodic solve: out = K^+ rhs with int out = 0.
-void fep3m_ctx::mesh_solve(double *rhs, double *out) {
-  solve(rhs, out);
+void fep3m_ctx::mesh_solve(double *rhs, double *out, int which) {
+  solve(rhs, out, which);
   launch_mass_dot(stream, nb, n, p, w1, out, partial);
   launch_sum_partials(stream, seg_blocks(nb, lv[0].ndof), partial, cfgs(kCsInt), nb);
   launch_sub_const(stream, nb, lv[0].ndof, 1.0 / (double(n) * n * n), cfgs(kCsInt), out);
@@ -624,22 +671,16 @@ void fep3m_ctx::mesh_solve(double *rhs, double *out) {
 void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *U, bool pair_forces) {
   const int MT = nb * n * n * n;
   stage_mark(FEP3M_PROF_SORT, true);
-  hip_check(hipMemsetAsync(count, 0, size_t(MT) * sizeof(int), stream), "zero counts");
-  hip_check(hipMemsetAsync(flags, 0, 4 * sizeof(int), stream), "zero flags");
+  launch_fill_int(stream, MT, 0, count);
+  launch_fill_int(stream, 4, 0, flags);
   const int gb = launch_bin(stream, nb, off_d, N, x, Qc, L, n, gtmp, elem, slot, count, flags, partial);
   launch_sum_partials(stream, gb, partial, cfgs(kCsQ), nb);
   launch_sum_partials(stream, gb, partial + size_t(nb) * gb, cfgs(kCsQabs), nb);
-  hip_check(hipMemcpyAsync(host_cs, cs, 2 * size_t(nb) * sizeof(double), hipMemcpyDeviceToHost, stream), "copy");
-  hip_check(hipMemcpyAsync(host_scal + 4, flags, sizeof(int), hipMemcpyDeviceToHost, stream), "copy");
-  sync("binning");
-  int fl;
-  std::memcpy(&fl, host_scal + 4, sizeof(int));
-  if (fl) throw Status(FEP3M_ERR_NONFINITE, "non-finite position or charge");
-  for (int bb = 0; bb < nb; ++bb) {
-    const double sq = host_cs[kCsQ * nb + bb], sa = host_cs[kCsQabs * nb + bb];
-    if (std::fabs(sq) > 1e-10 * sa)
-      throw Status(FEP3M_ERR_NOT_NEUTRAL, "charges are not neutral: sum Q = " + std::to_string(sq) +
-                                              (nb > 1 ? " in configuration " + std::to_string(bb) : std::string()));
+  if (!capturing) {   // under capture the same checks run after each replay
+    hip_check(hipMemcpyAsync(host_cs, cs, 2 * size_t(nb) * sizeof(double), hipMemcpyDeviceToHost, stream), "copy");
+    hip_check(hipMemcpyAsync(host_scal + 4, flags, sizeof(int), hipMemcpyDeviceToHost, stream), "copy");
+    sync("binning");
+    check_inputs();
   }
 
   launch_scan(stream, MT, count, start, maxcount);
@@ -656,7 +697,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   check_launch("assignment");
   stage_mark(FEP3M_PROF_ASSIGN, false);
   stage_mark(FEP3M_PROF_SOLVE, true);
-  mesh_solve(b, sol);
+  mesh_solve(b, sol, 0);
   stage_mark(FEP3M_PROF_SOLVE, false);
   stage_mark(FEP3M_PROF_NEAR, true);
   const int ps = mixed ? launch_psi<float>(stream, nb, n, nsr, p, C, Tf, sol, Welf)
@@ -750,7 +791,7 @@ void fep3m_ctx::reverse(double *F, double *dUdQ) {
   launch_assemble(stream, nb, p, n, gE, Gv, partial);
   launch_sum_partials(stream, seg_blocks(nb, lv[0].ndof), partial, cfgs(kCsAdjLoad), nb);
   launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsAdjLoad), Gv);
-  mesh_solve(Gv, lam);
+  mesh_solve(Gv, lam, 1);
   stage_mark(FEP3M_PROF_ADJ_SOLVE, false);
   stage_mark(FEP3M_PROF_ADJ_NEAR, true);
   if (launch_adj_moments(stream, nb, p, n, nsr, gE, Tt, lam, gw, Aadj) != 0)
@@ -764,6 +805,7 @@ void fep3m_ctx::reverse(double *F, double *dUdQ) {
     launch_forces<double>(stream, nb, off_d, p, n, N, 1.0 / h, bas, sg, sQ, Wel, Aadj, fpair, phip_s, phim_s, perm, F,
                           dUdQ);
   stage_mark(FEP3M_PROF_FORCES, false);
+  if (capturing) return;   // counts are recorded by the eager call before a capture
   stats.adj_iterations = stats.mg_iterations;
   stats.mg_iterations = fwd_iters;
   stats.mg_rel_residual = fwd_rel;
@@ -771,36 +813,138 @@ void fep3m_ctx::reverse(double *F, double *dUdQ) {
 
 void fep3m_ctx::finish(bool count_pairs) {
   if (count_pairs) {
-    hip_check(hipMemsetAsync(paircount, 0, sizeof(unsigned long long), stream), "zero pair count");
+    launch_fill_int(stream, 2, 0, reinterpret_cast<int *>(paircount));
     launch_pair_count(stream, nb, n, nsr, start, paircount);
+  }
+  if (capturing) return;
+  if (count_pairs) {
     hip_check(hipMemcpyAsync(host_scal + 8, paircount, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream),
               "copy");
     hip_check(hipMemcpyAsync(host_scal + 9, maxcount, sizeof(int), hipMemcpyDeviceToHost, stream), "copy");
   }
   check_launch("evaluation");
   sync("evaluation");
-  if (count_pairs) {
-    unsigned long long pc;
-    std::memcpy(&pc, host_scal + 8, sizeof(pc));
-    int mc;
-    std::memcpy(&mc, host_scal + 9, sizeof(int));
-    stats.near_pairs = int64_t(pc);
-    stats.max_per_element = mc;
-  }
+  if (count_pairs) finish_host();
   if (prof.on) profile_collect();
 }
 
-void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ) {
-  fwd_valid = false;
+void fep3m_ctx::finish_host() {   // pair statistics already copied to host_scal[8..9]
+  unsigned long long pc;
+  std::memcpy(&pc, host_scal + 8, sizeof(pc));
+  int mc;
+  std::memcpy(&mc, host_scal + 9, sizeof(int));
+  stats.near_pairs = int64_t(pc);
+  stats.max_per_element = mc;
+}
+
+void fep3m_ctx::run_once(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ) {
   prof.begin_call();
   stage_mark(FEP3M_PROF_TOTAL, true);
   forward(x, Qc, Phi, U, F != nullptr);
   if (F) reverse(F, dUdQ);
   stage_mark(FEP3M_PROF_TOTAL, false);
   finish(true);
+}
+
+void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ) {
+  fwd_valid = false;
+  if (opt.use_graph && !prof.on) evaluate_graph(x, Qc, Phi, U, F, dUdQ);
+  else run_once(x, Qc, Phi, U, F, dUdQ);
   ++generation;
   stats.generation = int64_t(generation);
   fwd_valid = true;
+}
+
+// Graph mode.  The evaluation runs on an internal stream ordered after the
+// caller's stream (and the caller's stream after it), on context copies of
+// the inputs and outputs.  A call that asks for the same outputs as the
+// captured graph replays it and then checks, on the host, the input flags,
+// the per-configuration neutrality and the final residuals of the mesh
+// solves; any other call (or a replay whose solves needed more iterations
+// than were captured) runs eagerly, which also yields the iteration counts,
+// and then captures the evaluation again.
+void fep3m_ctx::evaluate_graph(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ) {
+  if (!gstream) {
+    hip_check(hipStreamCreateWithFlags(&gstream, hipStreamNonBlocking), "graph stream");
+    hip_check(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming), "event");
+    hip_check(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming), "event");
+    gx = alloc<double>(3 * size_t(N), "graph positions");
+    gQ = alloc<double>(size_t(N), "graph charges");
+    gPhi = alloc<double>(size_t(N), "graph potentials");
+    gU = alloc<double>(size_t(nb), "graph energies");
+    gF = alloc<double>(3 * size_t(N), "graph forces");
+    gD = alloc<double>(size_t(N), "graph charge derivatives");
+  }
+  const int mask = (Phi ? 1 : 0) | (U ? 2 : 0) | (F ? 4 : 0) | (dUdQ ? 8 : 0);
+  double *oPhi = Phi ? gPhi : nullptr, *oU = U ? gU : nullptr, *oF = F ? gF : nullptr, *oD = dUdQ ? gD : nullptr;
+  hipStream_t user = stream;
+  hip_check(hipEventRecord(ev_in, user), "event");
+  hip_check(hipStreamWaitEvent(gstream, ev_in, 0), "wait");
+  stream = gstream;
+  try {
+    launch_copy_f64(stream, 3 * size_t(N), x, gx);
+    launch_copy_f64(stream, size_t(N), Qc, gQ);
+    bool done = false;
+    if (graph_ready && mask == gmask) {
+      hip_check(hipGraphLaunch(gexec, gstream), "graph launch");
+      hip_check(hipMemcpyAsync(host_cs, cs, size_t(kCsSlots) * nb * sizeof(double), hipMemcpyDeviceToHost, gstream),
+                "copy");
+      hip_check(hipMemcpyAsync(host_scal + 4, flags, sizeof(int), hipMemcpyDeviceToHost, gstream), "copy");
+      hip_check(hipMemcpyAsync(host_scal + 8, paircount, sizeof(unsigned long long), hipMemcpyDeviceToHost, gstream),
+                "copy");
+      hip_check(hipMemcpyAsync(host_scal + 9, maxcount, sizeof(int), hipMemcpyDeviceToHost, gstream), "copy");
+      sync("graph replay");
+      stats.graph_replays = ++replays;
+      check_inputs();
+      double fr = 0.0, ar = 0.0;
+      for (int bb = 0; bb < nb; ++bb) {
+        fr = std::max(fr, host_cs[kCsFwdRel * nb + bb]);
+        ar = std::max(ar, host_cs[kCsAdjRel * nb + bb]);
+      }
+      if (fr <= opt.mg_rtol && (!F || ar <= opt.mg_rtol)) {
+        done = true;
+        finish_host();
+        stats.mg_iterations = cap_iters[0];
+        stats.mg_rel_residual = fr;
+        if (F) stats.adj_iterations = cap_iters[1];
+      }
+    }
+    if (!done) {
+      run_once(gx, gQ, oPhi, oU, oF, oD);   // eager; synchronises and yields the iteration counts
+      cap_iters[0] = stats.mg_iterations;
+      cap_iters[1] = F ? stats.adj_iterations : 0;
+      if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
+      if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+      graph_ready = false;
+      hip_check(hipStreamBeginCapture(gstream, hipStreamCaptureModeThreadLocal), "begin capture");
+      capturing = true;
+      try {
+        run_once(gx, gQ, oPhi, oU, oF, oD);
+      } catch (...) {
+        capturing = false;
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(gstream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      capturing = false;
+      hip_check(hipStreamEndCapture(gstream, &graph), "end capture");
+      hip_check(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "instantiate");
+      graph_ready = true;
+      gmask = mask;
+    }
+    if (Phi) launch_copy_f64(stream, size_t(N), gPhi, Phi);
+    if (U) launch_copy_f64(stream, size_t(nb), gU, U);
+    if (F) launch_copy_f64(stream, 3 * size_t(N), gF, F);
+    if (dUdQ) launch_copy_f64(stream, size_t(N), gD, dUdQ);
+    check_launch("graph outputs");
+  } catch (...) {
+    stream = user;
+    throw;
+  }
+  hip_check(hipEventRecord(ev_out, gstream), "event");
+  hip_check(hipStreamWaitEvent(user, ev_out, 0), "wait");
+  stream = user;
 }
 
 void fep3m_ctx::backward(int64_t gen, double *F, double *dUdQ) {
@@ -870,6 +1014,7 @@ bool valid_options(const fep3m_options &o, std::string &why) {
   if (o.mg_max_iter < 1 || o.mg_max_iter > 1000) { why = "mg_max_iter must be 1..1000"; return false; }
   if (o.cheb_degree < 1 || o.cheb_degree > 10) { why = "cheb_degree must be 1..10"; return false; }
   if (o.autotune != 0 && o.autotune != 1) { why = "autotune must be 0 or 1"; return false; }
+  if (o.use_graph != 0 && o.use_graph != 1) { why = "use_graph must be 0 or 1"; return false; }
   if (o.table_box % 2 == 0 || o.table_box < 2 * o.n_sr + 3 || o.table_box > 41) {
     why = "table_box must be odd, > 2 n_sr + 1 and <= 41";
     return false;
@@ -890,6 +1035,7 @@ int fep3m_default_options(fep3m_options *opt) {
   opt->cheb_degree = 3;
   opt->table_box = 2 * 3 + 9;
   opt->autotune = 1;
+  opt->use_graph = 0;
   return FEP3M_OK;
 }
 

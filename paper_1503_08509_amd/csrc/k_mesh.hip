@@ -651,6 +651,14 @@ __global__ __launch_bounds__(256) void k_scale(size_t n, double s, const double 
     b[i] = s * a[i];
 }
 
+// Fill and copy as kernels (usable inside a captured graph).
+__global__ __launch_bounds__(256) void k_fill_f64(size_t n, double v, double *__restrict__ p) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+__global__ __launch_bounds__(256) void k_copy_f64(size_t n, const double *__restrict__ a, double *__restrict__ b) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) b[i] = a[i];
+}
+
 // Deterministic pseudo-random fill (power iteration start vector).
 __global__ __launch_bounds__(256) void k_hash_fill(size_t n, uint32_t seed, double *__restrict__ v) {
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
@@ -901,6 +909,12 @@ void launch_xpay(hipStream_t s, int nb, size_t per, const double *betas, const d
 }
 void launch_scale(hipStream_t s, size_t n, double sc, const double *a, double *b) {
   hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(256), 0, s, n, sc, a, b);
+}
+void launch_fill_f64(hipStream_t s, size_t n, double v, double *p) {
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(256), 0, s, n, v, p);
+}
+void launch_copy_f64(hipStream_t s, size_t n, const double *a, double *b) {
+  hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(n)), dim3(256), 0, s, n, a, b);
 }
 void launch_hash_fill(hipStream_t s, size_t n, uint32_t seed, double *v) {
   hipLaunchKernelGGL(k_hash_fill, dim3(grid_for(n)), dim3(256), 0, s, n, seed, v);

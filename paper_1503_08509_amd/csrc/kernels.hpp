@@ -109,5 +109,7 @@ int launch_cg_update(hipStream_t s, int nb, size_t per, const double *alphas, co
 void launch_xpay(hipStream_t s, int nb, size_t per, const double *betas, const double *z, double *p);
 void launch_scale(hipStream_t s, size_t n, double sc, const double *a, double *b);
 void launch_hash_fill(hipStream_t s, size_t n, uint32_t seed, double *v);
+void launch_fill_f64(hipStream_t s, size_t n, double v, double *p);
+void launch_copy_f64(hipStream_t s, size_t n, const double *a, double *b);
 
 }  // namespace fep3m
