@@ -132,6 +132,7 @@ struct fep3m_ctx {
   // mixed precision: float32 tables, element field, local coordinates
   float *Tf = nullptr, *Welf = nullptr;
   float4 *su = nullptr;
+  int4 *si = nullptr;
   int *sel = nullptr;
   double *partial = nullptr, *scal = nullptr;
   size_t partial_len = 0;
@@ -348,6 +349,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
     hip_check(hipMemcpy(Tf, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice), "upload tables");
     Welf = alloc<float>(size_t(nb) * M * (p + 1) * (p + 1) * (p + 1), "element field (f32)");
     su = alloc<float4>(size_t(N), "local coordinates (f32)");
+    si = alloc<int4>(size_t(N), "local coordinates (fixed point)");
     sel = alloc<int>(size_t(N), "packed elements");
   }
   nit = alloc<int>(size_t(nb) * M + 1, "items per element");
@@ -687,7 +689,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   launch_scatter(stream, N, elem, slot, start, tmp);
   launch_rank(stream, N, tmp, elem, start, gtmp, Qc, perm, sg, sQ);
   items_titem = -1;   // the pair work list follows this call's element starts
-  if (mixed) launch_local_f32(stream, n, N, sg, sQ, su, sel);
+  if (mixed) launch_local_f32(stream, n, N, sg, sQ, su, si, sel);
   stage_mark(FEP3M_PROF_SORT, false);
   stage_mark(FEP3M_PROF_ASSIGN, true);
   launch_moments(stream, nb, n, N, start, sg, sQ, C);
@@ -722,7 +724,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
 int fep3m_ctx::pair_launch(const PairPlan &pl, bool pair_forces) {
   double *fp = pair_forces ? fpair : nullptr;
   if (pl.kind == 0)
-    return mixed ? launch_pair_f32(stream, nb, n, nsr, N, start, su, sel, phip_s, fp)
+    return mixed ? launch_pair_f32(stream, nb, n, nsr, N, start, si, sel, phip_s, fp)
                  : launch_pair(stream, nb, n, nsr, N, start, sg, sQ, phip_s, fp);
   const int MT = nb * n * n * n;
   if (items_titem != pl.titem) {
@@ -730,7 +732,7 @@ int fep3m_ctx::pair_launch(const PairPlan &pl, bool pair_forces) {
     items_titem = pl.titem;
   }
   return mixed ? launch_pair_queue_f32(stream, pl.waves, n, nsr, N, start, items, item_start + MT, icounter, pl.titem,
-                                       su, sel, phip_s, fp)
+                                       si, sel, phip_s, fp)
                : launch_pair_queue(stream, pl.waves, n, nsr, N, start, items, item_start + MT, icounter, pl.titem, sg,
                                    sQ, phip_s, fp);
 }

@@ -102,12 +102,13 @@ __global__ __launch_bounds__(256) void k_assemble(int n, int K, const double *__
 //            (32 float64 accumulators) for one lane of an 8-node chunk,
 //   phase  = one (D_z, node chunk): the deposits g of the source slab and the
 //            tables of the 49 offsets of that D_z (transposed copy
-//            Tt[D][m][a], the chunk's nodes) are staged in LDS; per D_y a
-//            thread loads the 2 NSR + 8 sources its row sees into registers
-//            once and slides over D_x,
+//            Tt[D][m][a], the chunk's nodes) are staged in LDS, the next
+//            phase's deposits already in flight into registers; per D_y a thread
+//            loads the 2 NSR + 8 sources its row sees into registers once
+//            and slides over D_x,
 //   the 8 node lanes are reduced with shuffles at the end.
 template <int NSR, int PO>
-__global__ __launch_bounds__(256) void k_adj_moments(int n, const double *__restrict__ gE,
+__global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__restrict__ gE,
                                                      const double *__restrict__ Tt, const double *__restrict__ lam,
                                                      const double *__restrict__ gw, double *__restrict__ Aout) {
   constexpr int BX = 8, BY = 4, BZ = 4;
@@ -123,15 +124,14 @@ __global__ __launch_bounds__(256) void k_adj_moments(int n, const double *__rest
   __shared__ double Gs[SLAB * MS];               // [lz][hy][hx][m]
   __shared__ __align__(16) double Ts[TS];        // [D_y D_x][m][a]
   const int bx_n = (n + BX - 1) / BX, by_n = (n + BY - 1) / BY, bz_n = (n + BZ - 1) / BZ;
-  const int lin = xcd_linear(blockIdx.x, gridDim.x);
   {  // configuration of this brick
-    const int cfg = lin / (bx_n * by_n * bz_n);
+    const int cfg = blockIdx.x / (bx_n * by_n * bz_n);
     const size_t M = size_t(n) * n * n, P = size_t(PO) * n;
     gE += size_t(cfg) * M * NM;
     lam += size_t(cfg) * P * P * P;
     Aout += size_t(cfg) * M * 8;
   }
-  int b = lin % (bx_n * by_n * bz_n);
+  int b = blockIdx.x % (bx_n * by_n * bz_n);
   const int bx = b % bx_n;
   b /= bx_n;
   const int by = b % by_n;
@@ -146,24 +146,43 @@ __global__ __launch_bounds__(256) void k_adj_moments(int n, const double *__rest
 #pragma unroll
     for (int a = 0; a < AH; ++a) acc[e][a] = 0.0;
 
-  for (int Dz = -NSR; Dz <= NSR; ++Dz) {
-    for (int ch = 0; ch < NCH; ++ch) {
-      __syncthreads();
-      for (int i = tid; i < MC * SLAB; i += 256) {   // lanes walk nodes: contiguous loads
-        const int mm = i % MC, h = i / MC;
-        const int m = ch * MC + mm;
-        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-        const int ex = (x0 - NSR + hx + 2 * n) % n, ey = (y0 - NSR + hy + 2 * n) % n;
-        const int ez = (z0 + hz + Dz + 2 * n) % n;
-        Gs[h * MS + mm] = m < NM ? gE[(size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NM + m] : 0.0;
+  // Phases (D_z, node chunk) are software-pipelined: the next phase's
+  // deposits and tables are fetched into registers while this one computes.
+  constexpr int NPH = S * NCH;
+  constexpr int GPF = (MC * SLAB + 255) / 256;
+  double gpf[GPF];
+  auto fetch = [&](int ph) {
+    const int Dz = ph / NCH - NSR, ch = ph % NCH;
+#pragma unroll
+    for (int r = 0; r < GPF; ++r) {   // lanes walk nodes: contiguous loads
+      const int i = tid + 256 * r;
+      const int mm = i % MC, h = i / MC;
+      const int m = ch * MC + mm;
+      const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+      const int ex = (x0 - NSR + hx + 2 * n) % n, ey = (y0 - NSR + hy + 2 * n) % n;
+      const int ez = (z0 + hz + Dz + 2 * n) % n;
+      gpf[r] = (i < MC * SLAB && m < NM) ? gE[(size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NM + m] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int ph = 0; ph < NPH; ++ph) {
+    {
+      __syncthreads();   // the previous phase is done with the LDS slabs
+#pragma unroll
+      for (int r = 0; r < GPF; ++r) {
+        const int i = tid + 256 * r;
+        if (i < MC * SLAB) Gs[(i / MC) * MS + i % MC] = gpf[r];
       }
-      for (int i = tid; i < TS; i += 256) {   // 64 contiguous values per offset
-        const int a = i % 8, mm = (i / 8) % MC, dyx = i / (8 * MC);
-        const int m = ch * MC + mm;
-        const int iD = dyx + S * S * (Dz + NSR);
-        Ts[i] = m < NM ? Tt[(size_t(iD) * NM + m) * 8 + a] : 0.0;
+      {   // tables of this phase (shared by every block: L2-resident)
+        const int Dz = ph / NCH - NSR, ch = ph % NCH;
+        for (int i = tid; i < TS; i += 256) {   // 64 contiguous values per offset
+          const int a = i % 8, mm = (i / 8) % MC, dyx = i / (8 * MC);
+          const int m = ch * MC + mm;
+          Ts[i] = m < NM ? Tt[(size_t(dyx + S * S * (Dz + NSR)) * NM + m) * 8 + a] : 0.0;
+        }
       }
       __syncthreads();
+      if (ph + 1 < NPH) fetch(ph + 1);
 #pragma unroll 1
       for (int Dy = -NSR; Dy <= NSR; ++Dy) {
         // the x-row of sources this thread's 8 targets see at every D_x:

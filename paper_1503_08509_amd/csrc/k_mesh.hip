@@ -241,14 +241,16 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
     invd[i] = T(1) / (op.dk[kx] * op.dm[ky] * op.dm[kz] + op.dm[kx] * op.dk[ky] * op.dm[kz] +
                       op.dm[kx] * op.dm[ky] * op.dk[kz]);
   }
+  // Addresses: a block-uniform 64-bit tile base plus 32-bit offsets inside
+  // the tile (at most O P^2 + O P + O < 2^31 for every supported n).
+  const size_t tbase = (size_t(oz0) * P + oy0) * P + ox0;
   T pf_f[NIT], pf_d[NIT];
 #pragma unroll
   for (int r = 0; r < NIT; ++r) {
     const int li = tid + 256 * r;
     const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
-    const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
-    const bool ok = li < O * O * O && gx < P && gy < P && gz < P;
-    const size_t g = ok ? (size_t(gz) * P + gy) * P + gx : 0;
+    const bool ok = li < O * O * O && ox0 + ox < P && oy0 + oy < P && oz0 + oz < P;
+    const size_t g = tbase + unsigned(ok ? (oz * P + oy) * P + ox : 0);
     pf_f[r] = (ok && need_f) ? f[g] : T(0);
     pf_d[r] = (ok && need_d) ? xprev[g] : T(0);
   }
@@ -257,9 +259,11 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
   if (tid < I * I) {
     const int lx = tid % I, ly = tid / I;
     const int gx = wrapi(ox0 - PO + lx, P), gy = wrapi(oy0 - PO + ly, P);
+    const T *col = x + (size_t(gy) * P + gx);   // this thread's (x, y) column
+    const size_t P2 = size_t(P) * P;
     T v[I];
 #pragma unroll
-    for (int z = 0; z < I; ++z) v[z] = x[(size_t(wrapi(oz0 - PO + z, P)) * P + gy) * P + gx];
+    for (int z = 0; z < I; ++z) v[z] = col[size_t(wrapi(oz0 - PO + z, P)) * P2];   // plane offset is block-uniform
     if (lx >= PO && lx < PO + O && ly >= PO && ly < PO + O) {
 #pragma unroll
       for (int oz = 0; oz < O; ++oz) Xo[(oz * O + (ly - PO)) * O + (lx - PO)] = v[oz + PO];
@@ -316,14 +320,13 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
   for (int r = 0; r < NIT; ++r) {
     const int li = tid + 256 * r;
     const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
-    const int gx = ox0 + ox, gy = oy0 + oy, gz = oz0 + oz;
-    const bool ok = li < O * O * O && gx < P && gy < P && gz < P;
+    const bool ok = li < O * O * O && ox0 + ox < P && oy0 + oy < P && oz0 + oz < P;
     const int lc = ok ? li : 0;
     const int cx = lc % O, cy = (lc / O) % O, cz = lc / (O * O);
     const T y = Y[(cz * O + cy) * S::YS + cx];
     const T xv = Xo[lc];
     const T rr = (pf_f[r] - y) * invd[(ox % PO) + PO * ((oy % PO) + PO * (oz % PO))];
-    const size_t g = (size_t(gz) * P + gy) * P + gx;
+    const size_t g = tbase + unsigned((oz * P + oy) * P + ox);
     if (ok) {
       if (mode == kApply) out[g] = y;
       else if (mode == kResidual) out[g] = pf_f[r] - y;

@@ -5,10 +5,12 @@
 // interpolated potential); the energy and the combination stay float64.
 //
 // Local coordinates: a charge at element units g = e + 1/2 + u keeps u in
-// [-1/2, 1/2)^3 as float32 (absolute rounding below 3e-8) and its element
-// (ex, ey, ez) packed as ex | ey << 10 | ez << 20, so pair separations are
-// formed as (integer element offset) + (u_j - u_i) and never lose the
-// precision that global float32 coordinates would at large n.
+// [-1/2, 1/2)^3 as float32 (for the interpolation) and as 29-bit fixed point
+// iu = round(u 2^29) (for the pair sum), with its element (ex, ey, ez) packed
+// as ex | ey << 10 | ez << 20.  A pair separation in units of 2^-29 element
+// is then the exact int32 (element offset) 2^29 + iu_j - iu_i (|.| < 2^31
+// for offsets up to 3), converted to float32 once: relative rounding 6e-8
+// whatever the distance, where float32 coordinates would lose 3e-8 / r.
 #include "kernels.hpp"
 #include "pair_segments.hpp"
 
@@ -31,20 +33,27 @@ __device__ __forceinline__ double wave_sum(double v) {
 }  // namespace
 
 // u (float32) and Q of every sorted charge, and its packed element.
+constexpr double kFix = 536870912.0;   // 2^29
 __global__ __launch_bounds__(256) void k_local_f32(int n, int64_t N, const double *__restrict__ sg,
                                                    const double *__restrict__ sQ, float4 *__restrict__ su,
-                                                   int *__restrict__ sel) {
+                                                   int4 *__restrict__ si, int *__restrict__ sel) {
   for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < N; s += int64_t(gridDim.x) * blockDim.x) {
-    int e[3];
+    int e[3], iu[3];
     float u[3];
     for (int k = 0; k < 3; ++k) {
       const double g = sg[k * N + s];
       double ef = floor(g);
       if (ef > double(n - 1)) ef = double(n - 1);
       e[k] = int(ef);
-      u[k] = float(g - ef - 0.5);
+      const double ud = g - ef - 0.5;   // in [-1/2, 1/2]
+      u[k] = float(ud);
+      double fx = rint(ud * kFix);
+      fx = fx > 268435455.0 ? 268435455.0 : (fx < -268435456.0 ? -268435456.0 : fx);
+      iu[k] = int(fx);
     }
-    su[s] = make_float4(u[0], u[1], u[2], float(sQ[s]));
+    const float q = float(sQ[s]);
+    su[s] = make_float4(u[0], u[1], u[2], q);
+    si[s] = make_int4(iu[0], iu[1], iu[2], __float_as_int(q));
     sel[s] = e[0] | (e[1] << 10) | (e[2] << 20);
   }
 }
@@ -56,15 +65,15 @@ __global__ __launch_bounds__(256) void k_local_f32(int n, int64_t N, const doubl
 // are combined in float64.
 template <int NSR, bool FORCE, int NT>
 __device__ __forceinline__ void pair_chunk_f32(const PairSegments<NSR> &seg, int total, int lane, int64_t N, int t0,
-                                               int nt, int n, int ex, int ey, int ez, const float4 *__restrict__ su,
+                                               int nt, int n, int ex, int ey, int ez, const int4 *__restrict__ si,
                                                const int *__restrict__ sel, double *__restrict__ phip,
                                                double *__restrict__ fpair) {
-  float tx[NT], ty[NT], tz[NT];
+  int tx[NT], ty[NT], tz[NT];
   float ps[NT], pc[NT];
   float fs[3][NT], fc[3][NT];
 #pragma unroll
   for (int k = 0; k < NT; ++k) {
-    const float4 t = su[t0 + (k < nt ? k : 0)];
+    const int4 t = si[t0 + (k < nt ? k : 0)];
     tx[k] = t.x; ty[k] = t.y; tz[k] = t.z;
     ps[k] = pc[k] = 0.f;
 #pragma unroll
@@ -76,18 +85,19 @@ __device__ __forceinline__ void pair_chunk_f32(const PairSegments<NSR> &seg, int
     const int j = seg.sb[sp] + (f - seg.so[sp]);
     const int pk = seg.ss[sp];
     const int pe = sel[j];
-    const float4 s = su[j];
-    // source position relative to the target element centre (element units)
-    const float jx = float((pe & 1023) + seg.shift(pk, 0) * n - ex) + s.x;
-    const float jy = float(((pe >> 10) & 1023) + seg.shift(pk, 1) * n - ey) + s.y;
-    const float jz = float((pe >> 20) + seg.shift(pk, 2) * n - ez) + s.z;
+    const int4 s = si[j];
+    const float qj = __int_as_float(s.w);
+    // source position relative to the target element centre, units of 2^-29 element
+    const int jx = ((pe & 1023) + seg.shift(pk, 0) * n - ex) * (1 << 29) + s.x;
+    const int jy = (((pe >> 10) & 1023) + seg.shift(pk, 1) * n - ey) * (1 << 29) + s.y;
+    const int jz = ((pe >> 20) + seg.shift(pk, 2) * n - ez) * (1 << 29) + s.z;
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
-      const float dx = jx - tx[k], dy = jy - ty[k], dz = jz - tz[k];
+      const float dx = float(jx - tx[k]), dy = float(jy - ty[k]), dz = float(jz - tz[k]);
       const float r2 = dx * dx + dy * dy + dz * dz;
       const bool use = (k < nt) && (j != t0 + k);
       const float ri = use ? rsqrtf(r2) : 0.f;   // the skipped self pair has r = 0
-      const float qr = s.w * ri;
+      const float qr = qj * ri;
       kahan_add(ps[k], pc[k], qr);
       if (FORCE) {
         const float qr3 = qr * ri * ri;
@@ -99,11 +109,12 @@ __device__ __forceinline__ void pair_chunk_f32(const PairSegments<NSR> &seg, int
   }
 #pragma unroll
   for (int k = 0; k < NT; ++k) {
-    const double p = wave_sum(double(ps[k]) - double(pc[k]));
+    // sums in fixed-point units: 1/r carries 2^-29 and d/r^3 carries 2^-58
+    const double p = wave_sum(double(ps[k]) - double(pc[k])) * kFix;
     double g[3] = {0.0, 0.0, 0.0};
     if (FORCE) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) g[d] = wave_sum(double(fs[d][k]) - double(fc[d][k]));
+      for (int d = 0; d < 3; ++d) g[d] = wave_sum(double(fs[d][k]) - double(fc[d][k])) * (kFix * kFix);
     }
     if (lane == 0 && k < nt) {
       phip[t0 + k] = p;
@@ -118,7 +129,7 @@ __device__ __forceinline__ void pair_chunk_f32(const PairSegments<NSR> &seg, int
 
 template <int NSR, bool FORCE>
 __global__ __launch_bounds__(64) void k_pair_f32(int n, int64_t N, const int *__restrict__ start,
-                                                 const float4 *__restrict__ su, const int *__restrict__ sel,
+                                                 const int4 *__restrict__ si, const int *__restrict__ sel,
                                                  double *__restrict__ phip, double *__restrict__ fpair) {
   __shared__ PairSegments<NSR> seg;
   const int lane = threadIdx.x;
@@ -131,13 +142,13 @@ __global__ __launch_bounds__(64) void k_pair_f32(int n, int64_t N, const int *__
   for (int t0 = tb; t0 < te;) {   // chunk widths 8, 4, 2 as in the float64 kernel
     const int rem = te - t0;
     if (rem > 4) {
-      pair_chunk_f32<NSR, FORCE, 8>(seg, total, lane, N, t0, min(rem, 8), n, ex, ey, ez, su, sel, phip, fpair);
+      pair_chunk_f32<NSR, FORCE, 8>(seg, total, lane, N, t0, min(rem, 8), n, ex, ey, ez, si, sel, phip, fpair);
       t0 += 8;
     } else if (rem > 2) {
-      pair_chunk_f32<NSR, FORCE, 4>(seg, total, lane, N, t0, rem, n, ex, ey, ez, su, sel, phip, fpair);
+      pair_chunk_f32<NSR, FORCE, 4>(seg, total, lane, N, t0, rem, n, ex, ey, ez, si, sel, phip, fpair);
       t0 += 4;
     } else {
-      pair_chunk_f32<NSR, FORCE, 2>(seg, total, lane, N, t0, rem, n, ex, ey, ez, su, sel, phip, fpair);
+      pair_chunk_f32<NSR, FORCE, 2>(seg, total, lane, N, t0, rem, n, ex, ey, ez, si, sel, phip, fpair);
       t0 += 2;
     }
   }
@@ -148,7 +159,7 @@ template <int NSR, bool FORCE>
 __global__ __launch_bounds__(64) void k_pair_queue_f32(int n, int64_t N, const int *__restrict__ start,
                                                        const int2 *__restrict__ items, const int *__restrict__ nitems,
                                                        int *__restrict__ counter, int titem,
-                                                       const float4 *__restrict__ su, const int *__restrict__ sel,
+                                                       const int4 *__restrict__ si, const int *__restrict__ sel,
                                                        double *__restrict__ phip, double *__restrict__ fpair) {
   __shared__ PairSegments<NSR> seg;
   __shared__ int cur;
@@ -167,13 +178,13 @@ __global__ __launch_bounds__(64) void k_pair_queue_f32(int n, int64_t N, const i
     for (int t0 = w.y; t0 < te;) {
       const int rem = te - t0;
       if (rem > 4) {
-        pair_chunk_f32<NSR, FORCE, 8>(seg, total, lane, N, t0, min(rem, 8), n, ex, ey, ez, su, sel, phip, fpair);
+        pair_chunk_f32<NSR, FORCE, 8>(seg, total, lane, N, t0, min(rem, 8), n, ex, ey, ez, si, sel, phip, fpair);
         t0 += 8;
       } else if (rem > 2) {
-        pair_chunk_f32<NSR, FORCE, 4>(seg, total, lane, N, t0, rem, n, ex, ey, ez, su, sel, phip, fpair);
+        pair_chunk_f32<NSR, FORCE, 4>(seg, total, lane, N, t0, rem, n, ex, ey, ez, si, sel, phip, fpair);
         t0 += 4;
       } else {
-        pair_chunk_f32<NSR, FORCE, 2>(seg, total, lane, N, t0, rem, n, ex, ey, ez, su, sel, phip, fpair);
+        pair_chunk_f32<NSR, FORCE, 2>(seg, total, lane, N, t0, rem, n, ex, ey, ez, si, sel, phip, fpair);
         t0 += 2;
       }
     }
@@ -244,50 +255,51 @@ inline int grid_m(int64_t n) {
 }
 }  // namespace
 
-void launch_local_f32(hipStream_t s, int n, int64_t N, const double *sg, const double *sQ, float4 *su, int *sel) {
-  hipLaunchKernelGGL(k_local_f32, dim3(grid_m(N)), dim3(256), 0, s, n, N, sg, sQ, su, sel);
+void launch_local_f32(hipStream_t s, int n, int64_t N, const double *sg, const double *sQ, float4 *su, int4 *si,
+                      int *sel) {
+  hipLaunchKernelGGL(k_local_f32, dim3(grid_m(N)), dim3(256), 0, s, n, N, sg, sQ, su, si, sel);
 }
 
 template <int NSR>
-static void pair_f32_impl(hipStream_t s, int nb, int n, int64_t N, const int *start, const float4 *su, const int *sel,
+static void pair_f32_impl(hipStream_t s, int nb, int n, int64_t N, const int *start, const int4 *si, const int *sel,
                           double *phip, double *fpair) {
   dim3 g(nb * n * n * n);
-  if (fpair) hipLaunchKernelGGL((k_pair_f32<NSR, true>), g, dim3(64), 0, s, n, N, start, su, sel, phip, fpair);
-  else hipLaunchKernelGGL((k_pair_f32<NSR, false>), g, dim3(64), 0, s, n, N, start, su, sel, phip, fpair);
+  if (fpair) hipLaunchKernelGGL((k_pair_f32<NSR, true>), g, dim3(64), 0, s, n, N, start, si, sel, phip, fpair);
+  else hipLaunchKernelGGL((k_pair_f32<NSR, false>), g, dim3(64), 0, s, n, N, start, si, sel, phip, fpair);
 }
-int launch_pair_f32(hipStream_t s, int nb, int n, int nsr, int64_t N, const int *start, const float4 *su,
+int launch_pair_f32(hipStream_t s, int nb, int n, int nsr, int64_t N, const int *start, const int4 *si,
                     const int *sel, double *phip, double *fpair) {
-  if (n > 1024) return -1;   // packed element coordinates hold 10 bits per axis
+  // packed element coordinates hold 10 bits per axis; fixed-point separations
+  // stay inside int32 for element offsets up to 3
+  if (n > 1024 || nsr > 3) return -1;
   switch (nsr) {
-    case 1: pair_f32_impl<1>(s, nb, n, N, start, su, sel, phip, fpair); return 0;
-    case 2: pair_f32_impl<2>(s, nb, n, N, start, su, sel, phip, fpair); return 0;
-    case 3: pair_f32_impl<3>(s, nb, n, N, start, su, sel, phip, fpair); return 0;
-    case 4: pair_f32_impl<4>(s, nb, n, N, start, su, sel, phip, fpair); return 0;
+    case 1: pair_f32_impl<1>(s, nb, n, N, start, si, sel, phip, fpair); return 0;
+    case 2: pair_f32_impl<2>(s, nb, n, N, start, si, sel, phip, fpair); return 0;
+    case 3: pair_f32_impl<3>(s, nb, n, N, start, si, sel, phip, fpair); return 0;
     default: return -1;
   }
 }
 
 template <int NSR>
 static void pair_queue_f32_impl(hipStream_t s, int waves, int n, int64_t N, const int *start, const int2 *items,
-                                const int *nitems, int *counter, int titem, const float4 *su, const int *sel,
+                                const int *nitems, int *counter, int titem, const int4 *si, const int *sel,
                                 double *phip, double *fpair) {
   if (fpair)
     hipLaunchKernelGGL((k_pair_queue_f32<NSR, true>), dim3(waves), dim3(64), 0, s, n, N, start, items, nitems,
-                       counter, titem, su, sel, phip, fpair);
+                       counter, titem, si, sel, phip, fpair);
   else
     hipLaunchKernelGGL((k_pair_queue_f32<NSR, false>), dim3(waves), dim3(64), 0, s, n, N, start, items, nitems,
-                       counter, titem, su, sel, phip, fpair);
+                       counter, titem, si, sel, phip, fpair);
 }
 int launch_pair_queue_f32(hipStream_t s, int waves, int n, int nsr, int64_t N, const int *start, const int2 *items,
-                          const int *nitems, int *counter, int titem, const float4 *su, const int *sel, double *phip,
+                          const int *nitems, int *counter, int titem, const int4 *si, const int *sel, double *phip,
                           double *fpair) {
-  if (n > 1024) return -1;
+  if (n > 1024 || nsr > 3) return -1;
   launch_fill_int(s, 1, 0, counter);
   switch (nsr) {
-    case 1: pair_queue_f32_impl<1>(s, waves, n, N, start, items, nitems, counter, titem, su, sel, phip, fpair); return 0;
-    case 2: pair_queue_f32_impl<2>(s, waves, n, N, start, items, nitems, counter, titem, su, sel, phip, fpair); return 0;
-    case 3: pair_queue_f32_impl<3>(s, waves, n, N, start, items, nitems, counter, titem, su, sel, phip, fpair); return 0;
-    case 4: pair_queue_f32_impl<4>(s, waves, n, N, start, items, nitems, counter, titem, su, sel, phip, fpair); return 0;
+    case 1: pair_queue_f32_impl<1>(s, waves, n, N, start, items, nitems, counter, titem, si, sel, phip, fpair); return 0;
+    case 2: pair_queue_f32_impl<2>(s, waves, n, N, start, items, nitems, counter, titem, si, sel, phip, fpair); return 0;
+    case 3: pair_queue_f32_impl<3>(s, waves, n, N, start, items, nitems, counter, titem, si, sel, phip, fpair); return 0;
     default: return -1;
   }
 }

@@ -46,12 +46,14 @@ void launch_half(hipStream_t s, int nb, const double *in, double *out);
 void launch_unpermute(hipStream_t s, int64_t N, double scale, const int *perm, const double *in, double *out);
 
 // mixed precision (k_mixed.hip): float32 local coordinates and charges
-// (su = {ux, uy, uz, Q}), packed elements sel = ex | ey << 10 | ez << 20
-void launch_local_f32(hipStream_t s, int n, int64_t N, const double *sg, const double *sQ, float4 *su, int *sel);
-int launch_pair_f32(hipStream_t s, int nb, int n, int nsr, int64_t N, const int *start, const float4 *su,
+// (su = {ux, uy, uz, Q}), the same offsets in 2^-29 fixed point with the
+// charge's float bits (si), packed elements sel = ex | ey << 10 | ez << 20
+void launch_local_f32(hipStream_t s, int n, int64_t N, const double *sg, const double *sQ, float4 *su, int4 *si,
+                      int *sel);
+int launch_pair_f32(hipStream_t s, int nb, int n, int nsr, int64_t N, const int *start, const int4 *si,
                     const int *sel, double *phip, double *fpair);
 int launch_pair_queue_f32(hipStream_t s, int waves, int n, int nsr, int64_t N, const int *start, const int2 *items,
-                          const int *nitems, int *counter, int titem, const float4 *su, const int *sel, double *phip,
+                          const int *nitems, int *counter, int titem, const int4 *si, const int *sel, double *phip,
                           double *fpair);
 int launch_interp_f32(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h,
                       const GllBasis &bas, const float4 *su, const int *sel, const float *Wel, const double *phip,
