@@ -205,7 +205,7 @@ def kernel_rooflines(prof, steps, mixed):
     return {k: v for k, v in kernels.items() if v}
 
 
-def measure(name, precision, steps, warmup, forces=True, graph=False):
+def measure(name, precision, steps, warmup, forces=True, graph=False, solver=0):
     """Run `warmup` + `steps` evaluations of one workload; device-resident
     inputs; returns timings, per-stage device times, kernel rooflines, the
     outputs of the last step (host copies) and the context statistics."""
@@ -220,7 +220,8 @@ def measure(name, precision, steps, warmup, forces=True, graph=False):
     tx = torch.from_numpy(x).to(dev)
     tQ = torch.from_numpy(Q).to(dev)
     ctx = fp.Context(L, counts if len(counts) > 1 else counts[0], n,
-                     precision=fp.PRECISION_MIXED if mixed else fp.PRECISION_FP64, use_graph=1 if graph else 0)
+                     precision=fp.PRECISION_MIXED if mixed else fp.PRECISION_FP64, use_graph=1 if graph else 0,
+                     solver=solver)
 
     def step():
         if forces:
@@ -391,6 +392,12 @@ def main():
         ug = measure("uniform-1M-n64", "fp64", 3, 2, graph=True)
         variants["fp64 uniform-1M-n64 hipGraph"] = variant_summary(ug, r)
         del ug
+        # the exact fast-diagonalisation mesh solver in place of multigrid
+        for prec, wl in (("fp64", "uniform-1M-n64"), ("mixed", "uniform-1M-n64"), ("fp64", BATCH_WORKLOAD)):
+            fd = measure(wl, prec, 3, 1, solver=1)
+            variants[f"{prec} {wl} fast-diagonalisation solver"] = variant_summary(
+                fd, r if wl == "uniform-1M-n64" else None)
+            del fd
         out["variants"] = variants
     if not args.no_cpu_baseline:
         out["method_error_vs_ewald"] = method_error_vs_ewald()

@@ -70,6 +70,21 @@ enum {
                                    relative RMS (Phi, U, F, dU/dQ).               */
 };
 
+/* Mesh solvers (Section 2.2 leaves the solver open; the paper uses an
+ * AMG-preconditioned Krylov method). */
+enum {
+  FEP3M_SOLVER_MG = 0,   /* PCG with a p/h multigrid V-cycle (Chebyshev-Jacobi
+                            smoothing), iterated to mg_rtol                     */
+  FEP3M_SOLVER_FDM = 1   /* exact periodic solve by fast diagonalisation: the
+                            1-D pencil K1 v = lam M1 v is solved once at create
+                            (host, about 2 s for 320 nodes per axis), and each
+                            solve applies V^T along x, y, z, divides by
+                            lam_i + lam_j + lam_k and applies V back; the
+                            dense 1-D transforms are float64 GEMMs (rocBLAS).
+                            float64 in both precisions; mg_rtol is not used
+                            (the achieved residual is still measured).  */
+};
+
 typedef struct {
   int32_t n_sr;          /* near block radius in elements (default 3: 7^3 block,
                             the paper's short-range list, Section 4)             */
@@ -100,7 +115,9 @@ typedef struct {
                             read back: a replay that falls short of mg_rtol is
                             redone eagerly and the graph captured again.
                             Results are identical to eager calls.  0 (default):
-                            eager launches.  Not used while profiling is on.  */
+                            eager launches.  Not used while profiling is on,
+                            nor with solver = FEP3M_SOLVER_FDM.                */
+  int32_t solver;        /* FEP3M_SOLVER_* (default: multigrid-preconditioned CG) */
 } fep3m_options;
 
 typedef struct {

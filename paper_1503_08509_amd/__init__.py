@@ -27,13 +27,16 @@ ERR_UNSUPPORTED = -7
 PRECISION_FP64 = 0
 PRECISION_MIXED = 1
 
+SOLVER_MG = 0
+SOLVER_FDM = 1
+
 STAGES = {"perm": 0, "start": 1, "C": 2, "b": 3, "phi": 4, "Phi_p": 5, "Phi_m": 6, "T": 7}
 
 
 class Options(ctypes.Structure):
     _fields_ = [("n_sr", ctypes.c_int32), ("precision", ctypes.c_int32), ("mg_rtol", ctypes.c_double),
                 ("mg_max_iter", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("table_box", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("solver", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

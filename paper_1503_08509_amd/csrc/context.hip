@@ -20,6 +20,8 @@
 #include "fep3m.h"
 #include "host_fe.hpp"
 #include "host_tables.hpp"
+#include <rocblas/rocblas.h>
+
 #include "kernels.hpp"
 
 using namespace fep3m;
@@ -148,6 +150,11 @@ struct fep3m_ctx {
   double *coarseV = nullptr, *coarseLam = nullptr;
   int coarseP = 0;
   double *b = nullptr, *sol = nullptr, *rr = nullptr, *pv = nullptr, *qv = nullptr;
+  // fast-diagonalisation solver: 1-D eigenvectors (column-major, V[i + j P]:
+  // node i, mode j, M1-orthonormal) and eigenvalues of the fine pencil
+  rocblas_handle blas = nullptr;
+  double *fdmV = nullptr, *fdmLam = nullptr;
+  int fdm_i0 = 0;
   // pair-sum work decomposition (autotuned): kind 0 one wave per element,
   // kind 1 persistent waves over items of `titem` targets
   struct PairPlan {
@@ -193,6 +200,7 @@ struct fep3m_ctx {
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (gstream) (void)hipStreamDestroy(gstream);
+    if (blas) (void)rocblas_destroy_handle(blas);
   }
   void check_launch(const char *what) { hip_check(hipGetLastError(), what); }
   void sync(const char *what) { hip_check(hipStreamSynchronize(stream), what); }
@@ -251,6 +259,8 @@ struct fep3m_ctx {
   template <class T> void vcycle(int l, const T *f);
   template <class T> void cheb_smooth(int l, const T *f, bool zero_start);
   void solve(const double *rhs, double *out, int which);
+  void fdm_solve(const double *rhs, double *out, int which);
+  void build_fdm();
   void mesh_solve(double *rhs, double *out, int which);
   void run_once(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ);
   void finish_host();
@@ -373,6 +383,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
             "pinned scalars");
 
   build_mg();
+  if (opt.solver == FEP3M_SOLVER_FDM) build_fdm();
   // partials serve every two-stage reduction: the fixed reduction grids and
   // the per-tile partials of the fine-level operator
   partial_len = std::max(partial_len, size_t(nb) * apply_blocks(lv[0].op) + 64);
@@ -507,6 +518,91 @@ void fep3m_ctx::build_mg() {
   }
 }
 
+void fep3m_ctx::build_fdm() {
+  const LevelOp &op = lv[0].op;
+  Mat K1, M1;
+  assemble_1d(op.p, op.n, true, K1, M1);
+  Vec lamv;
+  Mat V;
+  sym_gen_eig(K1, M1, lamv, V);
+  const int P = op.P;
+  fdm_i0 = 0;
+  for (int i = 1; i < P; ++i)
+    if (std::fabs(lamv[i]) < std::fabs(lamv[fdm_i0])) fdm_i0 = i;
+  lamv[fdm_i0] = 0.0;   // the constant mode of the periodic pencil
+  std::vector<double> vcm(size_t(P) * P);
+  for (int i = 0; i < P; ++i)
+    for (int j = 0; j < P; ++j) vcm[i + size_t(j) * P] = V(i, j);
+  fdmV = alloc<double>(vcm.size(), "fdm eigenvectors");
+  fdmLam = alloc<double>(size_t(P), "fdm eigenvalues");
+  hip_check(hipMemcpy(fdmV, vcm.data(), vcm.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+  hip_check(hipMemcpy(fdmLam, lamv.data(), size_t(P) * sizeof(double), hipMemcpyHostToDevice), "upload");
+  if (rocblas_create_handle(&blas) != rocblas_status_success) throw Status(FEP3M_ERR_DEVICE, "rocblas handle");
+  if (rocblas_set_pointer_mode(blas, rocblas_pointer_mode_host) != rocblas_status_success)
+    throw Status(FEP3M_ERR_DEVICE, "rocblas pointer mode");
+}
+
+namespace {
+void blas_check(rocblas_status s, const char *what) {
+  if (s != rocblas_status_success)
+    throw Status(FEP3M_ERR_DEVICE, std::string(what) + ": " + rocblas_status_to_string(s));
+}
+}  // namespace
+
+// Exact periodic solve by fast diagonalisation of the Kronecker sum
+// K = K1 (x) M1 (x) M1 + M1 (x) K1 (x) M1 + M1 (x) M1 (x) K1 with
+// K1 V = M1 V diag(lam), V^T M1 V = I:  out = (V (x) V (x) V) D^+ (V (x) V (x) V)^T rhs,
+// D = lam_i + lam_j + lam_k.  Each 1-D transform is a float64 GEMM over the
+// whole batch: along x one GEMM of P x (nb P^2); along y a strided batch of
+// nb P slabs; along z a strided batch of nb configurations.  The PCG
+// buffers serve as the two work vectors.  The achieved relative residual
+// is measured with one operator apply, as for the iterative solver.
+void fep3m_ctx::fdm_solve(const double *rhs, double *sol, int which) {
+  const int P = lv[0].op.P;
+  const size_t per = lv[0].ndof, nd = per * nb;
+  const rocblas_int iP = P, iP2 = P * P;
+  const double one = 1.0, zero = 0.0;
+  blas_check(rocblas_set_stream(blas, stream), "rocblas stream");
+  double *A = rr, *B = pv;
+  // forward: x, y, z
+  blas_check(rocblas_dgemm(blas, rocblas_operation_transpose, rocblas_operation_none, iP, rocblas_int(nb) * iP2, iP,
+                           &one, fdmV, iP, rhs, iP, &zero, A, iP), "fdm x");
+  blas_check(rocblas_dgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_none, iP, iP, iP, &one, A,
+                                           iP, rocblas_stride(iP2), fdmV, iP, 0, &zero, B, iP, rocblas_stride(iP2),
+                                           rocblas_int(nb) * iP), "fdm y");
+  blas_check(rocblas_dgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_none, iP2, iP, iP, &one, B,
+                                           iP2, rocblas_stride(per), fdmV, iP, 0, &zero, A, iP2, rocblas_stride(per),
+                                           rocblas_int(nb)), "fdm z");
+  launch_fdm_scale(stream, nd, P, fdm_i0, fdmLam, A);
+  // inverse: z, y, x
+  blas_check(rocblas_dgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_transpose, iP2, iP, iP, &one,
+                                           A, iP2, rocblas_stride(per), fdmV, iP, 0, &zero, B, iP2,
+                                           rocblas_stride(per), rocblas_int(nb)), "fdm z back");
+  blas_check(rocblas_dgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_transpose, iP, iP, iP, &one,
+                                           B, iP, rocblas_stride(iP2), fdmV, iP, 0, &zero, A, iP,
+                                           rocblas_stride(iP2), rocblas_int(nb) * iP), "fdm y back");
+  blas_check(rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, iP, rocblas_int(nb) * iP2, iP, &one,
+                           fdmV, iP, A, iP, &zero, sol, iP), "fdm x back");
+  // achieved residual, per configuration
+  launch_sum_partials(stream, launch_dot(stream, nb, per, rhs, rhs, partial), partial, pcs.bn2, nb);
+  apply0<double>(sol, rhs, qv, nullptr, nullptr, 0.0, 0.0, kResidual, nullptr);
+  launch_sum_partials(stream, launch_dot(stream, nb, per, qv, qv, partial), partial, pcs.rr, nb);
+  launch_pcg_scalars(stream, nb, kPcgStart, 0.0, pcs);
+  launch_pcg_scalars(stream, nb, kPcgResid, 0.0, pcs);
+  launch_copy_f64(stream, nb, pcs.rel, cfgs(which ? kCsAdjRel : kCsFwdRel));
+  check_launch("fdm solve");
+  if (capturing) return;
+  hip_check(hipMemcpyAsync(host_cs, pcs.rel, nb * sizeof(double), hipMemcpyDeviceToHost, stream), "copy residuals");
+  sync("fdm residual");
+  double relmax = 0.0;
+  for (int bb = 0; bb < nb; ++bb) relmax = std::max(relmax, host_cs[bb]);
+  stats.mg_iterations = 0;
+  stats.mg_rel_residual = relmax;
+  if (!(relmax <= 1e-9))
+    throw Status(FEP3M_ERR_NOT_CONVERGED, "fast-diagonalisation solve reached relative residual " +
+                                              std::to_string(relmax));
+}
+
 void fep3m_ctx::estimate_spectra() {
   // largest eigenvalue of D^-1 K per smoothed level (power iteration)
   for (size_t i = 0; i + 1 < lv.size(); ++i) {
@@ -597,6 +693,10 @@ void fep3m_ctx::vcycle(int l, const T *f) {
 // preconditioner carries float32 rounding; everything else (K p, the
 // updates, every norm and inner product) is float64.
 void fep3m_ctx::solve(const double *rhs, double *sol, int which) {
+  if (opt.solver == FEP3M_SOLVER_FDM) {
+    fdm_solve(rhs, sol, which);
+    return;
+  }
   MGLevel &L0 = lv[0];
   const size_t per = L0.ndof, nd = per * nb;
   launch_fill_f64(stream, nd, 0.0, sol);
@@ -850,7 +950,7 @@ void fep3m_ctx::run_once(const double *x, const double *Qc, double *Phi, double 
 
 void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ) {
   fwd_valid = false;
-  if (opt.use_graph && !prof.on) evaluate_graph(x, Qc, Phi, U, F, dUdQ);
+  if (opt.use_graph && !prof.on && opt.solver == FEP3M_SOLVER_MG) evaluate_graph(x, Qc, Phi, U, F, dUdQ);
   else run_once(x, Qc, Phi, U, F, dUdQ);
   ++generation;
   stats.generation = int64_t(generation);
@@ -1017,6 +1117,7 @@ bool valid_options(const fep3m_options &o, std::string &why) {
   if (o.cheb_degree < 1 || o.cheb_degree > 10) { why = "cheb_degree must be 1..10"; return false; }
   if (o.autotune != 0 && o.autotune != 1) { why = "autotune must be 0 or 1"; return false; }
   if (o.use_graph != 0 && o.use_graph != 1) { why = "use_graph must be 0 or 1"; return false; }
+  if (o.solver != FEP3M_SOLVER_MG && o.solver != FEP3M_SOLVER_FDM) { why = "unknown solver"; return false; }
   if (o.table_box % 2 == 0 || o.table_box < 2 * o.n_sr + 3 || o.table_box > 41) {
     why = "table_box must be odd, > 2 n_sr + 1 and <= 41";
     return false;
@@ -1038,6 +1139,7 @@ int fep3m_default_options(fep3m_options *opt) {
   opt->table_box = 2 * 3 + 9;
   opt->autotune = 1;
   opt->use_graph = 0;
+  opt->solver = FEP3M_SOLVER_MG;
   return FEP3M_OK;
 }
 

@@ -4,6 +4,7 @@
 // objects feed the device kernels as constants; nothing here runs per call.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 

@@ -662,6 +662,19 @@ __global__ __launch_bounds__(256) void k_copy_f64(size_t n, const double *__rest
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) b[i] = a[i];
 }
 
+// Fast-diagonalisation solve, middle step: coefficient (i, j, k) of each
+// configuration (x index i fastest) divided by lam_i + lam_j + lam_k; the
+// constant mode (i = j = k = i0) is set to zero.
+__global__ __launch_bounds__(256) void k_fdm_scale(size_t total, int P, int i0, const double *__restrict__ lam,
+                                                   double *__restrict__ X) {
+  const size_t P3 = size_t(P) * P * P;
+  for (size_t g = size_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += size_t(gridDim.x) * blockDim.x) {
+    const size_t l = g % P3;
+    const int i = int(l % P), j = int((l / P) % P), k = int(l / (size_t(P) * P));
+    X[g] = (i == i0 && j == i0 && k == i0) ? 0.0 : X[g] / (lam[i] + lam[j] + lam[k]);
+  }
+}
+
 // Deterministic pseudo-random fill (power iteration start vector).
 __global__ __launch_bounds__(256) void k_hash_fill(size_t n, uint32_t seed, double *__restrict__ v) {
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) {
@@ -912,6 +925,9 @@ void launch_xpay(hipStream_t s, int nb, size_t per, const double *betas, const d
 }
 void launch_scale(hipStream_t s, size_t n, double sc, const double *a, double *b) {
   hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(256), 0, s, n, sc, a, b);
+}
+void launch_fdm_scale(hipStream_t s, size_t total, int P, int i0, const double *lam, double *X) {
+  hipLaunchKernelGGL(k_fdm_scale, dim3(grid_for(total)), dim3(256), 0, s, total, P, i0, lam, X);
 }
 void launch_fill_f64(hipStream_t s, size_t n, double v, double *p) {
   hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(256), 0, s, n, v, p);

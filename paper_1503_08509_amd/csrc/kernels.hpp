@@ -112,6 +112,7 @@ void launch_xpay(hipStream_t s, int nb, size_t per, const double *betas, const d
 void launch_scale(hipStream_t s, size_t n, double sc, const double *a, double *b);
 void launch_hash_fill(hipStream_t s, size_t n, uint32_t seed, double *v);
 void launch_fill_f64(hipStream_t s, size_t n, double v, double *p);
+void launch_fdm_scale(hipStream_t s, size_t total, int P, int i0, const double *lam, double *X);
 void launch_copy_f64(hipStream_t s, size_t n, const double *a, double *b);
 
 }  // namespace fep3m
