@@ -7,90 +7,120 @@
 // screens of every element in E's near block (D = 0 is the self term).  The
 // kernel writes W_E = phi_E - Psi_E, the field the charges of E interpolate.
 //
-// Work decomposition (a dense contraction over (D, a) with an implicit,
-// gathered left operand):
-//   block  = a 4 x 4 x 4 brick of target elements,
-//   thread = 8 target elements (a 2 x 2 x 2 sub-brick) x 8 nodes m, held as
-//            64 float64 accumulators; 216 of 256 threads compute,
-//   tables T[.][D][.] (8 x 216 values per offset) stream through a double
-//            LDS buffer, prefetched one offset ahead into registers, one
-//            barrier per offset; every table value fetched from L2 serves the
-//            brick's 64 elements,
+// This is a dense contraction over k = (D, a) (343 x 8 terms) with a
+// gathered left operand, run on the matrix cores:
+//   block  = a 4 x 4 x 8 brick of target elements, 8 waves,
+//   wave   = two 4 x 4 element layers (two 16-row tiles) x 7 of the 14
+//            16-node tiles, 14 accumulator tiles of 16 x 16,
+//   k-step = one offset D and four moments: one 16 x 16 x 4 MFMA per tile
+//            (float64, or float32 on the mixed-precision path),
+//   tables T[.][D][.] (8 x 216 values per offset, rows padded to 224 with
+//            zeros) stream through a double LDS buffer, prefetched one
+//            offset ahead into registers, one barrier per offset,
 //   moments C of the source elements sit in LDS as one z-slab per D_z.
+// On gfx950 these MFMAs round like four fused multiply-adds in k order: the
+// results equal those of a sequential loop over (D, a) bit for bit (checked
+// against such a loop on random operands, float64 and float32).
 //
-// The arithmetic type T is double, or float for the mixed-precision path:
-// then the tables and moments are float32, each D_z slab (8 (2 NSR + 1)^2
-// products per output) is summed into a float32 partial, and the seven slab
-// partials are added with Kahan compensation; phi stays float64 and W is
-// written as float32.
+// On the mixed-precision path the tables and moments are float32, each D_z
+// slab (8 (2 NSR + 1)^2 products per output) is summed into a float32
+// partial, and the seven slab partials are added with Kahan compensation;
+// phi stays float64 and W is written as float32.
 #include <type_traits>
 
 #include "kernels.hpp"
 
 namespace fep3m {
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// 16 x 16 x 4 matrix-core step acc += A B: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; accumulator value v of lane l is row row(l, v),
+// column l % 16.
+template <class T> struct Mfma16;
+template <> struct Mfma16<double> {
+  using V = f64x4;
+  static __device__ __forceinline__ V step(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct Mfma16<float> {
+  using V = f32x4;
+  static __device__ __forceinline__ V step(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+constexpr int kPsiBS = 4;    // brick edge in x and y (elements)
+constexpr int kPsiBZ = 8;    // brick depth in z
+constexpr int kPsiThreads = 64 * kPsiBZ;
+
 template <int NSR, int PO, class T>
-__global__ __launch_bounds__(256, 2) void k_psi(int n, const double *__restrict__ C, const T *__restrict__ Tab,
-                                             const double *__restrict__ phi, T *__restrict__ Wel) {
+__global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, const double *__restrict__ C,
+                                                        const T *__restrict__ Tab, const double *__restrict__ phi,
+                                                        T *__restrict__ Wel) {
+  using M = Mfma16<T>;
+  using V = typename M::V;
   constexpr bool kComp = std::is_same<T, float>::value;   // compensated slab sums
-  constexpr int BS = 4;                       // brick edge (elements)
+  constexpr int BS = kPsiBS, BZ = kPsiBZ, NTH = kPsiThreads;
   constexpr int H = BS + 2 * NSR;             // halo edge in x and y
   constexpr int S = 2 * NSR + 1;
   constexpr int ND = S * S * S;
   constexpr int Q1 = PO + 1;
   constexpr int NM = Q1 * Q1 * Q1;            // nodes per element (216 for p = 5)
-  constexpr int MT = 8;                       // nodes per thread
-  constexpr int NGM = NM / MT;                // node groups
-  constexpr int NTHR = 8 * NGM;               // computing threads
+  constexpr int NT = (NM + 15) / 16;          // 16-node tiles
+  constexpr int NTW = NT / 2;                 // node tiles per wave
+  constexpr int NMP = NT * 16;                // padded table row
   constexpr int TV = 8 * NM;                  // table values per offset
-  constexpr int TPF = (TV + 255) / 256;       // prefetch registers per thread
-  constexpr int SLAB = BS * H * H;            // one z-slab of the halo
-  static_assert(NM % MT == 0 && NTHR <= 256, "thread tile");
-  __shared__ __align__(16) T Ts[2][TV];
+  constexpr int TPF = (TV + NTH - 1) / NTH;   // prefetch registers per thread
+  constexpr int SLAB = BZ * H * H;            // one z-slab of the halo
+  static_assert(NT % 2 == 0 && BZ % 2 == 0, "wave tiling");
+  __shared__ __align__(16) T Ts[2][8 * NMP];
   __shared__ __align__(16) T Cs[8 * SLAB];
 
-  const int bricks = (n + BS - 1) / BS;
+  const int bricks = (n + BS - 1) / BS, bricksz = (n + BZ - 1) / BZ;
+  const int per = bricks * bricks * bricksz;
   const int lin = xcd_linear(blockIdx.x, gridDim.x);
   {  // configuration of this brick
-    const int cfg = lin / (bricks * bricks * bricks);
-    const size_t M = size_t(n) * n * n, P = size_t(PO) * n;
-    C += size_t(cfg) * M * 8;
+    const int cfg = lin / per;
+    const size_t Mn = size_t(n) * n * n, P = size_t(PO) * n;
+    C += size_t(cfg) * Mn * 8;
     phi += size_t(cfg) * P * P * P;
-    Wel += size_t(cfg) * M * NM;
+    Wel += size_t(cfg) * Mn * NM;
   }
-  int b = lin % (bricks * bricks * bricks);
+  int b = lin % per;
   const int bx = b % bricks;
   b /= bricks;
   const int by = b % bricks;
   const int bz = b / bricks;
-  const int x0 = bx * BS, y0 = by * BS, z0 = bz * BS;
-  const int tid = threadIdx.x;
-  const bool comp = tid < NTHR;
-  const int ge = tid % 8, gm = tid / 8;
-  const int ex0 = 2 * (ge & 1), ey0 = 2 * ((ge >> 1) & 1), ez0 = 2 * (ge >> 2);
-  const int m0 = gm * MT;
+  const int x0 = bx * BS, y0 = by * BS, z0 = bz * BZ;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int mh = w % (BZ / 2), nh = w / (BZ / 2);   // element layers 2 mh, 2 mh + 1; node tiles nh NTW + [0, NTW)
+  const int r = lane & 15, kq = lane >> 4;           // A row (element of the layer) and k (moment) of this lane
+  const int alx = r & 3, aly = r >> 2;
 
-  T acc[8][MT];                       // slab partial (float) or the whole sum (double)
-  T tot[kComp ? 8 : 1][MT], cmp[kComp ? 8 : 1][MT];   // Kahan total and compensation (float)
+  V acc[2 * NTW];                                    // slab partial (float) or the whole sum (double)
+  V tot[kComp ? 2 * NTW : 1], cmp[kComp ? 2 * NTW : 1];   // Kahan total and compensation (float)
 #pragma unroll
-  for (int e = 0; e < 8; ++e)
-#pragma unroll
-    for (int j = 0; j < MT; ++j) {
-      acc[e][j] = T(0);
-      if (kComp) { tot[e][j] = T(0); cmp[e][j] = T(0); }
-    }
-
-  // table values of offset 0 into buffer 0
-  for (int i = tid; i < TV; i += 256) {
+  for (int t = 0; t < 2 * NTW; ++t) {
+    acc[t] = V{0, 0, 0, 0};
+    if (kComp) { tot[t] = V{0, 0, 0, 0}; cmp[t] = V{0, 0, 0, 0}; }
+  }
+  for (int i = tid; i < 2 * 8 * NMP; i += NTH) (&Ts[0][0])[i] = T(0);   // padding stays zero
+  __syncthreads();
+  for (int i = tid; i < TV; i += NTH) {   // table values of offset 0 into buffer 0
     const int a = i / NM, m = i % NM;
-    Ts[0][i] = Tab[(size_t(a) * ND + 0) * NM + m];
+    Ts[0][a * NMP + m] = Tab[(size_t(a) * ND + 0) * NM + m];
   }
   int iD = 0;
   for (int Dz = -NSR; Dz <= NSR; ++Dz) {
     // stage the moments of the source slab for this D_z: target layer lz
     // reads halo layer lz - Dz + NSR
     __syncthreads();
-    for (int h = tid; h < SLAB; h += 256) {
+    for (int h = tid; h < SLAB; h += NTH) {
       const int hx = h % H, hy = (h / H) % H, lz = h / (H * H);
       const int ex = (x0 - NSR + hx + 2 * n) % n, ey = (y0 - NSR + hy + 2 * n) % n;
       const int ez = (z0 + lz - Dz + 2 * n) % n;
@@ -107,82 +137,86 @@ __global__ __launch_bounds__(256, 2) void k_psi(int n, const double *__restrict_
       const bool more = iD + 1 < ND;
       if (more) {
 #pragma unroll
-        for (int r = 0; r < TPF; ++r) {
-          const int i = tid + 256 * r;
+        for (int q = 0; q < TPF; ++q) {
+          const int i = tid + NTH * q;
           if (i < TV) {
             const int a = i / NM, m = i % NM;
-            tp[r] = Tab[(size_t(a) * ND + iD + 1) * NM + m];
+            tp[q] = Tab[(size_t(a) * ND + iD + 1) * NM + m];
           }
         }
       }
-      if (comp) {
-        const T *tb = Ts[cur];
+      const T *tb = Ts[cur];
+      const int cb = ((2 * mh) * H + (aly - Dy + NSR)) * H + (alx - Dx + NSR);
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          T tv[MT];
+      for (int a0 = 0; a0 < 8; a0 += 4) {
+        const T av0 = Cs[(a0 + kq) * SLAB + cb];           // layer 2 mh
+        const T av1 = Cs[(a0 + kq) * SLAB + cb + H * H];   // layer 2 mh + 1
+        const T *brow = tb + (a0 + kq) * NMP + 16 * NTW * nh + r;
+        T bv[NTW];
 #pragma unroll
-          for (int j = 0; j < MT; ++j) tv[j] = tb[a * NM + m0 + j];
-          T cv[8];
+        for (int t = 0; t < NTW; ++t) bv[t] = brow[16 * t];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int lx = ex0 + (e & 1), ly = ey0 + ((e >> 1) & 1), lz = ez0 + (e >> 2);
-            cv[e] = Cs[a * SLAB + (lz * H + (ly - Dy + NSR)) * H + (lx - Dx + NSR)];
-          }
-#pragma unroll
-          for (int e = 0; e < 8; ++e)
-#pragma unroll
-            for (int j = 0; j < MT; ++j) acc[e][j] += tv[j] * cv[e];
+        for (int t = 0; t < NTW; ++t) {
+          acc[t] = M::step(av0, bv[t], acc[t]);
+          acc[NTW + t] = M::step(av1, bv[t], acc[NTW + t]);
         }
       }
       if (more) {
 #pragma unroll
-        for (int r = 0; r < TPF; ++r) {
-          const int i = tid + 256 * r;
-          if (i < TV) Ts[cur ^ 1][i] = tp[r];
+        for (int q = 0; q < TPF; ++q) {
+          const int i = tid + NTH * q;
+          if (i < TV) {
+            const int a = i / NM, m = i % NM;
+            Ts[cur ^ 1][a * NMP + m] = tp[q];
+          }
         }
       }
       __syncthreads();
     }
     if (kComp) {   // fold this slab's partial into the compensated total
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
+      for (int t = 0; t < 2 * NTW; ++t)
 #pragma unroll
-        for (int j = 0; j < MT; ++j) {
-          const T y = acc[e][j] - cmp[e][j];
-          const T t = tot[e][j] + y;
-          cmp[e][j] = (t - tot[e][j]) - y;
-          tot[e][j] = t;
-          acc[e][j] = T(0);
+        for (int v = 0; v < 4; ++v) {
+          const T y = acc[t][v] - cmp[t][v];
+          const T s = tot[t][v] + y;
+          cmp[t][v] = (s - tot[t][v]) - y;
+          tot[t][v] = s;
+          acc[t][v] = T(0);
         }
     }
   }
-  if (!comp) return;
   const int P = PO * n;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int ex = x0 + ex0 + (e & 1), ey = y0 + ey0 + ((e >> 1) & 1), ez = z0 + ez0 + (e >> 2);
-    if (ex >= n || ey >= n || ez >= n) continue;
-    const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
+  for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
-    for (int j = 0; j < MT; ++j) {
-      const int m = m0 + j;
+    for (int t = 0; t < NTW; ++t) {
+      const int ti = hh * NTW + t;
+      const int m = 16 * (NTW * nh + t) + r;
+      if (m >= NM) continue;
       const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
-      const int gx = (PO * ex + mx) % P, gy = (PO * ey + my) % P, gz = (PO * ez + mz) % P;
-      const double psi = kComp ? double(tot[e][j]) - double(cmp[e][j]) : double(acc[e][j]);
-      Wel[E * NM + m] = T(phi[(size_t(gz) * P + gy) * P + gx] - psi);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int e = M::row(lane, v);
+        const int ex = x0 + (e & 3), ey = y0 + (e >> 2), ez = z0 + 2 * mh + hh;
+        if (ex >= n || ey >= n || ez >= n) continue;
+        const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
+        const int gx = (PO * ex + mx) % P, gy = (PO * ey + my) % P, gz = (PO * ez + mz) % P;
+        const double psi = kComp ? double(tot[ti][v]) - double(cmp[ti][v]) : double(acc[ti][v]);
+        Wel[E * NM + m] = T(phi[(size_t(gz) * P + gy) * P + gx] - psi);
+      }
     }
-  }
 }
 
 template <class T>
 int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, const double *C, const T *Tab, const double *phi, T *Wel) {
   if (p != 5) return -1;
-  const int bricks = (n + 3) / 4;
-  dim3 g(nb * bricks * bricks * bricks);
+  const int bricks = (n + kPsiBS - 1) / kPsiBS, bricksz = (n + kPsiBZ - 1) / kPsiBZ;
+  dim3 g(nb * bricks * bricks * bricksz);
   switch (nsr) {
-    case 1: hipLaunchKernelGGL((k_psi<1, 5, T>), g, dim3(256), 0, s, n, C, Tab, phi, Wel); return 0;
-    case 2: hipLaunchKernelGGL((k_psi<2, 5, T>), g, dim3(256), 0, s, n, C, Tab, phi, Wel); return 0;
-    case 3: hipLaunchKernelGGL((k_psi<3, 5, T>), g, dim3(256), 0, s, n, C, Tab, phi, Wel); return 0;
+    case 1: hipLaunchKernelGGL((k_psi<1, 5, T>), g, dim3(kPsiThreads), 0, s, n, C, Tab, phi, Wel); return 0;
+    case 2: hipLaunchKernelGGL((k_psi<2, 5, T>), g, dim3(kPsiThreads), 0, s, n, C, Tab, phi, Wel); return 0;
+    case 3: hipLaunchKernelGGL((k_psi<3, 5, T>), g, dim3(kPsiThreads), 0, s, n, C, Tab, phi, Wel); return 0;
     default: return -1;
   }
 }
