@@ -221,14 +221,17 @@ struct fep3m_ctx {
   }
   // fine-level operator launch, bracketed by events when profiling
   template <class T>
-  int apply0(const T *x, const T *f, T *out, const T *d, T *xo, T c1, T c2, int mode, double *part) {
+  int apply0(const T *x, const T *f, T *out, const T *d, T *xo, T c1, T c2, int mode, double *part, T s0 = T(0)) {
     const bool rec = prof.on && prof.kused < int(prof.kev.size()) / 2;
     if (rec) hip_check(hipEventRecord(prof.kev[2 * prof.kused], stream), "event");
-    const int K = launch_apply<T>(stream, nb, lv[0].oper<T>(), x, f, out, d, xo, c1, c2, mode, part);
+    const int K = launch_apply<T>(stream, nb, lv[0].oper<T>(), x, f, out, d, xo, c1, c2, mode, part, s0);
     if (rec) {
       hip_check(hipEventRecord(prof.kev[2 * prof.kused + 1], stream), "event");
-      // vectors read + written: x, f, x_prev (when read) and x_new; x, f, r; x, Kx
-      const double vec = mode == kCheb ? ((c1 != T(0) && d) ? 4.0 : 3.0) : mode == kResidual ? 3.0 : 2.0;
+      // vectors read + written: x, f, x_prev (when read) and x_new; f and x_new (x built from f);
+      // x, f and x_new (x_prev built from f); x, f, r; x, Kx
+      const double vec = mode == kCheb ? ((c1 != T(0) && d) ? 4.0 : 3.0)
+                         : mode == kChebZ2 ? 2.0
+                         : (mode == kChebZ3 || mode == kResidual) ? 3.0 : 2.0;
       prof.kwork[prof.kused] = vec * double(sizeof(T)) * double(lv[0].ndof) * nb;
       prof.kslot[prof.kused] = sizeof(T) == 8 ? FEP3M_PROF_FINE_APPLY : FEP3M_PROF_FINE_APPLY_F32;
       ++prof.kused;
@@ -637,6 +640,7 @@ void fep3m_ctx::cheb_smooth(int l, const T *f, bool zero_start) {
   const double theta = 0.5 * (bmax + amin), delta = 0.5 * (bmax - amin), sigma = theta / delta;
   double rho = 1.0 / sigma;
   const int deg = opt.cheb_degree;
+  double s0 = 0.0;   // first-step coefficient: x1 = s0 D^-1 f after a zero start
   for (int s = 0; s < deg; ++s) {
     double c1, c2;
     if (s == 0) {
@@ -649,13 +653,18 @@ void fep3m_ctx::cheb_smooth(int l, const T *f, bool zero_start) {
       rho = rn;
     }
     if (s == 0 && zero_start) {
-      launch_cheb_first<T>(stream, nb, op, f, V.x, T(c2));   // x = c2 D^-1 f; x_prev = 0 (not stored)
+      s0 = c2;
+      // with later steps, the operator rebuilds x1 from f where it needs it
+      if (deg == 1) launch_cheb_first<T>(stream, nb, op, f, V.x, T(c2));   // x = c2 D^-1 f
     } else {
-      // x2 holds x_prev on entry (null: zero, after the first step from a zero
-      // start) and receives x_new; then the two swap
-      const T *xprev = (s == 1 && zero_start) ? nullptr : V.x2;
-      if (l == 0) apply0<T>(V.x, f, nullptr, xprev, V.x2, T(c1), T(c2), kCheb, nullptr);
-      else launch_apply<T>(stream, nb, op, V.x, f, nullptr, xprev, V.x2, T(c1), T(c2), kCheb, nullptr);
+      // x2 holds x_prev on entry and receives x_new; then the two swap.
+      // Steps 2 and 3 after a zero start take x1 (step 2: x; step 3: x_prev)
+      // as s0 D^-1 f instead of reading it.
+      const int mode = !zero_start ? kCheb : s == 1 ? kChebZ2 : s == 2 ? kChebZ3 : kCheb;
+      const T *xin = mode == kChebZ2 ? nullptr : V.x;
+      const T *xprev = (mode == kCheb) ? V.x2 : nullptr;
+      if (l == 0) apply0<T>(xin, f, nullptr, xprev, V.x2, T(c1), T(c2), mode, nullptr, T(s0));
+      else launch_apply<T>(stream, nb, op, xin, f, nullptr, xprev, V.x2, T(c1), T(c2), mode, nullptr, T(s0));
       std::swap(V.x, V.x2);
     }
   }

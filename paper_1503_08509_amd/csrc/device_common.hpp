@@ -94,7 +94,11 @@ enum ApplyMode : int {
   kResidual = 1,   // out = f - K x
   kCheb = 2,       // xo = x + c1 (x - xprev) + c2 D^-1 (f - K x)   (xo may alias xprev)
   kApplyDot = 3,   // out = K x, block partial of x . (K x)
-  kDinvApply = 4   // out = D^-1 K x
+  kDinvApply = 4,  // out = D^-1 K x
+  // Second and third Chebyshev steps after a zero start, whose first step
+  // x1 = s0 D^-1 f is never stored:
+  kChebZ2 = 5,     // as kCheb with x = s0 D^-1 f (built from f on the fly) and x_prev = 0
+  kChebZ3 = 6      // as kCheb with x_prev = s0 D^-1 f
 };
 
 }  // namespace fep3m

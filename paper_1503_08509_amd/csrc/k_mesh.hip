@@ -203,7 +203,7 @@ __device__ __forceinline__ void band_apply_acc(const T *__restrict__ a, const T 
 template <class T, int PO, int TE>
 __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restrict__ x, const T *__restrict__ f,
                                                T *__restrict__ out, const T *xprev, T *xo, T c1, T c2, int mode,
-                                               double *__restrict__ partial) {
+                                               double *__restrict__ partial, T s0) {
   using S = ApplyShape<PO, TE>;
   constexpr int O = S::O, I = S::I;
   static_assert(S::LDS * sizeof(T) >= 256 * sizeof(double), "the dot-product tree reuses the tile");
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
   {  // configuration of this tile: every vector moves to its block
     const int tiles3 = tiles * tiles * tiles;
     const size_t off = size_t(blockIdx.x / tiles3) * P * P * P;
-    x += off;
+    if (x) x += off;   // null in kChebZ2 mode
     if (f) f += off;
     if (out) out += off;
     if (xprev) xprev += off;
@@ -234,7 +234,8 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
   // Epilogue operands of this thread's owned nodes, fetched now so their
   // latency hides behind the three passes.
   constexpr int NIT = (O * O * O + 255) / 256;
-  const bool need_f = (mode == kResidual) || (mode == kCheb);
+  const bool zstart = (mode == kChebZ2);   // input columns are s0 D^-1 f
+  const bool need_f = (mode == kResidual) || (mode == kCheb) || zstart || (mode == kChebZ3);
   const bool need_d = (mode == kCheb) && (c1 != T(0)) && (xprev != nullptr);   // null x_prev reads as zero
   for (int i = tid; i < PO * PO * PO; i += 256) {
     const int kx = i % PO, ky = (i / PO) % PO, kz = i / (PO * PO);
@@ -256,14 +257,22 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
   }
 
   // pass z
+  if (zstart) __syncthreads();   // the z pass scales by the inverse diagonal
   if (tid < I * I) {
     const int lx = tid % I, ly = tid / I;
     const int gx = wrapi(ox0 - PO + lx, P), gy = wrapi(oy0 - PO + ly, P);
-    const T *col = x + (size_t(gy) * P + gx);   // this thread's (x, y) column
+    const T *col = (zstart ? f : x) + (size_t(gy) * P + gx);   // this thread's (x, y) column
     const size_t P2 = size_t(P) * P;
     T v[I];
 #pragma unroll
     for (int z = 0; z < I; ++z) v[z] = col[size_t(wrapi(oz0 - PO + z, P)) * P2];   // plane offset is block-uniform
+    if (zstart) {
+      // tile origins are multiples of PO, so the local node index of input
+      // (lx, ly, z) along each axis is its tile offset mod PO
+      const T *id = invd + (lx % PO) + PO * (ly % PO);
+#pragma unroll
+      for (int z = 0; z < I; ++z) v[z] *= s0 * id[PO * PO * (z % PO)];
+    }
     if (lx >= PO && lx < PO + O && ly >= PO && ly < PO + O) {
 #pragma unroll
       for (int oz = 0; oz < O; ++oz) Xo[(oz * O + (ly - PO)) * O + (lx - PO)] = v[oz + PO];
@@ -325,13 +334,15 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
     const int cx = lc % O, cy = (lc / O) % O, cz = lc / (O * O);
     const T y = Y[(cz * O + cy) * S::YS + cx];
     const T xv = Xo[lc];
-    const T rr = (pf_f[r] - y) * invd[(ox % PO) + PO * ((oy % PO) + PO * (oz % PO))];
+    const T id = invd[(ox % PO) + PO * ((oy % PO) + PO * (oz % PO))];
+    const T rr = (pf_f[r] - y) * id;
     const size_t g = tbase + unsigned((oz * P + oy) * P + ox);
     if (ok) {
       if (mode == kApply) out[g] = y;
       else if (mode == kResidual) out[g] = pf_f[r] - y;
-      else if (mode == kCheb) xo[g] = xv + c1 * (xv - pf_d[r]) + c2 * rr;  // may overwrite x_prev
-      else if (mode == kDinvApply) out[g] = -rr;                            // f = 0 here: -rr = D^-1 K x
+      else if (mode == kCheb || zstart) xo[g] = xv + c1 * (xv - pf_d[r]) + c2 * rr;   // may overwrite x_prev
+      else if (mode == kChebZ3) xo[g] = xv + c1 * (xv - s0 * id * pf_f[r]) + c2 * rr;
+      else if (mode == kDinvApply) out[g] = -rr;                                       // f = 0 here: -rr = D^-1 K x
       else { out[g] = y; acc += double(xv) * double(y); }
     }
   }
@@ -813,22 +824,22 @@ void launch_sub_const(hipStream_t s, int nb, size_t per, double invV, const doub
 
 template <class T, int PO, int TE>
 static int apply_impl(hipStream_t s, int nb, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *d, T *xo,
-                      T c1, T c2, int mode, double *partial) {
+                      T c1, T c2, int mode, double *partial, T s0) {
   const int tiles = (op.n + TE - 1) / TE;
   const int K = tiles * tiles * tiles;
   hipLaunchKernelGGL((k_apply<T, PO, TE>), dim3(nb * K), dim3(256), 0, s, op, x, f, out, d, xo, c1, c2, mode,
-                     partial);
+                     partial, s0);
   return K;
 }
 
 template <class T>
 int launch_apply(hipStream_t s, int nb, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *d, T *xo,
-                 T c1, T c2, int mode, double *partial) {
+                 T c1, T c2, int mode, double *partial, T s0) {
   switch (op.p) {
-    case 1: return apply_impl<T, 1, 8>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial);
-    case 2: return apply_impl<T, 2, 4>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial);
-    case 3: return apply_impl<T, 3, 3>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial);
-    case 5: return apply_impl<T, 5, 2>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial);
+    case 1: return apply_impl<T, 1, 8>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
+    case 2: return apply_impl<T, 2, 4>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
+    case 3: return apply_impl<T, 3, 3>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
+    case 5: return apply_impl<T, 5, 2>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
     default: return -1;
   }
 }
@@ -884,7 +895,7 @@ void launch_coarse_solve(hipStream_t s, int nb, int Pn, const double *V, const d
 
 #define FEP3M_MESH_INSTANTIATE(T)                                                                                   \
   template int launch_apply<T>(hipStream_t, int, const LevelOpT<T> &, const T *, const T *, T *, const T *, T *, T, \
-                               T, int, double *);                                                                   \
+                               T, int, double *, T);                                                                \
   template void launch_cheb_first<T>(hipStream_t, int, const LevelOpT<T> &, const T *, T *, T);                     \
   template int launch_transfer<T>(hipStream_t, int, const TransferT<T> &, const T *, T *, bool);                    \
   template void launch_coarse_solve<T>(hipStream_t, int, int, const double *, const double *, const T *, T *);

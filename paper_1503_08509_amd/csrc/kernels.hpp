@@ -88,10 +88,11 @@ void launch_mass_dot(hipStream_t s, int nb, int n, int p, const double *w1, cons
 void launch_sub_const(hipStream_t s, int nb, size_t per, double invV, const double *scal, double *v);
 // Multigrid kernels in the arithmetic type T (double, or float for the
 // mixed-precision preconditioner); instantiated for both in k_mesh.hip.
-// launch_apply returns its blocks per configuration (the K of kApplyDot).
+// launch_apply returns its blocks per configuration (the K of kApplyDot);
+// s0 is the first-step coefficient of the kChebZ2 / kChebZ3 modes.
 template <class T>
 int launch_apply(hipStream_t s, int nb, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *xprev, T *xo,
-                 T c1, T c2, int mode, double *partial);
+                 T c1, T c2, int mode, double *partial, T s0 = T(0));
 int apply_blocks(const LevelOp &op);
 template <class T>
 void launch_cheb_first(hipStream_t s, int nb, const LevelOpT<T> &op, const T *f, T *x, T c2);
