@@ -323,8 +323,13 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
     for (int ox = 0; ox < O; ++ox) Y[(oz * O + oy) * S::YS + ox] = yv[ox];
   }
   __syncthreads();
-  // epilogue on the owned nodes, x fastest
+  // epilogue on the owned nodes, x fastest: every result and address first,
+  // then the stores back to back (a store whose registers the next one
+  // reused would make it wait for the earlier store)
   double acc = 0.0;
+  T res[NIT];
+  T *dst[NIT];
+  T *const base = (mode == kCheb || zstart || mode == kChebZ3) ? xo : out;   // xo may overwrite x_prev
 #pragma unroll
   for (int r = 0; r < NIT; ++r) {
     const int li = tid + 256 * r;
@@ -336,16 +341,20 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
     const T xv = Xo[lc];
     const T id = invd[(ox % PO) + PO * ((oy % PO) + PO * (oz % PO))];
     const T rr = (pf_f[r] - y) * id;
-    const size_t g = tbase + unsigned((oz * P + oy) * P + ox);
-    if (ok) {
-      if (mode == kApply) out[g] = y;
-      else if (mode == kResidual) out[g] = pf_f[r] - y;
-      else if (mode == kCheb || zstart) xo[g] = xv + c1 * (xv - pf_d[r]) + c2 * rr;   // may overwrite x_prev
-      else if (mode == kChebZ3) xo[g] = xv + c1 * (xv - s0 * id * pf_f[r]) + c2 * rr;
-      else if (mode == kDinvApply) out[g] = -rr;                                       // f = 0 here: -rr = D^-1 K x
-      else { out[g] = y; acc += double(xv) * double(y); }
-    }
+    T v;
+    if (mode == kApply || mode == kApplyDot) v = y;
+    else if (mode == kResidual) v = pf_f[r] - y;
+    else if (mode == kCheb || zstart) v = xv + c1 * (xv - pf_d[r]) + c2 * rr;
+    else if (mode == kChebZ3) v = xv + c1 * (xv - s0 * id * pf_f[r]) + c2 * rr;
+    else v = -rr;                                                          // kDinvApply (f = 0): D^-1 K x
+    if (ok && mode == kApplyDot) acc += double(xv) * double(y);
+    res[r] = v;
+    asm volatile("" : "+v"(res[r]));   // computed here, in registers of its own
+    dst[r] = ok ? base + (tbase + unsigned((oz * P + oy) * P + ox)) : nullptr;
   }
+#pragma unroll
+  for (int r = 0; r < NIT; ++r)
+    if (dst[r]) *dst[r] = res[r];
   if (mode == kApplyDot) {
     __syncthreads();  // every thread is done with Y before the tree reuses it
     double s = block_sum(acc, reinterpret_cast<double *>(lds));
@@ -540,13 +549,22 @@ __global__ __launch_bounds__(256) void k_prolong_add(TransferT<T> tr, const T *_
     for (int f = 0; f < FO; ++f) Out[(fz * FO + fy) * FO + f] = o[f];
   }
   __syncthreads();
+  // every address and sum first, then the stores back to back: a store
+  // whose registers are reused by the next one would make it wait
+  T *dst[NIT];
 #pragma unroll
   for (int r = 0; r < NIT; ++r) {
     const int li = tid + 256 * r;
     const int fx = li % FO, fy = (li / FO) % FO, fz = li / (FO * FO);
     const int gx = NS * TE * tx + fx, gy = NS * TE * ty + fy, gz = NS * TE * tz + fz;
-    if (li < FO * FO * FO && gx < Pf && gy < Pf && gz < Pf) xf[(size_t(gz) * Pf + gy) * Pf + gx] = pf[r] + Out[li];
+    const bool ok = li < FO * FO * FO && gx < Pf && gy < Pf && gz < Pf;
+    dst[r] = ok ? xf + ((size_t(gz) * Pf + gy) * Pf + gx) : nullptr;
+    pf[r] += Out[ok ? li : 0];
+    asm volatile("" : "+v"(pf[r]));   // keep each sum in its own registers, computed here
   }
+#pragma unroll
+  for (int r = 0; r < NIT; ++r)
+    if (dst[r]) *dst[r] = pf[r];
 }
 
 // ----------------------------------------------------------------- coarse solve
@@ -838,14 +856,14 @@ int launch_apply(hipStream_t s, int nb, const LevelOpT<T> &op, const T *x, const
   switch (op.p) {
     case 1: return apply_impl<T, 1, 8>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
     case 2: return apply_impl<T, 2, 4>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
-    case 3: return apply_impl<T, 3, 3>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
+    case 3: return apply_impl<T, 3, 4>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
     case 5: return apply_impl<T, 5, 2>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
     default: return -1;
   }
 }
 
 int apply_blocks(const LevelOp &op) {
-  int TE = op.p == 1 ? 8 : op.p == 2 ? 4 : op.p == 3 ? 3 : 2;
+  int TE = op.p == 1 ? 8 : op.p == 2 ? 4 : op.p == 3 ? 4 : 2;
   int tiles = (op.n + TE - 1) / TE;
   return tiles * tiles * tiles;
 }
