@@ -27,6 +27,7 @@ METRIC = "pair interactions/s + N=1M energy+force time at 1e-6 rel. RMS err vs E
 PEAK_FP64_TFLOPS = 78.6     # MI355X vector FP64 (256 CU x 2.4 GHz x 128 FLOP/clk); also dense FP64 MFMA
 PEAK_MFMA_FP32_TFLOPS = 157.3   # MI355X dense FP32 MFMA
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+OPERATOR_FLOP_PER_DOF = 98.0
 
 
 def parse():
@@ -47,6 +48,17 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 256 MiB (FETCH_SIZE/WRITE_SIZE calibration) and exit")
     return ap.parse_args()
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(x, Q, w, sample, F_gpu):
@@ -107,6 +119,7 @@ def cpu_baseline(x, Q, w, sample, F_gpu):
         "value": pairs / t_step,
         "unit": "pair interactions/s",
         "cores": int(threads),
+        "cpu_model": _cpu_model(),
         "kind": "oracle",
         "sample": (f"energy+forces; mesh side in full ({t_fixed:.1f} s: binning, moments, load, exact periodic "
                    f"solve, charge deposit, assembly, exact adjoint solve), per-charge side for {len(tgt)} of "
@@ -179,6 +192,27 @@ def load_workload(name):
     w = workloads.WORKLOADS[name]
     x, Q = workloads.make(w)
     return name, w.L, [w.N], w.n, x, Q
+
+
+def stream_copy_gbs():
+    """Practical HBM rate on this device: a 1 GiB device-to-device copy
+    (reads and writes 1 GiB), best of 5, timed with events on the current
+    stream."""
+    import torch
+    a = torch.ones(2**27, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return 2 * 2**30 / (best * 1e-3) / 1e9
 
 
 def kernel_rooflines(prof, steps, mixed):
@@ -340,6 +374,22 @@ def main():
     r = measure(args.workload, args.precision, args.steps, args.warmup, forces)
     mixed = args.precision == "mixed"
     kernels = r["kernels"]
+    practical = stream_copy_gbs() if not args.no_variants else None   # kept out of profiled runs
+    for k, v in kernels.items():
+        if v["bound"] == "hbm" and practical:
+            v["practical_peak"] = practical
+            v["frac_practical"] = v["achieved"] / practical
+    op = kernels.get("k_apply p=5 (fine-level operator)")
+    if op:
+        # the operator's own arithmetic: sum-factorised Kronecker-sum apply,
+        # 7 one-dimensional band passes of 7 multiply-adds per node on average
+        # (6 taps inside an element, 11 at a vertex) = 98 FLOP per DOF
+        dofs = (5 * r["n"]) ** 3 * len(r["counts"])
+        tf = OPERATOR_FLOP_PER_DOF * dofs / (op["avg_launch_ms"] * 1e-3) / 1e12
+        op["flop_achieved"] = tf
+        op["flop_peak"] = PEAK_FP64_TFLOPS   # the PCG operator is float64 in both precisions
+        op["flop_frac"] = tf / op["flop_peak"]
+        op["flop_unit"] = "TFLOP/s (98 FLOP per DOF)"
     dominant = max(kernels, key=lambda k: kernels[k]["avg_launch_ms"] * kernels[k]["launches_per_step"])
     roof = dict(kernels[dominant])
     roof["kernel"] = dominant
@@ -371,6 +421,8 @@ def main():
         "mg_iterations": st["mg_iterations"],
         "adj_mg_iterations": st["adj_iterations"] if forces else None,
         "mg_rel_residual": st["mg_rel_residual"],
+        "create_seconds": st["create_seconds"],
+        "practical_hbm_gbs": practical,
         "pair_variant": variant_summary(r)["pair_variant"],
         "U": [float(u) for u in np.atleast_1d(r["out"]["U"])][:4],
     }
@@ -396,6 +448,15 @@ def main():
         ug = measure("uniform-1M-n64", "fp64", 3, 2, graph=True)
         variants["fp64 uniform-1M-n64 hipGraph"] = variant_summary(ug, r)
         del ug
+        # the smaller configurations: 1000 charges on 8^3, 1e5 on 32^3 (FP64 and mixed side by side)
+        for wl in ("uniform-1k-n8", "uniform-100k-n32"):
+            s64 = measure(wl, "fp64", 5, 2)
+            variants["fp64 " + wl] = variant_summary(s64)
+            sm = measure(wl, "mixed", 5, 2)
+            variants["mixed " + wl] = variant_summary(sm, s64)
+            sg = measure(wl, "fp64", 5, 2, graph=True)   # small problems: launches and host reads dominate
+            variants["fp64 " + wl + " hipGraph"] = variant_summary(sg, s64)
+            del s64, sm, sg
         # the exact fast-diagonalisation mesh solver in place of multigrid
         for prec, wl in (("fp64", "uniform-1M-n64"), ("mixed", "uniform-1M-n64"), ("fp64", BATCH_WORKLOAD)):
             fd = measure(wl, prec, 3, 1, solver=1)

@@ -107,6 +107,15 @@ __global__ __launch_bounds__(256) void k_assemble(int n, int K, const double *__
 //            loads the 2 NSR + 8 sources its row sees into registers once
 //            and slides over D_x,
 //   the 8 node lanes are reduced with shuffles at the end.
+// v mod n for v in [-n, 3n), without an integer division (n is a run-time
+// value, so v % n would cost a full division sequence per use).
+__device__ __forceinline__ int wrap3(int v, int n) {
+  v += v < 0 ? n : 0;
+  v -= v >= n ? n : 0;
+  v -= v >= n ? n : 0;
+  return v;
+}
+
 template <int NSR, int PO>
 __global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__restrict__ gE,
                                                      const double *__restrict__ Tt, const double *__restrict__ lam,
@@ -159,8 +168,8 @@ __global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__r
       const int mm = i % MC, h = i / MC;
       const int m = ch * MC + mm;
       const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-      const int ex = (x0 - NSR + hx + 2 * n) % n, ey = (y0 - NSR + hy + 2 * n) % n;
-      const int ez = (z0 + hz + Dz + 2 * n) % n;
+      const int ex = wrap3(x0 - NSR + hx, n), ey = wrap3(y0 - NSR + hy, n);
+      const int ez = wrap3(z0 + hz + Dz, n);
       gpf[r] = (i < MC * SLAB && m < NM) ? gE[(size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NM + m] : 0.0;
     }
   };
@@ -232,7 +241,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__r
   double a1[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int mm = 0; mm < NM; ++mm) {
     const int mx = mm % Q1, my = (mm / Q1) % Q1, mz = mm / (Q1 * Q1);
-    const int gx = (PO * ex + mx) % P, gy = (PO * ey + my) % P, gz = (PO * ez + mz) % P;
+    const int gx = wrap3(PO * ex + mx, P), gy = wrap3(PO * ey + my, P), gz = wrap3(PO * ez + mz, P);
     const double lv = lam[(size_t(gz) * P + gy) * P + gx];
     const double gx0 = gw[mx], gx1 = gw[Q1 + mx], gy0 = gw[my], gy1 = gw[Q1 + my], gz0 = gw[mz], gz1 = gw[Q1 + mz];
     a1[0] += lv * gx0 * gy0 * gz0;
