@@ -91,7 +91,7 @@ enum CfgScalar : int {
   kCsQ = 0,        // sum Q
   kCsQabs = 1,     // sum |Q|
   kCsLoad = 2,     // sum b (compatibility projection of the load)
-  kCsInt = 3,      // integral of the last mesh solution (gauge)
+  kCsSpare = 3,    // unused (the gauge integrals have a buffer of 2 nb values)
   kCsEnergy = 4,   // sum Q Phi
   kCsAdjLoad = 5,  // sum G (compatibility projection of the deposit)
   kCsPcg = 6,      // 10 PCG scalars from here
@@ -108,7 +108,14 @@ struct fep3m_ctx {
   std::vector<int> off_h;       // first charge of each configuration (nb + 1 entries)
   int *off_d = nullptr;
   double *cs = nullptr, *host_cs = nullptr;   // per-configuration scalars (device, pinned mirror)
-  PcgScalars pcs{};
+  // Systems in the current mesh solve: nb, or 2 nb when the forward and the
+  // adjoint systems of every configuration are solved together (the adjoint
+  // right side does not depend on phi).  Their vectors are consecutive
+  // blocks: b then G, phi then lambda.
+  int nbs = 1;
+  PcgScalars pcs{};                 // 2 nb values per scalar
+  double *gauge = nullptr;          // 2 nb integrals of the solutions (gauge)
+  bool lam_ready = false;           // the last forward call also solved for lambda
   double *cfgs(int slot) const { return cs + size_t(slot) * nb; }
   int n = 0, q = 3, p = 5, d = 1, nsr = 3, B = 15;
   fep3m_options opt{};
@@ -224,7 +231,7 @@ struct fep3m_ctx {
   int apply0(const T *x, const T *f, T *out, const T *d, T *xo, T c1, T c2, int mode, double *part, T s0 = T(0)) {
     const bool rec = prof.on && prof.kused < int(prof.kev.size()) / 2;
     if (rec) hip_check(hipEventRecord(prof.kev[2 * prof.kused], stream), "event");
-    const int K = launch_apply<T>(stream, nb, lv[0].oper<T>(), x, f, out, d, xo, c1, c2, mode, part, s0);
+    const int K = launch_apply<T>(stream, nbs, lv[0].oper<T>(), x, f, out, d, xo, c1, c2, mode, part, s0);
     if (rec) {
       hip_check(hipEventRecord(prof.kev[2 * prof.kused + 1], stream), "event");
       // vectors read + written: x, f, x_prev (when read) and x_new; f and x_new (x built from f);
@@ -232,7 +239,7 @@ struct fep3m_ctx {
       const double vec = mode == kCheb ? ((c1 != T(0) && d) ? 4.0 : 3.0)
                          : mode == kChebZ2 ? 2.0
                          : (mode == kChebZ3 || mode == kResidual) ? 3.0 : 2.0;
-      prof.kwork[prof.kused] = vec * double(sizeof(T)) * double(lv[0].ndof) * nb;
+      prof.kwork[prof.kused] = vec * double(sizeof(T)) * double(lv[0].ndof) * nbs;
       prof.kslot[prof.kused] = sizeof(T) == 8 ? FEP3M_PROF_FINE_APPLY : FEP3M_PROF_FINE_APPLY_F32;
       ++prof.kused;
     }
@@ -264,7 +271,9 @@ struct fep3m_ctx {
   void solve(const double *rhs, double *out, int which);
   void fdm_solve(const double *rhs, double *out, int which);
   void build_fdm();
-  void mesh_solve(double *rhs, double *out, int which);
+  void mesh_solve(double *rhs, double *out, int which, int nsys = 1);
+  void adjoint_rhs();
+  void store_rel(int which);
   void run_once(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ);
   void finish_host();
   void evaluate_graph(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ);
@@ -318,12 +327,15 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   const int M = n * n * n;
   off_d = alloc<int>(off_h.size(), "configuration offsets");
   hip_check(hipMemcpy(off_d, off_h.data(), off_h.size() * sizeof(int), hipMemcpyHostToDevice), "upload offsets");
+  nbs = nb;
   cs = alloc<double>(size_t(kCsSlots) * nb, "configuration scalars");
   hip_check(hipHostMalloc(reinterpret_cast<void **>(&host_cs), size_t(kCsSlots) * nb * sizeof(double),
                           hipHostMallocDefault), "pinned configuration scalars");
   {
     double **slots[] = {&pcs.bn2, &pcs.rz, &pcs.rzn, &pcs.pq, &pcs.rr, &pcs.zq, &pcs.alpha, &pcs.beta, &pcs.act, &pcs.rel};
-    for (int k = 0; k < 10; ++k) *slots[k] = cfgs(kCsPcg + k);
+    double *pbuf = alloc<double>(size_t(10) * 2 * nb, "pcg scalars");
+    for (int k = 0; k < 10; ++k) *slots[k] = pbuf + size_t(k) * 2 * nb;
+    gauge = alloc<double>(size_t(2) * nb, "gauge integrals");
   }
   T = alloc<double>(T_host.size(), "tables");
   gw = alloc<double>(gwh.size(), "load weights");
@@ -389,7 +401,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   if (opt.solver == FEP3M_SOLVER_FDM) build_fdm();
   // partials serve every two-stage reduction: the fixed reduction grids and
   // the per-tile partials of the fine-level operator
-  partial_len = std::max(partial_len, size_t(nb) * apply_blocks(lv[0].op) + 64);
+  partial_len = std::max(partial_len, size_t(2) * nb * apply_blocks(lv[0].op) + 64);
   partial = alloc<double>(partial_len, "partials");
   estimate_spectra();
   auto t1 = std::chrono::steady_clock::now();
@@ -465,7 +477,7 @@ void fep3m_ctx::build_mg() {
     tr.push_back(make_transfer(hier[i].first, hier[i].second, hier[i + 1].first, hier[i + 1].second));
   for (size_t i = 0; i < lv.size(); ++i) {
     MGLevel &L_ = lv[i];
-    const size_t nv = L_.ndof * nb;   // one block of the level per configuration
+    const size_t nv = L_.ndof * 2 * nb;   // one block of the level per system (forward and adjoint)
     L_.vd.x = alloc<double>(nv, "mg x");
     if (i + 1 < lv.size()) L_.d = alloc<double>(L_.ndof, "mg d");
     if (!mixed) {
@@ -491,16 +503,16 @@ void fep3m_ctx::build_mg() {
   }
   const size_t nd0 = lv[0].ndof * nb;
   gE = alloc<double>(size_t(nb) * n * n * n * (p + 1) * (p + 1) * (p + 1), "deposit");
-  Gv = alloc<double>(nd0, "adjoint load");
-  lam = alloc<double>(nd0, "adjoint potential");
+  b = alloc<double>(2 * nd0, "load, adjoint load");
+  Gv = b + nd0;
+  sol = alloc<double>(2 * nd0, "phi, lambda");
+  lam = sol + nd0;
   Aadj = alloc<double>(size_t(nb) * n * n * n * 8, "moment adjoint");
   fpair = alloc<double>(3 * size_t(N), "pair forces");
   Phi_int = alloc<double>(size_t(N), "potential (caller order)");
-  b = alloc<double>(nd0, "load");
-  sol = alloc<double>(nd0, "phi");
-  rr = alloc<double>(nd0, "pcg r");
-  pv = alloc<double>(nd0, "pcg p");
-  qv = alloc<double>(nd0, "pcg q");
+  rr = alloc<double>(2 * nd0, "pcg r");
+  pv = alloc<double>(2 * nd0, "pcg p");
+  qv = alloc<double>(2 * nd0, "pcg q");
   // coarse level: 1-D periodic pencil K1 V = M1 V Lambda
   {
     const LevelOp &op = lv.back().op;
@@ -562,43 +574,43 @@ void blas_check(rocblas_status s, const char *what) {
 // is measured with one operator apply, as for the iterative solver.
 void fep3m_ctx::fdm_solve(const double *rhs, double *sol, int which) {
   const int P = lv[0].op.P;
-  const size_t per = lv[0].ndof, nd = per * nb;
+  const size_t per = lv[0].ndof, nd = per * nbs;
   const rocblas_int iP = P, iP2 = P * P;
   const double one = 1.0, zero = 0.0;
   blas_check(rocblas_set_stream(blas, stream), "rocblas stream");
   double *A = rr, *B = pv;
   // forward: x, y, z
-  blas_check(rocblas_dgemm(blas, rocblas_operation_transpose, rocblas_operation_none, iP, rocblas_int(nb) * iP2, iP,
+  blas_check(rocblas_dgemm(blas, rocblas_operation_transpose, rocblas_operation_none, iP, rocblas_int(nbs) * iP2, iP,
                            &one, fdmV, iP, rhs, iP, &zero, A, iP), "fdm x");
   blas_check(rocblas_dgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_none, iP, iP, iP, &one, A,
                                            iP, rocblas_stride(iP2), fdmV, iP, 0, &zero, B, iP, rocblas_stride(iP2),
-                                           rocblas_int(nb) * iP), "fdm y");
+                                           rocblas_int(nbs) * iP), "fdm y");
   blas_check(rocblas_dgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_none, iP2, iP, iP, &one, B,
                                            iP2, rocblas_stride(per), fdmV, iP, 0, &zero, A, iP2, rocblas_stride(per),
-                                           rocblas_int(nb)), "fdm z");
+                                           rocblas_int(nbs)), "fdm z");
   launch_fdm_scale(stream, nd, P, fdm_i0, fdmLam, A);
   // inverse: z, y, x
   blas_check(rocblas_dgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_transpose, iP2, iP, iP, &one,
                                            A, iP2, rocblas_stride(per), fdmV, iP, 0, &zero, B, iP2,
-                                           rocblas_stride(per), rocblas_int(nb)), "fdm z back");
+                                           rocblas_stride(per), rocblas_int(nbs)), "fdm z back");
   blas_check(rocblas_dgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_transpose, iP, iP, iP, &one,
                                            B, iP, rocblas_stride(iP2), fdmV, iP, 0, &zero, A, iP,
-                                           rocblas_stride(iP2), rocblas_int(nb) * iP), "fdm y back");
-  blas_check(rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, iP, rocblas_int(nb) * iP2, iP, &one,
+                                           rocblas_stride(iP2), rocblas_int(nbs) * iP), "fdm y back");
+  blas_check(rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, iP, rocblas_int(nbs) * iP2, iP, &one,
                            fdmV, iP, A, iP, &zero, sol, iP), "fdm x back");
   // achieved residual, per configuration
-  launch_sum_partials(stream, launch_dot(stream, nb, per, rhs, rhs, partial), partial, pcs.bn2, nb);
+  launch_sum_partials(stream, launch_dot(stream, nbs, per, rhs, rhs, partial), partial, pcs.bn2, nbs);
   apply0<double>(sol, rhs, qv, nullptr, nullptr, 0.0, 0.0, kResidual, nullptr);
-  launch_sum_partials(stream, launch_dot(stream, nb, per, qv, qv, partial), partial, pcs.rr, nb);
-  launch_pcg_scalars(stream, nb, kPcgStart, 0.0, pcs);
-  launch_pcg_scalars(stream, nb, kPcgResid, 0.0, pcs);
-  launch_copy_f64(stream, nb, pcs.rel, cfgs(which ? kCsAdjRel : kCsFwdRel));
+  launch_sum_partials(stream, launch_dot(stream, nbs, per, qv, qv, partial), partial, pcs.rr, nbs);
+  launch_pcg_scalars(stream, nbs, kPcgStart, 0.0, pcs);
+  launch_pcg_scalars(stream, nbs, kPcgResid, 0.0, pcs);
+  store_rel(which);
   check_launch("fdm solve");
   if (capturing) return;
-  hip_check(hipMemcpyAsync(host_cs, pcs.rel, nb * sizeof(double), hipMemcpyDeviceToHost, stream), "copy residuals");
+  hip_check(hipMemcpyAsync(host_cs, pcs.rel, nbs * sizeof(double), hipMemcpyDeviceToHost, stream), "copy residuals");
   sync("fdm residual");
   double relmax = 0.0;
-  for (int bb = 0; bb < nb; ++bb) relmax = std::max(relmax, host_cs[bb]);
+  for (int bb = 0; bb < nbs; ++bb) relmax = std::max(relmax, host_cs[bb]);
   stats.mg_iterations = 0;
   stats.mg_rel_residual = relmax;
   if (!(relmax <= 1e-9))
@@ -655,7 +667,7 @@ void fep3m_ctx::cheb_smooth(int l, const T *f, bool zero_start) {
     if (s == 0 && zero_start) {
       s0 = c2;
       // with later steps, the operator rebuilds x1 from f where it needs it
-      if (deg == 1) launch_cheb_first<T>(stream, nb, op, f, V.x, T(c2));   // x = c2 D^-1 f
+      if (deg == 1) launch_cheb_first<T>(stream, nbs, op, f, V.x, T(c2));   // x = c2 D^-1 f
     } else {
       // x2 holds x_prev on entry and receives x_new; then the two swap.
       // Steps 2 and 3 after a zero start take x1 (step 2: x; step 3: x_prev)
@@ -664,7 +676,7 @@ void fep3m_ctx::cheb_smooth(int l, const T *f, bool zero_start) {
       const T *xin = mode == kChebZ2 ? nullptr : V.x;
       const T *xprev = (mode == kCheb) ? V.x2 : nullptr;
       if (l == 0) apply0<T>(xin, f, nullptr, xprev, V.x2, T(c1), T(c2), mode, nullptr, T(s0));
-      else launch_apply<T>(stream, nb, op, xin, f, nullptr, xprev, V.x2, T(c1), T(c2), mode, nullptr, T(s0));
+      else launch_apply<T>(stream, nbs, op, xin, f, nullptr, xprev, V.x2, T(c1), T(c2), mode, nullptr, T(s0));
       std::swap(V.x, V.x2);
     }
   }
@@ -676,17 +688,17 @@ void fep3m_ctx::vcycle(int l, const T *f) {
   MGLevel &L_ = lv[l];
   LevelVecs<T> &V = L_.vec<T>();
   if (l + 1 == int(lv.size())) {
-    launch_coarse_solve<T>(stream, nb, coarseP, coarseV, coarseLam, f, V.x);
+    launch_coarse_solve<T>(stream, nbs, coarseP, coarseV, coarseLam, f, V.x);
     return;
   }
   const LevelOpT<T> &op = L_.oper<T>();
   LevelVecs<T> &Vc = lv[l + 1].vec<T>();
   cheb_smooth<T>(l, f, true);
   if (l == 0) apply0<T>(V.x, f, V.r, nullptr, nullptr, T(0), T(0), kResidual, nullptr);
-  else launch_apply<T>(stream, nb, op, V.x, f, V.r, nullptr, nullptr, T(0), T(0), kResidual, nullptr);
-  launch_transfer<T>(stream, nb, transfer<T>(l), V.r, Vc.f, true);
+  else launch_apply<T>(stream, nbs, op, V.x, f, V.r, nullptr, nullptr, T(0), T(0), kResidual, nullptr);
+  launch_transfer<T>(stream, nbs, transfer<T>(l), V.r, Vc.f, true);
   vcycle<T>(l + 1, Vc.f);
-  launch_transfer<T>(stream, nb, transfer<T>(l), Vc.x, V.x, false);
+  launch_transfer<T>(stream, nbs, transfer<T>(l), Vc.x, V.x, false);
   cheb_smooth<T>(l, f, false);
 }
 
@@ -707,29 +719,29 @@ void fep3m_ctx::solve(const double *rhs, double *sol, int which) {
     return;
   }
   MGLevel &L0 = lv[0];
-  const size_t per = L0.ndof, nd = per * nb;
+  const size_t per = L0.ndof, nd = per * nbs;
   launch_fill_f64(stream, nd, 0.0, sol);
   launch_copy_f64(stream, nd, rhs, rr);
-  launch_sum_partials(stream, launch_dot(stream, nb, per, rhs, rhs, partial), partial, pcs.bn2, nb);
+  launch_sum_partials(stream, launch_dot(stream, nbs, per, rhs, rhs, partial), partial, pcs.bn2, nbs);
   // z = M^-1 r; rzn = z . r (and zq = z . q when q is given)
   auto precondition = [&](const double *q) {
     if (!mixed) {
       vcycle<double>(0, rr);
-      launch_sum_partials(stream, launch_dot(stream, nb, per, rr, L0.vd.x, partial), partial, pcs.rzn, nb);
+      launch_sum_partials(stream, launch_dot(stream, nbs, per, rr, L0.vd.x, partial), partial, pcs.rzn, nbs);
     } else {
       launch_to_f32(stream, nd, rr, L0.vf.f);
       vcycle<float>(0, L0.vf.f);
-      const int K = launch_dot2_f32(stream, nb, per, L0.vf.x, rr, q, dot_scr);
-      launch_sum_partials(stream, K, dot_scr, pcs.rzn, nb);
-      launch_sum_partials(stream, K, dot_scr + size_t(nb) * K, pcs.zq, nb);
+      const int K = launch_dot2_f32(stream, nbs, per, L0.vf.x, rr, q, dot_scr);
+      launch_sum_partials(stream, K, dot_scr, pcs.rzn, nbs);
+      launch_sum_partials(stream, K, dot_scr + size_t(nbs) * K, pcs.zq, nbs);
     }
   };
   auto set_p = [&] {   // p = z + beta p
-    if (!mixed) launch_xpay(stream, nb, per, pcs.beta, L0.vd.x, pv);
-    else launch_xpay_f32(stream, nb, per, pcs.beta, L0.vf.x, pv);
+    if (!mixed) launch_xpay(stream, nbs, per, pcs.beta, L0.vd.x, pv);
+    else launch_xpay_f32(stream, nbs, per, pcs.beta, L0.vf.x, pv);
   };
   precondition(nullptr);
-  launch_pcg_scalars(stream, nb, kPcgStart, 0.0, pcs);   // act = (b != 0), beta = 0, rz = z . r
+  launch_pcg_scalars(stream, nbs, kPcgStart, 0.0, pcs);   // act = (b != 0), beta = 0, rz = z . r
   set_p();
   // Eagerly, the host reads the residuals after every iteration and stops
   // once all configurations have converged.  Under graph capture the loop
@@ -741,26 +753,26 @@ void fep3m_ctx::solve(const double *rhs, double *sol, int which) {
   int it = 0;
   for (it = 1; it <= opt.mg_max_iter; ++it) {
     const int Ka = apply0<double>(pv, nullptr, qv, nullptr, nullptr, 0.0, 0.0, kApplyDot, partial);
-    launch_sum_partials(stream, Ka, partial, pcs.pq, nb);
-    launch_pcg_scalars(stream, nb, kPcgAlpha, 0.0, pcs);
-    launch_sum_partials(stream, launch_cg_update(stream, nb, per, pcs.alpha, pv, qv, sol, rr, partial), partial,
-                        pcs.rr, nb);
-    launch_pcg_scalars(stream, nb, kPcgResid, opt.mg_rtol, pcs);
+    launch_sum_partials(stream, Ka, partial, pcs.pq, nbs);
+    launch_pcg_scalars(stream, nbs, kPcgAlpha, 0.0, pcs);
+    launch_sum_partials(stream, launch_cg_update(stream, nbs, per, pcs.alpha, pv, qv, sol, rr, partial), partial,
+                        pcs.rr, nbs);
+    launch_pcg_scalars(stream, nbs, kPcgResid, opt.mg_rtol, pcs);
     if (capturing) {
       if (it >= fixed) break;
     } else {
-      hip_check(hipMemcpyAsync(host_cs, pcs.rel, nb * sizeof(double), hipMemcpyDeviceToHost, stream),
+      hip_check(hipMemcpyAsync(host_cs, pcs.rel, nbs * sizeof(double), hipMemcpyDeviceToHost, stream),
                 "copy residuals");
       sync("mesh solve residual");
       relmax = 0.0;
-      for (int bb = 0; bb < nb; ++bb) relmax = std::max(relmax, host_cs[bb]);
+      for (int bb = 0; bb < nbs; ++bb) relmax = std::max(relmax, host_cs[bb]);
       if (relmax <= opt.mg_rtol) break;
     }
     precondition(qv);
-    launch_pcg_scalars(stream, nb, mixed ? kPcgBetaPR : kPcgBeta, 0.0, pcs);
+    launch_pcg_scalars(stream, nbs, mixed ? kPcgBetaPR : kPcgBeta, 0.0, pcs);
     set_p();
   }
-  launch_copy_f64(stream, nb, pcs.rel, cfgs(which ? kCsAdjRel : kCsFwdRel));
+  store_rel(which);
   check_launch("mesh solve");
   if (capturing) return;
   stats.mg_iterations = std::min(it, opt.mg_max_iter);
@@ -770,11 +782,26 @@ void fep3m_ctx::solve(const double *rhs, double *sol, int which) {
 }
 
 // Gauge-fixed periodic solve: out = K^+ rhs with int out = 0.
-void fep3m_ctx::mesh_solve(double *rhs, double *out, int which) {
+// nsys = 2: rhs and out hold the forward then the adjoint blocks, solved
+// together (which = 0).
+void fep3m_ctx::mesh_solve(double *rhs, double *out, int which, int nsys) {
+  nbs = nb * nsys;
+  struct Reset { int &v; int to; ~Reset() { v = to; } } reset{nbs, nb};
   solve(rhs, out, which);
-  launch_mass_dot(stream, nb, n, p, w1, out, partial);
-  launch_sum_partials(stream, seg_blocks(nb, lv[0].ndof), partial, cfgs(kCsInt), nb);
-  launch_sub_const(stream, nb, lv[0].ndof, 1.0 / (double(n) * n * n), cfgs(kCsInt), out);
+  launch_mass_dot(stream, nbs, n, p, w1, out, partial);
+  launch_sum_partials(stream, seg_blocks(nbs, lv[0].ndof), partial, gauge, nbs);
+  launch_sub_const(stream, nbs, lv[0].ndof, 1.0 / (double(n) * n * n), gauge, out);
+}
+
+// Final relative residuals into the per-configuration slots: one system
+// (forward or adjoint, by `which`) or both.
+void fep3m_ctx::store_rel(int which) {
+  if (nbs == nb) {
+    launch_copy_f64(stream, nb, pcs.rel, cfgs(which ? kCsAdjRel : kCsFwdRel));
+  } else {
+    launch_copy_f64(stream, nb, pcs.rel, cfgs(kCsFwdRel));
+    launch_copy_f64(stream, nb, pcs.rel + nb, cfgs(kCsAdjRel));
+  }
 }
 
 // ----------------------------------------------------------------- evaluate
@@ -807,8 +834,16 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsLoad), b);
   check_launch("assignment");
   stage_mark(FEP3M_PROF_ASSIGN, false);
+  // With forces the adjoint right side (the charges' deposit, which does not
+  // depend on phi) is built now and both systems go through one solve.
+  lam_ready = pair_forces;
+  if (pair_forces) {
+    stage_mark(FEP3M_PROF_ADJ_SOLVE, true);
+    adjoint_rhs();
+    stage_mark(FEP3M_PROF_ADJ_SOLVE, false);
+  }
   stage_mark(FEP3M_PROF_SOLVE, true);
-  mesh_solve(b, sol, 0);
+  mesh_solve(b, sol, 0, pair_forces ? 2 : 1);
   stage_mark(FEP3M_PROF_SOLVE, false);
   stage_mark(FEP3M_PROF_NEAR, true);
   const int ps = mixed ? launch_psi<float>(stream, nb, n, nsr, p, C, Tf, sol, Welf)
@@ -894,16 +929,24 @@ void fep3m_ctx::pair_pass(bool pair_forces) {
 
 // Reverse pass over the state the forward pass left in the context: deposit,
 // second mesh solve, moment adjoint, per-charge gradients.
-void fep3m_ctx::reverse(double *F, double *dUdQ) {
-  const int fwd_iters = stats.mg_iterations;
-  const double fwd_rel = stats.mg_rel_residual;
-  stage_mark(FEP3M_PROF_ADJ_SOLVE, true);
+// Adjoint right side: deposit g, assembly G, compatibility projection.
+void fep3m_ctx::adjoint_rhs() {
   launch_deposit(stream, nb, p, n, N, bas, start, sg, sQ, gE);
   launch_assemble(stream, nb, p, n, gE, Gv, partial);
   launch_sum_partials(stream, seg_blocks(nb, lv[0].ndof), partial, cfgs(kCsAdjLoad), nb);
   launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsAdjLoad), Gv);
-  mesh_solve(Gv, lam, 1);
-  stage_mark(FEP3M_PROF_ADJ_SOLVE, false);
+}
+
+void fep3m_ctx::reverse(double *F, double *dUdQ) {
+  const int fwd_iters = stats.mg_iterations;
+  const double fwd_rel = stats.mg_rel_residual;
+  if (!lam_ready) {   // lambda not solved with phi: a backward call after an energy-only forward
+    stage_mark(FEP3M_PROF_ADJ_SOLVE, true);
+    adjoint_rhs();
+    mesh_solve(Gv, lam, 1);
+    stage_mark(FEP3M_PROF_ADJ_SOLVE, false);
+    lam_ready = true;
+  }
   stage_mark(FEP3M_PROF_ADJ_NEAR, true);
   if (launch_adj_moments(stream, nb, p, n, nsr, gE, Tt, lam, gw, Aadj) != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
