@@ -151,6 +151,12 @@ struct fep3m_ctx {
   std::vector<MGLevel> lv;
   std::vector<Transfer> tr;
   std::vector<TransferF> trf;
+  // fine-level residual restricted inside the operator (p 5 -> 3, n even):
+  // per-tile partial coarse values, float64 or float32 like the V-cycle
+  bool fuse_rr = false;
+  double *rrp_d = nullptr;
+  float *rrp_f = nullptr;
+  template <class T> T *rr_part() const;
   bool mixed = false;        // float32 V-cycle, float32 near field and interpolation
   template <class T> const TransferT<T> &transfer(int l) const;
   double *dot_scr = nullptr; // two-dot partials of the mixed PCG
@@ -231,13 +237,16 @@ struct fep3m_ctx {
   int apply0(const T *x, const T *f, T *out, const T *d, T *xo, T c1, T c2, int mode, double *part, T s0 = T(0)) {
     const bool rec = prof.on && prof.kused < int(prof.kev.size()) / 2;
     if (rec) hip_check(hipEventRecord(prof.kev[2 * prof.kused], stream), "event");
-    const int K = launch_apply<T>(stream, nbs, lv[0].oper<T>(), x, f, out, d, xo, c1, c2, mode, part, s0);
+    const int K = mode == kResidualRestrict
+                      ? launch_apply_restrict<T>(stream, nbs, lv[0].oper<T>(), transfer<T>(0), x, f, rr_part<T>())
+                      : launch_apply<T>(stream, nbs, lv[0].oper<T>(), x, f, out, d, xo, c1, c2, mode, part, s0);
+    if (K < 0) throw Status(FEP3M_ERR_UNSUPPORTED, "fine-level operator variant");
     if (rec) {
       hip_check(hipEventRecord(prof.kev[2 * prof.kused + 1], stream), "event");
       // vectors read + written: x, f, x_prev (when read) and x_new; f and x_new (x built from f);
       // x, f and x_new (x_prev built from f); x, f, r; x, Kx
       const double vec = mode == kCheb ? ((c1 != T(0) && d) ? 4.0 : 3.0)
-                         : mode == kChebZ2 ? 2.0
+                         : (mode == kChebZ2 || mode == kResidualRestrict) ? 2.0
                          : (mode == kChebZ3 || mode == kResidual) ? 3.0 : 2.0;
       prof.kwork[prof.kused] = vec * double(sizeof(T)) * double(lv[0].ndof) * nbs;
       prof.kslot[prof.kused] = sizeof(T) == 8 ? FEP3M_PROF_FINE_APPLY : FEP3M_PROF_FINE_APPLY_F32;
@@ -456,6 +465,8 @@ static Transfer make_transfer(int pf, int nf, int pc, int nc) {
 
 template <> const Transfer &fep3m_ctx::transfer<double>(int l) const { return tr[l]; }
 template <> const TransferF &fep3m_ctx::transfer<float>(int l) const { return trf[l]; }
+template <> double *fep3m_ctx::rr_part<double>() const { return rrp_d; }
+template <> float *fep3m_ctx::rr_part<float>() const { return rrp_f; }
 
 void fep3m_ctx::build_mg() {
   std::vector<std::pair<int, int>> hier;
@@ -496,6 +507,12 @@ void fep3m_ctx::build_mg() {
         L_.vf.r = alloc<float>(nv, "mg r (f32)");
       }
     }
+  }
+  fuse_rr = lv.size() > 1 && lv[0].op.p == 5 && lv[1].op.p == 3 && n % 2 == 0;
+  if (fuse_rr) {
+    const size_t np = size_t(2) * nb * (n / 2) * (n / 2) * (n / 2) * 343;   // per system and tile
+    if (mixed) rrp_f = alloc<float>(np, "restriction partials (f32)");
+    else rrp_d = alloc<double>(np, "restriction partials");
   }
   if (mixed) {
     for (const Transfer &t : tr) trf.push_back(t.cast<float>());
@@ -694,9 +711,14 @@ void fep3m_ctx::vcycle(int l, const T *f) {
   const LevelOpT<T> &op = L_.oper<T>();
   LevelVecs<T> &Vc = lv[l + 1].vec<T>();
   cheb_smooth<T>(l, f, true);
-  if (l == 0) apply0<T>(V.x, f, V.r, nullptr, nullptr, T(0), T(0), kResidual, nullptr);
-  else launch_apply<T>(stream, nbs, op, V.x, f, V.r, nullptr, nullptr, T(0), T(0), kResidual, nullptr);
-  launch_transfer<T>(stream, nbs, transfer<T>(l), V.r, Vc.f, true);
+  if (l == 0 && fuse_rr) {   // residual restricted in the operator's epilogue, never stored
+    apply0<T>(V.x, f, nullptr, nullptr, nullptr, T(0), T(0), kResidualRestrict, nullptr);
+    launch_restrict_sum<T>(stream, nbs, n, rr_part<T>(), Vc.f);
+  } else {
+    if (l == 0) apply0<T>(V.x, f, V.r, nullptr, nullptr, T(0), T(0), kResidual, nullptr);
+    else launch_apply<T>(stream, nbs, op, V.x, f, V.r, nullptr, nullptr, T(0), T(0), kResidual, nullptr);
+    launch_transfer<T>(stream, nbs, transfer<T>(l), V.r, Vc.f, true);
+  }
   vcycle<T>(l + 1, Vc.f);
   launch_transfer<T>(stream, nbs, transfer<T>(l), Vc.x, V.x, false);
   cheb_smooth<T>(l, f, false);

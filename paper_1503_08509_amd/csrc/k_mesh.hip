@@ -193,6 +193,42 @@ __device__ __forceinline__ void band_apply_acc(const T *__restrict__ a, const T 
   for (int o = 0; o < NOUT; ++o) out[o] += t[o];
 }
 
+// Residual restricted in the operator's epilogue (p = 5 to p = 3 on the same
+// elements, whole 2^3-element tiles): 1-D weights w[s][j] (fine node s of an
+// element, coarse basis j, j = 3 the element's upper vertex) and the output
+// of 7^3 partial coarse values per tile.
+template <class T>
+struct RestrictArgs {
+  T w[5 * 4];
+  T *part;
+};
+
+// 1-D partial restriction of the 10 fine nodes of a 2-element row to the 7
+// coarse nodes they touch: (element ec, basis j < 3) for ec = 0, 1 and the
+// upper vertex of element 1.  The lower vertex of element 0 still lacks the
+// contribution of the element below, which the tile below supplies as its
+// seventh value.
+template <class T>
+__device__ __forceinline__ void restrict_partial(const T *__restrict__ w, const T (&v)[10], T (&o)[7]) {
+#pragma unroll
+  for (int ec = 0; ec < 2; ++ec)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      T s = T(0);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) s += w[q * 4 + j] * v[5 * ec + q];
+      if (j == 0 && ec == 1) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s += w[q * 4 + 3] * v[q];
+      }
+      o[3 * ec + j] = s;
+    }
+  T s = T(0);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) s += w[q * 4 + 3] * v[5 + q];
+  o[6] = s;
+}
+
 // One tile of TE^3 elements per block: y = K x on the owned nodes, then the
 // mode's epilogue.  The owned nodes of a tile are p*e + k, k < p, for its
 // elements; the inputs reach one element below and one node above.
@@ -200,10 +236,13 @@ __device__ __forceinline__ void band_apply_acc(const T *__restrict__ a, const T 
 // memory and writes A = Mz x, B = Kz x; pass y: one (z, x) column of A and B
 // gives C1 = My A and C2 = Ky A + My B; pass x: one (z, y) row of C1, C2
 // gives y = Kx C1 + Mx C2; the epilogue then walks the owned nodes x-fastest.
-template <class T, int PO, int TE>
+// With RR (kResidual, PO = 5, TE = 2, whole tiles) the residual is not
+// stored: the tile restricts it to 7^3 partial coarse values (RestrictArgs).
+template <class T, int PO, int TE, bool RR>
 __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restrict__ x, const T *__restrict__ f,
                                                T *__restrict__ out, const T *xprev, T *xo, T c1, T c2, int mode,
-                                               double *__restrict__ partial, T s0) {
+                                               double *__restrict__ partial, T s0, RestrictArgs<T> ra) {
+  static_assert(!RR || (PO == 5 && TE == 2), "the fused restriction covers p = 5 tiles of 2^3 elements");
   using S = ApplyShape<PO, TE>;
   constexpr int O = S::O, I = S::I;
   static_assert(S::LDS * sizeof(T) >= 256 * sizeof(double), "the dot-product tree reuses the tile");
@@ -220,6 +259,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
   {  // configuration of this tile: every vector moves to its block
     const int tiles3 = tiles * tiles * tiles;
     const size_t off = size_t(blockIdx.x / tiles3) * P * P * P;
+    if (RR) ra.part += size_t(blockIdx.x / tiles3) * tiles3 * 343;
     if (x) x += off;   // null in kChebZ2 mode
     if (f) f += off;
     if (out) out += off;
@@ -323,6 +363,50 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
     for (int ox = 0; ox < O; ++ox) Y[(oz * O + oy) * S::YS + ox] = yv[ox];
   }
   __syncthreads();
+  if (RR) {
+    // r on the owned nodes into Xo (x itself is not needed here), then three
+    // separable partial restrictions: x rows, y columns, z columns.
+#pragma unroll
+    for (int r = 0; r < NIT; ++r) {
+      const int li = tid + 256 * r;
+      if (li < O * O * O) {
+        const int cx = li % O, cy = (li / O) % O, cz = li / (O * O);
+        Xo[li] = pf_f[r] - Y[(cz * O + cy) * S::YS + cx];
+      }
+    }
+    __syncthreads();
+    T *R1 = lds;              // [oz][oy][7]
+    T *R2 = lds + O * O * 7;  // [oz][cy][cx]
+    T v[10], o[7];
+    if (tid < O * O) {
+      const int oz = tid / O, oy = tid % O;
+#pragma unroll
+      for (int i = 0; i < 10; ++i) v[i] = Xo[(oz * O + oy) * O + i];
+      restrict_partial<T>(ra.w, v, o);
+#pragma unroll
+      for (int k = 0; k < 7; ++k) R1[(oz * O + oy) * 7 + k] = o[k];
+    }
+    __syncthreads();
+    if (tid < O * 7) {
+      const int oz = tid / 7, cx = tid % 7;
+#pragma unroll
+      for (int i = 0; i < 10; ++i) v[i] = R1[(oz * O + i) * 7 + cx];
+      restrict_partial<T>(ra.w, v, o);
+#pragma unroll
+      for (int k = 0; k < 7; ++k) R2[(oz * 7 + k) * 7 + cx] = o[k];
+    }
+    __syncthreads();
+    if (tid < 49) {
+      const int cy = tid / 7, cx = tid % 7;
+#pragma unroll
+      for (int i = 0; i < 10; ++i) v[i] = R2[(i * 7 + cy) * 7 + cx];
+      restrict_partial<T>(ra.w, v, o);
+      T *dst = ra.part + size_t((tz * tiles + ty) * tiles + tx) * 343 + cy * 7 + cx;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) dst[k * 49] = o[k];
+    }
+    return;
+  }
   // epilogue on the owned nodes, x fastest: every result and address first,
   // then the stores back to back (a store whose registers the next one
   // reused would make it wait for the earlier store)
@@ -845,9 +929,66 @@ static int apply_impl(hipStream_t s, int nb, const LevelOpT<T> &op, const T *x, 
                       T c1, T c2, int mode, double *partial, T s0) {
   const int tiles = (op.n + TE - 1) / TE;
   const int K = tiles * tiles * tiles;
-  hipLaunchKernelGGL((k_apply<T, PO, TE>), dim3(nb * K), dim3(256), 0, s, op, x, f, out, d, xo, c1, c2, mode,
-                     partial, s0);
+  hipLaunchKernelGGL((k_apply<T, PO, TE, false>), dim3(nb * K), dim3(256), 0, s, op, x, f, out, d, xo, c1, c2, mode,
+                     partial, s0, RestrictArgs<T>{});
   return K;
+}
+
+// Partial coarse values of the tiles (7^3 each) summed per coarse node: own
+// tile, and for a node on a tile's lower face (local index 0 along an axis)
+// also the upper-vertex value (index 6) of the tile below, in a fixed order.
+template <class T>
+__global__ __launch_bounds__(256) void k_restrict_sum(int Pc, int tiles, int K, const T *__restrict__ partall,
+                                                      T *__restrict__ fcall) {
+  const size_t total = size_t(Pc) * Pc * Pc;
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const T *part = partall + size_t(cfg) * tiles * tiles * tiles * 343;
+  T *fc = fcall + size_t(cfg) * total;
+  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < total; g += size_t(K) * blockDim.x) {
+    const int gx = int(g % Pc), gy = int((g / Pc) % Pc), gz = int(g / (size_t(Pc) * Pc));
+    int t[3][2], k[3][2], nn[3];
+    const int gg[3] = {gx, gy, gz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      t[a][0] = gg[a] / 6;
+      k[a][0] = gg[a] % 6;
+      nn[a] = 1;
+      if (k[a][0] == 0) {
+        t[a][1] = t[a][0] == 0 ? tiles - 1 : t[a][0] - 1;
+        k[a][1] = 6;
+        nn[a] = 2;
+      }
+    }
+    T s = T(0);
+    for (int iz = 0; iz < nn[2]; ++iz)
+      for (int iy = 0; iy < nn[1]; ++iy)
+        for (int ix = 0; ix < nn[0]; ++ix) {
+          const size_t tile = (size_t(t[2][iz]) * tiles + t[1][iy]) * tiles + t[0][ix];
+          s += part[tile * 343 + (k[2][iz] * 7 + k[1][iy]) * 7 + k[0][ix]];
+        }
+    fc[g] = s;
+  }
+}
+
+template <class T>
+int launch_apply_restrict(hipStream_t s, int nb, const LevelOpT<T> &op, const TransferT<T> &tr, const T *x,
+                          const T *f, T *part) {
+  if (op.p != 5 || tr.pf != 5 || tr.pc != 3 || tr.r != 1 || op.n % 2 != 0) return -1;
+  RestrictArgs<T> ra{};
+  for (int i = 0; i < 20; ++i) ra.w[i] = tr.w[i];
+  ra.part = part;
+  const int tiles = op.n / 2;
+  const int K = tiles * tiles * tiles;
+  hipLaunchKernelGGL((k_apply<T, 5, 2, true>), dim3(nb * K), dim3(256), 0, s, op, x, f, nullptr, nullptr, nullptr,
+                     T(0), T(0), int(kResidual), nullptr, T(0), ra);
+  return K;
+}
+
+template <class T>
+void launch_restrict_sum(hipStream_t s, int nb, int n, const T *part, T *fc) {
+  const int Pc = 3 * n;
+  const int K = seg_blocks(nb, size_t(Pc) * Pc * Pc);
+  hipLaunchKernelGGL(k_restrict_sum<T>, dim3(nb * K), dim3(256), 0, s, Pc, n / 2, K, part, fc);
 }
 
 template <class T>
@@ -916,6 +1057,9 @@ void launch_coarse_solve(hipStream_t s, int nb, int Pn, const double *V, const d
                                T, int, double *, T);                                                                \
   template void launch_cheb_first<T>(hipStream_t, int, const LevelOpT<T> &, const T *, T *, T);                     \
   template int launch_transfer<T>(hipStream_t, int, const TransferT<T> &, const T *, T *, bool);                    \
+  template int launch_apply_restrict<T>(hipStream_t, int, const LevelOpT<T> &, const TransferT<T> &, const T *,       \
+                                        const T *, T *);                                                              \
+  template void launch_restrict_sum<T>(hipStream_t, int, int, const T *, T *);                                       \
   template void launch_coarse_solve<T>(hipStream_t, int, int, const double *, const double *, const T *, T *);
 FEP3M_MESH_INSTANTIATE(double)
 FEP3M_MESH_INSTANTIATE(float)

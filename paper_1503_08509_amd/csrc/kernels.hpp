@@ -96,6 +96,16 @@ int launch_apply(hipStream_t s, int nb, const LevelOpT<T> &op, const T *x, const
 int apply_blocks(const LevelOp &op);
 template <class T>
 void launch_cheb_first(hipStream_t s, int nb, const LevelOpT<T> &op, const T *f, T *x, T c2);
+// Fine-level residual f - K x restricted from p = 5 to p = 3 without storing
+// it: the operator tiles (2^3 elements, n even) write 7^3 partial coarse
+// values each into part (nb n^3 / 8 * 343 values); launch_restrict_sum adds
+// them into the coarse right side fc.  Returns -1 when the level or the
+// transfer is not the supported pair.
+template <class T>
+int launch_apply_restrict(hipStream_t s, int nb, const LevelOpT<T> &op, const TransferT<T> &tr, const T *x,
+                          const T *f, T *part);
+template <class T>
+void launch_restrict_sum(hipStream_t s, int nb, int n, const T *part, T *fc);
 template <class T>
 int launch_transfer(hipStream_t s, int nb, const TransferT<T> &tr, const T *in, T *out, bool restrict_);
 template <class T>
