@@ -1032,7 +1032,7 @@ template <class T>
 int launch_transfer(hipStream_t s, int nb, const TransferT<T> &tr, const T *in, T *out, bool restrict_) {
   if (tr.pf == 5 && tr.pc == 3 && tr.r == 1) {
     if (restrict_) restrict_impl<T, 5, 3, 1, 2>(s, nb, tr, in, out);
-    else prolong_impl<T, 5, 3, 1, 2>(s, nb, tr, in, out);
+    else prolong_impl<T, 5, 3, 1, 3>(s, nb, tr, in, out);
   } else if (tr.pf == 3 && tr.pc == 1 && tr.r == 1) {
     if (restrict_) restrict_impl<T, 3, 1, 1, 4>(s, nb, tr, in, out);
     else prolong_impl<T, 3, 1, 1, 5>(s, nb, tr, in, out);
