@@ -245,7 +245,7 @@ struct fep3m_ctx {
       hip_check(hipEventRecord(prof.kev[2 * prof.kused + 1], stream), "event");
       // vectors read + written: x, f, x_prev (when read) and x_new; f and x_new (x built from f);
       // x, f and x_new (x_prev built from f); x, f, r; x, Kx
-      const double vec = mode == kCheb ? ((c1 != T(0) && d) ? 4.0 : 3.0)
+      const double vec = (mode == kCheb || mode == kChebDot) ? ((c1 != T(0) && d) ? 4.0 : 3.0)
                          : (mode == kChebZ2 || mode == kResidualRestrict) ? 2.0
                          : (mode == kChebZ3 || mode == kResidual) ? 3.0 : 2.0;
       prof.kwork[prof.kused] = vec * double(sizeof(T)) * double(lv[0].ndof) * nbs;
@@ -275,8 +275,8 @@ struct fep3m_ctx {
   void backward(int64_t gen, double *F, double *dUdQ);
   void build_mg();
   void estimate_spectra();
-  template <class T> void vcycle(int l, const T *f);
-  template <class T> void cheb_smooth(int l, const T *f, bool zero_start);
+  template <class T> int vcycle(int l, const T *f, double *dot_part = nullptr);
+  template <class T> int cheb_smooth(int l, const T *f, bool zero_start, double *dot_part = nullptr);
   void solve(const double *rhs, double *out, int which);
   void fdm_solve(const double *rhs, double *out, int which);
   void build_fdm();
@@ -660,8 +660,11 @@ void fep3m_ctx::estimate_spectra() {
 
 // Chebyshev(deg)-Jacobi smoothing on level l in arithmetic type T, targeting
 // the interval [lmax / 12, 1.1 lmax] of D^-1 K.
+// With dot_part, the last step also writes block partials of x_new . f
+// (returns their count per system).
 template <class T>
-void fep3m_ctx::cheb_smooth(int l, const T *f, bool zero_start) {
+int fep3m_ctx::cheb_smooth(int l, const T *f, bool zero_start, double *dot_part) {
+  int Kd = 0;
   MGLevel &L_ = lv[l];
   LevelVecs<T> &V = L_.vec<T>();
   const LevelOpT<T> &op = L_.oper<T>();
@@ -689,24 +692,32 @@ void fep3m_ctx::cheb_smooth(int l, const T *f, bool zero_start) {
       // x2 holds x_prev on entry and receives x_new; then the two swap.
       // Steps 2 and 3 after a zero start take x1 (step 2: x; step 3: x_prev)
       // as s0 D^-1 f instead of reading it.
-      const int mode = !zero_start ? kCheb : s == 1 ? kChebZ2 : s == 2 ? kChebZ3 : kCheb;
+      int mode = !zero_start ? kCheb : s == 1 ? kChebZ2 : s == 2 ? kChebZ3 : kCheb;
+      const bool dot = dot_part && s == deg - 1 && mode == kCheb;
+      if (dot) mode = kChebDot;
       const T *xin = mode == kChebZ2 ? nullptr : V.x;
-      const T *xprev = (mode == kCheb) ? V.x2 : nullptr;
-      if (l == 0) apply0<T>(xin, f, nullptr, xprev, V.x2, T(c1), T(c2), mode, nullptr, T(s0));
-      else launch_apply<T>(stream, nbs, op, xin, f, nullptr, xprev, V.x2, T(c1), T(c2), mode, nullptr, T(s0));
+      const T *xprev = (mode == kCheb || mode == kChebDot) ? V.x2 : nullptr;
+      double *part = dot ? dot_part : nullptr;
+      const int K = l == 0 ? apply0<T>(xin, f, nullptr, xprev, V.x2, T(c1), T(c2), mode, part, T(s0))
+                           : launch_apply<T>(stream, nbs, op, xin, f, nullptr, xprev, V.x2, T(c1), T(c2), mode, part,
+                                             T(s0));
+      if (dot) Kd = K;
       std::swap(V.x, V.x2);
     }
   }
+  return Kd;
 }
 
-// One V-cycle for K x = f on level l (x from zero), in arithmetic type T.
+// One V-cycle for K x = f on level l (x from zero), in arithmetic type T;
+// with dot_part, block partials of x . f from the last smoothing step
+// (returns their count per system).
 template <class T>
-void fep3m_ctx::vcycle(int l, const T *f) {
+int fep3m_ctx::vcycle(int l, const T *f, double *dot_part) {
   MGLevel &L_ = lv[l];
   LevelVecs<T> &V = L_.vec<T>();
   if (l + 1 == int(lv.size())) {
     launch_coarse_solve<T>(stream, nbs, coarseP, coarseV, coarseLam, f, V.x);
-    return;
+    return 0;
   }
   const LevelOpT<T> &op = L_.oper<T>();
   LevelVecs<T> &Vc = lv[l + 1].vec<T>();
@@ -721,7 +732,7 @@ void fep3m_ctx::vcycle(int l, const T *f) {
   }
   vcycle<T>(l + 1, Vc.f);
   launch_transfer<T>(stream, nbs, transfer<T>(l), Vc.x, V.x, false);
-  cheb_smooth<T>(l, f, false);
+  return cheb_smooth<T>(l, f, false, dot_part);
 }
 
 // PCG on K out = rhs (rhs compatible), preconditioned by one V-cycle, for
@@ -747,9 +758,8 @@ void fep3m_ctx::solve(const double *rhs, double *sol, int which) {
   launch_sum_partials(stream, launch_dot(stream, nbs, per, rhs, rhs, partial), partial, pcs.bn2, nbs);
   // z = M^-1 r; rzn = z . r (and zq = z . q when q is given)
   auto precondition = [&](const double *q) {
-    if (!mixed) {
-      vcycle<double>(0, rr);
-      launch_sum_partials(stream, launch_dot(stream, nbs, per, rr, L0.vd.x, partial), partial, pcs.rzn, nbs);
+    if (!mixed) {   // z . r from the V-cycle's last smoothing step
+      launch_sum_partials(stream, vcycle<double>(0, rr, partial), partial, pcs.rzn, nbs);
     } else {
       launch_to_f32(stream, nd, rr, L0.vf.f);
       vcycle<float>(0, L0.vf.f);

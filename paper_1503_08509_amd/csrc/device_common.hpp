@@ -99,7 +99,8 @@ enum ApplyMode : int {
   // x1 = s0 D^-1 f is never stored:
   kChebZ2 = 5,     // as kCheb with x = s0 D^-1 f (built from f on the fly) and x_prev = 0
   kChebZ3 = 6,     // as kCheb with x_prev = s0 D^-1 f
-  kResidualRestrict = 7   // f - K x restricted to the next level, not stored (launch_apply_restrict)
+  kResidualRestrict = 7,  // f - K x restricted to the next level, not stored (launch_apply_restrict)
+  kChebDot = 8     // as kCheb, and block partials of x_new . f
 };
 
 }  // namespace fep3m

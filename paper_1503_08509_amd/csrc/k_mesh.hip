@@ -275,8 +275,9 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
   // latency hides behind the three passes.
   constexpr int NIT = (O * O * O + 255) / 256;
   const bool zstart = (mode == kChebZ2);   // input columns are s0 D^-1 f
-  const bool need_f = (mode == kResidual) || (mode == kCheb) || zstart || (mode == kChebZ3);
-  const bool need_d = (mode == kCheb) && (c1 != T(0)) && (xprev != nullptr);   // null x_prev reads as zero
+  const bool cheb = (mode == kCheb) || (mode == kChebDot);
+  const bool need_f = (mode == kResidual) || cheb || zstart || (mode == kChebZ3);
+  const bool need_d = cheb && (c1 != T(0)) && (xprev != nullptr);   // null x_prev reads as zero
   for (int i = tid; i < PO * PO * PO; i += 256) {
     const int kx = i % PO, ky = (i / PO) % PO, kz = i / (PO * PO);
     invd[i] = T(1) / (op.dk[kx] * op.dm[ky] * op.dm[kz] + op.dm[kx] * op.dk[ky] * op.dm[kz] +
@@ -413,7 +414,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
   double acc = 0.0;
   T res[NIT];
   T *dst[NIT];
-  T *const base = (mode == kCheb || zstart || mode == kChebZ3) ? xo : out;   // xo may overwrite x_prev
+  T *const base = (cheb || zstart || mode == kChebZ3) ? xo : out;   // xo may overwrite x_prev
 #pragma unroll
   for (int r = 0; r < NIT; ++r) {
     const int li = tid + 256 * r;
@@ -428,10 +429,11 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
     T v;
     if (mode == kApply || mode == kApplyDot) v = y;
     else if (mode == kResidual) v = pf_f[r] - y;
-    else if (mode == kCheb || zstart) v = xv + c1 * (xv - pf_d[r]) + c2 * rr;
+    else if (cheb || zstart) v = xv + c1 * (xv - pf_d[r]) + c2 * rr;
     else if (mode == kChebZ3) v = xv + c1 * (xv - s0 * id * pf_f[r]) + c2 * rr;
     else v = -rr;                                                          // kDinvApply (f = 0): D^-1 K x
     if (ok && mode == kApplyDot) acc += double(xv) * double(y);
+    if (ok && mode == kChebDot) acc += double(v) * double(pf_f[r]);
     res[r] = v;
     asm volatile("" : "+v"(res[r]));   // computed here, in registers of its own
     dst[r] = ok ? base + (tbase + unsigned((oz * P + oy) * P + ox)) : nullptr;
@@ -439,7 +441,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
 #pragma unroll
   for (int r = 0; r < NIT; ++r)
     if (dst[r]) *dst[r] = res[r];
-  if (mode == kApplyDot) {
+  if (mode == kApplyDot || mode == kChebDot) {
     __syncthreads();  // every thread is done with Y before the tree reuses it
     double s = block_sum(acc, reinterpret_cast<double *>(lds));
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -741,11 +743,34 @@ __global__ __launch_bounds__(256) void k_cg_update(size_t per, int K, const doub
   p += o; q += o; x += o; r += o;
   const double alpha = alphas[cfg];
   double acc = 0.0;
-  for (size_t i = size_t(kb) * blockDim.x + threadIdx.x; i < per; i += size_t(K) * blockDim.x) {
-    x[i] += alpha * p[i];
-    const double rv = r[i] - alpha * q[i];
-    r[i] = rv;
-    acc += rv * rv;
+  // four elements per thread and pass: every load first, then the stores
+  constexpr int U = 4;
+  const size_t stride = size_t(K) * blockDim.x;
+  for (size_t i0 = size_t(kb) * blockDim.x + threadIdx.x; i0 < per; i0 += U * stride) {
+    double pv[U], qv[U], xv[U], rv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t i = i0 + u * stride;
+      const bool ok = i < per;
+      pv[u] = ok ? p[i] : 0.0;
+      qv[u] = ok ? q[i] : 0.0;
+      xv[u] = ok ? x[i] : 0.0;
+      rv[u] = ok ? r[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      xv[u] += alpha * pv[u];
+      rv[u] -= alpha * qv[u];
+      acc += rv[u] * rv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t i = i0 + u * stride;
+      if (i < per) {
+        x[i] = xv[u];
+        r[i] = rv[u];
+      }
+    }
   }
   double t = block_sum(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
@@ -758,8 +783,8 @@ __global__ __launch_bounds__(256) void k_xpay(size_t per, int K, const double *_
   z += size_t(cfg) * per;
   p += size_t(cfg) * per;
   const double beta = betas[cfg];
-  for (size_t i = size_t(kb) * blockDim.x + threadIdx.x; i < per; i += size_t(K) * blockDim.x)
-    p[i] = beta == 0.0 ? z[i] : z[i] + beta * p[i];
+  const size_t i = size_t(kb) * blockDim.x + threadIdx.x;   // one element per thread
+  if (i < per) p[i] = beta == 0.0 ? z[i] : z[i] + beta * p[i];
 }
 
 __global__ __launch_bounds__(256) void k_scale(size_t n, double s, const double *__restrict__ a, double *__restrict__ b) {
@@ -836,8 +861,8 @@ __global__ __launch_bounds__(256) void k_xpay_f32(size_t per, int K, const doubl
   z += size_t(cfg) * per;
   p += size_t(cfg) * per;
   const double beta = betas[cfg];
-  for (size_t i = size_t(kb) * blockDim.x + threadIdx.x; i < per; i += size_t(K) * blockDim.x)
-    p[i] = beta == 0.0 ? double(z[i]) : double(z[i]) + beta * p[i];
+  const size_t i = size_t(kb) * blockDim.x + threadIdx.x;   // one element per thread
+  if (i < per) p[i] = beta == 0.0 ? double(z[i]) : double(z[i]) + beta * p[i];
 }
 
 // PCG scalars, one thread per configuration, on arrays of nb values:
@@ -1075,7 +1100,7 @@ int launch_dot2_f32(hipStream_t s, int nb, size_t per, const float *z, const dou
   return K;
 }
 void launch_xpay_f32(hipStream_t s, int nb, size_t per, const double *betas, const float *z, double *p) {
-  const int K = seg_blocks(nb, per);
+  const int K = int((per + 255) / 256);
   hipLaunchKernelGGL(k_xpay_f32, dim3(nb * K), dim3(256), 0, s, per, K, betas, z, p);
 }
 void launch_pcg_scalars(hipStream_t s, int nb, int step, double rtol, const PcgScalars &sc) {
@@ -1093,7 +1118,7 @@ int launch_cg_update(hipStream_t s, int nb, size_t per, const double *alphas, co
   return K;
 }
 void launch_xpay(hipStream_t s, int nb, size_t per, const double *betas, const double *z, double *p) {
-  const int K = seg_blocks(nb, per);
+  const int K = int((per + 255) / 256);
   hipLaunchKernelGGL(k_xpay, dim3(nb * K), dim3(256), 0, s, per, K, betas, z, p);
 }
 void launch_scale(hipStream_t s, size_t n, double sc, const double *a, double *b) {
