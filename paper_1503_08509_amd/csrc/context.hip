@@ -135,6 +135,7 @@ struct fep3m_ctx {
   // particles
   double *gtmp = nullptr, *sg = nullptr, *sQ = nullptr;
   int *elem = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *tmp = nullptr, *perm = nullptr;
+  int *scan_scr = nullptr;   // tile sums and maxima of the counting-sort scans
   int *flags = nullptr, *maxcount = nullptr;
   unsigned long long *paircount = nullptr;
   double *C = nullptr, *Wel = nullptr, *phip_s = nullptr, *phim_s = nullptr, *phi_s = nullptr;
@@ -372,6 +373,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   count = alloc<int>(size_t(nb) * M, "counts");
   start = alloc<int>(size_t(nb) * M + 1, "element starts");
   flags = alloc<int>(4, "flags");
+  scan_scr = alloc<int>(2 * ((size_t(nb) * M + 2047) / 2048) + 16, "scan scratch");
   maxcount = alloc<int>(4, "max count");
   paircount = alloc<unsigned long long>(2, "pair count");
   C = alloc<double>(size_t(nb) * M * 8, "moments");
@@ -853,7 +855,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
     check_inputs();
   }
 
-  launch_scan(stream, MT, count, start, maxcount);
+  launch_scan(stream, MT, count, start, maxcount, scan_scr);
   launch_scatter(stream, N, elem, slot, start, tmp);
   launch_rank(stream, N, tmp, elem, start, gtmp, Qc, perm, sg, sQ);
   items_titem = -1;   // the pair work list follows this call's element starts
@@ -904,7 +906,7 @@ int fep3m_ctx::pair_launch(const PairPlan &pl, bool pair_forces) {
                  : launch_pair(stream, nb, n, nsr, N, start, sg, sQ, phip_s, fp);
   const int MT = nb * n * n * n;
   if (items_titem != pl.titem) {
-    launch_items(stream, MT, pl.titem, start, nit, item_start, iscan_max, items);
+    launch_items(stream, MT, pl.titem, start, nit, item_start, iscan_max, items, scan_scr);
     items_titem = pl.titem;
   }
   return mixed ? launch_pair_queue_f32(stream, pl.waves, n, nsr, N, start, items, item_start + MT, icounter, pl.titem,
@@ -928,7 +930,7 @@ void fep3m_ctx::tune_pairs(bool pair_forces) {
   PairPlan pick = cand[0];
   for (const PairPlan &pl : cand) {
     if (pl.kind == 1 && items_titem != pl.titem) {   // list construction is not part of the timing
-      launch_items(stream, nb * n * n * n, pl.titem, start, nit, item_start, iscan_max, items);
+      launch_items(stream, nb * n * n * n, pl.titem, start, nit, item_start, iscan_max, items, scan_scr);
       items_titem = pl.titem;
     }
     hip_check(hipEventRecord(e0, stream), "event");

@@ -81,32 +81,98 @@ __global__ __launch_bounds__(256) void k_bin(int64_t N, int K, const int *__rest
 }
 
 // Exclusive scan of count[0..M) into start[0..M]; also the largest count.
-__global__ __launch_bounds__(1024) void k_scan(int M, const int *__restrict__ count, int *__restrict__ start,
-                                               int *__restrict__ maxcount) {
-  __shared__ int sums[1024];
-  __shared__ int mx[1024];
+// Exclusive scan of element counts (start[0..M], start[M] = total) and their
+// maximum, in three passes: per-tile sums and maxima, a one-block scan of
+// the tile sums, and a per-tile rescan with the tile's offset.  A tile is
+// 256 threads x 8 consecutive counts.
+constexpr int kScanPer = 8;
+constexpr int kScanTile = 256 * kScanPer;
+
+__device__ __forceinline__ void load8(const int *__restrict__ a, int M, int i0, int (&v)[kScanPer]) {
+  if (i0 + kScanPer <= M) {
+    const int4 p = *reinterpret_cast<const int4 *>(a + i0), q = *reinterpret_cast<const int4 *>(a + i0 + 4);
+    v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = p.w; v[4] = q.x; v[5] = q.y; v[6] = q.z; v[7] = q.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) v[k] = i0 + k < M ? a[i0 + k] : 0;
+  }
+}
+
+// exclusive block scan of one value per thread (256 threads); returns the total in *tot
+__device__ __forceinline__ int block_exscan256(int v, int *sh, int *tot) {
   const int t = threadIdx.x;
-  const int chunk = (M + 1023) / 1024;
-  const int b = t * chunk, e = min(M, b + chunk);
-  int s = 0, m = 0;
-  for (int i = b; i < e; ++i) { s += count[i]; m = max(m, count[i]); }
-  sums[t] = s;
-  mx[t] = m;
+  sh[t] = v;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
-    int v = (t >= off) ? sums[t - off] : 0;
+  for (int off = 1; off < 256; off <<= 1) {   // inclusive Hillis-Steele scan
+    const int u = t >= off ? sh[t - off] : 0;
     __syncthreads();
-    sums[t] += v;
-    __syncthreads();
-  }
-  for (int off = 512; off > 0; off >>= 1) {
-    if (t < off) mx[t] = max(mx[t], mx[t + off]);
+    sh[t] += u;
     __syncthreads();
   }
-  int run = sums[t] - s;
-  for (int i = b; i < e; ++i) { start[i] = run; run += count[i]; }
-  if (t == 1023) start[M] = sums[1023];
-  if (t == 0) maxcount[0] = mx[0];
+  const int inc = sh[t];
+  *tot = sh[255];
+  __syncthreads();
+  return inc - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(int M, const int *__restrict__ count, int *__restrict__ bsum,
+                                                     int *__restrict__ bmax) {
+  __shared__ int ss[256], sm[256];
+  const int t = threadIdx.x;
+  int v[kScanPer];
+  load8(count, M, blockIdx.x * kScanTile + t * kScanPer, v);
+  int s = 0, m = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) { s += v[k]; m = max(m, v[k]); }
+  ss[t] = s;
+  sm[t] = m;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) { ss[t] += ss[t + off]; sm[t] = max(sm[t], sm[t + off]); }
+    __syncthreads();
+  }
+  if (t == 0) { bsum[blockIdx.x] = ss[0]; bmax[blockIdx.x] = sm[0]; }
+}
+
+// one block: exclusive scan of the B tile sums in place, start[M] = total,
+// maxcount[0] = the largest count
+__global__ __launch_bounds__(256) void k_scan_top(int B, int M, int *__restrict__ bsum, const int *__restrict__ bmax,
+                                                  int *__restrict__ start, int *__restrict__ maxcount) {
+  __shared__ int sh[256];
+  const int t = threadIdx.x;
+  const int chunk = (B + 255) / 256;
+  const int b0 = min(B, t * chunk), b1 = min(B, b0 + chunk);
+  int s = 0, m = 0;
+  for (int i = b0; i < b1; ++i) { s += bsum[i]; m = max(m, bmax[i]); }
+  int tot;
+  int run = block_exscan256(s, sh, &tot);
+  for (int i = b0; i < b1; ++i) { const int v = bsum[i]; bsum[i] = run; run += v; }
+  sh[t] = m;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) sh[t] = max(sh[t], sh[t + off]);
+    __syncthreads();
+  }
+  if (t == 0) { start[M] = tot; maxcount[0] = sh[0]; }
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(int M, const int *__restrict__ count, const int *__restrict__ boff,
+                                                   int *__restrict__ start) {
+  __shared__ int sh[256];
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.x * kScanTile + t * kScanPer;
+  int v[kScanPer];
+  load8(count, M, i0, v);
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) s += v[k];
+  int tot;
+  int run = boff[blockIdx.x] + block_exscan256(s, sh, &tot);
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (i0 + k < M) start[i0 + k] = run;
+    run += v[k];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_scatter(int64_t N, const int *__restrict__ elem, const int *__restrict__ slot,
@@ -444,8 +510,12 @@ int launch_bin(hipStream_t s, int nb, const int *off, int64_t N, const double *x
                      partial);
   return K;
 }
-void launch_scan(hipStream_t s, int M, const int *count, int *start, int *maxcount) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, M, count, start, maxcount);
+void launch_scan(hipStream_t s, int M, const int *count, int *start, int *maxcount, int *scratch) {
+  const int B = (M + kScanTile - 1) / kScanTile;
+  int *bsum = scratch, *bmax = scratch + B;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(B), dim3(256), 0, s, M, count, bsum, bmax);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, B, M, bsum, bmax, start, maxcount);
+  hipLaunchKernelGGL(k_scan_down, dim3(B), dim3(256), 0, s, M, count, bsum, start);
 }
 void launch_scatter(hipStream_t s, int64_t N, const int *elem, const int *slot, const int *start, int *tmp) {
   hipLaunchKernelGGL(k_scatter, dim3(grid_n(N)), dim3(256), 0, s, N, elem, slot, start, tmp);
@@ -480,9 +550,9 @@ int launch_pair(hipStream_t s, int nb, int n, int nsr, int64_t N, const int *sta
 // item_start (MT + 1 ints) are scratch, items holds up to N entries, and
 // item_start[MT] receives the item count.
 void launch_items(hipStream_t s, int MT, int titem, const int *start, int *nit, int *item_start, int *scan_max,
-                  int2 *items) {
+                  int2 *items, int *scan_scratch) {
   hipLaunchKernelGGL(k_items_count, dim3(grid_n(MT)), dim3(256), 0, s, MT, titem, start, nit);
-  launch_scan(s, MT, nit, item_start, scan_max);
+  launch_scan(s, MT, nit, item_start, scan_max, scan_scratch);
   hipLaunchKernelGGL(k_items_fill, dim3(grid_n(MT)), dim3(256), 0, s, MT, titem, start, item_start, items);
 }
 void launch_fill_int(hipStream_t s, int count, int value, int *p) {

@@ -19,7 +19,8 @@ int bin_grid(int64_t N, int nb);
 int energy_grid(int64_t N, int nb);
 int launch_bin(hipStream_t s, int nb, const int *off, int64_t N, const double *x, const double *Q, double L, int n,
                double *gtmp, int *elem, int *slot, int *count, int *flags, double *partial);
-void launch_scan(hipStream_t s, int M, const int *count, int *start, int *maxcount);
+// scratch: 2 ceil(M / 2048) ints (tile sums and maxima)
+void launch_scan(hipStream_t s, int M, const int *count, int *start, int *maxcount, int *scratch);
 void launch_scatter(hipStream_t s, int64_t N, const int *elem, const int *slot, const int *start, int *tmp);
 void launch_rank(hipStream_t s, int64_t N, const int *tmp, const int *elem, const int *start, const double *gtmp,
                  const double *Q, int *perm, double *sg, double *sQ);
@@ -32,7 +33,7 @@ int launch_pair_count(hipStream_t s, int nb, int n, int nsr, const int *start, u
 // up to titem targets (item_start[MT] = item count; items up to N entries),
 // consumed by `waves` persistent one-wave blocks through *counter.
 void launch_items(hipStream_t s, int MT, int titem, const int *start, int *nit, int *item_start, int *scan_max,
-                  int2 *items);
+                  int2 *items, int *scan_scratch);
 void launch_fill_int(hipStream_t s, int count, int value, int *p);
 int launch_pair_queue(hipStream_t s, int waves, int n, int nsr, int64_t N, const int *start, const int2 *items,
                       const int *nitems, int *counter, int titem, const double *sg, const double *sQ, double *phip,
