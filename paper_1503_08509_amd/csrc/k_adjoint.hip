@@ -69,16 +69,23 @@ __global__ __launch_bounds__(256) void k_assemble(int n, int K, const double *__
   const double *gE = gEall + size_t(cfg) * n * n * n * NM;
   double *G = Gall + size_t(cfg) * total;
   double acc = 0.0;
-  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < total; g += size_t(K) * blockDim.x) {
-    const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
-    int ex[2], kx[2], ey[2], ky[2], ez[2], kz[2];
-    int nx = 1, ny = 1, nz = 1;
-    ex[0] = gx / PO; kx[0] = gx % PO;
-    ey[0] = gy / PO; ky[0] = gy % PO;
-    ez[0] = gz / PO; kz[0] = gz % PO;
-    if (kx[0] == 0) { ex[1] = (ex[0] + n - 1) % n; kx[1] = PO; nx = 2; }
-    if (ky[0] == 0) { ey[1] = (ey[0] + n - 1) % n; ky[1] = PO; ny = 2; }
-    if (kz[0] == 0) { ez[1] = (ez[0] + n - 1) % n; kz[1] = PO; nz = 2; }
+  (void)total;
+  auto owners = [n](int g, int (&e)[2], int (&k)[2]) {   // one owner, or two at a vertex (element below first)
+    e[0] = g / PO;
+    k[0] = g - e[0] * PO;
+    if (k[0] != 0) return 1;
+    e[1] = e[0] == 0 ? n - 1 : e[0] - 1;
+    k[1] = PO;
+    return 2;
+  };
+  for (int row = kb; row < P * P; row += K) {   // one (gz, gy) row per pass, x along the threads
+    const int gz = row / P, gy = row - gz * P;
+    int ey[2], ky[2], ez[2], kz[2];
+    const int ny = owners(gy, ey, ky), nz = owners(gz, ez, kz);
+    for (int gx = threadIdx.x; gx < P; gx += blockDim.x) {
+    const size_t g = size_t(row) * P + gx;
+    int ex[2], kx[2];
+    const int nx = owners(gx, ex, kx);
     double s = 0.0;
     for (int iz = 0; iz < nz; ++iz)
       for (int iy = 0; iy < ny; ++iy)
@@ -88,6 +95,7 @@ __global__ __launch_bounds__(256) void k_assemble(int n, int K, const double *__
         }
     G[g] = s;
     acc += s;
+    }
   }
   double t = block_sum_a(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;

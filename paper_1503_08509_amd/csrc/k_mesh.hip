@@ -31,6 +31,18 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 
 // ----------------------------------------------------------------- load
 
+// Elements owning global node g along one axis (order p, n elements,
+// periodic) and the node's local index in each: one, or two at a vertex
+// (the element below first with local index p).
+__device__ __forceinline__ int node_owners(int g, int p, int n, int (&e)[2], int (&k)[2]) {
+  e[0] = g / p;
+  k[0] = g - e[0] * p;
+  if (k[0] != 0) return 1;
+  e[1] = e[0] == 0 ? n - 1 : e[0] - 1;
+  k[1] = p;
+  return 2;
+}
+
 // b at node (gz, gy, gx): 4 pi sum over the 1..8 elements owning the node of
 // sum_a C[E][a] g[ax][kx] g[ay][ky] g[az][kz] (gather form, no atomics),
 // with per-configuration block partial sums of b (K blocks per
@@ -45,16 +57,15 @@ __global__ __launch_bounds__(256) void k_load(int n, int p, int K, const double 
   const double *C = Call + size_t(cfg) * n * n * n * 8;
   double *b = ball + size_t(cfg) * total;
   double acc = 0.0;
-  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < total; g += size_t(K) * blockDim.x) {
-    const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
-    int ex[2], kx[2], ey[2], ky[2], ez[2], kz[2];
-    int nx = 1, ny = 1, nz = 1;
-    ex[0] = gx / p; kx[0] = gx % p;
-    ey[0] = gy / p; ky[0] = gy % p;
-    ez[0] = gz / p; kz[0] = gz % p;
-    if (kx[0] == 0) { ex[1] = (ex[0] + n - 1) % n; kx[1] = p; nx = 2; }
-    if (ky[0] == 0) { ey[1] = (ey[0] + n - 1) % n; ky[1] = p; ny = 2; }
-    if (kz[0] == 0) { ez[1] = (ez[0] + n - 1) % n; kz[1] = p; nz = 2; }
+  (void)total;
+  for (int row = kb; row < P * P; row += K) {   // one (gz, gy) row per pass, x along the threads
+    const int gz = row / P, gy = row - gz * P;
+    int ey[2], ky[2], ez[2], kz[2];
+    const int ny = node_owners(gy, p, n, ey, ky), nz = node_owners(gz, p, n, ez, kz);
+    for (int gx = threadIdx.x; gx < P; gx += blockDim.x) {
+    const size_t g = size_t(row) * P + gx;
+    int ex[2], kx[2];
+    const int nx = node_owners(gx, p, n, ex, kx);
     double s = 0.0;
     for (int iz = 0; iz < nz; ++iz)
       for (int iy = 0; iy < ny; ++iy)
@@ -70,6 +81,7 @@ __global__ __launch_bounds__(256) void k_load(int n, int p, int K, const double 
     s *= 4.0 * M_PI;
     b[g] = s;
     acc += s;
+    }
   }
   double t = block_sum(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
@@ -85,9 +97,14 @@ __global__ __launch_bounds__(256) void k_sub_mass_ones(int n, int p, int K, cons
   const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
   double *v = vall + size_t(cfg) * total;
   const double s = scal[cfg] / (double(n) * n * n);
-  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < total; g += size_t(K) * blockDim.x) {
-    const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
-    v[g] -= s * w1[gx % p] * w1[gy % p] * w1[gz % p];
+  (void)total;
+  for (int row = kb; row < P * P; row += K) {
+    const int gz = row / P, gy = row - gz * P;
+    const double wy = w1[gy % p], wz = w1[gz % p];
+    for (int gx = threadIdx.x; gx < P; gx += blockDim.x) {
+      const size_t g = size_t(row) * P + gx;
+      v[g] -= s * w1[gx % p] * wy * wz;
+    }
   }
 }
 
@@ -101,9 +118,11 @@ __global__ __launch_bounds__(256) void k_mass_dot(int n, int p, int K, const dou
   const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
   const double *v = vall + size_t(cfg) * total;
   double acc = 0.0;
-  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < total; g += size_t(K) * blockDim.x) {
-    const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
-    acc += w1[gx % p] * w1[gy % p] * w1[gz % p] * v[g];
+  (void)total;
+  for (int row = kb; row < P * P; row += K) {
+    const int gz = row / P, gy = row - gz * P;
+    const double wy = w1[gy % p], wz = w1[gz % p];
+    for (int gx = threadIdx.x; gx < P; gx += blockDim.x) acc += w1[gx % p] * wy * wz * v[size_t(row) * P + gx];
   }
   double t = block_sum(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
