@@ -384,7 +384,8 @@ def main():
         # the operator's own arithmetic: sum-factorised Kronecker-sum apply,
         # 7 one-dimensional band passes of 7 multiply-adds per node on average
         # (6 taps inside an element, 11 at a vertex) = 98 FLOP per DOF
-        dofs = (5 * r["n"]) ** 3 * len(r["counts"])
+        # with forces every fine-level launch covers the forward and the adjoint system
+        dofs = (5 * r["n"]) ** 3 * len(r["counts"]) * (2 if forces else 1)
         tf = OPERATOR_FLOP_PER_DOF * dofs / (op["avg_launch_ms"] * 1e-3) / 1e12
         op["flop_achieved"] = tf
         op["flop_peak"] = PEAK_FP64_TFLOPS   # the PCG operator is float64 in both precisions
