@@ -1091,6 +1091,7 @@ void fep3m_ctx::evaluate_graph(const double *x, const double *Qc, double *Phi, d
       }
       if (fr <= opt.mg_rtol && (!F || ar <= opt.mg_rtol)) {
         done = true;
+        lam_ready = F != nullptr;   // the replayed forward solved lambda only with forces
         finish_host();
         stats.mg_iterations = cap_iters[0];
         stats.mg_rel_residual = fr;

@@ -64,3 +64,27 @@ def test_graph_replay_input_errors(torch):
     assert ei.value.status == fp.ERR_NOT_NEUTRAL
     tQ[3] -= 0.5
     assert g.energy(tx, tQ)[1].item() == ref
+
+
+def test_graph_replayed_energy_then_backward(torch):
+    """Energy-only graph replays followed by the reverse pass (autograd): each
+    backward call must solve the adjoint system of the replayed forward, not
+    reuse the previous call's, and equal an eager energy_forces call."""
+    N, n = 800, 8
+    rng = np.random.default_rng(21)
+    Q = rng.uniform(-1, 1, N)
+    Q -= Q.mean()
+    g = fp.Context(1.0, N, n, use_graph=1)
+    e = fp.Context(1.0, N, n)
+    tQ = torch.from_numpy(Q).cuda()
+    tx = torch.from_numpy(rng.random((N, 3))).cuda()
+    for k in range(4):
+        if k:
+            tx = (tx + 1e-2 * torch.from_numpy(rng.standard_normal((N, 3))).cuda()) % 1.0
+        xg = tx.clone().requires_grad_(True)
+        U = fp.FEP3MEnergy.apply(xg, tQ, g)
+        U.sum().backward()
+        oe = e.energy_forces(tx, tQ)
+        np.testing.assert_allclose(-xg.grad.cpu().numpy(), oe["F"].cpu().numpy(), rtol=0, atol=1e-9 * float(
+            oe["F"].abs().max()), err_msg=f"call {k}")
+    assert g.stats()["graph_replays"] >= 2
