@@ -28,31 +28,59 @@ __device__ __forceinline__ double block_sum_a(double v, double *red) {
   return r;
 }
 
-// g_E[m] for one element per block: thread m sums over the element's charges.
+// g_E[m] = sum over the element's charges of Q l_mx(u_x) l_my(u_y) l_mz(u_z):
+// one wave per element (4 per block), lane l owns nodes m = l + 64 k; per
+// charge every lane evaluates the (p+1) 1-D basis values of each axis once.
 template <int PO>
-__global__ __launch_bounds__(256) void k_deposit(int n, int64_t N, GllBasis bas, const int *__restrict__ start,
+__global__ __launch_bounds__(256) void k_deposit(int n, int MT, int64_t N, GllBasis bas, const int *__restrict__ start,
                                                  const double *__restrict__ sg, const double *__restrict__ sQ,
                                                  double *__restrict__ gE) {
-  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
-  const int E = blockIdx.x;   // element of the whole batch; local coordinates below
-  const int m = threadIdx.x;
-  if (m >= NM) return;
-  const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NK = (NM + 63) / 64;
+  const int E = blockIdx.x * 4 + (threadIdx.x >> 6);   // element of the whole batch
+  if (E >= MT) return;                                  // uniform over the wave
+  const int lane = threadIdx.x & 63;
   const int El = E % (n * n * n);
   const int ex = El % n, ey = (El / n) % n, ez = El / (n * n);
-  double acc = 0.0;
-  for (int s = start[E]; s < start[E + 1]; ++s) {
-    const double ux = sg[s] - ex - 0.5, uy = sg[N + s] - ey - 0.5, uz = sg[2 * N + s] - ez - 0.5;
-    double lx = bas.w[mx], ly = bas.w[my], lz = bas.w[mz];
+  int mx[NK], my[NK], mz[NK];
+  double acc[NK];
 #pragma unroll
-    for (int j = 0; j < Q1; ++j) {
-      if (j != mx) lx *= ux - bas.x[j];
-      if (j != my) ly *= uy - bas.x[j];
-      if (j != mz) lz *= uz - bas.x[j];
-    }
-    acc += sQ[s] * lx * ly * lz;
+  for (int k = 0; k < NK; ++k) {
+    const int m = min(lane + 64 * k, NM - 1);
+    mx[k] = m % Q1; my[k] = (m / Q1) % Q1; mz[k] = m / (Q1 * Q1);
+    acc[k] = 0.0;
   }
-  gE[size_t(E) * NM + m] = acc;
+  const int s1 = start[E + 1];
+  for (int s = start[E]; s < s1; ++s) {
+    const double u[3] = {sg[s] - ex - 0.5, sg[N + s] - ey - 0.5, sg[2 * N + s] - ez - 0.5};
+    double l[3][Q1];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+      for (int a = 0; a < Q1; ++a) {
+        double v = bas.w[a];
+#pragma unroll
+        for (int j = 0; j < Q1; ++j)
+          if (j != a) v *= u[ax] - bas.x[j];
+        l[ax][a] = v;
+      }
+    const double q = sQ[s];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      double lx = 0.0, ly = 0.0, lz = 0.0;   // select the lane's node values (indices are per lane)
+#pragma unroll
+      for (int a = 0; a < Q1; ++a) {
+        lx = mx[k] == a ? l[0][a] : lx;
+        ly = my[k] == a ? l[1][a] : ly;
+        lz = mz[k] == a ? l[2][a] : lz;
+      }
+      acc[k] += q * lx * ly * lz;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int m = lane + 64 * k;
+    if (m < NM) gE[size_t(E) * NM + m] = acc[k];
+  }
 }
 
 // G at each global node: sum of the owning elements' g values (gather form),
@@ -346,7 +374,8 @@ __global__ __launch_bounds__(256) void k_forces(int n, int64_t N, int nb, const 
 int launch_deposit(hipStream_t s, int nb, int p, int n, int64_t N, const GllBasis &bas, const int *start,
                    const double *sg, const double *sQ, double *gE) {
   if (p != 5) return -1;
-  hipLaunchKernelGGL(k_deposit<5>, dim3(nb * n * n * n), dim3(256), 0, s, n, N, bas, start, sg, sQ, gE);
+  const int MT = nb * n * n * n;
+  hipLaunchKernelGGL(k_deposit<5>, dim3((MT + 3) / 4), dim3(256), 0, s, n, MT, N, bas, start, sg, sQ, gE);
   return 0;
 }
 int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, double *G, double *partial) {
