@@ -50,9 +50,12 @@ def test_batch_matches_single_configurations(torch, precision):
         ctx = fp.Context(1.0, N, n, mg_rtol=1e-12, precision=precision)
         ref = ctx.energy_forces(torch.from_numpy(xs[b]).cuda(), torch.from_numpy(Qs[b]).cuda(), dUdQ=True, Phi=True)
         sl = slice(off[b], off[b + 1])
+        # FP64: the survey's bar of 1e-12 (measured: <= 3e-13; the batch's
+        # per-configuration reductions use other block counts than a single run)
+        tol = 1e-12 if precision == fp.PRECISION_FP64 else 1e-10
         for k in ("Phi", "F", "dUdQ"):
-            assert _rel(out[k][sl].cpu().numpy(), ref[k].cpu().numpy()) < 1e-10, (b, k)
-        assert abs(float(out["U"][b]) - float(ref["U"])) < 1e-10 * abs(float(ref["U"])), b
+            assert _rel(out[k][sl].cpu().numpy(), ref[k].cpu().numpy()) < tol, (b, k)
+        assert abs(float(out["U"][b]) - float(ref["U"])) < tol * abs(float(ref["U"])), b
 
 
 def test_batch_against_oracle(torch):
