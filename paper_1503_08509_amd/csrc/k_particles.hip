@@ -241,6 +241,15 @@ __global__ __launch_bounds__(256) void k_moments(int n, int MT, int64_t N, const
 // One chunk of nt <= NT targets starting at sorted slot t0: every lane
 // walks its strided share of the block's sources and accumulates for all NT
 // targets in registers; the wave then reduces.
+// 1 / sqrt(x) for a positive normal x: the hardware estimate refined by one
+// Newton-Raphson step y <- y (3 - x y^2) / 2, written as y + y e / 2 with
+// e = 1 - x y^2 (one step squares the estimate's relative error).
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
 template <int NSR, bool FORCE, int NT>
 __device__ __forceinline__ void pair_chunk(const PairSegments<NSR> &seg, int total, int lane, int64_t N, int t0,
                                            int nt, double nd, const double *__restrict__ sg,
@@ -265,14 +274,17 @@ __device__ __forceinline__ void pair_chunk(const PairSegments<NSR> &seg, int tot
     const double qj = sQ[j];
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
+      // slots k >= nt repeat the first target and are discarded at the end;
+      // the self pair gets r^2 = 2^1000, so its terms (below 2^-500) vanish
+      // in the sums
       const double dx = jx - tx[k], dy = jy - ty[k], dz = jz - tz[k];
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      const bool use = (k < nt) && (j != t0 + k);
-      const double ri = rsqrt(r2);
-      const double qr = use ? qj * ri : 0.0;
+      double r2 = dx * dx + dy * dy + dz * dz;
+      r2 = (j == t0 + k) ? 0x1p1000 : r2;
+      const double ri = rsqrt_pos(r2);
+      const double qr = qj * ri;
       acc[k] += qr;
       if (FORCE) {
-        const double qr3 = qr * (use ? ri * ri : 0.0);  // the skipped self pair has ri = inf
+        const double qr3 = qr * (ri * ri);
         fx[k] += qr3 * dx;
         fy[k] += qr3 * dy;
         fz[k] += qr3 * dz;
