@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="fp64: float64 throughout; mixed: float32 multigrid preconditioner, near field and "
                          "interpolation with compensated sums, float64 reductions")
+    ap.add_argument("--near", choices=["auto", "direct", "fft"], default="auto",
+                    help="near-screen field and its transpose: FFTs where the mesh allows (auto), table sums, or FFTs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mixed-precision, clustered and batched measurements reported beside the FP64 line")
@@ -215,7 +217,7 @@ def stream_copy_gbs():
     return 2 * 2**30 / (best * 1e-3) / 1e9
 
 
-def kernel_rooflines(prof, steps, mixed):
+def kernel_rooflines(prof, steps, mixed, near_fft=False):
     def kern(slot, bound):
         s = prof[slot]
         if s["count"] == 0 or s["ms"] <= 0:
@@ -234,16 +236,22 @@ def kernel_rooflines(prof, steps, mixed):
                 "frac": ach / peak, "traffic": None,
                 "avg_launch_ms": s["ms"] / s["count"], "launches_per_step": s["count"] / steps}
 
-    kernels = {"k_psi (near-screen field)": kern("near", "mfma"),
-               "k_pair (near-pair sum)": kern("pair", "alu"),
-               "k_apply p=5 (fine-level operator)": kern("fine_apply", "hbm"),
-               "k_adj_moments (transposed near field)": kern("adj_near", "alu")}
+    if near_fft:   # transforms and spectrum products: bytes in and out of each launch
+        kernels = {"near-screen field (FFTs + spectrum product)": kern("near", "hbm"),
+                   "k_pair (near-pair sum)": kern("pair", "alu"),
+                   "k_apply p=5 (fine-level operator)": kern("fine_apply", "hbm"),
+                   "transposed near field (FFTs + spectrum product)": kern("adj_near", "hbm")}
+    else:
+        kernels = {"k_psi (near-screen field)": kern("near", "mfma"),
+                   "k_pair (near-pair sum)": kern("pair", "alu"),
+                   "k_apply p=5 (fine-level operator)": kern("fine_apply", "hbm"),
+                   "k_adj_moments (transposed near field)": kern("adj_near", "alu")}
     if mixed:
         kernels["k_apply<float> p=5 (fine-level preconditioner operator)"] = kern("fine_apply_f32", "hbm")
     return {k: v for k, v in kernels.items() if v}
 
 
-def measure(name, precision, steps, warmup, forces=True, graph=False, solver=0):
+def measure(name, precision, steps, warmup, forces=True, graph=False, solver=0, near_field=0):
     """Run `warmup` + `steps` evaluations of one workload; device-resident
     inputs; returns timings, per-stage device times, kernel rooflines, the
     outputs of the last step (host copies) and the context statistics."""
@@ -259,7 +267,7 @@ def measure(name, precision, steps, warmup, forces=True, graph=False, solver=0):
     tQ = torch.from_numpy(Q).to(dev)
     ctx = fp.Context(L, counts if len(counts) > 1 else counts[0], n,
                      precision=fp.PRECISION_MIXED if mixed else fp.PRECISION_FP64, use_graph=1 if graph else 0,
-                     solver=solver)
+                     solver=solver, near_field=near_field)
 
     def step():
         if forces:
@@ -284,7 +292,7 @@ def measure(name, precision, steps, warmup, forces=True, graph=False, solver=0):
     res = {
         "workload": label, "precision": precision, "counts": counts, "n": n, "L": L, "ms_per_step": ms,
         "pairs": st["near_pairs"], "value": st["near_pairs"] / (ms * 1e-3), "stats": st,
-        "kernels": kernel_rooflines(prof, steps, mixed),
+        "kernels": kernel_rooflines(prof, steps, mixed, bool(st["near_fft"])),
         "stages_ms_per_step": {k: v["ms"] / steps for k, v in prof.items() if not k.startswith("fine_apply")},
         "out": {k: v.detach().cpu().numpy() for k, v in out.items()},
         "x": x, "Q": Q, "mg_rtol": ctx.options.mg_rtol,
@@ -371,7 +379,8 @@ def main():
         return
 
     forces = args.outputs == "forces"
-    r = measure(args.workload, args.precision, args.steps, args.warmup, forces)
+    r = measure(args.workload, args.precision, args.steps, args.warmup, forces,
+                near_field={"auto": 0, "direct": 1, "fft": 2}[args.near])
     mixed = args.precision == "mixed"
     kernels = r["kernels"]
     practical = stream_copy_gbs() if not args.no_variants else None   # kept out of profiled runs
@@ -449,6 +458,11 @@ def main():
         ug = measure("uniform-1M-n64", "fp64", 3, 2, graph=True)
         variants["fp64 uniform-1M-n64 hipGraph"] = variant_summary(ug, r)
         del ug
+        # the near field and its transpose as direct table sums instead of FFTs
+        for prec in ("fp64", "mixed"):
+            dn = measure("uniform-1M-n64", prec, 3, 1, near_field=1)
+            variants[f"{prec} uniform-1M-n64 direct near field"] = variant_summary(dn, r)
+            del dn
         # the smaller configurations: 1000 charges on 8^3, 1e5 on 32^3 (FP64 and mixed side by side)
         for wl in ("uniform-1k-n8", "uniform-100k-n32"):
             s64 = measure(wl, "fp64", 5, 2)

@@ -85,6 +85,24 @@ enum {
                             (the achieved residual is still measured).  */
 };
 
+/* Evaluation of the near-screen field and of its transpose in the moment
+ * adjoint (Section 3, eq. sc with the Remark's tables).  Both are periodic
+ * convolutions over the element lattice with the table as the kernel. */
+enum {
+  FEP3M_NEAR_AUTO = 0,    /* FFT when the mesh allows it (n a power of two,
+                             8 <= n <= 64), else DIRECT                         */
+  FEP3M_NEAR_DIRECT = 1,  /* the table sums themselves: 2 * 8 * (p+1)^3 FLOP per
+                             element and near offset (matrix cores forward,
+                             vector units for the transpose)                    */
+  FEP3M_NEAR_FFT = 2      /* the same linear maps through the convolution
+                             theorem: 3-D FFTs of the moments and node fields,
+                             products with the tables' spectrum (computed at
+                             create: n^2 (n/2 + 1) x 8 x (p+1)^3 complex float64,
+                             3.7 GB at n = 64).  float64 in both precisions;
+                             n must be a power of two in [8, 128]. Agrees with
+                             DIRECT to about 1e-15 relative.                    */
+};
+
 typedef struct {
   int32_t n_sr;          /* near block radius in elements (default 3: 7^3 block,
                             the paper's short-range list, Section 4)             */
@@ -118,6 +136,7 @@ typedef struct {
                             eager launches.  Not used while profiling is on,
                             nor with solver = FEP3M_SOLVER_FDM.                */
   int32_t solver;        /* FEP3M_SOLVER_* (default: multigrid-preconditioned CG) */
+  int32_t near_field;    /* FEP3M_NEAR_* (default AUTO)                          */
 } fep3m_options;
 
 typedef struct {
@@ -138,15 +157,18 @@ typedef struct {
   double  tune_ms_best;      /* device time of the chosen variant when tuned      */
   double  tune_ms_default;   /* device time of one wave per element when tuned    */
   int64_t graph_replays;     /* evaluations served by a graph replay (use_graph)  */
+  int32_t near_fft;          /* 1: the near field and its transpose run as FFTs   */
 } fep3m_stats;
 
 /* Profile slots: stages of one call, the fine-level operator launches, and
  * the whole call.  `work` holds the algorithmic work of the slot: floating
- * point operations for NEAR and ADJ_NEAR (2 * 8 * (p+1)^3 per element and
- * near offset) and PAIR (11 per ordered near pair, 20 when forces are
- * accumulated in the same pass), bytes that must cross HBM
- * for FINE_APPLY (the vectors each launch reads and writes, 8 bytes per DOF
- * each), 0 elsewhere. */
+ * point operations for NEAR and ADJ_NEAR on the direct path (2 * 8 * (p+1)^3
+ * per element and near offset) and PAIR (11 per ordered near pair, 20 when
+ * forces are accumulated in the same pass); bytes that must cross HBM for
+ * NEAR and ADJ_NEAR on the FFT path (what each of their launches reads and
+ * writes: the table spectrum once per product, every FFT pass's array in and
+ * out) and for FINE_APPLY (the vectors each launch reads and writes, 8 bytes
+ * per DOF each); 0 elsewhere. */
 enum {
   FEP3M_PROF_SORT = 0,        /* wrap, bin, counting sort, gather          */
   FEP3M_PROF_ASSIGN = 1,      /* element moments, load assembly, projection */

@@ -30,13 +30,18 @@ PRECISION_MIXED = 1
 SOLVER_MG = 0
 SOLVER_FDM = 1
 
+NEAR_AUTO = 0
+NEAR_DIRECT = 1
+NEAR_FFT = 2
+
 STAGES = {"perm": 0, "start": 1, "C": 2, "b": 3, "phi": 4, "Phi_p": 5, "Phi_m": 6, "T": 7}
 
 
 class Options(ctypes.Structure):
     _fields_ = [("n_sr", ctypes.c_int32), ("precision", ctypes.c_int32), ("mg_rtol", ctypes.c_double),
                 ("mg_max_iter", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("table_box", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("solver", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("solver", ctypes.c_int32),
+                ("near_field", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -47,7 +52,7 @@ class Stats(ctypes.Structure):
                 ("generation", ctypes.c_int64), ("pair_variant", ctypes.c_int32),
                 ("pair_item_targets", ctypes.c_int32), ("pair_waves", ctypes.c_int32),
                 ("tune_ms_best", ctypes.c_double), ("tune_ms_default", ctypes.c_double),
-                ("graph_replays", ctypes.c_int64)]
+                ("graph_replays", ctypes.c_int64), ("near_fft", ctypes.c_int32)]
 
 
 PROF_SLOTS = ["sort", "assign", "solve", "near", "pair", "interp", "fine_apply", "total",

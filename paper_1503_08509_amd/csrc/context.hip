@@ -131,6 +131,11 @@ struct fep3m_ctx {
   std::vector<double> T_host;
   double *T = nullptr, *Tt = nullptr, *gw = nullptr, *w1 = nullptr;
   GllBasis bas{};
+  // near field by FFTs: table spectrum, twiddles exp(-2 pi i j / n), the
+  // transformed moments / moment adjoint (4 complex channels) and node fields
+  // (108 complex channels)
+  bool near_fft = false;
+  double2 *spec = nullptr, *twd = nullptr, *zc = nullptr, *za = nullptr, *z108 = nullptr;
 
   // particles
   double *gtmp = nullptr, *sg = nullptr, *sQ = nullptr;
@@ -281,6 +286,7 @@ struct fep3m_ctx {
   void solve(const double *rhs, double *out, int which);
   void fdm_solve(const double *rhs, double *out, int which);
   void build_fdm();
+  void build_near_fft();
   void mesh_solve(double *rhs, double *out, int which, int nsys = 1);
   void adjoint_rhs();
   void store_rel(int which);
@@ -415,6 +421,9 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   partial_len = std::max(partial_len, size_t(2) * nb * apply_blocks(lv[0].op) + 64);
   partial = alloc<double>(partial_len, "partials");
   estimate_spectra();
+  near_fft = opt.near_field == FEP3M_NEAR_FFT || (opt.near_field == FEP3M_NEAR_AUTO && fft_size_ok(n) && n <= 64);
+  if (near_fft) build_near_fft();
+  stats.near_fft = near_fft ? 1 : 0;
   auto t1 = std::chrono::steady_clock::now();
   stats.create_seconds = std::chrono::duration<double>(t1 - t0).count();
   stats.mg_levels = int(lv.size());
@@ -550,6 +559,26 @@ void fep3m_ctx::build_mg() {
     hip_check(hipMemcpy(coarseV, V.a.data(), V.a.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
     hip_check(hipMemcpy(coarseLam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
   }
+}
+
+// Spectrum of the tables over the half set of frequencies (create time, on
+// the device) and the FFT work arrays.
+void fep3m_ctx::build_near_fft() {
+  const size_t M = size_t(n) * n * n, NM = size_t(p + 1) * (p + 1) * (p + 1);
+  std::vector<double2> tw(n);
+  for (int j = 0; j < n; ++j) {
+    const double t = 2.0 * M_PI * double(j) / double(n);
+    tw[j] = make_double2(std::cos(t), -std::sin(t));
+  }
+  twd = alloc<double2>(size_t(n), "FFT twiddles");
+  hip_check(hipMemcpy(twd, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice), "upload twiddles");
+  spec = alloc<double2>(spec_freqs(n) * 8 * NM, "table spectrum");
+  zc = alloc<double2>(size_t(nb) * M * 4, "transformed moments");
+  za = alloc<double2>(size_t(nb) * M * 4, "transformed moment adjoint");
+  z108 = alloc<double2>(size_t(nb) * M * NM / 2, "transformed node field");
+  launch_spec_build(stream, n, nsr, p, T, twd, spec);
+  check_launch("table spectrum");
+  hip_check(hipStreamSynchronize(stream), "table spectrum");
 }
 
 void fep3m_ctx::build_fdm() {
@@ -880,8 +909,13 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   mesh_solve(b, sol, 0, pair_forces ? 2 : 1);
   stage_mark(FEP3M_PROF_SOLVE, false);
   stage_mark(FEP3M_PROF_NEAR, true);
-  const int ps = mixed ? launch_psi<float>(stream, nb, n, nsr, p, C, Tf, sol, Welf)
-                       : launch_psi<double>(stream, nb, n, nsr, p, C, T, sol, Wel);
+  int ps;
+  if (near_fft)
+    ps = mixed ? launch_psi_fft<float>(stream, nb, n, p, C, spec, twd, sol, zc, z108, Welf)
+               : launch_psi_fft<double>(stream, nb, n, p, C, spec, twd, sol, zc, z108, Wel);
+  else
+    ps = mixed ? launch_psi<float>(stream, nb, n, nsr, p, C, Tf, sol, Welf)
+               : launch_psi<double>(stream, nb, n, nsr, p, C, T, sol, Wel);
   if (ps != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
   stage_mark(FEP3M_PROF_NEAR, false);
   pair_pass(pair_forces);
@@ -982,8 +1016,9 @@ void fep3m_ctx::reverse(double *F, double *dUdQ) {
     lam_ready = true;
   }
   stage_mark(FEP3M_PROF_ADJ_NEAR, true);
-  if (launch_adj_moments(stream, nb, p, n, nsr, gE, Tt, lam, gw, Aadj) != 0)
-    throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
+  const int as = near_fft ? launch_adj_moments_fft(stream, nb, p, n, gE, spec, twd, lam, gw, z108, za, Aadj)
+                          : launch_adj_moments(stream, nb, p, n, nsr, gE, Tt, lam, gw, Aadj);
+  if (as != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
   stage_mark(FEP3M_PROF_ADJ_NEAR, false);
   stage_mark(FEP3M_PROF_FORCES, true);
   if (mixed)
@@ -1158,11 +1193,19 @@ void fep3m_ctx::profile_collect() {
     prof.acc.count[s] += 1;
   }
   const double S = 2 * nsr + 1;
-  const double near_flop = 2.0 * 8.0 * (p + 1) * (p + 1) * (p + 1) * S * S * S * double(n) * n * n * nb;
+  const double Me = double(n) * n * n * nb, NM = double(p + 1) * (p + 1) * (p + 1);
+  double near_flop = 2.0 * 8.0 * NM * S * S * S * Me, adj_work = near_flop;
+  if (near_fft) {   // bytes in and out of every launch of the two FFT pipelines
+    const double spec_b = double(spec_freqs(n)) * 8.0 * NM * 16.0;
+    const double f4 = Me * 4.0 * 16.0, f108 = Me * NM / 2.0 * 16.0, phi_b = Me * 125.0 * 8.0;
+    const double w_b = Me * NM * (mixed ? 4.0 : 8.0);
+    near_flop = 3.0 * 2.0 * f4 + (spec_b + f4 + f108) + 2.0 * 2.0 * f108 + (f108 + phi_b + w_b);
+    adj_work = 3.0 * 2.0 * f108 + (spec_b + f108 + f4) + 3.0 * 2.0 * f4 + (f4 + phi_b + Me * 8.0 * 8.0);
+  }
   if (prof.marked & (1u << FEP3M_PROF_NEAR)) prof.acc.work[FEP3M_PROF_NEAR] += near_flop;
   if (prof.marked & (1u << FEP3M_PROF_PAIR))
     prof.acc.work[FEP3M_PROF_PAIR] += (prof.pair_forces ? 20.0 : 11.0) * double(stats.near_pairs);
-  if (prof.marked & (1u << FEP3M_PROF_ADJ_NEAR)) prof.acc.work[FEP3M_PROF_ADJ_NEAR] += near_flop;
+  if (prof.marked & (1u << FEP3M_PROF_ADJ_NEAR)) prof.acc.work[FEP3M_PROF_ADJ_NEAR] += adj_work;
   for (int k = 0; k < prof.kused; ++k) {
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, prof.kev[2 * k], prof.kev[2 * k + 1]), "elapsed");
@@ -1205,6 +1248,7 @@ bool valid_options(const fep3m_options &o, std::string &why) {
   if (o.autotune != 0 && o.autotune != 1) { why = "autotune must be 0 or 1"; return false; }
   if (o.use_graph != 0 && o.use_graph != 1) { why = "use_graph must be 0 or 1"; return false; }
   if (o.solver != FEP3M_SOLVER_MG && o.solver != FEP3M_SOLVER_FDM) { why = "unknown solver"; return false; }
+  if (o.near_field < FEP3M_NEAR_AUTO || o.near_field > FEP3M_NEAR_FFT) { why = "unknown near_field"; return false; }
   if (o.table_box % 2 == 0 || o.table_box < 2 * o.n_sr + 3 || o.table_box > 41) {
     why = "table_box must be odd, > 2 n_sr + 1 and <= 41";
     return false;
@@ -1227,6 +1271,7 @@ int fep3m_default_options(fep3m_options *opt) {
   opt->autotune = 1;
   opt->use_graph = 0;
   opt->solver = FEP3M_SOLVER_MG;
+  opt->near_field = FEP3M_NEAR_AUTO;
   return FEP3M_OK;
 }
 
@@ -1254,6 +1299,7 @@ int create_common(double L, const std::vector<int64_t> &Ns, const int32_t dims[3
   if (dims[0] < 2 * o.n_sr + 1 || dims[0] > 512) return FEP3M_ERR_ARG;
   if (q < 2 || q > 6) return FEP3M_ERR_ARG;
   if (q != 3) return FEP3M_ERR_UNSUPPORTED;
+  if (o.near_field == FEP3M_NEAR_FFT && !fft_size_ok(dims[0])) return FEP3M_ERR_UNSUPPORTED;
   std::unique_ptr<fep3m_ctx> ctx(new (std::nothrow) fep3m_ctx());
   if (!ctx) return FEP3M_ERR_OOM;
   int st = guarded(ctx.get(), [&] { ctx->build(L, Ns, dims[0], q, o); });

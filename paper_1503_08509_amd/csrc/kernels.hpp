@@ -77,6 +77,20 @@ int launch_forces(hipStream_t s, int nb, const int *off, int p, int n, int64_t N
 template <class T>
 int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, const double *C, const T *Tab, const double *phi, T *Wel);
 
+// near field and its transpose by 3-D FFTs of the element lattice (k_fft.hip);
+// n a power of two in [8, 128], p = 5.  S: table spectrum of spec_freqs(n)
+// frequencies x 8 x (p+1)^3 complex values; tw: exp(-2 pi i j / n), j < n.
+// Scratch: zc, za nb n^3 x 4 complex; z nb n^3 x (p+1)^3 / 2 complex.
+bool fft_size_ok(int n);
+size_t spec_freqs(int n);
+void launch_spec_build(hipStream_t s, int n, int nsr, int p, const double *T, const double2 *twf, double2 *S);
+template <class WT>
+int launch_psi_fft(hipStream_t s, int nb, int n, int p, const double *C, const double2 *S, const double2 *tw,
+                   const double *phi, double2 *zc, double2 *z, WT *Wel);
+int launch_adj_moments_fft(hipStream_t s, int nb, int p, int n, const double *gE, const double2 *S,
+                           const double2 *tw, const double *lam, const double *gw, double2 *z, double2 *za,
+                           double *A);
+
 // mesh (k_mesh.hip).  nb configurations; per-configuration reductions
 // write nb * K block partials (K = seg_blocks(nb, per) unless a launcher
 // returns its own K) that launch_sum_partials folds into out[0 .. nb).

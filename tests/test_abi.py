@@ -59,7 +59,7 @@ def test_create_rejects_bad_options():
     h = ctypes.c_void_p()
     d = (ctypes.c_int32 * 3)(8, 8, 8)
     for field, val in (("n_sr", 0), ("mg_rtol", 0.0), ("mg_max_iter", 0), ("table_box", 14), ("table_box", 7),
-                       ("precision", 5), ("cheb_degree", 0)):
+                       ("precision", 5), ("cheb_degree", 0), ("near_field", 3), ("near_field", -1)):
         o = fp.default_options()
         setattr(o, field, val)
         assert fp.lib().fep3m_create_ex(1.0, 100, d, 3, ctypes.byref(o), ctypes.byref(h)) == fp.ERR_ARG, field
@@ -70,6 +70,19 @@ def test_unsupported_degree_is_reported():
     h = ctypes.c_void_p()
     d = (ctypes.c_int32 * 3)(8, 8, 8)
     assert fp.lib().fep3m_create(1.0, 100, d, 4, ctypes.byref(h)) == fp.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n", [7, 9, 12, 256])
+def test_fft_near_field_needs_power_of_two_mesh(n):
+    """The FFT near field is refused (before any device work) unless n is a
+    power of two in [8, 128]; the default picks it only where it applies."""
+    h = ctypes.c_void_p()
+    d = (ctypes.c_int32 * 3)(n, n, n)
+    o = fp.default_options()
+    assert o.near_field == fp.NEAR_AUTO
+    o.near_field = fp.NEAR_FFT
+    assert fp.lib().fep3m_create_ex(1.0, 100, d, 3, ctypes.byref(o), ctypes.byref(h)) == fp.ERR_UNSUPPORTED
+    assert h.value is None
 
 
 def test_create_batch_rejects_bad_arguments():

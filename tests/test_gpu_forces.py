@@ -22,14 +22,17 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("wl,N,n", [("uniform-1k-n8", 1000, 8), ("adhoc-300-n9", 300, 9)])
-def test_forces_match_oracle(torch, wl, N, n):
+@pytest.mark.parametrize("wl,N,n,near", [("uniform-1k-n8", 1000, 8, fp.NEAR_AUTO),
+                                         ("uniform-1k-n8", 1000, 8, fp.NEAR_DIRECT),
+                                         ("adhoc-300-n9", 300, 9, fp.NEAR_AUTO)])
+def test_forces_match_oracle(torch, wl, N, n, near):
     if wl in workloads.WORKLOADS:
         x, Q = workloads.make(wl)
     else:
         x, Q = workloads.uniform(N, seed=31, charges="uniform")
     ref = adjoint.energy_forces(x, Q, fep3m.Params(L=1.0, n=n))
-    ctx = fp.Context(1.0, len(Q), n, mg_rtol=1e-13)
+    ctx = fp.Context(1.0, len(Q), n, mg_rtol=1e-13, near_field=near)
+    assert ctx.stats()["near_fft"] == (near == fp.NEAR_AUTO and n == 8)
     out = ctx.energy_forces(torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda(), dUdQ=True, Phi=True)
     F = out["F"].cpu().numpy()
     g = out["dUdQ"].cpu().numpy()

@@ -25,10 +25,11 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def test_mixed_config1_matches_oracle(torch):
+@pytest.mark.parametrize("near", [fp.NEAR_AUTO, fp.NEAR_DIRECT])
+def test_mixed_config1_matches_oracle(torch, near):
     x, Q = workloads.make("uniform-1k-n8")
     ref = adjoint.energy_forces(x, Q, fep3m.Params(L=1.0, n=8))
-    ctx = fp.Context(1.0, len(Q), 8, precision=fp.PRECISION_MIXED)
+    ctx = fp.Context(1.0, len(Q), 8, precision=fp.PRECISION_MIXED, near_field=near)
     out = ctx.energy_forces(torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda(), dUdQ=True, Phi=True)
     assert _rel(out["Phi"].cpu().numpy(), ref["Phi"]) < MIXED_TOL
     assert _rel(out["F"].cpu().numpy(), ref["F"]) < MIXED_TOL

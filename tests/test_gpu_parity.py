@@ -36,11 +36,13 @@ def _stable_order(e_lin, n):
     return np.argsort(e_lin, kind="stable"), np.concatenate([[0], np.cumsum(np.bincount(e_lin, minlength=n**3))])
 
 
-def test_config1_stage_parity(torch):
+@pytest.mark.parametrize("near", [fp.NEAR_FFT, fp.NEAR_DIRECT])
+def test_config1_stage_parity(torch, near):
     x, Q = workloads.make("uniform-1k-n8")
     L, n = 1.0, 8
     ref = fep3m.run(x, Q, fep3m.Params(L=L, n=n), stages=True)
-    ctx, Phi, U = _gpu(torch, x, Q, L, n, mg_rtol=1e-13)     # tight solve: stages exact
+    ctx, Phi, U = _gpu(torch, x, Q, L, n, mg_rtol=1e-13, near_field=near)     # tight solve: stages exact
+    assert ctx.stats()["near_fft"] == (near == fp.NEAR_FFT)
     order, start = _stable_order(ref["e_lin"], n)
     np.testing.assert_array_equal(ctx.stage("perm").cpu().numpy(), order)
     np.testing.assert_array_equal(ctx.stage("start").cpu().numpy(), start)
