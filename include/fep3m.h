@@ -97,8 +97,10 @@ enum {
   FEP3M_NEAR_FFT = 2      /* the same linear maps through the convolution
                              theorem: 3-D FFTs of the moments and node fields,
                              products with the tables' spectrum (computed at
-                             create: n^2 (n/2 + 1) x 8 x (p+1)^3 complex float64,
-                             3.7 GB at n = 64).  float64 in both precisions;
+                             create for one octant of frequencies, the tables
+                             being symmetric under axis reflections:
+                             (n/2 + 1)^3 x 8 x (p+1)^3 complex float64, 0.99 GB
+                             at n = 64).  float64 in both precisions;
                              n must be a power of two in [8, 128]. Agrees with
                              DIRECT to about 1e-15 relative.                    */
 };

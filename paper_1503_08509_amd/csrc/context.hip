@@ -55,6 +55,8 @@ struct Profiler {
   int kused = 0;
   unsigned marked = 0;        // slots recorded in the current call
   bool pair_forces = false;   // the current call's pair pass accumulated gradients
+  bool near_both = false;     // the near-field stage also transformed the deposits (FFT path)
+  bool adj_full = false;      // the moment-adjoint stage ran the deposits' transforms itself
   fep3m_profile acc{};
   void begin_call() {
     kused = 0;
@@ -116,6 +118,7 @@ struct fep3m_ctx {
   PcgScalars pcs{};                 // 2 nb values per scalar
   double *gauge = nullptr;          // 2 nb integrals of the solutions (gauge)
   bool lam_ready = false;           // the last forward call also solved for lambda
+  bool adj_near_ready = false;      // ... and transformed the moment adjoint's near part (FFT path)
   double *cfgs(int slot) const { return cs + size_t(slot) * nb; }
   int n = 0, q = 3, p = 5, d = 1, nsr = 3, B = 15;
   fep3m_options opt{};
@@ -132,10 +135,10 @@ struct fep3m_ctx {
   double *T = nullptr, *Tt = nullptr, *gw = nullptr, *w1 = nullptr;
   GllBasis bas{};
   // near field by FFTs: table spectrum, twiddles exp(-2 pi i j / n), the
-  // transformed moments / moment adjoint (4 complex channels) and node fields
-  // (108 complex channels)
+  // transformed moments / moment adjoint (4 complex channels), near-screen
+  // field and deposits (108 complex channels)
   bool near_fft = false;
-  double2 *spec = nullptr, *twd = nullptr, *zc = nullptr, *za = nullptr, *z108 = nullptr;
+  double2 *spec = nullptr, *twd = nullptr, *zc = nullptr, *za = nullptr, *zpsi = nullptr, *zg = nullptr;
 
   // particles
   double *gtmp = nullptr, *sg = nullptr, *sQ = nullptr;
@@ -561,8 +564,8 @@ void fep3m_ctx::build_mg() {
   }
 }
 
-// Spectrum of the tables over the half set of frequencies (create time, on
-// the device) and the FFT work arrays.
+// Spectrum of the tables at the octant frequencies (create time, on the
+// device) and the FFT work arrays.
 void fep3m_ctx::build_near_fft() {
   const size_t M = size_t(n) * n * n, NM = size_t(p + 1) * (p + 1) * (p + 1);
   std::vector<double2> tw(n);
@@ -575,7 +578,8 @@ void fep3m_ctx::build_near_fft() {
   spec = alloc<double2>(spec_freqs(n) * 8 * NM, "table spectrum");
   zc = alloc<double2>(size_t(nb) * M * 4, "transformed moments");
   za = alloc<double2>(size_t(nb) * M * 4, "transformed moment adjoint");
-  z108 = alloc<double2>(size_t(nb) * M * NM / 2, "transformed node field");
+  zpsi = alloc<double2>(size_t(nb) * M * NM / 2, "transformed near-screen field");
+  zg = alloc<double2>(size_t(nb) * M * NM / 2, "transformed deposits");
   launch_spec_build(stream, n, nsr, p, T, twd, spec);
   check_launch("table spectrum");
   hip_check(hipStreamSynchronize(stream), "table spectrum");
@@ -910,10 +914,17 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   stage_mark(FEP3M_PROF_SOLVE, false);
   stage_mark(FEP3M_PROF_NEAR, true);
   int ps;
-  if (near_fft)
-    ps = mixed ? launch_psi_fft<float>(stream, nb, n, p, C, spec, twd, sol, zc, z108, Welf)
-               : launch_psi_fft<double>(stream, nb, n, p, C, spec, twd, sol, zc, z108, Wel);
-  else
+  adj_near_ready = false;
+  if (near_fft) {
+    // with forces the deposits (built before the solve) are transformed too
+    // and one pass over the spectrum serves both products
+    ps = launch_near_fft(stream, nb, n, p, C, pair_forces ? gE : nullptr, spec, twd, zc, zpsi, zg, za);
+    if (ps == 0)
+      ps = mixed ? launch_psi_fft_finish<float>(stream, nb, n, p, twd, sol, zpsi, Welf)
+                 : launch_psi_fft_finish<double>(stream, nb, n, p, twd, sol, zpsi, Wel);
+    adj_near_ready = pair_forces;
+    prof.near_both = pair_forces;
+  } else
     ps = mixed ? launch_psi<float>(stream, nb, n, nsr, p, C, Tf, sol, Welf)
                : launch_psi<double>(stream, nb, n, nsr, p, C, T, sol, Wel);
   if (ps != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
@@ -1016,8 +1027,15 @@ void fep3m_ctx::reverse(double *F, double *dUdQ) {
     lam_ready = true;
   }
   stage_mark(FEP3M_PROF_ADJ_NEAR, true);
-  const int as = near_fft ? launch_adj_moments_fft(stream, nb, p, n, gE, spec, twd, lam, gw, z108, za, Aadj)
-                          : launch_adj_moments(stream, nb, p, n, nsr, gE, Tt, lam, gw, Aadj);
+  int as;
+  if (near_fft) {
+    prof.adj_full = !adj_near_ready;
+    as = adj_near_ready ? 0 : launch_near_fft(stream, nb, n, p, nullptr, gE, spec, twd, zc, zpsi, zg, za);
+    if (as == 0) as = launch_adj_fft_finish(stream, nb, n, p, lam, gw, za, Aadj);
+    adj_near_ready = false;
+  } else {
+    as = launch_adj_moments(stream, nb, p, n, nsr, gE, Tt, lam, gw, Aadj);
+  }
   if (as != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
   stage_mark(FEP3M_PROF_ADJ_NEAR, false);
   stage_mark(FEP3M_PROF_FORCES, true);
@@ -1127,6 +1145,7 @@ void fep3m_ctx::evaluate_graph(const double *x, const double *Qc, double *Phi, d
       if (fr <= opt.mg_rtol && (!F || ar <= opt.mg_rtol)) {
         done = true;
         lam_ready = F != nullptr;   // the replayed forward solved lambda only with forces
+        adj_near_ready = false;     // the replay's reverse pass consumed it
         finish_host();
         stats.mg_iterations = cap_iters[0];
         stats.mg_rel_residual = fr;
@@ -1195,12 +1214,17 @@ void fep3m_ctx::profile_collect() {
   const double S = 2 * nsr + 1;
   const double Me = double(n) * n * n * nb, NM = double(p + 1) * (p + 1) * (p + 1);
   double near_flop = 2.0 * 8.0 * NM * S * S * S * Me, adj_work = near_flop;
-  if (near_fft) {   // bytes in and out of every launch of the two FFT pipelines
+  if (near_fft) {   // bytes in and out of every launch of the FFT pipelines
     const double spec_b = double(spec_freqs(n)) * 8.0 * NM * 16.0;
     const double f4 = Me * 4.0 * 16.0, f108 = Me * NM / 2.0 * 16.0, phi_b = Me * 125.0 * 8.0;
     const double w_b = Me * NM * (mixed ? 4.0 : 8.0);
-    near_flop = 3.0 * 2.0 * f4 + (spec_b + f4 + f108) + 2.0 * 2.0 * f108 + (f108 + phi_b + w_b);
-    adj_work = 3.0 * 2.0 * f108 + (spec_b + f108 + f4) + 3.0 * 2.0 * f4 + (f4 + phi_b + Me * 8.0 * 8.0);
+    // moments: 3 passes; products; Psi: 2 passes and the last with phi and W
+    const double psi_part = 3.0 * 2.0 * f4 + (spec_b + f4 + f108) + 2.0 * 2.0 * f108 + (f108 + phi_b + w_b);
+    // deposits: 3 passes; their products (f108 in, f4 out); B: 3 passes
+    const double adj_part = 3.0 * 2.0 * f108 + (f108 + f4) + 3.0 * 2.0 * f4;
+    const double finish = f4 + phi_b + Me * 8.0 * 8.0;   // lambda term and A
+    near_flop = psi_part + (prof.near_both ? adj_part : 0.0);
+    adj_work = finish + (prof.adj_full ? adj_part + spec_b : 0.0);
   }
   if (prof.marked & (1u << FEP3M_PROF_NEAR)) prof.acc.work[FEP3M_PROF_NEAR] += near_flop;
   if (prof.marked & (1u << FEP3M_PROF_PAIR))

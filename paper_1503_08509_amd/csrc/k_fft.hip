@@ -15,8 +15,7 @@
 // B^_a(k) = sum_m conj(S[k][a][m]) g^_m(k) (T is real).  The same linear maps
 // as the direct sums, evaluated with 3-D FFTs of the element lattice: about
 // 2 * 8 * 216 * 16 FLOP per element for the products against 1.19 MFLOP per
-// element for the direct sums; the work becomes memory-bound (the spectrum,
-// 8 * 216 complex values per frequency, is read once per product).
+// element for the direct sums; the work becomes memory-bound.
 //
 // Layout: every transformed field is [config][z][y][x][channel] complex
 // (double2), channel fastest, where two consecutive real channels form one
@@ -25,9 +24,11 @@
 // transforms both real channels; X^_2c(k) = (Z(k) + conj Z(-k)) / 2 and
 // X^_2c+1(k) = (Z(k) - conj Z(-k)) / 2i separate them in the products, which
 // also pack their two real outputs the same way, so the inverse transforms
-// return real pairs directly.  The spectrum is kept for the half set of
-// frequencies k_z in [0, n/2] (S(-k) = conj S(k)); each product handles the
-// pair {k, -k} at once.
+// return real pairs directly.  The tables are symmetric under the three axis
+// reflections, so the spectrum is kept for one octant of frequencies
+// (0 <= k_x, k_y, k_z <= n/2: 0.99 GB at n = 64) and each product block
+// handles the orbit of one octant frequency (which holds -k as well).  With
+// forces both products run in the same blocks: one read of the spectrum.
 //
 // FFTs: one kernel per axis, radix-2 decimation in time in LDS.  A block
 // holds lb lines x cc channels of length n (at most 2048 complex values):
@@ -157,96 +158,125 @@ __global__ __launch_bounds__(256) void k_fft_axis(int n, int logn, int nch, int 
   }
 }
 
-// Forward product: Z_out(k) = (Psi^_2c(k) + i Psi^_2c+1(k)) * scale for the
-// 108 channel pairs c (one lane each), at k and -k.
-__global__ __launch_bounds__(128) void k_spec_psi(int n, int NF, int nm, const double2 *__restrict__ S,
-                                                  const double2 *__restrict__ ZC, double2 *__restrict__ Zout,
-                                                  double scale) {
-  const int kk = blockIdx.x % NF, cfg = blockIdx.x / NF;
-  int fk, fm;
-  if (!freq_pair(kk, n, fk, fm)) return;
-  const int c = threadIdx.x, nc = nm / 2;
-  if (c >= nc) return;
+// Spectrum products over the orbit of one octant frequency k (0 <= k_x,
+// k_y, k_z <= n/2) under the reflections of the axes whose component is
+// neither 0 nor n/2 (pm): the up to 8 frequencies R k, among them -k.  The
+// tables are symmetric under each axis reflection R (node m -> R m, offset
+// D -> R D, moment a -> (-1)^(a.R) a), so S[a][m](R k) = (-1)^(a.R)
+// S[a][R m](k): one stored row of 8 x 216 values serves the whole orbit.
+//   PSI: Zpsi(R k)[c] = (Psi^_2c + i Psi^_2c+1)(R k) * scale
+//   ADJ: ZA(R k)[j] = (B^_2j + i B^_2j+1)(R k) * scale
+// Moments are indexed a = a_x + 2 a_y + 4 a_z (each 0 or 1), nodes
+// m = m_x + 6 (m_y + 6 m_z).
+template <bool PSI, bool ADJ>
+__global__ __launch_bounds__(256) void k_spec_orbit(int n, int NO, const double2 *__restrict__ S,
+                                                    const double2 *__restrict__ ZC, double2 *__restrict__ Zpsi,
+                                                    const double2 *__restrict__ Zg, double2 *__restrict__ ZA,
+                                                    double scale) {
+  constexpr int Q1 = 6, NM = Q1 * Q1 * Q1, NC = NM / 2;
+  __shared__ double2 Ss[8 * NM];
+  __shared__ double2 Cs[8][8];
+  __shared__ double2 Gs[ADJ ? 8 * NM : 1];
+  __shared__ double2 red[ADJ ? 4 : 1][64];
+  const int H = n / 2 + 1;
+  const int ko = blockIdx.x % NO, cfg = blockIdx.x / NO;
+  const int kx = ko % H, ky = (ko / H) % H, kz = ko / (H * H);
+  int pm = 0;
+  if (kx != 0 && 2 * kx != n) pm |= 1;
+  if (ky != 0 && 2 * ky != n) pm |= 2;
+  if (kz != 0 && 2 * kz != n) pm |= 4;
+  auto fidx = [&](int r) {
+    const int x = (r & 1) ? n - kx : kx, y = (r & 2) ? n - ky : ky, z = (r & 4) ? n - kz : kz;
+    return size_t((z * n + y) * n + x);
+  };
+  auto refl = [](int m, int r) {
+    int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
+    if (r & 1) mx = Q1 - 1 - mx;
+    if (r & 2) my = Q1 - 1 - my;
+    if (r & 4) mz = Q1 - 1 - mz;
+    return (mz * Q1 + my) * Q1 + mx;
+  };
   const size_t M = size_t(n) * n * n;
-  ZC += size_t(cfg) * M * 4;
-  Zout += size_t(cfg) * M * nc;
-  double2 Ch[8];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const double2 z = ZC[size_t(fk) * 4 + a], zm = ZC[size_t(fm) * 4 + a];
-    Ch[2 * a] = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
-    Ch[2 * a + 1] = make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x));
-  }
-  const double2 *Sk = S + size_t(kk) * 8 * nm + 2 * c;
-  double2 P0 = make_double2(0.0, 0.0), P1 = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    const double2 s0 = Sk[a * nm], s1 = Sk[a * nm + 1];
-    P0 = cadd(P0, cmul(s0, Ch[a]));
-    P1 = cadd(P1, cmul(s1, Ch[a]));
-  }
-  Zout[size_t(fk) * nc + c] = make_double2((P0.x - P1.y) * scale, (P0.y + P1.x) * scale);
-  if (fm != fk) Zout[size_t(fm) * nc + c] = make_double2((P0.x + P1.y) * scale, (P1.x - P0.y) * scale);
-}
-
-// Transposed product: B^_a(k) = sum_m conj(S[k][a][m]) g^_m(k); lanes take
-// channel pairs, the 8 sums are reduced over the block in a fixed order.
-__global__ __launch_bounds__(128) void k_spec_adj(int n, int NF, int nm, const double2 *__restrict__ S,
-                                                  const double2 *__restrict__ Zg, double2 *__restrict__ ZA,
-                                                  double scale) {
-  __shared__ double red[2][16];
-  const int kk = blockIdx.x % NF, cfg = blockIdx.x / NF;
-  int fk, fm;
-  if (!freq_pair(kk, n, fk, fm)) return;   // uniform over the block
-  const int c = threadIdx.x, nc = nm / 2;
-  const size_t M = size_t(n) * n * n;
-  Zg += size_t(cfg) * M * nc;
-  ZA += size_t(cfg) * M * 4;
-  double acc[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.0;
-  if (c < nc) {
-    const double2 z = Zg[size_t(fk) * nc + c], zm = Zg[size_t(fm) * nc + c];
-    const double2 g0 = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
-    const double2 g1 = make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x));
-    const double2 *Sk = S + size_t(kk) * 8 * nm + 2 * c;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const double2 v = cadd(cmulc(Sk[a * nm], g0), cmulc(Sk[a * nm + 1], g1));
-      acc[2 * a] = v.x;
-      acc[2 * a + 1] = v.y;
+  const int tid = threadIdx.x;
+  const double2 *Sk = S + size_t(ko) * 8 * NM;
+  for (int i = tid; i < 8 * NM; i += 256) Ss[i] = Sk[i];
+  if (PSI && tid < 64) {   // C^_a at each orbit frequency, from Z(f) and Z(-f)
+    const int r = tid >> 3, a = tid & 7;
+    if ((r & ~pm) == 0) {
+      const double2 z = ZC[(size_t(cfg) * M + fidx(r)) * 4 + (a >> 1)];
+      const double2 zm = ZC[(size_t(cfg) * M + fidx(r ^ pm)) * 4 + (a >> 1)];
+      Cs[r][a] = (a & 1) ? make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x))
+                         : make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
     }
   }
-#pragma unroll
-  for (int i = 0; i < 16; ++i)
-    for (int off = 32; off > 0; off >>= 1) acc[i] += __shfl_xor(acc[i], off, 64);
-  const int w = c >> 6;
-  if ((c & 63) == 0)
-#pragma unroll
-    for (int i = 0; i < 16; ++i) red[w][i] = acc[i];
+  if (ADJ) {
+    for (int i = tid; i < 8 * NC; i += 256) {
+      const int r = i / NC, c = i % NC;
+      if (r & ~pm) continue;
+      const double2 z = Zg[(size_t(cfg) * M + fidx(r)) * NC + c];
+      const double2 zm = Zg[(size_t(cfg) * M + fidx(r ^ pm)) * NC + c];
+      Gs[r * NM + 2 * c] = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
+      Gs[r * NM + 2 * c + 1] = make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x));
+    }
+  }
   __syncthreads();
-  if (c < 4) {
-    const int j = c;
-    const double2 A0 = make_double2(red[0][4 * j] + red[1][4 * j], red[0][4 * j + 1] + red[1][4 * j + 1]);
-    const double2 A1 = make_double2(red[0][4 * j + 2] + red[1][4 * j + 2], red[0][4 * j + 3] + red[1][4 * j + 3]);
-    ZA[size_t(fk) * 4 + j] = make_double2((A0.x - A1.y) * scale, (A0.y + A1.x) * scale);
-    if (fm != fk) ZA[size_t(fm) * 4 + j] = make_double2((A0.x + A1.y) * scale, (A1.x - A0.y) * scale);
+  if (PSI) {
+    for (int i = tid; i < 8 * NC; i += 256) {
+      const int r = i / NC, c = i % NC;
+      if (r & ~pm) continue;
+      const int m0 = refl(2 * c, r), m1 = refl(2 * c + 1, r);
+      double2 P0 = make_double2(0.0, 0.0), P1 = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const double sg = (__popc(a & r) & 1) ? -1.0 : 1.0;
+        const double2 ch = make_double2(sg * Cs[r][a].x, sg * Cs[r][a].y);
+        P0 = cadd(P0, cmul(Ss[a * NM + m0], ch));
+        P1 = cadd(P1, cmul(Ss[a * NM + m1], ch));
+      }
+      Zpsi[(size_t(cfg) * M + fidx(r)) * NC + c] = make_double2((P0.x - P1.y) * scale, (P0.y + P1.x) * scale);
+    }
+  }
+  if (ADJ) {
+    const int o = tid & 63, q = tid >> 6;
+    const int r = o >> 3, a = o & 7;
+    double2 acc = make_double2(0.0, 0.0);
+    if ((r & ~pm) == 0) {
+      constexpr int MQ = NM / 4;
+      for (int m = q * MQ; m < (q + 1) * MQ; ++m) acc = cadd(acc, cmulc(Ss[a * NM + refl(m, r)], Gs[r * NM + m]));
+      if (__popc(a & r) & 1) acc = make_double2(-acc.x, -acc.y);
+    }
+    red[q][o] = acc;
+    __syncthreads();
+    if (tid < 32) {
+      const int rr = tid >> 2, j = tid & 3;
+      if ((rr & ~pm) == 0) {
+        double2 A0 = red[0][rr * 8 + 2 * j], A1 = red[0][rr * 8 + 2 * j + 1];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+          A0 = cadd(A0, red[k][rr * 8 + 2 * j]);
+          A1 = cadd(A1, red[k][rr * 8 + 2 * j + 1]);
+        }
+        ZA[(size_t(cfg) * M + fidx(rr)) * 4 + j] = make_double2((A0.x - A1.y) * scale, (A0.y + A1.x) * scale);
+      }
+    }
   }
 }
 
-// Table spectrum S[kk][a][m] over the half set of frequencies: 8 consecutive
-// frequencies per block, one thread per node m, the phases
-// exp(-2 pi i k.D / n) = tw[(k.D) mod n] of the block's frequencies in LDS.
+// Table spectrum S[ko][a][m] at the octant frequencies ko = k_x + H (k_y +
+// H k_z), H = n/2 + 1: 8 frequencies per block, one thread per node m, the
+// phases exp(-2 pi i k.D / n) = tw[(k.D) mod n] of the block's frequencies
+// in LDS.
 template <int NSR>
-__global__ __launch_bounds__(256) void k_spec_build(int n, int nm, const double *__restrict__ T,
+__global__ __launch_bounds__(256) void k_spec_build(int n, int NO, int nm, const double *__restrict__ T,
                                                     const double2 *__restrict__ twf, double2 *__restrict__ S) {
   constexpr int SD = 2 * NSR + 1, ND = SD * SD * SD, FB = 8;
   __shared__ double2 ph[FB][ND];
-  const int kk0 = blockIdx.x * FB;
+  const int H = n / 2 + 1;
+  const int ko0 = blockIdx.x * FB;
   for (int i = threadIdx.x; i < FB * ND; i += blockDim.x) {
     const int f = i / ND, iD = i % ND;
-    const int kk = kk0 + f;
-    const int kx = kk % n, ky = (kk / n) % n, kz = kk / (n * n);
+    const int ko = min(ko0 + f, NO - 1);
+    const int kx = ko % H, ky = (ko / H) % H, kz = ko / (H * H);
     const int Dx = iD % SD - NSR, Dy = (iD / SD) % SD - NSR, Dz = iD / (SD * SD) - NSR;
     int e = (kx * Dx + ky * Dy + kz * Dz) % n;
     e += e < 0 ? n : 0;
@@ -269,7 +299,8 @@ __global__ __launch_bounds__(256) void k_spec_build(int n, int nm, const double 
       }
     }
 #pragma unroll
-    for (int f = 0; f < FB; ++f) S[(size_t(kk0 + f) * 8 + a) * nm + m] = acc[f];
+    for (int f = 0; f < FB; ++f)
+      if (ko0 + f < NO) S[(size_t(ko0 + f) * 8 + a) * nm + m] = acc[f];
   }
 }
 
@@ -319,7 +350,7 @@ __global__ __launch_bounds__(256) void k_adj_finish(int n, int nb, const double 
 
 bool fft_size_ok(int n) { return n >= 8 && n <= 128 && (n & (n - 1)) == 0; }
 
-size_t spec_freqs(int n) { return size_t(n) * n * (n / 2 + 1); }
+size_t spec_freqs(int n) { return size_t(n / 2 + 1) * (n / 2 + 1) * (n / 2 + 1); }
 
 namespace {
 
@@ -358,45 +389,53 @@ void fft3_forward(hipStream_t s, int nb, int n, int nch, const double2 *src, dou
 
 void launch_spec_build(hipStream_t s, int n, int nsr, int p, const double *T, const double2 *twf, double2 *S) {
   const int nm = (p + 1) * (p + 1) * (p + 1);
-  const dim3 grid(unsigned(spec_freqs(n) / 8));
+  const int NO = int(spec_freqs(n));
+  const dim3 grid(unsigned((NO + 7) / 8));
   switch (nsr) {
-    case 1: hipLaunchKernelGGL(k_spec_build<1>, grid, dim3(256), 0, s, n, nm, T, twf, S); break;
-    case 2: hipLaunchKernelGGL(k_spec_build<2>, grid, dim3(256), 0, s, n, nm, T, twf, S); break;
-    default: hipLaunchKernelGGL(k_spec_build<3>, grid, dim3(256), 0, s, n, nm, T, twf, S); break;
+    case 1: hipLaunchKernelGGL(k_spec_build<1>, grid, dim3(256), 0, s, n, NO, nm, T, twf, S); break;
+    case 2: hipLaunchKernelGGL(k_spec_build<2>, grid, dim3(256), 0, s, n, NO, nm, T, twf, S); break;
+    default: hipLaunchKernelGGL(k_spec_build<3>, grid, dim3(256), 0, s, n, NO, nm, T, twf, S); break;
   }
 }
 
-template <class WT>
-int launch_psi_fft(hipStream_t s, int nb, int n, int p, const double *C, const double2 *S, const double2 *tw,
-                   const double *phi, double2 *zc, double2 *z, WT *Wel) {
-  if (p != 5 || !fft_size_ok(n)) return -1;
-  const int nm = (p + 1) * (p + 1) * (p + 1), nc = nm / 2;
-  const int NF = int(spec_freqs(n));
-  fft3_forward(s, nb, n, 4, reinterpret_cast<const double2 *>(C), zc, tw);
+int launch_near_fft(hipStream_t s, int nb, int n, int p, const double *C, const double *gE, const double2 *S,
+                    const double2 *tw, double2 *zc, double2 *zpsi, double2 *zg, double2 *za) {
+  if (p != 5 || !fft_size_ok(n) || (!C && !gE)) return -1;
+  const int nc = (p + 1) * (p + 1) * (p + 1) / 2;
+  const int NO = int(spec_freqs(n));
   const double scale = 1.0 / (double(n) * n * n);
-  hipLaunchKernelGGL(k_spec_psi, dim3(unsigned(size_t(nb) * NF)), dim3(128), 0, s, n, NF, nm, S, zc, z, scale);
-  fft_pass<true, 0, double>(s, nb, n, nc, 0, z, z, tw, nullptr, nullptr, p);
-  fft_pass<true, 0, double>(s, nb, n, nc, 1, z, z, tw, nullptr, nullptr, p);
-  fft_pass<true, 1, WT>(s, nb, n, nc, 2, z, z, tw, phi, Wel, p);
+  if (C) fft3_forward(s, nb, n, 4, reinterpret_cast<const double2 *>(C), zc, tw);
+  if (gE) fft3_forward(s, nb, n, nc, reinterpret_cast<const double2 *>(gE), zg, tw);
+  const dim3 grid(unsigned(size_t(nb) * NO));
+  if (C && gE)
+    hipLaunchKernelGGL((k_spec_orbit<true, true>), grid, dim3(256), 0, s, n, NO, S, zc, zpsi, zg, za, scale);
+  else if (C)
+    hipLaunchKernelGGL((k_spec_orbit<true, false>), grid, dim3(256), 0, s, n, NO, S, zc, zpsi, zg, za, scale);
+  else
+    hipLaunchKernelGGL((k_spec_orbit<false, true>), grid, dim3(256), 0, s, n, NO, S, zc, zpsi, zg, za, scale);
+  if (gE)
+    for (int axis = 0; axis < 3; ++axis) fft_pass<true, 0, double>(s, nb, n, 4, axis, za, za, tw, nullptr, nullptr, 0);
   return 0;
 }
-template int launch_psi_fft<double>(hipStream_t, int, int, int, const double *, const double2 *, const double2 *,
-                                    const double *, double2 *, double2 *, double *);
-template int launch_psi_fft<float>(hipStream_t, int, int, int, const double *, const double2 *, const double2 *,
-                                   const double *, double2 *, double2 *, float *);
 
-int launch_adj_moments_fft(hipStream_t s, int nb, int p, int n, const double *gE, const double2 *S,
-                           const double2 *tw, const double *lam, const double *gw, double2 *z, double2 *za,
-                           double *A) {
+template <class WT>
+int launch_psi_fft_finish(hipStream_t s, int nb, int n, int p, const double2 *tw, const double *phi, double2 *zpsi,
+                          WT *Wel) {
   if (p != 5 || !fft_size_ok(n)) return -1;
-  const int nm = (p + 1) * (p + 1) * (p + 1), nc = nm / 2;
-  const int NF = int(spec_freqs(n));
-  fft3_forward(s, nb, n, nc, reinterpret_cast<const double2 *>(gE), z, tw);
-  const double scale = 1.0 / (double(n) * n * n);
-  hipLaunchKernelGGL(k_spec_adj, dim3(unsigned(size_t(nb) * NF)), dim3(128), 0, s, n, NF, nm, S, z, za, scale);
-  fft_pass<true, 0, double>(s, nb, n, 4, 0, za, za, tw, nullptr, nullptr, 0);
-  fft_pass<true, 0, double>(s, nb, n, 4, 1, za, za, tw, nullptr, nullptr, 0);
-  fft_pass<true, 0, double>(s, nb, n, 4, 2, za, za, tw, nullptr, nullptr, 0);
+  const int nc = (p + 1) * (p + 1) * (p + 1) / 2;
+  fft_pass<true, 0, double>(s, nb, n, nc, 0, zpsi, zpsi, tw, nullptr, nullptr, p);
+  fft_pass<true, 0, double>(s, nb, n, nc, 1, zpsi, zpsi, tw, nullptr, nullptr, p);
+  fft_pass<true, 1, WT>(s, nb, n, nc, 2, zpsi, zpsi, tw, phi, Wel, p);
+  return 0;
+}
+template int launch_psi_fft_finish<double>(hipStream_t, int, int, int, const double2 *, const double *, double2 *,
+                                           double *);
+template int launch_psi_fft_finish<float>(hipStream_t, int, int, int, const double2 *, const double *, double2 *,
+                                          float *);
+
+int launch_adj_fft_finish(hipStream_t s, int nb, int n, int p, const double *lam, const double *gw, const double2 *za,
+                          double *A) {
+  if (p != 5 || !fft_size_ok(n)) return -1;
   const size_t ne = size_t(nb) * n * n * n;
   hipLaunchKernelGGL(k_adj_finish<5>, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, s, n, nb, lam, gw,
                      reinterpret_cast<const double *>(za), A);

@@ -78,18 +78,25 @@ template <class T>
 int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, const double *C, const T *Tab, const double *phi, T *Wel);
 
 // near field and its transpose by 3-D FFTs of the element lattice (k_fft.hip);
-// n a power of two in [8, 128], p = 5.  S: table spectrum of spec_freqs(n)
-// frequencies x 8 x (p+1)^3 complex values; tw: exp(-2 pi i j / n), j < n.
-// Scratch: zc, za nb n^3 x 4 complex; z nb n^3 x (p+1)^3 / 2 complex.
+// n a power of two in [8, 128], p = 5.  S: table spectrum at the
+// spec_freqs(n) = (n/2 + 1)^3 octant frequencies x 8 x (p+1)^3 complex;
+// tw: exp(-2 pi i j / n), j < n.  Work arrays: zc, za nb n^3 x 4 complex;
+// zpsi, zg nb n^3 x (p+1)^3 / 2 complex.
 bool fft_size_ok(int n);
 size_t spec_freqs(int n);
 void launch_spec_build(hipStream_t s, int n, int nsr, int p, const double *T, const double2 *twf, double2 *S);
+// transforms of C (if given) and of the deposits gE (if given), the spectrum
+// products (one read of S for both), the inverse transform of the moment
+// adjoint's near part (left in za as [E][8] doubles); Psi^ is left in zpsi.
+int launch_near_fft(hipStream_t s, int nb, int n, int p, const double *C, const double *gE, const double2 *S,
+                    const double2 *tw, double2 *zc, double2 *zpsi, double2 *zg, double2 *za);
+// inverse transform of Psi^ and W = phi - Psi into Wel
 template <class WT>
-int launch_psi_fft(hipStream_t s, int nb, int n, int p, const double *C, const double2 *S, const double2 *tw,
-                   const double *phi, double2 *zc, double2 *z, WT *Wel);
-int launch_adj_moments_fft(hipStream_t s, int nb, int p, int n, const double *gE, const double2 *S,
-                           const double2 *tw, const double *lam, const double *gw, double2 *z, double2 *za,
-                           double *A);
+int launch_psi_fft_finish(hipStream_t s, int nb, int n, int p, const double2 *tw, const double *phi, double2 *zpsi,
+                          WT *Wel);
+// A = 4 pi G^T lambda - (near part in za)
+int launch_adj_fft_finish(hipStream_t s, int nb, int n, int p, const double *lam, const double *gw, const double2 *za,
+                          double *A);
 
 // mesh (k_mesh.hip).  nb configurations; per-configuration reductions
 // write nb * K block partials (K = seg_blocks(nb, per) unless a launcher

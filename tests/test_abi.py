@@ -133,6 +133,30 @@ def test_host_tables_match_oracle(n_sr, box):
     assert np.abs(T - To).max() < 1e-12 * np.abs(To).max()
 
 
+@pytest.mark.parametrize("n_sr", [1, 3])
+def test_host_tables_reflection_symmetric(n_sr):
+    """Reflecting an axis maps offset D, node m and moment a to their mirror
+    images (the moment changes sign with its odd factor), and the tables are
+    invariant: T[a][R D][R m] = (-1)^(a.R) T[a][D][m].  The FFT near field
+    stores the tables' spectrum for one octant of frequencies on this
+    property."""
+    S = 2 * n_sr + 1
+    out = np.zeros(8 * S**3 * 216)
+    assert fp.lib().fep3m_host_tables(3, n_sr, 2 * n_sr + 9,
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size) == fp.OK
+    T = out.reshape(8, S, S, S, 6, 6, 6)   # [a][Dz][Dy][Dx][mz][my][mx], a = ax + 2 ay + 4 az
+    for r in range(1, 8):
+        R = T
+        if r & 1:
+            R = R[:, :, :, ::-1, :, :, ::-1]
+        if r & 2:
+            R = R[:, :, ::-1, :, :, ::-1, :]
+        if r & 4:
+            R = R[:, ::-1, :, :, ::-1, :, :]
+        sign = np.array([(-1) ** bin(a & r).count("1") for a in range(8)]).reshape(8, 1, 1, 1, 1, 1, 1)
+        assert np.abs(sign * R - T).max() < 1e-13 * np.abs(T).max(), r
+
+
 def test_host_tables_argument_checks():
     out = np.zeros(10)
     ptr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
