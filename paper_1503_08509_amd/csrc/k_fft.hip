@@ -67,52 +67,69 @@ __device__ __forceinline__ bool freq_pair(int kk, int n, int &fk, int &fm) {
 
 }  // namespace
 
-// One axis of a batched 3-D FFT over [cfg][z][y][x][nch] complex values.
-// EPI 0: store the transformed values to dst (src == dst allowed: a block
-// reads all its values before it writes).  EPI 1 (last inverse pass of the
-// field): the values are (Psi_2c, Psi_2c+1) of element E; store
-// W_E[m] = phi(node of m) - Psi_m to Wout (float64 or float32), phi the
-// order-po mesh potential.
-template <bool INV, int EPI, class WT>
-__global__ __launch_bounds__(256) void k_fft_axis(int n, int logn, int nch, int cc, int lb, int axis,
-                                                  const double2 *src, double2 *dst, const double2 *__restrict__ tw,
-                                                  const double *__restrict__ phi, WT *__restrict__ Wout, int po) {
-  extern __shared__ double2 fsm[];
-  const int U = lb * cc;
-  double2 *buf = fsm;                 // [j][u], u = l cc + c
-  double2 *tws = fsm + size_t(n) * U; // n / 2 twiddles
-  const int nchunk = nch / cc, ng = n / lb;
+// Block shape of an FFT pass: cc channels (a divisor of nch) x lb lines of
+// length n, at most kFftCap complex values.
+constexpr int fft_cc(int n, int nch) {
+  int cc = nch;
+  while (n * cc > kFftCap || nch % cc != 0) --cc;
+  return cc;
+}
+constexpr int fft_lb(int n, int nch) {
+  const int cc = fft_cc(n, nch);
+  int lb = 1;
+  while (2 * lb <= n && n * 2 * lb * cc <= kFftCap) lb *= 2;
+  return lb;
+}
+
+// One axis of a batched 3-D FFT over [cfg][z][y][x][NCH] complex values,
+// n = 2^LOGN.  EPI 0: store the transformed values to dst (src == dst
+// allowed: a block reads all its values before it writes).  EPI 1 (last
+// inverse pass of the field): the values are (Psi_2c, Psi_2c+1) of element
+// E; store W_E[m] = phi(node of m) - Psi_m to Wout (float64 or float32),
+// phi the order-po mesh potential.
+template <int LOGN, int NCH, bool INV, int EPI, class WT>
+__global__ __launch_bounds__(256) void k_fft_axis(int axis, const double2 *src, double2 *dst,
+                                                  const double2 *__restrict__ tw, const double *__restrict__ phi,
+                                                  WT *__restrict__ Wout, int po) {
+  constexpr int N = 1 << LOGN, CC = fft_cc(N, NCH), LB = fft_lb(N, NCH);
+  constexpr int U = LB * CC, TOT = N * U;
+  constexpr int NCHUNK = NCH / CC, NG = N / LB;
+  __shared__ double2 buf[TOT];   // [j][u], u = l CC + c
+  __shared__ double2 tws[N / 2];
   int b = blockIdx.x;
-  const int chunk = b % nchunk;
-  b /= nchunk;
-  const int g = b % ng;
-  b /= ng;
-  const int outer = b % n;
-  const int cfg = b / n;
-  const size_t nc = size_t(nch);
+  const int chunk = b % NCHUNK;
+  b /= NCHUNK;
+  const int g = b % NG;
+  b /= NG;
+  const int outer = b % N;
+  const int cfg = b / N;
   size_t sj, sl, so;
-  if (axis == 0) { sj = nc; sl = size_t(n) * nc; so = size_t(n) * n * nc; }
-  else if (axis == 1) { sj = size_t(n) * nc; sl = nc; so = size_t(n) * n * nc; }
-  else { sj = size_t(n) * n * nc; sl = nc; so = size_t(n) * nc; }
-  const size_t base = size_t(cfg) * n * n * n * nc + size_t(outer) * so + size_t(g) * lb * sl + size_t(chunk) * cc;
-  const int tid = threadIdx.x, tot = n * U;
-  for (int t = tid; t < n / 2; t += 256) tws[t] = tw[t];
-  // load in bit-reversed order of j; the thread order follows memory
-  for (int i = tid; i < tot; i += 256) {
-    const int c = i % cc, r = i / cc;
-    int j, l;
-    if (axis == 0) { j = r % n; l = r / n; } else { l = r % lb; j = r / lb; }
-    const int jr = int(__brev(unsigned(j)) >> (32 - logn));
-    buf[jr * U + l * cc + c] = src[base + j * sj + l * sl + c];
+  if (axis == 0) { sj = NCH; sl = size_t(N) * NCH; so = size_t(N) * N * NCH; }
+  else if (axis == 1) { sj = size_t(N) * NCH; sl = NCH; so = size_t(N) * N * NCH; }
+  else { sj = size_t(N) * N * NCH; sl = NCH; so = size_t(N) * NCH; }
+  const size_t base = size_t(cfg) * N * N * N * NCH + size_t(outer) * so + size_t(g) * LB * sl + size_t(chunk) * CC;
+  const int tid = threadIdx.x;
+  // position (j, l, c) of value i: the thread order follows memory
+  auto coords = [&](int i, int &j, int &l, int &c) {
+    c = i % CC;
+    const int r = i / CC;
+    if (axis == 0) { j = r % N; l = r / N; } else { l = r % LB; j = r / LB; }
+  };
+  if (tid < N / 2) tws[tid] = tw[tid];
+  for (int i = tid; i < TOT; i += 256) {   // stored in bit-reversed order of j
+    int j, l, c;
+    coords(i, j, l, c);
+    buf[int(__brev(unsigned(j)) >> (32 - LOGN)) * U + l * CC + c] = src[base + j * sj + l * sl + c];
   }
   __syncthreads();
-  for (int s = 0; s < logn; ++s) {
+#pragma unroll
+  for (int s = 0; s < LOGN; ++s) {
     const int h = 1 << s;
-    for (int t = tid; t < (n / 2) * U; t += 256) {
+    for (int t = tid; t < (N / 2) * U; t += 256) {
       const int u = t % U, bf = t / U;
       const int pos = bf & (h - 1);
       const int j0 = ((bf >> s) << (s + 1)) + pos, j1 = j0 + h;
-      double2 w = tws[pos << (logn - 1 - s)];
+      double2 w = tws[pos << (LOGN - 1 - s)];
       if (INV) w.y = -w.y;
       const double2 x0 = buf[j0 * U + u], x1 = cmul(buf[j1 * U + u], w);
       buf[j0 * U + u] = cadd(x0, x1);
@@ -121,28 +138,26 @@ __global__ __launch_bounds__(256) void k_fft_axis(int n, int logn, int nch, int 
     __syncthreads();
   }
   if (EPI == 0) {
-    for (int i = tid; i < tot; i += 256) {
-      const int c = i % cc, r = i / cc;
-      int j, l;
-      if (axis == 0) { j = r % n; l = r / n; } else { l = r % lb; j = r / lb; }
-      dst[base + j * sj + l * sl + c] = buf[j * U + l * cc + c];
+    for (int i = tid; i < TOT; i += 256) {
+      int j, l, c;
+      coords(i, j, l, c);
+      dst[base + j * sj + l * sl + c] = buf[j * U + l * CC + c];
     }
   } else {
-    const int Q1 = po + 1, NM = Q1 * Q1 * Q1, P = po * n;
-    const size_t M = size_t(n) * n * n;
+    const int Q1 = po + 1, NM = Q1 * Q1 * Q1, P = po * N;
+    const size_t M = size_t(N) * N * N;
     phi += size_t(cfg) * P * P * P;
-    for (int i = tid; i < tot; i += 256) {
-      const int c = i % cc, r = i / cc;
-      int j, l;
-      if (axis == 0) { j = r % n; l = r / n; } else { l = r % lb; j = r / lb; }
+    for (int i = tid; i < TOT; i += 256) {
+      int j, l, c;
+      coords(i, j, l, c);
       int ex, ey, ez;
-      const int lc = g * lb + l;
+      const int lc = g * LB + l;
       if (axis == 0) { ex = j; ey = lc; ez = outer; }
       else if (axis == 1) { ey = j; ex = lc; ez = outer; }
       else { ez = j; ex = lc; ey = outer; }
-      const double2 v = buf[j * U + l * cc + c];
-      const size_t E = size_t(cfg) * M + (size_t(ez) * n + ey) * n + ex;
-      const int ch = chunk * cc + c;
+      const double2 v = buf[j * U + l * CC + c];
+      const size_t E = size_t(cfg) * M + (size_t(ez) * N + ey) * N + ex;
+      const int ch = chunk * CC + c;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int m = 2 * ch + q;
@@ -174,7 +189,7 @@ __global__ __launch_bounds__(256) void k_spec_orbit(int n, int NO, const double2
                                                     const double2 *__restrict__ Zg, double2 *__restrict__ ZA,
                                                     double scale) {
   constexpr int Q1 = 6, NM = Q1 * Q1 * Q1, NC = NM / 2;
-  __shared__ double2 Ss[8 * NM];
+  __shared__ double2 Ss[8 * NM + 1];   // one spare slot
   __shared__ double2 Cs[8][8];
   __shared__ double2 Gs[ADJ ? 8 * NM : 1];
   __shared__ double2 red[ADJ ? 4 : 1][64];
@@ -199,7 +214,15 @@ __global__ __launch_bounds__(256) void k_spec_orbit(int n, int NO, const double2
   const size_t M = size_t(n) * n * n;
   const int tid = threadIdx.x;
   const double2 *Sk = S + size_t(ko) * 8 * NM;
-  for (int i = tid; i < 8 * NM; i += 256) Ss[i] = Sk[i];
+  {   // all loads of the row in flight before the LDS stores
+    constexpr int KS = (8 * NM + 255) / 256;
+    double2 v[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) v[k] = Sk[min(tid + 256 * k, 8 * NM - 1)];   // clamped: no branch per load
+    asm volatile("" ::: "memory");   // compiler fence: all loads issue before the stores
+#pragma unroll
+    for (int k = 0; k < KS; ++k) Ss[min(tid + 256 * k, 8 * NM)] = v[k];   // lanes past the end: spare slot
+  }
   if (PSI && tid < 64) {   // C^_a at each orbit frequency, from Z(f) and Z(-f)
     const int r = tid >> 3, a = tid & 7;
     if ((r & ~pm) == 0) {
@@ -210,13 +233,20 @@ __global__ __launch_bounds__(256) void k_spec_orbit(int n, int NO, const double2
     }
   }
   if (ADJ) {
-    for (int i = tid; i < 8 * NC; i += 256) {
-      const int r = i / NC, c = i % NC;
-      if (r & ~pm) continue;
-      const double2 z = Zg[(size_t(cfg) * M + fidx(r)) * NC + c];
-      const double2 zm = Zg[(size_t(cfg) * M + fidx(r ^ pm)) * NC + c];
-      Gs[r * NM + 2 * c] = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
-      Gs[r * NM + 2 * c + 1] = make_double2(0.5 * (z.y + zm.y), -0.5 * (z.x - zm.x));
+    constexpr int KG = (8 * NC + 255) / 256;
+    double2 z[KG], zm[KG];
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {   // unconditional loads (frequencies outside the orbit read k itself)
+      const int i = min(tid + 256 * k, 8 * NC - 1), r = (i / NC) & pm, c = i % NC;
+      z[k] = Zg[(size_t(cfg) * M + fidx(r)) * NC + c];
+      zm[k] = Zg[(size_t(cfg) * M + fidx(r ^ pm)) * NC + c];
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {   // slots outside the orbit are written but never read
+      const int i = min(tid + 256 * k, 8 * NC - 1), r = i / NC, c = i % NC;
+      Gs[r * NM + 2 * c] = make_double2(0.5 * (z[k].x + zm[k].x), 0.5 * (z[k].y - zm[k].y));
+      Gs[r * NM + 2 * c + 1] = make_double2(0.5 * (z[k].y + zm[k].y), -0.5 * (z[k].x - zm[k].x));
     }
   }
   __syncthreads();
@@ -354,28 +384,34 @@ size_t spec_freqs(int n) { return size_t(n / 2 + 1) * (n / 2 + 1) * (n / 2 + 1);
 
 namespace {
 
-int ilog2(int n) {
-  int l = 0;
-  while ((1 << l) < n) ++l;
-  return l;
+template <int LOGN, int NCH, bool INV, int EPI, class WT>
+void fft_launch(hipStream_t s, int nb, int axis, const double2 *src, double2 *dst, const double2 *tw,
+                const double *phi, WT *W, int po) {
+  constexpr int N = 1 << LOGN, CC = fft_cc(N, NCH), LB = fft_lb(N, NCH);
+  const dim3 grid(unsigned(size_t(nb) * N * (N / LB) * (NCH / CC)));
+  hipLaunchKernelGGL((k_fft_axis<LOGN, NCH, INV, EPI, WT>), grid, dim3(256), 0, s, axis, src, dst, tw, phi, W, po);
 }
 
-void fft_shape(int n, int nch, int &cc, int &lb) {
-  cc = nch;
-  while (n * cc > kFftCap || nch % cc != 0) --cc;
-  lb = 1;
-  while (2 * lb <= n && n * 2 * lb * cc <= kFftCap) lb *= 2;
+template <int NCH, bool INV, int EPI, class WT>
+void fft_pass_n(hipStream_t s, int nb, int n, int axis, const double2 *src, double2 *dst, const double2 *tw,
+                const double *phi, WT *W, int po) {
+  switch (n) {
+    case 8: fft_launch<3, NCH, INV, EPI, WT>(s, nb, axis, src, dst, tw, phi, W, po); break;
+    case 16: fft_launch<4, NCH, INV, EPI, WT>(s, nb, axis, src, dst, tw, phi, W, po); break;
+    case 32: fft_launch<5, NCH, INV, EPI, WT>(s, nb, axis, src, dst, tw, phi, W, po); break;
+    case 64: fft_launch<6, NCH, INV, EPI, WT>(s, nb, axis, src, dst, tw, phi, W, po); break;
+    default: fft_launch<7, NCH, INV, EPI, WT>(s, nb, axis, src, dst, tw, phi, W, po); break;
+  }
 }
 
+// nch: 4 (moments) or 108 (node fields); EPI 1 only for node fields
 template <bool INV, int EPI, class WT>
 void fft_pass(hipStream_t s, int nb, int n, int nch, int axis, const double2 *src, double2 *dst,
               const double2 *tw, const double *phi, WT *W, int po) {
-  int cc, lb;
-  fft_shape(n, nch, cc, lb);
-  const size_t lds = (size_t(n) * lb * cc + n / 2) * sizeof(double2);
-  const dim3 grid(unsigned(size_t(nb) * n * (n / lb) * (nch / cc)));
-  hipLaunchKernelGGL((k_fft_axis<INV, EPI, WT>), grid, dim3(256), lds, s, n, ilog2(n), nch, cc, lb, axis, src, dst,
-                     tw, phi, W, po);
+  if (EPI == 0 && nch == 4)
+    fft_pass_n<4, INV, 0, WT>(s, nb, n, axis, src, dst, tw, phi, W, po);
+  else
+    fft_pass_n<108, INV, EPI, WT>(s, nb, n, axis, src, dst, tw, phi, W, po);
 }
 
 // forward 3-D transform: src (real pairs) -> dst, x then y then z
