@@ -788,28 +788,35 @@ void fep3m_ctx::solve(const double *rhs, double *sol, int which) {
   }
   MGLevel &L0 = lv[0];
   const size_t per = L0.ndof, nd = per * nbs;
-  launch_fill_f64(stream, nd, 0.0, sol);
-  launch_copy_f64(stream, nd, rhs, rr);
   launch_sum_partials(stream, launch_dot(stream, nbs, per, rhs, rhs, partial), partial, pcs.bn2, nbs);
+  // The residual starts as the right side itself (read in place, not
+  // copied) and lives in rr from the first update on.  x = 0 is implicit:
+  // each iteration's x += alpha p is deferred to the pass that forms the
+  // next direction (p is read there anyway), the last one runs after the
+  // loop.
+  const double *rcur = rhs;
+  bool xinit = false;
   // z = M^-1 r; rzn = z . r (and zq = z . q when q is given)
   auto precondition = [&](const double *q) {
     if (!mixed) {   // z . r from the V-cycle's last smoothing step
-      launch_sum_partials(stream, vcycle<double>(0, rr, partial), partial, pcs.rzn, nbs);
+      launch_sum_partials(stream, vcycle<double>(0, rcur, partial), partial, pcs.rzn, nbs);
     } else {
-      launch_to_f32(stream, nd, rr, L0.vf.f);
+      launch_to_f32(stream, nd, rcur, L0.vf.f);
       vcycle<float>(0, L0.vf.f);
-      const int K = launch_dot2_f32(stream, nbs, per, L0.vf.x, rr, q, dot_scr);
+      const int K = launch_dot2_f32(stream, nbs, per, L0.vf.x, rcur, q, dot_scr);
       launch_sum_partials(stream, K, dot_scr, pcs.rzn, nbs);
       launch_sum_partials(stream, K, dot_scr + size_t(nbs) * K, pcs.zq, nbs);
     }
   };
-  auto set_p = [&] {   // p = z + beta p
-    if (!mixed) launch_xpay(stream, nbs, per, pcs.beta, L0.vd.x, pv);
-    else launch_xpay_f32(stream, nbs, per, pcs.beta, L0.vf.x, pv);
+  auto set_p = [&] {   // x += alpha p (deferred); p = z + beta p
+    if (!mixed) launch_xp_update<double>(stream, nbs, per, pcs.alpha, pcs.beta, L0.vd.x, pv, sol, xinit);
+    else launch_xp_update<float>(stream, nbs, per, pcs.alpha, pcs.beta, L0.vf.x, pv, sol, xinit);
+    xinit = true;
   };
   precondition(nullptr);
   launch_pcg_scalars(stream, nbs, kPcgStart, 0.0, pcs);   // act = (b != 0), beta = 0, rz = z . r
-  set_p();
+  if (!mixed) launch_p_init<double>(stream, nbs, per, L0.vd.x, pv);
+  else launch_p_init<float>(stream, nbs, per, L0.vf.x, pv);
   // Eagerly, the host reads the residuals after every iteration and stops
   // once all configurations have converged.  Under graph capture the loop
   // runs the iteration count of the eager call it was captured after; the
@@ -822,8 +829,9 @@ void fep3m_ctx::solve(const double *rhs, double *sol, int which) {
     const int Ka = apply0<double>(pv, nullptr, qv, nullptr, nullptr, 0.0, 0.0, kApplyDot, partial);
     launch_sum_partials(stream, Ka, partial, pcs.pq, nbs);
     launch_pcg_scalars(stream, nbs, kPcgAlpha, 0.0, pcs);
-    launch_sum_partials(stream, launch_cg_update(stream, nbs, per, pcs.alpha, pv, qv, sol, rr, partial), partial,
+    launch_sum_partials(stream, launch_r_update(stream, nbs, per, pcs.alpha, qv, rcur, rr, partial), partial,
                         pcs.rr, nbs);
+    rcur = rr;
     launch_pcg_scalars(stream, nbs, kPcgResid, opt.mg_rtol, pcs);
     if (capturing) {
       if (it >= fixed) break;
@@ -839,6 +847,10 @@ void fep3m_ctx::solve(const double *rhs, double *sol, int which) {
     launch_pcg_scalars(stream, nbs, mixed ? kPcgBetaPR : kPcgBeta, 0.0, pcs);
     set_p();
   }
+  // the loop left through its break (converged, or the captured count):
+  // the last iteration's x update is still pending (at the iteration cap
+  // set_p has applied it)
+  if (it <= opt.mg_max_iter) launch_x_final(stream, nbs, per, pcs.alpha, pv, sol, xinit);
   store_rel(which);
   check_launch("mesh solve");
   if (capturing) return;

@@ -752,58 +752,81 @@ __global__ __launch_bounds__(256) void k_dot(size_t per, int K, const double *__
 }
 
 // x += alpha_b p; r -= alpha_b q; partial of r.r
-__global__ __launch_bounds__(256) void k_cg_update(size_t per, int K, const double *__restrict__ alphas,
-                                                   const double *__restrict__ p, const double *__restrict__ q,
-                                                   double *__restrict__ x, double *__restrict__ r,
-                                                   double *__restrict__ partial) {
+// r_out = r_in - alpha_b q and block partials of r_out . r_out (r_in may be
+// r_out, or the right side in the first iteration).
+__global__ __launch_bounds__(256) void k_r_update(size_t per, int K, const double *__restrict__ alphas,
+                                                  const double *__restrict__ q, const double *r_in,
+                                                  double *r_out, double *__restrict__ partial) {
   __shared__ double red[256];
   const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
   const size_t o = size_t(cfg) * per;
-  p += o; q += o; x += o; r += o;
+  q += o; r_in += o; r_out += o;
   const double alpha = alphas[cfg];
   double acc = 0.0;
   // four elements per thread and pass: every load first, then the stores
   constexpr int U = 4;
   const size_t stride = size_t(K) * blockDim.x;
   for (size_t i0 = size_t(kb) * blockDim.x + threadIdx.x; i0 < per; i0 += U * stride) {
-    double pv[U], qv[U], xv[U], rv[U];
+    double qv[U], rv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const size_t i = i0 + u * stride;
       const bool ok = i < per;
-      pv[u] = ok ? p[i] : 0.0;
       qv[u] = ok ? q[i] : 0.0;
-      xv[u] = ok ? x[i] : 0.0;
-      rv[u] = ok ? r[i] : 0.0;
+      rv[u] = ok ? r_in[i] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      xv[u] += alpha * pv[u];
       rv[u] -= alpha * qv[u];
       acc += rv[u] * rv[u];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const size_t i = i0 + u * stride;
-      if (i < per) {
-        x[i] = xv[u];
-        r[i] = rv[u];
-      }
+      if (i < per) r_out[i] = rv[u];
     }
   }
   double t = block_sum(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// p = z + beta_b p (p = z when beta_b == 0: p is not read)
-__global__ __launch_bounds__(256) void k_xpay(size_t per, int K, const double *__restrict__ betas,
-                                              const double *__restrict__ z, double *__restrict__ p) {
+// The iterate's update of the previous iteration, deferred to the pass that
+// forms the next direction: x = x + alpha_b p (x = alpha_b p when xinit is
+// 0: x is not read), then p = z + beta_b p.  z float64 or float32.
+template <class ZT>
+__global__ __launch_bounds__(256) void k_xp_update(size_t per, int K, const double *__restrict__ alphas,
+                                                   const double *__restrict__ betas, const ZT *__restrict__ z,
+                                                   double *__restrict__ p, double *__restrict__ x, int xinit) {
   const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
-  z += size_t(cfg) * per;
-  p += size_t(cfg) * per;
-  const double beta = betas[cfg];
+  const size_t o = size_t(cfg) * per;
+  z += o; p += o; x += o;
+  const double alpha = alphas[cfg], beta = betas[cfg];
   const size_t i = size_t(kb) * blockDim.x + threadIdx.x;   // one element per thread
-  if (i < per) p[i] = beta == 0.0 ? z[i] : z[i] + beta * p[i];
+  if (i < per) {
+    const double pv = p[i], zv = double(z[i]);
+    const double xv = xinit ? x[i] : 0.0;
+    x[i] = xv + alpha * pv;
+    p[i] = zv + beta * pv;
+  }
+}
+
+// p = z (first direction; p is not read).  z float64 or float32.
+template <class ZT>
+__global__ __launch_bounds__(256) void k_p_init(size_t per, int K, const ZT *__restrict__ z, double *__restrict__ p) {
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const size_t i = size_t(kb) * blockDim.x + threadIdx.x;
+  if (i < per) p[size_t(cfg) * per + i] = double(z[size_t(cfg) * per + i]);
+}
+
+// x = x + alpha_b p (x = alpha_b p when xinit is 0): the last iteration's
+// update after the loop has stopped.
+__global__ __launch_bounds__(256) void k_x_final(size_t per, int K, const double *__restrict__ alphas,
+                                                 const double *__restrict__ p, double *__restrict__ x, int xinit) {
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const size_t o = size_t(cfg) * per;
+  const double alpha = alphas[cfg];
+  const size_t i = size_t(kb) * blockDim.x + threadIdx.x;
+  if (i < per) x[o + i] = (xinit ? x[o + i] : 0.0) + alpha * p[o + i];
 }
 
 __global__ __launch_bounds__(256) void k_scale(size_t n, double s, const double *__restrict__ a, double *__restrict__ b) {
@@ -871,17 +894,6 @@ __global__ __launch_bounds__(256) void k_dot2_f32(size_t per, int K, const float
     partial[blockIdx.x] = ta;
     partial[gridDim.x + blockIdx.x] = tb;
   }
-}
-
-// p = z + beta_b p (p = z when beta_b == 0: p is not read), z float32.
-__global__ __launch_bounds__(256) void k_xpay_f32(size_t per, int K, const double *__restrict__ betas,
-                                                  const float *__restrict__ z, double *__restrict__ p) {
-  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
-  z += size_t(cfg) * per;
-  p += size_t(cfg) * per;
-  const double beta = betas[cfg];
-  const size_t i = size_t(kb) * blockDim.x + threadIdx.x;   // one element per thread
-  if (i < per) p[i] = beta == 0.0 ? double(z[i]) : double(z[i]) + beta * p[i];
 }
 
 // PCG scalars, one thread per configuration, on arrays of nb values:
@@ -1118,10 +1130,6 @@ int launch_dot2_f32(hipStream_t s, int nb, size_t per, const float *z, const dou
   hipLaunchKernelGGL(k_dot2_f32, dim3(nb * K), dim3(256), 0, s, per, K, z, r, q, partial);
   return K;
 }
-void launch_xpay_f32(hipStream_t s, int nb, size_t per, const double *betas, const float *z, double *p) {
-  const int K = int((per + 255) / 256);
-  hipLaunchKernelGGL(k_xpay_f32, dim3(nb * K), dim3(256), 0, s, per, K, betas, z, p);
-}
 void launch_pcg_scalars(hipStream_t s, int nb, int step, double rtol, const PcgScalars &sc) {
   hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(64), 0, s, nb, step, rtol, sc);
 }
@@ -1130,15 +1138,33 @@ int launch_dot(hipStream_t s, int nb, size_t per, const double *a, const double 
   hipLaunchKernelGGL(k_dot, dim3(nb * K), dim3(256), 0, s, per, K, a, b, partial);
   return K;
 }
-int launch_cg_update(hipStream_t s, int nb, size_t per, const double *alphas, const double *p, const double *q,
-                     double *x, double *r, double *partial) {
+int launch_r_update(hipStream_t s, int nb, size_t per, const double *alphas, const double *q, const double *r_in,
+                    double *r_out, double *partial) {
   const int K = seg_blocks(nb, per);
-  hipLaunchKernelGGL(k_cg_update, dim3(nb * K), dim3(256), 0, s, per, K, alphas, p, q, x, r, partial);
+  hipLaunchKernelGGL(k_r_update, dim3(nb * K), dim3(256), 0, s, per, K, alphas, q, r_in, r_out, partial);
   return K;
 }
-void launch_xpay(hipStream_t s, int nb, size_t per, const double *betas, const double *z, double *p) {
+template <class ZT>
+void launch_xp_update(hipStream_t s, int nb, size_t per, const double *alphas, const double *betas, const ZT *z,
+                      double *p, double *x, bool xinit) {
   const int K = int((per + 255) / 256);
-  hipLaunchKernelGGL(k_xpay, dim3(nb * K), dim3(256), 0, s, per, K, betas, z, p);
+  hipLaunchKernelGGL(k_xp_update<ZT>, dim3(nb * K), dim3(256), 0, s, per, K, alphas, betas, z, p, x, xinit ? 1 : 0);
+}
+template void launch_xp_update<double>(hipStream_t, int, size_t, const double *, const double *, const double *,
+                                       double *, double *, bool);
+template void launch_xp_update<float>(hipStream_t, int, size_t, const double *, const double *, const float *,
+                                      double *, double *, bool);
+template <class ZT>
+void launch_p_init(hipStream_t s, int nb, size_t per, const ZT *z, double *p) {
+  const int K = int((per + 255) / 256);
+  hipLaunchKernelGGL(k_p_init<ZT>, dim3(nb * K), dim3(256), 0, s, per, K, z, p);
+}
+template void launch_p_init<double>(hipStream_t, int, size_t, const double *, double *);
+template void launch_p_init<float>(hipStream_t, int, size_t, const float *, double *);
+void launch_x_final(hipStream_t s, int nb, size_t per, const double *alphas, const double *p, double *x,
+                    bool xinit) {
+  const int K = int((per + 255) / 256);
+  hipLaunchKernelGGL(k_x_final, dim3(nb * K), dim3(256), 0, s, per, K, alphas, p, x, xinit ? 1 : 0);
 }
 void launch_scale(hipStream_t s, size_t n, double sc, const double *a, double *b) {
   hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(256), 0, s, n, sc, a, b);

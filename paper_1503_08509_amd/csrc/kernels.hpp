@@ -136,12 +136,19 @@ void launch_to_f32(hipStream_t s, size_t n, const double *a, float *b);
 // partial[0, nb K): block sums of z.r; partial[nb K, 2 nb K): z.q (0 if q is null); returns K
 int launch_dot2_f32(hipStream_t s, int nb, size_t per, const float *z, const double *r, const double *q,
                     double *partial);
-void launch_xpay_f32(hipStream_t s, int nb, size_t per, const double *betas, const float *z, double *p);
 void launch_pcg_scalars(hipStream_t s, int nb, int step, double rtol, const PcgScalars &sc);
 int launch_dot(hipStream_t s, int nb, size_t per, const double *a, const double *b, double *partial);
-int launch_cg_update(hipStream_t s, int nb, size_t per, const double *alphas, const double *p, const double *q,
-                     double *x, double *r, double *partial);
-void launch_xpay(hipStream_t s, int nb, size_t per, const double *betas, const double *z, double *p);
+// PCG updates.  r_out = r_in - alpha q with block partials of r_out . r_out
+// (returns K); x += alpha p (x = alpha p unless xinit) fused with the next
+// direction p = z + beta p; p = z; the last x update after the loop.
+int launch_r_update(hipStream_t s, int nb, size_t per, const double *alphas, const double *q, const double *r_in,
+                    double *r_out, double *partial);
+template <class ZT>
+void launch_xp_update(hipStream_t s, int nb, size_t per, const double *alphas, const double *betas, const ZT *z,
+                      double *p, double *x, bool xinit);
+template <class ZT>
+void launch_p_init(hipStream_t s, int nb, size_t per, const ZT *z, double *p);
+void launch_x_final(hipStream_t s, int nb, size_t per, const double *alphas, const double *p, double *x, bool xinit);
 void launch_scale(hipStream_t s, size_t n, double sc, const double *a, double *b);
 void launch_hash_fill(hipStream_t s, size_t n, uint32_t seed, double *v);
 void launch_fill_f64(hipStream_t s, size_t n, double v, double *p);
