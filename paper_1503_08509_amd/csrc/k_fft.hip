@@ -459,9 +459,11 @@ int launch_psi_fft_finish(hipStream_t s, int nb, int n, int p, const double2 *tw
                           WT *Wel) {
   if (p != 5 || !fft_size_ok(n)) return -1;
   const int nc = (p + 1) * (p + 1) * (p + 1) / 2;
-  fft_pass<true, 0, double>(s, nb, n, nc, 0, zpsi, zpsi, tw, nullptr, nullptr, p);
+  // z, y, then x with the W epilogue: along x the mesh potential is read in
+  // contiguous rows (nodes p e_x + m_x) and W in runs of one element's nodes
+  fft_pass<true, 0, double>(s, nb, n, nc, 2, zpsi, zpsi, tw, nullptr, nullptr, p);
   fft_pass<true, 0, double>(s, nb, n, nc, 1, zpsi, zpsi, tw, nullptr, nullptr, p);
-  fft_pass<true, 1, WT>(s, nb, n, nc, 2, zpsi, zpsi, tw, phi, Wel, p);
+  fft_pass<true, 1, WT>(s, nb, n, nc, 0, zpsi, zpsi, tw, phi, Wel, p);
   return 0;
 }
 template int launch_psi_fft_finish<double>(hipStream_t, int, int, int, const double2 *, const double *, double2 *,
