@@ -183,16 +183,18 @@ __global__ __launch_bounds__(256) void k_fft_axis(int axis, const double2 *src, 
 //   ADJ: ZA(R k)[j] = (B^_2j + i B^_2j+1)(R k) * scale
 // Moments are indexed a = a_x + 2 a_y + 4 a_z (each 0 or 1), nodes
 // m = m_x + 6 (m_y + 6 m_z).
+constexpr int kOrbitThreads = 512;
+
 template <bool PSI, bool ADJ>
-__global__ __launch_bounds__(256) void k_spec_orbit(int n, int NO, const double2 *__restrict__ S,
+__global__ __launch_bounds__(kOrbitThreads) void k_spec_orbit(int n, int NO, const double2 *__restrict__ S,
                                                     const double2 *__restrict__ ZC, double2 *__restrict__ Zpsi,
                                                     const double2 *__restrict__ Zg, double2 *__restrict__ ZA,
                                                     double scale) {
-  constexpr int Q1 = 6, NM = Q1 * Q1 * Q1, NC = NM / 2;
+  constexpr int Q1 = 6, NM = Q1 * Q1 * Q1, NC = NM / 2, NT = kOrbitThreads, NQ = NT / 64;
+  static_assert(NM % NQ == 0 && NQ * 64 <= 8 * NM, "node split of the transposed product");
   __shared__ double2 Ss[8 * NM + 1];   // one spare slot
   __shared__ double2 Cs[8][8];
-  __shared__ double2 Gs[ADJ ? 8 * NM : 1];
-  __shared__ double2 red[ADJ ? 4 : 1][64];
+  __shared__ double2 Gs[ADJ ? 8 * NM : 1];   // reused for the partial sums
   const int H = n / 2 + 1;
   const int ko = blockIdx.x % NO, cfg = blockIdx.x / NO;
   const int kx = ko % H, ky = (ko / H) % H, kz = ko / (H * H);
@@ -215,15 +217,15 @@ __global__ __launch_bounds__(256) void k_spec_orbit(int n, int NO, const double2
   const int tid = threadIdx.x;
   const double2 *Sk = S + size_t(ko) * 8 * NM;
   {   // all loads of the row in flight before the LDS stores
-    constexpr int KS = (8 * NM + 255) / 256;
+    constexpr int KS = (8 * NM + NT - 1) / NT;
     double2 v[KS];
 #pragma unroll
-    for (int k = 0; k < KS; ++k) v[k] = Sk[min(tid + 256 * k, 8 * NM - 1)];   // clamped: no branch per load
+    for (int k = 0; k < KS; ++k) v[k] = Sk[min(tid + NT * k, 8 * NM - 1)];   // clamped: no branch per load
     asm volatile("" ::: "memory");   // compiler fence: all loads issue before the stores
 #pragma unroll
-    for (int k = 0; k < KS; ++k) Ss[min(tid + 256 * k, 8 * NM)] = v[k];   // lanes past the end: spare slot
+    for (int k = 0; k < KS; ++k) Ss[min(tid + NT * k, 8 * NM)] = v[k];   // lanes past the end: spare slot
   }
-  if (PSI && tid < 64) {   // C^_a at each orbit frequency, from Z(f) and Z(-f)
+  if constexpr (PSI) if (tid < 64) {   // C^_a at each orbit frequency, from Z(f) and Z(-f)
     const int r = tid >> 3, a = tid & 7;
     if ((r & ~pm) == 0) {
       const double2 z = ZC[(size_t(cfg) * M + fidx(r)) * 4 + (a >> 1)];
@@ -232,26 +234,26 @@ __global__ __launch_bounds__(256) void k_spec_orbit(int n, int NO, const double2
                          : make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y - zm.y));
     }
   }
-  if (ADJ) {
-    constexpr int KG = (8 * NC + 255) / 256;
+  if constexpr (ADJ) {
+    constexpr int KG = (8 * NC + NT - 1) / NT;
     double2 z[KG], zm[KG];
 #pragma unroll
     for (int k = 0; k < KG; ++k) {   // unconditional loads (frequencies outside the orbit read k itself)
-      const int i = min(tid + 256 * k, 8 * NC - 1), r = (i / NC) & pm, c = i % NC;
+      const int i = min(tid + NT * k, 8 * NC - 1), r = (i / NC) & pm, c = i % NC;
       z[k] = Zg[(size_t(cfg) * M + fidx(r)) * NC + c];
       zm[k] = Zg[(size_t(cfg) * M + fidx(r ^ pm)) * NC + c];
     }
     asm volatile("" ::: "memory");
 #pragma unroll
     for (int k = 0; k < KG; ++k) {   // slots outside the orbit are written but never read
-      const int i = min(tid + 256 * k, 8 * NC - 1), r = i / NC, c = i % NC;
+      const int i = min(tid + NT * k, 8 * NC - 1), r = i / NC, c = i % NC;
       Gs[r * NM + 2 * c] = make_double2(0.5 * (z[k].x + zm[k].x), 0.5 * (z[k].y - zm[k].y));
       Gs[r * NM + 2 * c + 1] = make_double2(0.5 * (z[k].y + zm[k].y), -0.5 * (z[k].x - zm[k].x));
     }
   }
   __syncthreads();
-  if (PSI) {
-    for (int i = tid; i < 8 * NC; i += 256) {
+  if constexpr (PSI) {
+    for (int i = tid; i < 8 * NC; i += NT) {
       const int r = i / NC, c = i % NC;
       if (r & ~pm) continue;
       const int m0 = refl(2 * c, r), m1 = refl(2 * c + 1, r);
@@ -266,25 +268,29 @@ __global__ __launch_bounds__(256) void k_spec_orbit(int n, int NO, const double2
       Zpsi[(size_t(cfg) * M + fidx(r)) * NC + c] = make_double2((P0.x - P1.y) * scale, (P0.y + P1.x) * scale);
     }
   }
-  if (ADJ) {
+  if constexpr (ADJ) {
+    // 64 outputs (orbit member r, moment a) x NQ node ranges; the partial
+    // sums then go to Gs (no longer read) and are added in a fixed order
     const int o = tid & 63, q = tid >> 6;
     const int r = o >> 3, a = o & 7;
     double2 acc = make_double2(0.0, 0.0);
     if ((r & ~pm) == 0) {
-      constexpr int MQ = NM / 4;
+      constexpr int MQ = NM / NQ;
       for (int m = q * MQ; m < (q + 1) * MQ; ++m) acc = cadd(acc, cmulc(Ss[a * NM + refl(m, r)], Gs[r * NM + m]));
       if (__popc(a & r) & 1) acc = make_double2(-acc.x, -acc.y);
     }
-    red[q][o] = acc;
+    __syncthreads();
+    double2 *red = Gs;   // [q][64]
+    red[q * 64 + o] = acc;
     __syncthreads();
     if (tid < 32) {
       const int rr = tid >> 2, j = tid & 3;
       if ((rr & ~pm) == 0) {
-        double2 A0 = red[0][rr * 8 + 2 * j], A1 = red[0][rr * 8 + 2 * j + 1];
+        double2 A0 = red[rr * 8 + 2 * j], A1 = red[rr * 8 + 2 * j + 1];
 #pragma unroll
-        for (int k = 1; k < 4; ++k) {
-          A0 = cadd(A0, red[k][rr * 8 + 2 * j]);
-          A1 = cadd(A1, red[k][rr * 8 + 2 * j + 1]);
+        for (int k = 1; k < NQ; ++k) {
+          A0 = cadd(A0, red[k * 64 + rr * 8 + 2 * j]);
+          A1 = cadd(A1, red[k * 64 + rr * 8 + 2 * j + 1]);
         }
         ZA[(size_t(cfg) * M + fidx(rr)) * 4 + j] = make_double2((A0.x - A1.y) * scale, (A0.y + A1.x) * scale);
       }
@@ -444,11 +450,11 @@ int launch_near_fft(hipStream_t s, int nb, int n, int p, const double *C, const 
   if (gE) fft3_forward(s, nb, n, nc, reinterpret_cast<const double2 *>(gE), zg, tw);
   const dim3 grid(unsigned(size_t(nb) * NO));
   if (C && gE)
-    hipLaunchKernelGGL((k_spec_orbit<true, true>), grid, dim3(256), 0, s, n, NO, S, zc, zpsi, zg, za, scale);
+    hipLaunchKernelGGL((k_spec_orbit<true, true>), grid, dim3(kOrbitThreads), 0, s, n, NO, S, zc, zpsi, zg, za, scale);
   else if (C)
-    hipLaunchKernelGGL((k_spec_orbit<true, false>), grid, dim3(256), 0, s, n, NO, S, zc, zpsi, zg, za, scale);
+    hipLaunchKernelGGL((k_spec_orbit<true, false>), grid, dim3(kOrbitThreads), 0, s, n, NO, S, zc, zpsi, zg, za, scale);
   else
-    hipLaunchKernelGGL((k_spec_orbit<false, true>), grid, dim3(256), 0, s, n, NO, S, zc, zpsi, zg, za, scale);
+    hipLaunchKernelGGL((k_spec_orbit<false, true>), grid, dim3(kOrbitThreads), 0, s, n, NO, S, zc, zpsi, zg, za, scale);
   if (gE)
     for (int axis = 0; axis < 3; ++axis) fft_pass<true, 0, double>(s, nb, n, 4, axis, za, za, tw, nullptr, nullptr, 0);
   return 0;
