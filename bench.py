@@ -144,6 +144,8 @@ TRAFFIC_FILES = {
                                                                      "paper_1503_08509_amd/csrc/device_common.hpp"]),
     "k_psi (near-screen field)": ("k_psi_fp64", ["paper_1503_08509_amd/csrc/k_near.hip",
                                                  "paper_1503_08509_amd/csrc/device_common.hpp"]),
+    "k_fft_axis (near-field FFT pass, 108 channels)": ("k_fft_axis_108_fp64", ["paper_1503_08509_amd/csrc/k_fft.hip"]),
+    "k_spec_orbit (spectrum products, both)": ("k_spec_orbit_fp64", ["paper_1503_08509_amd/csrc/k_fft.hip"]),
 }
 
 
