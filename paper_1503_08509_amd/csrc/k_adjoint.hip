@@ -29,52 +29,52 @@ __device__ __forceinline__ double block_sum_a(double v, double *red) {
 }
 
 // g_E[m] = sum over the element's charges of Q l_mx(u_x) l_my(u_y) l_mz(u_z):
-// one wave per element (4 per block), lane l owns nodes m = l + 64 k; per
-// charge every lane evaluates the (p+1) 1-D basis values of each axis once.
+// one wave (block) per element.  Charges go in chunks of 64: lane j
+// evaluates the 3 (p+1) one-dimensional basis values of charge j of the
+// chunk once (Q folded into the x factor) into LDS (rows padded to 65: no
+// bank conflicts when lanes read different rows of one charge); then lane l
+// accumulates its nodes m = l + 64 k from three LDS values per charge.
 template <int PO>
-__global__ __launch_bounds__(256) void k_deposit(int n, int MT, int64_t N, GllBasis bas, const int *__restrict__ start,
-                                                 const double *__restrict__ sg, const double *__restrict__ sQ,
-                                                 double *__restrict__ gE) {
+__global__ __launch_bounds__(64) void k_deposit(int n, int MT, int64_t N, GllBasis bas, const int *__restrict__ start,
+                                                const double *__restrict__ sg, const double *__restrict__ sQ,
+                                                double *__restrict__ gE) {
   constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NK = (NM + 63) / 64;
-  const int E = blockIdx.x * 4 + (threadIdx.x >> 6);   // element of the whole batch
-  if (E >= MT) return;                                  // uniform over the wave
-  const int lane = threadIdx.x & 63;
+  __shared__ double Lb[3 * Q1][65];   // [axis * (p+1) + a][charge of the chunk]
+  const int E = blockIdx.x;           // element of the whole batch
+  const int lane = threadIdx.x;
   const int El = E % (n * n * n);
   const int ex = El % n, ey = (El / n) % n, ez = El / (n * n);
-  int mx[NK], my[NK], mz[NK];
+  int ix[NK], iy[NK], iz[NK];
   double acc[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     const int m = min(lane + 64 * k, NM - 1);
-    mx[k] = m % Q1; my[k] = (m / Q1) % Q1; mz[k] = m / (Q1 * Q1);
+    ix[k] = m % Q1; iy[k] = Q1 + (m / Q1) % Q1; iz[k] = 2 * Q1 + m / (Q1 * Q1);
     acc[k] = 0.0;
   }
-  const int s1 = start[E + 1];
-  for (int s = start[E]; s < s1; ++s) {
-    const double u[3] = {sg[s] - ex - 0.5, sg[N + s] - ey - 0.5, sg[2 * N + s] - ez - 0.5};
-    double l[3][Q1];
+  const int s0 = start[E], s1 = start[E + 1];
+  for (int c0 = s0; c0 < s1; c0 += 64) {
+    const int cnt = min(64, s1 - c0);
+    __syncthreads();   // the previous chunk's values are no longer read
+    if (lane < cnt) {
+      const int s = c0 + lane;
+      const double u[3] = {sg[s] - ex - 0.5, sg[N + s] - ey - 0.5, sg[2 * N + s] - ez - 0.5};
+      const double q = sQ[s];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax)
+      for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-      for (int a = 0; a < Q1; ++a) {
-        double v = bas.w[a];
+        for (int a = 0; a < Q1; ++a) {
+          double v = bas.w[a];
 #pragma unroll
-        for (int j = 0; j < Q1; ++j)
-          if (j != a) v *= u[ax] - bas.x[j];
-        l[ax][a] = v;
-      }
-    const double q = sQ[s];
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      double lx = 0.0, ly = 0.0, lz = 0.0;   // select the lane's node values (indices are per lane)
-#pragma unroll
-      for (int a = 0; a < Q1; ++a) {
-        lx = mx[k] == a ? l[0][a] : lx;
-        ly = my[k] == a ? l[1][a] : ly;
-        lz = mz[k] == a ? l[2][a] : lz;
-      }
-      acc[k] += q * lx * ly * lz;
+          for (int j = 0; j < Q1; ++j)
+            if (j != a) v *= u[ax] - bas.x[j];
+          Lb[ax * Q1 + a][lane] = ax == 0 ? q * v : v;
+        }
     }
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) acc[k] += Lb[ix[k]][j] * Lb[iy[k]][j] * Lb[iz[k]][j];
   }
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
@@ -375,7 +375,7 @@ int launch_deposit(hipStream_t s, int nb, int p, int n, int64_t N, const GllBasi
                    const double *sg, const double *sQ, double *gE) {
   if (p != 5) return -1;
   const int MT = nb * n * n * n;
-  hipLaunchKernelGGL(k_deposit<5>, dim3((MT + 3) / 4), dim3(256), 0, s, n, MT, N, bas, start, sg, sQ, gE);
+  hipLaunchKernelGGL(k_deposit<5>, dim3(MT), dim3(64), 0, s, n, MT, N, bas, start, sg, sQ, gE);
   return 0;
 }
 int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, double *G, double *partial) {
