@@ -422,6 +422,8 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   // partials serve every two-stage reduction: the fixed reduction grids and
   // the per-tile partials of the fine-level operator
   partial_len = std::max(partial_len, size_t(2) * nb * apply_blocks(lv[0].op) + 64);
+  // row-wise mesh kernels: nb K <= max(kRowBlocks, nb) partials (nb <= 2048 systems)
+  partial_len = std::max(partial_len, size_t(kRowBlocks) + 64);
   partial = alloc<double>(partial_len, "partials");
   estimate_spectra();
   near_fft = opt.near_field == FEP3M_NEAR_FFT || (opt.near_field == FEP3M_NEAR_AUTO && fft_size_ok(n) && n <= 64);
@@ -867,8 +869,7 @@ void fep3m_ctx::mesh_solve(double *rhs, double *out, int which, int nsys) {
   nbs = nb * nsys;
   struct Reset { int &v; int to; ~Reset() { v = to; } } reset{nbs, nb};
   solve(rhs, out, which);
-  launch_mass_dot(stream, nbs, n, p, w1, out, partial);
-  launch_sum_partials(stream, seg_blocks(nbs, lv[0].ndof), partial, gauge, nbs);
+  launch_sum_partials(stream, launch_mass_dot(stream, nbs, n, p, w1, out, partial), partial, gauge, nbs);
   launch_sub_const(stream, nbs, lv[0].ndof, 1.0 / (double(n) * n * n), gauge, out);
 }
 
@@ -908,8 +909,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   stage_mark(FEP3M_PROF_SORT, false);
   stage_mark(FEP3M_PROF_ASSIGN, true);
   launch_moments(stream, nb, n, N, start, sg, sQ, C);
-  launch_load(stream, nb, n, p, C, gw, b, partial);
-  launch_sum_partials(stream, seg_blocks(nb, lv[0].ndof), partial, cfgs(kCsLoad), nb);
+  launch_sum_partials(stream, launch_load(stream, nb, n, p, C, gw, b, partial), partial, cfgs(kCsLoad), nb);
   launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsLoad), b);
   check_launch("assignment");
   stage_mark(FEP3M_PROF_ASSIGN, false);
@@ -1023,8 +1023,9 @@ void fep3m_ctx::pair_pass(bool pair_forces) {
 // Adjoint right side: deposit g, assembly G, compatibility projection.
 void fep3m_ctx::adjoint_rhs() {
   launch_deposit(stream, nb, p, n, N, bas, start, sg, sQ, gE);
-  launch_assemble(stream, nb, p, n, gE, Gv, partial);
-  launch_sum_partials(stream, seg_blocks(nb, lv[0].ndof), partial, cfgs(kCsAdjLoad), nb);
+  const int Ka = launch_assemble(stream, nb, p, n, gE, Gv, partial);
+  if (Ka < 0) throw Status(FEP3M_ERR_UNSUPPORTED, "assembly variant");
+  launch_sum_partials(stream, Ka, partial, cfgs(kCsAdjLoad), nb);
   launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsAdjLoad), Gv);
 }
 

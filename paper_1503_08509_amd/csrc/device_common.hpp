@@ -9,6 +9,7 @@ namespace fep3m {
 
 constexpr int kMaxP = 6;           // largest element order handled by the kernels
 constexpr int kRedBlocks = 1024;   // fixed block count of every two-stage reduction
+constexpr int kRowBlocks = 8192;   // block count of the row-wise mesh kernels (load, assembly, mass)
 constexpr int kRedThreads = 256;
 
 // 1-D element operator of one multigrid level, passed by value, in the

@@ -380,10 +380,9 @@ int launch_deposit(hipStream_t s, int nb, int p, int n, int64_t N, const GllBasi
 }
 int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, double *G, double *partial) {
   if (p != 5) return -1;
-  const size_t per = size_t(p * n) * (p * n) * (p * n);
-  const int K = seg_blocks(nb, per);
+  const int K = row_blocks(nb, p * n);
   hipLaunchKernelGGL(k_assemble<5>, dim3(nb * K), dim3(256), 0, s, n, K, gE, G, partial);
-  return 0;
+  return K;
 }
 int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, const double *gE, const double *Tt,
                        const double *lam, const double *gw, double *A) {

@@ -956,24 +956,27 @@ int seg_blocks(int nb, size_t per) {
   return int(g < cap ? g : cap);
 }
 int red_grid(size_t n) { return grid_for(n); }
+int row_blocks(int nb, int P) {
+  const int cap = nb >= kRowBlocks ? 1 : kRowBlocks / nb;
+  return P * P < cap ? P * P : cap;
+}
 
-void launch_load(hipStream_t s, int nb, int n, int p, const double *C, const double *gw, double *b, double *partial) {
-  const size_t per = size_t(p * n) * (p * n) * (p * n);
-  const int K = seg_blocks(nb, per);
+int launch_load(hipStream_t s, int nb, int n, int p, const double *C, const double *gw, double *b, double *partial) {
+  const int K = row_blocks(nb, p * n);
   hipLaunchKernelGGL(k_load, dim3(nb * K), dim3(256), 0, s, n, p, K, C, gw, b, partial);
+  return K;
 }
 void launch_sum_partials(hipStream_t s, int K, const double *partial, double *out, int nb) {
   hipLaunchKernelGGL(k_sum_partials, dim3(nb), dim3(256), 0, s, K, partial, out);
 }
 void launch_sub_mass_ones(hipStream_t s, int nb, int n, int p, const double *w1, const double *scal, double *v) {
-  const size_t per = size_t(p * n) * (p * n) * (p * n);
-  const int K = seg_blocks(nb, per);
+  const int K = row_blocks(nb, p * n);
   hipLaunchKernelGGL(k_sub_mass_ones, dim3(nb * K), dim3(256), 0, s, n, p, K, w1, scal, v);
 }
-void launch_mass_dot(hipStream_t s, int nb, int n, int p, const double *w1, const double *v, double *partial) {
-  const size_t per = size_t(p * n) * (p * n) * (p * n);
-  const int K = seg_blocks(nb, per);
+int launch_mass_dot(hipStream_t s, int nb, int n, int p, const double *w1, const double *v, double *partial) {
+  const int K = row_blocks(nb, p * n);
   hipLaunchKernelGGL(k_mass_dot, dim3(nb * K), dim3(256), 0, s, n, p, K, w1, v, partial);
+  return K;
 }
 void launch_sub_const(hipStream_t s, int nb, size_t per, double invV, const double *scal, double *v) {
   const int K = seg_blocks(nb, per);

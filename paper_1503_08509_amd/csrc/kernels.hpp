@@ -63,6 +63,7 @@ int launch_interp_f32(hipStream_t s, int nb, const int *off, int p, int n, int64
 // adjoint (k_adjoint.hip)
 int launch_deposit(hipStream_t s, int nb, int p, int n, int64_t N, const GllBasis &bas, const int *start,
                    const double *sg, const double *sQ, double *gE);
+// returns the partial count K per configuration (-1: unsupported order)
 int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, double *G, double *partial);
 int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, const double *gE, const double *Tt,
                        const double *lam, const double *gw, double *A);
@@ -103,10 +104,12 @@ int launch_adj_fft_finish(hipStream_t s, int nb, int n, int p, const double *lam
 // returns its own K) that launch_sum_partials folds into out[0 .. nb).
 int red_grid(size_t n);
 int seg_blocks(int nb, size_t per);
-void launch_load(hipStream_t s, int nb, int n, int p, const double *C, const double *gw, double *b, double *partial);
+// block count per configuration of the row-wise mesh kernels (P nodes per axis)
+int row_blocks(int nb, int P);
+int launch_load(hipStream_t s, int nb, int n, int p, const double *C, const double *gw, double *b, double *partial);
 void launch_sum_partials(hipStream_t s, int K, const double *partial, double *out, int nb = 1);
 void launch_sub_mass_ones(hipStream_t s, int nb, int n, int p, const double *w1, const double *scal, double *v);
-void launch_mass_dot(hipStream_t s, int nb, int n, int p, const double *w1, const double *v, double *partial);
+int launch_mass_dot(hipStream_t s, int nb, int n, int p, const double *w1, const double *v, double *partial);
 void launch_sub_const(hipStream_t s, int nb, size_t per, double invV, const double *scal, double *v);
 // Multigrid kernels in the arithmetic type T (double, or float for the
 // mixed-precision preconditioner); instantiated for both in k_mesh.hip.
