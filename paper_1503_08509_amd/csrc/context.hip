@@ -426,7 +426,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   partial_len = std::max(partial_len, size_t(kRowBlocks) + 64);
   partial = alloc<double>(partial_len, "partials");
   estimate_spectra();
-  near_fft = opt.near_field == FEP3M_NEAR_FFT || (opt.near_field == FEP3M_NEAR_AUTO && fft_size_ok(n) && n <= 64);
+  near_fft = opt.near_field == FEP3M_NEAR_FFT || (opt.near_field == FEP3M_NEAR_AUTO && fft_size_ok(n));
   if (near_fft) build_near_fft();
   stats.near_fft = near_fft ? 1 : 0;
   auto t1 = std::chrono::steady_clock::now();

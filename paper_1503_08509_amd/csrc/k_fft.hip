@@ -34,7 +34,7 @@
 // holds lb lines x cc channels of length n (at most 2048 complex values):
 // rows of cc consecutive channels (and lb consecutive elements across the
 // line for the y and z passes) are contiguous in memory.  Twiddles come from
-// a table computed on the host.  n is a power of two, 8 .. 128.
+// a table computed on the host.  n is a power of two, 8 .. 64.
 #include "kernels.hpp"
 
 namespace fep3m {
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void k_adj_finish(int n, int nb, const double 
 
 // ------------------------------------------------------------- launchers
 
-bool fft_size_ok(int n) { return n >= 8 && n <= 128 && (n & (n - 1)) == 0; }
+bool fft_size_ok(int n) { return n >= 8 && n <= 64 && (n & (n - 1)) == 0; }
 
 size_t spec_freqs(int n) { return size_t(n / 2 + 1) * (n / 2 + 1) * (n / 2 + 1); }
 
@@ -405,8 +405,7 @@ void fft_pass_n(hipStream_t s, int nb, int n, int axis, const double2 *src, doub
     case 8: fft_launch<3, NCH, INV, EPI, WT>(s, nb, axis, src, dst, tw, phi, W, po); break;
     case 16: fft_launch<4, NCH, INV, EPI, WT>(s, nb, axis, src, dst, tw, phi, W, po); break;
     case 32: fft_launch<5, NCH, INV, EPI, WT>(s, nb, axis, src, dst, tw, phi, W, po); break;
-    case 64: fft_launch<6, NCH, INV, EPI, WT>(s, nb, axis, src, dst, tw, phi, W, po); break;
-    default: fft_launch<7, NCH, INV, EPI, WT>(s, nb, axis, src, dst, tw, phi, W, po); break;
+    default: fft_launch<6, NCH, INV, EPI, WT>(s, nb, axis, src, dst, tw, phi, W, po); break;
   }
 }
 

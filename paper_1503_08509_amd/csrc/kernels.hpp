@@ -79,7 +79,7 @@ template <class T>
 int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, const double *C, const T *Tab, const double *phi, T *Wel);
 
 // near field and its transpose by 3-D FFTs of the element lattice (k_fft.hip);
-// n a power of two in [8, 128], p = 5.  S: table spectrum at the
+// n a power of two in [8, 64], p = 5.  S: table spectrum at the
 // spec_freqs(n) = (n/2 + 1)^3 octant frequencies x 8 x (p+1)^3 complex;
 // tw: exp(-2 pi i j / n), j < n.  Work arrays: zc, za nb n^3 x 4 complex;
 // zpsi, zg nb n^3 x (p+1)^3 / 2 complex.

@@ -72,10 +72,10 @@ def test_unsupported_degree_is_reported():
     assert fp.lib().fep3m_create(1.0, 100, d, 4, ctypes.byref(h)) == fp.ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("n", [7, 9, 12, 256])
+@pytest.mark.parametrize("n", [7, 9, 12, 128, 256])
 def test_fft_near_field_needs_power_of_two_mesh(n):
     """The FFT near field is refused (before any device work) unless n is a
-    power of two in [8, 128]; the default picks it only where it applies."""
+    power of two in [8, 64]; the default picks it only where it applies."""
     h = ctypes.c_void_p()
     d = (ctypes.c_int32 * 3)(n, n, n)
     o = fp.default_options()
