@@ -53,18 +53,6 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {
 
 constexpr int kFftCap = 2048;   // complex values per FFT block (32 KB of LDS)
 
-// Frequency pair of half-set index kk: full indices of k and -k, and whether
-// kk is the representative of its pair (the planes k_z = 0 and k_z = n/2
-// hold both members; the lower (k_y, k_x) one is the representative).
-__device__ __forceinline__ bool freq_pair(int kk, int n, int &fk, int &fm) {
-  const int kx = kk % n, ky = (kk / n) % n, kz = kk / (n * n);
-  const int mx = (n - kx) & (n - 1), my = (n - ky) & (n - 1), mz = (n - kz) & (n - 1);
-  fk = (kz * n + ky) * n + kx;
-  fm = (mz * n + my) * n + mx;
-  if (kz == 0 || 2 * kz == n) return ky * n + kx <= my * n + mx;
-  return true;
-}
-
 }  // namespace
 
 // Block shape of an FFT pass: cc channels (a divisor of nch) x lb lines of
