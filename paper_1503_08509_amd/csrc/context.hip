@@ -869,7 +869,9 @@ void fep3m_ctx::mesh_solve(double *rhs, double *out, int which, int nsys) {
   nbs = nb * nsys;
   struct Reset { int &v; int to; ~Reset() { v = to; } } reset{nbs, nb};
   solve(rhs, out, which);
-  launch_sum_partials(stream, launch_mass_dot(stream, nbs, n, p, w1, out, partial), partial, gauge, nbs);
+  const int Km = launch_mass_dot(stream, nbs, n, p, w1, out, partial);
+  if (Km < 0) throw Status(FEP3M_ERR_UNSUPPORTED, "mass integral variant");
+  launch_sum_partials(stream, Km, partial, gauge, nbs);
   launch_sub_const(stream, nbs, lv[0].ndof, 1.0 / (double(n) * n * n), gauge, out);
 }
 
@@ -909,8 +911,11 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   stage_mark(FEP3M_PROF_SORT, false);
   stage_mark(FEP3M_PROF_ASSIGN, true);
   launch_moments(stream, nb, n, N, start, sg, sQ, C);
-  launch_sum_partials(stream, launch_load(stream, nb, n, p, C, gw, b, partial), partial, cfgs(kCsLoad), nb);
-  launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsLoad), b);
+  const int Kl = launch_load(stream, nb, n, p, C, gw, b, partial);
+  if (Kl < 0) throw Status(FEP3M_ERR_UNSUPPORTED, "load variant");
+  launch_sum_partials(stream, Kl, partial, cfgs(kCsLoad), nb);
+  if (launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsLoad), b) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "projection variant");
   check_launch("assignment");
   stage_mark(FEP3M_PROF_ASSIGN, false);
   // With forces the adjoint right side (the charges' deposit, which does not
@@ -1026,7 +1031,8 @@ void fep3m_ctx::adjoint_rhs() {
   const int Ka = launch_assemble(stream, nb, p, n, gE, Gv, partial);
   if (Ka < 0) throw Status(FEP3M_ERR_UNSUPPORTED, "assembly variant");
   launch_sum_partials(stream, Ka, partial, cfgs(kCsAdjLoad), nb);
-  launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsAdjLoad), Gv);
+  if (launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsAdjLoad), Gv) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "projection variant");
 }
 
 void fep3m_ctx::reverse(double *F, double *dUdQ) {

@@ -15,16 +15,15 @@
 
 namespace fep3m {
 
-__device__ __forceinline__ double block_sum_a(double v, double *red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+// Fixed-shape block sum for any block of whole waves (up to 8): shuffle tree
+// inside each wave, then the wave sums in order; valid in thread 0.
+__device__ __forceinline__ double block_sum_waves_a(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  double r = red[0];
-  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < int(blockDim.x >> 6); ++w) r += red[w];
   return r;
 }
 
@@ -87,10 +86,10 @@ __global__ __launch_bounds__(64) void k_deposit(int n, int MT, int64_t N, GllBas
 // with per-configuration block partials (K blocks per configuration) of
 // sum G for the compatibility projection.
 template <int PO>
-__global__ __launch_bounds__(256) void k_assemble(int n, int K, const double *__restrict__ gEall,
+__global__ __launch_bounds__(512) void k_assemble(int n, int K, const double *__restrict__ gEall,
                                                   double *__restrict__ Gall, double *__restrict__ partial) {
   constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
-  __shared__ double red[256];
+  __shared__ double red[8];
   const int P = PO * n;
   const size_t total = size_t(P) * P * P;
   const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
@@ -125,7 +124,7 @@ __global__ __launch_bounds__(256) void k_assemble(int n, int K, const double *__
     acc += s;
     }
   }
-  double t = block_sum_a(acc, red);
+  double t = block_sum_waves_a(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
@@ -381,7 +380,7 @@ int launch_deposit(hipStream_t s, int nb, int p, int n, int64_t N, const GllBasi
 int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, double *G, double *partial) {
   if (p != 5) return -1;
   const int K = row_blocks(nb, p * n);
-  hipLaunchKernelGGL(k_assemble<5>, dim3(nb * K), dim3(256), 0, s, n, K, gE, G, partial);
+  hipLaunchKernelGGL(k_assemble<5>, dim3(nb * K), dim3(row_threads(p * n)), 0, s, n, K, gE, G, partial);
   return K;
 }
 int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, const double *gE, const double *Tt,

@@ -29,6 +29,19 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return r;
 }
 
+// Fixed-shape block sum for any block of whole waves (up to 8): shuffle
+// tree inside each wave, then the wave sums in order.  The result is valid
+// in thread 0.
+__device__ __forceinline__ double block_sum_waves(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < int(blockDim.x >> 6); ++w) r += red[w];
+  return r;
+}
+
 // ----------------------------------------------------------------- load
 
 // Elements owning global node g along one axis (order p, n elements,
@@ -47,10 +60,12 @@ __device__ __forceinline__ int node_owners(int g, int p, int n, int (&e)[2], int
 // sum_a C[E][a] g[ax][kx] g[ay][ky] g[az][kz] (gather form, no atomics),
 // with per-configuration block partial sums of b (K blocks per
 // configuration) for the compatibility projection.
-__global__ __launch_bounds__(256) void k_load(int n, int p, int K, const double *__restrict__ Call,
+template <int PO>
+__global__ __launch_bounds__(512) void k_load(int n, int K, const double *__restrict__ Call,
                                               const double *__restrict__ gw, double *__restrict__ ball,
                                               double *__restrict__ partial) {
-  __shared__ double red[256];
+  constexpr int p = PO;
+  __shared__ double red[8];
   const int P = p * n;
   const size_t total = size_t(P) * P * P;
   const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
@@ -83,15 +98,17 @@ __global__ __launch_bounds__(256) void k_load(int n, int p, int K, const double 
     acc += s;
     }
   }
-  double t = block_sum(acc, red);
+  double t = block_sum_waves(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
 // v -= s * w1[kx] w1[ky] w1[kz] with s = scal[b] / V  (V = n^3 in element
 // units) on configuration b: subtracts the uniform-background multiple of
 // M 1.  Used on the load (compatibility) with scal = sum b.
-__global__ __launch_bounds__(256) void k_sub_mass_ones(int n, int p, int K, const double *__restrict__ w1,
+template <int PO>
+__global__ __launch_bounds__(512) void k_sub_mass_ones(int n, int K, const double *__restrict__ w1,
                                                        const double *__restrict__ scal, double *__restrict__ vall) {
+  constexpr int p = PO;
   const int P = p * n;
   const size_t total = size_t(P) * P * P;
   const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
@@ -110,9 +127,11 @@ __global__ __launch_bounds__(256) void k_sub_mass_ones(int n, int p, int K, cons
 
 // Per-configuration block partials of (M 1)^T v = sum w1 w1 w1 v (the
 // integral of the FE field).
-__global__ __launch_bounds__(256) void k_mass_dot(int n, int p, int K, const double *__restrict__ w1,
+template <int PO>
+__global__ __launch_bounds__(512) void k_mass_dot(int n, int K, const double *__restrict__ w1,
                                                   const double *__restrict__ vall, double *__restrict__ partial) {
-  __shared__ double red[256];
+  constexpr int p = PO;
+  __shared__ double red[8];
   const int P = p * n;
   const size_t total = size_t(P) * P * P;
   const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
@@ -124,7 +143,7 @@ __global__ __launch_bounds__(256) void k_mass_dot(int n, int p, int K, const dou
     const double wy = w1[gy % p], wz = w1[gz % p];
     for (int gx = threadIdx.x; gx < P; gx += blockDim.x) acc += w1[gx % p] * wy * wz * v[size_t(row) * P + gx];
   }
-  double t = block_sum(acc, red);
+  double t = block_sum_waves(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
@@ -961,21 +980,26 @@ int row_blocks(int nb, int P) {
   return P * P < cap ? P * P : cap;
 }
 
+int row_threads(int P) { return P >= 512 ? 512 : 64 * ((P + 63) / 64); }
 int launch_load(hipStream_t s, int nb, int n, int p, const double *C, const double *gw, double *b, double *partial) {
+  if (p != 5) return -1;
   const int K = row_blocks(nb, p * n);
-  hipLaunchKernelGGL(k_load, dim3(nb * K), dim3(256), 0, s, n, p, K, C, gw, b, partial);
+  hipLaunchKernelGGL(k_load<5>, dim3(nb * K), dim3(row_threads(p * n)), 0, s, n, K, C, gw, b, partial);
   return K;
 }
 void launch_sum_partials(hipStream_t s, int K, const double *partial, double *out, int nb) {
   hipLaunchKernelGGL(k_sum_partials, dim3(nb), dim3(256), 0, s, K, partial, out);
 }
-void launch_sub_mass_ones(hipStream_t s, int nb, int n, int p, const double *w1, const double *scal, double *v) {
+int launch_sub_mass_ones(hipStream_t s, int nb, int n, int p, const double *w1, const double *scal, double *v) {
+  if (p != 5) return -1;
   const int K = row_blocks(nb, p * n);
-  hipLaunchKernelGGL(k_sub_mass_ones, dim3(nb * K), dim3(256), 0, s, n, p, K, w1, scal, v);
+  hipLaunchKernelGGL(k_sub_mass_ones<5>, dim3(nb * K), dim3(row_threads(p * n)), 0, s, n, K, w1, scal, v);
+  return 0;
 }
 int launch_mass_dot(hipStream_t s, int nb, int n, int p, const double *w1, const double *v, double *partial) {
+  if (p != 5) return -1;
   const int K = row_blocks(nb, p * n);
-  hipLaunchKernelGGL(k_mass_dot, dim3(nb * K), dim3(256), 0, s, n, p, K, w1, v, partial);
+  hipLaunchKernelGGL(k_mass_dot<5>, dim3(nb * K), dim3(row_threads(p * n)), 0, s, n, K, w1, v, partial);
   return K;
 }
 void launch_sub_const(hipStream_t s, int nb, size_t per, double invV, const double *scal, double *v) {

@@ -104,11 +104,13 @@ int launch_adj_fft_finish(hipStream_t s, int nb, int n, int p, const double *lam
 // returns its own K) that launch_sum_partials folds into out[0 .. nb).
 int red_grid(size_t n);
 int seg_blocks(int nb, size_t per);
-// block count per configuration of the row-wise mesh kernels (P nodes per axis)
+// block count per configuration and block size (whole waves, up to 512
+// threads, one row of P nodes per pass) of the row-wise mesh kernels
 int row_blocks(int nb, int P);
+int row_threads(int P);
 int launch_load(hipStream_t s, int nb, int n, int p, const double *C, const double *gw, double *b, double *partial);
 void launch_sum_partials(hipStream_t s, int K, const double *partial, double *out, int nb = 1);
-void launch_sub_mass_ones(hipStream_t s, int nb, int n, int p, const double *w1, const double *scal, double *v);
+int launch_sub_mass_ones(hipStream_t s, int nb, int n, int p, const double *w1, const double *scal, double *v);
 int launch_mass_dot(hipStream_t s, int nb, int n, int p, const double *w1, const double *v, double *partial);
 void launch_sub_const(hipStream_t s, int nb, size_t per, double invV, const double *scal, double *v);
 // Multigrid kernels in the arithmetic type T (double, or float for the
