@@ -43,6 +43,28 @@ def test_forces_match_oracle(torch, wl, N, n, near):
     assert ctx.stats()["adj_iterations"] > 0
 
 
+@pytest.mark.parametrize("near", [fp.NEAR_AUTO, fp.NEAR_DIRECT])
+def test_forces_dense_elements_match_oracle(torch, near):
+    """Elements holding more than 64 charges (several 64-charge chunks in the
+    deposit, 8-target chunks in the pair sum): 150 charges inside one element
+    and 90 inside another, plus 160 spread uniformly, on 8^3 elements."""
+    rng = np.random.default_rng(41)
+    h = 1.0 / 8
+    a = (np.array([2, 5, 3]) + rng.uniform(0.05, 0.95, (150, 3))) * h
+    b = (np.array([7, 0, 6]) + rng.uniform(0.05, 0.95, (90, 3))) * h
+    x = np.concatenate([a, b, rng.random((160, 3))])
+    Q = np.where(rng.random(400) < 0.5, 1.0, -1.0)
+    Q -= Q.mean()
+    ref = adjoint.energy_forces(x, Q, fep3m.Params(L=1.0, n=8))
+    ctx = fp.Context(1.0, len(Q), 8, mg_rtol=1e-13, near_field=near)
+    out = ctx.energy_forces(torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda(), dUdQ=True, Phi=True)
+    assert ctx.stats()["max_per_element"] >= 150
+    assert _rel(out["F"].cpu().numpy(), ref["F"]) < 1e-9
+    assert _rel(out["dUdQ"].cpu().numpy(), ref["dUdQ"]) < 1e-9
+    assert _rel(out["Phi"].cpu().numpy(), ref["Phi"]) < 1e-10
+    assert abs(float(out["U"].item()) - ref["U"]) < 1e-10 * abs(ref["U"])
+
+
 def test_energy_forces_consistent_with_energy(torch):
     x, Q = workloads.make("uniform-1k-n8")
     ctx = fp.Context(1.0, len(Q), 8)
