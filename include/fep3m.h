@@ -101,8 +101,9 @@ enum {
                              being symmetric under axis reflections:
                              (n/2 + 1)^3 x 8 x (p+1)^3 complex float64, 0.99 GB
                              at n = 64).  float64 in both precisions;
-                             n must be a power of two in [8, 64]. Agrees with
-                             DIRECT to about 1e-15 relative.                    */
+                             n must be a power of two in [8, 64] (else create
+                             returns FEP3M_ERR_UNSUPPORTED).  Agrees with
+                             DIRECT to about 1e-14 relative (Phi, F).           */
 };
 
 typedef struct {
