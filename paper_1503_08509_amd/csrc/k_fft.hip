@@ -30,8 +30,9 @@
 // handles the orbit of one octant frequency (which holds -k as well).  With
 // forces both products run in the same blocks: one read of the spectrum.
 //
-// FFTs: one kernel per axis, radix-2 decimation in time in LDS.  A block
-// holds lb lines x cc channels of length n (at most 2048 complex values):
+// FFTs: one kernel per axis, decimation in time in LDS (radix-2 stages
+// taken two at a time).  A block holds lb lines x cc channels of length n
+// (at most 2048 complex values):
 // rows of cc consecutive channels (and lb consecutive elements across the
 // line for the y and z passes) are contiguous in memory.  Twiddles come from
 // a table computed on the host.  n is a power of two, 8 .. 64.
@@ -110,18 +111,39 @@ __global__ __launch_bounds__(256) void k_fft_axis(int axis, const double2 *src, 
     buf[int(__brev(unsigned(j)) >> (32 - LOGN)) * U + l * CC + c] = src[base + j * sj + l * sl + c];
   }
   __syncthreads();
+  // Radix-2 stages (half-size h = 2^s, twiddle W_2h^pos), taken two at a
+  // time: one pass over LDS does stages s and s + 1 on the four values
+  // j0 + {0, h, 2h, 3h} (the same operations in the same order, so the
+  // result equals the stage-by-stage one); an odd count starts with a single
+  // stage.
+  if (LOGN & 1) {
+    for (int t = tid; t < (N / 2) * U; t += 256) {   // s = 0: twiddle 1
+      const int u = t % U, j0 = 2 * (t / U);
+      const double2 x0 = buf[j0 * U + u], x1 = cmul(buf[(j0 + 1) * U + u], tws[0]);
+      buf[j0 * U + u] = cadd(x0, x1);
+      buf[(j0 + 1) * U + u] = csub(x0, x1);
+    }
+    __syncthreads();
+  }
 #pragma unroll
-  for (int s = 0; s < LOGN; ++s) {
+  for (int s = LOGN & 1; s < LOGN; s += 2) {
     const int h = 1 << s;
-    for (int t = tid; t < (N / 2) * U; t += 256) {
+    for (int t = tid; t < (N / 4) * U; t += 256) {
       const int u = t % U, bf = t / U;
       const int pos = bf & (h - 1);
-      const int j0 = ((bf >> s) << (s + 1)) + pos, j1 = j0 + h;
-      double2 w = tws[pos << (LOGN - 1 - s)];
-      if (INV) w.y = -w.y;
-      const double2 x0 = buf[j0 * U + u], x1 = cmul(buf[j1 * U + u], w);
-      buf[j0 * U + u] = cadd(x0, x1);
-      buf[j1 * U + u] = csub(x0, x1);
+      const int j0 = ((bf >> s) << (s + 2)) + pos;
+      double2 w1 = tws[pos << (LOGN - 1 - s)], w2 = tws[pos << (LOGN - 2 - s)],
+              w3 = tws[(pos + h) << (LOGN - 2 - s)];
+      if (INV) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
+      const double2 x0 = buf[j0 * U + u], x1 = buf[(j0 + h) * U + u];
+      const double2 x2 = buf[(j0 + 2 * h) * U + u], x3 = buf[(j0 + 3 * h) * U + u];
+      const double2 t1 = cmul(x1, w1), t3 = cmul(x3, w1);
+      const double2 a0 = cadd(x0, t1), a1 = csub(x0, t1), a2 = cadd(x2, t3), a3 = csub(x2, t3);
+      const double2 t2 = cmul(a2, w2), t4 = cmul(a3, w3);
+      buf[j0 * U + u] = cadd(a0, t2);
+      buf[(j0 + h) * U + u] = cadd(a1, t4);
+      buf[(j0 + 2 * h) * U + u] = csub(a0, t2);
+      buf[(j0 + 3 * h) * U + u] = csub(a1, t4);
     }
     __syncthreads();
   }
