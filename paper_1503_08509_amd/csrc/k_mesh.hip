@@ -853,10 +853,7 @@ __global__ __launch_bounds__(256) void k_scale(size_t n, double s, const double 
     b[i] = s * a[i];
 }
 
-// Fill and copy as kernels (usable inside a captured graph).
-__global__ __launch_bounds__(256) void k_fill_f64(size_t n, double v, double *__restrict__ p) {
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) p[i] = v;
-}
+// Copy as a kernel (usable inside a captured graph, unlike a memcpy node).
 __global__ __launch_bounds__(256) void k_copy_f64(size_t n, const double *__restrict__ a, double *__restrict__ b) {
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x) b[i] = a[i];
 }
@@ -974,7 +971,6 @@ int seg_blocks(int nb, size_t per) {
   if (g < 1) g = 1;
   return int(g < cap ? g : cap);
 }
-int red_grid(size_t n) { return grid_for(n); }
 int row_blocks(int nb, int P) {
   const int cap = nb >= kRowBlocks ? 1 : kRowBlocks / nb;
   return P * P < cap ? P * P : cap;
@@ -1198,9 +1194,6 @@ void launch_scale(hipStream_t s, size_t n, double sc, const double *a, double *b
 }
 void launch_fdm_scale(hipStream_t s, size_t total, int P, int i0, const double *lam, double *X) {
   hipLaunchKernelGGL(k_fdm_scale, dim3(grid_for(total)), dim3(256), 0, s, total, P, i0, lam, X);
-}
-void launch_fill_f64(hipStream_t s, size_t n, double v, double *p) {
-  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(256), 0, s, n, v, p);
 }
 void launch_copy_f64(hipStream_t s, size_t n, const double *a, double *b) {
   hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(n)), dim3(256), 0, s, n, a, b);

@@ -102,7 +102,6 @@ int launch_adj_fft_finish(hipStream_t s, int nb, int n, int p, const double *lam
 // mesh (k_mesh.hip).  nb configurations; per-configuration reductions
 // write nb * K block partials (K = seg_blocks(nb, per) unless a launcher
 // returns its own K) that launch_sum_partials folds into out[0 .. nb).
-int red_grid(size_t n);
 int seg_blocks(int nb, size_t per);
 // block count per configuration and block size (whole waves, up to 512
 // threads, one row of P nodes per pass) of the row-wise mesh kernels
@@ -156,7 +155,6 @@ void launch_p_init(hipStream_t s, int nb, size_t per, const ZT *z, double *p);
 void launch_x_final(hipStream_t s, int nb, size_t per, const double *alphas, const double *p, double *x, bool xinit);
 void launch_scale(hipStream_t s, size_t n, double sc, const double *a, double *b);
 void launch_hash_fill(hipStream_t s, size_t n, uint32_t seed, double *v);
-void launch_fill_f64(hipStream_t s, size_t n, double v, double *p);
 void launch_fdm_scale(hipStream_t s, size_t total, int P, int i0, const double *lam, double *X);
 void launch_copy_f64(hipStream_t s, size_t n, const double *a, double *b);
 
