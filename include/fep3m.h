@@ -52,7 +52,7 @@ enum {
   FEP3M_ERR_NOT_CONVERGED = -4, /* mesh solve missed mg_rtol within mg_max_iter     */
   FEP3M_ERR_DEVICE = -5,        /* HIP runtime error                               */
   FEP3M_ERR_OOM = -6,           /* device allocation failed                        */
-  FEP3M_ERR_UNSUPPORTED = -7    /* valid request this build does not implement      */
+  FEP3M_ERR_UNSUPPORTED = -7    /* valid request the library does not implement     */
 };
 
 enum {
