@@ -184,6 +184,13 @@ struct fep3m_ctx {
   };
   PairPlan plan;
   bool tuned = false;
+  // The near-pair sum depends only on the sorted charges and is
+  // instruction-bound, the mesh solve is memory-bound: eagerly (tuning done,
+  // no capture) the pair pass runs on a second stream forked after the sort
+  // and joined before the interpolation, overlapping the assignment, solve
+  // and near field.  Default priority, like every stream here.
+  hipStream_t pstream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // graph mode: the whole evaluation captured once per set of argument
   // pointers on an internal stream, then replayed
   hipStream_t gstream = nullptr;
@@ -222,6 +229,9 @@ struct fep3m_ctx {
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (gstream) (void)hipStreamDestroy(gstream);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (pstream) (void)hipStreamDestroy(pstream);
     if (blas) (void)rocblas_destroy_handle(blas);
   }
   void check_launch(const char *what) { hip_check(hipGetLastError(), what); }
@@ -909,6 +919,31 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   items_titem = -1;   // the pair work list follows this call's element starts
   if (mixed) launch_local_f32(stream, n, N, sg, sQ, su, si, sel);
   stage_mark(FEP3M_PROF_SORT, false);
+  // overlap only with one wave per element (short blocks that interleave
+  // with the solve's); persistent waves would hold every CU for the pass
+  const bool overlap = !capturing && !(opt.autotune && !tuned && !prof.on) && plan.kind == 0;
+  if (overlap) {
+    if (!pstream) {
+      hip_check(hipStreamCreateWithFlags(&pstream, hipStreamNonBlocking), "pair stream");
+      hip_check(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming), "event");
+      hip_check(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming), "event");
+    }
+    hip_check(hipEventRecord(ev_fork, stream), "event");
+    hip_check(hipStreamWaitEvent(pstream, ev_fork, 0), "wait");
+    struct Restore { hipStream_t &s; hipStream_t to; ~Restore() { s = to; } } restore{stream, stream};
+    stream = pstream;   // the pair pass's launches and stage events go to the second stream
+    pair_pass(pair_forces);
+    hip_check(hipEventRecord(ev_join, pstream), "event");
+  }
+  // the main stream waits for the pair pass before the interpolation, and on
+  // any early exit, so that no later work overwrites what it reads
+  struct Join {
+    hipStream_t &s;
+    hipEvent_t e;
+    bool pending;
+    void now() { if (pending) hip_check(hipStreamWaitEvent(s, e, 0), "wait"); pending = false; }
+    ~Join() { if (pending) (void)hipStreamWaitEvent(s, e, 0); }
+  } join{stream, ev_join, overlap};
   stage_mark(FEP3M_PROF_ASSIGN, true);
   launch_moments(stream, nb, n, N, start, sg, sQ, C);
   const int Kl = launch_load(stream, nb, n, p, C, gw, b, partial);
@@ -946,7 +981,8 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
                : launch_psi<double>(stream, nb, n, nsr, p, C, T, sol, Wel);
   if (ps != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
   stage_mark(FEP3M_PROF_NEAR, false);
-  pair_pass(pair_forces);
+  if (overlap) join.now();
+  else pair_pass(pair_forces);
   stage_mark(FEP3M_PROF_INTERP, true);
   const int is = mixed ? launch_interp_f32(stream, nb, off_d, p, n, N, 1.0 / h, bas, su, sel, Welf, phip_s, perm,
                                            phim_s, phi_s, Phi)
