@@ -950,8 +950,16 @@ __global__ __launch_bounds__(64) void k_pcg_scalars(int nb, int step, double rto
 __global__ __launch_bounds__(256) void k_sum_partials(int K, const double *__restrict__ partial, double *__restrict__ out) {
   __shared__ double red[256];
   partial += size_t(blockIdx.x) * K;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < K; i += blockDim.x) acc += partial[i];
+  // eight independent sums per thread keep eight loads in flight (one block
+  // may read tens of thousands of partials); fixed order, so repeatable
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int i = threadIdx.x;
+  for (; i + 7 * 256 < K; i += 8 * 256) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += partial[i + u * 256];
+  }
+  for (; i < K; i += 256) a[0] += partial[i];
+  const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   double t = block_sum(acc, red);
   if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
