@@ -1,0 +1,108 @@
+"""How the error of the GPU path falls with the distance at which pair
+interactions are cut off: the near block of (2 n_sr + 1)^3 elements.
+
+Beyond the near block a charge acts on another only through the mesh, i.e.
+through its screen, so the error there is the short-range potential 1/R minus
+the screen's potential.  Section 2.1 studies that quantity for charges in an
+element, sampled along 42 directions: for the one-element q = 3 screen
+(monopole and dipole cancelled, Section 5) it falls like R^-3 once R is a few
+elements.  These tests measure it through the whole GPU path, against Ewald:
+
+* one unit charge at each of 84 seeded locations in an element (its
+  opposite charge at the farthest periodic point), zero-charge probes along
+  42 directions (icosahedron vertices and edge midpoints) at 2.5 .. 4
+  elements, all outside the 3^3 near block; the mean and the peak error fall
+  with a log-log slope near -3 (measured -2.9 and -3.3);
+* the paper's two-cube charge set (Section 4), N = 1000, 16^3 elements: the
+  RMS errors of Phi and F fall at every step n_sr = 1, 2, 3 (measured ratios
+  0.36 .. 0.56 per step), on the FFT and DIRECT near fields alike."""
+import numpy as np
+import pytest
+
+import paper_1503_08509_amd as fp
+import workloads
+from oracle import ewald
+from oracle import fep3m as ofe
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available()
+    return _t
+
+
+def _directions42():
+    """Unit vectors to the 12 vertices and 30 edge midpoints of an icosahedron."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    v = []
+    for a in (-1.0, 1.0):
+        for b in (-t, t):
+            v += [(0.0, a, b), (a, b, 0.0), (b, 0.0, a)]
+    v = np.array(v)
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    mids = [v[i] + v[j] for i in range(12) for j in range(i + 1, 12) if np.dot(v[i], v[j]) > 0.4]
+    d = np.vstack([v, np.array(mids)])
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    assert d.shape == (42, 3)
+    return d
+
+
+def test_single_charge_error_decays_like_R3(torch):
+    n, h, n_sr = 16, 1.0 / 16, 1
+    R = np.array([2.5, 3.0, 3.5, 4.0])          # in elements
+    D = _directions42()
+    rng = np.random.default_rng(84)
+    nprobe = len(R) * len(D)
+    ctx = fp.Context(1.0, 2 + nprobe, n, n_sr=n_sr, mg_rtol=1e-13)
+    err = np.zeros((84, len(R), len(D)))
+    for s in range(84):
+        x0 = (np.array([5.0, 6.0, 7.0]) + rng.random(3)) * h
+        probes = (x0[None, None, :] + R[:, None, None] * h * D[None, :, :]).reshape(-1, 3)
+        # every probe lies outside the source's near block
+        assert (np.abs(np.floor(probes / h) - np.floor(x0 / h)).max(axis=1) > n_sr).all()
+        x = np.vstack([x0, (x0 + 0.5) % 1.0, probes]) % 1.0
+        Q = np.zeros(len(x))
+        Q[0], Q[1] = 1.0, -1.0
+        out = ctx.energy_forces(torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda(), Phi=True)
+        tg = np.arange(2, len(x))
+        ref = ewald.ewald(x, Q, targets=tg)
+        _, _, u = ofe.bin_particles(x, 1.0, n)
+        e = out["Phi"].cpu().numpy()[tg] + ofe.ewald_constant(u, Q, ofe.Params(L=1.0, n=n)) - ref["Phi"]
+        err[s] = np.abs(e).reshape(len(R), len(D)) * h   # in units of 1/h, as R is in units of h
+    mean = err.mean(axis=(0, 2))
+    peak = err.max(axis=(0, 2))
+    s_mean = np.polyfit(np.log(R), np.log(mean), 1)[0]
+    s_peak = np.polyfit(np.log(R), np.log(peak), 1)[0]
+    print(f"|Phi_sr| h: mean {mean}, peak {peak}; slopes {s_mean:.2f}, {s_peak:.2f}")
+    assert np.all(np.diff(mean) < 0) and np.all(np.diff(peak) < 0)
+    assert -3.5 < s_mean < -2.5
+    assert -4.0 < s_peak < -2.5
+
+
+def test_error_falls_with_near_block_size(torch):
+    N, n = 1000, 16
+    w = workloads.Workload("twocube-1000-n16", N, n, kind="twocube", charges="biased", seed=77)
+    x, Q = workloads.make(w)
+    ref = ewald.ewald(x, Q, forces=True, targets=np.arange(N))
+    _, _, u = ofe.bin_particles(x, 1.0, n)
+    c = ofe.ewald_constant(u, Q, ofe.Params(L=1.0, n=n))
+    tx, tQ = torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda()
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    errs = {}
+    for near in (fp.NEAR_FFT, fp.NEAR_DIRECT):
+        for n_sr in (1, 2, 3):
+            out = fp.Context(1.0, N, n, n_sr=n_sr, mg_rtol=1e-12, near_field=near).energy_forces(tx, tQ, Phi=True)
+            errs[near, n_sr] = (rel(out["Phi"].cpu().numpy() + c, ref["Phi"]), rel(out["F"].cpu().numpy(), ref["F"]))
+            print(f"near={near} n_sr={n_sr}: Phi {errs[near, n_sr][0]:.3e}, F {errs[near, n_sr][1]:.3e}")
+    for near in (fp.NEAR_FFT, fp.NEAR_DIRECT):
+        for n_sr in (1, 2):
+            for k in range(2):
+                assert errs[near, n_sr + 1][k] < 0.65 * errs[near, n_sr][k]
+    for n_sr in (1, 2, 3):
+        np.testing.assert_allclose(errs[fp.NEAR_FFT, n_sr], errs[fp.NEAR_DIRECT, n_sr], rtol=1e-6)
