@@ -227,10 +227,10 @@ int fep3m_create_batch(double L, int32_t nconf, const int64_t *N_per_conf, const
                        const fep3m_options *opt, fep3m_ctx **out);
 
 /* Order subsequent calls on the given hipStream_t (NULL: null stream).
- * Inside an eager call the near-pair sum may run on a second stream that
- * the context owns (default priority), forked from and joined back into this
- * stream before the call's later work, so every output is ordered on this
- * stream when the call returns. */
+ * Inside a call (eager, or a graph replay) the near-pair sum may run on a
+ * second stream that the context owns (default priority), forked from and
+ * joined back into this stream before the call's later work, so every output
+ * is ordered on this stream when the call returns. */
 int fep3m_set_stream(fep3m_ctx *ctx, void *hip_stream);
 
 /* Phi[i] for every charge (eq. potential evaluated by the method). */
@@ -288,7 +288,7 @@ int64_t fep3m_stage_bytes(const fep3m_ctx *ctx, int32_t stage);
 /* Turn per-stage device timing on (1) or off (0) and clear the profile.
  * While on, every call records hipEvents on the context's stream around
  * each stage and each fine-level operator launch.  When the near-pair sum
- * runs on the second stream (eager calls, one wave per element) its time
+ * runs on the second stream (tuned calls, one wave per element) its time
  * overlaps that of ASSIGN, SOLVE and NEAR, which then include the slowdown
  * from sharing the GPU, and TOTAL is less than the sum of the stages. */
 int fep3m_set_profiling(fep3m_ctx *ctx, int32_t on);

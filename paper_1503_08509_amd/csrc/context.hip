@@ -185,12 +185,19 @@ struct fep3m_ctx {
   PairPlan plan;
   bool tuned = false;
   // The near-pair sum depends only on the sorted charges and is
-  // instruction-bound, the mesh solve is memory-bound: eagerly (tuning done,
-  // no capture) the pair pass runs on a second stream forked after the sort
-  // and joined before the interpolation, overlapping the assignment, solve
-  // and near field.  Default priority, like every stream here.
+  // instruction-bound, the mesh solve is memory-bound: once tuning is done the
+  // pair pass runs on a second stream forked after the sort and joined before
+  // the interpolation, overlapping the assignment, solve and near field.
+  // Under graph capture the fork and the join become graph dependencies.
+  // Default priority, like every stream here.
   hipStream_t pstream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  void side_stream() {   // created before any capture begins
+    if (pstream) return;
+    hip_check(hipStreamCreateWithFlags(&pstream, hipStreamNonBlocking), "pair stream");
+    hip_check(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming), "event");
+    hip_check(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming), "event");
+  }
   // graph mode: the whole evaluation captured once per set of argument
   // pointers on an internal stream, then replayed
   hipStream_t gstream = nullptr;
@@ -921,13 +928,13 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   stage_mark(FEP3M_PROF_SORT, false);
   // overlap only with one wave per element (short blocks that interleave
   // with the solve's); persistent waves would hold every CU for the pass
-  const bool overlap = !capturing && !(opt.autotune && !tuned && !prof.on) && plan.kind == 0;
+  // and only on meshes of at least 2^16 elements in all: below that the pass
+  // is too short to pay for the fork and the join (graph replays of 1000
+  // charges on 8^3 elements: 1.25 -> 1.39 ms)
+  const bool overlap = !(opt.autotune && !tuned && !prof.on) && plan.kind == 0 &&
+                       size_t(nb) * n * n * n >= (size_t(1) << 16);
   if (overlap) {
-    if (!pstream) {
-      hip_check(hipStreamCreateWithFlags(&pstream, hipStreamNonBlocking), "pair stream");
-      hip_check(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming), "event");
-      hip_check(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming), "event");
-    }
+    side_stream();
     hip_check(hipEventRecord(ev_fork, stream), "event");
     hip_check(hipStreamWaitEvent(pstream, ev_fork, 0), "wait");
     struct Restore { hipStream_t &s; hipStream_t to; ~Restore() { s = to; } } restore{stream, stream};
@@ -1214,6 +1221,7 @@ void fep3m_ctx::evaluate_graph(const double *x, const double *Qc, double *Phi, d
       if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
       if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
       graph_ready = false;
+      side_stream();
       hip_check(hipStreamBeginCapture(gstream, hipStreamCaptureModeThreadLocal), "begin capture");
       capturing = true;
       try {

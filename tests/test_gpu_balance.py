@@ -3,8 +3,8 @@ decompositions (one wave per element, persistent waves over a queue of
 target chunks) never changes results, on uniform and on strongly clustered
 inputs (up to a few hundred charges per element).  The tuned context is
 called twice: the first call tunes on one stream, the second runs the tuned
-plan (with one wave per element, the pair sum on the second stream beside the
-mesh solve)."""
+plan (with one wave per element on 64^3 elements, the pair sum on the second
+stream beside the mesh solve)."""
 import numpy as np
 import pytest
 
@@ -31,9 +31,9 @@ def _run(torch, x, Q, n, calls=1, **opts):
 
 @pytest.mark.parametrize("precision", [fp.PRECISION_FP64, fp.PRECISION_MIXED])
 def test_autotuned_pairs_identical_uniform(torch, precision):
-    x, Q = workloads.make("uniform-100k-n32")
-    a, sa = _run(torch, x, Q, 32, autotune=0, precision=precision)
-    b, sb = _run(torch, x, Q, 32, calls=2, autotune=1, precision=precision)
+    x, Q = workloads.make("uniform-1M-n64")
+    a, sa = _run(torch, x, Q, 64, autotune=0, precision=precision)
+    b, sb = _run(torch, x, Q, 64, calls=2, autotune=1, precision=precision)
     assert sa["pair_variant"] == 0 and sb["tune_ms_default"] > 0
     for k in ("Phi", "F", "dUdQ", "U"):
         np.testing.assert_array_equal(a[k], b[k])
