@@ -37,6 +37,37 @@ def test_matches_ewald_within_truncation_error(small):
     assert abs(o["U"] - E["U"]) < 1e-2 * abs(E["U"])
 
 
+def test_gauge_constant_pinned_against_ewald():
+    """The constant c that relates the zero-mean mesh gauge to tin-foil Ewald
+    (c = (2 pi / 3V) sum_j Q_j |delta_j|^2 for this screen) is pinned on
+    charges chosen so that it dominates the truncation error: positive
+    charges near element corners (|delta|^2 ~ 0.6 h^2), negative charges
+    near element centres.  Phi + c must match Ewald, while Phi alone and
+    Phi + 2c must miss by far more; the constant that best fits Ewald in the
+    least-squares sense (the mean difference) must equal c (Section 4
+    compares potentials up to an additive constant)."""
+    n, N = 8, 200
+    rng = np.random.default_rng(77)
+    e = rng.integers(0, n, size=(N, 3))
+    half = N // 2
+    u = np.empty((N, 3))
+    u[:half] = rng.choice([-1.0, 1.0], size=(half, 3)) * rng.uniform(0.40, 0.46, size=(half, 3))
+    u[half:] = rng.uniform(-0.05, 0.05, size=(half, 3))
+    x = (e + 0.5 + u) / n
+    Q = np.concatenate([np.ones(half), -np.ones(half)])
+    E = ewald.ewald(x, Q)
+    P = fep3m.Params(L=1.0, n=n)
+    o = fep3m.run(x, Q, P, stages=True)
+    c = fep3m.ewald_constant(o["u"], Q, P)
+    assert c > 1.0
+    good = _rel(o["Phi"] + c, E["Phi"])
+    assert good < 2e-3
+    assert _rel(o["Phi"], E["Phi"]) > 10 * good
+    assert _rel(o["Phi"] + 2 * c, E["Phi"]) > 10 * good
+    c_fit = float(np.mean(E["Phi"] - o["Phi"]))
+    assert abs(c_fit - c) < 0.01 * c
+
+
 def test_larger_near_block_is_more_accurate(small):
     """Truncation error falls with the near-block radius (R^-3 tail)."""
     x, Q = small
