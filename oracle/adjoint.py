@@ -77,14 +77,24 @@ def assemble(gE, n, p):
     return out
 
 
-def moment_adjoint(lam, gE, T, n, p, q, n_sr, elems=None):
-    """A[E][a] = 4 pi <lambda_E, G_a> - sum_D <g_{E+D}, T_a[D]> for the given
-    elements (default: all)."""
-    d = q - 2
-    g = screens.load_weights(p, q)
+def patch_values(v, p, n, elems, s):
+    """Nodal values of the global field on the support patch of each given
+    element (s elements per axis around it, (s p + 1)^3 nodes, x fastest)."""
+    idx = mesh.support_node_index(p, n, s)
+    ex, ey, ez = elems % n, (elems // n) % n, elems // (n * n)
+    out = v[idx[ez][:, :, None, None], idx[ey][:, None, :, None], idx[ex][:, None, None, :]]
+    return out.reshape(len(elems), -1)
+
+
+def moment_adjoint(lam, gE, T, n, p, q, n_sr, elems=None, support="one"):
+    """A[E][a] = 4 pi <lambda on the support of E, G_a> - sum_D <g_{E+D}, T_a[D]>
+    for the given elements (default: all)."""
+    d = screens.moment_degree(q, support)
+    sp = screens.span(support)
+    g = screens.load_weights(p, q, support)
     A_exp = screens.moment_exponents(d)
     E = np.arange(n**3) if elems is None else np.asarray(elems)
-    lamE = fep3m.element_phi(lam, p, n, E)
+    lamE = patch_values(lam, p, n, E, sp)
     Gs = np.stack([np.einsum("k,j,i->kji", g[az], g[ay], g[ax]).ravel() for (ax, ay, az) in A_exp])
     A1 = 4.0 * math.pi * lamE @ Gs.T
     A2 = np.zeros_like(A1)
@@ -135,18 +145,18 @@ def energy_forces(x, Q, params: fep3m.Params, targets=None):
     tgt = np.arange(len(Q)) if all_targets else np.asarray(targets)
     fw = fep3m.run(x, Q, params, targets=None if all_targets else tgt, stages=True)
     e, e_lin, u, C, phi = fw["e"], fw["e_lin"], fw["u"], fw["C"], fw["phi"]
-    T = tables.screen_tables(p, q, params.n_sr, params.B, params.table_bc)
+    T = tables.screen_tables(p, q, params.n_sr, params.B, params.table_bc, params.support)
     uel, inv = np.unique(e_lin[tgt], return_inverse=True)
     W = fep3m.element_phi(phi, p, n, uel) - fep3m.near_field(C, T, n, params.n_sr, uel)
     gE = element_deposit(e_lin, u, Q, n, p)
     G = mesh.project_compatible(assemble(gE, n, p), p, n)
     lam = mesh.solve_periodic(G, p, n)
     lam = lam - mesh.mean_value(lam, p, n)
-    A = moment_adjoint(lam, gE, T, n, p, q, params.n_sr, uel)
+    A = moment_adjoint(lam, gE, T, n, p, q, params.n_sr, uel, params.support)
     ut = u[tgt]
     Qt = Q[tgt]
     grad_v = basis_gradients(p, ut)                      # (T,3,M)
-    grad_a = monomial_gradients(ut, d)                   # (T,3,8)
+    grad_a = monomial_gradients(ut, d)                   # (T,3,(d+1)^3)
     mesh_grad = 0.5 * Qt[:, None] * (np.einsum("nkm,nm->nk", grad_v, W[inv])
                                      + np.einsum("nka,na->nk", grad_a, A[inv]))
     dUp = pair_forces(e, e_lin, u, Q, n, params.n_sr, tgt)

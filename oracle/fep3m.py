@@ -2,8 +2,9 @@
 
 Follows Algorithm 1 of the paper (charge assignment, mesh solve, evaluation
 of the smooth potential, short-range potential) for a periodic cube
-[0, L]^3 meshed by n^3 elements of size h = L/n, with the one-element
-polynomial screen of degree q and an order p = q + 2 mesh.
+[0, L]^3 meshed by n^3 elements of size h = L/n, with polynomial screens
+of degree q (one-element support, Section 5, or the 27-element support of
+Section 2.1) and an order p = q + 2 mesh.
 
 Element units (h = 1) are used throughout; physical potentials are the
 element-unit values divided by h.
@@ -37,6 +38,7 @@ class Params:
     n_sr: int = 3
     B: int | None = None
     table_bc: str = "exact"
+    support: str = "one"
 
     @property
     def p(self):
@@ -44,7 +46,7 @@ class Params:
 
     @property
     def d(self):
-        return self.q - 2
+        return screens.moment_degree(self.q, self.support)
 
     @property
     def h(self):
@@ -137,13 +139,28 @@ def pair_potential(e, e_lin, u, Q, n, n_sr, targets):
 
 
 def ewald_constant(u, Q, params: Params):
-    """Constant c with  Phi + c  comparable to the tin-foil Ewald potential:
-    c = (2 pi / 3 V) sum_j Q_j |delta_j|^2 (one-element q = 3 screen; the
-    screen's second moment about the element centre does not depend on the
-    charge offset).  Physical units."""
+    """Constant c with  Phi + c  comparable to the tin-foil Ewald potential.
+
+    For a neutral set of compact charge distributions the zero-mean
+    periodic potential differs from the tin-foil Ewald (image-sum) potential
+    by a constant set by the distributions' second moments.  Each point
+    charge minus its screen is such a distribution, with second moment
+    -s_j, s_j = int |xi - x_j|^2 rho_j(xi) dxi, so (with int phi = 0)
+
+        c = -(2 pi / 3 V) sum_j Q_j s_j .
+
+    Per axis the screen's second moment about its charge is
+    m2 - 2 delta m1 + delta^2 with m_k = sum_l delta^l int x^k r_l: for
+    d >= 2 it is zero (the x^2 moment is cancelled); for d = 1 it is
+    mu_0 - delta^2 (mu_0 = int x^2 r_0), and mu_0 drops out by neutrality,
+    leaving c = (2 pi / 3V) sum_j Q_j |delta_j|^2.  Physical units."""
     h = params.h
     V = params.L ** 3
-    return 2.0 * math.pi / (3.0 * V) * float(np.sum(Q * np.sum((u * h) ** 2, axis=1)))
+    m1c, m2c = screens.axis_moment_coefficients(params.q, params.support)
+    d = len(m1c) - 1
+    pw = u[:, :, None] ** np.arange(d + 1)[None, None, :]
+    s2 = np.sum(pw @ m2c - 2.0 * u * (pw @ m1c) + u**2, axis=1)   # per charge, element units
+    return -2.0 * math.pi / (3.0 * V) * float(np.sum(Q * s2)) * h * h
 
 
 def run(x, Q, params: Params, targets=None, stages=False):
@@ -157,11 +174,11 @@ def run(x, Q, params: Params, targets=None, stages=False):
         raise ValueError("mesh too coarse for the near block")
     e, e_lin, u = bin_particles(x, params.L, n)
     C = screens.element_moments(e_lin, u, Q, n ** 3, d)
-    b = mesh.load_vector(C, n, p, q)
+    b = mesh.load_vector(C, n, p, q, params.support)
     b = mesh.project_compatible(b, p, n)
     phi = mesh.solve_periodic(b, p, n)
     phi = phi - mesh.mean_value(phi, p, n)
-    T = tables.screen_tables(p, q, params.n_sr, params.B, params.table_bc)
+    T = tables.screen_tables(p, q, params.n_sr, params.B, params.table_bc, params.support)
     all_targets = targets is None
     targets = np.arange(len(Q)) if all_targets else np.asarray(targets)
     te = e_lin[targets]

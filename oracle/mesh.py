@@ -37,19 +37,33 @@ def element_node_index(p, n):
     return (p * np.arange(n)[:, None] + np.arange(p + 1)[None, :]) % (p * n)
 
 
-def load_vector(C, n, p, q):
-    d = q - 2
-    g = screens.load_weights(p, q)
+def support_node_index(p, n, s):
+    """Global 1-D node index of the support-local node k = 0 .. s p of the
+    screens of element e (s = 1 or 3 elements per axis, the support starting
+    (s - 1) / 2 elements below e): (p (e - (s-1)/2) + k) mod p n."""
+    e0 = np.arange(n) - (s - 1) // 2
+    return (p * e0[:, None] + np.arange(s * p + 1)[None, :]) % (p * n)
+
+
+def load_vector(C, n, p, q, support="one"):
+    """b_m = 4 pi sum_E sum_a C[E][a] int u_m R_a(. - xbar_E): every element
+    adds its screens' load to the nodes of its support."""
+    d = screens.moment_degree(q, support)
+    s = screens.span(support)
+    g = screens.load_weights(p, q, support)
     A = screens.moment_exponents(d)
     P = p * n
     Cg = C.reshape(n, n, n, len(A))                       # [ez, ey, ex, a]
     Gs = np.stack([np.einsum("k,j,i->kji", g[az], g[ay], g[ax]) for (ax, ay, az) in A])
     loc = 4.0 * math.pi * np.einsum("zyxa,akji->zyxkji", Cg, Gs, optimize=True)
     b = np.zeros((P, P, P))
-    idx = element_node_index(p, n)
-    for mz in range(p + 1):
-        for my in range(p + 1):
-            for mx in range(p + 1):
+    idx = support_node_index(p, n, s)
+    K = s * p + 1
+    # for a fixed local node (mz, my, mx) the global nodes of different
+    # elements are distinct, so the fancy-indexed += does not drop terms
+    for mz in range(K):
+        for my in range(K):
+            for mx in range(K):
                 b[np.ix_(idx[:, mz], idx[:, my], idx[:, mx])] += loc[:, :, :, mz, my, mx]
     return b
 

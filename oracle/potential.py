@@ -98,29 +98,54 @@ def gaussian_factor(coef, t, x):
     return out
 
 
+def _axis_factor(f, t, x):
+    """1-D factor of one axis: f is either the monomial coefficients of a
+    polynomial on the element [-1/2, 1/2], or a list of (offset, coefficients)
+    pieces, each a polynomial on the element centred at `offset` (in the local
+    coordinate of that element).  The factor of a sum of pieces is the sum of
+    their factors."""
+    if isinstance(f, list) and f and isinstance(f[0], tuple):
+        return sum(gaussian_factor(c, t, np.asarray(x) - off) for off, c in f)
+    return gaussian_factor(f, t, x)
+
+
 def separable_potential(coefs, pts, chunk=2048):
     """Potential of rho = f_0(x) f_1(y) f_2(z) at points pts (M,3).
-    coefs: three monomial coefficient arrays (one per axis)."""
+    coefs: one entry per axis, monomial coefficients of a polynomial on the
+    element or a list of (offset, coefficients) pieces (see _axis_factor)."""
     pts = np.asarray(pts, dtype=np.float64)
     t = np.exp(_TAU)
     wt = _TAU_W * t * (2.0 / _SQRT_PI)
     out = np.empty(len(pts))
     for s in range(0, len(pts), chunk):
         q = pts[s:s + chunk]
-        Fx = gaussian_factor(coefs[0], t, q[:, 0])
-        Fy = gaussian_factor(coefs[1], t, q[:, 1])
-        Fz = gaussian_factor(coefs[2], t, q[:, 2])
+        Fx = _axis_factor(coefs[0], t, q[:, 0])
+        Fy = _axis_factor(coefs[1], t, q[:, 1])
+        Fz = _axis_factor(coefs[2], t, q[:, 2])
         out[s:s + chunk] = wt @ (Fx * Fy * Fz)
     return out
 
 
-def dual_polynomials(q):
-    """Monomial coefficients of the one-element dual functions r_l on the
-    element (they are polynomials of degree q there)."""
+def dual_polynomials(q, support="one"):
+    """The dual functions r_l as polynomial pieces.  One-element support:
+    per l the monomial coefficients on the element (degree q).  27-element
+    support: per l a list of (offset, coefficients) for the elements at
+    offsets -1, 0, 1 (coefficients in the local coordinate of each)."""
     from . import screens
+    s = screens.span(support)
     xs = np.linspace(-0.5, 0.5, q + 3)
-    r = screens.dual_functions(q, xs)
-    return [P.polyfit(xs, r[:, l], q) for l in range(r.shape[1])]
+    d = screens.moment_degree(q, support)
+    if s == 1:
+        r = screens.dual_functions(q, xs, support)
+        return [P.polyfit(xs, r[:, l], q) for l in range(d + 1)]
+    out = [[] for _ in range(d + 1)]
+    for off in (-1, 0, 1):
+        # sample strictly inside the element so each piece is fitted alone
+        xi = 0.499 * np.linspace(-1.0, 1.0, q + 3)
+        r = screens.dual_functions(q, xi + off, support)
+        for l in range(d + 1):
+            out[l].append((float(off), P.polyfit(xi, r[:, l], q)))
+    return out
 
 
 def uniform_box_potential(lo, hi, x):

@@ -17,11 +17,21 @@ combined screen of all charges in an element E is
     sum_{j in E} Q_j rho_j = sum_a C[E][a] R_a ,  R_a = r_ax (x) r_ay (x) r_az,
     C[E][a] = sum_{j in E} Q_j delta_j^a   (a in {0..d}^3).
 
-Variant implemented: the one-element support of the Discussion (Section 5):
-only DOFs interior to the charge's element, i.e. the (q-1) interior order-q
-Lagrange functions per axis; d = q-2 moments per axis are cancelled.  With
-q = 3 this is the lowest order that cancels monopole and dipole, so the
-short-range potential decays like R^-3, while the mesh solve uses p = q+2.
+Two supports are implemented:
+
+  "27"   the paper's construction (Section 2.1): the order-q Lagrange
+         functions of the nodes in the closed element of the charge; the
+         functions of its face nodes reach into the neighbouring elements,
+         so the support is the 3^3 block of elements and the (q+1) functions
+         per axis cancel d = q moments (short-range decay R^-(q+2)).  The
+         order-q mesh nodes are equispaced in every element (the paper does
+         not name the node family; for q >= 2 the span depends on it).
+  "one"  the one-element variant of the Discussion (Section 5): only the
+         (q-1) functions interior to the element; d = q-2 moments are
+         cancelled (q = 3: monopole and dipole, R^-3).  Its span,
+         bubble * P_{q-2}, does not depend on the node family.
+
+The mesh solve uses order p = q + 2 in both cases (Section 2.2).
 
 Everything is in element units (h = 1, element = [-1/2, 1/2], delta = u).
 """
@@ -31,60 +41,129 @@ import numpy as np
 
 from . import fe1d
 
+SUPPORTS = ("one", "27")
+
+
+def moment_degree(q, support="one"):
+    """Moments cancelled per axis: d = q - 2 (one element) or q (27 elements)."""
+    return q - 2 if support == "one" else q
+
+
+def span(support="one"):
+    """Elements per axis covered by one element's screens."""
+    return 1 if support == "one" else 3
+
+
+def _check(q, support):
+    if support not in SUPPORTS:
+        raise ValueError(f"unknown screen support {support!r}")
+    if support == "one" and q < 2:
+        raise ValueError("one-element screens need q >= 2")
+    if support == "27" and q < 1:
+        raise ValueError("27-element screens need q >= 1")
+
 
 def interior_basis_nodes(q):
-    """Nodes of the order-q element (equispaced); the screen uses the
-    interior ones.  The span of the interior functions, bubble * P_{q-2},
+    """Nodes of the order-q element (equispaced); the one-element screen uses
+    the interior ones.  The span of the interior functions, bubble * P_{q-2},
     does not depend on this choice."""
     return np.linspace(-0.5, 0.5, q + 1)
 
 
-def moment_matrix_1d(q):
-    """mom[l, i] = int_{-1/2}^{1/2} x^l psi_i(x) dx for the q-1 interior
-    order-q basis functions psi_i, l = 0..q-2 (eq. moment1d, one-element
-    support)."""
-    nodes = interior_basis_nodes(q)
-    xq, wq = fe1d.gauss_legendre(q + 2)
-    psi = fe1d.lagrange(nodes, xq)[:, 1:q]      # interior functions only
-    d = q - 2
-    mom = np.array([[np.sum(wq * xq**l * psi[:, i]) for i in range(q - 1)]
-                    for l in range(d + 1)])
-    return mom
+def screen_basis(q, support, x):
+    """Values of the screen basis functions psi_i at points x (element units,
+    the charge's element is [-1/2, 1/2]): shape (len(x), number of functions).
 
-
-def dual_coefficients(q):
-    """Coefficients c[i, l] of the dual functions r_l = sum_i c[i,l] psi_i,
-    i.e. the inverse of the 1-D moment matrix."""
-    return np.linalg.inv(moment_matrix_1d(q))
-
-
-def dual_functions(q, x):
-    """r_l(x) for l = 0..d on the element (zero outside): shape (len(x), d+1)."""
+    one: the q-1 interior order-q Lagrange functions of the element.
+    27:  the q+1 order-q Lagrange functions of the nodes of the closed
+         element; the end functions continue into the element below (node
+         at -1/2, the upper node there) or above (node at +1/2, the lower
+         node there) and vanish beyond."""
+    _check(q, support)
     x = np.atleast_1d(np.asarray(x, dtype=np.float64))
     nodes = interior_basis_nodes(q)
-    psi = fe1d.lagrange(nodes, x)[:, 1:q]
-    r = psi @ dual_coefficients(q)
-    r[np.abs(x) > 0.5] = 0.0
-    return r
+    if support == "one":
+        out = fe1d.lagrange(nodes, x)[:, 1:q]
+        out[np.abs(x) > 0.5] = 0.0
+        return out
+    out = np.zeros((len(x), q + 1))
+    mid = np.abs(x) <= 0.5
+    out[mid] = fe1d.lagrange(nodes, x[mid])
+    lo = (x < -0.5) & (x >= -1.5)
+    out[lo, 0] = fe1d.lagrange(nodes, x[lo] + 1.0)[:, q]
+    hi = (x > 0.5) & (x <= 1.5)
+    out[hi, q] = fe1d.lagrange(nodes, x[hi] - 1.0)[:, 0]
+    return out
 
 
-def screen_1d(q, x, delta):
+def _element_rule(q, support, m):
+    """Gauss-Legendre points and weights covering the support element by
+    element (m points per element)."""
+    xq, wq = fe1d.gauss_legendre(m)
+    s = span(support)
+    offs = np.arange(s) - (s - 1) // 2
+    return (offs[:, None] + xq[None, :]).ravel(), np.tile(wq, s)
+
+
+def moment_matrix_1d(q, support="one"):
+    """mom[l, i] = int x^l psi_i(x) dx over the support for the screen basis
+    functions psi_i, l = 0..d (eq. moment1d)."""
+    d = moment_degree(q, support)
+    xs, ws = _element_rule(q, support, q + 3)
+    psi = screen_basis(q, support, xs)
+    return np.array([[np.sum(ws * xs**l * psi[:, i]) for i in range(psi.shape[1])]
+                     for l in range(d + 1)])
+
+
+def dual_coefficients(q, support="one"):
+    """Coefficients c[i, l] of the dual functions r_l = sum_i c[i,l] psi_i,
+    i.e. the inverse of the 1-D moment matrix."""
+    return np.linalg.inv(moment_matrix_1d(q, support))
+
+
+def dual_functions(q, x, support="one"):
+    """r_l(x) for l = 0..d (zero outside the support): shape (len(x), d+1)."""
+    x = np.atleast_1d(np.asarray(x, dtype=np.float64))
+    return screen_basis(q, support, x) @ dual_coefficients(q, support)
+
+
+def screen_1d(q, x, delta, support="one"):
     """1-D screen of a charge at offset delta: sum_l delta^l r_l(x)."""
-    r = dual_functions(q, x)
+    r = dual_functions(q, x, support)
     d = r.shape[1] - 1
     return r @ (np.asarray(delta) ** np.arange(d + 1))
 
 
-def load_weights(p, q):
-    """g[l, k] = int l_k^(p)(x) r_l(x) dx over the element, for the order-p
-    GLL basis l_k.  The load of element E on its node m = (mx, my, mz) is
-    4 pi sum_a C[E][a] g[ax,mx] g[ay,my] g[az,mz] (eq. defineassign with the
-    Galerkin right-hand side of eq. poisson)."""
+def load_weights(p, q, support="one"):
+    """g[l, k] = int l_k^(p)(x) r_l(x) dx for the order-p GLL basis functions
+    l_k of the support's nodes: k = 0 .. s p along one axis (s = 1 or 3
+    elements; node s p is the upper end), the first at the lower end of the
+    support.  The load of element E on the node with support-local index
+    (kx, ky, kz) is 4 pi sum_a C[E][a] g[ax,kx] g[ay,ky] g[az,kz] (eq.
+    defineassign with the Galerkin right-hand side of eq. poisson)."""
+    s = span(support)
     nodes_p = fe1d.gll_nodes(p)
-    xq, wq = fe1d.gauss_legendre(p + 1)   # degree p + q <= 2p + 1
-    lp = fe1d.lagrange(nodes_p, xq)
-    r = dual_functions(q, xq)
-    return (r * wq[:, None]).T @ lp
+    xq, wq = fe1d.gauss_legendre(p + 1)   # degree p + q <= 2p + 1 per element
+    lp = fe1d.lagrange(nodes_p, xq)        # (Q, p+1)
+    d = moment_degree(q, support)
+    g = np.zeros((d + 1, s * p + 1))
+    for e in range(s):
+        off = e - (s - 1) // 2
+        r = dual_functions(q, xq + off, support)
+        g[:, e * p:e * p + p + 1] += (r * wq[:, None]).T @ lp
+    return g
+
+
+def axis_moment_coefficients(q, support="one"):
+    """nu[l] = int x r_l(x) dx and mu[l] = int x^2 r_l(x) dx: the 1-D screen
+    rho_1 = sum_l delta^l r_l has first and second moments (about the
+    element centre) sum_l delta^l nu[l] and sum_l delta^l mu[l]."""
+    d = moment_degree(q, support)
+    xs, ws = _element_rule(q, support, q + 3)
+    r = dual_functions(q, xs, support)
+    nu = np.array([np.sum(ws * xs * r[:, l]) for l in range(d + 1)])
+    mu = np.array([np.sum(ws * xs**2 * r[:, l]) for l in range(d + 1)])
+    return nu, mu
 
 
 def moment_exponents(d):
@@ -107,17 +186,15 @@ def element_moments(e_lin, u, Q, n_elem, d):
     return C
 
 
-def screen_3d_dense(q, delta):
-    """Screen coefficients from the full 3-D moment system (eq. momentmatrix)
-    for the one-element support: unknowns are the (q-1)^3 products of
-    interior basis functions, rows the moments (l,m,n) <= (d,d,d) about the
-    charge.  Used only to check that the separable route gives the same
-    screen.  Returns c (ordered x fastest)."""
-    d = q - 2
-    nodes = interior_basis_nodes(q)
-    xq, wq = fe1d.gauss_legendre(q + 4)
-    psi = fe1d.lagrange(nodes, xq)[:, 1:q]
-    nb = q - 1
+def screen_3d_dense(q, delta, support="one"):
+    """Screen coefficients from the full 3-D moment system (eq. momentmatrix):
+    unknowns are the products of the 1-D screen basis functions, rows the
+    moments (l,m,n) <= (d,d,d) about the charge.  Used only to check that the
+    separable route gives the same screen.  Returns c (ordered x fastest)."""
+    d = moment_degree(q, support)
+    xq, wq = _element_rule(q, support, q + 4)
+    psi = screen_basis(q, support, xq)
+    nb = psi.shape[1]
     A = moment_exponents(d)
     rows = []
     for (l, m, nn) in A:

@@ -12,7 +12,9 @@ Here the basis screens are the dual functions R_a = r_ax (x) r_ay (x) r_az
 (a in {0..d}^3), so the combined screen of an element with moments C[E][a]
 has near-field potential  sum_a C[E][a] T_a .  For each a:
 
-  * domain: B^3 unit elements centred on the source element (B odd),
+  * domain: B^3 unit elements centred on the source element (B odd); the
+    screen covers the source element (one-element support) or the 3^3
+    elements around it (27-element support),
   * weak form  K w = 4 pi G_a  (G_a = int u_m R_a),
   * Dirichlet data on the outer nodes: the exact free-space potential of R_a
     (all multipole terms, the Remark's boundary condition taken to all
@@ -43,9 +45,9 @@ def _potential_grid(coef3, coords):
     coefficients coef3 on the full tensor grid coords^3 -> [z, y, x]."""
     t = np.exp(potential._TAU)
     wt = potential._TAU_W * t * (2.0 / math.sqrt(math.pi))
-    Fx = potential.gaussian_factor(coef3[0], t, coords)
-    Fy = potential.gaussian_factor(coef3[1], t, coords)
-    Fz = potential.gaussian_factor(coef3[2], t, coords)
+    Fx = potential._axis_factor(coef3[0], t, coords)
+    Fy = potential._axis_factor(coef3[1], t, coords)
+    Fz = potential._axis_factor(coef3[2], t, coords)
     T, n = Fx.shape
     ZY = ((Fz * wt[:, None])[:, :, None] * Fy[:, None, :]).reshape(T, n * n)
     return (ZY.T @ Fx).reshape(n, n, n)
@@ -59,20 +61,21 @@ def node_coords(p, B):
     return np.array(xs)
 
 
-def screen_tables(p=5, q=3, n_sr=3, B=None, bc="exact"):
+def screen_tables(p=5, q=3, n_sr=3, B=None, bc="exact", support="one"):
     B = 2 * n_sr + 1 + 8 if B is None else B
-    key = (p, q, n_sr, B, bc)
+    key = (p, q, n_sr, B, bc, support)
     if key in _CACHE:
         return _CACHE[key]
     if B % 2 == 0 or B < 2 * n_sr + 3:
         raise ValueError("table box must be odd and larger than the near block")
-    d = q - 2
+    d = screens.moment_degree(q, support)
+    sp = screens.span(support)
     c = (B - 1) // 2
     S = 2 * n_sr + 1
     nn = B * p + 1
     coords = node_coords(p, B)
-    polys = potential.dual_polynomials(q)
-    g = screens.load_weights(p, q)                    # (d+1, p+1)
+    polys = potential.dual_polynomials(q, support)
+    g = screens.load_weights(p, q, support)           # (d+1, sp p + 1)
     A = screens.moment_exponents(d)
     Kd, Md = fe1d.dirichlet_matrices(p, B)
     inner = np.arange(1, nn - 1)
@@ -88,7 +91,8 @@ def screen_tables(p=5, q=3, n_sr=3, B=None, bc="exact"):
             w = exact
         else:
             b = np.zeros((nn, nn, nn))
-            sl = slice(p * c, p * c + p + 1)
+            k0 = p * (c - (sp - 1) // 2)
+            sl = slice(k0, k0 + sp * p + 1)
             b[sl, sl, sl] = 4.0 * math.pi * np.einsum("k,j,i->kji", g[az], g[ay], g[ax])
             gext = exact.copy()
             gext[1:-1, 1:-1, 1:-1] = 0.0
