@@ -85,6 +85,16 @@ enum {
                             (the achieved residual is still measured).  */
 };
 
+/* Screen supports (Section 2.1 and the Discussion, Section 5). */
+enum {
+  FEP3M_SUPPORT_ONE = 0,  /* screens interior to the charge's element: degree q
+                             cancels d = q - 2 moments per axis (R^-q decay) */
+  FEP3M_SUPPORT_27 = 1    /* the order-q Lagrange functions of the nodes of the
+                             closed element (equispaced order-q nodes): support
+                             of 3^3 elements, d = q moments per axis cancelled
+                             (R^-(q+2) decay)                                 */
+};
+
 /* Evaluation of the near-screen field and of its transpose in the moment
  * adjoint (Section 3, eq. sc with the Remark's tables).  Both are periodic
  * convolutions over the element lattice with the table as the kernel. */
@@ -310,12 +320,16 @@ const char *fep3m_status_string(int status);
 /* The create-time near-field tables on the host (no device needed), for
  * inspection and tests: order-p Dirichlet FE solutions of the basis screens
  * on a box of `box` elements (Remark, Section 4), element units, layout as
- * debug stage 7: T[a][D][m], a = ax + 2 ay + 4 az, D the target-minus-source
- * element offset in [-n_sr, n_sr]^3 (x fastest), m the node (x fastest).
- * out (host memory, caller-owned) must hold out_len >= 8 (2 n_sr + 1)^3
- * (q + 3)^3 doubles.  Returns FEP3M_ERR_ARG for q != 3, n_sr outside 1..3,
- * an even box or box <= 2 n_sr + 1, or a short buffer. */
-int fep3m_host_tables(int32_t q, int32_t n_sr, int32_t box, double *out, int64_t out_len);
+ * debug stage 7: T[a][D][m], a = ax + nl ay + nl^2 az with nl = d + 1 moments
+ * per axis (d = q - 2 for support FEP3M_SUPPORT_ONE, q for
+ * FEP3M_SUPPORT_27), D the target-minus-source element offset in
+ * [-n_sr, n_sr]^3 (x fastest), m the node of the order p = q + 2 element
+ * (x fastest).  out (host memory, caller-owned) must hold
+ * out_len >= nl^3 (2 n_sr + 1)^3 (q + 3)^3 doubles.  Returns FEP3M_ERR_ARG
+ * for a degree outside 2..6 (one element) or 1..4 (27 elements), an unknown
+ * support, n_sr outside 1..3, an even box or box <= 2 n_sr + 1, or a short
+ * buffer. */
+int fep3m_host_tables(int32_t q, int32_t support, int32_t n_sr, int32_t box, double *out, int64_t out_len);
 
 #ifdef __cplusplus
 }

@@ -104,7 +104,7 @@ def lib():
         L.fep3m_status_string.restype = ctypes.c_char_p
         L.fep3m_set_profiling.argtypes = [vp, i32]
         L.fep3m_get_profile.argtypes = [vp, ctypes.POINTER(Profile)]
-        L.fep3m_host_tables.argtypes = [i32, i32, i32, ctypes.POINTER(dp), i64]
+        L.fep3m_host_tables.argtypes = [i32, i32, i32, i32, ctypes.POINTER(dp), i64]
         _lib = L
     return _lib
 
@@ -115,16 +115,23 @@ def default_options():
     return o
 
 
-def host_tables(q=3, n_sr=3, box=None):
-    """Near-field tables from the library's create-time precompute (host)."""
+SUPPORT_ONE, SUPPORT_27 = 0, 1
+_SUPPORTS = {"one": SUPPORT_ONE, "27": SUPPORT_27, SUPPORT_ONE: SUPPORT_ONE, SUPPORT_27: SUPPORT_27}
+
+
+def host_tables(q=3, n_sr=3, box=None, support="one"):
+    """Near-field tables from the library's create-time precompute (host):
+    shape (nl^3, (2 n_sr + 1)^3, (q + 3)^3), nl moments per axis."""
     box = 2 * n_sr + 9 if box is None else box
+    sup = _SUPPORTS[support]
     p = q + 2
+    nl = q + 1 if sup == SUPPORT_27 else q - 1
     S = 2 * n_sr + 1
-    out = np.zeros(8 * S**3 * (p + 1) ** 3)
-    st = lib().fep3m_host_tables(q, n_sr, box, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size)
+    out = np.zeros(nl**3 * S**3 * (p + 1) ** 3)
+    st = lib().fep3m_host_tables(q, sup, n_sr, box, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size)
     if st != OK:
         raise FEP3MError(st, lib().fep3m_status_string(st).decode())
-    return out.reshape(8, S**3, (p + 1) ** 3)
+    return out.reshape(nl**3, S**3, (p + 1) ** 3)
 
 
 class Context:

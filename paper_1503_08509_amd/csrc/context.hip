@@ -336,7 +336,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   h = L / n;
   mixed = o.precision == FEP3M_PRECISION_MIXED;
 
-  Screen1D scr = make_screen(q);
+  Screen1D scr = make_screen(q, FEP3M_SUPPORT_ONE);
   compute_tables(p, scr, nsr, B, T_host);
   Mat g = load_weights(p, scr);
   Mat ke, me;
@@ -1533,14 +1533,18 @@ const char *fep3m_status_string(int status) {
   }
 }
 
-int fep3m_host_tables(int32_t q, int32_t n_sr, int32_t box, double *out, int64_t out_len) {
-  if (!out || q != 3 || n_sr < 1 || n_sr > 3 || box % 2 == 0 || box < 2 * n_sr + 3 || box > 41) return FEP3M_ERR_ARG;
-  const int p = q + 2, S = 2 * n_sr + 1;
-  const int64_t need = int64_t(8) * S * S * S * (p + 1) * (p + 1) * (p + 1);
+int fep3m_host_tables(int32_t q, int32_t support, int32_t n_sr, int32_t box, double *out, int64_t out_len) {
+  if (!out || (support != FEP3M_SUPPORT_ONE && support != FEP3M_SUPPORT_27) || n_sr < 1 || n_sr > 3 ||
+      box % 2 == 0 || box < 2 * n_sr + 3 || box > 41)
+    return FEP3M_ERR_ARG;
+  if (support == FEP3M_SUPPORT_ONE ? (q < 2 || q > 6) : (q < 1 || q > 4)) return FEP3M_ERR_ARG;
+  const Screen1D scr = make_screen(q, support);
+  const int p = q + 2, S = 2 * n_sr + 1, nl = scr.d + 1;
+  const int64_t need = int64_t(nl) * nl * nl * S * S * S * (p + 1) * (p + 1) * (p + 1);
   if (out_len < need) return FEP3M_ERR_ARG;
   try {
     Vec T;
-    compute_tables(p, make_screen(q), n_sr, box, T);
+    compute_tables(p, scr, n_sr, box, T);
     std::memcpy(out, T.data(), size_t(need) * sizeof(double));
   } catch (...) {
     return FEP3M_ERR_ARG;

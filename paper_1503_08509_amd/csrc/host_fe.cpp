@@ -226,54 +226,112 @@ Mat inverse(const Mat &A0) {
   return I;
 }
 
-double Screen1D::eval(int l, double x) const {
-  if (x < -0.5 || x > 0.5) return 0.0;
-  double bub = 0.25 - x * x, s = 0.0, xp = 1.0;
-  for (int j = 0; j <= d; ++j) { s += coef(j, l) * xp; xp *= x; }
-  return bub * s;
+namespace {
+
+// int_{-1/2}^{1/2} (t + o)^m c(t) dt for the polynomial c of degree deg
+// (ascending coefficients): (t + o)^m expanded binomially, t^k integrated
+// exactly.
+double moment_exact(const double *c, int deg, int m, double o) {
+  auto tint = [](int k) { return (k % 2) ? 0.0 : 2.0 * std::pow(0.5, k + 1) / (k + 1); };
+  double s = 0.0, binom = 1.0;
+  for (int j = 0; j <= m; ++j) {   // (t + o)^m = sum_j C(m, j) t^j o^(m - j)
+    double tj = 0.0;
+    for (int k = 0; k <= deg; ++k) tj += c[k] * tint(j + k);
+    s += binom * std::pow(o, m - j) * tj;
+    binom = binom * (m - j) / (j + 1);
+  }
+  return s;
 }
 
-Vec Screen1D::monomial(int l) const {
-  Vec c(d + 3, 0.0);
-  for (int j = 0; j <= d; ++j) {
-    c[j] += 0.25 * coef(j, l);
-    c[j + 2] -= coef(j, l);
+// Monomial coefficients of the Lagrange polynomial of nodes[k].
+Vec lagrange_monomial(const Vec &nodes, int k) {
+  Vec c(1, 1.0);
+  for (size_t j = 0; j < nodes.size(); ++j) {
+    if (int(j) == k) continue;
+    const double den = nodes[k] - nodes[j];
+    Vec nc(c.size() + 1, 0.0);
+    for (size_t i = 0; i < c.size(); ++i) {
+      nc[i] -= c[i] * nodes[j] / den;
+      nc[i + 1] += c[i] / den;
+    }
+    c = nc;
   }
   return c;
 }
 
-Screen1D make_screen(int q) {
-  // Moment system of eq. moment1d in the basis bubble * x^j: W(m, j) =
-  // int x^m bubble x^j; the dual coefficients are its inverse.
+}  // namespace
+
+double Screen1D::eval_piece(int s, int l, double t) const {
+  const double *c = piece(s, l);
+  double v = 0.0;
+  for (int k = q; k >= 0; --k) v = v * t + c[k];
+  return v;
+}
+
+double Screen1D::eval(int l, double x) const {
+  const int h = (span - 1) / 2;
+  const double lo = -0.5 - h, hi = 0.5 + h;
+  if (x < lo || x > hi) return 0.0;
+  int s = int(std::floor(x + 0.5)) + h;
+  if (s >= span) s = span - 1;
+  return eval_piece(s, l, x - (s - h));
+}
+
+Screen1D make_screen(int q, int support) {
+  // The screen basis functions as monomial pieces, their moment matrix of
+  // eq. moment1d by exact monomial integrals, and the dual functions from
+  // its inverse.
   Screen1D s;
   s.q = q;
-  s.d = q - 2;
-  const int nb = s.d + 1;
-  Vec xq, wq;
-  gauss_legendre(q + 2, xq, wq);
+  s.support = support;
+  s.span = support ? 3 : 1;
+  s.d = support ? q : q - 2;
+  const int nb = s.d + 1, nk = q + 1;
+  // basis[i][piece] coefficients (degree q), piece 0..span-1
+  std::vector<std::vector<Vec>> basis(nb, std::vector<Vec>(s.span, Vec(nk, 0.0)));
+  if (!support) {
+    for (int j = 0; j < nb; ++j) {       // bubble * t^j = (1/4 - t^2) t^j
+      basis[j][0][j] += 0.25;
+      basis[j][0][j + 2] -= 1.0;
+    }
+  } else {
+    Vec nodes(q + 1);
+    for (int k = 0; k <= q; ++k) nodes[k] = -0.5 + double(k) / q;
+    for (int i = 0; i <= q; ++i) {
+      basis[i][1] = lagrange_monomial(nodes, i);
+      if (i == 0) basis[i][0] = lagrange_monomial(nodes, q);   // the node is the upper end of the element below
+      if (i == q) basis[i][2] = lagrange_monomial(nodes, 0);   // ... and the lower end of the element above
+    }
+  }
+  const int h = (s.span - 1) / 2;
   Mat W(nb, nb);
   for (int m = 0; m < nb; ++m)
-    for (int j = 0; j < nb; ++j) {
+    for (int i = 0; i < nb; ++i) {
       double t = 0.0;
-      for (size_t i = 0; i < xq.size(); ++i)
-        t += wq[i] * std::pow(xq[i], m) * (0.25 - xq[i] * xq[i]) * std::pow(xq[i], j);
-      W(m, j) = t;
+      for (int pz = 0; pz < s.span; ++pz) t += moment_exact(basis[i][pz].data(), q, m, double(pz - h));
+      W(m, i) = t;
     }
-  s.coef = inverse(W);
+  Mat Wi = inverse(W);   // r_l = sum_i Wi(i, l) basis_i
+  s.pc.assign(size_t(s.span) * nb * nk, 0.0);
+  for (int pz = 0; pz < s.span; ++pz)
+    for (int l = 0; l < nb; ++l)
+      for (int i = 0; i < nb; ++i)
+        for (int k = 0; k < nk; ++k) s.pc[(size_t(pz) * nb + l) * nk + k] += Wi(i, l) * basis[i][pz][k];
   return s;
 }
 
 Mat load_weights(int p, const Screen1D &s) {
   Vec nodes = gll_nodes(p), xq, wq, l(p + 1);
-  gauss_legendre(p + 1, xq, wq);  // degree p + q <= 2p + 1
-  Mat g(s.d + 1, p + 1);
-  for (size_t iq = 0; iq < xq.size(); ++iq) {
-    lagrange(nodes, xq[iq], l.data(), nullptr);
-    for (int ll = 0; ll <= s.d; ++ll) {
-      double r = s.eval(ll, xq[iq]);
-      for (int k = 0; k <= p; ++k) g(ll, k) += wq[iq] * r * l[k];
+  gauss_legendre(p + 1, xq, wq);  // degree p + q <= 2p + 1 per element
+  Mat g(s.d + 1, s.span * p + 1);
+  for (int pz = 0; pz < s.span; ++pz)
+    for (size_t iq = 0; iq < xq.size(); ++iq) {
+      lagrange(nodes, xq[iq], l.data(), nullptr);
+      for (int ll = 0; ll <= s.d; ++ll) {
+        const double r = s.eval_piece(pz, ll, xq[iq]);
+        for (int k = 0; k <= p; ++k) g(ll, pz * p + k) += wq[iq] * r * l[k];
+      }
     }
-  }
   return g;
 }
 

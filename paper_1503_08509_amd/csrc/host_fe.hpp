@@ -39,20 +39,33 @@ void sym_gen_eig(const Mat &K, const Mat &M, Vec &w, Mat &V);
 // Dense inverse by Gauss-Jordan with partial pivoting.
 Mat inverse(const Mat &A);
 
-// One-element polynomial screen of degree q (moment degree d = q - 2):
-// dual functions r_l, l = 0..d, on the element, with int x^m r_l = [m == l].
-// The interior order-q Lagrange functions span bubble * P_d with
-// bubble = 1/4 - x^2, so r_l is represented in that basis.
+// Polynomial screens of degree q (Section 2.1): per axis the dual functions
+// r_l, l = 0..d, of the screen space, with int x^m r_l = [m == l] for
+// m <= d, so that the combined screen of an element's charges is
+// sum_a C[E][a] r_ax (x) r_ay (x) r_az with C[E][a] = sum Q u^a.
+//   support 0, one element (Section 5): the order-q functions interior to the
+//     element, span bubble * P_{q-2}; d = q - 2, one piece.
+//   support 1, 27 elements (Section 2.1): the order-q Lagrange functions of
+//     the nodes of the closed element on equispaced order-q nodes; the face
+//     functions reach one element further, so the support spans 3 elements
+//     per axis; d = q, pieces on the elements at offsets -1, 0, 1.
+// Each piece is a polynomial of degree q in the local coordinate t in
+// [-1/2, 1/2] of its element.
 struct Screen1D {
-  int q = 3, d = 1;
-  Mat coef;                  // coef(j, l): r_l = sum_j coef(j,l) * bubble * x^j
+  int q = 3, d = 1, support = 0;
+  int span = 1;              // elements per axis of the support
+  Vec pc;                    // pc[(s (d + 1) + l) (q + 1) + k]: t^k coefficient of r_l on piece s
+  const double *piece(int s, int l) const { return &pc[(size_t(s) * (d + 1) + l) * (q + 1)]; }
+  // r_l at x, element units from the centre of the charge's element
   double eval(int l, double x) const;
-  // Monomial coefficients (ascending) of r_l on the element, degree d + 2.
-  Vec monomial(int l) const;
+  // r_l on piece s at local coordinate t
+  double eval_piece(int s, int l, double t) const;
 };
-Screen1D make_screen(int q);
+Screen1D make_screen(int q, int support = 0);
 
-// g(l, k) = int l_k^(p) r_l over the element (load weights), (d+1) x (p+1).
+// g(l, j) = int phi_j r_l over the support (load weights), (d + 1) x
+// (span p + 1): phi_j the order-p GLL Lagrange function of the support's
+// node j, j = 0 at the lower end of the support.
 Mat load_weights(int p, const Screen1D &s);
 
 // Assembled 1-D matrices of `ne` unit elements, order p.

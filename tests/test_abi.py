@@ -125,10 +125,17 @@ def test_energy_function_is_an_autograd_function():
     assert issubclass(fp.FEP3MEnergy, torch.autograd.Function)
 
 
-@pytest.mark.parametrize("n_sr,box", [(3, 15), (2, 11), (1, 9)])
-def test_host_tables_match_oracle(n_sr, box):
-    T = fp.host_tables(3, n_sr, box)
-    To = tables.screen_tables(5, 3, n_sr, B=box)
+@pytest.mark.parametrize("q,support,n_sr,box", [(3, "one", 3, 15), (3, "one", 2, 11), (3, "one", 1, 9),
+                                                (4, "one", 1, 9), (1, "27", 3, 15), (2, "27", 1, 9),
+                                                (3, "27", 1, 9)])
+def test_host_tables_match_oracle(q, support, n_sr, box):
+    """The library's tables (screens by exact monomial integrals, boundary data
+    by tensor Gauss quadrature over the screen's elements, boundary coupling
+    assembled over the shell of elements) equal the oracle's (screens by
+    quadrature of Lagrange values, boundary data by the Gaussian identity,
+    global Kronecker lifting)."""
+    T = fp.host_tables(q, n_sr, box, support)
+    To = tables.screen_tables(q + 2, q, n_sr, B=box, support=support)
     assert T.shape == To.shape
     assert np.abs(T - To).max() < 1e-12 * np.abs(To).max()
 
@@ -142,7 +149,7 @@ def test_host_tables_reflection_symmetric(n_sr):
     property."""
     S = 2 * n_sr + 1
     out = np.zeros(8 * S**3 * 216)
-    assert fp.lib().fep3m_host_tables(3, n_sr, 2 * n_sr + 9,
+    assert fp.lib().fep3m_host_tables(3, 0, n_sr, 2 * n_sr + 9,
                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size) == fp.OK
     T = out.reshape(8, S, S, S, 6, 6, 6)   # [a][Dz][Dy][Dx][mz][my][mx], a = ax + 2 ay + 4 az
     for r in range(1, 8):
@@ -160,6 +167,8 @@ def test_host_tables_reflection_symmetric(n_sr):
 def test_host_tables_argument_checks():
     out = np.zeros(10)
     ptr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    assert fp.lib().fep3m_host_tables(3, 3, 15, ptr, 10) == fp.ERR_ARG      # short buffer
-    assert fp.lib().fep3m_host_tables(3, 3, 14, ptr, 10**7) == fp.ERR_ARG   # even box
-    assert fp.lib().fep3m_host_tables(4, 3, 15, ptr, 10**7) == fp.ERR_ARG   # degree
+    assert fp.lib().fep3m_host_tables(3, 0, 3, 15, ptr, 10) == fp.ERR_ARG      # short buffer
+    assert fp.lib().fep3m_host_tables(3, 0, 3, 14, ptr, 10**7) == fp.ERR_ARG   # even box
+    assert fp.lib().fep3m_host_tables(7, 0, 3, 15, ptr, 10**7) == fp.ERR_ARG   # degree
+    assert fp.lib().fep3m_host_tables(5, 1, 3, 15, ptr, 10**7) == fp.ERR_ARG   # degree (27 elements)
+    assert fp.lib().fep3m_host_tables(3, 2, 3, 15, ptr, 10**7) == fp.ERR_ARG   # support
