@@ -163,7 +163,7 @@ def energy_forces(x, Q, params: fep3m.Params, targets=None):
     F = -(dUp + mesh_grad) / h**2
     mono = np.prod(ut[:, None, :] ** screens.moment_exponents(d)[None, :, :], axis=2)
     dUdQ = (fw["Phi_p"] * h + 0.5 * fw["Phi_m"] * h + 0.5 * np.sum(A[inv] * mono, axis=1)) / h
-    out = {"Phi": fw["Phi"], "F": F, "dUdQ": dUdQ, "A": A, "lam": lam, "gE": gE}
+    out = {"Phi": fw["Phi"], "F": F, "dUdQ": dUdQ, "A": A, "lam": lam, "gE": gE, "phi": phi}
     if all_targets:
         out["U"] = fw["U"]
     return out
