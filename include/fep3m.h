@@ -171,6 +171,7 @@ typedef struct {
   double  tune_ms_default;   /* device time of one wave per element when tuned    */
   int64_t graph_replays;     /* evaluations served by a graph replay (use_graph)  */
   int32_t near_fft;          /* 1: the near field and its transpose run as FFTs   */
+  int64_t device_bytes;      /* device memory the context holds                   */
 } fep3m_stats;
 
 /* Profile slots: stages of one call, the fine-level operator launches, and
@@ -235,6 +236,27 @@ int fep3m_create_ex(double L, int64_t N, const int32_t dims[3], int32_t q,
  * nconf = 1 case.  Errors as fep3m_create_ex. */
 int fep3m_create_batch(double L, int32_t nconf, const int64_t *N_per_conf, const int32_t dims[3], int32_t q,
                        const fep3m_options *opt, fep3m_ctx **out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): fep3m_create_ex
+ * for one configuration with every device buffer placed in a static device
+ * array of 192 MiB that the library holds on each GPU it runs on until the
+ * process ends (enough for 16^3 elements and about 10^5 charges; the
+ * context's need is fep3m_stats.device_bytes of a fep3m_create_ex context).
+ * No hipMalloc, hipFree, pinned host allocation, stream, event or library
+ * handle is created, at create or in any evaluation call on the context;
+ * host-side setup uses ordinary heap memory.  Evaluation calls behave as on
+ * a fep3m_create_ex context with autotune = 0 (one wave per element for the
+ * pair sum, on the caller's stream only).  One static context per device at
+ * a time: the array keeps the last context's contents and is cleared at
+ * create; while a static context lives, fep3m_create_static on the same
+ * device returns FEP3M_ERR_ARG, and fep3m_destroy releases it.  Calls on
+ * static contexts of different threads must not overlap.  Errors:
+ * FEP3M_ERR_ARG when the context needs more than the array holds (the
+ * message names the buffer) or the array is held, FEP3M_ERR_UNSUPPORTED for
+ * use_graph = 1 or solver = FEP3M_SOLVER_FDM, else as fep3m_create_ex. */
+int fep3m_create_static(double L, int64_t N, const int32_t dims[3], int32_t q, const fep3m_options *opt,
+                        fep3m_ctx **out);
 
 /* Order subsequent calls on the given hipStream_t (NULL: null stream).
  * Inside a call (eager, or a graph replay) the near-pair sum may run on a

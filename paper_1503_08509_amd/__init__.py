@@ -52,7 +52,8 @@ class Stats(ctypes.Structure):
                 ("generation", ctypes.c_int64), ("pair_variant", ctypes.c_int32),
                 ("pair_item_targets", ctypes.c_int32), ("pair_waves", ctypes.c_int32),
                 ("tune_ms_best", ctypes.c_double), ("tune_ms_default", ctypes.c_double),
-                ("graph_replays", ctypes.c_int64), ("near_fft", ctypes.c_int32)]
+                ("graph_replays", ctypes.c_int64), ("near_fft", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64)]
 
 
 PROF_SLOTS = ["sort", "assign", "solve", "near", "pair", "interp", "fine_apply", "total",
@@ -86,6 +87,8 @@ def lib():
         L.fep3m_create_ex.argtypes = [dp, i64, ctypes.POINTER(i32), i32, ctypes.POINTER(Options), ctypes.POINTER(vp)]
         L.fep3m_create_batch.argtypes = [dp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32), i32,
                                          ctypes.POINTER(Options), ctypes.POINTER(vp)]
+        L.fep3m_create_static.argtypes = [dp, i64, ctypes.POINTER(i32), i32, ctypes.POINTER(Options),
+                                          ctypes.POINTER(vp)]
         L.fep3m_set_stream.argtypes = [vp, vp]
         L.fep3m_potential.argtypes = [vp, vp, vp, vp]
         L.fep3m_energy.argtypes = [vp, vp, vp, vp, vp]
@@ -142,7 +145,9 @@ class Context:
     the configurations in order, and energies come back one per
     configuration)."""
 
-    def __init__(self, L, N, n, q=3, **opts):
+    def __init__(self, L, N, n, q=3, static=False, **opts):
+        """static=True: fep3m_create_static (one configuration; device buffers
+        in the library's static storage, nothing allocated)."""
         import torch  # device memory and streams only
 
         self._torch = torch
@@ -155,7 +160,11 @@ class Context:
         h = ctypes.c_void_p()
         self.batch = not np.isscalar(N)
         counts = [int(v) for v in N] if self.batch else [int(N)]
-        if self.batch:
+        if static and self.batch:
+            raise ValueError("static contexts hold one configuration")
+        if static:
+            st = lib().fep3m_create_static(float(L), counts[0], dims, int(q), ctypes.byref(o), ctypes.byref(h))
+        elif self.batch:
             arr = (ctypes.c_int64 * len(counts))(*counts)
             st = lib().fep3m_create_batch(float(L), len(counts), arr, dims, int(q), ctypes.byref(o), ctypes.byref(h))
         else:

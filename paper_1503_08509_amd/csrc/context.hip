@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -88,6 +89,21 @@ template <> const LevelOpF &MGLevel::oper<float>() const { return opf; }
 
 }  // namespace
 
+// Device storage of contexts made by fep3m_create_static: one array per
+// GPU the library runs on, held until the process ends.  Its device address
+// comes from hipGetSymbolAddress (the array's name is only a host-side
+// stand-in), taken once per device with that device current and kept in
+// g_static_ptr; one static context may hold a device's array at a time.
+constexpr size_t kStaticBytes = size_t(192) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+bool g_static_busy[kMaxDevices] = {};
+}  // namespace
+
 // Per-configuration scalar slots (nb values each).
 enum CfgScalar : int {
   kCsQ = 0,        // sum Q
@@ -128,6 +144,14 @@ struct fep3m_ctx {
   uint64_t generation = 0;   // successful evaluations so far
   bool fwd_valid = false;    // buffers hold the state of evaluation `generation`
   std::vector<void *> allocs;
+  size_t dev_bytes = 0;        // device memory the context holds
+  // static contexts: every device buffer is carved from the device's static
+  // array (no hipMalloc), host mirrors are ordinary host memory (no pinned
+  // allocation)
+  unsigned char *arena = nullptr;
+  size_t arena_used = 0;
+  int arena_dev = -1;
+  std::vector<double> host_cs_buf, host_scal_buf;
   Profiler prof;
 
   // precompute
@@ -220,8 +244,28 @@ struct fep3m_ctx {
 
   template <class T>
   T *alloc(size_t count, const char *what) {
+    const size_t bytes = count * sizeof(T) + 64;
+    dev_bytes += bytes;
+    if (arena) {
+      const size_t at = (arena_used + 255) & ~size_t(255);
+      if (at + bytes > kStaticBytes)
+        throw Status(FEP3M_ERR_ARG, std::string("static storage of ") + std::to_string(kStaticBytes >> 20) +
+                                        " MiB exceeded at " + what + " (the context needs more; use fep3m_create_ex)");
+      arena_used = at + bytes;
+      return reinterpret_cast<T *>(arena + at);
+    }
     T *p = dalloc<T>(count, what);
     allocs.push_back(p);
+    return p;
+  }
+  // host mirror of `count` doubles: pinned, or ordinary memory for static contexts
+  double *host_mirror(size_t count, std::vector<double> &buf, const char *what) {
+    if (arena) {
+      buf.assign(count, 0.0);
+      return buf.data();
+    }
+    double *p = nullptr;
+    hip_check(hipHostMalloc(reinterpret_cast<void **>(&p), count * sizeof(double), hipHostMallocDefault), what);
     return p;
   }
   ~fep3m_ctx() {
@@ -229,8 +273,13 @@ struct fep3m_ctx {
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : prof.kev) (void)hipEventDestroy(e);
     for (void *p : allocs) (void)hipFree(p);
-    if (host_scal) (void)hipHostFree(host_scal);
-    if (host_cs) (void)hipHostFree(host_cs);
+    if (!arena) {
+      if (host_scal) (void)hipHostFree(host_scal);
+      if (host_cs) (void)hipHostFree(host_cs);
+    } else {
+      std::lock_guard<std::mutex> lk(g_static_mu);
+      g_static_busy[arena_dev] = false;
+    }
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (ev_in) (void)hipEventDestroy(ev_in);
@@ -365,8 +414,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   hip_check(hipMemcpy(off_d, off_h.data(), off_h.size() * sizeof(int), hipMemcpyHostToDevice), "upload offsets");
   nbs = nb;
   cs = alloc<double>(size_t(kCsSlots) * nb, "configuration scalars");
-  hip_check(hipHostMalloc(reinterpret_cast<void **>(&host_cs), size_t(kCsSlots) * nb * sizeof(double),
-                          hipHostMallocDefault), "pinned configuration scalars");
+  host_cs = host_mirror(size_t(kCsSlots) * nb, host_cs_buf, "pinned configuration scalars");
   {
     double **slots[] = {&pcs.bn2, &pcs.rz, &pcs.rzn, &pcs.pq, &pcs.rr, &pcs.zq, &pcs.alpha, &pcs.beta, &pcs.act, &pcs.rel};
     double *pbuf = alloc<double>(size_t(10) * 2 * nb, "pcg scalars");
@@ -431,8 +479,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   phi_s = alloc<double>(size_t(N), "potential");
   partial_len = size_t(4 * kRedBlocks) + 64;
   scal = alloc<double>(64, "scalars");
-  hip_check(hipHostMalloc(reinterpret_cast<void **>(&host_scal), 64 * sizeof(double), hipHostMallocDefault),
-            "pinned scalars");
+  host_scal = host_mirror(64, host_scal_buf, "pinned scalars");
 
   build_mg();
   if (opt.solver == FEP3M_SOLVER_FDM) build_fdm();
@@ -449,6 +496,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   auto t1 = std::chrono::steady_clock::now();
   stats.create_seconds = std::chrono::duration<double>(t1 - t0).count();
   stats.mg_levels = int(lv.size());
+  stats.device_bytes = int64_t(dev_bytes);
 }
 
 // Operator of a level whose elements are H fine elements wide: in fine
@@ -931,7 +979,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   // and only on meshes of at least 2^16 elements in all: below that the pass
   // is too short to pay for the fork and the join (graph replays of 1000
   // charges on 8^3 elements: 1.25 -> 1.39 ms)
-  const bool overlap = !(opt.autotune && !tuned && !prof.on) && plan.kind == 0 &&
+  const bool overlap = !(opt.autotune && !tuned && !prof.on) && plan.kind == 0 && !arena &&
                        size_t(nb) * n * n * n >= (size_t(1) << 16);
   if (overlap) {
     side_stream();
@@ -1365,7 +1413,7 @@ int fep3m_default_options(fep3m_options *opt) {
 namespace {
 
 int create_common(double L, const std::vector<int64_t> &Ns, const int32_t dims[3], int32_t q,
-                  const fep3m_options *opt, fep3m_ctx **out) {
+                  const fep3m_options *opt, fep3m_ctx **out, bool static_storage = false) {
   if (!out) return FEP3M_ERR_ARG;
   *out = nullptr;
   fep3m_options o;
@@ -1387,9 +1435,45 @@ int create_common(double L, const std::vector<int64_t> &Ns, const int32_t dims[3
   if (q < 2 || q > 6) return FEP3M_ERR_ARG;
   if (q != 3) return FEP3M_ERR_UNSUPPORTED;
   if (o.near_field == FEP3M_NEAR_FFT && !fft_size_ok(dims[0])) return FEP3M_ERR_UNSUPPORTED;
+  int dev = -1;
+  if (static_storage) {
+    // no tuning events, graph staging buffers, side stream or library handles
+    if (o.use_graph || o.solver != FEP3M_SOLVER_MG) {
+      g_create_error = "static contexts support neither use_graph nor the FDM solver";
+      return FEP3M_ERR_UNSUPPORTED;
+    }
+    o.autotune = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+      g_create_error = "no usable device for static storage";
+      return FEP3M_ERR_DEVICE;
+    }
+  }
   std::unique_ptr<fep3m_ctx> ctx(new (std::nothrow) fep3m_ctx());
   if (!ctx) return FEP3M_ERR_OOM;
-  int st = guarded(ctx.get(), [&] { ctx->build(L, Ns, dims[0], q, o); });
+  if (static_storage) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_busy[dev]) {
+      g_create_error = "the device's static storage is held by another static context (destroy it first)";
+      return FEP3M_ERR_ARG;
+    }
+    if (!g_static_ptr[dev]) {
+      void *ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        g_create_error = std::string("static storage address: ") + hipGetErrorString(e);
+        return FEP3M_ERR_DEVICE;
+      }
+      g_static_ptr[dev] = ptr;
+    }
+    g_static_busy[dev] = true;
+    ctx->arena = static_cast<unsigned char *>(g_static_ptr[dev]);
+    ctx->arena_dev = dev;   // the destructor releases the claim
+  }
+  int st = guarded(ctx.get(), [&] {
+    if (ctx->arena)   // the array keeps the last static context's contents
+      hip_check(hipMemset(ctx->arena, 0, kStaticBytes), "clear static storage");
+    ctx->build(L, Ns, dims[0], q, o);
+  });
   if (st != FEP3M_OK) {
     g_create_error = ctx->err;
     return st;
@@ -1413,6 +1497,11 @@ int fep3m_create_batch(double L, int32_t nconf, const int64_t *N_per_conf, const
 
 int fep3m_create(double L, int64_t N, const int32_t dims[3], int32_t q, fep3m_ctx **out) {
   return fep3m_create_ex(L, N, dims, q, nullptr, out);
+}
+
+int fep3m_create_static(double L, int64_t N, const int32_t dims[3], int32_t q, const fep3m_options *opt,
+                        fep3m_ctx **out) {
+  return create_common(L, std::vector<int64_t>{N}, dims, q, opt, out, true);
 }
 
 int fep3m_set_stream(fep3m_ctx *ctx, void *hip_stream) {
