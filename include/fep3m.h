@@ -150,6 +150,12 @@ typedef struct {
                             nor with solver = FEP3M_SOLVER_FDM.                */
   int32_t solver;        /* FEP3M_SOLVER_* (default: multigrid-preconditioned CG) */
   int32_t near_field;    /* FEP3M_NEAR_* (default AUTO)                          */
+  int32_t support;       /* FEP3M_SUPPORT_* (default ONE).  Every family but the
+                            one-element q = 3 screen runs in float64 with the
+                            direct near field (vector units); create returns
+                            FEP3M_ERR_UNSUPPORTED for precision = MIXED or
+                            near_field = FFT there, and for element orders
+                            above 6 (one-element q = 5, 6)                     */
 } fep3m_options;
 
 typedef struct {
@@ -211,13 +217,16 @@ int fep3m_default_options(fep3m_options *opt);
 
 /* Create a context for N charges in the periodic cube [0, L]^3 meshed by
  * dims[0] x dims[1] x dims[2] elements (cubic meshes only: all three equal),
- * one-element screens of degree q, mesh order p = q + 2.  q = 3 (the
- * lowest degree whose one-element screen cancels monopole and dipole) is
- * implemented; other degrees return FEP3M_ERR_UNSUPPORTED.
+ * screens of degree q with the support of opt->support, mesh order
+ * p = q + 2: one-element screens (Section 5) for q = 2..4 (q = 3, the lowest
+ * degree that cancels monopole and dipole, is the default and the fastest
+ * path), 27-element screens (Section 2.1) for q = 1..4.
  * Precomputes the 1-D element matrices, screens, near-field tables and the
  * multigrid hierarchy, and allocates every device buffer the evaluation
  * needs.  Errors: FEP3M_ERR_ARG for L <= 0 or non-finite, N < 2,
- * dims < 2 n_sr + 1 or unequal, q out of range, bad options;
+ * dims < 2 n_sr + 1 or unequal, q out of range for the support (2..6 one
+ * element, 1..4 27 elements), bad options; FEP3M_ERR_UNSUPPORTED as listed
+ * under fep3m_options.support;
  * FEP3M_ERR_OOM, FEP3M_ERR_DEVICE.  *out is NULL on failure. */
 int fep3m_create(double L, int64_t N, const int32_t dims[3], int32_t q, fep3m_ctx **out);
 int fep3m_create_ex(double L, int64_t N, const int32_t dims[3], int32_t q,

@@ -137,6 +137,11 @@ struct fep3m_ctx {
   bool adj_near_ready = false;      // ... and transformed the moment adjoint's near part (FFT path)
   double *cfgs(int slot) const { return cs + size_t(slot) * nb; }
   int n = 0, q = 3, p = 5, d = 1, nsr = 3, B = 15;
+  // screens: nl = d + 1 moments per axis, na = nl^3, span elements per axis
+  // of an element's screens; `generic` for every family but the one-element
+  // q = 3 screen (their float64 kernels are in k_screens.hip)
+  int nl = 2, na = 8, span = 1;
+  bool generic = false;
   fep3m_options opt{};
   hipStream_t stream = nullptr;
   std::string err;
@@ -378,21 +383,26 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   n = n_;
   q = q_;
   p = q + 2;
-  d = q - 2;
   opt = o;
   nsr = o.n_sr;
   B = o.table_box;
   h = L / n;
   mixed = o.precision == FEP3M_PRECISION_MIXED;
 
-  Screen1D scr = make_screen(q, FEP3M_SUPPORT_ONE);
+  Screen1D scr = make_screen(q, o.support);
+  d = scr.d;
+  nl = d + 1;
+  na = nl * nl * nl;
+  span = scr.span;
+  generic = !(o.support == FEP3M_SUPPORT_ONE && q == 3);
   compute_tables(p, scr, nsr, B, T_host);
   Mat g = load_weights(p, scr);
   Mat ke, me;
   element_matrices(p, ke, me);
-  std::vector<double> gwh(size_t(d + 1) * (p + 1)), w1h(p);
-  for (int l = 0; l <= d; ++l)
-    for (int k = 0; k <= p; ++k) gwh[l * (p + 1) + k] = g(l, k);
+  const int ks = span * p + 1;   // support nodes per axis
+  std::vector<double> gwh(size_t(nl) * ks), w1h(p);
+  for (int l = 0; l < nl; ++l)
+    for (int k = 0; k < ks; ++k) gwh[l * ks + k] = g(l, k);
   for (int k = 0; k < p; ++k) {  // (M1 1) at local index k (k = 0 collects both elements)
     double s = 0.0;
     for (int j = 0; j <= p; ++j) s += me(k, j);
@@ -425,7 +435,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   gw = alloc<double>(gwh.size(), "load weights");
   w1 = alloc<double>(w1h.size(), "mass ones");
   hip_check(hipMemcpy(T, T_host.data(), T_host.size() * sizeof(double), hipMemcpyHostToDevice), "upload tables");
-  {  // transposed copy Tt[D][m][a] for the reverse pass
+  if (!generic) {  // transposed copy Tt[D][m][a] for the reverse pass
     const size_t ND = size_t(2 * nsr + 1) * (2 * nsr + 1) * (2 * nsr + 1), NM = size_t(p + 1) * (p + 1) * (p + 1);
     std::vector<double> tt(T_host.size());
     for (size_t a = 0; a < 8; ++a)
@@ -450,7 +460,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   scan_scr = alloc<int>(2 * ((size_t(nb) * M + 2047) / 2048) + 16, "scan scratch");
   maxcount = alloc<int>(4, "max count");
   paircount = alloc<unsigned long long>(2, "pair count");
-  C = alloc<double>(size_t(nb) * M * 8, "moments");
+  C = alloc<double>(size_t(nb) * M * na, "moments");
   if (!mixed) {
     Wel = alloc<double>(size_t(nb) * M * (p + 1) * (p + 1) * (p + 1), "element field");
   } else {
@@ -490,7 +500,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   partial_len = std::max(partial_len, size_t(kRowBlocks) + 64);
   partial = alloc<double>(partial_len, "partials");
   estimate_spectra();
-  near_fft = opt.near_field == FEP3M_NEAR_FFT || (opt.near_field == FEP3M_NEAR_AUTO && fft_size_ok(n));
+  near_fft = !generic && (opt.near_field == FEP3M_NEAR_FFT || (opt.near_field == FEP3M_NEAR_AUTO && fft_size_ok(n)));
   if (near_fft) build_near_fft();
   stats.near_fft = near_fft ? 1 : 0;
   auto t1 = std::chrono::steady_clock::now();
@@ -605,7 +615,7 @@ void fep3m_ctx::build_mg() {
   Gv = b + nd0;
   sol = alloc<double>(2 * nd0, "phi, lambda");
   lam = sol + nd0;
-  Aadj = alloc<double>(size_t(nb) * n * n * n * 8, "moment adjoint");
+  Aadj = alloc<double>(size_t(nb) * n * n * n * na, "moment adjoint");
   fpair = alloc<double>(3 * size_t(N), "pair forces");
   Phi_int = alloc<double>(size_t(N), "potential (caller order)");
   rr = alloc<double>(2 * nd0, "pcg r");
@@ -1000,8 +1010,14 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
     ~Join() { if (pending) (void)hipStreamWaitEvent(s, e, 0); }
   } join{stream, ev_join, overlap};
   stage_mark(FEP3M_PROF_ASSIGN, true);
-  launch_moments(stream, nb, n, N, start, sg, sQ, C);
-  const int Kl = launch_load(stream, nb, n, p, C, gw, b, partial);
+  if (generic) {
+    if (launch_moments_g(stream, nb, n, nl, N, start, sg, sQ, C) != 0)
+      throw Status(FEP3M_ERR_UNSUPPORTED, "moments variant");
+  } else {
+    launch_moments(stream, nb, n, N, start, sg, sQ, C);
+  }
+  const int Kl = generic ? launch_load_g(stream, nb, n, p, span, nl, C, gw, b, partial)
+                         : launch_load(stream, nb, n, p, C, gw, b, partial);
   if (Kl < 0) throw Status(FEP3M_ERR_UNSUPPORTED, "load variant");
   launch_sum_partials(stream, Kl, partial, cfgs(kCsLoad), nb);
   if (launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsLoad), b) != 0)
@@ -1031,6 +1047,8 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
                  : launch_psi_fft_finish<double>(stream, nb, n, p, twd, sol, zpsi, Wel);
     adj_near_ready = pair_forces;
     prof.near_both = pair_forces;
+  } else if (generic) {
+    ps = launch_psi_g(stream, nb, n, nsr, p, nl, C, T, sol, Wel);
   } else
     ps = mixed ? launch_psi<float>(stream, nb, n, nsr, p, C, Tf, sol, Welf)
                : launch_psi<double>(stream, nb, n, nsr, p, C, T, sol, Wel);
@@ -1143,18 +1161,20 @@ void fep3m_ctx::reverse(double *F, double *dUdQ) {
     as = adj_near_ready ? 0 : launch_near_fft(stream, nb, n, p, nullptr, gE, spec, twd, zc, zpsi, zg, za);
     if (as == 0) as = launch_adj_fft_finish(stream, nb, n, p, lam, gw, za, Aadj);
     adj_near_ready = false;
+  } else if (generic) {
+    as = launch_adj_g(stream, nb, n, nsr, p, span, nl, gE, T, lam, gw, Aadj);
   } else {
     as = launch_adj_moments(stream, nb, p, n, nsr, gE, Tt, lam, gw, Aadj);
   }
   if (as != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
   stage_mark(FEP3M_PROF_ADJ_NEAR, false);
   stage_mark(FEP3M_PROF_FORCES, true);
-  if (mixed)
-    launch_forces<float>(stream, nb, off_d, p, n, N, 1.0 / h, bas, sg, sQ, Welf, Aadj, fpair, phip_s, phim_s, perm, F,
-                         dUdQ);
-  else
-    launch_forces<double>(stream, nb, off_d, p, n, N, 1.0 / h, bas, sg, sQ, Wel, Aadj, fpair, phip_s, phim_s, perm, F,
-                          dUdQ);
+  const int fs =
+      mixed ? launch_forces<float>(stream, nb, off_d, p, n, nl, N, 1.0 / h, bas, sg, sQ, Welf, Aadj, fpair, phip_s,
+                                   phim_s, perm, F, dUdQ)
+            : launch_forces<double>(stream, nb, off_d, p, n, nl, N, 1.0 / h, bas, sg, sQ, Wel, Aadj, fpair, phip_s,
+                                    phim_s, perm, F, dUdQ);
+  if (fs != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "forces variant");
   stage_mark(FEP3M_PROF_FORCES, false);
   if (capturing) return;   // counts are recorded by the eager call before a capture
   stats.adj_iterations = stats.mg_iterations;
@@ -1324,7 +1344,7 @@ void fep3m_ctx::profile_collect() {
   }
   const double S = 2 * nsr + 1;
   const double Me = double(n) * n * n * nb, NM = double(p + 1) * (p + 1) * (p + 1);
-  double near_flop = 2.0 * 8.0 * NM * S * S * S * Me, adj_work = near_flop;
+  double near_flop = 2.0 * double(na) * NM * S * S * S * Me, adj_work = near_flop;
   if (near_fft) {   // bytes in and out of every launch of the FFT pipelines
     const double spec_b = double(spec_freqs(n)) * 8.0 * NM * 16.0;
     const double f4 = Me * 4.0 * 16.0, f108 = Me * NM / 2.0 * 16.0, phi_b = Me * 125.0 * 8.0;
@@ -1384,6 +1404,7 @@ bool valid_options(const fep3m_options &o, std::string &why) {
   if (o.use_graph != 0 && o.use_graph != 1) { why = "use_graph must be 0 or 1"; return false; }
   if (o.solver != FEP3M_SOLVER_MG && o.solver != FEP3M_SOLVER_FDM) { why = "unknown solver"; return false; }
   if (o.near_field < FEP3M_NEAR_AUTO || o.near_field > FEP3M_NEAR_FFT) { why = "unknown near_field"; return false; }
+  if (o.support != FEP3M_SUPPORT_ONE && o.support != FEP3M_SUPPORT_27) { why = "unknown support"; return false; }
   if (o.table_box % 2 == 0 || o.table_box < 2 * o.n_sr + 3 || o.table_box > 41) {
     why = "table_box must be odd, > 2 n_sr + 1 and <= 41";
     return false;
@@ -1407,6 +1428,7 @@ int fep3m_default_options(fep3m_options *opt) {
   opt->use_graph = 0;
   opt->solver = FEP3M_SOLVER_MG;
   opt->near_field = FEP3M_NEAR_AUTO;
+  opt->support = FEP3M_SUPPORT_ONE;
   return FEP3M_OK;
 }
 
@@ -1432,8 +1454,17 @@ int create_common(double L, const std::vector<int64_t> &Ns, const int32_t dims[3
   if (int64_t(Ns.size()) * dims[0] * dims[0] * dims[0] > (int64_t(1) << 28)) return FEP3M_ERR_ARG;
   if (!valid_options(o, why)) return FEP3M_ERR_ARG;
   if (dims[0] < 2 * o.n_sr + 1 || dims[0] > 512) return FEP3M_ERR_ARG;
-  if (q < 2 || q > 6) return FEP3M_ERR_ARG;
-  if (q != 3) return FEP3M_ERR_UNSUPPORTED;
+  if (o.support == FEP3M_SUPPORT_ONE ? (q < 2 || q > 6) : (q < 1 || q > 4)) return FEP3M_ERR_ARG;
+  if (q + 2 > kMaxP) {
+    g_create_error = "element orders above 6 (one-element screens of degree 5 and 6) are not implemented";
+    return FEP3M_ERR_UNSUPPORTED;
+  }
+  if (!(o.support == FEP3M_SUPPORT_ONE && q == 3)) {   // the other screen families: float64, table sums
+    if (o.precision != FEP3M_PRECISION_FP64 || o.near_field == FEP3M_NEAR_FFT) {
+      g_create_error = "screens other than the one-element q = 3 screen run in float64 with the direct near field";
+      return FEP3M_ERR_UNSUPPORTED;
+    }
+  }
   if (o.near_field == FEP3M_NEAR_FFT && !fft_size_ok(dims[0])) return FEP3M_ERR_UNSUPPORTED;
   int dev = -1;
   if (static_storage) {
@@ -1542,7 +1573,7 @@ int64_t fep3m_stage_bytes(const fep3m_ctx *ctx, int32_t stage) {
   switch (stage) {
     case 0: return ctx->N * 4;
     case 1: return (M + 1) * 4;
-    case 2: return M * 8 * 8;
+    case 2: return M * ctx->na * 8;
     case 3: case 4: return P3 * 8;
     case 5: case 6: return ctx->N * 8;
     case 7: return int64_t(ctx->T_host.size()) * 8;

@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__r
 }
 
 // Forces and dU/dQ per sorted charge, scattered to caller order.
-template <int PO, class WT>
+template <int PO, int NL, class WT>
 __global__ __launch_bounds__(256) void k_forces(int n, int64_t N, int nb, const int *__restrict__ off, double inv_h,
                                                 GllBasis bas,
                                                 const double *__restrict__ sg, const double *__restrict__ sQ,
@@ -348,14 +348,45 @@ __global__ __launch_bounds__(256) void k_forces(int n, int64_t N, int nb, const 
       gys += l[2][mz] * sy_ld;
       gzs += dl[2][mz] * sy_ll;
     }
-    const double *A = Aadj + E * 8;
+    constexpr int NA = NL * NL * NL;
+    const double *A = Aadj + E * NA;
     const double ux = u[0], uy = u[1], uz = u[2];
-    // grad of u^a, a = ax + 2 ay + 4 az, each exponent 0 or 1
-    const double ax = A[1] + A[3] * uy + A[5] * uz + A[7] * uy * uz;
-    const double ay = A[2] + A[3] * ux + A[6] * uz + A[7] * ux * uz;
-    const double az = A[4] + A[5] * ux + A[6] * uy + A[7] * ux * uy;
-    const double au = A[0] + A[1] * ux + A[2] * uy + A[3] * ux * uy + A[4] * uz + A[5] * ux * uz + A[6] * uy * uz +
-                      A[7] * ux * uy * uz;
+    double ax, ay, az, au;
+    if constexpr (NL == 2) {
+      // grad of u^a, a = ax + 2 ay + 4 az, each exponent 0 or 1
+      ax = A[1] + A[3] * uy + A[5] * uz + A[7] * uy * uz;
+      ay = A[2] + A[3] * ux + A[6] * uz + A[7] * ux * uz;
+      az = A[4] + A[5] * ux + A[6] * uy + A[7] * ux * uy;
+      au = A[0] + A[1] * ux + A[2] * uy + A[3] * ux * uy + A[4] * uz + A[5] * ux * uz + A[6] * uy * uz +
+           A[7] * ux * uy * uz;
+    } else {
+      // powers u^k and their derivatives k u^(k-1) per axis, a = ax + NL ay + NL^2 az
+      double pw[3][NL], dp[3][NL];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        pw[k][0] = 1.0;
+        dp[k][0] = 0.0;
+#pragma unroll
+        for (int j = 1; j < NL; ++j) {
+          pw[k][j] = pw[k][j - 1] * u[k];
+          dp[k][j] = double(j) * pw[k][j - 1];
+        }
+      }
+      ax = ay = az = au = 0.0;
+      for (int kz = 0; kz < NL; ++kz)
+        for (int ky = 0; ky < NL; ++ky) {
+          double rv = 0.0, rd = 0.0;
+          for (int kx = 0; kx < NL; ++kx) {
+            const double c = A[(kz * NL + ky) * NL + kx];
+            rv += c * pw[0][kx];
+            rd += c * dp[0][kx];
+          }
+          au += pw[2][kz] * pw[1][ky] * rv;
+          ax += pw[2][kz] * pw[1][ky] * rd;
+          ay += pw[2][kz] * dp[1][ky] * rv;
+          az += dp[2][kz] * pw[1][ky] * rv;
+        }
+    }
     const double q = sQ[s];
     const double s2 = inv_h * inv_h;
     const int i = perm[s];
@@ -372,16 +403,25 @@ __global__ __launch_bounds__(256) void k_forces(int n, int64_t N, int nb, const 
 
 int launch_deposit(hipStream_t s, int nb, int p, int n, int64_t N, const GllBasis &bas, const int *start,
                    const double *sg, const double *sQ, double *gE) {
-  if (p != 5) return -1;
   const int MT = nb * n * n * n;
-  hipLaunchKernelGGL(k_deposit<5>, dim3(MT), dim3(64), 0, s, n, MT, N, bas, start, sg, sQ, gE);
-  return 0;
+  switch (p) {
+    case 3: hipLaunchKernelGGL(k_deposit<3>, dim3(MT), dim3(64), 0, s, n, MT, N, bas, start, sg, sQ, gE); return 0;
+    case 4: hipLaunchKernelGGL(k_deposit<4>, dim3(MT), dim3(64), 0, s, n, MT, N, bas, start, sg, sQ, gE); return 0;
+    case 5: hipLaunchKernelGGL(k_deposit<5>, dim3(MT), dim3(64), 0, s, n, MT, N, bas, start, sg, sQ, gE); return 0;
+    case 6: hipLaunchKernelGGL(k_deposit<6>, dim3(MT), dim3(64), 0, s, n, MT, N, bas, start, sg, sQ, gE); return 0;
+    default: return -1;
+  }
 }
 int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, double *G, double *partial) {
-  if (p != 5) return -1;
   const int K = row_blocks(nb, p * n);
-  hipLaunchKernelGGL(k_assemble<5>, dim3(nb * K), dim3(row_threads(p * n)), 0, s, n, K, gE, G, partial);
-  return K;
+  const dim3 g(nb * K), b(row_threads(p * n));
+  switch (p) {
+    case 3: hipLaunchKernelGGL(k_assemble<3>, g, b, 0, s, n, K, gE, G, partial); return K;
+    case 4: hipLaunchKernelGGL(k_assemble<4>, g, b, 0, s, n, K, gE, G, partial); return K;
+    case 5: hipLaunchKernelGGL(k_assemble<5>, g, b, 0, s, n, K, gE, G, partial); return K;
+    case 6: hipLaunchKernelGGL(k_assemble<6>, g, b, 0, s, n, K, gE, G, partial); return K;
+    default: return -1;
+  }
 }
 int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, const double *gE, const double *Tt,
                        const double *lam, const double *gw, double *A) {
@@ -396,20 +436,32 @@ int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, const doubl
   }
 }
 template <class WT>
-int launch_forces(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h, const GllBasis &bas,
-                  const double *sg, const double *sQ, const WT *Wel, const double *A, const double *fpair,
-                  const double *phip, const double *phim_s, const int *perm, double *F, double *dUdQ) {
-  if (p != 5) return -1;
+int launch_forces(hipStream_t s, int nb, const int *off, int p, int n, int nl, int64_t N, double inv_h,
+                  const GllBasis &bas, const double *sg, const double *sQ, const WT *Wel, const double *A,
+                  const double *fpair, const double *phip, const double *phim_s, const int *perm, double *F,
+                  double *dUdQ) {
   int64_t gb = (N + 255) / 256;
   if (gb > 4096) gb = 4096;
-  hipLaunchKernelGGL((k_forces<5, WT>), dim3(int(gb)), dim3(256), 0, s, n, N, nb, off, inv_h, bas, sg, sQ, Wel, A,
-                     fpair, phip, phim_s, perm, F, dUdQ);
-  return 0;
+#define CALL(PO, NL)                                                                                                \
+  hipLaunchKernelGGL((k_forces<PO, NL, WT>), dim3(int(gb)), dim3(256), 0, s, n, N, nb, off, inv_h, bas, sg, sQ, Wel, \
+                     A, fpair, phip, phim_s, perm, F, dUdQ)
+  const int key = 10 * p + nl;   // the screen families: (p, nl) = (5, 2) and q + 2 with q - 1 or q + 1
+  switch (key) {
+    case 52: CALL(5, 2); return 0;
+    case 32: CALL(3, 2); return 0;
+    case 43: CALL(4, 3); return 0;
+    case 54: CALL(5, 4); return 0;
+    case 65: CALL(6, 5); return 0;
+    case 63: CALL(6, 3); return 0;
+    case 41: CALL(4, 1); return 0;
+    default: return -1;
+  }
+#undef CALL
 }
-template int launch_forces<double>(hipStream_t, int, const int *, int, int, int64_t, double, const GllBasis &,
+template int launch_forces<double>(hipStream_t, int, const int *, int, int, int, int64_t, double, const GllBasis &,
                                    const double *, const double *, const double *, const double *, const double *,
                                    const double *, const double *, const int *, double *, double *);
-template int launch_forces<float>(hipStream_t, int, const int *, int, int, int64_t, double, const GllBasis &,
+template int launch_forces<float>(hipStream_t, int, const int *, int, int, int, int64_t, double, const GllBasis &,
                                   const double *, const double *, const float *, const double *, const double *,
                                   const double *, const double *, const int *, double *, double *);
 

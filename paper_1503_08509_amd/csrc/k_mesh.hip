@@ -995,16 +995,26 @@ void launch_sum_partials(hipStream_t s, int K, const double *partial, double *ou
   hipLaunchKernelGGL(k_sum_partials, dim3(nb), dim3(256), 0, s, K, partial, out);
 }
 int launch_sub_mass_ones(hipStream_t s, int nb, int n, int p, const double *w1, const double *scal, double *v) {
-  if (p != 5) return -1;
   const int K = row_blocks(nb, p * n);
-  hipLaunchKernelGGL(k_sub_mass_ones<5>, dim3(nb * K), dim3(row_threads(p * n)), 0, s, n, K, w1, scal, v);
-  return 0;
+  const dim3 g(nb * K), b(row_threads(p * n));
+  switch (p) {
+    case 3: hipLaunchKernelGGL(k_sub_mass_ones<3>, g, b, 0, s, n, K, w1, scal, v); return 0;
+    case 4: hipLaunchKernelGGL(k_sub_mass_ones<4>, g, b, 0, s, n, K, w1, scal, v); return 0;
+    case 5: hipLaunchKernelGGL(k_sub_mass_ones<5>, g, b, 0, s, n, K, w1, scal, v); return 0;
+    case 6: hipLaunchKernelGGL(k_sub_mass_ones<6>, g, b, 0, s, n, K, w1, scal, v); return 0;
+    default: return -1;
+  }
 }
 int launch_mass_dot(hipStream_t s, int nb, int n, int p, const double *w1, const double *v, double *partial) {
-  if (p != 5) return -1;
   const int K = row_blocks(nb, p * n);
-  hipLaunchKernelGGL(k_mass_dot<5>, dim3(nb * K), dim3(row_threads(p * n)), 0, s, n, K, w1, v, partial);
-  return K;
+  const dim3 g(nb * K), b(row_threads(p * n));
+  switch (p) {
+    case 3: hipLaunchKernelGGL(k_mass_dot<3>, g, b, 0, s, n, K, w1, v, partial); return K;
+    case 4: hipLaunchKernelGGL(k_mass_dot<4>, g, b, 0, s, n, K, w1, v, partial); return K;
+    case 5: hipLaunchKernelGGL(k_mass_dot<5>, g, b, 0, s, n, K, w1, v, partial); return K;
+    case 6: hipLaunchKernelGGL(k_mass_dot<6>, g, b, 0, s, n, K, w1, v, partial); return K;
+    default: return -1;
+  }
 }
 void launch_sub_const(hipStream_t s, int nb, size_t per, double invV, const double *scal, double *v) {
   const int K = seg_blocks(nb, per);
@@ -1085,13 +1095,15 @@ int launch_apply(hipStream_t s, int nb, const LevelOpT<T> &op, const T *x, const
     case 1: return apply_impl<T, 1, 8>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
     case 2: return apply_impl<T, 2, 4>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
     case 3: return apply_impl<T, 3, 4>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
+    case 4: return apply_impl<T, 4, 2>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
     case 5: return apply_impl<T, 5, 2>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
+    case 6: return apply_impl<T, 6, 1>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
     default: return -1;
   }
 }
 
 int apply_blocks(const LevelOp &op) {
-  int TE = op.p == 1 ? 8 : op.p == 2 ? 4 : op.p == 3 ? 4 : 2;
+  int TE = op.p == 1 ? 8 : op.p == 2 ? 4 : op.p == 3 ? 4 : op.p == 6 ? 1 : 2;
   int tiles = (op.n + TE - 1) / TE;
   return tiles * tiles * tiles;
 }
@@ -1120,6 +1132,12 @@ int launch_transfer(hipStream_t s, int nb, const TransferT<T> &tr, const T *in, 
   if (tr.pf == 5 && tr.pc == 3 && tr.r == 1) {
     if (restrict_) restrict_impl<T, 5, 3, 1, 2>(s, nb, tr, in, out);
     else prolong_impl<T, 5, 3, 1, 3>(s, nb, tr, in, out);
+  } else if (tr.pf == 4 && tr.pc == 3 && tr.r == 1) {
+    if (restrict_) restrict_impl<T, 4, 3, 1, 2>(s, nb, tr, in, out);
+    else prolong_impl<T, 4, 3, 1, 3>(s, nb, tr, in, out);
+  } else if (tr.pf == 6 && tr.pc == 3 && tr.r == 1) {
+    if (restrict_) restrict_impl<T, 6, 3, 1, 1>(s, nb, tr, in, out);
+    else prolong_impl<T, 6, 3, 1, 2>(s, nb, tr, in, out);
   } else if (tr.pf == 3 && tr.pc == 1 && tr.r == 1) {
     if (restrict_) restrict_impl<T, 3, 1, 1, 4>(s, nb, tr, in, out);
     else prolong_impl<T, 3, 1, 1, 5>(s, nb, tr, in, out);

@@ -607,10 +607,17 @@ int launch_pair_count(hipStream_t s, int nb, int n, int nsr, const int *start, u
 int launch_interp(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h, const GllBasis &bas,
                   const double *sg, const double *Wel, const double *phip, const int *perm, double *phim_s,
                   double *phi_s, double *Phi) {
-  if (p != 5) return -1;
-  hipLaunchKernelGGL(k_interp<5>, dim3(grid_n(N)), dim3(256), 0, s, n, N, nb, off, inv_h, bas, sg, Wel, phip, perm,
-                     phim_s, phi_s, Phi);
-  return 0;
+#define CALL(PO)                                                                                                 \
+  hipLaunchKernelGGL(k_interp<PO>, dim3(grid_n(N)), dim3(256), 0, s, n, N, nb, off, inv_h, bas, sg, Wel, phip, perm, \
+                     phim_s, phi_s, Phi)
+  switch (p) {
+    case 3: CALL(3); return 0;
+    case 4: CALL(4); return 0;
+    case 5: CALL(5); return 0;
+    case 6: CALL(6); return 0;
+    default: return -1;
+  }
+#undef CALL
 }
 int launch_energy(hipStream_t s, int nb, const int *off, int64_t N, const double *sQ, const double *phi_s,
                   double *partial) {

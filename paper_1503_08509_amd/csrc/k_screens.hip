@@ -1,0 +1,416 @@
+// Kernels of the screen families other than the one-element q = 3 screen
+// (Section 2.1: 27-element screens of degree q = 1..4; Section 5:
+// one-element screens of degree q != 3).  They differ from it in the number
+// of moments per axis (NL = d + 1), the element order (PO = q + 2) and the
+// support of an element's screens (SPAN = 1 or 3 elements per axis), so the
+// stages that touch the screens have their own float64 kernels here:
+//   moments      C[E][a] = sum_{i in E} Q_i u_i^a, a = ax + NL ay + NL^2 az
+//   load         b_g = 4 pi sum over the source elements whose support holds
+//                node g of sum_a C[s][a] gw[ax][jx] gw[ay][jy] gw[az][jz],
+//                j the node's index in the source's support (gather form)
+//   near field   W_E[m] = phi_E[m] - sum_D sum_a T[a][D][m] C[E - D][a]
+//   adjoint      A[E][a] = 4 pi <lambda on the support of E, G_a>
+//                          - sum_D <g_{E + D}, T_a[D]>
+// The pair sum, the interpolation, the deposit, the assembly, the mesh
+// operator and the forces are shared with the q = 3 path (templated on the
+// order and the moment count).
+//
+// Element ids are configuration-major (b n^3 + e); mesh vectors are nb
+// consecutive (PO n)^3 blocks [z][y][x].
+#include "kernels.hpp"
+
+namespace fep3m {
+namespace {
+
+__device__ __forceinline__ int wrapn(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Fixed-order block sum (shuffle tree in each wave, then the waves in
+// order); valid in thread 0.  blockDim a multiple of 64, at most 1024.
+__device__ double block_sum_s(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+// One thread per (element, moment).
+template <int NL>
+__global__ __launch_bounds__(256) void k_moments_g(int n, int MT, int64_t N, const int *__restrict__ start,
+                                                   const double *__restrict__ sg, const double *__restrict__ sQ,
+                                                   double *__restrict__ C) {
+  constexpr int NA = NL * NL * NL;
+  const int M = n * n * n;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < int64_t(MT) * NA;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int E = int(t / NA), a = int(t % NA);
+    const int ax = a % NL, ay = (a / NL) % NL, az = a / (NL * NL);
+    const int El = E % M;
+    const int ex = El % n, ey = (El / n) % n, ez = El / (n * n);
+    double c = 0.0;
+    for (int s = start[E]; s < start[E + 1]; ++s) {
+      const double ux = sg[s] - ex - 0.5, uy = sg[N + s] - ey - 0.5, uz = sg[2 * N + s] - ez - 0.5;
+      double m = sQ[s];
+      for (int k = 0; k < ax; ++k) m *= ux;
+      for (int k = 0; k < ay; ++k) m *= uy;
+      for (int k = 0; k < az; ++k) m *= uz;
+      c += m;
+    }
+    C[t] = c;
+  }
+}
+
+// Sources along one axis whose support holds global node g: SPAN of them
+// (SPAN + 1 at an element vertex), with the node's index j in each support.
+template <int PO, int SPAN>
+__device__ __forceinline__ int axis_sources(int g, int n, int (&s)[SPAN + 1], int (&j)[SPAN + 1]) {
+  constexpr int H = (SPAN - 1) / 2;
+  const int e = g / PO, k = g - e * PO;
+  const int lo = e - SPAN + (k > 0 ? 1 : 0);   // lowest s - H
+  const int cnt = e - lo + 1;
+#pragma unroll
+  for (int c = 0; c < SPAN + 1; ++c) {
+    const int sh = lo + c;
+    s[c] = ((sh + H) % n + n) % n;
+    j[c] = g - PO * sh;
+  }
+  return cnt;
+}
+
+// b (per configuration, K blocks strided over its nodes) and block partials
+// of sum b for the compatibility projection.
+template <int PO, int SPAN, int NL>
+__global__ __launch_bounds__(256) void k_load_g(int n, int K, const double *__restrict__ Call,
+                                                const double *__restrict__ gw, double *__restrict__ ball,
+                                                double *__restrict__ partial) {
+  constexpr int NA = NL * NL * NL, KS = SPAN * PO + 1;
+  __shared__ double red[8];
+  const int P = PO * n;
+  const size_t per = size_t(P) * P * P;
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const double *C = Call + size_t(cfg) * n * n * n * NA;
+  double *b = ball + size_t(cfg) * per;
+  double acc = 0.0;
+  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < per; g += size_t(K) * blockDim.x) {
+    const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
+    int sx[SPAN + 1], jx[SPAN + 1], sy[SPAN + 1], jy[SPAN + 1], sz[SPAN + 1], jz[SPAN + 1];
+    const int cx = axis_sources<PO, SPAN>(gx, n, sx, jx);
+    const int cy = axis_sources<PO, SPAN>(gy, n, sy, jy);
+    const int cz = axis_sources<PO, SPAN>(gz, n, sz, jz);
+    double v = 0.0;
+#pragma unroll
+    for (int iz = 0; iz < SPAN + 1; ++iz) {
+      if (iz >= cz) continue;
+#pragma unroll
+      for (int iy = 0; iy < SPAN + 1; ++iy) {
+        if (iy >= cy) continue;
+#pragma unroll
+        for (int ix = 0; ix < SPAN + 1; ++ix) {
+          if (ix >= cx) continue;
+          const double *c = C + (size_t(sx[ix]) + size_t(n) * (sy[iy] + size_t(n) * sz[iz])) * NA;
+          double tz = 0.0;
+          for (int az = 0; az < NL; ++az) {
+            double ty = 0.0;
+            for (int ay = 0; ay < NL; ++ay) {
+              double tx = 0.0;
+              for (int ax = 0; ax < NL; ++ax) tx += gw[ax * KS + jx[ix]] * c[(az * NL + ay) * NL + ax];
+              ty += gw[ay * KS + jy[iy]] * tx;
+            }
+            tz += gw[az * KS + jz[iz]] * ty;
+          }
+          v += tz;
+        }
+      }
+    }
+    v *= 4.0 * M_PI;
+    b[g] = v;
+    acc += v;
+  }
+  const double s = block_sum_s(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Near-screen field on bricks of BX x BY x BZ target elements: thread m
+// holds node m of every target of the brick; per near offset the sources'
+// moments are staged in LDS and each table value read serves all targets.
+constexpr int kBX = 4, kBY = 2, kBZ = 2, kBT = kBX * kBY * kBZ;
+
+template <int PO, int NL>
+__global__ __launch_bounds__(384) void k_psi_g(int n, int nsr, const double *__restrict__ Call,
+                                               const double *__restrict__ T, const double *__restrict__ phiall,
+                                               double *__restrict__ Wall) {
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NA = NL * NL * NL;
+  __shared__ double Cs[kBT * NA];
+  const int bxn = (n + kBX - 1) / kBX, byn = (n + kBY - 1) / kBY, bzn = (n + kBZ - 1) / kBZ;
+  const int per_cfg = bxn * byn * bzn;
+  const int cfg = blockIdx.x / per_cfg;
+  int br = blockIdx.x % per_cfg;
+  const int bx = br % bxn, by = (br / bxn) % byn, bz = br / (bxn * byn);
+  const size_t M = size_t(n) * n * n;
+  const int P = PO * n;
+  const double *C = Call + size_t(cfg) * M * NA;
+  const double *phi = phiall + size_t(cfg) * P * P * P;
+  double *W = Wall + size_t(cfg) * M * NM;
+  const int S = 2 * nsr + 1, ND = S * S * S;
+  const int m = threadIdx.x;
+  double acc[kBT];
+#pragma unroll
+  for (int t = 0; t < kBT; ++t) acc[t] = 0.0;
+  for (int iD = 0; iD < ND; ++iD) {
+    const int Dx = iD % S - nsr, Dy = (iD / S) % S - nsr, Dz = iD / (S * S) - nsr;
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBT * NA; i += blockDim.x) {
+      const int t = i / NA, a = i % NA;
+      const int ex = bx * kBX + t % kBX, ey = by * kBY + (t / kBX) % kBY, ez = bz * kBZ + t / (kBX * kBY);
+      double v = 0.0;
+      if (ex < n && ey < n && ez < n) {
+        const int sx = wrapn(ex - Dx, n), sy = wrapn(ey - Dy, n), sz = wrapn(ez - Dz, n);
+        v = C[(size_t(sx) + size_t(n) * (sy + size_t(n) * sz)) * NA + a];
+      }
+      Cs[i] = v;
+    }
+    __syncthreads();
+    if (m < NM) {
+      const double *Tm = T + size_t(iD) * NM + m;
+      for (int a = 0; a < NA; ++a) {
+        const double tv = Tm[size_t(a) * ND * NM];
+#pragma unroll
+        for (int t = 0; t < kBT; ++t) acc[t] += tv * Cs[t * NA + a];
+      }
+    }
+  }
+  if (m >= NM) return;
+  const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
+#pragma unroll
+  for (int t = 0; t < kBT; ++t) {
+    const int ex = bx * kBX + t % kBX, ey = by * kBY + (t / kBX) % kBY, ez = bz * kBZ + t / (kBX * kBY);
+    if (ex >= n || ey >= n || ez >= n) continue;
+    const int gx = wrapn(PO * ex + mx, P), gy = wrapn(PO * ey + my, P), gz = wrapn(PO * ez + mz, P);
+    const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
+    W[E * NM + m] = phi[(size_t(gz) * P + gy) * P + gx] - acc[t];
+  }
+}
+
+// Near part of the moment adjoint, A[E][a] = -sum_D sum_m g_{E+D}[m] T[a][D][m],
+// on bricks of target elements: thread (t, a) pairs, the deposits of the
+// brick's sources for each offset staged in LDS.
+template <int PO, int NL>
+__global__ __launch_bounds__(256) void k_adj_near_g(int n, int nsr, const double *__restrict__ gEall,
+                                                    const double *__restrict__ T, double *__restrict__ Aall) {
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NA = NL * NL * NL, NP = kBT * NA;
+  constexpr int PT = (NP + 255) / 256;   // (t, a) pairs per thread
+  __shared__ double Gs[kBT * NM];
+  const int bxn = (n + kBX - 1) / kBX, byn = (n + kBY - 1) / kBY, bzn = (n + kBZ - 1) / kBZ;
+  const int per_cfg = bxn * byn * bzn;
+  const int cfg = blockIdx.x / per_cfg;
+  int br = blockIdx.x % per_cfg;
+  const int bx = br % bxn, by = (br / bxn) % byn, bz = br / (bxn * byn);
+  const size_t M = size_t(n) * n * n;
+  const double *gE = gEall + size_t(cfg) * M * NM;
+  double *A = Aall + size_t(cfg) * M * NA;
+  const int S = 2 * nsr + 1, ND = S * S * S;
+  double acc[PT];
+#pragma unroll
+  for (int r = 0; r < PT; ++r) acc[r] = 0.0;
+  for (int iD = 0; iD < ND; ++iD) {
+    const int Dx = iD % S - nsr, Dy = (iD / S) % S - nsr, Dz = iD / (S * S) - nsr;
+    __syncthreads();
+    for (int i = threadIdx.x; i < kBT * NM; i += blockDim.x) {
+      const int t = i / NM, m = i % NM;
+      const int ex = bx * kBX + t % kBX, ey = by * kBY + (t / kBX) % kBY, ez = bz * kBZ + t / (kBX * kBY);
+      double v = 0.0;
+      if (ex < n && ey < n && ez < n) {
+        const int sx = wrapn(ex + Dx, n), sy = wrapn(ey + Dy, n), sz = wrapn(ez + Dz, n);
+        v = gE[(size_t(sx) + size_t(n) * (sy + size_t(n) * sz)) * NM + m];
+      }
+      Gs[i] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PT; ++r) {
+      const int pidx = threadIdx.x + 256 * r;
+      if (pidx >= NP) continue;
+      const int t = pidx % kBT, a = pidx / kBT;
+      const double *Tr = T + (size_t(a) * ND + iD) * NM;
+      const double *gs = Gs + t * NM;
+      double s = 0.0;
+      for (int m = 0; m < NM; ++m) s += gs[m] * Tr[m];
+      acc[r] += s;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < PT; ++r) {
+    const int pidx = threadIdx.x + 256 * r;
+    if (pidx >= NP) continue;
+    const int t = pidx % kBT, a = pidx / kBT;
+    const int ex = bx * kBX + t % kBX, ey = by * kBY + (t / kBX) % kBY, ez = bz * kBZ + t / (kBX * kBY);
+    if (ex >= n || ey >= n || ez >= n) continue;
+    A[(size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NA + a] = -acc[r];
+  }
+}
+
+// Mesh part of the moment adjoint: A[E][a] += 4 pi sum over the support's
+// nodes of lambda * gw[ax][jx] gw[ay][jy] gw[az][jz], one thread per
+// (element, moment), contracted along x, then y, then z.
+template <int PO, int SPAN, int NL>
+__global__ __launch_bounds__(256) void k_adj_lam_g(int n, int MT, const double *__restrict__ lamall,
+                                                   const double *__restrict__ gw, double *__restrict__ A) {
+  constexpr int NA = NL * NL * NL, KS = SPAN * PO + 1, H = (SPAN - 1) / 2;
+  const int M = n * n * n, P = PO * n;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < int64_t(MT) * NA;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int E = int(t / NA), a = int(t % NA);
+    const int ax = a % NL, ay = (a / NL) % NL, az = a / (NL * NL);
+    const int cfg = E / M, El = E % M;
+    const int ex = El % n, ey = (El / n) % n, ez = El / (n * n);
+    const double *lam = lamall + size_t(cfg) * P * P * P;
+    const int x0 = PO * (ex - H), y0 = PO * (ey - H), z0 = PO * (ez - H);
+    double sz = 0.0;
+    for (int kz = 0; kz < KS; ++kz) {
+      const size_t rz = size_t(wrapn(((z0 + kz) % P + P) % P, P)) * P;
+      double sy = 0.0;
+      for (int ky = 0; ky < KS; ++ky) {
+        const double *row = lam + (rz + size_t(wrapn(((y0 + ky) % P + P) % P, P))) * P;
+        double sx = 0.0;
+        for (int kx = 0; kx < KS; ++kx) sx += gw[ax * KS + kx] * row[wrapn(((x0 + kx) % P + P) % P, P)];
+        sy += gw[ay * KS + ky] * sx;
+      }
+      sz += gw[az * KS + kz] * sy;
+    }
+    A[t] += 4.0 * M_PI * sz;
+  }
+}
+
+inline int grid_for_count(int64_t count) {
+  int64_t g = (count + 255) / 256;
+  if (g < 1) g = 1;
+  return int(g > 65536 ? 65536 : g);
+}
+
+inline int psi_threads(int po) {
+  const int nm = (po + 1) * (po + 1) * (po + 1);
+  return ((nm + 63) / 64) * 64;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- launchers
+
+#define FEP3M_NL_SWITCH(NLV, CALL) \
+  switch (NLV) {                   \
+    case 1: CALL(1); break;        \
+    case 2: CALL(2); break;        \
+    case 3: CALL(3); break;        \
+    case 4: CALL(4); break;        \
+    case 5: CALL(5); break;        \
+    default: return -1;            \
+  }
+
+int launch_moments_g(hipStream_t s, int nb, int n, int nl, int64_t N, const int *start, const double *sg,
+                     const double *sQ, double *C) {
+  const int MT = nb * n * n * n;
+  const int g = grid_for_count(int64_t(MT) * nl * nl * nl);
+#define CALL(NL) hipLaunchKernelGGL(k_moments_g<NL>, dim3(g), dim3(256), 0, s, n, MT, N, start, sg, sQ, C)
+  FEP3M_NL_SWITCH(nl, CALL)
+#undef CALL
+  return 0;
+}
+
+template <int PO, int SPAN>
+static int load_g_nl(hipStream_t s, int nb, int n, int nl, int K, const double *C, const double *gw, double *b,
+                     double *partial) {
+#define CALL(NL) hipLaunchKernelGGL((k_load_g<PO, SPAN, NL>), dim3(nb * K), dim3(256), 0, s, n, K, C, gw, b, partial)
+  FEP3M_NL_SWITCH(nl, CALL)
+#undef CALL
+  return 0;
+}
+
+int launch_load_g(hipStream_t s, int nb, int n, int p, int span, int nl, const double *C, const double *gw, double *b,
+                  double *partial) {
+  const int P = p * n;
+  const int K = seg_blocks(nb, size_t(P) * P * P);
+  int r = -1;
+  if (span == 1) {
+    switch (p) {
+      case 4: r = load_g_nl<4, 1>(s, nb, n, nl, K, C, gw, b, partial); break;
+      case 5: r = load_g_nl<5, 1>(s, nb, n, nl, K, C, gw, b, partial); break;
+      case 6: r = load_g_nl<6, 1>(s, nb, n, nl, K, C, gw, b, partial); break;
+      default: return -1;
+    }
+  } else if (span == 3) {
+    switch (p) {
+      case 3: r = load_g_nl<3, 3>(s, nb, n, nl, K, C, gw, b, partial); break;
+      case 4: r = load_g_nl<4, 3>(s, nb, n, nl, K, C, gw, b, partial); break;
+      case 5: r = load_g_nl<5, 3>(s, nb, n, nl, K, C, gw, b, partial); break;
+      case 6: r = load_g_nl<6, 3>(s, nb, n, nl, K, C, gw, b, partial); break;
+      default: return -1;
+    }
+  }
+  return r < 0 ? -1 : K;
+}
+
+template <int PO>
+static int psi_g_nl(hipStream_t s, int nb, int n, int nsr, int nl, const double *C, const double *T,
+                    const double *phi, double *W) {
+  const int bricks = ((n + kBX - 1) / kBX) * ((n + kBY - 1) / kBY) * ((n + kBZ - 1) / kBZ);
+#define CALL(NL) \
+  hipLaunchKernelGGL((k_psi_g<PO, NL>), dim3(nb * bricks), dim3(psi_threads(PO)), 0, s, n, nsr, C, T, phi, W)
+  FEP3M_NL_SWITCH(nl, CALL)
+#undef CALL
+  return 0;
+}
+
+int launch_psi_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, const double *C, const double *T,
+                 const double *phi, double *W) {
+  switch (p) {
+    case 3: return psi_g_nl<3>(s, nb, n, nsr, nl, C, T, phi, W);
+    case 4: return psi_g_nl<4>(s, nb, n, nsr, nl, C, T, phi, W);
+    case 5: return psi_g_nl<5>(s, nb, n, nsr, nl, C, T, phi, W);
+    case 6: return psi_g_nl<6>(s, nb, n, nsr, nl, C, T, phi, W);
+    default: return -1;
+  }
+}
+
+template <int PO, int SPAN>
+static int adj_g_nl(hipStream_t s, int nb, int n, int nsr, int nl, const double *gE, const double *T,
+                    const double *lam, const double *gw, double *A) {
+  const int bricks = ((n + kBX - 1) / kBX) * ((n + kBY - 1) / kBY) * ((n + kBZ - 1) / kBZ);
+  const int MT = nb * n * n * n;
+  const int g = grid_for_count(int64_t(MT) * nl * nl * nl);
+#define CALL(NL)                                                                                                  \
+  hipLaunchKernelGGL((k_adj_near_g<PO, NL>), dim3(nb * bricks), dim3(256), 0, s, n, nsr, gE, T, A);              \
+  hipLaunchKernelGGL((k_adj_lam_g<PO, SPAN, NL>), dim3(g), dim3(256), 0, s, n, MT, lam, gw, A)
+  FEP3M_NL_SWITCH(nl, CALL)
+#undef CALL
+  return 0;
+}
+
+int launch_adj_g(hipStream_t s, int nb, int n, int nsr, int p, int span, int nl, const double *gE, const double *T,
+                 const double *lam, const double *gw, double *A) {
+  if (span == 1) {
+    switch (p) {
+      case 4: return adj_g_nl<4, 1>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
+      case 5: return adj_g_nl<5, 1>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
+      case 6: return adj_g_nl<6, 1>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
+      default: return -1;
+    }
+  }
+  if (span == 3) {
+    switch (p) {
+      case 3: return adj_g_nl<3, 3>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
+      case 4: return adj_g_nl<4, 3>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
+      case 5: return adj_g_nl<5, 3>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
+      case 6: return adj_g_nl<6, 3>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
+      default: return -1;
+    }
+  }
+  return -1;
+}
+
+#undef FEP3M_NL_SWITCH
+
+}  // namespace fep3m

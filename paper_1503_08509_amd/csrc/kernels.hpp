@@ -68,10 +68,25 @@ int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, doubl
 int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, const double *gE, const double *Tt,
                        const double *lam, const double *gw, double *A);
 // W of the forward pass in float64, or float32 on the mixed-precision path
+// (nl moments per axis; the screen families' (p, nl) pairs are instantiated)
 template <class WT>
-int launch_forces(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h, const GllBasis &bas,
-                  const double *sg, const double *sQ, const WT *Wel, const double *A, const double *fpair,
-                  const double *phip, const double *phim_s, const int *perm, double *F, double *dUdQ);
+int launch_forces(hipStream_t s, int nb, const int *off, int p, int n, int nl, int64_t N, double inv_h,
+                  const GllBasis &bas, const double *sg, const double *sQ, const WT *Wel, const double *A,
+                  const double *fpair, const double *phip, const double *phim_s, const int *perm, double *F,
+                  double *dUdQ);
+
+// screen families other than the one-element q = 3 screen (k_screens.hip),
+// float64: nl moments per axis, p the order, span 1 or 3 elements per axis;
+// gw the load weights [nl][span p + 1].  The load returns its partial count
+// per configuration (-1: unsupported combination), the others 0 or -1.
+int launch_moments_g(hipStream_t s, int nb, int n, int nl, int64_t N, const int *start, const double *sg,
+                     const double *sQ, double *C);
+int launch_load_g(hipStream_t s, int nb, int n, int p, int span, int nl, const double *C, const double *gw, double *b,
+                  double *partial);
+int launch_psi_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, const double *C, const double *T,
+                 const double *phi, double *W);
+int launch_adj_g(hipStream_t s, int nb, int n, int nsr, int p, int span, int nl, const double *gE, const double *T,
+                 const double *lam, const double *gw, double *A);
 
 // near field (k_near.hip)
 // T = double, or float (float32 tables, compensated slab sums, float32 W)

@@ -66,10 +66,28 @@ def test_create_rejects_bad_options():
     assert fp.lib().fep3m_create_ex(1.0, 100, d, 3, None, None) == fp.ERR_ARG
 
 
-def test_unsupported_degree_is_reported():
+def test_screen_family_arguments():
+    """Degree ranges per support (one element 2..6, 27 elements 1..4), orders
+    above 6 not implemented, and the float64 / direct-near-field restriction
+    of the families other than the one-element q = 3 screen (all refused
+    before any device work)."""
     h = ctypes.c_void_p()
     d = (ctypes.c_int32 * 3)(8, 8, 8)
-    assert fp.lib().fep3m_create(1.0, 100, d, 4, ctypes.byref(h)) == fp.ERR_UNSUPPORTED
+    L = fp.lib()
+
+    def create(q, **kw):
+        o = fp.default_options()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return L.fep3m_create_ex(1.0, 100, d, q, ctypes.byref(o), ctypes.byref(h))
+
+    assert create(5) == fp.ERR_UNSUPPORTED and create(6) == fp.ERR_UNSUPPORTED   # p = 7, 8
+    assert create(1) == fp.ERR_ARG and create(7) == fp.ERR_ARG
+    assert create(0, support=fp.SUPPORT_27) == fp.ERR_ARG and create(5, support=fp.SUPPORT_27) == fp.ERR_ARG
+    assert create(2, support=fp.SUPPORT_27, precision=fp.PRECISION_MIXED) == fp.ERR_UNSUPPORTED
+    assert create(4, near_field=fp.NEAR_FFT) == fp.ERR_UNSUPPORTED
+    assert create(3, support=2) == fp.ERR_ARG
+    assert h.value is None
 
 
 @pytest.mark.parametrize("n", [7, 9, 12, 128, 256])
