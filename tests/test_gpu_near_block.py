@@ -106,3 +106,46 @@ def test_error_falls_with_near_block_size(torch):
                 assert errs[near, n_sr + 1][k] < 0.65 * errs[near, n_sr][k]
     for n_sr in (1, 2, 3):
         np.testing.assert_allclose(errs[fp.NEAR_FFT, n_sr], errs[fp.NEAR_DIRECT, n_sr], rtol=1e-6)
+
+
+@pytest.mark.parametrize("q,rate", [(1, 3.0), (2, 4.0), (3, 5.0), (4, 6.0)])
+def test_27_element_screen_error_decay(torch, q, rate):
+    """Fig. decayavg through the GPU path for the 27-element screens: one unit
+    charge at 84 seeded locations in an element, probes along the 42
+    directions at 5 .. 10 elements (outside the 5^3 near block, in the
+    asymptotic range that the paper places beyond about three elements), on
+    32^3 elements so that the opposite charge (half a box away) adds no
+    error of the same size at the probes; the mean error falls like
+    R^-(q+2) (log-log slope within 0.6 of it; q = 4 still falls faster than
+    its asymptotic rate over this range)."""
+    n, h, n_sr = 32, 1.0 / 32, 2
+    R = np.array([5.0, 6.5, 8.0, 10.0])
+    D = _directions42()
+    rng = np.random.default_rng(840 + q)
+    nprobe = len(R) * len(D)
+    ctx = fp.Context(1.0, 2 + nprobe, n, q=q, support=fp.SUPPORT_27, n_sr=n_sr, mg_rtol=1e-14, mg_max_iter=200)
+    err = np.zeros((84, len(R), len(D)))
+    for s in range(84):
+        x0 = (np.array([3.0, 4.0, 5.0]) + rng.random(3)) * h
+        probes = (x0[None, None, :] + R[:, None, None] * h * D[None, :, :]).reshape(-1, 3)
+        assert (np.abs(np.floor(probes / h) - np.floor(x0 / h)).max(axis=1) > n_sr).all()
+        x = np.vstack([x0, (x0 + 0.5) % 1.0, probes]) % 1.0
+        Q = np.zeros(len(x))
+        Q[0], Q[1] = 1.0, -1.0
+        out = ctx.energy_forces(torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda(), Phi=True)
+        tg = np.arange(2, len(x))
+        ref = ewald.ewald(x, Q, targets=tg)
+        _, _, u = ofe.bin_particles(x, 1.0, n)
+        e = out["Phi"].cpu().numpy()[tg] + ofe.ewald_constant(u, Q, ofe.Params(L=1.0, n=n, q=q, support="27")) \
+            - ref["Phi"]
+        err[s] = np.abs(e).reshape(len(R), len(D)) * h
+    mean = err.mean(axis=(0, 2))
+    peak = err.max(axis=(0, 2))
+    s_mean = np.polyfit(np.log(R), np.log(mean), 1)[0]
+    s_peak = np.polyfit(np.log(R), np.log(peak), 1)[0]
+    print(f"q={q} |Phi_sr| h: mean {mean}, peak {peak}; slopes {s_mean:.2f}, {s_peak:.2f}", flush=True)
+    assert np.all(np.diff(mean) < 0)
+    if q < 4:
+        assert abs(s_mean + rate) < 0.6
+    else:
+        assert s_mean < -rate + 0.6

@@ -50,3 +50,37 @@ def test_twocube_accuracy_against_ewald(torch, N, nsample):
     e_phi, e_f = _rel(Phi, ref["Phi"]), _rel(F, ref["F"])
     print(f"twocube N={N} h=1/15: Phi rel RMS {e_phi:.3e}, F rel RMS {e_f:.3e} ({len(pick)} charges)")
     assert e_phi < 1e-2 and e_f < 1e-2
+
+
+def test_twocube_accuracy_against_q(torch):
+    """Section 4's comparison of screen orders (Fig. compareerr): the
+    two-cube set, N = 1e4, h = 1/15, 7^3 near block, the 27-element screens
+    of degree q = 1..4 of Section 2.1 and the one-element q = 3, 4 screens of
+    Section 5, 150 sampled charges against Ewald.  The constant separating
+    the gauges is zero once the x^2 moments are cancelled (d >= 2).  The
+    paper states super-algebraic convergence in q without values; here the
+    error of Phi must fall from q = 1 to q = 2 to q = 3 (the 27-element
+    family) and the one-element q = 4 screen must beat its q = 3 sibling."""
+    N, n = 10000, 15
+    w = workloads.Workload(f"twocube-{N}", N, n, kind="twocube", charges="biased", seed=2000 + N)
+    x, Q = workloads.make(w)
+    rng = np.random.default_rng(N + 1)
+    pick = np.sort(rng.choice(N, 150, replace=False))
+    ref = ewald.ewald(x, Q, forces=True, targets=pick)
+    tx, tQ = torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda()
+    errs = {}
+    for support, q in (("27", 1), ("27", 2), ("27", 3), ("27", 4), ("one", 3), ("one", 4)):
+        ctx = fp.Context(1.0, N, n, q=q, support=fp.SUPPORT_27 if support == "27" else fp.SUPPORT_ONE,
+                         mg_rtol=1e-12)
+        out = ctx.energy_forces(tx, tQ, Phi=True)
+        P = ofe.Params(L=1.0, n=n, q=q, support=support)
+        _, _, u = ofe.bin_particles(x, 1.0, n)
+        Phi = out["Phi"].cpu().numpy()[pick] + ofe.ewald_constant(u, Q, P)
+        F = out["F"].cpu().numpy()[pick]
+        errs[support, q] = (_rel(Phi, ref["Phi"]), _rel(F, ref["F"]))
+        print(f"twocube N={N} h=1/15 support={support} q={q}: Phi {errs[support, q][0]:.3e}, "
+              f"F {errs[support, q][1]:.3e}", flush=True)
+    assert errs["27", 2][0] < errs["27", 1][0] and errs["27", 3][0] < errs["27", 2][0]
+    assert errs["one", 4][0] < errs["one", 3][0]
+    for e in errs.values():
+        assert e[0] < 1e-2 and e[1] < 2e-2
