@@ -36,7 +36,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="uniform-1M-n64")
-    ap.add_argument("--cpu-sample", type=int, default=1000, help="oracle target sample for the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=4000, help="oracle target sample for the CPU baseline")
+    ap.add_argument("--cpu-baseline-child", nargs=3, metavar=("WORKLOAD", "SAMPLE", "OUT"),
+                    help=argparse.SUPPRESS)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the screen-family sweep at full size")
     ap.add_argument("--outputs", choices=["forces", "energy"], default="forces",
                     help="forces: U and F (the metric's energy+force step); energy: Phi and U")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
@@ -63,20 +66,55 @@ def _cpu_model():
     return None
 
 
-def cpu_baseline(x, Q, w, sample, F_gpu):
-    """The FP64 oracle's energy + force evaluation, stage by stage in the
-    order the oracle computes it, on this host: every mesh-side stage in full
-    (binning, moments, load, exact periodic solve; charge deposit, assembly,
-    exact adjoint solve), the per-charge stages (near-screen field, moment
-    adjoint, interpolation and its gradient, near pairs and pair forces) for
-    `sample` charges, scaled to all N."""
+# state shared with the oracle's worker processes (forked after it is set)
+_CPU = {}
+
+
+def _cpu_chunk(tgt):
+    """Per-charge stages of the oracle for one chunk of target charges."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import adjoint as oadj, fep3m as ofe
+
+    g = _CPU
+    P = g["P"]
+    n, p, q, d, h = P.n, P.p, P.q, P.d, P.h
+    with threadpool_limits(1):
+        e, e_lin, u, Q = g["e"], g["e_lin"], g["u"], g["Q"]
+        uel, inv = np.unique(e_lin[tgt], return_inverse=True)
+        W = ofe.element_phi(g["phi"], p, n, uel) - ofe.near_field(g["C"], g["T"], n, P.n_sr, uel)
+        A = oadj.moment_adjoint(g["lam"], g["gE"], g["T"], n, p, q, P.n_sr, uel)
+        ut, Qt = u[tgt], Q[tgt]
+        mesh_grad = 0.5 * Qt[:, None] * (np.einsum("nkm,nm->nk", oadj.basis_gradients(p, ut), W[inv])
+                                         + np.einsum("nka,na->nk", oadj.monomial_gradients(ut, d), A[inv]))
+        Phi_m = np.sum(W[inv] * ofe.basis_values(p, ut), axis=1)
+        Phi_p = ofe.pair_potential(e, e_lin, u, Q, n, P.n_sr, tgt)
+        dUp = oadj.pair_forces(e, e_lin, u, Q, n, P.n_sr, tgt)
+        F_s = -(dUp + mesh_grad) / h**2
+    return tgt, F_s, (Phi_p + Phi_m) / h
+
+
+def cpu_baseline_child(workload, sample, out_path):
+    """The FP64 oracle's energy + force evaluation on this host, in a process
+    that never touches the GPU: the mesh-side stages in full (binning,
+    moments, load, exact periodic solve; charge deposit, assembly, exact
+    adjoint solve) with BLAS on every core, then the per-charge stages
+    (near-screen field, moment adjoint, interpolation and its gradient, near
+    pairs and pair forces) for `sample` seeded charges, in chunks over one
+    worker process per core."""
+    import multiprocessing as mp
+
     import numpy as np
     from threadpoolctl import threadpool_info
 
+    import workloads
     from oracle import adjoint as oadj, fep3m as ofe, mesh, screens, tables
 
+    w = workloads.WORKLOADS[workload]
+    x, Q = workloads.make(w)
     P = ofe.Params(L=w.L, n=w.n)
-    n, p, q, d, h = P.n, P.p, P.q, P.d, P.h
+    n, p, q, d = P.n, P.p, P.q, P.d
     t0 = time.perf_counter()
     T = tables.screen_tables(p, q, P.n_sr, P.B, P.table_bc)
     t_tables = time.perf_counter() - t0
@@ -91,21 +129,17 @@ def cpu_baseline(x, Q, w, sample, F_gpu):
     lam = mesh.solve_periodic(G, p, n)
     lam = lam - mesh.mean_value(lam, p, n)
     t_fixed = time.perf_counter() - t0
+    blas_threads = max([dd.get("num_threads", 1) for dd in threadpool_info()] + [1])
     rng = np.random.default_rng(0)
     tgt = np.sort(rng.choice(len(Q), min(sample, len(Q)), replace=False))
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    _CPU.update(P=P, e=e, e_lin=e_lin, u=u, Q=Q, C=C, T=T, phi=phi, lam=lam, gE=gE)
+    chunks = [c for c in np.array_split(tgt, 4 * nproc) if len(c)]
     t0 = time.perf_counter()
-    uel, inv = np.unique(e_lin[tgt], return_inverse=True)
-    W = ofe.element_phi(phi, p, n, uel) - ofe.near_field(C, T, n, P.n_sr, uel)
-    A = oadj.moment_adjoint(lam, gE, T, n, p, q, P.n_sr, uel)
-    ut, Qt = u[tgt], Q[tgt]
-    mesh_grad = 0.5 * Qt[:, None] * (np.einsum("nkm,nm->nk", oadj.basis_gradients(p, ut), W[inv])
-                                     + np.einsum("nka,na->nk", oadj.monomial_gradients(ut, d), A[inv]))
-    Phi_m = np.sum(W[inv] * ofe.basis_values(p, ut), axis=1)
-    Phi_p = ofe.pair_potential(e, e_lin, u, Q, n, P.n_sr, tgt)
-    dUp = oadj.pair_forces(e, e_lin, u, Q, n, P.n_sr, tgt)
-    F_s = -(dUp + mesh_grad) / h**2
+    with mp.get_context("fork").Pool(nproc) as pool:
+        parts = pool.map(_cpu_chunk, chunks)
     t_tgt = time.perf_counter() - t0
-    t_step = t_fixed + t_tgt * len(Q) / len(tgt)
+    F_s = np.concatenate([pp[1] for pp in parts])
     counts = np.bincount(e_lin, minlength=n**3).reshape(n, n, n)
     block = np.zeros_like(counts)
     r = range(-P.n_sr, P.n_sr + 1)
@@ -114,22 +148,39 @@ def cpu_baseline(x, Q, w, sample, F_gpu):
             for dx in r:
                 block += np.roll(counts, (dz, dy, dx), axis=(0, 1, 2))
     pairs = float(np.sum(counts * block) - len(Q))
-    threads = max([dd.get("num_threads", 1) for dd in threadpool_info()] + [1])
-    err = float(np.linalg.norm(F_gpu[tgt] - F_s) / np.linalg.norm(F_s))
-    del Phi_m, Phi_p
-    return {
-        "value": pairs / t_step,
-        "unit": "pair interactions/s",
-        "cores": int(threads),
-        "cpu_model": _cpu_model(),
-        "kind": "oracle",
-        "sample": (f"energy+forces; mesh side in full ({t_fixed:.1f} s: binning, moments, load, exact periodic "
-                   f"solve, charge deposit, assembly, exact adjoint solve), per-charge side for {len(tgt)} of "
-                   f"{len(Q)} charges ({t_tgt:.1f} s), scaled to all charges; tables precomputed once "
-                   f"({t_tables:.1f} s, excluded); BLAS threads={threads}, per-charge loops single-threaded"),
-        "step_seconds_extrapolated": t_step,
-        "gpu_vs_oracle_force_rel_rms_on_sample": err,
-    }
+    t_step = t_fixed + t_tgt * len(Q) / len(tgt)
+    out = {"value": pairs / t_step, "unit": "pair interactions/s", "cores": int(nproc),
+           "blas_threads": int(blas_threads), "worker_processes": int(nproc), "nproc": int(os.cpu_count() or 1),
+           "cpu_model": _cpu_model(), "kind": "oracle",
+           "sample": (f"energy+forces; mesh side in full ({t_fixed:.1f} s: binning, moments, load, exact periodic "
+                      f"solve, charge deposit, assembly, exact adjoint solve; BLAS threads {blas_threads}), "
+                      f"per-charge side for {len(tgt)} of {len(Q)} charges over {nproc} worker processes "
+                      f"({t_tgt:.1f} s), scaled to all charges; tables precomputed once ({t_tables:.1f} s, "
+                      f"excluded)"),
+           "step_seconds_extrapolated": t_step, "targets": [int(t) for t in tgt],
+           "F_sample": F_s.tolist()}
+    with open(out_path, "w") as f:
+        json.dump(out, f)
+
+
+def cpu_baseline(workload, sample, F_gpu):
+    """Run the oracle's timing in a child process (no GPU there) and compare
+    the GPU forces with its sampled ones."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "cpu.json")
+        subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", workload, str(sample),
+                        path], check=True)
+        with open(path) as f:
+            out = json.load(f)
+    tgt = np.array(out.pop("targets"))
+    F_s = np.array(out.pop("F_sample"))
+    out["gpu_vs_oracle_force_rel_rms_on_sample"] = _rel_rms(F_gpu[tgt], F_s)
+    return out
 
 
 BATCH_WORKLOAD = "batch-64-n16"
@@ -253,7 +304,7 @@ def kernel_rooflines(prof, steps, mixed, near_fft=False):
     return {k: v for k, v in kernels.items() if v}
 
 
-def measure(name, precision, steps, warmup, forces=True, graph=False, solver=0, near_field=0):
+def measure(name, precision, steps, warmup, forces=True, graph=False, solver=0, near_field=0, **opts):
     """Run `warmup` + `steps` evaluations of one workload; device-resident
     inputs; returns timings, per-stage device times, kernel rooflines, the
     outputs of the last step (host copies) and the context statistics."""
@@ -267,9 +318,10 @@ def measure(name, precision, steps, warmup, forces=True, graph=False, solver=0, 
     dev = torch.device("cuda:0")
     tx = torch.from_numpy(x).to(dev)
     tQ = torch.from_numpy(Q).to(dev)
-    ctx = fp.Context(L, counts if len(counts) > 1 else counts[0], n,
+    q = opts.pop("q", 3)
+    ctx = fp.Context(L, counts if len(counts) > 1 else counts[0], n, q=q,
                      precision=fp.PRECISION_MIXED if mixed else fp.PRECISION_FP64, use_graph=1 if graph else 0,
-                     solver=solver, near_field=near_field)
+                     solver=solver, near_field=near_field, **opts)
 
     def step():
         if forces:
@@ -297,7 +349,7 @@ def measure(name, precision, steps, warmup, forces=True, graph=False, solver=0, 
         "kernels": kernel_rooflines(prof, steps, mixed, bool(st["near_fft"])),
         "stages_ms_per_step": {k: v["ms"] / steps for k, v in prof.items() if not k.startswith("fine_apply")},
         "out": {k: v.detach().cpu().numpy() for k, v in out.items()},
-        "x": x, "Q": Q, "mg_rtol": ctx.options.mg_rtol,
+        "x": x, "Q": Q, "mg_rtol": ctx.options.mg_rtol, "prof": prof, "steps": steps,
     }
     ctx.close()
     return res
@@ -337,6 +389,87 @@ def _rel_rms(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+# algorithmic bytes per launch of these kernels are recorded by the library
+# (fep3m.h, profile slots MOMENTS, LOAD, DEPOSIT, INTERP_KERNEL)
+HBM_STAGES = {"moments": "k_moments (charge projection: element moments)",
+              "load": "k_load (load-vector assembly)",
+              "deposit": "k_deposit + k_assemble (charge deposit on the order-p basis)",
+              "interp_kernel": "k_interp (mesh-to-charge interpolation)"}
+
+
+def hbm_stage_rooflines(name="uniform-1M-n64", precision="fp64", steps=3):
+    """HBM rate of the projection, load, deposit and interpolation kernels,
+    measured with every launch on one stream (no pair sum running beside
+    them): algorithmic bytes per launch / launch time (hipEvents)."""
+    r = measure(name, precision, steps, 1, pair_stream=0)
+    out = {}
+    for slot, label in HBM_STAGES.items():
+        s = r["prof"][slot]
+        if s["count"] == 0 or s["ms"] <= 0:
+            continue
+        ach = s["work"] / (s["ms"] * 1e-3) / 1e9
+        out[label] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": ach / PEAK_HBM_GBS, "avg_launch_ms": s["ms"] / s["count"],
+                      "algorithmic_gb_per_launch": s["work"] / s["count"] / 1e9}
+    return {"workload": name, "precision": precision, "pair_stream": 0, "kernels": out,
+            "ms_per_step_single_stream": r["ms_per_step"]}
+
+
+def ewald_fixture(name):
+    path = os.path.join(ROOT, "tests", "golden", f"ewald_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def ewald_error_full_size(r, support="one", q=3, n_sr=3):
+    """Method error of a full-size run against the committed Ewald reference
+    of its workload's sampled charges (tests/golden/ewald_<workload>.json,
+    written by the oracle): Phi shifted by the gauge constant c of the screen
+    (zero once the x^2 moments are cancelled), F unshifted."""
+    import numpy as np
+
+    from oracle import fep3m as ofe
+
+    fx = ewald_fixture(r["workload"])
+    if fx is None:
+        return None
+    tg = np.array(fx["targets"])
+    P = ofe.Params(L=r["L"], n=r["n"], q=q, support=support, n_sr=n_sr)
+    _, _, u = ofe.bin_particles(r["x"], P.L, P.n)
+    c = ofe.ewald_constant(u, r["Q"], P)
+    Phi = r["out"]["Phi"][tg] + c
+    F = r["out"]["F"][tg]
+    return {"reference": fx["reference"], "sampled_charges": len(tg),
+            "Phi_rel_rms": _rel_rms(Phi, np.array(fx["Phi"])), "F_rel_rms": _rel_rms(F, np.array(fx["F"])),
+            "gauge_constant": c}
+
+
+SCREEN_SWEEP = [("one", 3, 3), ("one", 4, 3), ("27", 1, 3), ("27", 2, 3), ("27", 3, 2), ("27", 3, 3), ("27", 4, 3)]
+
+
+def screen_sweep(name="uniform-1M-n64"):
+    """Time per energy+force step and method error against Ewald at full
+    size for the screen families and near-block radii (the headline screen
+    first)."""
+    import paper_1503_08509_amd as fp
+
+    rows = []
+    for support, q, nsr in SCREEN_SWEEP:
+        r = measure(name, "fp64", 2, 1, q=q, support=fp.SUPPORT_27 if support == "27" else fp.SUPPORT_ONE,
+                    n_sr=nsr, table_box=2 * nsr + 9)
+        err = ewald_error_full_size(r, support, q, nsr)
+        rows.append({"screen": f"{'27-element' if support == '27' else 'one-element'} q={q}",
+                     "near_block": f"{2 * nsr + 1}^3", "mesh_order": q + 2, "ms_per_step": r["ms_per_step"],
+                     "pair_interactions_per_s": r["value"], "mg_iterations": r["stats"]["mg_iterations"],
+                     "ewald": err})
+        print(f"# sweep {rows[-1]['screen']} {rows[-1]['near_block']}: {r['ms_per_step']:.1f} ms, "
+              f"Phi {err['Phi_rel_rms'] if err else float('nan'):.2e}", file=sys.stderr, flush=True)
+        del r
+    return {"workload": name, "rows": rows}
+
+
 def variant_summary(r, ref=None):
     import numpy as np
     k = r["kernels"]
@@ -365,6 +498,10 @@ def variant_summary(r, ref=None):
 
 def main():
     args = parse()
+    if args.cpu_baseline_child:   # the oracle's timing, in a process of its own (never touches the GPU)
+        wl, sample, path = args.cpu_baseline_child
+        cpu_baseline_child(wl, int(sample), path)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU (one process, no collectives); --gpus must be 1"}))
@@ -445,6 +582,7 @@ def main():
         del m
         c64 = measure("clustered-1M-n64", "fp64", 3, 1)
         variants["fp64 clustered-1M-n64"] = variant_summary(c64)
+        variants["fp64 clustered-1M-n64"]["method_error_vs_ewald"] = ewald_error_full_size(c64)
         cm = measure("clustered-1M-n64", "mixed", 3, 1)
         variants["mixed clustered-1M-n64"] = variant_summary(cm, c64)
         del c64, cm
@@ -481,12 +619,16 @@ def main():
                 fd, r if wl == "uniform-1M-n64" else None)
             del fd
         out["variants"] = variants
+        out["hbm_stages"] = hbm_stage_rooflines()
+        if not args.no_sweep:
+            out["screen_sweep"] = screen_sweep()
     if not args.no_cpu_baseline:
         out["method_error_vs_ewald"] = method_error_vs_ewald()
+        if args.workload in ("uniform-1M-n64", "clustered-1M-n64") and forces and not mixed:
+            out["method_error_vs_ewald_full_size"] = ewald_error_full_size(r)
         if forces and len(r["counts"]) == 1:
             import workloads
-            out["cpu_baseline"] = cpu_baseline(r["x"], r["Q"], workloads.WORKLOADS[r["workload"]], args.cpu_sample,
-                                               r["out"]["F"])
+            out["cpu_baseline"] = cpu_baseline(r["workload"], args.cpu_sample, r["out"]["F"])
         else:
             out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

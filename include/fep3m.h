@@ -150,6 +150,10 @@ typedef struct {
                             nor with solver = FEP3M_SOLVER_FDM.                */
   int32_t solver;        /* FEP3M_SOLVER_* (default: multigrid-preconditioned CG) */
   int32_t near_field;    /* FEP3M_NEAR_* (default AUTO)                          */
+  int32_t pair_stream;   /* 1 (default): on meshes of at least 2^16 elements
+                            the near-pair sum of a tuned context runs on a
+                            second stream beside the assignment and the mesh
+                            solve; 0: every launch on the caller's stream      */
   int32_t support;       /* FEP3M_SUPPORT_* (default ONE).  Every family but the
                             one-element q = 3 screen runs in float64 with the
                             direct near field (vector units); create returns
@@ -188,7 +192,12 @@ typedef struct {
  * NEAR and ADJ_NEAR on the FFT path (what each of their launches reads and
  * writes: the table spectrum once per product, every FFT pass's array in and
  * out) and for FINE_APPLY (the vectors each launch reads and writes, 8 bytes
- * per DOF each); 0 elsewhere. */
+ * per DOF each) and for MOMENTS (sorted positions and charges in, 32 bytes
+ * per charge, the element starts and moments), LOAD (the moments in, the
+ * load vector out), DEPOSIT (positions and charges in, the per-element
+ * deposits out and back in, the assembled vector out) and INTERP_KERNEL
+ * (per charge its position, pair potential and slot in and three potentials
+ * out, 60 bytes, plus the element field once); 0 elsewhere. */
 enum {
   FEP3M_PROF_SORT = 0,        /* wrap, bin, counting sort, gather          */
   FEP3M_PROF_ASSIGN = 1,      /* element moments, load assembly, projection */
@@ -203,7 +212,11 @@ enum {
   FEP3M_PROF_FORCES = 10,     /* forces: per-charge gradient and dU/dQ      */
   FEP3M_PROF_FINE_APPLY_F32 = 11, /* fine-level operator launches in float32
                                      (mixed-precision preconditioner)     */
-  FEP3M_PROF_SLOTS = 12
+  FEP3M_PROF_MOMENTS = 12,    /* element moments kernel (inside ASSIGN)   */
+  FEP3M_PROF_LOAD = 13,       /* load assembly kernel (inside ASSIGN)     */
+  FEP3M_PROF_DEPOSIT = 14,    /* forces: charge deposit and its assembly  */
+  FEP3M_PROF_INTERP_KERNEL = 15, /* interpolation kernel (inside INTERP)  */
+  FEP3M_PROF_SLOTS = 16
 };
 
 typedef struct {

@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
     _fields_ = [("n_sr", ctypes.c_int32), ("precision", ctypes.c_int32), ("mg_rtol", ctypes.c_double),
                 ("mg_max_iter", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("table_box", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("solver", ctypes.c_int32),
-                ("near_field", ctypes.c_int32), ("support", ctypes.c_int32)]
+                ("near_field", ctypes.c_int32), ("pair_stream", ctypes.c_int32), ("support", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -57,7 +57,7 @@ class Stats(ctypes.Structure):
 
 
 PROF_SLOTS = ["sort", "assign", "solve", "near", "pair", "interp", "fine_apply", "total",
-              "adj_solve", "adj_near", "forces", "fine_apply_f32"]
+              "adj_solve", "adj_near", "forces", "fine_apply_f32", "moments", "load", "deposit", "interp_kernel"]
 
 
 class Profile(ctypes.Structure):

@@ -989,7 +989,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   // and only on meshes of at least 2^16 elements in all: below that the pass
   // is too short to pay for the fork and the join (graph replays of 1000
   // charges on 8^3 elements: 1.25 -> 1.39 ms)
-  const bool overlap = !(opt.autotune && !tuned && !prof.on) && plan.kind == 0 && !arena &&
+  const bool overlap = !(opt.autotune && !tuned && !prof.on) && plan.kind == 0 && !arena && opt.pair_stream &&
                        size_t(nb) * n * n * n >= (size_t(1) << 16);
   if (overlap) {
     side_stream();
@@ -1010,14 +1010,18 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
     ~Join() { if (pending) (void)hipStreamWaitEvent(s, e, 0); }
   } join{stream, ev_join, overlap};
   stage_mark(FEP3M_PROF_ASSIGN, true);
+  stage_mark(FEP3M_PROF_MOMENTS, true);
   if (generic) {
     if (launch_moments_g(stream, nb, n, nl, N, start, sg, sQ, C) != 0)
       throw Status(FEP3M_ERR_UNSUPPORTED, "moments variant");
   } else {
     launch_moments(stream, nb, n, N, start, sg, sQ, C);
   }
+  stage_mark(FEP3M_PROF_MOMENTS, false);
+  stage_mark(FEP3M_PROF_LOAD, true);
   const int Kl = generic ? launch_load_g(stream, nb, n, p, span, nl, C, gw, b, partial)
                          : launch_load(stream, nb, n, p, C, gw, b, partial);
+  stage_mark(FEP3M_PROF_LOAD, false);
   if (Kl < 0) throw Status(FEP3M_ERR_UNSUPPORTED, "load variant");
   launch_sum_partials(stream, Kl, partial, cfgs(kCsLoad), nb);
   if (launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsLoad), b) != 0)
@@ -1057,11 +1061,13 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   if (overlap) join.now();
   else pair_pass(pair_forces);
   stage_mark(FEP3M_PROF_INTERP, true);
+  stage_mark(FEP3M_PROF_INTERP_KERNEL, true);
   const int is = mixed ? launch_interp_f32(stream, nb, off_d, p, n, N, 1.0 / h, bas, su, sel, Welf, phip_s, perm,
                                            phim_s, phi_s, Phi)
                        : launch_interp(stream, nb, off_d, p, n, N, 1.0 / h, bas, sg, Wel, phip_s, perm, phim_s, phi_s,
                                        Phi);
   if (is != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "interpolation variant");
+  stage_mark(FEP3M_PROF_INTERP_KERNEL, false);
   if (U) {
     const int Ke = launch_energy(stream, nb, off_d, N, sQ, phi_s, partial);
     launch_sum_partials(stream, Ke, partial, cfgs(kCsEnergy), nb);
@@ -1136,9 +1142,12 @@ void fep3m_ctx::pair_pass(bool pair_forces) {
 // second mesh solve, moment adjoint, per-charge gradients.
 // Adjoint right side: deposit g, assembly G, compatibility projection.
 void fep3m_ctx::adjoint_rhs() {
-  launch_deposit(stream, nb, p, n, N, bas, start, sg, sQ, gE);
+  stage_mark(FEP3M_PROF_DEPOSIT, true);
+  if (launch_deposit(stream, nb, p, n, N, bas, start, sg, sQ, gE) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "deposit variant");
   const int Ka = launch_assemble(stream, nb, p, n, gE, Gv, partial);
   if (Ka < 0) throw Status(FEP3M_ERR_UNSUPPORTED, "assembly variant");
+  stage_mark(FEP3M_PROF_DEPOSIT, false);
   launch_sum_partials(stream, Ka, partial, cfgs(kCsAdjLoad), nb);
   if (launch_sub_mass_ones(stream, nb, n, p, w1, cfgs(kCsAdjLoad), Gv) != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "projection variant");
@@ -1361,6 +1370,15 @@ void fep3m_ctx::profile_collect() {
   if (prof.marked & (1u << FEP3M_PROF_PAIR))
     prof.acc.work[FEP3M_PROF_PAIR] += (prof.pair_forces ? 20.0 : 11.0) * double(stats.near_pairs);
   if (prof.marked & (1u << FEP3M_PROF_ADJ_NEAR)) prof.acc.work[FEP3M_PROF_ADJ_NEAR] += adj_work;
+  // bytes of the assignment, deposit and interpolation kernels
+  const double P3 = double(lv[0].ndof) * nb, Nd = double(N);
+  const double bytes[4] = {32.0 * Nd + (4.0 + 8.0 * na) * Me,                  // moments
+                           8.0 * na * Me + 8.0 * P3,                           // load
+                           32.0 * Nd + 2.0 * 8.0 * NM * Me + 8.0 * P3,         // deposit and assembly
+                           60.0 * Nd + (mixed ? 4.0 : 8.0) * NM * Me};         // interpolation
+  const int slots[4] = {FEP3M_PROF_MOMENTS, FEP3M_PROF_LOAD, FEP3M_PROF_DEPOSIT, FEP3M_PROF_INTERP_KERNEL};
+  for (int k = 0; k < 4; ++k)
+    if (prof.marked & (1u << slots[k])) prof.acc.work[slots[k]] += bytes[k];
   for (int k = 0; k < prof.kused; ++k) {
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, prof.kev[2 * k], prof.kev[2 * k + 1]), "elapsed");
@@ -1405,6 +1423,7 @@ bool valid_options(const fep3m_options &o, std::string &why) {
   if (o.solver != FEP3M_SOLVER_MG && o.solver != FEP3M_SOLVER_FDM) { why = "unknown solver"; return false; }
   if (o.near_field < FEP3M_NEAR_AUTO || o.near_field > FEP3M_NEAR_FFT) { why = "unknown near_field"; return false; }
   if (o.support != FEP3M_SUPPORT_ONE && o.support != FEP3M_SUPPORT_27) { why = "unknown support"; return false; }
+  if (o.pair_stream != 0 && o.pair_stream != 1) { why = "pair_stream must be 0 or 1"; return false; }
   if (o.table_box % 2 == 0 || o.table_box < 2 * o.n_sr + 3 || o.table_box > 41) {
     why = "table_box must be odd, > 2 n_sr + 1 and <= 41";
     return false;
@@ -1428,6 +1447,7 @@ int fep3m_default_options(fep3m_options *opt) {
   opt->use_graph = 0;
   opt->solver = FEP3M_SOLVER_MG;
   opt->near_field = FEP3M_NEAR_AUTO;
+  opt->pair_stream = 1;
   opt->support = FEP3M_SUPPORT_ONE;
   return FEP3M_OK;
 }

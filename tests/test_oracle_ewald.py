@@ -5,6 +5,7 @@ import os
 
 import numpy as np
 
+import workloads
 from oracle import ewald
 
 HERE = os.path.dirname(__file__)
@@ -77,3 +78,19 @@ def test_direct_image_sum_equals_ewald_plus_surface_term():
     Uext = (R2 * U2 - R1 * U1) / (R2 - R1)
     assert abs(U2 - target) < 0.05 * abs(ewald.surface_term(x, Q)) + 1e-3
     assert abs(Uext - target) < 2e-4 * abs(target)
+
+
+def test_sampled_ewald_matches_full_sum():
+    """The large-N form (real space to rcut = L with alpha = 6/L, reciprocal
+    cube |m| <= 12 from separable structure factors) equals the paper's
+    setting (alpha = 2.5, two image shells, four modes) on a small system,
+    and does not depend on its own splitting (alpha 6 vs 7.5, mmax raised
+    with it): both sums converge to the same periodic potential."""
+    x, Q = workloads.uniform(300, seed=5, charges="uniform")
+    t = np.array([0, 7, 150, 299])
+    a = ewald.ewald(x, Q, forces=True, targets=t)
+    b = ewald.ewald_sampled(x, Q, t, forces=True)
+    c = ewald.ewald_sampled(x, Q, t, alpha=7.5, mmax=15, forces=True)
+    for r in (b, c):
+        assert np.abs(r["Phi"] - a["Phi"]).max() < 1e-12 * np.abs(a["Phi"]).max()
+        assert np.abs(r["F"] - a["F"]).max() < 1e-12 * np.abs(a["F"]).max()
