@@ -206,6 +206,12 @@ struct fep3m_ctx {
   rocblas_handle blas = nullptr;
   double *fdmV = nullptr, *fdmLam = nullptr;
   int fdm_i0 = 0;
+  // the same solve by Fourier analysis over the element lattice (meshes
+  // whose edge is a power of two): per-frequency eigenvectors of the 1-D
+  // blocks, twiddles, and the element-major complex work array
+  bool fs_ready = false;
+  double2 *fsW = nullptr, *fsTw = nullptr, *fsZ = nullptr;
+  double *fsL = nullptr;
   // pair-sum work decomposition (autotuned): kind 0 one wave per element,
   // kind 1 persistent waves over items of `titem` targets
   struct PairPlan {
@@ -663,6 +669,27 @@ void fep3m_ctx::build_near_fft() {
 }
 
 void fep3m_ctx::build_fdm() {
+  if (fft_size_ok(n)) {
+    Vec wr, wi, lamf;
+    periodic_fourier_eigen(p, n, wr, wi, lamf);
+    std::vector<double2> w(wr.size()), tw(n);
+    for (size_t i = 0; i < wr.size(); ++i) w[i] = make_double2(wr[i], wi[i]);
+    for (int j = 0; j < n; ++j) {
+      const double t = 2.0 * M_PI * double(j) / double(n);
+      tw[j] = make_double2(std::cos(t), -std::sin(t));
+    }
+    fsW = alloc<double2>(w.size(), "Fourier block eigenvectors");
+    fsL = alloc<double>(lamf.size(), "Fourier block eigenvalues");
+    fsTw = alloc<double2>(tw.size(), "FFT twiddles");
+    // two real systems per complex one: the forward and adjoint systems of
+    // every configuration
+    fsZ = alloc<double2>(size_t(nb) * n * n * n * (p * p * p), "Fourier solve work array");
+    hip_check(hipMemcpy(fsW, w.data(), w.size() * sizeof(double2), hipMemcpyHostToDevice), "upload");
+    hip_check(hipMemcpy(fsL, lamf.data(), lamf.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+    hip_check(hipMemcpy(fsTw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice), "upload");
+    fs_ready = true;
+    return;
+  }
   const LevelOp &op = lv[0].op;
   Mat K1, M1;
   assemble_1d(op.p, op.n, true, K1, M1);
@@ -704,6 +731,10 @@ void blas_check(rocblas_status s, const char *what) {
 void fep3m_ctx::fdm_solve(const double *rhs, double *sol, int which) {
   const int P = lv[0].op.P;
   const size_t per = lv[0].ndof, nd = per * nbs;
+  if (fs_ready) {
+    if (launch_fs_solve(stream, nbs, n, p, rhs, sol, fsZ, fsTw, fsW, fsL) != 0)
+      throw Status(FEP3M_ERR_UNSUPPORTED, "Fourier solve variant");
+  } else {
   const rocblas_int iP = P, iP2 = P * P;
   const double one = 1.0, zero = 0.0;
   blas_check(rocblas_set_stream(blas, stream), "rocblas stream");
@@ -727,6 +758,7 @@ void fep3m_ctx::fdm_solve(const double *rhs, double *sol, int which) {
                                            rocblas_stride(iP2), rocblas_int(nbs) * iP), "fdm y back");
   blas_check(rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, iP, rocblas_int(nbs) * iP2, iP, &one,
                            fdmV, iP, A, iP, &zero, sol, iP), "fdm x back");
+  }
   // achieved residual, per configuration
   launch_sum_partials(stream, launch_dot(stream, nbs, per, rhs, rhs, partial), partial, pcs.bn2, nbs);
   apply0<double>(sol, rhs, qv, nullptr, nullptr, 0.0, 0.0, kResidual, nullptr);

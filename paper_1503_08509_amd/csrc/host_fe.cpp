@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <stdexcept>
 
 namespace fep3m {
@@ -333,6 +334,86 @@ Mat load_weights(int p, const Screen1D &s) {
       }
     }
   return g;
+}
+
+void periodic_fourier_eigen(int p, int n, Vec &Wre, Vec &Wim, Vec &lam) {
+  using C = std::complex<double>;
+  Mat ke, me;
+  element_matrices(p, ke, me);
+  Wre.assign(size_t(n) * p * p, 0.0);
+  Wim.assign(size_t(n) * p * p, 0.0);
+  lam.assign(size_t(n) * p, 0.0);
+  for (int f = 0; f < n; ++f) {
+    const double th = 2.0 * M_PI * double(f) / double(n), c = std::cos(th), sn = std::sin(th);
+    std::vector<C> Kc(size_t(p) * p), Mc(size_t(p) * p);
+    auto block = [&](const Mat &e, std::vector<C> &out) {
+      for (int k = 0; k < p; ++k)
+        for (int l = 0; l < p; ++l) out[size_t(k) * p + l] = e(k, l);
+      out[0] += e(p, p);                                    // the vertex shared with the element below
+      for (int k = 0; k < p; ++k) {
+        out[size_t(k) * p] += e(k, p) * C(c, sn);           // owned node k -> vertex of the element above
+        out[k] += e(p, k) * C(c, -sn);                      // vertex -> owned node k of the element below
+      }
+    };
+    block(ke, Kc);
+    block(me, Mc);
+    // real symmetric embedding [[Re, -Im], [Im, Re]] of both Hermitian blocks
+    Mat KR(2 * p, 2 * p), MR(2 * p, 2 * p);
+    for (int k = 0; k < p; ++k)
+      for (int l = 0; l < p; ++l) {
+        const C a = Kc[size_t(k) * p + l], b = Mc[size_t(k) * p + l];
+        KR(k, l) = KR(k + p, l + p) = a.real();
+        KR(k, l + p) = -a.imag();
+        KR(k + p, l) = a.imag();
+        MR(k, l) = MR(k + p, l + p) = b.real();
+        MR(k, l + p) = -b.imag();
+        MR(k + p, l) = b.imag();
+      }
+    Vec w;
+    Mat V;
+    sym_gen_eig(KR, MR, w, V);
+    // every eigenvalue appears twice (z and i z); keep one M^-orthonormal
+    // complex vector per complex dimension, in ascending order
+    auto mdot = [&](const std::vector<C> &a, const std::vector<C> &b) {
+      C s = 0.0;
+      for (int k = 0; k < p; ++k) {
+        C t = 0.0;
+        for (int l = 0; l < p; ++l) t += Mc[size_t(k) * p + l] * b[l];
+        s += std::conj(a[k]) * t;
+      }
+      return s;
+    };
+    std::vector<std::vector<C>> acc;
+    std::vector<double> accl;
+    for (int col = 0; col < 2 * p && int(acc.size()) < p; ++col) {
+      std::vector<C> z(p);
+      for (int k = 0; k < p; ++k) z[k] = C(V(k, col), V(k + p, col));
+      for (const auto &a : acc) {
+        const C pr = mdot(a, z);
+        for (int k = 0; k < p; ++k) z[k] -= pr * a[k];
+      }
+      const double nrm = mdot(z, z).real();
+      if (nrm < 0.25) continue;
+      const double sc = 1.0 / std::sqrt(nrm);
+      for (C &v : z) v *= sc;
+      acc.push_back(z);
+      accl.push_back(w[col]);
+    }
+    if (int(acc.size()) != p) throw std::runtime_error("Fourier block eigenvectors");
+    if (f == 0) {   // constants: the mode of smallest eigenvalue
+      int i0 = 0;
+      for (int i = 1; i < p; ++i)
+        if (std::fabs(accl[i]) < std::fabs(accl[i0])) i0 = i;
+      accl[i0] = 0.0;
+    }
+    for (int i = 0; i < p; ++i) {
+      lam[size_t(f) * p + i] = accl[i];
+      for (int k = 0; k < p; ++k) {
+        Wre[(size_t(f) * p + k) * p + i] = acc[i][k].real();
+        Wim[(size_t(f) * p + k) * p + i] = acc[i][k].imag();
+      }
+    }
+  }
 }
 
 void assemble_1d(int p, int ne, bool periodic, Mat &K, Mat &M) {

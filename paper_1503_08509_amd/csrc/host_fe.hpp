@@ -68,6 +68,15 @@ Screen1D make_screen(int q, int support = 0);
 // node j, j = 0 at the lower end of the support.
 Mat load_weights(int p, const Screen1D &s);
 
+// Fourier blocks of the periodic order-p 1-D operators over n unit
+// elements: for each frequency f < n the p x p Hermitian pencil
+// K^(f) = B0 + B+ w^f + B- w^-f (w = exp(2 pi i / n), B+- the couplings of
+// an element's owned nodes to the next / previous element) and M^(f)
+// alike, and its generalized eigenvectors: W[f][k][i] (component k of mode
+// i, real and imaginary parts) with W^H M^ W = I, eigenvalues lam[f][i]
+// ascending.  The null mode (constants, f = 0) has lam exactly 0.
+void periodic_fourier_eigen(int p, int n, Vec &Wre, Vec &Wim, Vec &lam);
+
 // Assembled 1-D matrices of `ne` unit elements, order p.
 // periodic: p*ne DOFs; otherwise p*ne + 1 DOFs (all nodes).
 void assemble_1d(int p, int ne, bool periodic, Mat &K, Mat &M);

@@ -1,0 +1,170 @@
+// Exact periodic mesh solve by Fourier analysis over the element lattice
+// (the solver option of fep3m.h for meshes whose edge is a power of two).
+//
+// On the uniform periodic mesh the 1-D operators K1, M1 are block circulant:
+// node p e + k (owned local index k < p of element e) couples only to the
+// nodes of elements e - 1, e, e + 1.  A DFT over the element index turns them
+// into p x p Hermitian blocks per frequency f,
+//   K^(f) = B0 + B+ w^f + B- w^-f,   w = exp(2 pi i / n),
+// and the 3-D operator K = K1 (x) M1 (x) M1 + ... into independent p^3 x p^3
+// blocks per frequency triple.  With the generalized eigenvectors of each
+// 1-D block, K^(f) W_f = M^(f) W_f diag(lam_f), W_f^H M^(f) W_f = I, the block
+// solve is  x^ = (W (x) W (x) W) diag(1 / (lam_x + lam_y + lam_z)) (W (x) W (x) W)^H b^
+// (the constant mode, all three null modes at f = 0, dropped: int phi = 0).
+//
+// Data path per solve: gather the mesh vector into element-major complex
+// channels [E][kz][ky][kx] (two real systems as the real and imaginary
+// parts of one complex system: the operator is real), three FFT passes over
+// the element lattice, the per-frequency block solve, three inverse passes,
+// scatter back (real part: first system, imaginary part: second).
+#include "kernels.hpp"
+
+namespace fep3m {
+namespace {
+
+// Mesh vectors of systems 2c and 2c + 1 -> complex system c, element-major.
+template <int PO>
+__global__ __launch_bounds__(256) void k_fs_gather(int n, int nsys, const double *__restrict__ v,
+                                                   double2 *__restrict__ Z) {
+  constexpr int NCH = PO * PO * PO;
+  const int P = PO * n;
+  const size_t per = size_t(P) * P * P;
+  const int ncs = (nsys + 1) / 2;
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < per * ncs; t += size_t(gridDim.x) * blockDim.x) {
+    const int cs = int(t / per);
+    const size_t g = t % per;
+    const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
+    const int ex = gx / PO, ey = gy / PO, ez = gz / PO;
+    const int k = ((gz - PO * ez) * PO + (gy - PO * ey)) * PO + (gx - PO * ex);
+    const double re = v[size_t(2 * cs) * per + g];
+    const double im = (2 * cs + 1 < nsys) ? v[size_t(2 * cs + 1) * per + g] : 0.0;
+    Z[(size_t(cs) * n * n * n + (size_t(ez) * n + ey) * n + ex) * NCH + k] = make_double2(re, im);
+  }
+}
+
+template <int PO>
+__global__ __launch_bounds__(256) void k_fs_scatter(int n, int nsys, const double2 *__restrict__ Z,
+                                                    double *__restrict__ v) {
+  constexpr int NCH = PO * PO * PO;
+  const int P = PO * n;
+  const size_t per = size_t(P) * P * P;
+  const int ncs = (nsys + 1) / 2;
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < per * ncs; t += size_t(gridDim.x) * blockDim.x) {
+    const int cs = int(t / per);
+    const size_t g = t % per;
+    const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
+    const int ex = gx / PO, ey = gy / PO, ez = gz / PO;
+    const int k = ((gz - PO * ez) * PO + (gy - PO * ey)) * PO + (gx - PO * ex);
+    const double2 z = Z[(size_t(cs) * n * n * n + (size_t(ez) * n + ey) * n + ex) * NCH + k];
+    v[size_t(2 * cs) * per + g] = z.x;
+    if (2 * cs + 1 < nsys) v[size_t(2 * cs + 1) * per + g] = z.y;
+  }
+}
+
+// One frequency triple per block: the p^3 values of complex system cs at
+// (fx, fy, fz), transformed by W^H along x, y, z, divided by the eigenvalue
+// sums (times `scale`, the inverse transform's 1 / n^3), transformed back.
+// W[f][k][i]: component k of mode i of frequency f; lam[f][i].
+template <int PO>
+__global__ __launch_bounds__(256) void k_fs_solve(int n, const double2 *__restrict__ W, const double *__restrict__ lam,
+                                                  double2 *__restrict__ Z, double scale) {
+  constexpr int NCH = PO * PO * PO, P2 = PO * PO;
+  __shared__ double2 buf[2][NCH];
+  __shared__ double2 w[3][P2];
+  __shared__ double l[3][PO];
+  const size_t M = size_t(n) * n * n;
+  const size_t f = blockIdx.x % M, cs = blockIdx.x / M;
+  const int fx = int(f % n), fy = int((f / n) % n), fz = int(f / (size_t(n) * n));
+  const int tid = threadIdx.x;
+  const int fa[3] = {fx, fy, fz};
+  for (int i = tid; i < 3 * P2; i += blockDim.x) w[i / P2][i % P2] = W[size_t(fa[i / P2]) * P2 + i % P2];
+  for (int i = tid; i < 3 * PO; i += blockDim.x) l[i / PO][i % PO] = lam[size_t(fa[i / PO]) * PO + i % PO];
+  double2 *zf = Z + (cs * M + f) * NCH;
+  const bool act = tid < NCH;
+  const int kx = tid % PO, ky = (tid / PO) % PO, kz = tid / P2;
+  if (act) buf[0][tid] = zf[tid];
+  __syncthreads();
+  // y = (W^H)_z (W^H)_y (W^H)_x b: out index i along the axis takes
+  // sum_k conj(W[k][i]) in[k]
+  int cur = 0;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (act) {
+      const int i = ax == 0 ? kx : (ax == 1 ? ky : kz);
+      const int stride = ax == 0 ? 1 : (ax == 1 ? PO : P2);
+      const int base = tid - i * stride;
+      double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < PO; ++k) {
+        const double2 a = w[ax][k * PO + i], b = buf[cur][base + k * stride];
+        s.x += a.x * b.x + a.y * b.y;
+        s.y += a.x * b.y - a.y * b.x;
+      }
+      buf[cur ^ 1][tid] = s;
+    }
+    cur ^= 1;
+    __syncthreads();
+  }
+  if (act) {
+    const double den = l[0][kx] + l[1][ky] + l[2][kz];
+    const double r = den == 0.0 ? 0.0 : scale / den;
+    buf[cur][tid].x *= r;
+    buf[cur][tid].y *= r;
+  }
+  __syncthreads();
+  // x = W_x W_y W_z y: out index k along the axis takes sum_i W[k][i] in[i]
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (act) {
+      const int k = ax == 0 ? kx : (ax == 1 ? ky : kz);
+      const int stride = ax == 0 ? 1 : (ax == 1 ? PO : P2);
+      const int base = tid - k * stride;
+      double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < PO; ++i) {
+        const double2 a = w[ax][k * PO + i], b = buf[cur][base + i * stride];
+        s.x += a.x * b.x - a.y * b.y;
+        s.y += a.x * b.y + a.y * b.x;
+      }
+      buf[cur ^ 1][tid] = s;
+    }
+    cur ^= 1;
+    __syncthreads();
+  }
+  if (act) zf[tid] = buf[cur][tid];
+}
+
+inline int grid_of(size_t count) {
+  size_t g = (count + 255) / 256;
+  if (g < 1) g = 1;
+  return int(g > 65536 ? 65536 : g);
+}
+
+template <int PO>
+int fs_solve_impl(hipStream_t s, int nsys, int n, const double *rhs, double *out, double2 *Z, const double2 *tw,
+                  const double2 *W, const double *lam) {
+  const size_t P = size_t(PO) * n, per = P * P * P;
+  const int ncs = (nsys + 1) / 2;
+  const size_t M = size_t(n) * n * n;
+  hipLaunchKernelGGL(k_fs_gather<PO>, dim3(grid_of(per * ncs)), dim3(256), 0, s, n, nsys, rhs, Z);
+  if (launch_fft3_nodes(s, ncs, n, PO * PO * PO, Z, tw, false) != 0) return -1;
+  hipLaunchKernelGGL(k_fs_solve<PO>, dim3(unsigned(M * ncs)), dim3(256), 0, s, n, W, lam, Z, 1.0 / double(M));
+  if (launch_fft3_nodes(s, ncs, n, PO * PO * PO, Z, tw, true) != 0) return -1;
+  hipLaunchKernelGGL(k_fs_scatter<PO>, dim3(grid_of(per * ncs)), dim3(256), 0, s, n, nsys, Z, out);
+  return 0;
+}
+
+}  // namespace
+
+int launch_fs_solve(hipStream_t s, int nsys, int n, int p, const double *rhs, double *out, double2 *Z,
+                    const double2 *tw, const double2 *W, const double *lam) {
+  switch (p) {
+    case 3: return fs_solve_impl<3>(s, nsys, n, rhs, out, Z, tw, W, lam);
+    case 4: return fs_solve_impl<4>(s, nsys, n, rhs, out, Z, tw, W, lam);
+    case 5: return fs_solve_impl<5>(s, nsys, n, rhs, out, Z, tw, W, lam);
+    case 6: return fs_solve_impl<6>(s, nsys, n, rhs, out, Z, tw, W, lam);
+    default: return -1;
+  }
+}
+
+}  // namespace fep3m

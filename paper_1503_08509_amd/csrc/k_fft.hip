@@ -429,6 +429,17 @@ void fft_pass(hipStream_t s, int nb, int n, int nch, int axis, const double2 *sr
     fft_pass_n<108, INV, EPI, WT>(s, nb, n, axis, src, dst, tw, phi, W, po);
 }
 
+template <bool INV>
+int fft_pass_nodes(hipStream_t s, int nb, int n, int nch, int axis, double2 *z, const double2 *tw) {
+  switch (nch) {
+    case 27: fft_pass_n<27, INV, 0, double>(s, nb, n, axis, z, z, tw, nullptr, nullptr, 0); return 0;
+    case 64: fft_pass_n<64, INV, 0, double>(s, nb, n, axis, z, z, tw, nullptr, nullptr, 0); return 0;
+    case 125: fft_pass_n<125, INV, 0, double>(s, nb, n, axis, z, z, tw, nullptr, nullptr, 0); return 0;
+    case 216: fft_pass_n<216, INV, 0, double>(s, nb, n, axis, z, z, tw, nullptr, nullptr, 0); return 0;
+    default: return -1;
+  }
+}
+
 // forward 3-D transform: src (real pairs) -> dst, x then y then z
 void fft3_forward(hipStream_t s, int nb, int n, int nch, const double2 *src, double2 *dst, const double2 *tw) {
   fft_pass<false, 0, double>(s, nb, n, nch, 0, src, dst, tw, nullptr, nullptr, 0);
@@ -437,6 +448,16 @@ void fft3_forward(hipStream_t s, int nb, int n, int nch, const double2 *src, dou
 }
 
 }  // namespace
+
+int launch_fft3_nodes(hipStream_t s, int nb, int n, int nch, double2 *z, const double2 *tw, bool inverse) {
+  if (!fft_size_ok(n)) return -1;
+  for (int a = 0; a < 3; ++a) {
+    const int axis = inverse ? 2 - a : a;
+    if ((inverse ? fft_pass_nodes<true>(s, nb, n, nch, axis, z, tw) : fft_pass_nodes<false>(s, nb, n, nch, axis, z, tw)) != 0)
+      return -1;
+  }
+  return 0;
+}
 
 void launch_spec_build(hipStream_t s, int n, int nsr, int p, const double *T, const double2 *twf, double2 *S) {
   const int nm = (p + 1) * (p + 1) * (p + 1);

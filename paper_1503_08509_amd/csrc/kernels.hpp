@@ -114,6 +114,15 @@ int launch_psi_fft_finish(hipStream_t s, int nb, int n, int p, const double2 *tw
 int launch_adj_fft_finish(hipStream_t s, int nb, int n, int p, const double *lam, const double *gw, const double2 *za,
                           double *A);
 
+// exact periodic solve by Fourier analysis over the element lattice
+// (k_fdm.hip): nsys real systems (pairs share one complex work system),
+// n a power of two in [8, 64], p = 3..6.  Z: ceil(nsys / 2) n^3 p^3
+// complex; W, lam from periodic_fourier_eigen; tw: exp(-2 pi i j / n).
+int launch_fs_solve(hipStream_t s, int nsys, int n, int p, const double *rhs, double *out, double2 *Z,
+                    const double2 *tw, const double2 *W, const double *lam);
+// in-place 3-D FFT of [nb][z][y][x][nch] complex arrays, nch = p^3 (k_fft.hip)
+int launch_fft3_nodes(hipStream_t s, int nb, int n, int nch, double2 *z, const double2 *tw, bool inverse);
+
 // mesh (k_mesh.hip).  nb configurations; per-configuration reductions
 // write nb * K block partials (K = seg_blocks(nb, per) unless a launcher
 // returns its own K) that launch_sum_partials folds into out[0 .. nb).

@@ -72,3 +72,20 @@ def test_fdm_batch_mixed_graph(torch):
         og = g.energy_forces(tx, tQ, Phi=True)
         np.testing.assert_array_equal(og["F"].cpu().numpy(), bf["F"].cpu().numpy())
     assert g.stats()["graph_replays"] == 0     # this solver always runs eagerly
+
+
+@pytest.mark.parametrize("n,q,support", [(16, 3, 0), (8, 1, 1), (8, 4, 0)])
+def test_fourier_solver_energy_only_and_screen_families(torch, n, q, support):
+    """The Fourier-analysis path of the exact solver (meshes whose edge is a
+    power of two): a single real system (energy only: the complex work
+    system's imaginary part is empty) and the orders 3 and 6 of the other
+    screen families, against the oracle's exact solve."""
+    x, Q = workloads.uniform(500, seed=40 + n + q, charges="uniform")
+    sup = "27" if support else "one"
+    ctx = fp.Context(1.0, len(Q), n, q=q, support=support, solver=fp.SOLVER_FDM)
+    Phi, U = ctx.energy(torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda())
+    st = fep3m.run(x, Q, fep3m.Params(L=1.0, n=n, q=q, support=sup), stages=True)
+    phi = ctx.stage("phi").cpu().numpy()
+    assert np.abs(phi - st["phi"].ravel()).max() < 1e-11 * np.abs(st["phi"]).max()
+    assert _rel(Phi.cpu().numpy(), st["Phi"]) < 1e-10
+    assert ctx.stats()["mg_rel_residual"] < 1e-11
