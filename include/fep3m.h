@@ -75,14 +75,21 @@ enum {
 enum {
   FEP3M_SOLVER_MG = 0,   /* PCG with a p/h multigrid V-cycle (Chebyshev-Jacobi
                             smoothing), iterated to mg_rtol                     */
-  FEP3M_SOLVER_FDM = 1   /* exact periodic solve by fast diagonalisation: the
-                            1-D pencil K1 v = lam M1 v is solved once at create
-                            (host, about 2 s for 320 nodes per axis), and each
-                            solve applies V^T along x, y, z, divides by
-                            lam_i + lam_j + lam_k and applies V back; the
-                            dense 1-D transforms are float64 GEMMs (rocBLAS).
-                            float64 in both precisions; mg_rtol is not used
-                            (the achieved residual is still measured).  */
+  FEP3M_SOLVER_FDM = 1   /* exact periodic solve by fast diagonalisation.  On
+                            meshes whose edge is a power of two in [8, 64]:
+                            the 1-D operators are block circulant over the
+                            element index, so a DFT over the element lattice
+                            leaves p x p Hermitian pencils per frequency,
+                            diagonalised once at create; each solve gathers
+                            the vector into element-major channels (two real
+                            systems per complex one), runs 3-D FFTs, divides
+                            by lam_x + lam_y + lam_z in each frequency's
+                            eigenbasis and transforms back.  Other meshes: the
+                            P x P pencil K1 v = lam M1 v (host, about 2 s for
+                            320 nodes per axis) and dense tiled transforms
+                            along x, y, z.  float64 in both precisions;
+                            mg_rtol is not used (the achieved residual is
+                            still measured and must be <= 1e-9).            */
 };
 
 /* Screen supports (Section 2.1 and the Discussion, Section 5). */

@@ -21,7 +21,6 @@
 #include "fep3m.h"
 #include "host_fe.hpp"
 #include "host_tables.hpp"
-#include <rocblas/rocblas.h>
 
 #include "kernels.hpp"
 
@@ -203,7 +202,6 @@ struct fep3m_ctx {
   double *b = nullptr, *sol = nullptr, *rr = nullptr, *pv = nullptr, *qv = nullptr;
   // fast-diagonalisation solver: 1-D eigenvectors (column-major, V[i + j P]:
   // node i, mode j, M1-orthonormal) and eigenvalues of the fine pencil
-  rocblas_handle blas = nullptr;
   double *fdmV = nullptr, *fdmLam = nullptr;
   int fdm_i0 = 0;
   // the same solve by Fourier analysis over the element lattice (meshes
@@ -299,7 +297,6 @@ struct fep3m_ctx {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (pstream) (void)hipStreamDestroy(pstream);
-    if (blas) (void)rocblas_destroy_handle(blas);
   }
   void check_launch(const char *what) { hip_check(hipGetLastError(), what); }
   void sync(const char *what) { hip_check(hipStreamSynchronize(stream), what); }
@@ -708,25 +705,16 @@ void fep3m_ctx::build_fdm() {
   fdmLam = alloc<double>(size_t(P), "fdm eigenvalues");
   hip_check(hipMemcpy(fdmV, vcm.data(), vcm.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
   hip_check(hipMemcpy(fdmLam, lamv.data(), size_t(P) * sizeof(double), hipMemcpyHostToDevice), "upload");
-  if (rocblas_create_handle(&blas) != rocblas_status_success) throw Status(FEP3M_ERR_DEVICE, "rocblas handle");
-  if (rocblas_set_pointer_mode(blas, rocblas_pointer_mode_host) != rocblas_status_success)
-    throw Status(FEP3M_ERR_DEVICE, "rocblas pointer mode");
 }
 
-namespace {
-void blas_check(rocblas_status s, const char *what) {
-  if (s != rocblas_status_success)
-    throw Status(FEP3M_ERR_DEVICE, std::string(what) + ": " + rocblas_status_to_string(s));
-}
-}  // namespace
 
 // Exact periodic solve by fast diagonalisation of the Kronecker sum
 // K = K1 (x) M1 (x) M1 + M1 (x) K1 (x) M1 + M1 (x) M1 (x) K1 with
 // K1 V = M1 V diag(lam), V^T M1 V = I:  out = (V (x) V (x) V) D^+ (V (x) V (x) V)^T rhs,
-// D = lam_i + lam_j + lam_k.  Each 1-D transform is a float64 GEMM over the
-// whole batch: along x one GEMM of P x (nb P^2); along y a strided batch of
-// nb P slabs; along z a strided batch of nb configurations.  The PCG
-// buffers serve as the two work vectors.  The achieved relative residual
+// D = lam_i + lam_j + lam_k.  On meshes whose edge is a power of two the
+// same solve runs by Fourier analysis over the element lattice (k_fdm.hip:
+// FFTs and p x p blocks per frequency); otherwise the 1-D transforms are
+// dense tiled kernels over the whole batch.  The achieved relative residual
 // is measured with one operator apply, as for the iterative solver.
 void fep3m_ctx::fdm_solve(const double *rhs, double *sol, int which) {
   const int P = lv[0].op.P;
@@ -735,29 +723,16 @@ void fep3m_ctx::fdm_solve(const double *rhs, double *sol, int which) {
     if (launch_fs_solve(stream, nbs, n, p, rhs, sol, fsZ, fsTw, fsW, fsL) != 0)
       throw Status(FEP3M_ERR_UNSUPPORTED, "Fourier solve variant");
   } else {
-  const rocblas_int iP = P, iP2 = P * P;
-  const double one = 1.0, zero = 0.0;
-  blas_check(rocblas_set_stream(blas, stream), "rocblas stream");
-  double *A = rr, *B = pv;
-  // forward: x, y, z
-  blas_check(rocblas_dgemm(blas, rocblas_operation_transpose, rocblas_operation_none, iP, rocblas_int(nbs) * iP2, iP,
-                           &one, fdmV, iP, rhs, iP, &zero, A, iP), "fdm x");
-  blas_check(rocblas_dgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_none, iP, iP, iP, &one, A,
-                                           iP, rocblas_stride(iP2), fdmV, iP, 0, &zero, B, iP, rocblas_stride(iP2),
-                                           rocblas_int(nbs) * iP), "fdm y");
-  blas_check(rocblas_dgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_none, iP2, iP, iP, &one, B,
-                                           iP2, rocblas_stride(per), fdmV, iP, 0, &zero, A, iP2, rocblas_stride(per),
-                                           rocblas_int(nbs)), "fdm z");
-  launch_fdm_scale(stream, nd, P, fdm_i0, fdmLam, A);
-  // inverse: z, y, x
-  blas_check(rocblas_dgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_transpose, iP2, iP, iP, &one,
-                                           A, iP2, rocblas_stride(per), fdmV, iP, 0, &zero, B, iP2,
-                                           rocblas_stride(per), rocblas_int(nbs)), "fdm z back");
-  blas_check(rocblas_dgemm_strided_batched(blas, rocblas_operation_none, rocblas_operation_transpose, iP, iP, iP, &one,
-                                           B, iP, rocblas_stride(iP2), fdmV, iP, 0, &zero, A, iP,
-                                           rocblas_stride(iP2), rocblas_int(nbs) * iP), "fdm y back");
-  blas_check(rocblas_dgemm(blas, rocblas_operation_none, rocblas_operation_none, iP, rocblas_int(nbs) * iP2, iP, &one,
-                           fdmV, iP, A, iP, &zero, sol, iP), "fdm x back");
+    // dense transforms of the pencil's eigenvectors along x, y, z (the PCG
+    // buffers serve as the two work vectors), the eigenvalue division, back
+    double *A = rr, *B = pv;
+    launch_axis_transform(stream, P, 0, nbs, fdmV, true, rhs, A);
+    launch_axis_transform(stream, P, 1, nbs, fdmV, true, A, B);
+    launch_axis_transform(stream, P, 2, nbs, fdmV, true, B, A);
+    launch_fdm_scale(stream, nd, P, fdm_i0, fdmLam, A);
+    launch_axis_transform(stream, P, 2, nbs, fdmV, false, A, B);
+    launch_axis_transform(stream, P, 1, nbs, fdmV, false, B, A);
+    launch_axis_transform(stream, P, 0, nbs, fdmV, false, A, sol);
   }
   // achieved residual, per configuration
   launch_sum_partials(stream, launch_dot(stream, nbs, per, rhs, rhs, partial), partial, pcs.bn2, nbs);

@@ -134,6 +134,74 @@ __global__ __launch_bounds__(256) void k_fs_solve(int n, const double2 *__restri
   if (act) zf[tid] = buf[cur][tid];
 }
 
+// Dense transform along one axis of nsys P^3 arrays [z][y][x]:
+// out[line][o] = sum_k A(o, k) in[line][k], A(o, k) = V[k + o P] (TRANS:
+// V^T, the forward transform into modes) or V[o + k P] (back), V the
+// column-major eigenvector matrix.  Tiles of 64 outputs x 64 lines, k in
+// chunks of 16 staged in LDS, 4 x 4 results per thread.
+template <bool TRANS>
+__global__ __launch_bounds__(256) void k_axis_transform(int P, int axis, int nsys, const double *__restrict__ V,
+                                                        const double *__restrict__ in, double *__restrict__ out) {
+  __shared__ double As[16][65];   // [k][o]
+  __shared__ double Xs[16][65];   // [k][line]
+  const size_t P2 = size_t(P) * P, per = P2 * P;
+  const int otiles = (P + 63) / 64;
+  const size_t lines = P2 * nsys;
+  const size_t ltile = blockIdx.x / otiles;
+  const int o0 = (blockIdx.x % otiles) * 64;
+  const size_t l0 = ltile * 64;
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  // element k of line l: line l = (system, a, b) with a, b the other two axes
+  auto addr = [&](size_t l, int k) -> size_t {
+    const size_t sys = l / P2, r = l % P2;
+    const size_t a = r / P, b = r % P;   // axis 0: (z, y); axis 1: (z, x); axis 2: (y, x)
+    if (axis == 0) return sys * per + r * P + k;
+    if (axis == 1) return sys * per + a * P2 + size_t(k) * P + b;
+    return sys * per + size_t(k) * P2 + r;
+  };
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < P; k0 += 16) {
+    for (int i = tid; i < 16 * 64; i += 256) {
+      int kk, oo;
+      if (TRANS) { kk = i % 16; oo = i / 16; } else { oo = i % 64; kk = i / 64; }
+      const int k = k0 + kk, o = o0 + oo;
+      As[kk][oo] = (k < P && o < P) ? (TRANS ? V[k + size_t(o) * P] : V[o + size_t(k) * P]) : 0.0;
+    }
+    for (int i = tid; i < 16 * 64; i += 256) {
+      int kk, ll;
+      if (axis == 0) { kk = i % 16; ll = i / 16; } else { ll = i % 64; kk = i / 64; }
+      const int k = k0 + kk;
+      const size_t l = l0 + ll;
+      Xs[kk][ll] = (k < P && l < lines) ? in[addr(l, k)] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], x[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        a[r] = As[kk][tx + 16 * r];
+        x[r] = Xs[kk][ty + 16 * r];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[j] * x[i];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const size_t l = l0 + ty + 16 * i;
+    if (l >= lines) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = o0 + tx + 16 * j;
+      if (o < P) out[addr(l, o)] = acc[i][j];
+    }
+  }
+}
+
 inline int grid_of(size_t count) {
   size_t g = (count + 255) / 256;
   if (g < 1) g = 1;
@@ -155,6 +223,16 @@ int fs_solve_impl(hipStream_t s, int nsys, int n, const double *rhs, double *out
 }
 
 }  // namespace
+
+void launch_axis_transform(hipStream_t s, int P, int axis, int nsys, const double *V, bool to_modes, const double *in,
+                           double *out) {
+  const size_t lines = size_t(P) * P * nsys;
+  const unsigned grid = unsigned(((lines + 63) / 64) * ((P + 63) / 64));
+  if (to_modes)
+    hipLaunchKernelGGL(k_axis_transform<true>, dim3(grid), dim3(256), 0, s, P, axis, nsys, V, in, out);
+  else
+    hipLaunchKernelGGL(k_axis_transform<false>, dim3(grid), dim3(256), 0, s, P, axis, nsys, V, in, out);
+}
 
 int launch_fs_solve(hipStream_t s, int nsys, int n, int p, const double *rhs, double *out, double2 *Z,
                     const double2 *tw, const double2 *W, const double *lam) {

@@ -120,6 +120,12 @@ int launch_adj_fft_finish(hipStream_t s, int nb, int n, int p, const double *lam
 // complex; W, lam from periodic_fourier_eigen; tw: exp(-2 pi i j / n).
 int launch_fs_solve(hipStream_t s, int nsys, int n, int p, const double *rhs, double *out, double2 *Z,
                     const double2 *tw, const double2 *W, const double *lam);
+// the same solve on any mesh size (k_fdm.hip): the dense 1-D transform of
+// the pencil's eigenvectors V (P x P, column-major, node i of mode j at
+// V[i + j P]) along one axis (0 x, 1 y, 2 z) of nsys P^3 arrays; to_modes:
+// V^T, else V.
+void launch_axis_transform(hipStream_t s, int P, int axis, int nsys, const double *V, bool to_modes, const double *in,
+                           double *out);
 // in-place 3-D FFT of [nb][z][y][x][nch] complex arrays, nch = p^3 (k_fft.hip)
 int launch_fft3_nodes(hipStream_t s, int nb, int n, int nch, double2 *z, const double2 *tw, bool inverse);
 
