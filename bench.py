@@ -478,7 +478,7 @@ def variant_summary(r, ref=None):
          "N": int(sum(r["counts"])), "elements": f"{r['n']}^3",
          "graph_replays": r["stats"]["graph_replays"],
          "mg_iterations": r["stats"]["mg_iterations"], "adj_mg_iterations": r["stats"]["adj_iterations"],
-         "pair_variant": {"kind": "queue" if r["stats"]["pair_variant"] else "element",
+         "pair_variant": {"kind": {0: "element", 1: "queue", 2: "rows"}[r["stats"]["pair_variant"]],
                           "item_targets": r["stats"]["pair_item_targets"], "waves": r["stats"]["pair_waves"],
                           "tuned_ms": r["stats"]["tune_ms_best"], "element_ms": r["stats"]["tune_ms_default"]}}
     if k:

@@ -137,9 +137,14 @@ typedef struct {
   int32_t autotune;      /* 1 (default): the first evaluation times the pair
                             sum's work decompositions (one wave per element;
                             persistent waves over a queue of target chunks of
-                            several sizes and grid sizes) and keeps the
-                            fastest; 0: one wave per element.  Every variant
-                            gives bit-identical results.                        */
+                            several sizes and grid sizes; in float64 also
+                            workgroups of up to 256 targets of one row of
+                            elements against LDS-staged source rows) and
+                            keeps the fastest; 0: one wave per element; 2:
+                            the row form (float64 only).  The first two give
+                            bit-identical results, the row form sums each
+                            charge's pairs in another order (equal to
+                            rounding).                                         */
   int32_t use_graph;     /* 1: run each evaluation as one captured hipGraph
                             replay on an internal stream ordered after the
                             caller's stream, on context copies of the inputs

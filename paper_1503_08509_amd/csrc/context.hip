@@ -211,7 +211,8 @@ struct fep3m_ctx {
   double2 *fsW = nullptr, *fsTw = nullptr, *fsZ = nullptr;
   double *fsL = nullptr;
   // pair-sum work decomposition (autotuned): kind 0 one wave per element,
-  // kind 1 persistent waves over items of `titem` targets
+  // kind 1 persistent waves over items of `titem` targets, kind 2 workgroups
+  // over rows of elements with LDS-staged source rows (float64)
   struct PairPlan {
     int kind = 0, titem = 0, waves = 0;
   };
@@ -248,6 +249,9 @@ struct fep3m_ctx {
   int cus = 256;                // compute units of the device
   int *nit = nullptr, *item_start = nullptr, *icounter = nullptr, *iscan_max = nullptr;
   int2 *items = nullptr;
+  // pair sum on rows of target elements (kind 2): row starts and work items
+  int *rowstart = nullptr, *rnit = nullptr, *ritem_start = nullptr, *riscan_max = nullptr;
+  int2 *ritems = nullptr;
   // adjoint
   double *gE = nullptr, *Gv = nullptr, *lam = nullptr, *Aadj = nullptr, *fpair = nullptr, *Phi_int = nullptr;
 
@@ -480,6 +484,14 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   items = alloc<int2>(size_t(N), "pair work items");
   icounter = alloc<int>(4, "item counter");
   iscan_max = alloc<int>(4, "item scan max");
+  if (!mixed) {
+    const size_t RT = size_t(nb) * n * n;
+    rowstart = alloc<int>(RT + 1, "row starts");
+    rnit = alloc<int>(RT, "row items");
+    ritem_start = alloc<int>(RT + 1, "row item starts");
+    riscan_max = alloc<int>(4, "row item scan max");
+    ritems = alloc<int2>(size_t(pair_rows_items_max(nb, n, N)), "row work items");
+  }
   {
     int dev = 0;
     hip_check(hipGetDevice(&dev), "device");
@@ -996,7 +1008,8 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   // and only on meshes of at least 2^16 elements in all: below that the pass
   // is too short to pay for the fork and the join (graph replays of 1000
   // charges on 8^3 elements: 1.25 -> 1.39 ms)
-  const bool overlap = !(opt.autotune && !tuned && !prof.on) && plan.kind == 0 && !arena && opt.pair_stream &&
+  if (opt.autotune == 2) plan = PairPlan{2, 2, 0};
+  const bool overlap = !(opt.autotune == 1 && !tuned && !prof.on) && plan.kind != 1 && !arena && opt.pair_stream &&
                        size_t(nb) * n * n * n >= (size_t(1) << 16);
   if (overlap) {
     side_stream();
@@ -1085,6 +1098,11 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
 
 int fep3m_ctx::pair_launch(const PairPlan &pl, bool pair_forces) {
   double *fp = pair_forces ? fpair : nullptr;
+  if (pl.kind == 2) {
+    if (mixed) return -1;
+    return launch_pair_rows(stream, nb, n, nsr, pl.titem, N, start, rowstart, rnit, ritem_start, riscan_max, ritems,
+                            scan_scr, sg, sQ, phip_s, fp);
+  }
   if (pl.kind == 0)
     return mixed ? launch_pair_f32(stream, nb, n, nsr, N, start, si, sel, phip_s, fp)
                  : launch_pair(stream, nb, n, nsr, N, start, sg, sQ, phip_s, fp);
@@ -1100,13 +1118,17 @@ int fep3m_ctx::pair_launch(const PairPlan &pl, bool pair_forces) {
 }
 
 // Time each candidate decomposition of the pair sum on this call's data and
-// keep the fastest.  The candidates produce identical results, so the
-// outputs of the last one timed are the call's outputs.
+// keep the fastest.  Kinds 0 and 1 produce identical results; kind 2 sums
+// each target's pairs in another order (equal to rounding), so the chosen
+// plan runs once more when it is not the last one timed: the call's outputs
+// are those of the plan every later call uses.
 void fep3m_ctx::tune_pairs(bool pair_forces) {
   std::vector<PairPlan> cand;
   cand.push_back(PairPlan{0, 0, 0});
   for (int titem : {8, 32, 64})
     for (int per_cu : {16, 32}) cand.push_back(PairPlan{1, titem, per_cu * cus});
+  if (!mixed)   // rows of elements, 1, 2 or 4 lanes per target
+    for (int sl : {1, 2, 4}) cand.push_back(PairPlan{2, sl, 0});
   hipEvent_t e0, e1;
   hip_check(hipEventCreate(&e0), "event");
   hip_check(hipEventCreate(&e1), "event");
@@ -1128,6 +1150,14 @@ void fep3m_ctx::tune_pairs(bool pair_forces) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  const PairPlan &last = cand.back();
+  if (pick.kind != last.kind || pick.titem != last.titem || pick.waves != last.waves) {
+    if (pick.kind == 1 && items_titem != pick.titem) {
+      launch_items(stream, nb * n * n * n, pick.titem, start, nit, item_start, iscan_max, items, scan_scr);
+      items_titem = pick.titem;
+    }
+    if (pair_launch(pick, pair_forces) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "pair variant");
+  }
   plan = pick;
   tuned = true;
   stats.tune_ms_best = best;
@@ -1135,7 +1165,7 @@ void fep3m_ctx::tune_pairs(bool pair_forces) {
 }
 
 void fep3m_ctx::pair_pass(bool pair_forces) {
-  if (opt.autotune && !tuned && !prof.on) tune_pairs(pair_forces);
+  if (opt.autotune == 1 && !tuned && !prof.on) tune_pairs(pair_forces);
   stage_mark(FEP3M_PROF_PAIR, true);
   if (pair_launch(plan, pair_forces) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "pair variant");
   prof.pair_forces = pair_forces;
@@ -1425,7 +1455,8 @@ bool valid_options(const fep3m_options &o, std::string &why) {
   if (!(o.mg_rtol > 0.0) || !(o.mg_rtol < 1.0)) { why = "mg_rtol must be in (0, 1)"; return false; }
   if (o.mg_max_iter < 1 || o.mg_max_iter > 1000) { why = "mg_max_iter must be 1..1000"; return false; }
   if (o.cheb_degree < 1 || o.cheb_degree > 10) { why = "cheb_degree must be 1..10"; return false; }
-  if (o.autotune != 0 && o.autotune != 1) { why = "autotune must be 0 or 1"; return false; }
+  if (o.autotune < 0 || o.autotune > 2) { why = "autotune must be 0, 1 or 2"; return false; }
+  if (o.autotune == 2 && o.precision != FEP3M_PRECISION_FP64) { why = "autotune = 2 needs float64"; return false; }
   if (o.use_graph != 0 && o.use_graph != 1) { why = "use_graph must be 0 or 1"; return false; }
   if (o.solver != FEP3M_SOLVER_MG && o.solver != FEP3M_SOLVER_FDM) { why = "unknown solver"; return false; }
   if (o.near_field < FEP3M_NEAR_AUTO || o.near_field > FEP3M_NEAR_FFT) { why = "unknown near_field"; return false; }

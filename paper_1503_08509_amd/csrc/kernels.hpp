@@ -38,6 +38,15 @@ void launch_fill_int(hipStream_t s, int count, int value, int *p);
 int launch_pair_queue(hipStream_t s, int waves, int n, int nsr, int64_t N, const int *start, const int2 *items,
                       const int *nitems, int *counter, int titem, const double *sg, const double *sQ, double *phip,
                       double *fpair);
+// Near-pair sum on rows of target elements (k_pair_rows.hip, float64):
+// one-wave workgroups of up to 64 targets of one x-row, LDS-staged source rows.
+// Work arrays: rowstart, ritem_start nb n^2 + 1 ints, rnit nb n^2,
+// rscan_max 4, ritems pair_rows_items_max() int2, scan_scratch as launch_scan.
+int pair_rows_items_max(int nb, int n, int64_t N);
+// sl: lanes per target (1, 2 or 4; 64 / sl targets per wave)
+int launch_pair_rows(hipStream_t s, int nb, int n, int nsr, int sl, int64_t N, const int *start, int *rowstart,
+                     int *rnit, int *ritem_start, int *rscan_max, int2 *ritems, int *scan_scratch, const double *sg,
+                     const double *sQ, double *phip, double *fpair);
 int launch_interp(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h, const GllBasis &bas,
                   const double *sg, const double *Wel, const double *phip, const int *perm, double *phim_s,
                   double *phi_s, double *Phi);
