@@ -47,6 +47,8 @@ def parse():
                          "interpolation with compensated sums, float64 reductions")
     ap.add_argument("--near", choices=["auto", "direct", "fft"], default="auto",
                     help="near-screen field and its transpose: FFTs where the mesh allows (auto), table sums, or FFTs")
+    ap.add_argument("--solver", choices=["mg", "exact"], default="mg",
+                    help="mesh solve: multigrid PCG (the method's default) or the exact periodic solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mixed-precision, clustered and batched measurements reported beside the FP64 line")
@@ -519,7 +521,7 @@ def main():
 
     forces = args.outputs == "forces"
     r = measure(args.workload, args.precision, args.steps, args.warmup, forces,
-                near_field={"auto": 0, "direct": 1, "fft": 2}[args.near])
+                solver={"mg": 0, "exact": 1}[args.solver], near_field={"auto": 0, "direct": 1, "fft": 2}[args.near])
     mixed = args.precision == "mixed"
     kernels = r["kernels"]
     practical = stream_copy_gbs() if not args.no_variants else None   # kept out of profiled runs
@@ -563,7 +565,8 @@ def main():
         "config": {"workload": r["workload"], "N": int(sum(r["counts"])), "configurations": len(r["counts"]),
                    "elements": f"{r['n']}^3", "L": r["L"], "screen": "one-element q=3", "mesh_order": 5,
                    "near_block": "7^3", "outputs": "U, F" if forces else "Phi, U", "precision": args.precision,
-                   "mg_rtol": r["mg_rtol"], "near_pairs_per_step": r["pairs"]},
+                   "mg_rtol": r["mg_rtol"], "solver": "multigrid PCG" if args.solver == "mg" else "exact",
+                   "near_pairs_per_step": r["pairs"]},
         "roofline": roof,
         "kernels": kernels,
         "stages_ms_per_step": r["stages_ms_per_step"],
@@ -612,10 +615,10 @@ def main():
             sg = measure(wl, "fp64", 5, 2, graph=True)   # small problems: launches and host reads dominate
             variants["fp64 " + wl + " hipGraph"] = variant_summary(sg, s64)
             del s64, sm, sg
-        # the exact fast-diagonalisation mesh solver in place of multigrid
+        # the exact periodic mesh solve (Fourier analysis over the element lattice) in place of multigrid
         for prec, wl in (("fp64", "uniform-1M-n64"), ("mixed", "uniform-1M-n64"), ("fp64", BATCH_WORKLOAD)):
             fd = measure(wl, prec, 3, 1, solver=1)
-            variants[f"{prec} {wl} fast-diagonalisation solver"] = variant_summary(
+            variants[f"{prec} {wl} exact mesh solver"] = variant_summary(
                 fd, r if wl == "uniform-1M-n64" else None)
             del fd
         out["variants"] = variants

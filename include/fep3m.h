@@ -11,7 +11,7 @@
  * split as Phi = Phi_sr + Phi_sm (eq. phisplit) with polynomial screens
  * (Section 2.1): a near-field pair sum minus the potential of the screens in
  * the (2 n_sr + 1)^3 block of elements around each charge (eq. sc, the
- * self term of Section 2.4 included), plus an order-p finite element
+ * self term of Section 2.5 included), plus an order-p finite element
  * solution of the periodic Poisson problem for the screens (Section 2.2),
  * evaluated at the charges (eq. evalsmooth).  The screen is the
  * one-element-support variant of the Discussion (Section 5) with degree q;

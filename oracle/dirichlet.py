@@ -1,0 +1,294 @@
+"""The method with a homogeneous Dirichlet boundary (oracle; test
+infrastructure, not part of the product).
+
+Section 2.6 ("Alternate boundary conditions"): on the box V = [0, L]^3 with
+Phi = g on its faces, the mesh potential takes the boundary values
+g - Phi_sr (eq. bcadjust), so that Phi = Phi_sm + Phi_sr meets the boundary
+condition; the rest of the method is unchanged.  Here g = 0 (a grounded
+box), the screens are the one-element screens of Section 5 (every screen
+lies inside its element, hence inside V), and nothing wraps: the near block
+of an element is cut at the faces and there are no periodic images.
+
+Element units (h = 1) throughout, physical potentials divided by h at the
+end, as in `fep3m`.  Arrays on the mesh are indexed [z, y, x] over the
+(p n + 1)^3 nodes of the box, global node g = p e + k along each axis.
+
+Stages:
+  bin      e = min(floor(x / h), n - 1), u = x / h - e - 1/2 (no wrap; the
+           charges must lie in [0, L)^3)
+  C        element moments (as in the periodic case)
+  b        load vector, assembled without wrap (no compatibility projection:
+           the Dirichlet problem has no null space and the charges need not
+           be neutral)
+  phiB     on the boundary nodes: -Phi_sr(x_B) in element units, Phi_sr(x_B)
+           = sum over the charges of the near block of B's element of
+           Q_j / |x_B - x_j| minus that block's screen potential at B (the
+           tables' nodal value); B's element is the one with index
+           min(g // p, n - 1) along each axis
+  phi      K_II phi_I = b_I - K_IB phiB by fast diagonalisation of the
+           interior 1-D pencil; phi = phiB on the boundary
+  Phi      Phi_p + sum_m (phi_E - Psi_E)[m] u_m(u_i), as in `fep3m.run`
+           with the near block cut at the faces
+
+Charges closer than about half an element to a face are resolved poorly:
+their images lie within h of the face, so the mesh potential (the exact
+potential minus the near sums) varies there on a scale below the element
+size.  The boundary adjustment of eq. bcadjust is accurate for charges at
+least an element or so away from the faces.
+
+The ground truth is the image construction of the grounded cube: the odd
+reflections of every charge in the three coordinate planes give 8 charges
+per charge in the box [0, 2L)^3 (sign (-1)^(number of reflections)); that
+set is neutral with zero dipole moment, its 2L-periodic potential is odd
+about every face of the unit box, hence zero on the faces, and inside the
+box it equals the Dirichlet potential of the original charges
+(`image_ewald`).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.linalg
+
+from . import ewald, fe1d, fep3m, screens, tables
+
+_EIG: dict = {}
+
+
+def bin_box(x, L, n):
+    """Element and local offset of each charge, no wrap."""
+    x = np.asarray(x, dtype=np.float64)
+    if np.any(x < 0.0) or np.any(x >= L):
+        raise ValueError("charges must lie in [0, L)^3")
+    t = x / L * n
+    e = np.minimum(np.floor(t), n - 1)
+    u = t - e - 0.5
+    e = e.astype(np.int64)
+    return e, e[:, 0] + n * (e[:, 1] + n * e[:, 2]), u
+
+
+def node_positions(p, n):
+    """Coordinates (element units) of the p n + 1 nodes along an axis."""
+    nodes = fe1d.gll_nodes(p)
+    pos = np.zeros(p * n + 1)
+    for e in range(n):
+        pos[p * e:p * e + p + 1] = e + 0.5 + nodes
+    return pos
+
+
+def node_element(p, n):
+    """Element of each node along an axis (min(g // p, n - 1)) and the
+    node's local index in it."""
+    g = np.arange(p * n + 1)
+    e = np.minimum(g // p, n - 1)
+    return e, g - p * e
+
+
+def boundary_mask(p, n):
+    P = p * n + 1
+    m = np.zeros((P, P, P), dtype=bool)
+    m[0, :, :] = m[-1, :, :] = True
+    m[:, 0, :] = m[:, -1, :] = True
+    m[:, :, 0] = m[:, :, -1] = True
+    return m
+
+
+def load_vector(C, n, p, q):
+    """b_m = 4 pi sum_E sum_a C[E][a] int u_m R_a(. - xbar_E), every element
+    adding its screens' load to its own (p+1)^3 nodes, no wrap."""
+    d = screens.moment_degree(q, "one")
+    g = screens.load_weights(p, q, "one")
+    A = screens.moment_exponents(d)
+    Cg = C.reshape(n, n, n, len(A))
+    Gs = np.stack([np.einsum("k,j,i->kji", g[az], g[ay], g[ax]) for (ax, ay, az) in A])
+    loc = 4.0 * math.pi * np.einsum("zyxa,akji->zyxkji", Cg, Gs, optimize=True)
+    P = p * n + 1
+    b = np.zeros((P, P, P))
+    idx = p * np.arange(n)[:, None] + np.arange(p + 1)[None, :]
+    for mz in range(p + 1):
+        for my in range(p + 1):
+            for mx in range(p + 1):
+                b[np.ix_(idx[:, mz], idx[:, my], idx[:, mx])] += loc[:, :, :, mz, my, mx]
+    return b
+
+
+def _sorted(e_lin, n):
+    order = np.argsort(e_lin, kind="stable")
+    start = np.concatenate([[0], np.cumsum(np.bincount(e_lin, minlength=n ** 3))])
+    return order, start
+
+
+def near_field(C, T, n, n_sr, elems):
+    """Psi_E at the element's nodes: sum over the offsets D whose source
+    element E - D lies in the box of T[a, D, :] C[E - D][a]."""
+    offs = tables.offsets(n_sr)
+    ex, ey, ez = elems % n, (elems // n) % n, elems // (n * n)
+    out = np.zeros((len(elems), T.shape[2]))
+    for iD, (Dx, Dy, Dz) in enumerate(offs):
+        sx, sy, sz = ex - Dx, ey - Dy, ez - Dz
+        ok = (sx >= 0) & (sx < n) & (sy >= 0) & (sy < n) & (sz >= 0) & (sz < n)
+        if not ok.any():
+            continue
+        src = sx[ok] + n * (sy[ok] + n * sz[ok])
+        out[ok] += C[src] @ T[:, iD, :]
+    return out
+
+
+def near_sources(E, n, n_sr, order, start):
+    """Charges of the near block of element E, cut at the faces."""
+    ex, ey, ez = E % n, (E // n) % n, E // (n * n)
+    js = []
+    for (Dx, Dy, Dz) in tables.offsets(n_sr):
+        sx, sy, sz = ex + Dx, ey + Dy, ez + Dz
+        if 0 <= sx < n and 0 <= sy < n and 0 <= sz < n:
+            S = sx + n * (sy + n * sz)
+            js.append(order[start[S]:start[S + 1]])
+    return np.concatenate(js) if js else np.zeros(0, dtype=np.int64)
+
+
+def pair_potential(e, e_lin, u, Q, n, n_sr, targets):
+    """Near sum sum_{j != i} Q_j / |y_j - y_i| over the near block cut at the
+    faces (y = e + 1/2 + u, element units)."""
+    order, start = _sorted(e_lin, n)
+    y = e + 0.5 + u
+    out = np.zeros(len(targets))
+    tgt_e = e_lin[targets]
+    for E in np.unique(tgt_e):
+        sel = np.nonzero(tgt_e == E)[0]
+        ti = targets[sel]
+        js = near_sources(E, n, n_sr, order, start)
+        r = np.sqrt(np.sum((y[js][None, :, :] - y[ti][:, None, :]) ** 2, axis=2))
+        r[js[None, :] == ti[:, None]] = np.inf
+        out[sel] = np.sum(Q[js][None, :] / r, axis=1)
+    return out
+
+
+def boundary_values(e, e_lin, u, Q, C, T, n, p, n_sr):
+    """phiB = -Phi_sr at every boundary node (eq. bcadjust with g = 0),
+    element units; zero on the interior nodes."""
+    P = p * n + 1
+    pos = node_positions(p, n)
+    ne, nk = node_element(p, n)
+    order, start = _sorted(e_lin, n)
+    y = e + 0.5 + u
+    phiB = np.zeros((P, P, P))
+    gz, gy, gx = np.nonzero(boundary_mask(p, n))
+    E = ne[gx] + n * (ne[gy] + n * ne[gz])
+    m = nk[gx] + (p + 1) * (nk[gy] + (p + 1) * nk[gz])
+    uE, inv = np.unique(E, return_inverse=True)
+    Psi = near_field(C, T, n, n_sr, uE)
+    xb = np.stack([pos[gx], pos[gy], pos[gz]], axis=1)
+    vals = np.zeros(len(gx))
+    for k, Ek in enumerate(uE):
+        sel = np.nonzero(inv == k)[0]
+        js = near_sources(Ek, n, n_sr, order, start)
+        if len(js):
+            r = np.sqrt(np.sum((y[js][None, :, :] - xb[sel][:, None, :]) ** 2, axis=2))
+            vals[sel] = np.sum(Q[js][None, :] / r, axis=1)
+        vals[sel] -= Psi[k, m[sel]]
+    phiB[gz, gy, gx] = -vals
+    return phiB
+
+
+def _interior_eig(p, n):
+    key = (p, n)
+    if key not in _EIG:
+        K1, M1 = fe1d.dirichlet_matrices(p, n)
+        lam, V = scipy.linalg.eigh(K1[1:-1, 1:-1], M1[1:-1, 1:-1])
+        _EIG[key] = (K1, M1, lam, V)
+    return _EIG[key]
+
+
+def stiffness_apply(phi, p, n):
+    """K phi on all (p n + 1)^3 nodes of the box (non-periodic assembly)."""
+    K1, M1, _, _ = _interior_eig(p, n)
+    return fe1d.stiffness_apply(K1, M1, phi)
+
+
+def solve(b, phiB, p, n):
+    """phi with phi = phiB on the boundary and (K phi)_I = b_I: the interior
+    system K_II phi_I = b_I - K_IB phiB by fast diagonalisation."""
+    _, _, lam, V = _interior_eig(p, n)
+    r = (b - stiffness_apply(phiB, p, n))[1:-1, 1:-1, 1:-1]
+    D = lam[:, None, None] + lam[None, :, None] + lam[None, None, :]
+    phi = phiB.copy()
+    phi[1:-1, 1:-1, 1:-1] = fe1d.kron_apply(V, V, V, fe1d.kron_apply(V.T, V.T, V.T, r) / D)
+    return phi
+
+
+def element_phi(phi, p, n, elems):
+    """Local (p+1)^3 nodal values (x fastest) of the box field on elements."""
+    idx = p * np.arange(n)[:, None] + np.arange(p + 1)[None, :]
+    ex, ey, ez = elems % n, (elems // n) % n, elems // (n * n)
+    out = phi[idx[ez][:, :, None, None], idx[ey][:, None, :, None], idx[ex][:, None, None, :]]
+    return out.reshape(len(elems), -1)
+
+
+def run(x, Q, params: fep3m.Params, targets=None, stages=False):
+    """Phi at `targets` (default: every charge) and U (when every charge is
+    a target) for the grounded box."""
+    if params.support != "one":
+        raise ValueError("the box form takes the one-element screens")
+    x = np.asarray(x, dtype=np.float64)
+    Q = np.asarray(Q, dtype=np.float64)
+    n, p, q, d, n_sr = params.n, params.p, params.q, params.d, params.n_sr
+    if n < 2 * n_sr + 1:
+        raise ValueError("mesh too coarse for the near block")
+    e, e_lin, u = bin_box(x, params.L, n)
+    C = screens.element_moments(e_lin, u, Q, n ** 3, d)
+    T = tables.screen_tables(p, q, n_sr, params.B, params.table_bc, "one")
+    b = load_vector(C, n, p, q)
+    phiB = boundary_values(e, e_lin, u, Q, C, T, n, p, n_sr)
+    phi = solve(b, phiB, p, n)
+    all_targets = targets is None
+    targets = np.arange(len(Q)) if all_targets else np.asarray(targets)
+    uel, inv = np.unique(e_lin[targets], return_inverse=True)
+    phiE = element_phi(phi, p, n, uel)
+    PsiE = near_field(C, T, n, n_sr, uel)
+    Phi_m = np.sum((phiE - PsiE)[inv] * fep3m.basis_values(p, u[targets]), axis=1)
+    Phi_p = pair_potential(e, e_lin, u, Q, n, n_sr, targets)
+    h = params.h
+    Phi = (Phi_p + Phi_m) / h
+    out = {"Phi": Phi}
+    if all_targets:
+        out["U"] = 0.5 * float(np.sum(Q * Phi))
+    if stages:
+        out.update(e=e, e_lin=e_lin, u=u, C=C, b=b, phiB=phiB, phi=phi, Psi_elems=uel, Psi=PsiE,
+                   Phi_m=Phi_m / h, Phi_p=Phi_p / h)
+    return out
+
+
+def image_charges(x, Q, L):
+    """The 8 odd images of every charge in [0, 2L)^3: reflection of a
+    coordinate s in the plane 0 is 2L - s (mod 2L), with a sign change per
+    reflection.  Charge i's images are rows 8 i .. 8 i + 7, the first being
+    the charge itself."""
+    x = np.asarray(x, dtype=np.float64)
+    out_x, out_q = [], []
+    for mz in (0, 1):
+        for my in (0, 1):
+            for mx in (0, 1):
+                m = np.array([mx, my, mz])
+                out_x.append(np.where(m[None, :] == 1, 2.0 * L - x, x))
+                out_q.append(Q * (-1.0) ** (mx + my + mz))
+    X = np.stack(out_x, axis=1).reshape(-1, 3)
+    return X, np.stack(out_q, axis=1).reshape(-1)
+
+
+def image_ewald(x, Q, L=1.0, targets=None, points=None, alpha=None, nimg=2, mmax=8):
+    """Potential of the grounded box at the charges (`targets`, default all)
+    or at arbitrary `points` inside the box: Ewald summation of the image
+    set in the 2L-periodic box."""
+    X, QQ = image_charges(x, Q, L)
+    L2 = 2.0 * L
+    alpha = 5.0 / L2 if alpha is None else alpha
+    if points is not None:
+        P = np.asarray(points, dtype=np.float64)
+        Xall = np.concatenate([X, P])
+        Qall = np.concatenate([QQ, np.zeros(len(P))])
+        t = np.arange(len(X), len(Xall))
+        return ewald.ewald(Xall, Qall, L=L2, alpha=alpha, nimg=nimg, mmax=mmax, targets=t)["Phi"]
+    N = len(Q)
+    t = 8 * (np.arange(N) if targets is None else np.asarray(targets))
+    return ewald.ewald(X, QQ, L=L2, alpha=alpha, nimg=nimg, mmax=mmax, targets=t)["Phi"]

@@ -1003,8 +1003,9 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   items_titem = -1;   // the pair work list follows this call's element starts
   if (mixed) launch_local_f32(stream, n, N, sg, sQ, su, si, sel);
   stage_mark(FEP3M_PROF_SORT, false);
-  // overlap only with one wave per element (short blocks that interleave
-  // with the solve's); persistent waves would hold every CU for the pass
+  // overlap only with the decompositions of short blocks (one wave per
+  // element, rows of elements) that interleave with the solve's; persistent
+  // waves would hold every CU for the pass
   // and only on meshes of at least 2^16 elements in all: below that the pass
   // is too short to pay for the fork and the join (graph replays of 1000
   // charges on 8^3 elements: 1.25 -> 1.39 ms)

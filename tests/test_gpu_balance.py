@@ -78,3 +78,18 @@ def test_row_pair_kernel_matches_element_kernel(torch, wl, n):
     c, _ = _run(torch, x, Q, n, autotune=2)
     for k in ("Phi", "F", "dUdQ", "U"):
         np.testing.assert_array_equal(b[k], c[k])
+
+
+@pytest.mark.parametrize("wl", ["uniform-1M-n64", "clustered-1M-n64"])
+def test_tuning_call_equals_overlapped_call(torch, wl):
+    """The first call of a tuning context times the decompositions and then
+    runs the chosen one on the context's stream; the second call runs the
+    same decomposition on the second stream beside the mesh solve (64^3
+    elements).  Both must give the same bits."""
+    x, Q = workloads.make(wl)
+    ctx = fp.Context(1.0, len(Q), 64, autotune=1)
+    tx, tQ = torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda()
+    first = {k: v.cpu().numpy() for k, v in ctx.energy_forces(tx, tQ, dUdQ=True, Phi=True).items()}
+    second = {k: v.cpu().numpy() for k, v in ctx.energy_forces(tx, tQ, dUdQ=True, Phi=True).items()}
+    _same(first, second, 0)
+

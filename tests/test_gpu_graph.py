@@ -21,7 +21,10 @@ def torch():
 
 @pytest.mark.parametrize("counts,n,precision", [(1000, 8, fp.PRECISION_FP64),
                                                  (100_000, 32, fp.PRECISION_MIXED),
-                                                 ([300, 1200, 40, 700], 8, fp.PRECISION_FP64)])
+                                                 ([300, 1200, 40, 700], 8, fp.PRECISION_FP64),
+                                                 # 64^3 elements: the captured graph forks the pair sum
+                                                 # onto the second stream and joins it before interpolation
+                                                 (100_000, 64, fp.PRECISION_FP64)])
 def test_graph_replays_equal_eager(torch, counts, n, precision):
     N = counts if np.isscalar(counts) else sum(counts)
     rng = np.random.default_rng(11)
