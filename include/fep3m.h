@@ -102,6 +102,28 @@ enum {
                              (R^-(q+2) decay)                                 */
 };
 
+/* Boundary conditions (Section 2.6). */
+enum {
+  FEP3M_BOUNDARY_PERIODIC = 0,  /* the periodic cube (the method's main case) */
+  FEP3M_BOUNDARY_GROUNDED = 1   /* Phi = 0 on the faces of the box [0, L]^3: the
+                             mesh potential takes the boundary values -Phi_sr
+                             of the charges of the near block (eq. bcadjust with
+                             g = 0), the near block is cut at the faces and
+                             nothing wraps.  Charges must lie strictly inside
+                             the box (else the call returns FEP3M_ERR_ARG); the
+                             net charge is free.  Needs one-element screens
+                             (q = 2..4), float64, solver = FEP3M_SOLVER_FDM
+                             (the interior pencil diagonalised by dense
+                             transforms) and near_field DIRECT or AUTO; no
+                             use_graph, no static storage (else create returns
+                             FEP3M_ERR_UNSUPPORTED).  fep3m_potential and
+                             fep3m_energy only: the force entry points return
+                             FEP3M_ERR_UNSUPPORTED.  Charges within about half
+                             an element of a face are resolved poorly: their
+                             images lie within h of the face, where the mesh
+                             cannot follow them.                               */
+};
+
 /* Evaluation of the near-screen field and of its transpose in the moment
  * adjoint (Section 3, eq. sc with the Remark's tables).  Both are periodic
  * convolutions over the element lattice with the table as the kernel. */
@@ -172,6 +194,7 @@ typedef struct {
                             FEP3M_ERR_UNSUPPORTED for precision = MIXED or
                             near_field = FFT there, and for element orders
                             above 6 (one-element q = 5, 6)                     */
+  int32_t boundary;      /* FEP3M_BOUNDARY_* (default PERIODIC)                  */
 } fep3m_options;
 
 typedef struct {

@@ -15,7 +15,7 @@ end, as in `fep3m`.  Arrays on the mesh are indexed [z, y, x] over the
 
 Stages:
   bin      e = min(floor(x / h), n - 1), u = x / h - e - 1/2 (no wrap; the
-           charges must lie in [0, L)^3)
+           charges must lie inside the box, 0 < x < L)
   C        element moments (as in the periodic case)
   b        load vector, assembled without wrap (no compatibility projection:
            the Dirichlet problem has no null space and the charges need not
@@ -59,8 +59,8 @@ _EIG: dict = {}
 def bin_box(x, L, n):
     """Element and local offset of each charge, no wrap."""
     x = np.asarray(x, dtype=np.float64)
-    if np.any(x < 0.0) or np.any(x >= L):
-        raise ValueError("charges must lie in [0, L)^3")
+    if np.any(x <= 0.0) or np.any(x >= L):
+        raise ValueError("charges must lie inside the box (0, L)^3")
     t = x / L * n
     e = np.minimum(np.floor(t), n - 1)
     u = t - e - 0.5

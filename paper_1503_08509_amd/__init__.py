@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
     _fields_ = [("n_sr", ctypes.c_int32), ("precision", ctypes.c_int32), ("mg_rtol", ctypes.c_double),
                 ("mg_max_iter", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("table_box", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("solver", ctypes.c_int32),
-                ("near_field", ctypes.c_int32), ("pair_stream", ctypes.c_int32), ("support", ctypes.c_int32)]
+                ("near_field", ctypes.c_int32), ("pair_stream", ctypes.c_int32), ("support", ctypes.c_int32),
+                ("boundary", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -119,6 +120,7 @@ def default_options():
 
 
 SUPPORT_ONE, SUPPORT_27 = 0, 1
+BOUNDARY_PERIODIC, BOUNDARY_GROUNDED = 0, 1
 _SUPPORTS = {"one": SUPPORT_ONE, "27": SUPPORT_27, SUPPORT_ONE: SUPPORT_ONE, SUPPORT_27: SUPPORT_27}
 
 

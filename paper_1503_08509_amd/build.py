@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libfep3m.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["host_fe.cpp", "host_tables.cpp", "context.hip", "k_mesh.hip", "k_particles.hip", "k_near.hip", "k_adjoint.hip", "k_mixed.hip", "k_fft.hip", "k_screens.hip", "k_fdm.hip", "k_pair_rows.hip"]
+SOURCES = ["host_fe.cpp", "host_tables.cpp", "context.hip", "k_mesh.hip", "k_particles.hip", "k_near.hip", "k_adjoint.hip", "k_mixed.hip", "k_fft.hip", "k_screens.hip", "k_fdm.hip", "k_pair_rows.hip", "k_box.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

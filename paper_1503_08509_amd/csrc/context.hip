@@ -141,6 +141,15 @@ struct fep3m_ctx {
   // q = 3 screen (their float64 kernels are in k_screens.hip)
   int nl = 2, na = 8, span = 1;
   bool generic = false;
+  // grounded box (boundary = FEP3M_BOUNDARY_GROUNDED, Section 2.6): mesh
+  // vectors of Pb = p n + 1 nodes per axis ([z][y][x] per configuration),
+  // the dense 1-D stiffness and mass of the box and the eigenbasis of the
+  // interior pencil (K1_II V = M1_II V Lambda, V^T M1_II V = I)
+  bool box = false;
+  int Pb = 0;
+  double *bxb = nullptr, *bxphi = nullptr, *bxy = nullptr, *bxt1 = nullptr, *bxt2 = nullptr, *bxt3 = nullptr;
+  double *bxK1 = nullptr, *bxM1 = nullptr, *bxV = nullptr, *bxLam = nullptr;
+  BoxNodes bxnodes{};
   fep3m_options opt{};
   hipStream_t stream = nullptr;
   std::string err;
@@ -351,8 +360,9 @@ struct fep3m_ctx {
   void check_inputs() {   // flags and per-configuration charge sums, already on the host
     int fl;
     std::memcpy(&fl, host_scal + 4, sizeof(int));
-    if (fl) throw Status(FEP3M_ERR_NONFINITE, "non-finite position or charge");
-    for (int bb = 0; bb < nb; ++bb) {
+    if (fl & 1) throw Status(FEP3M_ERR_NONFINITE, "non-finite position or charge");
+    if (fl & 2) throw Status(FEP3M_ERR_ARG, "positions must lie inside the box (0, L)^3");
+    for (int bb = 0; bb < nb && !box; ++bb) {   // a grounded box takes any net charge
       const double sq = host_cs[kCsQ * nb + bb], sa = host_cs[kCsQabs * nb + bb];
       if (std::fabs(sq) > 1e-10 * sa)
         throw Status(FEP3M_ERR_NOT_NEUTRAL, "charges are not neutral: sum Q = " + std::to_string(sq) +
@@ -367,6 +377,10 @@ struct fep3m_ctx {
   void solve(const double *rhs, double *out, int which);
   void fdm_solve(const double *rhs, double *out, int which);
   void build_fdm();
+  void build_box();
+  void box_apply(const double *v, double *y);
+  void box_solve();
+  void forward_box(double *Phi, double *U);
   void build_near_fft();
   void mesh_solve(double *rhs, double *out, int which, int nsys = 1);
   void adjoint_rhs();
@@ -402,6 +416,12 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   na = nl * nl * nl;
   span = scr.span;
   generic = !(o.support == FEP3M_SUPPORT_ONE && q == 3);
+  box = o.boundary == FEP3M_BOUNDARY_GROUNDED;
+  if (box) {   // the box runs on the float64 table-sum kernels, the pair sum on rows of elements
+    generic = true;
+    plan = PairPlan{2, 2, 0};
+    tuned = true;
+  }
   compute_tables(p, scr, nsr, B, T_host);
   Mat g = load_weights(p, scr);
   Mat ke, me;
@@ -507,7 +527,8 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   host_scal = host_mirror(64, host_scal_buf, "pinned scalars");
 
   build_mg();
-  if (opt.solver == FEP3M_SOLVER_FDM) build_fdm();
+  if (box) build_box();
+  else if (opt.solver == FEP3M_SOLVER_FDM) build_fdm();
   // partials serve every two-stage reduction: the fixed reduction grids and
   // the per-tile partials of the fine-level operator
   partial_len = std::max(partial_len, size_t(2) * nb * apply_blocks(lv[0].op) + 64);
@@ -866,6 +887,146 @@ int fep3m_ctx::vcycle(int l, const T *f, double *dot_part) {
   return cheb_smooth<T>(l, f, false, dot_part);
 }
 
+// Grounded box: the dense 1-D stiffness and mass on the p n + 1 nodes of
+// an axis (non-periodic assembly), the generalised eigenbasis of the
+// interior pencil, the GLL nodes, and the box vectors.
+void fep3m_ctx::build_box() {
+  Pb = p * n + 1;
+  const int Pi = Pb - 2;
+  const size_t nv = size_t(Pb) * Pb * Pb * nb;
+  bxb = alloc<double>(nv, "box load");
+  bxphi = alloc<double>(nv, "box potential");
+  bxy = alloc<double>(nv, "box operator output");
+  bxt1 = alloc<double>(nv, "box work");
+  bxt2 = alloc<double>(nv, "box work");
+  bxt3 = alloc<double>(nv, "box work");
+  Mat K1, M1;
+  assemble_1d(p, n, false, K1, M1);
+  std::vector<double> kc(size_t(Pb) * Pb), mc(size_t(Pb) * Pb);
+  for (int i = 0; i < Pb; ++i)
+    for (int j = 0; j < Pb; ++j) {   // column-major (both symmetric)
+      kc[i + size_t(j) * Pb] = K1(i, j);
+      mc[i + size_t(j) * Pb] = M1(i, j);
+    }
+  Mat Ki(Pi, Pi), Mi(Pi, Pi);
+  for (int i = 0; i < Pi; ++i)
+    for (int j = 0; j < Pi; ++j) {
+      Ki(i, j) = K1(i + 1, j + 1);
+      Mi(i, j) = M1(i + 1, j + 1);
+    }
+  Vec lamv;
+  Mat V;
+  sym_gen_eig(Ki, Mi, lamv, V);
+  std::vector<double> vc(size_t(Pi) * Pi);
+  for (int i = 0; i < Pi; ++i)
+    for (int j = 0; j < Pi; ++j) vc[i + size_t(j) * Pi] = V(i, j);
+  bxK1 = alloc<double>(kc.size(), "box stiffness");
+  bxM1 = alloc<double>(mc.size(), "box mass");
+  bxV = alloc<double>(vc.size(), "box interior eigenvectors");
+  bxLam = alloc<double>(size_t(Pi), "box interior eigenvalues");
+  hip_check(hipMemcpy(bxK1, kc.data(), kc.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+  hip_check(hipMemcpy(bxM1, mc.data(), mc.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+  hip_check(hipMemcpy(bxV, vc.data(), vc.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+  hip_check(hipMemcpy(bxLam, lamv.data(), size_t(Pi) * sizeof(double), hipMemcpyHostToDevice), "upload");
+  const Vec nodes = gll_nodes(p);
+  for (int a = 0; a <= p; ++a) bxnodes.x[a] = nodes[a];
+}
+
+// y = K v on the box (all nodes; the rows of the interior nodes are those of
+// the Dirichlet problem): K = Kx My Mz + Mx Ky Mz + Mx My Kz as dense 1-D
+// transforms, y = Kx (My Mz v) + Mx (Ky Mz v + My Kz v).
+void fep3m_ctx::box_apply(const double *v, double *y) {
+  const size_t nv = size_t(Pb) * Pb * Pb * nb;
+  launch_axis_transform(stream, Pb, 2, nb, bxM1, false, v, bxt1);      // Mz v
+  launch_axis_transform(stream, Pb, 1, nb, bxM1, false, bxt1, bxt2);   // My Mz v
+  launch_axis_transform(stream, Pb, 0, nb, bxK1, false, bxt2, y);      // Kx My Mz v
+  launch_axis_transform(stream, Pb, 1, nb, bxK1, false, bxt1, bxt2);   // Ky Mz v
+  launch_axis_transform(stream, Pb, 2, nb, bxK1, false, v, bxt1);      // Kz v
+  launch_axis_transform(stream, Pb, 1, nb, bxM1, false, bxt1, bxt3);   // My Kz v
+  launch_box_axpby(stream, nv, 1.0, bxt3, 1.0, bxt2);
+  launch_axis_transform(stream, Pb, 0, nb, bxM1, false, bxt2, bxt1);   // Mx (Ky Mz v + My Kz v)
+  launch_box_axpby(stream, nv, 1.0, bxt1, 1.0, y);
+}
+
+// Interior solve of the box: bxphi holds phi_B on the boundary and zero
+// inside; K_II phi_I = b_I - K_IB phi_B by fast diagonalisation of the
+// interior pencil, phi_I written into bxphi.  The relative residual of the
+// interior equations (against the norm of their right side) is measured
+// with one more operator apply; above 1e-9 the call fails.
+void fep3m_ctx::box_solve() {
+  const int Pi = Pb - 2;
+  const size_t nv = size_t(Pb) * Pb * Pb * nb, ni = size_t(Pi) * Pi * Pi * nb;
+  box_apply(bxphi, bxy);                                    // K phi_B
+  int K = launch_box_resid(stream, Pb, nb, bxb, bxy, partial);
+  launch_sum_partials(stream, K, partial, pcs.bn2, nb);     // |b_I - K_IB phi_B|^2
+  launch_box_axpby(stream, nv, 1.0, bxb, -1.0, bxy);        // r = b - K phi_B
+  launch_box_interior(stream, Pb, nb, true, bxy, bxt1);
+  launch_axis_transform(stream, Pi, 0, nb, bxV, true, bxt1, bxt2);
+  launch_axis_transform(stream, Pi, 1, nb, bxV, true, bxt2, bxt1);
+  launch_axis_transform(stream, Pi, 2, nb, bxV, true, bxt1, bxt2);
+  launch_fdm_scale(stream, ni, Pi, -1, bxLam, bxt2);        // no null mode
+  launch_axis_transform(stream, Pi, 2, nb, bxV, false, bxt2, bxt1);
+  launch_axis_transform(stream, Pi, 1, nb, bxV, false, bxt1, bxt2);
+  launch_axis_transform(stream, Pi, 0, nb, bxV, false, bxt2, bxt3);
+  launch_box_interior(stream, Pb, nb, false, bxt3, bxphi);
+  box_apply(bxphi, bxy);
+  K = launch_box_resid(stream, Pb, nb, bxb, bxy, partial);
+  launch_sum_partials(stream, K, partial, pcs.rr, nb);
+  launch_pcg_scalars(stream, nb, kPcgStart, 0.0, pcs);
+  launch_pcg_scalars(stream, nb, kPcgResid, 0.0, pcs);
+  store_rel(0);
+  check_launch("box solve");
+  hip_check(hipMemcpyAsync(host_cs, pcs.rel, nb * sizeof(double), hipMemcpyDeviceToHost, stream), "copy residuals");
+  sync("box residual");
+  double relmax = 0.0;
+  for (int bb = 0; bb < nb; ++bb) relmax = std::max(relmax, host_cs[bb]);
+  stats.mg_iterations = 0;
+  stats.mg_rel_residual = relmax;
+  if (!(relmax <= 1e-9))
+    throw Status(FEP3M_ERR_NOT_CONVERGED, "box solve left relative residual " + std::to_string(relmax));
+}
+
+// Forward pass in the grounded box (after binning and sorting): moments,
+// load, the near field without phi (W = -Psi), the near pairs, the
+// boundary values -Phi_sr (eq. bcadjust with g = 0), the interior solve,
+// W = phi_E - Psi, interpolation and energy.
+void fep3m_ctx::forward_box(double *Phi, double *U) {
+  stage_mark(FEP3M_PROF_ASSIGN, true);
+  stage_mark(FEP3M_PROF_MOMENTS, true);
+  if (launch_moments_g(stream, nb, n, nl, N, start, sg, sQ, C) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "moments variant");
+  stage_mark(FEP3M_PROF_MOMENTS, false);
+  stage_mark(FEP3M_PROF_LOAD, true);
+  if (launch_load_g(stream, nb, n, p, span, nl, 1, C, gw, bxb, partial) < 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "load variant");
+  stage_mark(FEP3M_PROF_LOAD, false);
+  stage_mark(FEP3M_PROF_ASSIGN, false);
+  stage_mark(FEP3M_PROF_NEAR, true);
+  if (launch_psi_g(stream, nb, n, nsr, p, nl, 1, C, T, nullptr, Wel) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
+  stage_mark(FEP3M_PROF_NEAR, false);
+  pair_pass(false);
+  stage_mark(FEP3M_PROF_SOLVE, true);
+  launch_box_fill(stream, size_t(Pb) * Pb * Pb * nb, 0.0, bxphi);
+  if (launch_box_bvals(stream, nb, n, nsr, p, N, bxnodes, start, sg, sQ, Wel, bxphi) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "boundary values variant");
+  box_solve();
+  stage_mark(FEP3M_PROF_SOLVE, false);
+  if (launch_box_addphi(stream, nb, n, p, bxphi, Wel) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "element field variant");
+  stage_mark(FEP3M_PROF_INTERP, true);
+  stage_mark(FEP3M_PROF_INTERP_KERNEL, true);
+  if (launch_interp(stream, nb, off_d, p, n, N, 1.0 / h, bas, sg, Wel, phip_s, perm, phim_s, phi_s, Phi) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "interpolation variant");
+  stage_mark(FEP3M_PROF_INTERP_KERNEL, false);
+  if (U) {
+    const int Ke = launch_energy(stream, nb, off_d, N, sQ, phi_s, partial);
+    launch_sum_partials(stream, Ke, partial, cfgs(kCsEnergy), nb);
+    launch_half(stream, nb, cfgs(kCsEnergy), U);
+  }
+  stage_mark(FEP3M_PROF_INTERP, false);
+}
+
 // PCG on K out = rhs (rhs compatible), preconditioned by one V-cycle, for
 // every configuration of the batch at once: the scalars of each
 // configuration live on the device (one thread per configuration updates
@@ -987,7 +1148,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   stage_mark(FEP3M_PROF_SORT, true);
   launch_fill_int(stream, MT, 0, count);
   launch_fill_int(stream, 4, 0, flags);
-  const int gb = launch_bin(stream, nb, off_d, N, x, Qc, L, n, gtmp, elem, slot, count, flags, partial);
+  const int gb = launch_bin(stream, nb, off_d, N, x, Qc, L, n, box ? 1 : 0, gtmp, elem, slot, count, flags, partial);
   launch_sum_partials(stream, gb, partial, cfgs(kCsQ), nb);
   launch_sum_partials(stream, gb, partial + size_t(nb) * gb, cfgs(kCsQabs), nb);
   if (!capturing) {   // under capture the same checks run after each replay
@@ -1003,6 +1164,10 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   items_titem = -1;   // the pair work list follows this call's element starts
   if (mixed) launch_local_f32(stream, n, N, sg, sQ, su, si, sel);
   stage_mark(FEP3M_PROF_SORT, false);
+  if (box) {
+    forward_box(Phi, U);
+    return;
+  }
   // overlap only with the decompositions of short blocks (one wave per
   // element, rows of elements) that interleave with the solve's; persistent
   // waves would hold every CU for the pass
@@ -1040,7 +1205,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   }
   stage_mark(FEP3M_PROF_MOMENTS, false);
   stage_mark(FEP3M_PROF_LOAD, true);
-  const int Kl = generic ? launch_load_g(stream, nb, n, p, span, nl, C, gw, b, partial)
+  const int Kl = generic ? launch_load_g(stream, nb, n, p, span, nl, 0, C, gw, b, partial)
                          : launch_load(stream, nb, n, p, C, gw, b, partial);
   stage_mark(FEP3M_PROF_LOAD, false);
   if (Kl < 0) throw Status(FEP3M_ERR_UNSUPPORTED, "load variant");
@@ -1073,7 +1238,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
     adj_near_ready = pair_forces;
     prof.near_both = pair_forces;
   } else if (generic) {
-    ps = launch_psi_g(stream, nb, n, nsr, p, nl, C, T, sol, Wel);
+    ps = launch_psi_g(stream, nb, n, nsr, p, nl, 0, C, T, sol, Wel);
   } else
     ps = mixed ? launch_psi<float>(stream, nb, n, nsr, p, C, Tf, sol, Welf)
                : launch_psi<double>(stream, nb, n, nsr, p, C, T, sol, Wel);
@@ -1101,8 +1266,8 @@ int fep3m_ctx::pair_launch(const PairPlan &pl, bool pair_forces) {
   double *fp = pair_forces ? fpair : nullptr;
   if (pl.kind == 2) {
     if (mixed) return -1;
-    return launch_pair_rows(stream, nb, n, nsr, pl.titem, N, start, rowstart, rnit, ritem_start, riscan_max, ritems,
-                            scan_scr, sg, sQ, phip_s, fp);
+    return launch_pair_rows(stream, nb, n, nsr, pl.titem, box ? 1 : 0, N, start, rowstart, rnit, ritem_start,
+                            riscan_max, ritems, scan_scr, sg, sQ, phip_s, fp);
   }
   if (pl.kind == 0)
     return mixed ? launch_pair_f32(stream, nb, n, nsr, N, start, si, sel, phip_s, fp)
@@ -1265,6 +1430,7 @@ void fep3m_ctx::run_once(const double *x, const double *Qc, double *Phi, double 
 }
 
 void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ) {
+  if (box && (F || dUdQ)) throw Status(FEP3M_ERR_UNSUPPORTED, "forces in the grounded box are not implemented");
   fwd_valid = false;
   if (opt.use_graph && !prof.on && opt.solver == FEP3M_SOLVER_MG) evaluate_graph(x, Qc, Phi, U, F, dUdQ);
   else run_once(x, Qc, Phi, U, F, dUdQ);
@@ -1369,6 +1535,7 @@ void fep3m_ctx::evaluate_graph(const double *x, const double *Qc, double *Phi, d
 }
 
 void fep3m_ctx::backward(int64_t gen, double *F, double *dUdQ) {
+  if (box) throw Status(FEP3M_ERR_UNSUPPORTED, "forces in the grounded box are not implemented");
   if (!fwd_valid || gen != int64_t(generation))
     throw Status(FEP3M_ERR_ARG, "backward needs the state of forward call " + std::to_string(gen) +
                                     " but the context holds call " + std::to_string(generation) +
@@ -1463,6 +1630,10 @@ bool valid_options(const fep3m_options &o, std::string &why) {
   if (o.near_field < FEP3M_NEAR_AUTO || o.near_field > FEP3M_NEAR_FFT) { why = "unknown near_field"; return false; }
   if (o.support != FEP3M_SUPPORT_ONE && o.support != FEP3M_SUPPORT_27) { why = "unknown support"; return false; }
   if (o.pair_stream != 0 && o.pair_stream != 1) { why = "pair_stream must be 0 or 1"; return false; }
+  if (o.boundary != FEP3M_BOUNDARY_PERIODIC && o.boundary != FEP3M_BOUNDARY_GROUNDED) {
+    why = "unknown boundary";
+    return false;
+  }
   if (o.table_box % 2 == 0 || o.table_box < 2 * o.n_sr + 3 || o.table_box > 41) {
     why = "table_box must be odd, > 2 n_sr + 1 and <= 41";
     return false;
@@ -1488,6 +1659,7 @@ int fep3m_default_options(fep3m_options *opt) {
   opt->near_field = FEP3M_NEAR_AUTO;
   opt->pair_stream = 1;
   opt->support = FEP3M_SUPPORT_ONE;
+  opt->boundary = FEP3M_BOUNDARY_PERIODIC;
   return FEP3M_OK;
 }
 
@@ -1525,6 +1697,13 @@ int create_common(double L, const std::vector<int64_t> &Ns, const int32_t dims[3
     }
   }
   if (o.near_field == FEP3M_NEAR_FFT && !fft_size_ok(dims[0])) return FEP3M_ERR_UNSUPPORTED;
+  if (o.boundary == FEP3M_BOUNDARY_GROUNDED &&
+      (o.support != FEP3M_SUPPORT_ONE || o.precision != FEP3M_PRECISION_FP64 || o.solver != FEP3M_SOLVER_FDM ||
+       o.near_field == FEP3M_NEAR_FFT || o.use_graph || static_storage)) {
+    g_create_error = "the grounded box takes one-element screens in float64 with the exact mesh solve and the direct "
+                     "near field, eager (no graph, no static storage)";
+    return FEP3M_ERR_UNSUPPORTED;
+  }
   int dev = -1;
   if (static_storage) {
     // no tuning events, graph staging buffers, side stream or library handles

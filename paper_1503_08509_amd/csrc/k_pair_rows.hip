@@ -52,8 +52,11 @@ struct RowRuns {
 // SL lanes per target (each walks every SL-th source of the target's
 // window; their sums are added at the end in a fixed order), 64 / SL
 // targets per wave.
+// box: the near block is cut at the faces of [0, n)^3: rows outside are
+// skipped (a block-uniform test) and the x-range is clipped, so no run is
+// wrapped.
 template <int NSR, bool FORCE, int SL>
-__global__ __launch_bounds__(kRowTargets) void k_pair_rows(int n, int64_t N, const int *__restrict__ start,
+__global__ __launch_bounds__(kRowTargets) void k_pair_rows(int n, int box, int64_t N, const int *__restrict__ start,
                                                            const int2 *__restrict__ items,
                                                            const int *__restrict__ nitems,
                                                            const double *__restrict__ sg,
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(kRowTargets) void k_pair_rows(int n, int64_t N, con
   }
   auto elem_of = [&](int s) { return min(int(floor(sg[s])), n - 1); };
   const int exA = elem_of(t0), exB = elem_of(te - 1);
-  const int uA = exA - NSR, uB = exB + NSR;
+  const int uA = box ? max(exA - NSR, 0) : exA - NSR, uB = box ? min(exB + NSR, n - 1) : exB + NSR;
   double acc = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
   auto pair = [&](const double4 &q) {
     const double dx = q.x - tx, dyv = q.y - ty, dzv = q.z - tz;
@@ -103,9 +106,11 @@ __global__ __launch_bounds__(kRowTargets) void k_pair_rows(int n, int64_t N, con
   };
   for (int dz = -NSR; dz <= NSR; ++dz) {
     int zz = ez + dz, sz = 0;
+    if (box && (zz < 0 || zz >= n)) continue;
     if (zz < 0) { zz += n; sz = -1; } else if (zz >= n) { zz -= n; sz = 1; }
     for (int dy = -NSR; dy <= NSR; ++dy) {
       int yy = ey + dy, sy = 0;
+      if (box && (yy < 0 || yy >= n)) continue;
       if (yy < 0) { yy += n; sy = -1; } else if (yy >= n) { yy -= n; sy = 1; }
       RowRuns rw;
       rw.st = stc + n * (yy + n * zz);
@@ -122,8 +127,9 @@ __global__ __launch_bounds__(kRowTargets) void k_pair_rows(int n, int64_t N, con
       const bool central = dy == 0 && dz == 0;
       int lo = 0, hi = 0, self = -1;
       if (act) {
-        lo = rw.off(ext - NSR) + sl;   // this lane's sources: lo, lo + SL, ...
-        hi = rw.off(ext + NSR + 1);
+        const int wa = box ? max(ext - NSR, 0) : ext - NSR, wb = box ? min(ext + NSR, n - 1) : ext + NSR;
+        lo = rw.off(wa) + sl;   // this lane's sources: lo, lo + SL, ...
+        hi = rw.off(wb + 1);
         if (central) self = rw.off(ext) + (t - rw.st[ext]);
       }
       for (int c0 = 0; c0 < U; c0 += kRowCap) {
@@ -178,23 +184,23 @@ __global__ __launch_bounds__(kRowTargets) void k_pair_rows(int n, int64_t N, con
 }
 
 template <int NSR, int SL>
-void pair_rows_impl(hipStream_t s, int grid, int n, int64_t N, const int *start, const int2 *items, const int *nitems,
-                    const double *sg, const double *sQ, double *phip, double *fpair) {
+void pair_rows_impl(hipStream_t s, int grid, int n, int box, int64_t N, const int *start, const int2 *items,
+                    const int *nitems, const double *sg, const double *sQ, double *phip, double *fpair) {
   if (fpair)
-    hipLaunchKernelGGL((k_pair_rows<NSR, true, SL>), dim3(grid), dim3(kRowTargets), 0, s, n, N, start, items, nitems,
-                       sg, sQ, phip, fpair);
+    hipLaunchKernelGGL((k_pair_rows<NSR, true, SL>), dim3(grid), dim3(kRowTargets), 0, s, n, box, N, start, items,
+                       nitems, sg, sQ, phip, fpair);
   else
-    hipLaunchKernelGGL((k_pair_rows<NSR, false, SL>), dim3(grid), dim3(kRowTargets), 0, s, n, N, start, items, nitems,
-                       sg, sQ, phip, fpair);
+    hipLaunchKernelGGL((k_pair_rows<NSR, false, SL>), dim3(grid), dim3(kRowTargets), 0, s, n, box, N, start, items,
+                       nitems, sg, sQ, phip, fpair);
 }
 
 template <int NSR>
-int pair_rows_sl(hipStream_t s, int sl, int grid, int n, int64_t N, const int *start, const int2 *items,
+int pair_rows_sl(hipStream_t s, int sl, int grid, int n, int box, int64_t N, const int *start, const int2 *items,
                  const int *nitems, const double *sg, const double *sQ, double *phip, double *fpair) {
   switch (sl) {
-    case 1: pair_rows_impl<NSR, 1>(s, grid, n, N, start, items, nitems, sg, sQ, phip, fpair); return 0;
-    case 2: pair_rows_impl<NSR, 2>(s, grid, n, N, start, items, nitems, sg, sQ, phip, fpair); return 0;
-    case 4: pair_rows_impl<NSR, 4>(s, grid, n, N, start, items, nitems, sg, sQ, phip, fpair); return 0;
+    case 1: pair_rows_impl<NSR, 1>(s, grid, n, box, N, start, items, nitems, sg, sQ, phip, fpair); return 0;
+    case 2: pair_rows_impl<NSR, 2>(s, grid, n, box, N, start, items, nitems, sg, sQ, phip, fpair); return 0;
+    case 4: pair_rows_impl<NSR, 4>(s, grid, n, box, N, start, items, nitems, sg, sQ, phip, fpair); return 0;
     default: return -1;
   }
 }
@@ -205,18 +211,18 @@ int pair_rows_items_max(int nb, int n, int64_t N) {   // for up to 64 targets pe
   return nb * n * n + int(N / 16) + 1;
 }
 
-int launch_pair_rows(hipStream_t s, int nb, int n, int nsr, int sl, int64_t N, const int *start, int *rowstart,
-                     int *rnit, int *ritem_start, int *rscan_max, int2 *ritems, int *scan_scratch, const double *sg,
-                     const double *sQ, double *phip, double *fpair) {
+int launch_pair_rows(hipStream_t s, int nb, int n, int nsr, int sl, int box, int64_t N, const int *start,
+                     int *rowstart, int *rnit, int *ritem_start, int *rscan_max, int2 *ritems, int *scan_scratch,
+                     const double *sg, const double *sQ, double *phip, double *fpair) {
   if (sl != 1 && sl != 2 && sl != 4) return -1;
   const int RT = nb * n * n, tpw = kRowTargets / sl;
   hipLaunchKernelGGL(k_row_starts, dim3((RT + 256) / 256), dim3(256), 0, s, RT, n, start, rowstart);
   launch_items(s, RT, tpw, rowstart, rnit, ritem_start, rscan_max, ritems, scan_scratch);
   const int grid = RT + int(N / tpw) + 1;
   switch (nsr) {
-    case 1: return pair_rows_sl<1>(s, sl, grid, n, N, start, ritems, ritem_start + RT, sg, sQ, phip, fpair);
-    case 2: return pair_rows_sl<2>(s, sl, grid, n, N, start, ritems, ritem_start + RT, sg, sQ, phip, fpair);
-    case 3: return pair_rows_sl<3>(s, sl, grid, n, N, start, ritems, ritem_start + RT, sg, sQ, phip, fpair);
+    case 1: return pair_rows_sl<1>(s, sl, grid, n, box, N, start, ritems, ritem_start + RT, sg, sQ, phip, fpair);
+    case 2: return pair_rows_sl<2>(s, sl, grid, n, box, N, start, ritems, ritem_start + RT, sg, sQ, phip, fpair);
+    case 3: return pair_rows_sl<3>(s, sl, grid, n, box, N, start, ritems, ritem_start + RT, sg, sQ, phip, fpair);
     default: return -1;
   }
 }

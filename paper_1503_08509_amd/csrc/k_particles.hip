@@ -31,7 +31,7 @@ __device__ __forceinline__ double block_sum_p(double v, double *red) {
 // sum |Q| go to partial[blockIdx] and partial[gridDim.x + blockIdx].
 __global__ __launch_bounds__(256) void k_bin(int64_t N, int K, const int *__restrict__ off,
                                              const double *__restrict__ x, const double *__restrict__ Q, double L,
-                                             int n, double *__restrict__ gtmp, int *__restrict__ elem,
+                                             int n, int box, double *__restrict__ gtmp, int *__restrict__ elem,
                                              int *__restrict__ slot, int *__restrict__ count, int *__restrict__ flags,
                                              double *__restrict__ partial) {
   __shared__ double red[256];
@@ -46,6 +46,7 @@ __global__ __launch_bounds__(256) void k_bin(int64_t N, int K, const int *__rest
     for (int k = 0; k < 3; ++k) {
       const double xv = x[3 * i + k];
       if (!isfinite(xv)) ok = false;
+      if (box && !(xv > 0.0 && xv < L)) atomicOr(flags, 2);   // outside the box (the run is refused)
       double s = xv / L;
       s = s - floor(s);
       double t = s * double(n);
@@ -516,10 +517,10 @@ inline int grid_n(int64_t n, int maxb = 4096) {
 int bin_grid(int64_t N, int nb) { return seg_blocks(nb, size_t((N + nb - 1) / nb)); }
 
 int launch_bin(hipStream_t s, int nb, const int *off, int64_t N, const double *x, const double *Q, double L, int n,
-               double *gtmp, int *elem, int *slot, int *count, int *flags, double *partial) {
+               int box, double *gtmp, int *elem, int *slot, int *count, int *flags, double *partial) {
   const int K = bin_grid(N, nb);
-  hipLaunchKernelGGL(k_bin, dim3(nb * K), dim3(256), 0, s, N, K, off, x, Q, L, n, gtmp, elem, slot, count, flags,
-                     partial);
+  hipLaunchKernelGGL(k_bin, dim3(nb * K), dim3(256), 0, s, N, K, off, x, Q, L, n, box, gtmp, elem, slot, count,
+                     flags, partial);
   return K;
 }
 void launch_scan(hipStream_t s, int M, const int *count, int *start, int *maxcount, int *scratch) {

@@ -66,8 +66,9 @@ __global__ __launch_bounds__(256) void k_moments_g(int n, int MT, int64_t N, con
 
 // Sources along one axis whose support holds global node g: SPAN of them
 // (SPAN + 1 at an element vertex), with the node's index j in each support.
+// In a box (no wrap) a source outside [0, n) gets j = -1.
 template <int PO, int SPAN>
-__device__ __forceinline__ int axis_sources(int g, int n, int (&s)[SPAN + 1], int (&j)[SPAN + 1]) {
+__device__ __forceinline__ int axis_sources(int g, int n, bool box, int (&s)[SPAN + 1], int (&j)[SPAN + 1]) {
   constexpr int H = (SPAN - 1) / 2;
   const int e = g / PO, k = g - e * PO;
   const int lo = e - SPAN + (k > 0 ? 1 : 0);   // lowest s - H
@@ -75,21 +76,22 @@ __device__ __forceinline__ int axis_sources(int g, int n, int (&s)[SPAN + 1], in
 #pragma unroll
   for (int c = 0; c < SPAN + 1; ++c) {
     const int sh = lo + c;
-    s[c] = ((sh + H) % n + n) % n;
-    j[c] = g - PO * sh;
+    s[c] = box ? sh + H : ((sh + H) % n + n) % n;
+    j[c] = (box && (s[c] < 0 || s[c] >= n)) ? -1 : g - PO * sh;
   }
   return cnt;
 }
 
 // b (per configuration, K blocks strided over its nodes) and block partials
-// of sum b for the compatibility projection.
+// of sum b for the compatibility projection.  box: the (PO n + 1)^3 nodes of
+// the box [0, n]^3, elements outside it contribute nothing.
 template <int PO, int SPAN, int NL>
-__global__ __launch_bounds__(256) void k_load_g(int n, int K, const double *__restrict__ Call,
+__global__ __launch_bounds__(256) void k_load_g(int n, int K, int box, const double *__restrict__ Call,
                                                 const double *__restrict__ gw, double *__restrict__ ball,
                                                 double *__restrict__ partial) {
   constexpr int NA = NL * NL * NL, KS = SPAN * PO + 1;
   __shared__ double red[8];
-  const int P = PO * n;
+  const int P = PO * n + (box ? 1 : 0);
   const size_t per = size_t(P) * P * P;
   const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
   const double *C = Call + size_t(cfg) * n * n * n * NA;
@@ -98,19 +100,19 @@ __global__ __launch_bounds__(256) void k_load_g(int n, int K, const double *__re
   for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < per; g += size_t(K) * blockDim.x) {
     const int gx = int(g % P), gy = int((g / P) % P), gz = int(g / (size_t(P) * P));
     int sx[SPAN + 1], jx[SPAN + 1], sy[SPAN + 1], jy[SPAN + 1], sz[SPAN + 1], jz[SPAN + 1];
-    const int cx = axis_sources<PO, SPAN>(gx, n, sx, jx);
-    const int cy = axis_sources<PO, SPAN>(gy, n, sy, jy);
-    const int cz = axis_sources<PO, SPAN>(gz, n, sz, jz);
+    const int cx = axis_sources<PO, SPAN>(gx, n, box, sx, jx);
+    const int cy = axis_sources<PO, SPAN>(gy, n, box, sy, jy);
+    const int cz = axis_sources<PO, SPAN>(gz, n, box, sz, jz);
     double v = 0.0;
 #pragma unroll
     for (int iz = 0; iz < SPAN + 1; ++iz) {
-      if (iz >= cz) continue;
+      if (iz >= cz || jz[iz] < 0) continue;
 #pragma unroll
       for (int iy = 0; iy < SPAN + 1; ++iy) {
-        if (iy >= cy) continue;
+        if (iy >= cy || jy[iy] < 0) continue;
 #pragma unroll
         for (int ix = 0; ix < SPAN + 1; ++ix) {
-          if (ix >= cx) continue;
+          if (ix >= cx || jx[ix] < 0) continue;
           const double *c = C + (size_t(sx[ix]) + size_t(n) * (sy[iy] + size_t(n) * sz[iz])) * NA;
           double tz = 0.0;
           for (int az = 0; az < NL; ++az) {
@@ -139,8 +141,10 @@ __global__ __launch_bounds__(256) void k_load_g(int n, int K, const double *__re
 // moments are staged in LDS and each table value read serves all targets.
 constexpr int kBX = 4, kBY = 2, kBZ = 2, kBT = kBX * kBY * kBZ;
 
+// box: sources outside [0, n)^3 are absent and phi is the (PO n + 1)^3
+// nodal field of the box; a null phi gives W = -Psi.
 template <int PO, int NL>
-__global__ __launch_bounds__(384) void k_psi_g(int n, int nsr, const double *__restrict__ Call,
+__global__ __launch_bounds__(384) void k_psi_g(int n, int nsr, int box, const double *__restrict__ Call,
                                                const double *__restrict__ T, const double *__restrict__ phiall,
                                                double *__restrict__ Wall) {
   constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NA = NL * NL * NL;
@@ -151,9 +155,9 @@ __global__ __launch_bounds__(384) void k_psi_g(int n, int nsr, const double *__r
   int br = blockIdx.x % per_cfg;
   const int bx = br % bxn, by = (br / bxn) % byn, bz = br / (bxn * byn);
   const size_t M = size_t(n) * n * n;
-  const int P = PO * n;
+  const int P = PO * n + (box ? 1 : 0);
   const double *C = Call + size_t(cfg) * M * NA;
-  const double *phi = phiall + size_t(cfg) * P * P * P;
+  const double *phi = phiall ? phiall + size_t(cfg) * P * P * P : nullptr;
   double *W = Wall + size_t(cfg) * M * NM;
   const int S = 2 * nsr + 1, ND = S * S * S;
   const int m = threadIdx.x;
@@ -168,8 +172,14 @@ __global__ __launch_bounds__(384) void k_psi_g(int n, int nsr, const double *__r
       const int ex = bx * kBX + t % kBX, ey = by * kBY + (t / kBX) % kBY, ez = bz * kBZ + t / (kBX * kBY);
       double v = 0.0;
       if (ex < n && ey < n && ez < n) {
-        const int sx = wrapn(ex - Dx, n), sy = wrapn(ey - Dy, n), sz = wrapn(ez - Dz, n);
-        v = C[(size_t(sx) + size_t(n) * (sy + size_t(n) * sz)) * NA + a];
+        int sx = ex - Dx, sy = ey - Dy, sz = ez - Dz;
+        const bool in = sx >= 0 && sx < n && sy >= 0 && sy < n && sz >= 0 && sz < n;
+        if (!box) {
+          sx = wrapn(sx, n);
+          sy = wrapn(sy, n);
+          sz = wrapn(sz, n);
+        }
+        if (!box || in) v = C[(size_t(sx) + size_t(n) * (sy + size_t(n) * sz)) * NA + a];
       }
       Cs[i] = v;
     }
@@ -191,7 +201,7 @@ __global__ __launch_bounds__(384) void k_psi_g(int n, int nsr, const double *__r
     if (ex >= n || ey >= n || ez >= n) continue;
     const int gx = wrapn(PO * ex + mx, P), gy = wrapn(PO * ey + my, P), gz = wrapn(PO * ez + mz, P);
     const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
-    W[E * NM + m] = phi[(size_t(gz) * P + gy) * P + gx] - acc[t];
+    W[E * NM + m] = (phi ? phi[(size_t(gz) * P + gy) * P + gx] : 0.0) - acc[t];
   }
 }
 
@@ -321,32 +331,34 @@ int launch_moments_g(hipStream_t s, int nb, int n, int nl, int64_t N, const int 
 }
 
 template <int PO, int SPAN>
-static int load_g_nl(hipStream_t s, int nb, int n, int nl, int K, const double *C, const double *gw, double *b,
-                     double *partial) {
-#define CALL(NL) hipLaunchKernelGGL((k_load_g<PO, SPAN, NL>), dim3(nb * K), dim3(256), 0, s, n, K, C, gw, b, partial)
+static int load_g_nl(hipStream_t s, int nb, int n, int nl, int K, int box, const double *C, const double *gw,
+                     double *b, double *partial) {
+#define CALL(NL) \
+  hipLaunchKernelGGL((k_load_g<PO, SPAN, NL>), dim3(nb * K), dim3(256), 0, s, n, K, box, C, gw, b, partial)
   FEP3M_NL_SWITCH(nl, CALL)
 #undef CALL
   return 0;
 }
 
-int launch_load_g(hipStream_t s, int nb, int n, int p, int span, int nl, const double *C, const double *gw, double *b,
-                  double *partial) {
-  const int P = p * n;
+int launch_load_g(hipStream_t s, int nb, int n, int p, int span, int nl, int box, const double *C, const double *gw,
+                  double *b, double *partial) {
+  if (box && span != 1) return -1;   // a box holds the one-element screens only
+  const int P = p * n + (box ? 1 : 0);
   const int K = seg_blocks(nb, size_t(P) * P * P);
   int r = -1;
   if (span == 1) {
     switch (p) {
-      case 4: r = load_g_nl<4, 1>(s, nb, n, nl, K, C, gw, b, partial); break;
-      case 5: r = load_g_nl<5, 1>(s, nb, n, nl, K, C, gw, b, partial); break;
-      case 6: r = load_g_nl<6, 1>(s, nb, n, nl, K, C, gw, b, partial); break;
+      case 4: r = load_g_nl<4, 1>(s, nb, n, nl, K, box, C, gw, b, partial); break;
+      case 5: r = load_g_nl<5, 1>(s, nb, n, nl, K, box, C, gw, b, partial); break;
+      case 6: r = load_g_nl<6, 1>(s, nb, n, nl, K, box, C, gw, b, partial); break;
       default: return -1;
     }
   } else if (span == 3) {
     switch (p) {
-      case 3: r = load_g_nl<3, 3>(s, nb, n, nl, K, C, gw, b, partial); break;
-      case 4: r = load_g_nl<4, 3>(s, nb, n, nl, K, C, gw, b, partial); break;
-      case 5: r = load_g_nl<5, 3>(s, nb, n, nl, K, C, gw, b, partial); break;
-      case 6: r = load_g_nl<6, 3>(s, nb, n, nl, K, C, gw, b, partial); break;
+      case 3: r = load_g_nl<3, 3>(s, nb, n, nl, K, box, C, gw, b, partial); break;
+      case 4: r = load_g_nl<4, 3>(s, nb, n, nl, K, box, C, gw, b, partial); break;
+      case 5: r = load_g_nl<5, 3>(s, nb, n, nl, K, box, C, gw, b, partial); break;
+      case 6: r = load_g_nl<6, 3>(s, nb, n, nl, K, box, C, gw, b, partial); break;
       default: return -1;
     }
   }
@@ -354,23 +366,24 @@ int launch_load_g(hipStream_t s, int nb, int n, int p, int span, int nl, const d
 }
 
 template <int PO>
-static int psi_g_nl(hipStream_t s, int nb, int n, int nsr, int nl, const double *C, const double *T,
+static int psi_g_nl(hipStream_t s, int nb, int n, int nsr, int nl, int box, const double *C, const double *T,
                     const double *phi, double *W) {
   const int bricks = ((n + kBX - 1) / kBX) * ((n + kBY - 1) / kBY) * ((n + kBZ - 1) / kBZ);
-#define CALL(NL) \
-  hipLaunchKernelGGL((k_psi_g<PO, NL>), dim3(nb * bricks), dim3(psi_threads(PO)), 0, s, n, nsr, C, T, phi, W)
+#define CALL(NL)                                                                                              \
+  hipLaunchKernelGGL((k_psi_g<PO, NL>), dim3(nb * bricks), dim3(psi_threads(PO)), 0, s, n, nsr, box, C, T, phi, \
+                     W)
   FEP3M_NL_SWITCH(nl, CALL)
 #undef CALL
   return 0;
 }
 
-int launch_psi_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, const double *C, const double *T,
+int launch_psi_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, int box, const double *C, const double *T,
                  const double *phi, double *W) {
   switch (p) {
-    case 3: return psi_g_nl<3>(s, nb, n, nsr, nl, C, T, phi, W);
-    case 4: return psi_g_nl<4>(s, nb, n, nsr, nl, C, T, phi, W);
-    case 5: return psi_g_nl<5>(s, nb, n, nsr, nl, C, T, phi, W);
-    case 6: return psi_g_nl<6>(s, nb, n, nsr, nl, C, T, phi, W);
+    case 3: return psi_g_nl<3>(s, nb, n, nsr, nl, box, C, T, phi, W);
+    case 4: return psi_g_nl<4>(s, nb, n, nsr, nl, box, C, T, phi, W);
+    case 5: return psi_g_nl<5>(s, nb, n, nsr, nl, box, C, T, phi, W);
+    case 6: return psi_g_nl<6>(s, nb, n, nsr, nl, box, C, T, phi, W);
     default: return -1;
   }
 }

@@ -17,8 +17,10 @@ struct GllBasis {
 // and fall in elements b n^3 .. (b+1) n^3 - 1.
 int bin_grid(int64_t N, int nb);
 int energy_grid(int64_t N, int nb);
+// box: positions must lie strictly inside [0, L)^3 (flags bit 2 otherwise);
+// else they wrap periodically.
 int launch_bin(hipStream_t s, int nb, const int *off, int64_t N, const double *x, const double *Q, double L, int n,
-               double *gtmp, int *elem, int *slot, int *count, int *flags, double *partial);
+               int box, double *gtmp, int *elem, int *slot, int *count, int *flags, double *partial);
 // scratch: 2 ceil(M / 2048) ints (tile sums and maxima)
 void launch_scan(hipStream_t s, int M, const int *count, int *start, int *maxcount, int *scratch);
 void launch_scatter(hipStream_t s, int64_t N, const int *elem, const int *slot, const int *start, int *tmp);
@@ -43,10 +45,11 @@ int launch_pair_queue(hipStream_t s, int waves, int n, int nsr, int64_t N, const
 // Work arrays: rowstart, ritem_start nb n^2 + 1 ints, rnit nb n^2,
 // rscan_max 4, ritems pair_rows_items_max() int2, scan_scratch as launch_scan.
 int pair_rows_items_max(int nb, int n, int64_t N);
-// sl: lanes per target (1, 2 or 4; 64 / sl targets per wave)
-int launch_pair_rows(hipStream_t s, int nb, int n, int nsr, int sl, int64_t N, const int *start, int *rowstart,
-                     int *rnit, int *ritem_start, int *rscan_max, int2 *ritems, int *scan_scratch, const double *sg,
-                     const double *sQ, double *phip, double *fpair);
+// sl: lanes per target (1, 2 or 4; 64 / sl targets per wave); box: the near
+// block is cut at the faces of [0, n)^3 (no periodic images)
+int launch_pair_rows(hipStream_t s, int nb, int n, int nsr, int sl, int box, int64_t N, const int *start,
+                     int *rowstart, int *rnit, int *ritem_start, int *rscan_max, int2 *ritems, int *scan_scratch,
+                     const double *sg, const double *sQ, double *phip, double *fpair);
 int launch_interp(hipStream_t s, int nb, const int *off, int p, int n, int64_t N, double inv_h, const GllBasis &bas,
                   const double *sg, const double *Wel, const double *phip, const int *perm, double *phim_s,
                   double *phi_s, double *Phi);
@@ -90,12 +93,32 @@ int launch_forces(hipStream_t s, int nb, const int *off, int p, int n, int nl, i
 // per configuration (-1: unsupported combination), the others 0 or -1.
 int launch_moments_g(hipStream_t s, int nb, int n, int nl, int64_t N, const int *start, const double *sg,
                      const double *sQ, double *C);
-int launch_load_g(hipStream_t s, int nb, int n, int p, int span, int nl, const double *C, const double *gw, double *b,
-                  double *partial);
-int launch_psi_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, const double *C, const double *T,
+// box = 1: the grounded box [0, n]^3 (no wrap, (p n + 1)^3 nodes per
+// configuration; span 1 only); a null phi makes the near field W = -Psi.
+int launch_load_g(hipStream_t s, int nb, int n, int p, int span, int nl, int box, const double *C, const double *gw,
+                  double *b, double *partial);
+int launch_psi_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, int box, const double *C, const double *T,
                  const double *phi, double *W);
 int launch_adj_g(hipStream_t s, int nb, int n, int nsr, int p, int span, int nl, const double *gE, const double *T,
                  const double *lam, const double *gw, double *A);
+
+// grounded box (k_box.hip): mesh vectors of (p n + 1)^3 nodes per
+// configuration, P = p n + 1.
+struct BoxNodes {
+  double x[8];   // GLL nodes of the element (p + 1 used) on [-1/2, 1/2]
+};
+// phi_B = -Phi_sr on the boundary nodes (only those are written); Wneg the
+// near field -Psi per element (launch_psi_g with box = 1 and no phi)
+int launch_box_bvals(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const BoxNodes &nodes, const int *start,
+                     const double *sg, const double *sQ, const double *Wneg, double *phiB);
+// interior nodes of the box <-> contiguous (P - 2)^3 blocks
+void launch_box_interior(hipStream_t s, int P, int nb, bool to_interior, const double *src, double *dst);
+// y = c y + a x (c = 0: y is not read); fill y = v
+void launch_box_axpby(hipStream_t s, size_t total, double a, const double *x, double c, double *y);
+void launch_box_fill(hipStream_t s, size_t total, double v, double *y);
+int launch_box_addphi(hipStream_t s, int nb, int n, int p, const double *phi, double *W);
+// returns K: partial[0, nb K) holds the residual's squares, [nb K, 2 nb K) b's
+int launch_box_resid(hipStream_t s, int P, int nb, const double *b, const double *y, double *partial);
 
 // near field (k_near.hip)
 // T = double, or float (float32 tables, compensated slab sums, float32 W)

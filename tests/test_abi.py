@@ -90,6 +90,35 @@ def test_screen_family_arguments():
     assert h.value is None
 
 
+def test_grounded_box_arguments():
+    """The grounded box (Section 2.6): boundary 0 by default, unknown values
+    refused, and the combinations it does not take (27-element screens,
+    mixed precision, the multigrid solver, the FFT near field, graphs,
+    static storage) refused before any device work."""
+    h = ctypes.c_void_p()
+    d = (ctypes.c_int32 * 3)(8, 8, 8)
+    L = fp.lib()
+    assert fp.default_options().boundary == fp.BOUNDARY_PERIODIC
+
+    def create(q=3, static=False, **kw):
+        o = fp.default_options()
+        o.boundary = fp.BOUNDARY_GROUNDED
+        o.solver = fp.SOLVER_FDM
+        for k, v in kw.items():
+            setattr(o, k, v)
+        f = L.fep3m_create_static if static else L.fep3m_create_ex
+        return f(1.0, 100, d, q, ctypes.byref(o), ctypes.byref(h))
+
+    assert create(boundary=2) == fp.ERR_ARG and create(boundary=-1) == fp.ERR_ARG
+    assert create(solver=fp.SOLVER_MG) == fp.ERR_UNSUPPORTED
+    assert create(2, support=fp.SUPPORT_27) == fp.ERR_UNSUPPORTED
+    assert create(precision=fp.PRECISION_MIXED) == fp.ERR_UNSUPPORTED
+    assert create(near_field=fp.NEAR_FFT) == fp.ERR_UNSUPPORTED
+    assert create(use_graph=1) == fp.ERR_UNSUPPORTED
+    assert create(static=True) == fp.ERR_UNSUPPORTED
+    assert h.value is None
+
+
 @pytest.mark.parametrize("n", [7, 9, 12, 128, 256])
 def test_fft_near_field_needs_power_of_two_mesh(n):
     """The FFT near field is refused (before any device work) unless n is a

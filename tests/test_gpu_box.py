@@ -1,0 +1,103 @@
+"""The grounded box on the GPU (Section 2.6, eq. bcadjust with g = 0):
+potentials and energy through the C ABI against the oracle's box form on
+the same inputs (element by element), the method against the image-charge
+ground truth, a non-neutral set, a batch of boxes, and the refusals
+(positions outside the box, forces)."""
+import numpy as np
+import pytest
+
+import paper_1503_08509_amd as fp
+from oracle import dirichlet as odir
+from oracle import fep3m as ofe
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available()
+    return _t
+
+
+def _layer(N, seed, n, L=1.0, charges="pm1"):
+    """At least half an element from every face; half the charges within
+    one element of a face."""
+    rng = np.random.default_rng(seed)
+    h = L / n
+    x = rng.uniform(0.5 * h, L - 0.5 * h, (N, 3))
+    k = N // 2
+    ax = rng.integers(0, 3, k)
+    side = rng.integers(0, 2, k)
+    d = rng.uniform(0.5, 1.0, k) * h
+    x[np.arange(k), ax] = np.where(side == 1, L - d, d)
+    Q = rng.choice([-1.0, 1.0], N) if charges == "pm1" else rng.uniform(0.0, 1.0, N)
+    return x, Q
+
+
+def _ctx(N, n, q=3, n_sr=3):
+    return fp.Context(1.0, N, n, q=q, n_sr=n_sr, boundary=fp.BOUNDARY_GROUNDED, solver=fp.SOLVER_FDM,
+                      table_box=2 * n_sr + 9)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("N,n,q,n_sr,seed", [(300, 8, 3, 3, 1), (500, 9, 3, 2, 2), (200, 8, 4, 3, 3),
+                                             (200, 7, 2, 3, 4), (2000, 16, 3, 3, 5)])
+def test_box_matches_oracle(torch, N, n, q, n_sr, seed):
+    x, Q = _layer(N, seed, n)
+    ctx = _ctx(N, n, q, n_sr)
+    Phi, U = ctx.energy(torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda())
+    ref = odir.run(x, Q, ofe.Params(L=1.0, n=n, q=q, n_sr=n_sr))
+    e = _rel(Phi.cpu().numpy(), ref["Phi"])
+    print(f"box N={N} n={n} q={q} n_sr={n_sr}: GPU vs oracle Phi {e:.2e}, U {U.item():.10e} vs {ref['U']:.10e}")
+    assert e < 1e-10
+    assert abs(U.item() - ref["U"]) <= 1e-10 * abs(ref["U"])
+    assert ctx.stats()["mg_rel_residual"] < 1e-9
+
+
+def test_box_method_against_images(torch):
+    """The GPU method against the grounded cube's image sum: within the
+    screen's truncation error."""
+    N, n = 400, 8
+    x, Q = _layer(N, 11, n)
+    Phi, U = _ctx(N, n).energy(torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda())
+    ref = odir.image_ewald(x, Q)
+    e = _rel(Phi.cpu().numpy(), ref)
+    print(f"box N={N} n={n}: Phi vs image sum {e:.3e}")
+    assert e < 5e-3
+
+
+def test_box_net_charge_and_batch(torch):
+    """Positive charges only (a grounded box holds any net charge), and a
+    batch of three boxes equal to three single contexts."""
+    n = 8
+    sets = [_layer(150, 20 + k, n, charges="pos") for k in range(3)]
+    x = np.concatenate([s[0] for s in sets])
+    Q = np.concatenate([s[1] for s in sets])
+    ctx = fp.Context(1.0, [150, 150, 150], n, boundary=fp.BOUNDARY_GROUNDED, solver=fp.SOLVER_FDM)
+    Phi, U = ctx.energy(torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda())
+    Phi = Phi.cpu().numpy()
+    for k, (xs, Qs) in enumerate(sets):
+        ref = odir.run(xs, Qs, ofe.Params(L=1.0, n=n))
+        assert _rel(Phi[150 * k:150 * (k + 1)], ref["Phi"]) < 1e-10
+        assert abs(U[k].item() - ref["U"]) <= 1e-10 * abs(ref["U"])
+
+
+def test_box_refusals(torch):
+    n = 8
+    x, Q = _layer(100, 30, n)
+    ctx = _ctx(100, n)
+    tx, tQ = torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda()
+    with pytest.raises(fp.FEP3MError) as ei:
+        ctx.energy_forces(tx, tQ)
+    assert ei.value.status == fp.ERR_UNSUPPORTED
+    bad = x.copy()
+    bad[3, 1] = 1.0                      # on the face x_1 = L
+    with pytest.raises(fp.FEP3MError) as ei:
+        ctx.energy(torch.from_numpy(bad).cuda(), tQ)
+    assert ei.value.status == fp.ERR_ARG
+    Phi, _ = ctx.energy(tx, tQ)           # the context stays usable
+    assert np.all(np.isfinite(Phi.cpu().numpy()))
