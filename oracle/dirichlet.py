@@ -292,3 +292,117 @@ def image_ewald(x, Q, L=1.0, targets=None, points=None, alpha=None, nimg=2, mmax
     N = len(Q)
     t = 8 * (np.arange(N) if targets is None else np.asarray(targets))
     return ewald.ewald(X, QQ, L=L2, alpha=alpha, nimg=nimg, mmax=mmax, targets=t)["Phi"]
+
+
+def assemble(gE, n, p):
+    """Sum per-element nodal values into the box vector (no wrap)."""
+    P = p * n + 1
+    q1 = p + 1
+    loc = gE.reshape(n, n, n, q1, q1, q1)
+    out = np.zeros((P, P, P))
+    idx = p * np.arange(n)[:, None] + np.arange(q1)[None, :]
+    for mz in range(q1):
+        for my in range(q1):
+            for mx in range(q1):
+                out[np.ix_(idx[:, mz], idx[:, my], idx[:, mx])] += loc[:, :, :, mz, my, mx]
+    return out
+
+
+def _boundary_nodes(p, n):
+    """Index arrays (gz, gy, gx) of the boundary nodes, their elements, local
+    node indices and coordinates (element units)."""
+    pos = node_positions(p, n)
+    ne, nk = node_element(p, n)
+    gz, gy, gx = np.nonzero(boundary_mask(p, n))
+    E = ne[gx] + n * (ne[gy] + n * ne[gz])
+    m = nk[gx] + (p + 1) * (nk[gy] + (p + 1) * nk[gz])
+    xb = np.stack([pos[gx], pos[gy], pos[gz]], axis=1)
+    return (gz, gy, gx), E, m, xb, np.stack([ne[gx], ne[gy], ne[gz]], axis=1)
+
+
+def energy_forces(x, Q, params: fep3m.Params):
+    """U, F = -dU/dx and dU/dQ of the grounded-box method (every charge a
+    target), by the adjoint of every stage.  In element units (U_hat = h U,
+    g = x / h):
+
+      U_m = 1/2 <G, phi> - 1/2 sum_E <g_E, Psi_E>,  G = assemble(g),
+      and phi = phiB + K_II^-1 (b_I - K_IB phiB), so that
+      <G, phi> = <lambda, b> + <mu, phiB>,  lambda = K_II^-1 G_I (zero on
+      the boundary),  mu = G - K lambda on the boundary nodes.
+
+    The load b and the table part of phiB are linear in the moments C, the
+    pair part of phiB is -sum_j Q_j / |x_B - x_j|, hence
+      A[E][a] = 4 pi <lambda_E, G_a> - sum_D <g_{E+D}, T_a[D]>
+                + sum_B mu_B T_a[e(B) - E](m_B)
+      dU_hat/dg_i = (pairs) + 1/2 Q_i [sum_m W_E[m] grad u_m + sum_a A grad u^a]
+                    - 1/2 Q_i sum_B mu_B (x_B - g_i) / |x_B - g_i|^3
+      dU_hat/dQ_i = Phi_p + 1/2 Phi_m + 1/2 sum_a A u_i^a
+                    - 1/2 sum_B mu_B / |x_B - g_i|
+    with B over the boundary nodes whose element's near block holds the
+    charge (or the element E).  Physical: F = -(1/h^2) dU_hat/dg,
+    dU/dQ = (1/h) dU_hat/dQ."""
+    from . import adjoint
+
+    x = np.asarray(x, dtype=np.float64)
+    Q = np.asarray(Q, dtype=np.float64)
+    n, p, q, d, n_sr, h = params.n, params.p, params.q, params.d, params.n_sr, params.h
+    fw = run(x, Q, params, stages=True)
+    e, e_lin, u, C, phi = fw["e"], fw["e_lin"], fw["u"], fw["C"], fw["phi"]
+    T = tables.screen_tables(p, q, n_sr, params.B, params.table_bc, "one")
+    allE = np.arange(n**3)
+    W = element_phi(phi, p, n, allE) - near_field(C, T, n, n_sr, allE)
+    gE = adjoint.element_deposit(e_lin, u, Q, n, p)
+    G = assemble(gE, n, p)
+    lam = solve(G, np.zeros_like(G), p, n)
+    mu_full = G - stiffness_apply(lam, p, n)
+    (gz, gy, gx), EB, mB, xb, eB = _boundary_nodes(p, n)
+    mu = mu_full[gz, gy, gx]
+    # moment adjoint
+    g1 = screens.load_weights(p, q, "one")
+    A_exp = screens.moment_exponents(d)
+    Gs = np.stack([np.einsum("k,j,i->kji", g1[az], g1[ay], g1[ax]).ravel() for (ax, ay, az) in A_exp])
+    A = 4.0 * math.pi * element_phi(lam, p, n, allE) @ Gs.T
+    offs = tables.offsets(n_sr)
+    ex, ey, ez = allE % n, (allE // n) % n, allE // (n * n)
+    for iD, (Dx, Dy, Dz) in enumerate(offs):
+        sx, sy, sz = ex + Dx, ey + Dy, ez + Dz
+        ok = (sx >= 0) & (sx < n) & (sy >= 0) & (sy < n) & (sz >= 0) & (sz < n)
+        src = sx[ok] + n * (sy[ok] + n * sz[ok])
+        A[ok] -= gE[src] @ T[:, iD, :].T
+    for iD, (Dx, Dy, Dz) in enumerate(offs):      # source E = e(B) - D inside the box
+        s = eB - np.array([Dx, Dy, Dz])[None, :]
+        ok = np.all((s >= 0) & (s < n), axis=1)
+        Es = s[ok, 0] + n * (s[ok, 1] + n * s[ok, 2])
+        np.add.at(A, Es, mu[ok][:, None] * T[:, iD, mB[ok]].T)
+    # per-charge terms
+    y = e + 0.5 + u
+    grad_v = adjoint.basis_gradients(p, u)
+    grad_a = adjoint.monomial_gradients(u, d)
+    mesh_grad = 0.5 * Q[:, None] * (np.einsum("nkm,nm->nk", grad_v, W[e_lin])
+                                    + np.einsum("nka,na->nk", grad_a, A[e_lin]))
+    dUp = _pair_forces(e, e_lin, u, Q, n, n_sr)
+    near = np.all(np.abs(e[:, None, :] - eB[None, :, :]) <= n_sr, axis=2)   # (N, nB)
+    dv = xb[None, :, :] - y[:, None, :]
+    r = np.sqrt(np.sum(dv * dv, axis=2))
+    wmu = np.where(near, mu[None, :], 0.0)
+    bp = np.einsum("ib,ibk->ik", wmu / r**3, dv)
+    bq = np.sum(wmu / r, axis=1)
+    dU = dUp + mesh_grad - 0.5 * Q[:, None] * bp
+    mono = np.prod(u[:, None, :] ** A_exp[None, :, :], axis=2)
+    dUdQ = (fw["Phi_p"] * h + 0.5 * fw["Phi_m"] * h + 0.5 * np.sum(A[e_lin] * mono, axis=1) - 0.5 * bq) / h
+    return {"U": fw["U"], "Phi": fw["Phi"], "F": -dU / h**2, "dUdQ": dUdQ, "A": A, "lam": lam, "mu": mu}
+
+
+def _pair_forces(e, e_lin, u, Q, n, n_sr):
+    """dU_p/dg_i = sum_j Q_i Q_j (g_j - g_i) / r^3 over the cut near block."""
+    order, start = _sorted(e_lin, n)
+    y = e + 0.5 + u
+    out = np.zeros((len(Q), 3))
+    for E in np.unique(e_lin):
+        ti = np.nonzero(e_lin == E)[0]
+        js = near_sources(E, n, n_sr, order, start)
+        dv = y[js][None, :, :] - y[ti][:, None, :]
+        r = np.sqrt(np.sum(dv * dv, axis=2))
+        r[js[None, :] == ti[:, None]] = np.inf
+        out[ti] = np.einsum("ij,ijk->ik", Q[ti][:, None] * Q[js][None, :] / r**3, dv)
+    return out

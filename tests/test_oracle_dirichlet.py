@@ -170,3 +170,46 @@ def test_method_error_falls_with_the_near_block():
 def test_charges_outside_the_box_are_rejected():
     with pytest.raises(ValueError):
         odir.bin_box(np.array([[0.5, 1.0, 0.5]]), 1.0, 8)
+
+
+def test_box_gradients_match_central_differences():
+    """The adjoint forces and charge derivatives of the grounded-box energy
+    (with the two terms that eq. bcadjust adds: the boundary values depend
+    on the moments and on the positions) equal central differences of the
+    oracle's own energy, for charges next to the faces."""
+    N, n = 60, 7
+    x, Q = _boundary_layer(N, 12, n)
+    P = fep3m.Params(L=1.0, n=n)
+    out = odir.energy_forces(x, Q, P)
+    h = P.h
+    # probe charges away from element faces (the energy is smooth inside elements)
+    frac = (x / h) % 1.0
+    ok = np.nonzero(np.all((frac > 0.1) & (frac < 0.9), axis=1))[0][:6]
+    assert len(ok) >= 4
+    dx = 1e-6
+    for i in ok:
+        for k in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += dx
+            xm[i, k] -= dx
+            fd = -(odir.run(xp, Q, P)["U"] - odir.run(xm, Q, P)["U"]) / (2 * dx)
+            assert abs(out["F"][i, k] - fd) < 1e-5 * np.max(np.abs(out["F"][ok])), (i, k, out["F"][i, k], fd)
+        Qp, Qm = Q.copy(), Q.copy()
+        Qp[i] += 1e-6
+        Qm[i] -= 1e-6
+        fdq = (odir.run(x, Qp, P)["U"] - odir.run(x, Qm, P)["U"]) / 2e-6
+        assert abs(out["dUdQ"][i] - fdq) < 1e-6 * np.max(np.abs(out["dUdQ"])), (i, out["dUdQ"][i], fdq)
+
+
+def test_box_forces_against_images():
+    """Forces of the grounded-box method against the image-charge forces
+    (Ewald of the image set): within the screen's truncation error."""
+    N, n = 200, 8
+    x, Q = _boundary_layer(N, 13, n)
+    out = odir.energy_forces(x, Q, fep3m.Params(L=1.0, n=n))
+    X, QQ = odir.image_charges(x, Q, 1.0)
+    from oracle import ewald
+    ref = ewald.ewald(X, QQ, L=2.0, alpha=2.5, nimg=2, mmax=8, forces=True, targets=8 * np.arange(N))["F"]
+    err = np.linalg.norm(out["F"] - ref) / np.linalg.norm(ref)
+    print(f"grounded box forces vs images: {err:.3e}")
+    assert err < 1e-2
