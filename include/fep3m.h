@@ -116,9 +116,11 @@ enum {
                              (the interior pencil diagonalised by dense
                              transforms) and near_field DIRECT or AUTO; no
                              use_graph, no static storage (else create returns
-                             FEP3M_ERR_UNSUPPORTED).  fep3m_potential and
-                             fep3m_energy only: the force entry points return
-                             FEP3M_ERR_UNSUPPORTED.  Charges within about half
+                             FEP3M_ERR_UNSUPPORTED).  Forces and dU/dQ come
+                             from the adjoint with two more terms: the
+                             boundary values depend on the moments (tables)
+                             and on the positions (near pairs).  Charges
+                             within about half
                              an element of a face are resolved poorly: their
                              images lie within h of the face, where the mesh
                              cannot follow them.                               */

@@ -381,12 +381,16 @@ def energy_forces(x, Q, params: fep3m.Params):
     mesh_grad = 0.5 * Q[:, None] * (np.einsum("nkm,nm->nk", grad_v, W[e_lin])
                                     + np.einsum("nka,na->nk", grad_a, A[e_lin]))
     dUp = _pair_forces(e, e_lin, u, Q, n, n_sr)
-    near = np.all(np.abs(e[:, None, :] - eB[None, :, :]) <= n_sr, axis=2)   # (N, nB)
-    dv = xb[None, :, :] - y[:, None, :]
-    r = np.sqrt(np.sum(dv * dv, axis=2))
-    wmu = np.where(near, mu[None, :], 0.0)
-    bp = np.einsum("ib,ibk->ik", wmu / r**3, dv)
-    bq = np.sum(wmu / r, axis=1)
+    bp = np.zeros((len(Q), 3))
+    bq = np.zeros(len(Q))
+    for c0 in range(0, len(Q), 64):                     # charges in chunks (N x boundary-node arrays)
+        sl = slice(c0, c0 + 64)
+        near = np.all(np.abs(e[sl, None, :] - eB[None, :, :]) <= n_sr, axis=2)
+        dv = xb[None, :, :] - y[sl, None, :]
+        r = np.sqrt(np.sum(dv * dv, axis=2))
+        wmu = np.where(near, mu[None, :], 0.0)
+        bp[sl] = np.einsum("ib,ibk->ik", wmu / r**3, dv)
+        bq[sl] = np.sum(wmu / r, axis=1)
     dU = dUp + mesh_grad - 0.5 * Q[:, None] * bp
     mono = np.prod(u[:, None, :] ** A_exp[None, :, :], axis=2)
     dUdQ = (fw["Phi_p"] * h + 0.5 * fw["Phi_m"] * h + 0.5 * np.sum(A[e_lin] * mono, axis=1) - 0.5 * bq) / h

@@ -148,6 +148,7 @@ struct fep3m_ctx {
   bool box = false;
   int Pb = 0;
   double *bxb = nullptr, *bxphi = nullptr, *bxy = nullptr, *bxt1 = nullptr, *bxt2 = nullptr, *bxt3 = nullptr;
+  double *bxg = nullptr, *bxlam = nullptr;   // reverse pass: assembled deposit, adjoint potential
   double *bxK1 = nullptr, *bxM1 = nullptr, *bxV = nullptr, *bxLam = nullptr;
   BoxNodes bxnodes{};
   fep3m_options opt{};
@@ -379,8 +380,9 @@ struct fep3m_ctx {
   void build_fdm();
   void build_box();
   void box_apply(const double *v, double *y);
-  void box_solve();
-  void forward_box(double *Phi, double *U);
+  void box_solve(const double *rhs, double *sol, int which);
+  void forward_box(double *Phi, double *U, bool pair_forces);
+  void reverse_box(double *F, double *dUdQ);
   void build_near_fft();
   void mesh_solve(double *rhs, double *out, int which, int nsys = 1);
   void adjoint_rhs();
@@ -900,6 +902,8 @@ void fep3m_ctx::build_box() {
   bxt1 = alloc<double>(nv, "box work");
   bxt2 = alloc<double>(nv, "box work");
   bxt3 = alloc<double>(nv, "box work");
+  bxg = alloc<double>(nv, "box assembled deposit");
+  bxlam = alloc<double>(nv, "box adjoint potential");
   Mat K1, M1;
   assemble_1d(p, n, false, K1, M1);
   std::vector<double> kc(size_t(Pb) * Pb), mc(size_t(Pb) * Pb);
@@ -948,18 +952,19 @@ void fep3m_ctx::box_apply(const double *v, double *y) {
   launch_box_axpby(stream, nv, 1.0, bxt1, 1.0, y);
 }
 
-// Interior solve of the box: bxphi holds phi_B on the boundary and zero
-// inside; K_II phi_I = b_I - K_IB phi_B by fast diagonalisation of the
-// interior pencil, phi_I written into bxphi.  The relative residual of the
+// Interior solve of the box: sol holds phi_B on the boundary and zero
+// inside; K_II phi_I = rhs_I - K_IB phi_B by fast diagonalisation of the
+// interior pencil, phi_I written into sol.  The relative residual of the
 // interior equations (against the norm of their right side) is measured
-// with one more operator apply; above 1e-9 the call fails.
-void fep3m_ctx::box_solve() {
+// with one more operator apply; above 1e-9 the call fails.  which: 0 the
+// forward solve, 1 the adjoint one (their statistics slots).
+void fep3m_ctx::box_solve(const double *rhs, double *sol, int which) {
   const int Pi = Pb - 2;
   const size_t nv = size_t(Pb) * Pb * Pb * nb, ni = size_t(Pi) * Pi * Pi * nb;
-  box_apply(bxphi, bxy);                                    // K phi_B
-  int K = launch_box_resid(stream, Pb, nb, bxb, bxy, partial);
-  launch_sum_partials(stream, K, partial, pcs.bn2, nb);     // |b_I - K_IB phi_B|^2
-  launch_box_axpby(stream, nv, 1.0, bxb, -1.0, bxy);        // r = b - K phi_B
+  box_apply(sol, bxy);                                      // K phi_B
+  int K = launch_box_resid(stream, Pb, nb, rhs, bxy, partial);
+  launch_sum_partials(stream, K, partial, pcs.bn2, nb);     // |rhs_I - K_IB phi_B|^2
+  launch_box_axpby(stream, nv, 1.0, rhs, -1.0, bxy);        // r = rhs - K phi_B
   launch_box_interior(stream, Pb, nb, true, bxy, bxt1);
   launch_axis_transform(stream, Pi, 0, nb, bxV, true, bxt1, bxt2);
   launch_axis_transform(stream, Pi, 1, nb, bxV, true, bxt2, bxt1);
@@ -968,20 +973,24 @@ void fep3m_ctx::box_solve() {
   launch_axis_transform(stream, Pi, 2, nb, bxV, false, bxt2, bxt1);
   launch_axis_transform(stream, Pi, 1, nb, bxV, false, bxt1, bxt2);
   launch_axis_transform(stream, Pi, 0, nb, bxV, false, bxt2, bxt3);
-  launch_box_interior(stream, Pb, nb, false, bxt3, bxphi);
-  box_apply(bxphi, bxy);
-  K = launch_box_resid(stream, Pb, nb, bxb, bxy, partial);
+  launch_box_interior(stream, Pb, nb, false, bxt3, sol);
+  box_apply(sol, bxy);
+  K = launch_box_resid(stream, Pb, nb, rhs, bxy, partial);
   launch_sum_partials(stream, K, partial, pcs.rr, nb);
   launch_pcg_scalars(stream, nb, kPcgStart, 0.0, pcs);
   launch_pcg_scalars(stream, nb, kPcgResid, 0.0, pcs);
-  store_rel(0);
+  store_rel(which);
   check_launch("box solve");
   hip_check(hipMemcpyAsync(host_cs, pcs.rel, nb * sizeof(double), hipMemcpyDeviceToHost, stream), "copy residuals");
   sync("box residual");
   double relmax = 0.0;
   for (int bb = 0; bb < nb; ++bb) relmax = std::max(relmax, host_cs[bb]);
-  stats.mg_iterations = 0;
-  stats.mg_rel_residual = relmax;
+  if (which == 0) {
+    stats.mg_iterations = 0;
+    stats.mg_rel_residual = relmax;
+  } else {
+    stats.adj_iterations = 0;
+  }
   if (!(relmax <= 1e-9))
     throw Status(FEP3M_ERR_NOT_CONVERGED, "box solve left relative residual " + std::to_string(relmax));
 }
@@ -990,7 +999,7 @@ void fep3m_ctx::box_solve() {
 // load, the near field without phi (W = -Psi), the near pairs, the
 // boundary values -Phi_sr (eq. bcadjust with g = 0), the interior solve,
 // W = phi_E - Psi, interpolation and energy.
-void fep3m_ctx::forward_box(double *Phi, double *U) {
+void fep3m_ctx::forward_box(double *Phi, double *U, bool pair_forces) {
   stage_mark(FEP3M_PROF_ASSIGN, true);
   stage_mark(FEP3M_PROF_MOMENTS, true);
   if (launch_moments_g(stream, nb, n, nl, N, start, sg, sQ, C) != 0)
@@ -1005,12 +1014,12 @@ void fep3m_ctx::forward_box(double *Phi, double *U) {
   if (launch_psi_g(stream, nb, n, nsr, p, nl, 1, C, T, nullptr, Wel) != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
   stage_mark(FEP3M_PROF_NEAR, false);
-  pair_pass(false);
+  pair_pass(pair_forces);
   stage_mark(FEP3M_PROF_SOLVE, true);
   launch_box_fill(stream, size_t(Pb) * Pb * Pb * nb, 0.0, bxphi);
   if (launch_box_bvals(stream, nb, n, nsr, p, N, bxnodes, start, sg, sQ, Wel, bxphi) != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "boundary values variant");
-  box_solve();
+  box_solve(bxb, bxphi, 0);
   stage_mark(FEP3M_PROF_SOLVE, false);
   if (launch_box_addphi(stream, nb, n, p, bxphi, Wel) != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "element field variant");
@@ -1025,6 +1034,38 @@ void fep3m_ctx::forward_box(double *Phi, double *U) {
     launch_half(stream, nb, cfgs(kCsEnergy), U);
   }
   stage_mark(FEP3M_PROF_INTERP, false);
+}
+
+// Reverse pass in the grounded box.  With G the assembled deposit,
+// lambda = K_II^-1 G_I (zero on the boundary) and mu = G - K lambda on the
+// boundary nodes, the gradients of U are the periodic ones (moment adjoint
+// from lambda and the near deposits, cut at the faces) plus the terms of
+// the boundary values: A[E][a] += sum_B mu_B T_a[e(B) - E][m_B] and, per
+// charge, the derivative of -Q_j / |x_B - x_j| weighted by mu_B.
+void fep3m_ctx::reverse_box(double *F, double *dUdQ) {
+  stage_mark(FEP3M_PROF_ADJ_SOLVE, true);
+  stage_mark(FEP3M_PROF_DEPOSIT, true);
+  if (launch_deposit(stream, nb, p, n, N, bas, start, sg, sQ, gE) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "deposit variant");
+  if (launch_box_assemble(stream, nb, n, p, gE, bxg) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "assembly variant");
+  stage_mark(FEP3M_PROF_DEPOSIT, false);
+  const size_t nv = size_t(Pb) * Pb * Pb * nb;
+  launch_box_fill(stream, nv, 0.0, bxlam);
+  box_solve(bxg, bxlam, 1);
+  box_apply(bxlam, bxy);
+  launch_box_axpby(stream, nv, 1.0, bxg, -1.0, bxy);   // mu = G - K lambda (read on the boundary nodes)
+  stage_mark(FEP3M_PROF_ADJ_SOLVE, false);
+  stage_mark(FEP3M_PROF_ADJ_NEAR, true);
+  if (launch_adj_g(stream, nb, n, nsr, p, span, nl, 1, gE, T, bxlam, gw, Aadj) != 0 ||
+      launch_box_adj_bnd(stream, nb, n, nsr, p, nl, T, bxy, Aadj) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
+  stage_mark(FEP3M_PROF_ADJ_NEAR, false);
+  stage_mark(FEP3M_PROF_FORCES, true);
+  if (launch_forces<double>(stream, nb, off_d, p, n, nl, N, 1.0 / h, bas, sg, sQ, Wel, Aadj, fpair, phip_s, phim_s,
+                            perm, F, dUdQ) != 0 ||
+      launch_box_charge_bnd(stream, nb, n, nsr, p, N, off_d, 1.0 / h, bxnodes, sg, sQ, bxy, perm, F, dUdQ) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "forces variant");
+  stage_mark(FEP3M_PROF_FORCES, false);
 }
 
 // PCG on K out = rhs (rhs compatible), preconditioned by one V-cycle, for
@@ -1165,7 +1206,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   if (mixed) launch_local_f32(stream, n, N, sg, sQ, su, si, sel);
   stage_mark(FEP3M_PROF_SORT, false);
   if (box) {
-    forward_box(Phi, U);
+    forward_box(Phi, U, pair_forces);
     return;
   }
   // overlap only with the decompositions of short blocks (one wave per
@@ -1357,6 +1398,10 @@ void fep3m_ctx::adjoint_rhs() {
 }
 
 void fep3m_ctx::reverse(double *F, double *dUdQ) {
+  if (box) {
+    reverse_box(F, dUdQ);
+    return;
+  }
   const int fwd_iters = stats.mg_iterations;
   const double fwd_rel = stats.mg_rel_residual;
   if (!lam_ready) {   // lambda not solved with phi: a backward call after an energy-only forward
@@ -1374,7 +1419,7 @@ void fep3m_ctx::reverse(double *F, double *dUdQ) {
     if (as == 0) as = launch_adj_fft_finish(stream, nb, n, p, lam, gw, za, Aadj);
     adj_near_ready = false;
   } else if (generic) {
-    as = launch_adj_g(stream, nb, n, nsr, p, span, nl, gE, T, lam, gw, Aadj);
+    as = launch_adj_g(stream, nb, n, nsr, p, span, nl, 0, gE, T, lam, gw, Aadj);
   } else {
     as = launch_adj_moments(stream, nb, p, n, nsr, gE, Tt, lam, gw, Aadj);
   }
@@ -1430,7 +1475,6 @@ void fep3m_ctx::run_once(const double *x, const double *Qc, double *Phi, double 
 }
 
 void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ) {
-  if (box && (F || dUdQ)) throw Status(FEP3M_ERR_UNSUPPORTED, "forces in the grounded box are not implemented");
   fwd_valid = false;
   if (opt.use_graph && !prof.on && opt.solver == FEP3M_SOLVER_MG) evaluate_graph(x, Qc, Phi, U, F, dUdQ);
   else run_once(x, Qc, Phi, U, F, dUdQ);
@@ -1535,7 +1579,6 @@ void fep3m_ctx::evaluate_graph(const double *x, const double *Qc, double *Phi, d
 }
 
 void fep3m_ctx::backward(int64_t gen, double *F, double *dUdQ) {
-  if (box) throw Status(FEP3M_ERR_UNSUPPORTED, "forces in the grounded box are not implemented");
   if (!fwd_valid || gen != int64_t(generation))
     throw Status(FEP3M_ERR_ARG, "backward needs the state of forward call " + std::to_string(gen) +
                                     " but the context holds call " + std::to_string(generation) +

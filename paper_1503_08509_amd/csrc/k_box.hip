@@ -157,6 +157,155 @@ __global__ __launch_bounds__(256) void k_box_resid(int P, int K, int nb, const d
   }
 }
 
+// The boundary nodes B whose element e(B) lies within nsr elements of Ec
+// along every axis, each visited once (x faces whole, y faces without the
+// x edges, z faces without the x and y edges): f(g, e, k) per node.
+template <int PO, class Fn>
+__device__ __forceinline__ void for_near_boundary(const int (&Ec)[3], int n, int nsr, Fn f) {
+  const int P = PO * n + 1;
+  int lo[3], hi[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int el = max(Ec[c] - nsr, 0), eh = min(Ec[c] + nsr, n - 1);
+    lo[c] = PO * el;
+    hi[c] = eh == n - 1 ? P - 1 : PO * eh + PO - 1;
+  }
+  for (int face = 0; face < 6; ++face) {
+    const int ax = face >> 1, side = face & 1;
+    if (side == 0 ? Ec[ax] > nsr : (n - 1 - Ec[ax]) > nsr) continue;
+    int g[3], a0[3], a1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a0[c] = lo[c];
+      a1[c] = hi[c];
+      if (c < ax) {   // nodes on the faces of a lower axis were visited there
+        a0[c] = max(a0[c], 1);
+        a1[c] = min(a1[c], P - 2);
+      }
+    }
+    a0[ax] = a1[ax] = side ? P - 1 : 0;
+    for (g[2] = a0[2]; g[2] <= a1[2]; ++g[2])
+      for (g[1] = a0[1]; g[1] <= a1[1]; ++g[1])
+        for (g[0] = a0[0]; g[0] <= a1[0]; ++g[0]) {
+          int e[3], k[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            e[c] = node_elem(g[c], PO, n);
+            k[c] = g[c] - PO * e[c];
+          }
+          f(g, e, k);
+        }
+  }
+}
+
+// Box assembly of element-local nodal values: G[node] = sum over the
+// elements holding the node of gE[E][m] (gather form, no wrap).
+template <int PO>
+__global__ __launch_bounds__(256) void k_box_assemble(int n, int nb, const double *__restrict__ gE,
+                                                      double *__restrict__ G) {
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
+  const int P = PO * n + 1;
+  const size_t per = size_t(P) * P * P, M = size_t(n) * n * n;
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < per * nb; t += size_t(gridDim.x) * blockDim.x) {
+    const int cfg = int(t / per);
+    const size_t l = t % per;
+    const int g[3] = {int(l % P), int((l / P) % P), int(l / (size_t(P) * P))};
+    int es[3][2], ks[3][2], cnt[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int e = g[c] / PO, k = g[c] - PO * e;
+      cnt[c] = 0;
+      if (k == 0 && e > 0) { es[c][cnt[c]] = e - 1; ks[c][cnt[c]] = PO; ++cnt[c]; }
+      if (e < n) { es[c][cnt[c]] = e; ks[c][cnt[c]] = k; ++cnt[c]; }
+    }
+    double v = 0.0;
+    for (int iz = 0; iz < cnt[2]; ++iz)
+      for (int iy = 0; iy < cnt[1]; ++iy)
+        for (int ix = 0; ix < cnt[0]; ++ix) {
+          const size_t E = size_t(cfg) * M + es[0][ix] + size_t(n) * (es[1][iy] + size_t(n) * es[2][iz]);
+          v += gE[E * NM + ks[0][ix] + Q1 * (ks[1][iy] + Q1 * ks[2][iz])];
+        }
+    G[t] = v;
+  }
+}
+
+// Boundary part of the moment adjoint: A[E][a] += sum_B mu_B T[a][e(B) - E][m_B]
+// over the boundary nodes whose element has E in its near block; one thread
+// per element (elements farther than nsr from every face have none).
+template <int PO, int NL>
+__global__ __launch_bounds__(256) void k_box_adj_bnd(int n, int nsr, int nb, const double *__restrict__ T,
+                                                     const double *__restrict__ mu, double *__restrict__ A) {
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NA = NL * NL * NL;
+  const int P = PO * n + 1, S = 2 * nsr + 1, ND = S * S * S;
+  const size_t per = size_t(P) * P * P, M = size_t(n) * n * n;
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < M * nb; t += size_t(gridDim.x) * blockDim.x) {
+    const int cfg = int(t / M);
+    const size_t El = t % M;
+    const int Ec[3] = {int(El % n), int((El / n) % n), int(El / (size_t(n) * n))};
+    if (Ec[0] > nsr && Ec[1] > nsr && Ec[2] > nsr && n - 1 - Ec[0] > nsr && n - 1 - Ec[1] > nsr &&
+        n - 1 - Ec[2] > nsr)
+      continue;
+    const double *muc = mu + size_t(cfg) * per;
+    double acc[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = 0.0;
+    for_near_boundary<PO>(Ec, n, nsr, [&](const int (&g)[3], const int (&e)[3], const int (&k)[3]) {
+      const double mv = muc[(size_t(g[2]) * P + g[1]) * P + g[0]];
+      const int iD = (e[0] - Ec[0] + nsr) + S * ((e[1] - Ec[1] + nsr) + S * (e[2] - Ec[2] + nsr));
+      const int m = k[0] + Q1 * (k[1] + Q1 * k[2]);
+#pragma unroll
+      for (int a = 0; a < NA; ++a) acc[a] += mv * T[(size_t(a) * ND + iD) * NM + m];
+    });
+#pragma unroll
+    for (int a = 0; a < NA; ++a) A[t * NA + a] += acc[a];
+  }
+}
+
+// Boundary part of the per-charge gradients: for a sorted charge s near a
+// face, bp = sum_B mu_B (x_B - x_s) / r^3 and bq = sum_B mu_B / r over the
+// boundary nodes whose element's near block holds it; F += s2 Q bp / 2 and
+// dU/dQ -= inv_h bq / 2 (physical units), in caller order.
+template <int PO>
+__global__ __launch_bounds__(256) void k_box_charge_bnd(int n, int nsr, int nb, int64_t N, const int *__restrict__ off,
+                                                        double inv_h, BoxNodes nodes, const double *__restrict__ sg,
+                                                        const double *__restrict__ sQ, const double *__restrict__ mu,
+                                                        const int *__restrict__ perm, double *__restrict__ F,
+                                                        double *__restrict__ dUdQ) {
+  const int P = PO * n + 1;
+  const size_t per = size_t(P) * P * P;
+  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < N; s += int64_t(gridDim.x) * blockDim.x) {
+    const double xs[3] = {sg[s], sg[N + s], sg[2 * N + s]};
+    int Ec[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Ec[c] = min(int(floor(xs[c])), n - 1);
+    if (Ec[0] > nsr && Ec[1] > nsr && Ec[2] > nsr && n - 1 - Ec[0] > nsr && n - 1 - Ec[1] > nsr &&
+        n - 1 - Ec[2] > nsr)
+      continue;
+    const double *muc = mu + size_t(cfg_of(off, nb, s)) * per;
+    double bx = 0.0, by = 0.0, bz = 0.0, bq = 0.0;
+    for_near_boundary<PO>(Ec, n, nsr, [&](const int (&g)[3], const int (&e)[3], const int (&k)[3]) {
+      const double mv = muc[(size_t(g[2]) * P + g[1]) * P + g[0]];
+      const double dx = e[0] + 0.5 + nodes.x[k[0]] - xs[0];
+      const double dy = e[1] + 0.5 + nodes.x[k[1]] - xs[1];
+      const double dz = e[2] + 0.5 + nodes.x[k[2]] - xs[2];
+      const double ri = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+      const double w = mv * ri * ri * ri;
+      bx += w * dx;
+      by += w * dy;
+      bz += w * dz;
+      bq += mv * ri;
+    });
+    const int i = perm[s];
+    const double q = sQ[s], c = 0.5 * inv_h * inv_h * q;
+    if (F) {
+      F[3 * size_t(i) + 0] += c * bx;
+      F[3 * size_t(i) + 1] += c * by;
+      F[3 * size_t(i) + 2] += c * bz;
+    }
+    if (dUdQ) dUdQ[i] -= 0.5 * inv_h * bq;
+  }
+}
+
 inline int grid_of(size_t count) {
   size_t g = (count + 255) / 256;
   if (g < 1) g = 1;
@@ -207,6 +356,41 @@ int launch_box_resid(hipStream_t s, int P, int nb, const double *b, const double
   if (K < 1) K = 1;
   hipLaunchKernelGGL(k_box_resid, dim3(nb * K), dim3(256), 0, s, P, K, nb, b, y, partial);
   return K;
+}
+
+int launch_box_assemble(hipStream_t s, int nb, int n, int p, const double *gE, double *G) {
+  const size_t P = size_t(p) * n + 1;
+  const int g = grid_of(P * P * P * nb);
+  switch (p) {
+    case 4: hipLaunchKernelGGL(k_box_assemble<4>, dim3(g), dim3(256), 0, s, n, nb, gE, G); return 0;
+    case 5: hipLaunchKernelGGL(k_box_assemble<5>, dim3(g), dim3(256), 0, s, n, nb, gE, G); return 0;
+    case 6: hipLaunchKernelGGL(k_box_assemble<6>, dim3(g), dim3(256), 0, s, n, nb, gE, G); return 0;
+    default: return -1;
+  }
+}
+
+int launch_box_adj_bnd(hipStream_t s, int nb, int n, int nsr, int p, int nl, const double *T, const double *mu,
+                       double *A) {
+  const int g = grid_of(size_t(n) * n * n * nb);
+  const int key = 10 * p + nl;   // one-element screens: nl = q - 1, p = q + 2
+  switch (key) {
+    case 41: hipLaunchKernelGGL((k_box_adj_bnd<4, 1>), dim3(g), dim3(256), 0, s, n, nsr, nb, T, mu, A); return 0;
+    case 52: hipLaunchKernelGGL((k_box_adj_bnd<5, 2>), dim3(g), dim3(256), 0, s, n, nsr, nb, T, mu, A); return 0;
+    case 63: hipLaunchKernelGGL((k_box_adj_bnd<6, 3>), dim3(g), dim3(256), 0, s, n, nsr, nb, T, mu, A); return 0;
+    default: return -1;
+  }
+}
+
+int launch_box_charge_bnd(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const int *off, double inv_h,
+                          const BoxNodes &nodes, const double *sg, const double *sQ, const double *mu, const int *perm,
+                          double *F, double *dUdQ) {
+  const int g = grid_of(size_t(N));
+  switch (p) {
+    case 4: hipLaunchKernelGGL(k_box_charge_bnd<4>, dim3(g), dim3(256), 0, s, n, nsr, nb, N, off, inv_h, nodes, sg, sQ, mu, perm, F, dUdQ); return 0;
+    case 5: hipLaunchKernelGGL(k_box_charge_bnd<5>, dim3(g), dim3(256), 0, s, n, nsr, nb, N, off, inv_h, nodes, sg, sQ, mu, perm, F, dUdQ); return 0;
+    case 6: hipLaunchKernelGGL(k_box_charge_bnd<6>, dim3(g), dim3(256), 0, s, n, nsr, nb, N, off, inv_h, nodes, sg, sQ, mu, perm, F, dUdQ); return 0;
+    default: return -1;
+  }
 }
 
 }  // namespace fep3m

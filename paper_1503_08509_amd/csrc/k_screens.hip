@@ -209,7 +209,7 @@ __global__ __launch_bounds__(384) void k_psi_g(int n, int nsr, int box, const do
 // on bricks of target elements: thread (t, a) pairs, the deposits of the
 // brick's sources for each offset staged in LDS.
 template <int PO, int NL>
-__global__ __launch_bounds__(256) void k_adj_near_g(int n, int nsr, const double *__restrict__ gEall,
+__global__ __launch_bounds__(256) void k_adj_near_g(int n, int nsr, int box, const double *__restrict__ gEall,
                                                     const double *__restrict__ T, double *__restrict__ Aall) {
   constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NA = NL * NL * NL, NP = kBT * NA;
   constexpr int PT = (NP + 255) / 256;   // (t, a) pairs per thread
@@ -234,8 +234,14 @@ __global__ __launch_bounds__(256) void k_adj_near_g(int n, int nsr, const double
       const int ex = bx * kBX + t % kBX, ey = by * kBY + (t / kBX) % kBY, ez = bz * kBZ + t / (kBX * kBY);
       double v = 0.0;
       if (ex < n && ey < n && ez < n) {
-        const int sx = wrapn(ex + Dx, n), sy = wrapn(ey + Dy, n), sz = wrapn(ez + Dz, n);
-        v = gE[(size_t(sx) + size_t(n) * (sy + size_t(n) * sz)) * NM + m];
+        int sx = ex + Dx, sy = ey + Dy, sz = ez + Dz;
+        const bool in = sx >= 0 && sx < n && sy >= 0 && sy < n && sz >= 0 && sz < n;
+        if (!box) {
+          sx = wrapn(sx, n);
+          sy = wrapn(sy, n);
+          sz = wrapn(sz, n);
+        }
+        if (!box || in) v = gE[(size_t(sx) + size_t(n) * (sy + size_t(n) * sz)) * NM + m];
       }
       Gs[i] = v;
     }
@@ -265,12 +271,13 @@ __global__ __launch_bounds__(256) void k_adj_near_g(int n, int nsr, const double
 
 // Mesh part of the moment adjoint: A[E][a] += 4 pi sum over the support's
 // nodes of lambda * gw[ax][jx] gw[ay][jy] gw[az][jz], one thread per
-// (element, moment), contracted along x, then y, then z.
+// (element, moment), contracted along x, then y, then z.  box: lambda on the
+// (PO n + 1)^3 nodes of the box (SPAN 1, so no index leaves it).
 template <int PO, int SPAN, int NL>
-__global__ __launch_bounds__(256) void k_adj_lam_g(int n, int MT, const double *__restrict__ lamall,
+__global__ __launch_bounds__(256) void k_adj_lam_g(int n, int MT, int box, const double *__restrict__ lamall,
                                                    const double *__restrict__ gw, double *__restrict__ A) {
   constexpr int NA = NL * NL * NL, KS = SPAN * PO + 1, H = (SPAN - 1) / 2;
-  const int M = n * n * n, P = PO * n;
+  const int M = n * n * n, P = PO * n + (box ? 1 : 0);
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < int64_t(MT) * NA;
        t += int64_t(gridDim.x) * blockDim.x) {
     const int E = int(t / NA), a = int(t % NA);
@@ -389,35 +396,36 @@ int launch_psi_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, int box, 
 }
 
 template <int PO, int SPAN>
-static int adj_g_nl(hipStream_t s, int nb, int n, int nsr, int nl, const double *gE, const double *T,
+static int adj_g_nl(hipStream_t s, int nb, int n, int nsr, int nl, int box, const double *gE, const double *T,
                     const double *lam, const double *gw, double *A) {
   const int bricks = ((n + kBX - 1) / kBX) * ((n + kBY - 1) / kBY) * ((n + kBZ - 1) / kBZ);
   const int MT = nb * n * n * n;
   const int g = grid_for_count(int64_t(MT) * nl * nl * nl);
 #define CALL(NL)                                                                                                  \
-  hipLaunchKernelGGL((k_adj_near_g<PO, NL>), dim3(nb * bricks), dim3(256), 0, s, n, nsr, gE, T, A);              \
-  hipLaunchKernelGGL((k_adj_lam_g<PO, SPAN, NL>), dim3(g), dim3(256), 0, s, n, MT, lam, gw, A)
+  hipLaunchKernelGGL((k_adj_near_g<PO, NL>), dim3(nb * bricks), dim3(256), 0, s, n, nsr, box, gE, T, A);         \
+  hipLaunchKernelGGL((k_adj_lam_g<PO, SPAN, NL>), dim3(g), dim3(256), 0, s, n, MT, box, lam, gw, A)
   FEP3M_NL_SWITCH(nl, CALL)
 #undef CALL
   return 0;
 }
 
-int launch_adj_g(hipStream_t s, int nb, int n, int nsr, int p, int span, int nl, const double *gE, const double *T,
-                 const double *lam, const double *gw, double *A) {
+int launch_adj_g(hipStream_t s, int nb, int n, int nsr, int p, int span, int nl, int box, const double *gE,
+                 const double *T, const double *lam, const double *gw, double *A) {
+  if (box && span != 1) return -1;
   if (span == 1) {
     switch (p) {
-      case 4: return adj_g_nl<4, 1>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
-      case 5: return adj_g_nl<5, 1>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
-      case 6: return adj_g_nl<6, 1>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
+      case 4: return adj_g_nl<4, 1>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
+      case 5: return adj_g_nl<5, 1>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
+      case 6: return adj_g_nl<6, 1>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
       default: return -1;
     }
   }
   if (span == 3) {
     switch (p) {
-      case 3: return adj_g_nl<3, 3>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
-      case 4: return adj_g_nl<4, 3>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
-      case 5: return adj_g_nl<5, 3>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
-      case 6: return adj_g_nl<6, 3>(s, nb, n, nsr, nl, gE, T, lam, gw, A);
+      case 3: return adj_g_nl<3, 3>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
+      case 4: return adj_g_nl<4, 3>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
+      case 5: return adj_g_nl<5, 3>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
+      case 6: return adj_g_nl<6, 3>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
       default: return -1;
     }
   }

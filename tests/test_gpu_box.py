@@ -1,8 +1,8 @@
 """The grounded box on the GPU (Section 2.6, eq. bcadjust with g = 0):
-potentials and energy through the C ABI against the oracle's box form on
-the same inputs (element by element), the method against the image-charge
-ground truth, a non-neutral set, a batch of boxes, and the refusals
-(positions outside the box, forces)."""
+potentials, energy, forces and dU/dQ through the C ABI against the
+oracle's box form on the same inputs (element by element), the method
+against the image-charge ground truth, a non-neutral set, a batch of boxes,
+the autograd path, and the refusal of positions outside the box."""
 import numpy as np
 import pytest
 
@@ -91,9 +91,6 @@ def test_box_refusals(torch):
     x, Q = _layer(100, 30, n)
     ctx = _ctx(100, n)
     tx, tQ = torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda()
-    with pytest.raises(fp.FEP3MError) as ei:
-        ctx.energy_forces(tx, tQ)
-    assert ei.value.status == fp.ERR_UNSUPPORTED
     bad = x.copy()
     bad[3, 1] = 1.0                      # on the face x_1 = L
     with pytest.raises(fp.FEP3MError) as ei:
@@ -101,3 +98,42 @@ def test_box_refusals(torch):
     assert ei.value.status == fp.ERR_ARG
     Phi, _ = ctx.energy(tx, tQ)           # the context stays usable
     assert np.all(np.isfinite(Phi.cpu().numpy()))
+
+
+@pytest.mark.parametrize("N,n,q,seed", [(300, 8, 3, 41), (200, 8, 4, 42), (200, 7, 2, 43), (800, 16, 3, 44)])
+def test_box_forces_match_oracle(torch, N, n, q, seed):
+    """Forces and dU/dQ in the grounded box (the reverse pass with the
+    boundary terms of eq. bcadjust) against the oracle's adjoint, charge by
+    charge."""
+    x, Q = _layer(N, seed, n)
+    ctx = _ctx(N, n, q)
+    out = ctx.energy_forces(torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda(), dUdQ=True, Phi=True)
+    ref = odir.energy_forces(x, Q, ofe.Params(L=1.0, n=n, q=q))
+    eF = _rel(out["F"].cpu().numpy(), ref["F"])
+    eQ = _rel(out["dUdQ"].cpu().numpy(), ref["dUdQ"])
+    print(f"box forces N={N} n={n} q={q}: F {eF:.2e}, dU/dQ {eQ:.2e}")
+    assert eF < 1e-10 and eQ < 1e-10
+    assert _rel(out["Phi"].cpu().numpy(), ref["Phi"]) < 1e-10
+    assert abs(out["U"].item() - ref["U"]) <= 1e-10 * abs(ref["U"])
+
+
+def test_box_autograd_and_images(torch):
+    """The autograd path (energy, then the reverse pass on its state) gives
+    the fused call's gradients, and the forces lie within the screen's
+    truncation error of the image-charge forces."""
+    N, n = 300, 8
+    x, Q = _layer(N, 45, n)
+    ctx = _ctx(N, n)
+    tx = torch.from_numpy(x).cuda().requires_grad_(True)
+    tQ = torch.from_numpy(Q).cuda().requires_grad_(True)
+    U = fp.FEP3MEnergy.apply(tx, tQ, ctx)
+    U.backward()
+    fused = ctx.energy_forces(tx.detach(), tQ.detach(), dUdQ=True)
+    assert _rel(-tx.grad.cpu().numpy(), fused["F"].cpu().numpy()) < 1e-12
+    assert _rel(tQ.grad.cpu().numpy(), fused["dUdQ"].cpu().numpy()) < 1e-12
+    from oracle import ewald
+    X, QQ = odir.image_charges(x, Q, 1.0)
+    ref = ewald.ewald(X, QQ, L=2.0, alpha=2.5, nimg=2, mmax=8, forces=True, targets=8 * np.arange(N))["F"]
+    e = _rel(fused["F"].cpu().numpy(), ref)
+    print(f"box forces vs image sum: {e:.3e}")
+    assert e < 1e-2
