@@ -105,7 +105,7 @@ enum {
 /* Boundary conditions (Section 2.6). */
 enum {
   FEP3M_BOUNDARY_PERIODIC = 0,  /* the periodic cube (the method's main case) */
-  FEP3M_BOUNDARY_GROUNDED = 1   /* Phi = 0 on the faces of the box [0, L]^3: the
+  FEP3M_BOUNDARY_GROUNDED = 1,  /* Phi = 0 on the faces of the box [0, L]^3: the
                              mesh potential takes the boundary values -Phi_sr
                              of the charges of the near block (eq. bcadjust with
                              g = 0), the near block is cut at the faces and
@@ -120,10 +120,23 @@ enum {
                              from the adjoint with two more terms: the
                              boundary values depend on the moments (tables)
                              and on the positions (near pairs).  Charges
-                             within about half
-                             an element of a face are resolved poorly: their
-                             images lie within h of the face, where the mesh
-                             cannot follow them.                               */
+                             within about half an element of a face are
+                             resolved poorly: their images lie within h of the
+                             face, where the mesh cannot follow them.        */
+  FEP3M_BOUNDARY_INSULATED = 2  /* dPhi/dn = 0 on the faces of the box [0, L]^3:
+                             the mesh potential has the normal derivative
+                             -dPhi_sr/dn there, a surface load on the faces'
+                             nodes (tensor Gauss rule of 10 x 10 points per
+                             element face, the near sums of the face's element
+                             and its screen field differentiated exactly); the
+                             load is projected on the compatible subspace and
+                             the pure-Neumann system solved on every node with
+                             the constant mode dropped (int phi = 0): Phi is
+                             defined up to a constant, U of neutral charges is
+                             not.  Charges must be neutral and strictly inside
+                             the box; the same restrictions as GROUNDED; no
+                             forces (the force entry points return
+                             FEP3M_ERR_UNSUPPORTED)                          */
 };
 
 /* Evaluation of the near-screen field and of its transpose in the moment

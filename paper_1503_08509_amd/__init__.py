@@ -120,7 +120,7 @@ def default_options():
 
 
 SUPPORT_ONE, SUPPORT_27 = 0, 1
-BOUNDARY_PERIODIC, BOUNDARY_GROUNDED = 0, 1
+BOUNDARY_PERIODIC, BOUNDARY_GROUNDED, BOUNDARY_INSULATED = 0, 1, 2
 _SUPPORTS = {"one": SUPPORT_ONE, "27": SUPPORT_27, SUPPORT_ONE: SUPPORT_ONE, SUPPORT_27: SUPPORT_27}
 
 

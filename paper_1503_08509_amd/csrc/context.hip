@@ -146,9 +146,15 @@ struct fep3m_ctx {
   // the dense 1-D stiffness and mass of the box and the eigenbasis of the
   // interior pencil (K1_II V = M1_II V Lambda, V^T M1_II V = I)
   bool box = false;
+  bool insulated = false;   // boundary = FEP3M_BOUNDARY_INSULATED (else grounded)
   int Pb = 0;
   double *bxb = nullptr, *bxphi = nullptr, *bxy = nullptr, *bxt1 = nullptr, *bxt2 = nullptr, *bxt3 = nullptr;
   double *bxg = nullptr, *bxlam = nullptr;   // reverse pass: assembled deposit, adjoint potential
+  // insulating box: eigenbasis of the whole box pencil (its constant mode
+  // at index bx_i0), the mass row sums, the face quadrature and face values
+  double *bxVf = nullptr, *bxLamf = nullptr, *bxw1 = nullptr, *bxtF = nullptr;
+  int bx_i0 = 0;
+  BoxQuad bxquad{};
   double *bxK1 = nullptr, *bxM1 = nullptr, *bxV = nullptr, *bxLam = nullptr;
   BoxNodes bxnodes{};
   fep3m_options opt{};
@@ -363,7 +369,7 @@ struct fep3m_ctx {
     std::memcpy(&fl, host_scal + 4, sizeof(int));
     if (fl & 1) throw Status(FEP3M_ERR_NONFINITE, "non-finite position or charge");
     if (fl & 2) throw Status(FEP3M_ERR_ARG, "positions must lie inside the box (0, L)^3");
-    for (int bb = 0; bb < nb && !box; ++bb) {   // a grounded box takes any net charge
+    for (int bb = 0; bb < nb && !(box && !insulated); ++bb) {   // a grounded box takes any net charge
       const double sq = host_cs[kCsQ * nb + bb], sa = host_cs[kCsQabs * nb + bb];
       if (std::fabs(sq) > 1e-10 * sa)
         throw Status(FEP3M_ERR_NOT_NEUTRAL, "charges are not neutral: sum Q = " + std::to_string(sq) +
@@ -381,6 +387,7 @@ struct fep3m_ctx {
   void build_box();
   void box_apply(const double *v, double *y);
   void box_solve(const double *rhs, double *sol, int which);
+  void box_solve_neumann(double *f, double *sol);
   void forward_box(double *Phi, double *U, bool pair_forces);
   void reverse_box(double *F, double *dUdQ);
   void build_near_fft();
@@ -418,7 +425,8 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   na = nl * nl * nl;
   span = scr.span;
   generic = !(o.support == FEP3M_SUPPORT_ONE && q == 3);
-  box = o.boundary == FEP3M_BOUNDARY_GROUNDED;
+  box = o.boundary != FEP3M_BOUNDARY_PERIODIC;
+  insulated = o.boundary == FEP3M_BOUNDARY_INSULATED;
   if (box) {   // the box runs on the float64 table-sum kernels, the pair sum on rows of elements
     generic = true;
     plan = PairPlan{2, 2, 0};
@@ -934,6 +942,79 @@ void fep3m_ctx::build_box() {
   hip_check(hipMemcpy(bxLam, lamv.data(), size_t(Pi) * sizeof(double), hipMemcpyHostToDevice), "upload");
   const Vec nodes = gll_nodes(p);
   for (int a = 0; a <= p; ++a) bxnodes.x[a] = nodes[a];
+  if (!insulated) return;
+  // the whole pencil K1 V = M1 V Lambda (one zero eigenvalue: the constants)
+  Vec lf;
+  Mat Vf;
+  sym_gen_eig(K1, M1, lf, Vf);
+  bx_i0 = 0;
+  for (int i = 1; i < Pb; ++i)
+    if (std::fabs(lf[i]) < std::fabs(lf[bx_i0])) bx_i0 = i;
+  lf[bx_i0] = 0.0;
+  std::vector<double> vf(size_t(Pb) * Pb), w1(Pb);
+  for (int i = 0; i < Pb; ++i) {
+    double r = 0.0;
+    for (int j = 0; j < Pb; ++j) {
+      vf[i + size_t(j) * Pb] = Vf(i, j);
+      r += M1(i, j);
+    }
+    w1[i] = r;
+  }
+  bxVf = alloc<double>(vf.size(), "box pencil eigenvectors");
+  bxLamf = alloc<double>(size_t(Pb), "box pencil eigenvalues");
+  bxw1 = alloc<double>(size_t(Pb), "box mass row sums");
+  bxtF = alloc<double>(size_t(nb) * 6 * n * n * (p + 1) * (p + 1), "box face loads");
+  hip_check(hipMemcpy(bxVf, vf.data(), vf.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+  hip_check(hipMemcpy(bxLamf, lf.data(), size_t(Pb) * sizeof(double), hipMemcpyHostToDevice), "upload");
+  hip_check(hipMemcpy(bxw1, w1.data(), size_t(Pb) * sizeof(double), hipMemcpyHostToDevice), "upload");
+  Vec xq, wq;
+  gauss_legendre(kBoxNQ, xq, wq);
+  std::vector<double> l(p + 1), dl(p + 1);
+  for (int qi = 0; qi < kBoxNQ; ++qi) {
+    bxquad.xq[qi] = xq[qi];
+    bxquad.wq[qi] = wq[qi];
+    lagrange(nodes, xq[qi], l.data(), nullptr);
+    for (int k = 0; k <= p; ++k) bxquad.lq[qi][k] = l[k];
+  }
+  for (int sd = 0; sd < 2; ++sd) {
+    lagrange(nodes, sd ? 0.5 : -0.5, l.data(), dl.data());
+    for (int k = 0; k <= p; ++k) bxquad.dend[sd][k] = dl[k];
+  }
+}
+
+// Pure-Neumann solve of the insulating box on every node: f projected on
+// the compatible subspace (f -= (1^T f / V) M 1), then K^+ f by fast
+// diagonalisation of the whole box pencil with the constant mode dropped
+// (gauge int phi = 0).  The residual against f is checked as for the other
+// exact solves.
+void fep3m_ctx::box_solve_neumann(double *f, double *sol) {
+  int K = launch_box_resid(stream, Pb, nb, false, true, f, nullptr, partial);
+  launch_sum_partials(stream, K, partial + size_t(nb) * K, pcs.zq, nb);   // 1^T f per configuration
+  launch_box_sub_mass(stream, Pb, nb, 1.0 / (double(n) * n * n), bxw1, pcs.zq, f);
+  launch_axis_transform(stream, Pb, 0, nb, bxVf, true, f, bxt1);
+  launch_axis_transform(stream, Pb, 1, nb, bxVf, true, bxt1, bxt2);
+  launch_axis_transform(stream, Pb, 2, nb, bxVf, true, bxt2, bxt1);
+  launch_fdm_scale(stream, size_t(Pb) * Pb * Pb * nb, Pb, bx_i0, bxLamf, bxt1);
+  launch_axis_transform(stream, Pb, 2, nb, bxVf, false, bxt1, bxt2);
+  launch_axis_transform(stream, Pb, 1, nb, bxVf, false, bxt2, bxt1);
+  launch_axis_transform(stream, Pb, 0, nb, bxVf, false, bxt1, sol);
+  K = launch_box_resid(stream, Pb, nb, false, false, f, nullptr, partial);
+  launch_sum_partials(stream, K, partial, pcs.bn2, nb);
+  box_apply(sol, bxy);
+  K = launch_box_resid(stream, Pb, nb, false, false, f, bxy, partial);
+  launch_sum_partials(stream, K, partial, pcs.rr, nb);
+  launch_pcg_scalars(stream, nb, kPcgStart, 0.0, pcs);
+  launch_pcg_scalars(stream, nb, kPcgResid, 0.0, pcs);
+  store_rel(0);
+  check_launch("box solve");
+  hip_check(hipMemcpyAsync(host_cs, pcs.rel, nb * sizeof(double), hipMemcpyDeviceToHost, stream), "copy residuals");
+  sync("box residual");
+  double relmax = 0.0;
+  for (int bb = 0; bb < nb; ++bb) relmax = std::max(relmax, host_cs[bb]);
+  stats.mg_iterations = 0;
+  stats.mg_rel_residual = relmax;
+  if (!(relmax <= 1e-9))
+    throw Status(FEP3M_ERR_NOT_CONVERGED, "box solve left relative residual " + std::to_string(relmax));
 }
 
 // y = K v on the box (all nodes; the rows of the interior nodes are those of
@@ -962,7 +1043,7 @@ void fep3m_ctx::box_solve(const double *rhs, double *sol, int which) {
   const int Pi = Pb - 2;
   const size_t nv = size_t(Pb) * Pb * Pb * nb, ni = size_t(Pi) * Pi * Pi * nb;
   box_apply(sol, bxy);                                      // K phi_B
-  int K = launch_box_resid(stream, Pb, nb, rhs, bxy, partial);
+  int K = launch_box_resid(stream, Pb, nb, true, false, rhs, bxy, partial);
   launch_sum_partials(stream, K, partial, pcs.bn2, nb);     // |rhs_I - K_IB phi_B|^2
   launch_box_axpby(stream, nv, 1.0, rhs, -1.0, bxy);        // r = rhs - K phi_B
   launch_box_interior(stream, Pb, nb, true, bxy, bxt1);
@@ -975,7 +1056,7 @@ void fep3m_ctx::box_solve(const double *rhs, double *sol, int which) {
   launch_axis_transform(stream, Pi, 0, nb, bxV, false, bxt2, bxt3);
   launch_box_interior(stream, Pb, nb, false, bxt3, sol);
   box_apply(sol, bxy);
-  K = launch_box_resid(stream, Pb, nb, rhs, bxy, partial);
+  K = launch_box_resid(stream, Pb, nb, true, false, rhs, bxy, partial);
   launch_sum_partials(stream, K, partial, pcs.rr, nb);
   launch_pcg_scalars(stream, nb, kPcgStart, 0.0, pcs);
   launch_pcg_scalars(stream, nb, kPcgResid, 0.0, pcs);
@@ -1016,10 +1097,16 @@ void fep3m_ctx::forward_box(double *Phi, double *U, bool pair_forces) {
   stage_mark(FEP3M_PROF_NEAR, false);
   pair_pass(pair_forces);
   stage_mark(FEP3M_PROF_SOLVE, true);
-  launch_box_fill(stream, size_t(Pb) * Pb * Pb * nb, 0.0, bxphi);
-  if (launch_box_bvals(stream, nb, n, nsr, p, N, bxnodes, start, sg, sQ, Wel, bxphi) != 0)
-    throw Status(FEP3M_ERR_UNSUPPORTED, "boundary values variant");
-  box_solve(bxb, bxphi, 0);
+  if (insulated) {   // surface load of -dPhi_sr/dn, then the pure-Neumann solve
+    if (launch_box_flux(stream, nb, n, nsr, p, N, bxquad, start, sg, sQ, Wel, bxtF, bxb) != 0)
+      throw Status(FEP3M_ERR_UNSUPPORTED, "surface load variant");
+    box_solve_neumann(bxb, bxphi);
+  } else {           // boundary values -Phi_sr, then the interior solve
+    launch_box_fill(stream, size_t(Pb) * Pb * Pb * nb, 0.0, bxphi);
+    if (launch_box_bvals(stream, nb, n, nsr, p, N, bxnodes, start, sg, sQ, Wel, bxphi) != 0)
+      throw Status(FEP3M_ERR_UNSUPPORTED, "boundary values variant");
+    box_solve(bxb, bxphi, 0);
+  }
   stage_mark(FEP3M_PROF_SOLVE, false);
   if (launch_box_addphi(stream, nb, n, p, bxphi, Wel) != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "element field variant");
@@ -1475,6 +1562,8 @@ void fep3m_ctx::run_once(const double *x, const double *Qc, double *Phi, double 
 }
 
 void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ) {
+  if (insulated && (F || dUdQ))
+    throw Status(FEP3M_ERR_UNSUPPORTED, "forces in the insulating box are not implemented");
   fwd_valid = false;
   if (opt.use_graph && !prof.on && opt.solver == FEP3M_SOLVER_MG) evaluate_graph(x, Qc, Phi, U, F, dUdQ);
   else run_once(x, Qc, Phi, U, F, dUdQ);
@@ -1579,6 +1668,7 @@ void fep3m_ctx::evaluate_graph(const double *x, const double *Qc, double *Phi, d
 }
 
 void fep3m_ctx::backward(int64_t gen, double *F, double *dUdQ) {
+  if (insulated) throw Status(FEP3M_ERR_UNSUPPORTED, "forces in the insulating box are not implemented");
   if (!fwd_valid || gen != int64_t(generation))
     throw Status(FEP3M_ERR_ARG, "backward needs the state of forward call " + std::to_string(gen) +
                                     " but the context holds call " + std::to_string(generation) +
@@ -1673,7 +1763,8 @@ bool valid_options(const fep3m_options &o, std::string &why) {
   if (o.near_field < FEP3M_NEAR_AUTO || o.near_field > FEP3M_NEAR_FFT) { why = "unknown near_field"; return false; }
   if (o.support != FEP3M_SUPPORT_ONE && o.support != FEP3M_SUPPORT_27) { why = "unknown support"; return false; }
   if (o.pair_stream != 0 && o.pair_stream != 1) { why = "pair_stream must be 0 or 1"; return false; }
-  if (o.boundary != FEP3M_BOUNDARY_PERIODIC && o.boundary != FEP3M_BOUNDARY_GROUNDED) {
+  if (o.boundary != FEP3M_BOUNDARY_PERIODIC && o.boundary != FEP3M_BOUNDARY_GROUNDED &&
+      o.boundary != FEP3M_BOUNDARY_INSULATED) {
     why = "unknown boundary";
     return false;
   }
@@ -1740,11 +1831,11 @@ int create_common(double L, const std::vector<int64_t> &Ns, const int32_t dims[3
     }
   }
   if (o.near_field == FEP3M_NEAR_FFT && !fft_size_ok(dims[0])) return FEP3M_ERR_UNSUPPORTED;
-  if (o.boundary == FEP3M_BOUNDARY_GROUNDED &&
+  if (o.boundary != FEP3M_BOUNDARY_PERIODIC &&
       (o.support != FEP3M_SUPPORT_ONE || o.precision != FEP3M_PRECISION_FP64 || o.solver != FEP3M_SOLVER_FDM ||
        o.near_field == FEP3M_NEAR_FFT || o.use_graph || static_storage)) {
-    g_create_error = "the grounded box takes one-element screens in float64 with the exact mesh solve and the direct "
-                     "near field, eager (no graph, no static storage)";
+    g_create_error = "the grounded and insulating boxes take one-element screens in float64 with the exact mesh solve "
+                     "and the direct near field, eager (no graph, no static storage)";
     return FEP3M_ERR_UNSUPPORTED;
   }
   int dev = -1;

@@ -121,20 +121,23 @@ __global__ __launch_bounds__(256) void k_box_addphi(int n, int nb, const double 
 }
 
 // K blocks per configuration; partial[cfg K + kb] = sum (b - y)^2 and
-// partial[nb K + cfg K + kb] = sum b^2 over this block's interior nodes.
-__global__ __launch_bounds__(256) void k_box_resid(int P, int K, int nb, const double *__restrict__ ball,
-                                                   const double *__restrict__ yall, double *__restrict__ partial) {
+// partial[nb K + cfg K + kb] = sum b (plain = 1) or sum b^2 over this
+// block's nodes: the interior ones (off = 1) or all (off = 0).  A null y
+// reads as zero.
+__global__ __launch_bounds__(256) void k_box_resid(int P, int off, int plain, int K, int nb,
+                                                   const double *__restrict__ ball, const double *__restrict__ yall,
+                                                   double *__restrict__ partial) {
   __shared__ double red[2][4];
   const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
-  const int Pi = P - 2;
+  const int Pi = P - 2 * off;
   const size_t per = size_t(P) * P * P, peri = size_t(Pi) * Pi * Pi;
   double sr = 0.0, sb = 0.0;
   for (size_t l = size_t(kb) * blockDim.x + threadIdx.x; l < peri; l += size_t(K) * blockDim.x) {
     const int i = int(l % Pi), j = int((l / Pi) % Pi), k = int(l / (size_t(Pi) * Pi));
-    const size_t g = size_t(cfg) * per + (size_t(k + 1) * P + (j + 1)) * P + (i + 1);
-    const double bv = ball[g], rv = bv - yall[g];
+    const size_t g = size_t(cfg) * per + (size_t(k + off) * P + (j + off)) * P + (i + off);
+    const double bv = ball[g], rv = bv - (yall ? yall[g] : 0.0);
     sr += rv * rv;
-    sb += bv * bv;
+    sb += plain ? bv : bv * bv;
   }
   for (int o = 32; o > 0; o >>= 1) {
     sr += __shfl_down(sr, o, 64);
@@ -306,6 +309,130 @@ __global__ __launch_bounds__(256) void k_box_charge_bnd(int n, int nsr, int nb, 
   }
 }
 
+// Surface load of the insulating box, per boundary element face (one block
+// each): at the NQ x NQ Gauss points of the face, the outward normal
+// derivative of Phi_sr (near pairs of the face's element, cut at the
+// faces, minus the element's screen field Psi = -Wneg, differentiated from
+// its nodal values); then the face's (PO + 1)^2 nodal contributions
+// -sum_q w_q dPhi_sr/dn(x_q) u_m(x_q) into tF[cfg][face][kb][kc] (kb along
+// the higher tangential axis, kc along the lower).  Faces: f = a 2 n^2 +
+// s n^2 + j n + i (axis a, side s, tangential element indices i lower, j
+// higher).
+template <int PO>
+__global__ __launch_bounds__(128) void k_box_flux(int n, int nsr, int64_t N, BoxQuad qd, const int *__restrict__ start,
+                                                  const double *__restrict__ sg, const double *__restrict__ sQ,
+                                                  const double *__restrict__ Wneg, double *__restrict__ tF) {
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NQ = kBoxNQ;
+  __shared__ double fl[NQ * NQ];
+  const int nf = 6 * n * n;
+  const int cfg = blockIdx.x / nf, f = blockIdx.x % nf;
+  const int a = f / (2 * n * n), side = (f / (n * n)) % 2, i = f % n, j = (f / n) % n;
+  const int t0 = a == 0 ? 1 : 0, t1 = a == 2 ? 1 : 2;
+  int e[3];
+  e[a] = side ? n - 1 : 0;
+  e[t0] = i;
+  e[t1] = j;
+  const size_t M = size_t(n) * n * n;
+  const size_t cbase = size_t(cfg) * M;
+  const size_t E = cbase + e[0] + size_t(n) * (e[1] + size_t(n) * e[2]);
+  const double sgn = side ? 1.0 : -1.0;
+  const int q = threadIdx.x;
+  if (q < NQ * NQ) {
+    const int qi = q / NQ, qj = q % NQ;   // qi along t1, qj along t0
+    double X[3];
+    X[a] = side ? double(n) : 0.0;
+    X[t0] = e[t0] + 0.5 + qd.xq[qj];
+    X[t1] = e[t1] + 0.5 + qd.xq[qi];
+    double dn = 0.0;   // n . grad of sum_j Q_j / |x - y_j|
+    for (int dz = -nsr; dz <= nsr; ++dz) {
+      const int sz = e[2] + dz;
+      if (sz < 0 || sz >= n) continue;
+      for (int dy = -nsr; dy <= nsr; ++dy) {
+        const int sy = e[1] + dy;
+        if (sy < 0 || sy >= n) continue;
+        const int sx0 = max(e[0] - nsr, 0), sx1 = min(e[0] + nsr, n - 1);
+        const size_t row = cbase + size_t(n) * (sy + size_t(n) * sz);
+        for (int s = start[row + sx0]; s < start[row + sx1 + 1]; ++s) {
+          const double d0 = X[0] - sg[s], d1 = X[1] - sg[N + s], d2 = X[2] - sg[2 * N + s];
+          const double ri = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+          const double da = a == 0 ? d0 : (a == 1 ? d1 : d2);
+          dn -= sQ[s] * da * ri * ri * ri;
+        }
+      }
+    }
+    dn *= sgn;
+    // n . grad Psi = -n . grad Wneg from the element's nodal values
+    const double *w = Wneg + E * NM;
+    double dpsi = 0.0;
+    for (int m = 0; m < NM; ++m) {
+      const int k[3] = {m % Q1, (m / Q1) % Q1, m / (Q1 * Q1)};
+      dpsi -= w[m] * qd.dend[side][k[a]] * qd.lq[qi][k[t1]] * qd.lq[qj][k[t0]];
+    }
+    dpsi *= sgn;
+    fl[q] = (dn - dpsi) * qd.wq[qi] * qd.wq[qj];
+  }
+  __syncthreads();
+  if (q < Q1 * Q1) {
+    const int kb = q / Q1, kc = q % Q1;
+    double v = 0.0;
+    for (int qi = 0; qi < NQ; ++qi)
+      for (int qj = 0; qj < NQ; ++qj) v += fl[qi * NQ + qj] * qd.lq[qi][kb] * qd.lq[qj][kc];
+    tF[(size_t(blockIdx.x) * Q1 + kb) * Q1 + kc] = -v;
+  }
+}
+
+// f[node] += the contributions of the boundary faces holding the node (in
+// a fixed order: planes by axis and side, then faces by element).
+template <int PO>
+__global__ __launch_bounds__(256) void k_box_flux_add(int n, int nb, const double *__restrict__ tF,
+                                                      double *__restrict__ f) {
+  constexpr int Q1 = PO + 1;
+  const int P = PO * n + 1;
+  const size_t per = size_t(P) * P * P, nf = size_t(6) * n * n;
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < per * nb; t += size_t(gridDim.x) * blockDim.x) {
+    const int cfg = int(t / per);
+    const size_t l = t % per;
+    const int g[3] = {int(l % P), int((l / P) % P), int(l / (size_t(P) * P))};
+    if (g[0] != 0 && g[0] != P - 1 && g[1] != 0 && g[1] != P - 1 && g[2] != 0 && g[2] != P - 1) continue;
+    double v = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int side = 0; side < 2; ++side) {
+        if (g[a] != (side ? P - 1 : 0)) continue;
+        const int t0 = a == 0 ? 1 : 0, t1 = a == 2 ? 1 : 2;
+        int e0[2], k0[2], c0 = 0, e1[2], k1[2], c1 = 0;
+        {
+          const int ee = g[t0] / PO, kk = g[t0] - PO * ee;
+          if (kk == 0 && ee > 0) { e0[c0] = ee - 1; k0[c0] = PO; ++c0; }
+          if (ee < n) { e0[c0] = ee; k0[c0] = kk; ++c0; }
+        }
+        {
+          const int ee = g[t1] / PO, kk = g[t1] - PO * ee;
+          if (kk == 0 && ee > 0) { e1[c1] = ee - 1; k1[c1] = PO; ++c1; }
+          if (ee < n) { e1[c1] = ee; k1[c1] = kk; ++c1; }
+        }
+        for (int u1 = 0; u1 < c1; ++u1)
+          for (int u0 = 0; u0 < c0; ++u0) {
+            const size_t face = size_t(a) * 2 * n * n + size_t(side) * n * n + size_t(e1[u1]) * n + e0[u0];
+            v += tF[((size_t(cfg) * nf + face) * Q1 + k1[u1]) * Q1 + k0[u0]];
+          }
+      }
+    f[t] += v;
+  }
+}
+
+// f -= (s_cfg / V) w1 (x) w1 (x) w1 on every node (the compatibility
+// projection: s the sum of f, V = n^3, w1 the row sums of the 1-D mass).
+__global__ __launch_bounds__(256) void k_box_sub_mass(int P, int nb, double invV, const double *__restrict__ w1,
+                                                      const double *__restrict__ sums, double *__restrict__ f) {
+  const size_t per = size_t(P) * P * P;
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < per * nb; t += size_t(gridDim.x) * blockDim.x) {
+    const int cfg = int(t / per);
+    const size_t l = t % per;
+    const int i = int(l % P), j = int((l / P) % P), k = int(l / (size_t(P) * P));
+    f[t] -= sums[cfg] * invV * w1[i] * w1[j] * w1[k];
+  }
+}
+
 inline int grid_of(size_t count) {
   size_t g = (count + 255) / 256;
   if (g < 1) g = 1;
@@ -349,12 +476,14 @@ int launch_box_addphi(hipStream_t s, int nb, int n, int p, const double *phi, do
   }
 }
 
-int launch_box_resid(hipStream_t s, int P, int nb, const double *b, const double *y, double *partial) {
-  const size_t Pi = size_t(P) - 2;
+int launch_box_resid(hipStream_t s, int P, int nb, bool interior, bool plain, const double *b, const double *y,
+                     double *partial) {
+  const int off = interior ? 1 : 0;
+  const size_t Pi = size_t(P) - 2 * off;
   const size_t peri = Pi * Pi * Pi;
   int K = int(std::min<size_t>((peri + 255) / 256, size_t(1024) / size_t(nb > 0 ? nb : 1)));
   if (K < 1) K = 1;
-  hipLaunchKernelGGL(k_box_resid, dim3(nb * K), dim3(256), 0, s, P, K, nb, b, y, partial);
+  hipLaunchKernelGGL(k_box_resid, dim3(nb * K), dim3(256), 0, s, P, off, plain ? 1 : 0, K, nb, b, y, partial);
   return K;
 }
 
@@ -391,6 +520,32 @@ int launch_box_charge_bnd(hipStream_t s, int nb, int n, int nsr, int p, int64_t 
     case 6: hipLaunchKernelGGL(k_box_charge_bnd<6>, dim3(g), dim3(256), 0, s, n, nsr, nb, N, off, inv_h, nodes, sg, sQ, mu, perm, F, dUdQ); return 0;
     default: return -1;
   }
+}
+
+int launch_box_flux(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const BoxQuad &qd, const int *start,
+                    const double *sg, const double *sQ, const double *Wneg, double *tF, double *f) {
+  const int g = nb * 6 * n * n;
+  const size_t P = size_t(p) * n + 1;
+  switch (p) {
+    case 4:
+      hipLaunchKernelGGL(k_box_flux<4>, dim3(g), dim3(128), 0, s, n, nsr, N, qd, start, sg, sQ, Wneg, tF);
+      hipLaunchKernelGGL(k_box_flux_add<4>, dim3(grid_of(P * P * P * nb)), dim3(256), 0, s, n, nb, tF, f);
+      return 0;
+    case 5:
+      hipLaunchKernelGGL(k_box_flux<5>, dim3(g), dim3(128), 0, s, n, nsr, N, qd, start, sg, sQ, Wneg, tF);
+      hipLaunchKernelGGL(k_box_flux_add<5>, dim3(grid_of(P * P * P * nb)), dim3(256), 0, s, n, nb, tF, f);
+      return 0;
+    case 6:
+      hipLaunchKernelGGL(k_box_flux<6>, dim3(g), dim3(128), 0, s, n, nsr, N, qd, start, sg, sQ, Wneg, tF);
+      hipLaunchKernelGGL(k_box_flux_add<6>, dim3(grid_of(P * P * P * nb)), dim3(256), 0, s, n, nb, tF, f);
+      return 0;
+    default: return -1;
+  }
+}
+
+void launch_box_sub_mass(hipStream_t s, int P, int nb, double invV, const double *w1, const double *sums, double *f) {
+  const size_t per = size_t(P) * P * P;
+  hipLaunchKernelGGL(k_box_sub_mass, dim3(grid_of(per * nb)), dim3(256), 0, s, P, nb, invV, w1, sums, f);
 }
 
 }  // namespace fep3m

@@ -107,6 +107,15 @@ int launch_adj_g(hipStream_t s, int nb, int n, int nsr, int p, int span, int nl,
 struct BoxNodes {
   double x[8];   // GLL nodes of the element (p + 1 used) on [-1/2, 1/2]
 };
+// face quadrature of the insulating box: kBoxNQ Gauss-Legendre points per
+// direction on [-1/2, 1/2], the order-p Lagrange values there and the
+// basis derivatives at the element ends (-1/2, +1/2)
+constexpr int kBoxNQ = 10;
+struct BoxQuad {
+  double xq[kBoxNQ], wq[kBoxNQ];
+  double lq[kBoxNQ][8];
+  double dend[2][8];
+};
 // phi_B = -Phi_sr on the boundary nodes (only those are written); Wneg the
 // near field -Psi per element (launch_psi_g with box = 1 and no phi)
 int launch_box_bvals(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const BoxNodes &nodes, const int *start,
@@ -127,8 +136,15 @@ int launch_box_adj_bnd(hipStream_t s, int nb, int n, int nsr, int p, int nl, con
 int launch_box_charge_bnd(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const int *off, double inv_h,
                           const BoxNodes &nodes, const double *sg, const double *sQ, const double *mu, const int *perm,
                           double *F, double *dUdQ);
-// returns K: partial[0, nb K) holds the residual's squares, [nb K, 2 nb K) b's
-int launch_box_resid(hipStream_t s, int P, int nb, const double *b, const double *y, double *partial);
+// returns K: partial[0, nb K) holds the squares of b - y (y null: zero),
+// [nb K, 2 nb K) those of b (plain: b itself), over the interior nodes or all
+int launch_box_resid(hipStream_t s, int P, int nb, bool interior, bool plain, const double *b, const double *y,
+                     double *partial);
+// insulating box: f += surface load (tF: nb 6 n^2 (p + 1)^2 face values);
+// f -= (sums / V) w1 (x) w1 (x) w1 (compatibility projection)
+int launch_box_flux(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const BoxQuad &qd, const int *start,
+                    const double *sg, const double *sQ, const double *Wneg, double *tF, double *f);
+void launch_box_sub_mass(hipStream_t s, int P, int nb, double invV, const double *w1, const double *sums, double *f);
 
 // near field (k_near.hip)
 // T = double, or float (float32 tables, compensated slab sums, float32 W)

@@ -91,8 +91,8 @@ def test_screen_family_arguments():
 
 
 def test_grounded_box_arguments():
-    """The grounded box (Section 2.6): boundary 0 by default, unknown values
-    refused, and the combinations it does not take (27-element screens,
+    """The grounded and insulating boxes (Section 2.6): boundary 0 by
+    default, unknown values refused, and the combinations they do not take (27-element screens,
     mixed precision, the multigrid solver, the FFT near field, graphs,
     static storage) refused before any device work."""
     h = ctypes.c_void_p()
@@ -109,7 +109,9 @@ def test_grounded_box_arguments():
         f = L.fep3m_create_static if static else L.fep3m_create_ex
         return f(1.0, 100, d, q, ctypes.byref(o), ctypes.byref(h))
 
-    assert create(boundary=2) == fp.ERR_ARG and create(boundary=-1) == fp.ERR_ARG
+    assert create(boundary=3) == fp.ERR_ARG and create(boundary=-1) == fp.ERR_ARG
+    assert create(boundary=fp.BOUNDARY_INSULATED, solver=fp.SOLVER_MG) == fp.ERR_UNSUPPORTED
+    assert create(boundary=fp.BOUNDARY_INSULATED, precision=fp.PRECISION_MIXED) == fp.ERR_UNSUPPORTED
     assert create(solver=fp.SOLVER_MG) == fp.ERR_UNSUPPORTED
     assert create(2, support=fp.SUPPORT_27) == fp.ERR_UNSUPPORTED
     assert create(precision=fp.PRECISION_MIXED) == fp.ERR_UNSUPPORTED

@@ -137,3 +137,65 @@ def test_box_autograd_and_images(torch):
     e = _rel(fused["F"].cpu().numpy(), ref)
     print(f"box forces vs image sum: {e:.3e}")
     assert e < 1e-2
+
+
+def _neutral_layer(N, seed, n):
+    x, _ = _layer(N, seed, n)
+    Q = np.random.default_rng(seed + 1).permutation(np.repeat([1.0, -1.0], N // 2))
+    return x, Q
+
+
+def _ictx(N, n, q=3, n_sr=3):
+    return fp.Context(1.0, N, n, q=q, n_sr=n_sr, boundary=fp.BOUNDARY_INSULATED, solver=fp.SOLVER_FDM,
+                      table_box=2 * n_sr + 9)
+
+
+@pytest.mark.parametrize("N,n,q,n_sr,seed", [(300, 8, 3, 3, 51), (400, 9, 3, 2, 52), (200, 8, 4, 3, 53),
+                                             (200, 7, 2, 3, 54), (1000, 16, 3, 3, 55)])
+def test_insulated_box_matches_oracle(torch, N, n, q, n_sr, seed):
+    """The insulating box (surface load of -dPhi_sr/dn, pure-Neumann solve)
+    against the oracle's form: potentials (same gauge, int phi = 0) and
+    energy."""
+    from oracle import neumann as oneu
+    x, Q = _neutral_layer(N, seed, n)
+    ctx = _ictx(N, n, q, n_sr)
+    Phi, U = ctx.energy(torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda())
+    ref = oneu.run(x, Q, ofe.Params(L=1.0, n=n, q=q, n_sr=n_sr))
+    e = _rel(Phi.cpu().numpy(), ref["Phi"])
+    print(f"insulated box N={N} n={n} q={q} n_sr={n_sr}: GPU vs oracle Phi {e:.2e}")
+    assert e < 1e-10
+    assert abs(U.item() - ref["U"]) <= 1e-10 * abs(ref["U"])
+    assert ctx.stats()["mg_rel_residual"] < 1e-9
+
+
+def test_insulated_box_against_images_and_refusals(torch):
+    """The GPU method against the even-image sum (potential up to a
+    constant, energy), a batch of two boxes, and the refusal of forces and
+    of non-neutral charges."""
+    from oracle import neumann as oneu
+    N, n = 400, 8
+    x, Q = _neutral_layer(N, 56, n)
+    ctx = _ictx(N, n)
+    tx, tQ = torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda()
+    Phi, U = ctx.energy(tx, tQ)
+    Phi = Phi.cpu().numpy()
+    ref = oneu.image_ewald(x, Q)
+    c = np.mean(ref - Phi)
+    e = float(np.linalg.norm(Phi + c - ref) / np.linalg.norm(ref - ref.mean()))
+    eU = abs(U.item() - 0.5 * np.sum(Q * ref)) / abs(0.5 * np.sum(Q * ref))
+    print(f"insulated box N={N} n={n}: Phi vs image sum {e:.3e} (up to a constant), U {eU:.3e}")
+    assert e < 5e-3 and eU < 1e-2     # U of a neutral set: a sum with cancellation
+    with pytest.raises(fp.FEP3MError) as ei:
+        ctx.energy_forces(tx, tQ)
+    assert ei.value.status == fp.ERR_UNSUPPORTED
+    Qb = Q.copy()
+    Qb[0] += 0.5
+    with pytest.raises(fp.FEP3MError) as ei:
+        ctx.energy(tx, torch.from_numpy(Qb).cuda())
+    assert ei.value.status == fp.ERR_NOT_NEUTRAL
+    x2, Q2 = _neutral_layer(N, 57, n)
+    b = fp.Context(1.0, [N, N], n, boundary=fp.BOUNDARY_INSULATED, solver=fp.SOLVER_FDM)
+    Pb, Ub = b.energy(torch.from_numpy(np.concatenate([x, x2])).cuda(), torch.from_numpy(np.concatenate([Q, Q2])).cuda())
+    assert _rel(Pb.cpu().numpy()[:N], Phi) < 1e-12
+    single2 = _ictx(N, n).energy(torch.from_numpy(x2).cuda(), torch.from_numpy(Q2).cuda())[0].cpu().numpy()
+    assert _rel(Pb.cpu().numpy()[N:], single2) < 1e-12
