@@ -480,6 +480,8 @@ def variant_summary(r, ref=None):
          "N": int(sum(r["counts"])), "elements": f"{r['n']}^3",
          "graph_replays": r["stats"]["graph_replays"],
          "mg_iterations": r["stats"]["mg_iterations"], "adj_mg_iterations": r["stats"]["adj_iterations"],
+         "create_seconds": r["stats"]["create_seconds"],
+         "stages_ms_per_step": {s: round(t, 4) for s, t in r["stages_ms_per_step"].items()},
          "pair_variant": {"kind": {0: "element", 1: "queue", 2: "rows"}[r["stats"]["pair_variant"]],
                           "item_targets": r["stats"]["pair_item_targets"], "waves": r["stats"]["pair_waves"],
                           "tuned_ms": r["stats"]["tune_ms_best"], "element_ms": r["stats"]["tune_ms_default"]}}
@@ -621,6 +623,13 @@ def main():
             variants[f"{prec} {wl} exact mesh solver"] = variant_summary(
                 fd, r if wl == "uniform-1M-n64" else None)
             del fd
+        # the boxes of Section 2.6 (exact solve of the box pencil): grounded with forces, insulated
+        gb = measure("uniform-1M-n64", "fp64", 3, 1, solver=1, boundary=1)
+        variants["fp64 uniform-1M-n64 grounded box (energy + forces)"] = variant_summary(gb)
+        del gb
+        ib = measure("uniform-1M-n64", "fp64", 3, 1, forces=False, solver=1, boundary=2)
+        variants["fp64 uniform-1M-n64 insulated box (energy)"] = variant_summary(ib)
+        del ib
         out["variants"] = variants
         out["hbm_stages"] = hbm_stage_rooflines()
         if not args.no_sweep:

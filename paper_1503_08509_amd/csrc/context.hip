@@ -1127,8 +1127,9 @@ void fep3m_ctx::forward_box(double *Phi, double *U, bool pair_forces) {
 // lambda = K_II^-1 G_I (zero on the boundary) and mu = G - K lambda on the
 // boundary nodes, the gradients of U are the periodic ones (moment adjoint
 // from lambda and the near deposits, cut at the faces) plus the terms of
-// the boundary values: A[E][a] += sum_B mu_B T_a[e(B) - E][m_B] and, per
-// charge, the derivative of -Q_j / |x_B - x_j| weighted by mu_B.
+// the boundary values: A[E][a] += sum_B mu_B T_a[e(B) - E][m_B] (carried by
+// the near part of the adjoint with -mu_B in the deposit's slot of B) and,
+// per charge, the derivative of -Q_j / |x_B - x_j| weighted by mu_B.
 void fep3m_ctx::reverse_box(double *F, double *dUdQ) {
   stage_mark(FEP3M_PROF_ADJ_SOLVE, true);
   stage_mark(FEP3M_PROF_DEPOSIT, true);
@@ -1143,8 +1144,10 @@ void fep3m_ctx::reverse_box(double *F, double *dUdQ) {
   launch_box_axpby(stream, nv, 1.0, bxg, -1.0, bxy);   // mu = G - K lambda (read on the boundary nodes)
   stage_mark(FEP3M_PROF_ADJ_SOLVE, false);
   stage_mark(FEP3M_PROF_ADJ_NEAR, true);
-  if (launch_adj_g(stream, nb, n, nsr, p, span, nl, 1, gE, T, bxlam, gw, Aadj) != 0 ||
-      launch_box_adj_bnd(stream, nb, n, nsr, p, nl, T, bxy, Aadj) != 0)
+  // the boundary term of the moment adjoint as -mu in the deposit's
+  // canonical slots (the deposit is rebuilt by every reverse pass)
+  if (launch_box_mu_slots(stream, nb, n, p, bxy, gE) != 0 ||
+      launch_adj_g(stream, nb, n, nsr, p, span, nl, 1, gE, T, bxlam, gw, Aadj) != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
   stage_mark(FEP3M_PROF_ADJ_NEAR, false);
   stage_mark(FEP3M_PROF_FORCES, true);

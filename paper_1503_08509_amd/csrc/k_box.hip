@@ -232,35 +232,39 @@ __global__ __launch_bounds__(256) void k_box_assemble(int n, int nb, const doubl
   }
 }
 
-// Boundary part of the moment adjoint: A[E][a] += sum_B mu_B T[a][e(B) - E][m_B]
-// over the boundary nodes whose element has E in its near block; one thread
-// per element (elements farther than nsr from every face have none).
-template <int PO, int NL>
-__global__ __launch_bounds__(256) void k_box_adj_bnd(int n, int nsr, int nb, const double *__restrict__ T,
-                                                     const double *__restrict__ mu, double *__restrict__ A) {
-  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NA = NL * NL * NL;
-  const int P = PO * n + 1, S = 2 * nsr + 1, ND = S * S * S;
-  const size_t per = size_t(P) * P * P, M = size_t(n) * n * n;
-  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < M * nb; t += size_t(gridDim.x) * blockDim.x) {
-    const int cfg = int(t / M);
-    const size_t El = t % M;
-    const int Ec[3] = {int(El % n), int((El / n) % n), int(El / (size_t(n) * n))};
-    if (Ec[0] > nsr && Ec[1] > nsr && Ec[2] > nsr && n - 1 - Ec[0] > nsr && n - 1 - Ec[1] > nsr &&
-        n - 1 - Ec[2] > nsr)
-      continue;
-    const double *muc = mu + size_t(cfg) * per;
-    double acc[NA];
+// The boundary part of the moment adjoint, sum_B mu_B T[a][e(B) - E][m_B],
+// is the transposed near-field sum of mu placed at each boundary node's
+// canonical slot (e(B), m_B): so g[e(B)][m_B] -= mu_B turns the near part
+// of the adjoint, -sum_D <g_{E+D}, T_a[D]>, into the sum of both.  One
+// thread per boundary node, each node once (x faces whole, y faces without
+// the x edges, z faces without the x and y edges); the slots are distinct.
+template <int PO>
+__global__ __launch_bounds__(256) void k_box_mu_slots(int n, int nb, const double *__restrict__ mu,
+                                                      double *__restrict__ gE) {
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
+  const int P = PO * n + 1;
+  const size_t P2 = size_t(P) * P, per = P2 * P, M = size_t(n) * n * n;
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < size_t(nb) * 6 * P2;
+       t += size_t(gridDim.x) * blockDim.x) {
+    const int cfg = int(t / (6 * P2));
+    const size_t r = t % (6 * P2);
+    const int face = int(r / P2), a = int((r % P2) % P), b = int((r % P2) / P);
+    const int ax = face >> 1, side = face & 1;
+    int g[3];
+    g[ax] = side ? P - 1 : 0;
+    g[ax == 0 ? 1 : 0] = a;
+    g[ax == 2 ? 1 : 2] = b;
+    bool dup = false;
+    for (int c = 0; c < ax; ++c) dup = dup || g[c] == 0 || g[c] == P - 1;
+    if (dup) continue;
+    int e[3], k[3];
 #pragma unroll
-    for (int a = 0; a < NA; ++a) acc[a] = 0.0;
-    for_near_boundary<PO>(Ec, n, nsr, [&](const int (&g)[3], const int (&e)[3], const int (&k)[3]) {
-      const double mv = muc[(size_t(g[2]) * P + g[1]) * P + g[0]];
-      const int iD = (e[0] - Ec[0] + nsr) + S * ((e[1] - Ec[1] + nsr) + S * (e[2] - Ec[2] + nsr));
-      const int m = k[0] + Q1 * (k[1] + Q1 * k[2]);
-#pragma unroll
-      for (int a = 0; a < NA; ++a) acc[a] += mv * T[(size_t(a) * ND + iD) * NM + m];
-    });
-#pragma unroll
-    for (int a = 0; a < NA; ++a) A[t * NA + a] += acc[a];
+    for (int c = 0; c < 3; ++c) {
+      e[c] = node_elem(g[c], PO, n);
+      k[c] = g[c] - PO * e[c];
+    }
+    const size_t E = size_t(cfg) * M + e[0] + size_t(n) * (e[1] + size_t(n) * e[2]);
+    gE[E * NM + k[0] + Q1 * (k[1] + Q1 * k[2])] -= mu[size_t(cfg) * per + (size_t(g[2]) * P + g[1]) * P + g[0]];
   }
 }
 
@@ -498,18 +502,6 @@ int launch_box_assemble(hipStream_t s, int nb, int n, int p, const double *gE, d
   }
 }
 
-int launch_box_adj_bnd(hipStream_t s, int nb, int n, int nsr, int p, int nl, const double *T, const double *mu,
-                       double *A) {
-  const int g = grid_of(size_t(n) * n * n * nb);
-  const int key = 10 * p + nl;   // one-element screens: nl = q - 1, p = q + 2
-  switch (key) {
-    case 41: hipLaunchKernelGGL((k_box_adj_bnd<4, 1>), dim3(g), dim3(256), 0, s, n, nsr, nb, T, mu, A); return 0;
-    case 52: hipLaunchKernelGGL((k_box_adj_bnd<5, 2>), dim3(g), dim3(256), 0, s, n, nsr, nb, T, mu, A); return 0;
-    case 63: hipLaunchKernelGGL((k_box_adj_bnd<6, 3>), dim3(g), dim3(256), 0, s, n, nsr, nb, T, mu, A); return 0;
-    default: return -1;
-  }
-}
-
 int launch_box_charge_bnd(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const int *off, double inv_h,
                           const BoxNodes &nodes, const double *sg, const double *sQ, const double *mu, const int *perm,
                           double *F, double *dUdQ) {
@@ -546,6 +538,17 @@ int launch_box_flux(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, con
 void launch_box_sub_mass(hipStream_t s, int P, int nb, double invV, const double *w1, const double *sums, double *f) {
   const size_t per = size_t(P) * P * P;
   hipLaunchKernelGGL(k_box_sub_mass, dim3(grid_of(per * nb)), dim3(256), 0, s, P, nb, invV, w1, sums, f);
+}
+
+int launch_box_mu_slots(hipStream_t s, int nb, int n, int p, const double *mu, double *gE) {
+  const size_t P = size_t(p) * n + 1;
+  const int g = grid_of(size_t(nb) * 6 * P * P);
+  switch (p) {
+    case 4: hipLaunchKernelGGL(k_box_mu_slots<4>, dim3(g), dim3(256), 0, s, n, nb, mu, gE); return 0;
+    case 5: hipLaunchKernelGGL(k_box_mu_slots<5>, dim3(g), dim3(256), 0, s, n, nb, mu, gE); return 0;
+    case 6: hipLaunchKernelGGL(k_box_mu_slots<6>, dim3(g), dim3(256), 0, s, n, nb, mu, gE); return 0;
+    default: return -1;
+  }
 }
 
 }  // namespace fep3m

@@ -126,13 +126,13 @@ void launch_box_interior(hipStream_t s, int P, int nb, bool to_interior, const d
 void launch_box_axpby(hipStream_t s, size_t total, double a, const double *x, double c, double *y);
 void launch_box_fill(hipStream_t s, size_t total, double v, double *y);
 int launch_box_addphi(hipStream_t s, int nb, int n, int p, const double *phi, double *W);
-// reverse pass: box assembly of element-local values; the boundary parts of
-// the moment adjoint (A += sum_B mu_B T_a[e(B) - E][m_B]) and of the
-// per-charge gradients (F += Q bp / (2 h^2), dU/dQ -= bq / (2 h), added to
-// what launch_forces wrote); mu on the boundary nodes of a box vector
+// reverse pass: box assembly of element-local values; the boundary part of
+// the per-charge gradients (F += Q bp / (2 h^2), dU/dQ -= bq / (2 h), added
+// to what launch_forces wrote); mu on the boundary nodes of a box vector
 int launch_box_assemble(hipStream_t s, int nb, int n, int p, const double *gE, double *G);
-int launch_box_adj_bnd(hipStream_t s, int nb, int n, int nsr, int p, int nl, const double *T, const double *mu,
-                       double *A);
+// gE[e(B)][m_B] -= mu_B: the boundary part then rides in the near part of
+// the moment adjoint (launch_adj_g)
+int launch_box_mu_slots(hipStream_t s, int nb, int n, int p, const double *mu, double *gE);
 int launch_box_charge_bnd(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const int *off, double inv_h,
                           const BoxNodes &nodes, const double *sg, const double *sQ, const double *mu, const int *perm,
                           double *F, double *dUdQ);
