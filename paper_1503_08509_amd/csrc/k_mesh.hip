@@ -186,6 +186,17 @@ __device__ __forceinline__ void tile_coords(int b, int tiles, int &tx, int &ty, 
   }
 }
 
+// An entry of op.dk / op.dm at a run-time local index, as a select over the
+// compile-time indices: an indexed read of the by-value operator argument
+// would copy the whole operator to scratch memory.
+template <int PO, class T>
+__device__ __forceinline__ T pick(const T (&v)[kMaxP], int k) {
+  T r = v[0];
+#pragma unroll
+  for (int j = 1; j < PO; ++j) r = (k == j) ? v[j] : r;
+  return r;
+}
+
 template <int PO, int TE>
 struct ApplyShape {
   static constexpr int O = TE * PO;          // owned nodes per axis
@@ -287,6 +298,11 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
   __shared__ __align__(16) T lds[S::LDS];  // A, B; then C1, C2, Y; last the dot-product tree
   __shared__ T invd[PO * PO * PO];         // 1 / diag(K) by local node index
   __shared__ T Xo[O * O * O];              // x on the owned nodes (from the z-pass columns)
+  // p = 6: the band coefficients (2 x 49 values) in LDS; read through the
+  // by-value argument they make the compiler copy the whole operator to
+  // scratch memory
+  constexpr bool kLdsCoef = PO == 6;
+  __shared__ T coef[kLdsCoef ? 2 * (PO + 1) * (PO + 1) : 1];
   T *A = lds;
   T *B = lds + O * S::SA;
   T *C1 = lds;
@@ -318,8 +334,20 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
   const bool need_d = cheb && (c1 != T(0)) && (xprev != nullptr);   // null x_prev reads as zero
   for (int i = tid; i < PO * PO * PO; i += 256) {
     const int kx = i % PO, ky = (i / PO) % PO, kz = i / (PO * PO);
-    invd[i] = T(1) / (op.dk[kx] * op.dm[ky] * op.dm[kz] + op.dm[kx] * op.dk[ky] * op.dm[kz] +
-                      op.dm[kx] * op.dm[ky] * op.dk[kz]);
+    const T dkx = pick<PO>(op.dk, kx), dky = pick<PO>(op.dk, ky), dkz = pick<PO>(op.dk, kz);
+    const T dmx = pick<PO>(op.dm, kx), dmy = pick<PO>(op.dm, ky), dmz = pick<PO>(op.dm, kz);
+    invd[i] = T(1) / (dkx * dmy * dmz + dmx * dky * dmz + dmx * dmy * dkz);
+  }
+  const T *cme = op.me, *cke = op.ke;
+  if constexpr (kLdsCoef) {
+    constexpr int Q2 = (PO + 1) * (PO + 1);
+    if (tid < Q2) {
+      coef[tid] = op.me[tid];
+      coef[Q2 + tid] = op.ke[tid];
+    }
+    __syncthreads();
+    cme = coef;
+    cke = coef + Q2;
   }
   // Addresses: a block-uniform 64-bit tile base plus 32-bit offsets inside
   // the tile (at most O P^2 + O P + O < 2^31 for every supported n).
@@ -357,10 +385,10 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
       for (int oz = 0; oz < O; ++oz) Xo[(oz * O + (ly - PO)) * O + (lx - PO)] = v[oz + PO];
     }
     T a[O];
-    band_apply<PO, O>(op.me, v, a);
+    band_apply<PO, O>(cme, v, a);
 #pragma unroll
     for (int oz = 0; oz < O; ++oz) A[oz * S::SA + tid] = a[oz];
-    band_apply<PO, O>(op.ke, v, a);
+    band_apply<PO, O>(cke, v, a);
 #pragma unroll
     for (int oz = 0; oz < O; ++oz) B[oz * S::SA + tid] = a[oz];
   }
@@ -373,11 +401,11 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
     T v[I];
 #pragma unroll
     for (int y = 0; y < I; ++y) v[y] = A[oz2 * S::SA + y * I + lx2];
-    band_apply<PO, O>(op.me, v, c1v);
-    band_apply<PO, O>(op.ke, v, c2v);
+    band_apply<PO, O>(cme, v, c1v);
+    band_apply<PO, O>(cke, v, c2v);
 #pragma unroll
     for (int y = 0; y < I; ++y) v[y] = B[oz2 * S::SA + y * I + lx2];
-    band_apply_acc<PO, O>(op.me, v, c2v);
+    band_apply_acc<PO, O>(cme, v, c2v);
   }
   __syncthreads();
   if (act2) {
@@ -394,10 +422,10 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
     T v[I], yv[O];
 #pragma unroll
     for (int xx = 0; xx < I; ++xx) v[xx] = C1[oz * S::SC + oy * S::RS + xx];
-    band_apply<PO, O>(op.ke, v, yv);
+    band_apply<PO, O>(cke, v, yv);
 #pragma unroll
     for (int xx = 0; xx < I; ++xx) v[xx] = C2[oz * S::SC + oy * S::RS + xx];
-    band_apply_acc<PO, O>(op.me, v, yv);
+    band_apply_acc<PO, O>(cme, v, yv);
 #pragma unroll
     for (int ox = 0; ox < O; ++ox) Y[(oz * O + oy) * S::YS + ox] = yv[ox];
   }
