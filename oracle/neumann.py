@@ -189,3 +189,96 @@ def image_ewald(x, Q, L=1.0, targets=None, points=None, alpha=None, nimg=2, mmax
     N = len(Q)
     t = 8 * (np.arange(N) if targets is None else np.asarray(targets))
     return ewald.ewald(X, QQ, L=L2, alpha=alpha, nimg=nimg, mmax=mmax, targets=t)["Phi"]
+
+
+def energy_forces(x, Q, params: fep3m.Params):
+    """U, F and dU/dQ of the insulating-box method (every charge a target)
+    by the adjoint.  In element units, with G the assembled deposit and
+    lambda = K^+ G (the gauge-fixed pseudo-inverse; its mean vanishes, so
+    the compatibility projection drops out of the adjoint):
+
+      U_m = 1/2 <G, phi> - 1/2 sum_E <g_E, Psi_E>,  <G, phi> = <lambda, b + t>.
+
+    The surface load t depends on the moments (the faces' screen fields) and
+    on the positions (the faces' near sums).  With Lam_q = lambda at the
+    face's Gauss point x_q and w_q its weight:
+      A[E][a] += sum_F sum_m h_F[m] T_a[e(F) - E][m],
+                 h_F[m] = sum_q w_q Lam_q dn u_m(x_q)
+      dU_hat/dg_i += 1/2 Q_i sum_F sum_q w_q Lam_q (-n / r^3 + 3 (n.d) d / r^5)
+      dU_hat/dQ_i += 1/2 sum_F sum_q w_q Lam_q (n.d) / r^3,   d = x_q - g_i,
+    F over the boundary faces whose element's near block holds the charge
+    (or E); the rest as in the periodic method (near block cut at the
+    faces)."""
+    from . import adjoint
+
+    x = np.asarray(x, dtype=np.float64)
+    Q = np.asarray(Q, dtype=np.float64)
+    n, p, q, d, n_sr, h = params.n, params.p, params.q, params.d, params.n_sr, params.h
+    fw = run(x, Q, params, stages=True)
+    e, e_lin, u, C, phi = fw["e"], fw["e_lin"], fw["u"], fw["C"], fw["phi"]
+    T = tables.screen_tables(p, q, n_sr, params.B, params.table_bc, "one")
+    allE = np.arange(n**3)
+    W = dirichlet.element_phi(phi, p, n, allE) - dirichlet.near_field(C, T, n, n_sr, allE)
+    gE = adjoint.element_deposit(e_lin, u, Q, n, p)
+    G = dirichlet.assemble(gE, n, p)
+    lam = solve(project_compatible(G, p, n), p, n)
+    g1 = screens.load_weights(p, q, "one")
+    A_exp = screens.moment_exponents(d)
+    Gs = np.stack([np.einsum("k,j,i->kji", g1[az], g1[ay], g1[ax]).ravel() for (ax, ay, az) in A_exp])
+    A = 4.0 * math.pi * dirichlet.element_phi(lam, p, n, allE) @ Gs.T
+    offs = tables.offsets(n_sr)
+    ex, ey, ez = allE % n, (allE // n) % n, allE // (n * n)
+    for iD, (Dx, Dy, Dz) in enumerate(offs):
+        sx, sy, sz = ex + Dx, ey + Dy, ez + Dz
+        ok = (sx >= 0) & (sx < n) & (sy >= 0) & (sy < n) & (sz >= 0) & (sz < n)
+        src = sx[ok] + n * (sy[ok] + n * sz[ok])
+        A[ok] -= gE[src] @ T[:, iD, :].T
+    # face terms
+    nodes = fe1d.gll_nodes(p)
+    xq, wq = fe1d.gauss_legendre(NQ)
+    Lq = fe1d.lagrange(nodes, xq)
+    Dend = fe1d.lagrange_deriv(nodes, np.array([-0.5, 0.5]))
+    y = e + 0.5 + u
+    lamE = dirichlet.element_phi(lam, p, n, allE).reshape(n**3, p + 1, p + 1, p + 1)   # [z, y, x]
+    dU_face = np.zeros((len(Q), 3))
+    dQ_face = np.zeros(len(Q))
+    for (ec, a, s) in boundary_faces(n):
+        E = ec[0] + n * (ec[1] + n * ec[2])
+        tg = [c for c in range(3) if c != a]
+        sign = -1.0 if s == 0 else 1.0
+        perm = {0: (2, 0, 1), 1: (1, 0, 2), 2: (0, 1, 2)}[a]
+        la = np.transpose(lamE[E], perm)[0 if s == 0 else p]       # face nodes [k_t1, k_t0]
+        Lam = np.einsum("ib,jc,bc->ij", Lq, Lq, la)                # lambda at the face points
+        Lw = Lam * wq[:, None] * wq[None, :]
+        # h_F[m] = sum_q w_q Lam_q dn u_m(x_q), m over the element's nodes [k_a, k_t1, k_t0]
+        hF = sign * np.einsum("ij,ib,jc,k->kbc", Lw, Lq, Lq, Dend[s])
+        hm = np.transpose(hF, np.argsort(perm)).reshape(-1)        # back to [z, y, x], x fastest
+        for iD, (Dx, Dy, Dz) in enumerate(offs):
+            sx, sy, sz = ec[0] - Dx, ec[1] - Dy, ec[2] - Dz
+            if 0 <= sx < n and 0 <= sy < n and 0 <= sz < n:
+                A[sx + n * (sy + n * sz)] += T[:, iD, :] @ hm
+        # charges whose element lies in the face element's near block
+        near = np.nonzero(np.all(np.abs(e - np.array(ec)[None, :]) <= n_sr, axis=1))[0]
+        if len(near) == 0:
+            continue
+        X = np.zeros((NQ, NQ, 3))
+        X[:, :, a] = 0.0 if s == 0 else float(n)
+        X[:, :, tg[0]] = (ec[tg[0]] + 0.5 + xq)[None, :]
+        X[:, :, tg[1]] = (ec[tg[1]] + 0.5 + xq)[:, None]
+        dv = X[None, :, :, :] - y[near][:, None, None, :]        # (k, NQ, NQ, 3)
+        r = np.sqrt(np.sum(dv * dv, axis=3))
+        nd = sign * dv[..., a]
+        nvec = np.zeros(3)
+        nvec[a] = sign
+        gterm = -nvec[None, None, None, :] / r[..., None] ** 3 + 3.0 * (nd / r**5)[..., None] * dv
+        dU_face[near] += 0.5 * Q[near][:, None] * np.einsum("ij,kijc->kc", Lw, gterm)
+        dQ_face[near] += 0.5 * np.einsum("ij,kij->k", Lw, nd / r**3)
+    grad_v = adjoint.basis_gradients(p, u)
+    grad_a = adjoint.monomial_gradients(u, d)
+    mesh_grad = 0.5 * Q[:, None] * (np.einsum("nkm,nm->nk", grad_v, W[e_lin])
+                                    + np.einsum("nka,na->nk", grad_a, A[e_lin]))
+    dUp = dirichlet._pair_forces(e, e_lin, u, Q, n, n_sr)
+    dU = dUp + mesh_grad + dU_face
+    mono = np.prod(u[:, None, :] ** A_exp[None, :, :], axis=2)
+    dUdQ = (fw["Phi_p"] * h + 0.5 * fw["Phi_m"] * h + 0.5 * np.sum(A[e_lin] * mono, axis=1) + dQ_face) / h
+    return {"U": fw["U"], "Phi": fw["Phi"], "F": -dU / h**2, "dUdQ": dUdQ, "A": A, "lam": lam}

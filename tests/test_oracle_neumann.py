@@ -140,3 +140,49 @@ def test_non_neutral_charges_are_refused():
     Q[0] += 1.0
     with pytest.raises(ValueError):
         oneu.run(x, Q, fep3m.Params(L=1.0, n=8))
+
+
+def test_insulated_gradients_match_central_differences():
+    """Forces and dU/dQ of the insulating box by the adjoint (with the terms
+    of the surface load: its dependence on the moments and on the
+    positions) equal central differences of the oracle's energy.  dU/dQ is
+    checked along neutral directions (dQ_i = -dQ_j), the only ones the
+    neutrality constraint allows."""
+    N, n = 60, 7
+    x, Q = _layer(N, 23, n)
+    P = fep3m.Params(L=1.0, n=n)
+    out = oneu.energy_forces(x, Q, P)
+    h = P.h
+    frac = (x / h) % 1.0
+    ok = np.nonzero(np.all((frac > 0.1) & (frac < 0.9), axis=1))[0][:6]
+    assert len(ok) >= 4
+    dx = 1e-6
+    scale = np.max(np.abs(out["F"][ok]))
+    for i in ok:
+        for k in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += dx
+            xm[i, k] -= dx
+            fd = -(oneu.run(xp, Q, P)["U"] - oneu.run(xm, Q, P)["U"]) / (2 * dx)
+            assert abs(out["F"][i, k] - fd) < 1e-5 * scale, (i, k, out["F"][i, k], fd)
+    j = ok[-1]
+    for i in ok[:-1]:
+        Qp, Qm = Q.copy(), Q.copy()
+        Qp[i] += 1e-6
+        Qp[j] -= 1e-6
+        Qm[i] -= 1e-6
+        Qm[j] += 1e-6
+        fdq = (oneu.run(x, Qp, P)["U"] - oneu.run(x, Qm, P)["U"]) / 2e-6
+        assert abs((out["dUdQ"][i] - out["dUdQ"][j]) - fdq) < 1e-6 * np.max(np.abs(out["dUdQ"])), (i, fdq)
+
+
+def test_insulated_forces_against_images():
+    N, n = 200, 8
+    x, Q = _layer(N, 24, n)
+    out = oneu.energy_forces(x, Q, fep3m.Params(L=1.0, n=n))
+    X, QQ = oneu.image_charges(x, Q, 1.0)
+    from oracle import ewald
+    ref = ewald.ewald(X, QQ, L=2.0, alpha=2.5, nimg=2, mmax=8, forces=True, targets=8 * np.arange(N))["F"]
+    err = np.linalg.norm(out["F"] - ref) / np.linalg.norm(ref)
+    print(f"insulating box forces vs images: {err:.3e}")
+    assert err < 1e-2
