@@ -627,8 +627,8 @@ def main():
         gb = measure("uniform-1M-n64", "fp64", 3, 1, solver=1, boundary=1)
         variants["fp64 uniform-1M-n64 grounded box (energy + forces)"] = variant_summary(gb)
         del gb
-        ib = measure("uniform-1M-n64", "fp64", 3, 1, forces=False, solver=1, boundary=2)
-        variants["fp64 uniform-1M-n64 insulated box (energy)"] = variant_summary(ib)
+        ib = measure("uniform-1M-n64", "fp64", 3, 1, solver=1, boundary=2)
+        variants["fp64 uniform-1M-n64 insulated box (energy + forces)"] = variant_summary(ib)
         del ib
         out["variants"] = variants
         out["hbm_stages"] = hbm_stage_rooflines()

@@ -134,9 +134,9 @@ enum {
                              the constant mode dropped (int phi = 0): Phi is
                              defined up to a constant, U of neutral charges is
                              not.  Charges must be neutral and strictly inside
-                             the box; the same restrictions as GROUNDED; no
-                             forces (the force entry points return
-                             FEP3M_ERR_UNSUPPORTED)                          */
+                             the box; the same restrictions as GROUNDED.
+                             Forces and dU/dQ by the adjoint with the surface
+                             load's dependence on the moments and positions  */
 };
 
 /* Evaluation of the near-screen field and of its transpose in the moment

@@ -153,6 +153,7 @@ struct fep3m_ctx {
   // insulating box: eigenbasis of the whole box pencil (its constant mode
   // at index bx_i0), the mass row sums, the face quadrature and face values
   double *bxVf = nullptr, *bxLamf = nullptr, *bxw1 = nullptr, *bxtF = nullptr;
+  double *bxLw = nullptr, *bxhF = nullptr;   // reverse pass: face weights of lambda, face adjoint weights
   int bx_i0 = 0;
   BoxQuad bxquad{};
   double *bxK1 = nullptr, *bxM1 = nullptr, *bxV = nullptr, *bxLam = nullptr;
@@ -387,7 +388,7 @@ struct fep3m_ctx {
   void build_box();
   void box_apply(const double *v, double *y);
   void box_solve(const double *rhs, double *sol, int which);
-  void box_solve_neumann(double *f, double *sol);
+  void box_solve_neumann(double *f, double *sol, int which);
   void forward_box(double *Phi, double *U, bool pair_forces);
   void reverse_box(double *F, double *dUdQ);
   void build_near_fft();
@@ -964,6 +965,8 @@ void fep3m_ctx::build_box() {
   bxLamf = alloc<double>(size_t(Pb), "box pencil eigenvalues");
   bxw1 = alloc<double>(size_t(Pb), "box mass row sums");
   bxtF = alloc<double>(size_t(nb) * 6 * n * n * (p + 1) * (p + 1), "box face loads");
+  bxLw = alloc<double>(size_t(nb) * 6 * n * n * kBoxNQ * kBoxNQ, "box face adjoint weights");
+  bxhF = alloc<double>(size_t(nb) * 6 * n * n * (p + 1) * (p + 1) * (p + 1), "box face adjoint moments");
   hip_check(hipMemcpy(bxVf, vf.data(), vf.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
   hip_check(hipMemcpy(bxLamf, lf.data(), size_t(Pb) * sizeof(double), hipMemcpyHostToDevice), "upload");
   hip_check(hipMemcpy(bxw1, w1.data(), size_t(Pb) * sizeof(double), hipMemcpyHostToDevice), "upload");
@@ -987,7 +990,7 @@ void fep3m_ctx::build_box() {
 // diagonalisation of the whole box pencil with the constant mode dropped
 // (gauge int phi = 0).  The residual against f is checked as for the other
 // exact solves.
-void fep3m_ctx::box_solve_neumann(double *f, double *sol) {
+void fep3m_ctx::box_solve_neumann(double *f, double *sol, int which) {
   int K = launch_box_resid(stream, Pb, nb, false, true, f, nullptr, partial);
   launch_sum_partials(stream, K, partial + size_t(nb) * K, pcs.zq, nb);   // 1^T f per configuration
   launch_box_sub_mass(stream, Pb, nb, 1.0 / (double(n) * n * n), bxw1, pcs.zq, f);
@@ -1005,14 +1008,18 @@ void fep3m_ctx::box_solve_neumann(double *f, double *sol) {
   launch_sum_partials(stream, K, partial, pcs.rr, nb);
   launch_pcg_scalars(stream, nb, kPcgStart, 0.0, pcs);
   launch_pcg_scalars(stream, nb, kPcgResid, 0.0, pcs);
-  store_rel(0);
+  store_rel(which);
   check_launch("box solve");
   hip_check(hipMemcpyAsync(host_cs, pcs.rel, nb * sizeof(double), hipMemcpyDeviceToHost, stream), "copy residuals");
   sync("box residual");
   double relmax = 0.0;
   for (int bb = 0; bb < nb; ++bb) relmax = std::max(relmax, host_cs[bb]);
-  stats.mg_iterations = 0;
-  stats.mg_rel_residual = relmax;
+  if (which == 0) {
+    stats.mg_iterations = 0;
+    stats.mg_rel_residual = relmax;
+  } else {
+    stats.adj_iterations = 0;
+  }
   if (!(relmax <= 1e-9))
     throw Status(FEP3M_ERR_NOT_CONVERGED, "box solve left relative residual " + std::to_string(relmax));
 }
@@ -1100,7 +1107,7 @@ void fep3m_ctx::forward_box(double *Phi, double *U, bool pair_forces) {
   if (insulated) {   // surface load of -dPhi_sr/dn, then the pure-Neumann solve
     if (launch_box_flux(stream, nb, n, nsr, p, N, bxquad, start, sg, sQ, Wel, bxtF, bxb) != 0)
       throw Status(FEP3M_ERR_UNSUPPORTED, "surface load variant");
-    box_solve_neumann(bxb, bxphi);
+    box_solve_neumann(bxb, bxphi, 0);
   } else {           // boundary values -Phi_sr, then the interior solve
     launch_box_fill(stream, size_t(Pb) * Pb * Pb * nb, 0.0, bxphi);
     if (launch_box_bvals(stream, nb, n, nsr, p, N, bxnodes, start, sg, sQ, Wel, bxphi) != 0)
@@ -1137,6 +1144,26 @@ void fep3m_ctx::reverse_box(double *F, double *dUdQ) {
     throw Status(FEP3M_ERR_UNSUPPORTED, "deposit variant");
   if (launch_box_assemble(stream, nb, n, p, gE, bxg) != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "assembly variant");
   stage_mark(FEP3M_PROF_DEPOSIT, false);
+  if (insulated) {
+    // lambda = K^+ G (mean zero, so the projection drops out of the adjoint);
+    // the surface load's table term rides in the near part of the moment
+    // adjoint (-hF in the boundary elements' deposit), its pair term per charge
+    box_solve_neumann(bxg, bxlam, 1);
+    stage_mark(FEP3M_PROF_ADJ_SOLVE, false);
+    stage_mark(FEP3M_PROF_ADJ_NEAR, true);
+    if (launch_box_flux_adj(stream, nb, n, p, bxquad, bxlam, bxLw, bxhF) != 0 ||
+        launch_box_h_slots(stream, nb, n, p, bxhF, gE) != 0 ||
+        launch_adj_g(stream, nb, n, nsr, p, span, nl, 1, gE, T, bxlam, gw, Aadj) != 0)
+      throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
+    stage_mark(FEP3M_PROF_ADJ_NEAR, false);
+    stage_mark(FEP3M_PROF_FORCES, true);
+    if (launch_forces<double>(stream, nb, off_d, p, n, nl, N, 1.0 / h, bas, sg, sQ, Wel, Aadj, fpair, phip_s, phim_s,
+                              perm, F, dUdQ) != 0 ||
+        launch_box_flux_charge(stream, nb, n, nsr, p, N, off_d, 1.0 / h, bxquad, sg, sQ, bxLw, perm, F, dUdQ) != 0)
+      throw Status(FEP3M_ERR_UNSUPPORTED, "forces variant");
+    stage_mark(FEP3M_PROF_FORCES, false);
+    return;
+  }
   const size_t nv = size_t(Pb) * Pb * Pb * nb;
   launch_box_fill(stream, nv, 0.0, bxlam);
   box_solve(bxg, bxlam, 1);
@@ -1565,8 +1592,6 @@ void fep3m_ctx::run_once(const double *x, const double *Qc, double *Phi, double 
 }
 
 void fep3m_ctx::evaluate(const double *x, const double *Qc, double *Phi, double *U, double *F, double *dUdQ) {
-  if (insulated && (F || dUdQ))
-    throw Status(FEP3M_ERR_UNSUPPORTED, "forces in the insulating box are not implemented");
   fwd_valid = false;
   if (opt.use_graph && !prof.on && opt.solver == FEP3M_SOLVER_MG) evaluate_graph(x, Qc, Phi, U, F, dUdQ);
   else run_once(x, Qc, Phi, U, F, dUdQ);
@@ -1671,7 +1696,6 @@ void fep3m_ctx::evaluate_graph(const double *x, const double *Qc, double *Phi, d
 }
 
 void fep3m_ctx::backward(int64_t gen, double *F, double *dUdQ) {
-  if (insulated) throw Status(FEP3M_ERR_UNSUPPORTED, "forces in the insulating box are not implemented");
   if (!fwd_valid || gen != int64_t(generation))
     throw Status(FEP3M_ERR_ARG, "backward needs the state of forward call " + std::to_string(gen) +
                                     " but the context holds call " + std::to_string(generation) +

@@ -385,6 +385,145 @@ __global__ __launch_bounds__(128) void k_box_flux(int n, int nsr, int64_t N, Box
   }
 }
 
+// Reverse pass of the insulating box, per boundary face (one block each):
+// Lw[q] = w_q lambda(x_q) at the face's Gauss points (lambda interpolated
+// from the face's nodes) and hF[m] = sum_q Lw[q] dn u_m(x_q) over the
+// element's nodes m (x fastest), the face's weight on the moment adjoint.
+template <int PO>
+__global__ __launch_bounds__(128) void k_box_flux_adj(int n, BoxQuad qd, const double *__restrict__ lam,
+                                                      double *__restrict__ Lw, double *__restrict__ hF) {
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NQ = kBoxNQ;
+  __shared__ double lw[NQ * NQ];
+  const int P = PO * n + 1;
+  const int nf = 6 * n * n;
+  const int cfg = blockIdx.x / nf, f = blockIdx.x % nf;
+  const int a = f / (2 * n * n), side = (f / (n * n)) % 2, i = f % n, j = (f / n) % n;
+  const int t0 = a == 0 ? 1 : 0, t1 = a == 2 ? 1 : 2;
+  const double *lc = lam + size_t(cfg) * P * P * P;
+  const double sgn = side ? 1.0 : -1.0;
+  const int q = threadIdx.x;
+  if (q < NQ * NQ) {
+    const int qi = q / NQ, qj = q % NQ;
+    int g[3];
+    g[a] = side ? P - 1 : 0;
+    double v = 0.0;
+    for (int kb = 0; kb < Q1; ++kb) {
+      g[t1] = PO * j + kb;
+      double r = 0.0;
+      for (int kc = 0; kc < Q1; ++kc) {
+        g[t0] = PO * i + kc;
+        r += lc[(size_t(g[2]) * P + g[1]) * P + g[0]] * qd.lq[qj][kc];
+      }
+      v += r * qd.lq[qi][kb];
+    }
+    v *= qd.wq[qi] * qd.wq[qj];
+    lw[q] = v;
+    Lw[size_t(blockIdx.x) * NQ * NQ + q] = v;
+  }
+  __syncthreads();
+  for (int m = threadIdx.x; m < NM; m += blockDim.x) {
+    const int k[3] = {m % Q1, (m / Q1) % Q1, m / (Q1 * Q1)};
+    double v = 0.0;
+    for (int qi = 0; qi < NQ; ++qi) {
+      double r = 0.0;
+      for (int qj = 0; qj < NQ; ++qj) r += lw[qi * NQ + qj] * qd.lq[qj][k[t0]];
+      v += r * qd.lq[qi][k[t1]];
+    }
+    hF[size_t(blockIdx.x) * NM + m] = sgn * qd.dend[side][k[a]] * v;
+  }
+}
+
+// gE[E][m] -= sum of hF over E's boundary faces (axes in order), so that the
+// near part of the moment adjoint carries the surface load's table term.
+template <int PO>
+__global__ __launch_bounds__(256) void k_box_h_slots(int n, int nb, const double *__restrict__ hF,
+                                                     double *__restrict__ gE) {
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
+  const size_t M = size_t(n) * n * n, nf = size_t(6) * n * n;
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < size_t(nb) * M * NM;
+       t += size_t(gridDim.x) * blockDim.x) {
+    const size_t E = t / NM;
+    const int m = int(t % NM), cfg = int(E / M);
+    const size_t El = E % M;
+    const int e[3] = {int(El % n), int((El / n) % n), int(El / (size_t(n) * n))};
+    double v = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const int t0 = a == 0 ? 1 : 0, t1 = a == 2 ? 1 : 2;
+      for (int side = 0; side < 2; ++side) {
+        if (e[a] != (side ? n - 1 : 0)) continue;
+        const size_t face = size_t(a) * 2 * n * n + size_t(side) * n * n + size_t(e[t1]) * n + e[t0];
+        v += hF[(size_t(cfg) * nf + face) * NM + m];
+      }
+    }
+    if (v != 0.0) gE[t] -= v;
+  }
+}
+
+// Per-charge face terms of the insulating box's gradients: for a sorted
+// charge whose element lies in the near block of a boundary face's element,
+// sum over the face's Gauss points of Lw (-n / r^3 + 3 (n.d) d / r^5) and of
+// Lw (n.d) / r^3 (d = x_q - x_s); F -= Q s2 / 2 times the first, dU/dQ +=
+// inv_h / 2 times the second (physical units, caller order).
+template <int PO>
+__global__ __launch_bounds__(256) void k_box_flux_charge(int n, int nsr, int nb, int64_t N,
+                                                         const int *__restrict__ off, double inv_h, BoxQuad qd,
+                                                         const double *__restrict__ sg, const double *__restrict__ sQ,
+                                                         const double *__restrict__ Lw, const int *__restrict__ perm,
+                                                         double *__restrict__ F, double *__restrict__ dUdQ) {
+  constexpr int NQ = kBoxNQ;
+  const size_t nf = size_t(6) * n * n;
+  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < N; s += int64_t(gridDim.x) * blockDim.x) {
+    const double xs[3] = {sg[s], sg[N + s], sg[2 * N + s]};
+    int Ec[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Ec[c] = min(int(floor(xs[c])), n - 1);
+    if (Ec[0] > nsr && Ec[1] > nsr && Ec[2] > nsr && n - 1 - Ec[0] > nsr && n - 1 - Ec[1] > nsr &&
+        n - 1 - Ec[2] > nsr)
+      continue;
+    const int cfg = cfg_of(off, nb, s);
+    double gx = 0.0, gy = 0.0, gz = 0.0, dq = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const int t0 = a == 0 ? 1 : 0, t1 = a == 2 ? 1 : 2;
+      for (int side = 0; side < 2; ++side) {
+        if (side == 0 ? Ec[a] > nsr : (n - 1 - Ec[a]) > nsr) continue;
+        const double sgn = side ? 1.0 : -1.0;
+        const double xa = side ? double(n) : 0.0;
+        const int i0 = max(Ec[t0] - nsr, 0), i1 = min(Ec[t0] + nsr, n - 1);
+        const int j0 = max(Ec[t1] - nsr, 0), j1 = min(Ec[t1] + nsr, n - 1);
+        for (int j = j0; j <= j1; ++j)
+          for (int i = i0; i <= i1; ++i) {
+            const size_t face = size_t(a) * 2 * n * n + size_t(side) * n * n + size_t(j) * n + i;
+            const double *lw = Lw + (size_t(cfg) * nf + face) * NQ * NQ;
+            for (int qi = 0; qi < NQ; ++qi)
+              for (int qj = 0; qj < NQ; ++qj) {
+                double d[3];
+                d[a] = xa - xs[a];
+                d[t0] = i + 0.5 + qd.xq[qj] - xs[t0];
+                d[t1] = j + 0.5 + qd.xq[qi] - xs[t1];
+                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                const double ri = 1.0 / sqrt(r2), ri3 = ri * ri * ri;
+                const double w = lw[qi * NQ + qj];
+                const double nd = sgn * d[a];
+                const double c5 = 3.0 * nd * ri3 * ri * ri;
+                gx += w * (c5 * d[0] - (a == 0 ? sgn : 0.0) * ri3);
+                gy += w * (c5 * d[1] - (a == 1 ? sgn : 0.0) * ri3);
+                gz += w * (c5 * d[2] - (a == 2 ? sgn : 0.0) * ri3);
+                dq += w * nd * ri3;
+              }
+          }
+      }
+    }
+    const int idx = perm[s];
+    const double qv = sQ[s], c = 0.5 * inv_h * inv_h * qv;
+    if (F) {
+      F[3 * size_t(idx) + 0] -= c * gx;
+      F[3 * size_t(idx) + 1] -= c * gy;
+      F[3 * size_t(idx) + 2] -= c * gz;
+    }
+    if (dUdQ) dUdQ[idx] += 0.5 * inv_h * dq;
+  }
+}
+
 // f[node] += the contributions of the boundary faces holding the node (in
 // a fixed order: planes by axis and side, then faces by element).
 template <int PO>
@@ -547,6 +686,39 @@ int launch_box_mu_slots(hipStream_t s, int nb, int n, int p, const double *mu, d
     case 4: hipLaunchKernelGGL(k_box_mu_slots<4>, dim3(g), dim3(256), 0, s, n, nb, mu, gE); return 0;
     case 5: hipLaunchKernelGGL(k_box_mu_slots<5>, dim3(g), dim3(256), 0, s, n, nb, mu, gE); return 0;
     case 6: hipLaunchKernelGGL(k_box_mu_slots<6>, dim3(g), dim3(256), 0, s, n, nb, mu, gE); return 0;
+    default: return -1;
+  }
+}
+
+int launch_box_flux_adj(hipStream_t s, int nb, int n, int p, const BoxQuad &qd, const double *lam, double *Lw,
+                        double *hF) {
+  const int g = nb * 6 * n * n;
+  switch (p) {
+    case 4: hipLaunchKernelGGL(k_box_flux_adj<4>, dim3(g), dim3(128), 0, s, n, qd, lam, Lw, hF); return 0;
+    case 5: hipLaunchKernelGGL(k_box_flux_adj<5>, dim3(g), dim3(128), 0, s, n, qd, lam, Lw, hF); return 0;
+    case 6: hipLaunchKernelGGL(k_box_flux_adj<6>, dim3(g), dim3(128), 0, s, n, qd, lam, Lw, hF); return 0;
+    default: return -1;
+  }
+}
+
+int launch_box_h_slots(hipStream_t s, int nb, int n, int p, const double *hF, double *gE) {
+  const int g = grid_of(size_t(nb) * n * n * n * (p + 1) * (p + 1) * (p + 1));
+  switch (p) {
+    case 4: hipLaunchKernelGGL(k_box_h_slots<4>, dim3(g), dim3(256), 0, s, n, nb, hF, gE); return 0;
+    case 5: hipLaunchKernelGGL(k_box_h_slots<5>, dim3(g), dim3(256), 0, s, n, nb, hF, gE); return 0;
+    case 6: hipLaunchKernelGGL(k_box_h_slots<6>, dim3(g), dim3(256), 0, s, n, nb, hF, gE); return 0;
+    default: return -1;
+  }
+}
+
+int launch_box_flux_charge(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const int *off, double inv_h,
+                           const BoxQuad &qd, const double *sg, const double *sQ, const double *Lw, const int *perm,
+                           double *F, double *dUdQ) {
+  const int g = grid_of(size_t(N));
+  switch (p) {
+    case 4: hipLaunchKernelGGL(k_box_flux_charge<4>, dim3(g), dim3(256), 0, s, n, nsr, nb, N, off, inv_h, qd, sg, sQ, Lw, perm, F, dUdQ); return 0;
+    case 5: hipLaunchKernelGGL(k_box_flux_charge<5>, dim3(g), dim3(256), 0, s, n, nsr, nb, N, off, inv_h, qd, sg, sQ, Lw, perm, F, dUdQ); return 0;
+    case 6: hipLaunchKernelGGL(k_box_flux_charge<6>, dim3(g), dim3(256), 0, s, n, nsr, nb, N, off, inv_h, qd, sg, sQ, Lw, perm, F, dUdQ); return 0;
     default: return -1;
   }
 }

@@ -145,6 +145,15 @@ int launch_box_resid(hipStream_t s, int P, int nb, bool interior, bool plain, co
 int launch_box_flux(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const BoxQuad &qd, const int *start,
                     const double *sg, const double *sQ, const double *Wneg, double *tF, double *f);
 void launch_box_sub_mass(hipStream_t s, int P, int nb, double invV, const double *w1, const double *sums, double *f);
+// insulating box, reverse pass: per face Lw (nb 6 n^2 kBoxNQ^2) and hF
+// (nb 6 n^2 (p + 1)^3); gE -= the faces' hF per element; the per-charge
+// face terms added to F and dU/dQ (after launch_forces)
+int launch_box_flux_adj(hipStream_t s, int nb, int n, int p, const BoxQuad &qd, const double *lam, double *Lw,
+                        double *hF);
+int launch_box_h_slots(hipStream_t s, int nb, int n, int p, const double *hF, double *gE);
+int launch_box_flux_charge(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const int *off, double inv_h,
+                           const BoxQuad &qd, const double *sg, const double *sQ, const double *Lw, const int *perm,
+                           double *F, double *dUdQ);
 
 // near field (k_near.hip)
 // T = double, or float (float32 tables, compensated slab sums, float32 W)
