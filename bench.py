@@ -49,6 +49,8 @@ def parse():
                     help="near-screen field and its transpose: FFTs where the mesh allows (auto), table sums, or FFTs")
     ap.add_argument("--solver", choices=["mg", "exact"], default="mg",
                     help="mesh solve: multigrid PCG (the method's default) or the exact periodic solve")
+    ap.add_argument("--boundary", choices=["periodic", "grounded", "insulated"], default="periodic",
+                    help="the periodic cube, or the boxes of Section 2.6 (with --solver exact)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mixed-precision, clustered and batched measurements reported beside the FP64 line")
@@ -522,8 +524,13 @@ def main():
         return
 
     forces = args.outputs == "forces"
+    bc = {"periodic": 0, "grounded": 1, "insulated": 2}[args.boundary]
+    if bc and args.solver != "exact":
+        print(json.dumps({"error": "the boxes of Section 2.6 need --solver exact"}))
+        sys.exit(2)
     r = measure(args.workload, args.precision, args.steps, args.warmup, forces,
-                solver={"mg": 0, "exact": 1}[args.solver], near_field={"auto": 0, "direct": 1, "fft": 2}[args.near])
+                solver={"mg": 0, "exact": 1}[args.solver], near_field={"auto": 0, "direct": 1, "fft": 2}[args.near],
+                boundary=bc)
     mixed = args.precision == "mixed"
     kernels = r["kernels"]
     practical = stream_copy_gbs() if not args.no_variants else None   # kept out of profiled runs
@@ -568,6 +575,7 @@ def main():
                    "elements": f"{r['n']}^3", "L": r["L"], "screen": "one-element q=3", "mesh_order": 5,
                    "near_block": "7^3", "outputs": "U, F" if forces else "Phi, U", "precision": args.precision,
                    "mg_rtol": r["mg_rtol"], "solver": "multigrid PCG" if args.solver == "mg" else "exact",
+                   "boundary": args.boundary,
                    "near_pairs_per_step": r["pairs"]},
         "roofline": roof,
         "kernels": kernels,
