@@ -588,7 +588,7 @@ def main():
         "pair_variant": variant_summary(r)["pair_variant"],
         "U": [float(u) for u in np.atleast_1d(r["out"]["U"])][:4],
     }
-    if not args.no_variants and forces and args.workload == "uniform-1M-n64" and not mixed:
+    if not args.no_variants and forces and args.workload == "uniform-1M-n64" and not mixed and not bc:
         variants = {}
         m = measure("uniform-1M-n64", "mixed", 3, 1)
         variants["mixed uniform-1M-n64"] = variant_summary(m, r)
@@ -642,7 +642,7 @@ def main():
         out["hbm_stages"] = hbm_stage_rooflines()
         if not args.no_sweep:
             out["screen_sweep"] = screen_sweep()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.boundary == "periodic":
         out["method_error_vs_ewald"] = method_error_vs_ewald()
         if args.workload in ("uniform-1M-n64", "clustered-1M-n64") and forces and not mixed:
             out["method_error_vs_ewald_full_size"] = ewald_error_full_size(r)
