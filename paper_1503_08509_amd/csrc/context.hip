@@ -156,7 +156,8 @@ struct fep3m_ctx {
   double *bxLw = nullptr, *bxhF = nullptr;   // reverse pass: face weights of lambda, face adjoint weights
   int bx_i0 = 0;
   BoxQuad bxquad{};
-  double *bxK1 = nullptr, *bxM1 = nullptr, *bxV = nullptr, *bxLam = nullptr;
+  double *bxV = nullptr, *bxLam = nullptr;
+  double *bxKb = nullptr, *bxMb = nullptr, *bxt4 = nullptr;   // the 1-D matrices as bands; operator work vector
   BoxNodes bxnodes{};
   fep3m_options opt{};
   hipStream_t stream = nullptr;
@@ -473,12 +474,13 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   gw = alloc<double>(gwh.size(), "load weights");
   w1 = alloc<double>(w1h.size(), "mass ones");
   hip_check(hipMemcpy(T, T_host.data(), T_host.size() * sizeof(double), hipMemcpyHostToDevice), "upload tables");
-  if (!generic) {  // transposed copy Tt[D][m][a] for the reverse pass
+  {  // transposed copy Tt[D][m][a] for the reverse pass
     const size_t ND = size_t(2 * nsr + 1) * (2 * nsr + 1) * (2 * nsr + 1), NM = size_t(p + 1) * (p + 1) * (p + 1);
+    const size_t NA = size_t(na);
     std::vector<double> tt(T_host.size());
-    for (size_t a = 0; a < 8; ++a)
+    for (size_t a = 0; a < NA; ++a)
       for (size_t iD = 0; iD < ND; ++iD)
-        for (size_t m = 0; m < NM; ++m) tt[(iD * NM + m) * 8 + a] = T_host[(a * ND + iD) * NM + m];
+        for (size_t m = 0; m < NM; ++m) tt[(iD * NM + m) * NA + a] = T_host[(a * ND + iD) * NM + m];
     Tt = alloc<double>(tt.size(), "transposed tables");
     hip_check(hipMemcpy(Tt, tt.data(), tt.size() * sizeof(double), hipMemcpyHostToDevice), "upload tables");
   }
@@ -911,16 +913,29 @@ void fep3m_ctx::build_box() {
   bxt1 = alloc<double>(nv, "box work");
   bxt2 = alloc<double>(nv, "box work");
   bxt3 = alloc<double>(nv, "box work");
+  bxt4 = alloc<double>(nv, "box work");
   bxg = alloc<double>(nv, "box assembled deposit");
   bxlam = alloc<double>(nv, "box adjoint potential");
   Mat K1, M1;
   assemble_1d(p, n, false, K1, M1);
-  std::vector<double> kc(size_t(Pb) * Pb), mc(size_t(Pb) * Pb);
+  // bands of half-width p: row o holds A(o, o - p .. o + p); every entry
+  // outside the band must be zero (elements couple nodes at most p apart)
+  const int W = 2 * p + 1;
+  std::vector<double> kb(size_t(Pb) * W, 0.0), mb(size_t(Pb) * W, 0.0);
   for (int i = 0; i < Pb; ++i)
-    for (int j = 0; j < Pb; ++j) {   // column-major (both symmetric)
-      kc[i + size_t(j) * Pb] = K1(i, j);
-      mc[i + size_t(j) * Pb] = M1(i, j);
+    for (int j = 0; j < Pb; ++j) {
+      const int d = j - i + p;
+      if (d >= 0 && d < W) {
+        kb[size_t(i) * W + d] = K1(i, j);
+        mb[size_t(i) * W + d] = M1(i, j);
+      } else if (K1(i, j) != 0.0 || M1(i, j) != 0.0) {
+        throw Status(FEP3M_ERR_UNSUPPORTED, "box matrices wider than their band");
+      }
     }
+  bxKb = alloc<double>(kb.size(), "box stiffness band");
+  bxMb = alloc<double>(mb.size(), "box mass band");
+  hip_check(hipMemcpy(bxKb, kb.data(), kb.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
+  hip_check(hipMemcpy(bxMb, mb.data(), mb.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
   Mat Ki(Pi, Pi), Mi(Pi, Pi);
   for (int i = 0; i < Pi; ++i)
     for (int j = 0; j < Pi; ++j) {
@@ -933,12 +948,8 @@ void fep3m_ctx::build_box() {
   std::vector<double> vc(size_t(Pi) * Pi);
   for (int i = 0; i < Pi; ++i)
     for (int j = 0; j < Pi; ++j) vc[i + size_t(j) * Pi] = V(i, j);
-  bxK1 = alloc<double>(kc.size(), "box stiffness");
-  bxM1 = alloc<double>(mc.size(), "box mass");
   bxV = alloc<double>(vc.size(), "box interior eigenvectors");
   bxLam = alloc<double>(size_t(Pi), "box interior eigenvalues");
-  hip_check(hipMemcpy(bxK1, kc.data(), kc.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
-  hip_check(hipMemcpy(bxM1, mc.data(), mc.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
   hip_check(hipMemcpy(bxV, vc.data(), vc.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
   hip_check(hipMemcpy(bxLam, lamv.data(), size_t(Pi) * sizeof(double), hipMemcpyHostToDevice), "upload");
   const Vec nodes = gll_nodes(p);
@@ -1025,19 +1036,12 @@ void fep3m_ctx::box_solve_neumann(double *f, double *sol, int which) {
 }
 
 // y = K v on the box (all nodes; the rows of the interior nodes are those of
-// the Dirichlet problem): K = Kx My Mz + Mx Ky Mz + Mx My Kz as dense 1-D
-// transforms, y = Kx (My Mz v) + Mx (Ky Mz v + My Kz v).
+// the Dirichlet problem): K = Kx My Mz + Mx Ky Mz + Mx My Kz by banded 1-D
+// passes, y = Kx (My Mz v) + Mx (Ky Mz v + My Kz v).  Uses bxt1, bxt2, bxt3
+// and bxt4.
 void fep3m_ctx::box_apply(const double *v, double *y) {
-  const size_t nv = size_t(Pb) * Pb * Pb * nb;
-  launch_axis_transform(stream, Pb, 2, nb, bxM1, false, v, bxt1);      // Mz v
-  launch_axis_transform(stream, Pb, 1, nb, bxM1, false, bxt1, bxt2);   // My Mz v
-  launch_axis_transform(stream, Pb, 0, nb, bxK1, false, bxt2, y);      // Kx My Mz v
-  launch_axis_transform(stream, Pb, 1, nb, bxK1, false, bxt1, bxt2);   // Ky Mz v
-  launch_axis_transform(stream, Pb, 2, nb, bxK1, false, v, bxt1);      // Kz v
-  launch_axis_transform(stream, Pb, 1, nb, bxM1, false, bxt1, bxt3);   // My Kz v
-  launch_box_axpby(stream, nv, 1.0, bxt3, 1.0, bxt2);
-  launch_axis_transform(stream, Pb, 0, nb, bxM1, false, bxt2, bxt1);   // Mx (Ky Mz v + My Kz v)
-  launch_box_axpby(stream, nv, 1.0, bxt1, 1.0, y);
+  if (launch_box_apply(stream, Pb, nb, p, bxKb, bxMb, v, bxt1, bxt2, bxt3, bxt4, y) != 0)
+    throw Status(FEP3M_ERR_UNSUPPORTED, "box operator variant");
 }
 
 // Interior solve of the box: sol holds phi_B on the boundary and zero
@@ -1153,7 +1157,7 @@ void fep3m_ctx::reverse_box(double *F, double *dUdQ) {
     stage_mark(FEP3M_PROF_ADJ_NEAR, true);
     if (launch_box_flux_adj(stream, nb, n, p, bxquad, bxlam, bxLw, bxhF) != 0 ||
         launch_box_h_slots(stream, nb, n, p, bxhF, gE) != 0 ||
-        launch_adj_g(stream, nb, n, nsr, p, span, nl, 1, gE, T, bxlam, gw, Aadj) != 0)
+        launch_adj_g(stream, nb, n, nsr, p, span, nl, 1, gE, Tt, bxlam, gw, Aadj) != 0)
       throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
     stage_mark(FEP3M_PROF_ADJ_NEAR, false);
     stage_mark(FEP3M_PROF_FORCES, true);
@@ -1174,7 +1178,7 @@ void fep3m_ctx::reverse_box(double *F, double *dUdQ) {
   // the boundary term of the moment adjoint as -mu in the deposit's
   // canonical slots (the deposit is rebuilt by every reverse pass)
   if (launch_box_mu_slots(stream, nb, n, p, bxy, gE) != 0 ||
-      launch_adj_g(stream, nb, n, nsr, p, span, nl, 1, gE, T, bxlam, gw, Aadj) != 0)
+      launch_adj_g(stream, nb, n, nsr, p, span, nl, 1, gE, Tt, bxlam, gw, Aadj) != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
   stage_mark(FEP3M_PROF_ADJ_NEAR, false);
   stage_mark(FEP3M_PROF_FORCES, true);
@@ -1536,7 +1540,7 @@ void fep3m_ctx::reverse(double *F, double *dUdQ) {
     if (as == 0) as = launch_adj_fft_finish(stream, nb, n, p, lam, gw, za, Aadj);
     adj_near_ready = false;
   } else if (generic) {
-    as = launch_adj_g(stream, nb, n, nsr, p, span, nl, 0, gE, T, lam, gw, Aadj);
+    as = launch_adj_g(stream, nb, n, nsr, p, span, nl, 0, gE, Tt, lam, gw, Aadj);
   } else {
     as = launch_adj_moments(stream, nb, p, n, nsr, gE, Tt, lam, gw, Aadj);
   }

@@ -576,13 +576,105 @@ __global__ __launch_bounds__(256) void k_box_sub_mass(int P, int nb, double invV
   }
 }
 
+// One pass of the box operator K = Kx My Mz + Mx Ky Mz + Mx My Kz along one
+// axis of nb P^3 blocks.  The 1-D element-assembled matrices are banded (node
+// o couples to nodes o - HB .. o + HB, HB = p), stored row by row as
+// band[o (2 HB + 1) + d] = A(o, o - HB + d), zero outside the matrix:
+// out0 = Ba in0 (+ Bb in1 when in1 is given), and out1 = Bc in0 when out1 is
+// given.  A thread owns R consecutive outputs of one line and holds the
+// R + 2 HB inputs they need in registers; along x (R = 1) the lanes run over
+// the outputs themselves, along y and z over x, so every load and store of a
+// wave covers consecutive x.
+template <int HB, int R>
+__global__ __launch_bounds__(256) void k_box_band(int P, int axis, int nb, const double *__restrict__ Ba,
+                                                  const double *__restrict__ Bb, const double *__restrict__ Bc,
+                                                  const double *__restrict__ in0, const double *__restrict__ in1,
+                                                  double *__restrict__ out0, double *__restrict__ out1) {
+  constexpr int W = 2 * HB + 1, NV = R + 2 * HB;
+  const size_t P2 = size_t(P) * P, per = P2 * P;
+  const int nrun = (P + R - 1) / R;
+  const size_t total = size_t(nb) * P2 * nrun;
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += size_t(gridDim.x) * blockDim.x) {
+    size_t base, stride;
+    int o0;
+    if (axis == 0) {            // t = (line, run), lanes along x
+      o0 = int(t % nrun) * R;
+      base = (t / nrun) * P;
+      stride = 1;
+    } else if (axis == 1) {     // t = ((sys, z), run, x)
+      const int x = int(t % P);
+      const size_t r = t / P;
+      o0 = int(r % nrun) * R;
+      const size_t sz = r / nrun;   // sys * P + z
+      base = (sz / P) * per + (sz % P) * P2 + x;
+      stride = P;
+    } else {                    // t = (sys, run, y, x)
+      const size_t xy = t % P2, r = t / P2;
+      o0 = int(r % nrun) * R;
+      base = (r / nrun) * per + xy;
+      stride = P2;
+    }
+    double v0[NV], v1[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int k = o0 - HB + j;
+      const bool ok = k >= 0 && k < P;
+      v0[j] = ok ? in0[base + size_t(k) * stride] : 0.0;
+      v1[j] = (ok && in1) ? in1[base + size_t(k) * stride] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int o = o0 + r;
+      if (o >= P) break;
+      const double *ba = Ba + size_t(o) * W, *bb = Bb + size_t(o) * W, *bc = Bc + size_t(o) * W;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int d = 0; d < W; ++d) s0 += ba[d] * v0[r + d];
+      if (in1) {
+#pragma unroll
+        for (int d = 0; d < W; ++d) s0 += bb[d] * v1[r + d];
+      }
+      out0[base + size_t(o) * stride] = s0;
+      if (out1) {
+#pragma unroll
+        for (int d = 0; d < W; ++d) s1 += bc[d] * v0[r + d];
+        out1[base + size_t(o) * stride] = s1;
+      }
+    }
+  }
+}
+
 inline int grid_of(size_t count) {
   size_t g = (count + 255) / 256;
   if (g < 1) g = 1;
   return int(g > 65536 ? 65536 : g);
 }
 
+template <int HB>
+void box_apply_impl(hipStream_t s, int P, int nb, const double *Kb, const double *Mb, const double *v, double *t1,
+                    double *t2, double *t3, double *t4, double *y) {
+  constexpr int RYZ = 8;
+  const size_t lines = size_t(nb) * P * P;
+  const int gyz = grid_of(lines * ((P + RYZ - 1) / RYZ)), gx = grid_of(lines * P);
+  // t1 = Mz v, t3 = Kz v
+  hipLaunchKernelGGL((k_box_band<HB, RYZ>), dim3(gyz), dim3(256), 0, s, P, 2, nb, Mb, Mb, Kb, v, nullptr, t1, t3);
+  // t2 = Ky t1 + My t3, t4 = My t1
+  hipLaunchKernelGGL((k_box_band<HB, RYZ>), dim3(gyz), dim3(256), 0, s, P, 1, nb, Kb, Mb, Mb, t1, t3, t2, t4);
+  // y = Kx t4 + Mx t2
+  hipLaunchKernelGGL((k_box_band<HB, 1>), dim3(gx), dim3(256), 0, s, P, 0, nb, Kb, Mb, Kb, t4, t2, y, nullptr);
+}
+
 }  // namespace
+
+int launch_box_apply(hipStream_t s, int P, int nb, int p, const double *Kb, const double *Mb, const double *v,
+                     double *t1, double *t2, double *t3, double *t4, double *y) {
+  switch (p) {
+    case 4: box_apply_impl<4>(s, P, nb, Kb, Mb, v, t1, t2, t3, t4, y); return 0;
+    case 5: box_apply_impl<5>(s, P, nb, Kb, Mb, v, t1, t2, t3, t4, y); return 0;
+    case 6: box_apply_impl<6>(s, P, nb, Kb, Mb, v, t1, t2, t3, t4, y); return 0;
+    default: return -1;
+  }
+}
 
 int launch_box_bvals(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const BoxNodes &nodes, const int *start,
                      const double *sg, const double *sQ, const double *Wneg, double *phiB) {

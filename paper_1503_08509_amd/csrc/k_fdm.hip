@@ -137,9 +137,20 @@ __global__ __launch_bounds__(256) void k_fs_solve(int n, const double2 *__restri
 // Dense transform along one axis of nsys P^3 arrays [z][y][x]:
 // out[line][o] = sum_k A(o, k) in[line][k], A(o, k) = V[k + o P] (TRANS:
 // V^T, the forward transform into modes) or V[o + k P] (back), V the
-// column-major eigenvector matrix.  Tiles of 64 outputs x 64 lines, k in
-// chunks of 16 staged in LDS, 4 x 4 results per thread.
-template <bool TRANS>
+// column-major eigenvector matrix.  A block covers 64 outputs x 64 lines,
+// k in chunks of 16 staged in LDS; each of its four waves owns 32 x 32 of
+// them as 2 x 2 float64 matrix-core tiles (16 x 16 x 4 steps: lane l
+// supplies row l % 16, k l / 16 of the left operand and k l / 16, column
+// l % 16 of the right one; accumulator value v of lane l is row l / 16 + 4 v,
+// column l % 16).  LR: the tile rows are lines and the columns outputs
+// (along x, where outputs are contiguous, so a store covers 16 consecutive
+// outputs); otherwise rows are outputs and columns lines (along y and z,
+// where consecutive lines are consecutive x).  The steps accumulate in k
+// order like fused multiply-adds, so every output equals a sequential loop
+// over k.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <bool TRANS, bool LR>
 __global__ __launch_bounds__(256) void k_axis_transform(int P, int axis, int nsys, const double *__restrict__ V,
                                                         const double *__restrict__ in, double *__restrict__ out) {
   __shared__ double As[16][65];   // [k][o]
@@ -150,7 +161,9 @@ __global__ __launch_bounds__(256) void k_axis_transform(int P, int axis, int nsy
   const size_t ltile = blockIdx.x / otiles;
   const int o0 = (blockIdx.x % otiles) * 64;
   const size_t l0 = ltile * 64;
-  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int wo = (w & 1) * 32, wl = (w >> 1) * 32;
   // element k of line l: line l = (system, a, b) with a, b the other two axes
   auto addr = [&](size_t l, int k) -> size_t {
     const size_t sys = l / P2, r = l % P2;
@@ -159,7 +172,11 @@ __global__ __launch_bounds__(256) void k_axis_transform(int P, int axis, int nsy
     if (axis == 1) return sys * per + a * P2 + size_t(k) * P + b;
     return sys * per + size_t(k) * P2 + r;
   };
-  double acc[4][4] = {};
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < P; k0 += 16) {
     for (int i = tid; i < 16 * 64; i += 256) {
       int kk, oo;
@@ -176,30 +193,31 @@ __global__ __launch_bounds__(256) void k_axis_transform(int P, int axis, int nsy
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], x[4];
+    for (int ks = 0; ks < 16; ks += 4) {
+      double xa[2], ob[2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        a[r] = As[kk][tx + 16 * r];
-        x[r] = Xs[kk][ty + 16 * r];
-      }
+      for (int i = 0; i < 2; ++i) xa[i] = Xs[ks + kq][wl + 16 * i + r16];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 2; ++j) ob[j] = As[ks + kq][wo + 16 * j + r16];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[j] * x[i];
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = LR ? __builtin_amdgcn_mfma_f64_16x16x4f64(xa[i], ob[j], acc[i][j], 0, 0, 0)
+                         : __builtin_amdgcn_mfma_f64_16x16x4f64(ob[j], xa[i], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const size_t l = l0 + ty + 16 * i;
-    if (l >= lines) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int o = o0 + tx + 16 * j;
-      if (o < P) out[addr(l, o)] = acc[i][j];
-    }
-  }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const size_t l = l0 + wl + 16 * i + (LR ? kq + 4 * v : r16);
+        const int o = o0 + wo + 16 * j + (LR ? r16 : kq + 4 * v);
+        if (l < lines && o < P) out[addr(l, o)] = acc[i][j][v];
+      }
 }
 
 inline int grid_of(size_t count) {
@@ -228,10 +246,14 @@ void launch_axis_transform(hipStream_t s, int P, int axis, int nsys, const doubl
                            double *out) {
   const size_t lines = size_t(P) * P * nsys;
   const unsigned grid = unsigned(((lines + 63) / 64) * ((P + 63) / 64));
-  if (to_modes)
-    hipLaunchKernelGGL(k_axis_transform<true>, dim3(grid), dim3(256), 0, s, P, axis, nsys, V, in, out);
+  if (to_modes && axis == 0)
+    hipLaunchKernelGGL((k_axis_transform<true, true>), dim3(grid), dim3(256), 0, s, P, axis, nsys, V, in, out);
+  else if (to_modes)
+    hipLaunchKernelGGL((k_axis_transform<true, false>), dim3(grid), dim3(256), 0, s, P, axis, nsys, V, in, out);
+  else if (axis == 0)
+    hipLaunchKernelGGL((k_axis_transform<false, true>), dim3(grid), dim3(256), 0, s, P, axis, nsys, V, in, out);
   else
-    hipLaunchKernelGGL(k_axis_transform<false>, dim3(grid), dim3(256), 0, s, P, axis, nsys, V, in, out);
+    hipLaunchKernelGGL((k_axis_transform<false, false>), dim3(grid), dim3(256), 0, s, P, axis, nsys, V, in, out);
 }
 
 int launch_fs_solve(hipStream_t s, int nsys, int n, int p, const double *rhs, double *out, double2 *Z,

@@ -205,68 +205,93 @@ __global__ __launch_bounds__(384) void k_psi_g(int n, int nsr, int box, const do
   }
 }
 
-// Near part of the moment adjoint, A[E][a] = -sum_D sum_m g_{E+D}[m] T[a][D][m],
-// on bricks of target elements: thread (t, a) pairs, the deposits of the
-// brick's sources for each offset staged in LDS.
+// Near part of the moment adjoint, A[E][a] = -sum_D sum_m g_{E+D}[m] T[a][D][m].
+// A block takes a brick of TB target elements and NG groups of AG moments
+// (NA = NG AG); thread (group, target) accumulates its group's moments of its
+// target.  The deposits of the brick's source halo (the brick widened by
+// n_sr <= 3 elements on every side) are staged in LDS MC nodes at a time;
+// per (offset D, node m) a thread reads the one deposit of its target's
+// source E + D from LDS and multiplies it into AG table values that are the
+// same for the whole wave (a wave lies inside one group), read from the
+// transposed tables Tt[D][m][a] through scalar loads.  Sums run over m
+// chunks, then D, then the chunk's nodes.
+template <int NA>
+struct AdjNearShape {
+  static constexpr int AG = NA == 27 ? 9 : (NA == 125 ? 25 : (NA >= 8 ? 8 : NA));
+  static constexpr int NG = NA / AG;
+  static constexpr int TB = NG == 1 ? 256 : 64;   // targets per block (a multiple of the wave)
+  static constexpr int BX = TB == 256 ? 8 : 4, BY = BX, BZ = 4;
+  static constexpr int MC = 2;                    // deposit nodes per LDS stage
+  static constexpr int HX = BX + 6, HY = BY + 6, HZ = BZ + 6;
+  static constexpr int NH = HX * HY * HZ;
+  static constexpr int THREADS = NG * TB;
+  static_assert(NG * AG == NA && BX * BY * BZ == TB && TB % 64 == 0, "adjoint brick shape");
+};
+
 template <int PO, int NL>
-__global__ __launch_bounds__(256) void k_adj_near_g(int n, int nsr, int box, const double *__restrict__ gEall,
-                                                    const double *__restrict__ T, double *__restrict__ Aall) {
-  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NA = NL * NL * NL, NP = kBT * NA;
-  constexpr int PT = (NP + 255) / 256;   // (t, a) pairs per thread
-  __shared__ double Gs[kBT * NM];
-  const int bxn = (n + kBX - 1) / kBX, byn = (n + kBY - 1) / kBY, bzn = (n + kBZ - 1) / kBZ;
+__global__ __launch_bounds__(AdjNearShape<NL * NL * NL>::THREADS) void k_adj_near_g(
+    int n, int nsr, int box, const double *__restrict__ gEall, const double *__restrict__ Tt,
+    double *__restrict__ Aall) {
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NA = NL * NL * NL;
+  using S = AdjNearShape<NA>;
+  constexpr int AG = S::AG, TB = S::TB, MC = S::MC, HX = S::HX, HY = S::HY, NH = S::NH;
+  __shared__ double Gs[MC * NH];
+  const int bxn = (n + S::BX - 1) / S::BX, byn = (n + S::BY - 1) / S::BY, bzn = (n + S::BZ - 1) / S::BZ;
   const int per_cfg = bxn * byn * bzn;
   const int cfg = blockIdx.x / per_cfg;
-  int br = blockIdx.x % per_cfg;
+  const int br = blockIdx.x % per_cfg;
   const int bx = br % bxn, by = (br / bxn) % byn, bz = br / (bxn * byn);
   const size_t M = size_t(n) * n * n;
   const double *gE = gEall + size_t(cfg) * M * NM;
   double *A = Aall + size_t(cfg) * M * NA;
-  const int S = 2 * nsr + 1, ND = S * S * S;
-  double acc[PT];
+  const int S1 = 2 * nsr + 1, ND = S1 * S1 * S1;
+  const int tid = threadIdx.x, t = tid % TB;
+  const int g = __builtin_amdgcn_readfirstlane(tid / TB);
+  const int tx = t % S::BX, ty = (t / S::BX) % S::BY, tz = t / (S::BX * S::BY);
+  const int hx0 = bx * S::BX - nsr, hy0 = by * S::BY - nsr, hz0 = bz * S::BZ - nsr;
+  const int LX = S::BX + 2 * nsr, LY = S::BY + 2 * nsr, LZ = S::BZ + 2 * nsr;   // halo in use
+  const int hbase = (tz * HY + ty) * HX + tx;   // halo index of the source at D = (-nsr, -nsr, -nsr)
+  double acc[AG];
 #pragma unroll
-  for (int r = 0; r < PT; ++r) acc[r] = 0.0;
-  for (int iD = 0; iD < ND; ++iD) {
-    const int Dx = iD % S - nsr, Dy = (iD / S) % S - nsr, Dz = iD / (S * S) - nsr;
+  for (int j = 0; j < AG; ++j) acc[j] = 0.0;
+  for (int m0 = 0; m0 < NM; m0 += MC) {
     __syncthreads();
-    for (int i = threadIdx.x; i < kBT * NM; i += blockDim.x) {
-      const int t = i / NM, m = i % NM;
-      const int ex = bx * kBX + t % kBX, ey = by * kBY + (t / kBX) % kBY, ez = bz * kBZ + t / (kBX * kBY);
-      double v = 0.0;
-      if (ex < n && ey < n && ez < n) {
-        int sx = ex + Dx, sy = ey + Dy, sz = ez + Dz;
-        const bool in = sx >= 0 && sx < n && sy >= 0 && sy < n && sz >= 0 && sz < n;
-        if (!box) {
-          sx = wrapn(sx, n);
-          sy = wrapn(sy, n);
-          sz = wrapn(sz, n);
-        }
-        if (!box || in) v = gE[(size_t(sx) + size_t(n) * (sy + size_t(n) * sz)) * NM + m];
+    for (int i = tid; i < MC * LX * LY * LZ; i += S::THREADS) {
+      const int mm = i % MC, h = i / MC;
+      const int lx = h % LX, ly = (h / LX) % LY, lz = h / (LX * LY);
+      int sx = hx0 + lx, sy = hy0 + ly, sz = hz0 + lz;
+      const bool in = sx >= 0 && sx < n && sy >= 0 && sy < n && sz >= 0 && sz < n;
+      if (!box) {
+        sx = wrapn(sx, n);
+        sy = wrapn(sy, n);
+        sz = wrapn(sz, n);
       }
-      Gs[i] = v;
+      double v = 0.0;
+      if ((!box || in) && m0 + mm < NM) v = gE[(size_t(sx) + size_t(n) * (sy + size_t(n) * sz)) * NM + m0 + mm];
+      Gs[mm * NH + (lz * HY + ly) * HX + lx] = v;
     }
     __syncthreads();
+    for (int dz = 0; dz < S1; ++dz)
+      for (int dy = 0; dy < S1; ++dy) {
+        const int hrow = hbase + (dz * HY + dy) * HX;
+        const double *Trow = Tt + (size_t((dz * S1 + dy) * S1) * NM + m0) * NA + g * AG;
+        for (int dx = 0; dx < S1; ++dx) {
+          const double *Td = Trow + size_t(dx) * NM * NA;
 #pragma unroll
-    for (int r = 0; r < PT; ++r) {
-      const int pidx = threadIdx.x + 256 * r;
-      if (pidx >= NP) continue;
-      const int t = pidx % kBT, a = pidx / kBT;
-      const double *Tr = T + (size_t(a) * ND + iD) * NM;
-      const double *gs = Gs + t * NM;
-      double s = 0.0;
-      for (int m = 0; m < NM; ++m) s += gs[m] * Tr[m];
-      acc[r] += s;
-    }
-  }
+          for (int mm = 0; mm < MC; ++mm) {
+            if (m0 + mm >= NM) break;
+            const double gv = Gs[mm * NH + hrow + dx];
 #pragma unroll
-  for (int r = 0; r < PT; ++r) {
-    const int pidx = threadIdx.x + 256 * r;
-    if (pidx >= NP) continue;
-    const int t = pidx % kBT, a = pidx / kBT;
-    const int ex = bx * kBX + t % kBX, ey = by * kBY + (t / kBX) % kBY, ez = bz * kBZ + t / (kBX * kBY);
-    if (ex >= n || ey >= n || ez >= n) continue;
-    A[(size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NA + a] = -acc[r];
+            for (int j = 0; j < AG; ++j) acc[j] += gv * Td[mm * NA + j];
+          }
+        }
+      }
   }
+  const int ex = bx * S::BX + tx, ey = by * S::BY + ty, ez = bz * S::BZ + tz;
+  if (ex >= n || ey >= n || ez >= n) return;
+  double *dst = A + (size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NA + g * AG;
+#pragma unroll
+  for (int j = 0; j < AG; ++j) dst[j] = -acc[j];
 }
 
 // Mesh part of the moment adjoint: A[E][a] += 4 pi sum over the support's
@@ -395,14 +420,22 @@ int launch_psi_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, int box, 
   }
 }
 
+template <int PO, int NL>
+static void adj_near_launch(hipStream_t s, int nb, int n, int nsr, int box, const double *gE, const double *Tt,
+                            double *A) {
+  using S = AdjNearShape<NL * NL * NL>;
+  const int bricks = ((n + S::BX - 1) / S::BX) * ((n + S::BY - 1) / S::BY) * ((n + S::BZ - 1) / S::BZ);
+  hipLaunchKernelGGL((k_adj_near_g<PO, NL>), dim3(nb * bricks), dim3(S::THREADS), 0, s, n, nsr, box, gE, Tt, A);
+}
+
 template <int PO, int SPAN>
-static int adj_g_nl(hipStream_t s, int nb, int n, int nsr, int nl, int box, const double *gE, const double *T,
+static int adj_g_nl(hipStream_t s, int nb, int n, int nsr, int nl, int box, const double *gE, const double *Tt,
                     const double *lam, const double *gw, double *A) {
-  const int bricks = ((n + kBX - 1) / kBX) * ((n + kBY - 1) / kBY) * ((n + kBZ - 1) / kBZ);
+  if (nsr < 1 || nsr > 3) return -1;
   const int MT = nb * n * n * n;
   const int g = grid_for_count(int64_t(MT) * nl * nl * nl);
-#define CALL(NL)                                                                                                  \
-  hipLaunchKernelGGL((k_adj_near_g<PO, NL>), dim3(nb * bricks), dim3(256), 0, s, n, nsr, box, gE, T, A);         \
+#define CALL(NL)                                             \
+  adj_near_launch<PO, NL>(s, nb, n, nsr, box, gE, Tt, A); \
   hipLaunchKernelGGL((k_adj_lam_g<PO, SPAN, NL>), dim3(g), dim3(256), 0, s, n, MT, box, lam, gw, A)
   FEP3M_NL_SWITCH(nl, CALL)
 #undef CALL

@@ -100,7 +100,7 @@ int launch_load_g(hipStream_t s, int nb, int n, int p, int span, int nl, int box
 int launch_psi_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, int box, const double *C, const double *T,
                  const double *phi, double *W);
 int launch_adj_g(hipStream_t s, int nb, int n, int nsr, int p, int span, int nl, int box, const double *gE,
-                 const double *T, const double *lam, const double *gw, double *A);
+                 const double *Tt, const double *lam, const double *gw, double *A);   // Tt: tables as [D][m][a]
 
 // grounded box (k_box.hip): mesh vectors of (p n + 1)^3 nodes per
 // configuration, P = p n + 1.
@@ -120,6 +120,11 @@ struct BoxQuad {
 // near field -Psi per element (launch_psi_g with box = 1 and no phi)
 int launch_box_bvals(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const BoxNodes &nodes, const int *start,
                      const double *sg, const double *sQ, const double *Wneg, double *phiB);
+// y = K v on every node of the box (K = Kx My Mz + Mx Ky Mz + Mx My Kz) by
+// three banded 1-D passes; Kb, Mb the 1-D matrices as P x (2 p + 1) bands,
+// t1..t4 work vectors of nb P^3
+int launch_box_apply(hipStream_t s, int P, int nb, int p, const double *Kb, const double *Mb, const double *v,
+                     double *t1, double *t2, double *t3, double *t4, double *y);
 // interior nodes of the box <-> contiguous (P - 2)^3 blocks
 void launch_box_interior(hipStream_t s, int P, int nb, bool to_interior, const double *src, double *dst);
 // y = c y + a x (c = 0: y is not read); fill y = v
