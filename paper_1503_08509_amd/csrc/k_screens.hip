@@ -136,72 +136,107 @@ __global__ __launch_bounds__(256) void k_load_g(int n, int K, int box, const dou
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// Near-screen field on bricks of BX x BY x BZ target elements: thread m
-// holds node m of every target of the brick; per near offset the sources'
-// moments are staged in LDS and each table value read serves all targets.
-constexpr int kBX = 4, kBY = 2, kBZ = 2, kBT = kBX * kBY * kBZ;
-
-// box: sources outside [0, n)^3 are absent and phi is the (PO n + 1)^3
-// nodal field of the box; a null phi gives W = -Psi.
+// Near-screen field, Psi_E[m] = sum_D sum_a T[a][D][m] C[E - D][a].  A block
+// takes a brick of 4 x 4 x 4 target elements and NG groups of MG nodes
+// (NM = NG MG); thread (group, target) accumulates its group's nodes of its
+// target.  The moments of the brick's source halo (the brick widened by
+// n_sr <= 3 elements on every side) are staged in LDS AC moments at a time;
+// per (offset D, moment a) a thread reads the one moment of its target's
+// source E - D from LDS and multiplies it into MG table values that are the
+// same for the whole wave (a wave lies inside one group), read through
+// scalar loads.  Sums run over moment chunks, then D, then the chunk's
+// moments.  box: sources outside [0, n)^3 are absent and phi is the
+// (PO n + 1)^3 nodal field of the box; a null phi gives W = -Psi.
 template <int PO, int NL>
-__global__ __launch_bounds__(384) void k_psi_g(int n, int nsr, int box, const double *__restrict__ Call,
-                                               const double *__restrict__ T, const double *__restrict__ phiall,
-                                               double *__restrict__ Wall) {
-  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1, NA = NL * NL * NL;
-  __shared__ double Cs[kBT * NA];
-  const int bxn = (n + kBX - 1) / kBX, byn = (n + kBY - 1) / kBY, bzn = (n + kBZ - 1) / kBZ;
+struct PsiShape {
+  static constexpr int NM = (PO + 1) * (PO + 1) * (PO + 1), NA = NL * NL * NL;
+  static constexpr int MG = NM == 64 ? 16 : (NM == 125 ? 25 : (NM == 216 ? 27 : 49));
+  static constexpr int NG = NM / MG;
+  static constexpr int BX = 4, BY = 4, BZ = 4, TB = BX * BY * BZ;
+  static constexpr int AC = NA < 8 ? NA : 8;      // moments per LDS stage
+  static constexpr int HX = BX + 6, HY = BY + 6, HZ = BZ + 6, NH = HX * HY * HZ;
+  static constexpr int THREADS = NG * TB;
+  static_assert(NG * MG == NM && THREADS <= 1024, "near-field brick shape");
+};
+
+template <int PO, int NL>
+__global__ __launch_bounds__((PsiShape<PO, NL>::THREADS)) void k_psi_g(int n, int nsr, int box,
+                                                                     const double *__restrict__ Call,
+                                                                     const double *__restrict__ T,
+                                                                     const double *__restrict__ phiall,
+                                                                     double *__restrict__ Wall) {
+  using S = PsiShape<PO, NL>;
+  constexpr int Q1 = PO + 1, NM = S::NM, NA = S::NA, MG = S::MG, AC = S::AC, HX = S::HX, HY = S::HY, NH = S::NH;
+  __shared__ double Cs[AC * NH];
+  const int bxn = (n + S::BX - 1) / S::BX, byn = (n + S::BY - 1) / S::BY, bzn = (n + S::BZ - 1) / S::BZ;
   const int per_cfg = bxn * byn * bzn;
   const int cfg = blockIdx.x / per_cfg;
-  int br = blockIdx.x % per_cfg;
+  const int br = blockIdx.x % per_cfg;
   const int bx = br % bxn, by = (br / bxn) % byn, bz = br / (bxn * byn);
   const size_t M = size_t(n) * n * n;
   const int P = PO * n + (box ? 1 : 0);
   const double *C = Call + size_t(cfg) * M * NA;
   const double *phi = phiall ? phiall + size_t(cfg) * P * P * P : nullptr;
   double *W = Wall + size_t(cfg) * M * NM;
-  const int S = 2 * nsr + 1, ND = S * S * S;
-  const int m = threadIdx.x;
-  double acc[kBT];
+  const int S1 = 2 * nsr + 1, ND = S1 * S1 * S1;
+  const int tid = threadIdx.x, t = tid % S::TB;
+  const int g = __builtin_amdgcn_readfirstlane(tid / S::TB);
+  const int tx = t % S::BX, ty = (t / S::BX) % S::BY, tz = t / (S::BX * S::BY);
+  const int hx0 = bx * S::BX - nsr, hy0 = by * S::BY - nsr, hz0 = bz * S::BZ - nsr;
+  const int LX = S::BX + 2 * nsr, LY = S::BY + 2 * nsr, LZ = S::BZ + 2 * nsr;   // halo in use
+  // the source of offset D sits at halo (t + nsr - D): index hbase - (D + nsr) . (1, HX, HX HY)
+  const int hbase = ((tz + 2 * nsr) * HY + ty + 2 * nsr) * HX + tx + 2 * nsr;
+  double acc[MG];
 #pragma unroll
-  for (int t = 0; t < kBT; ++t) acc[t] = 0.0;
-  for (int iD = 0; iD < ND; ++iD) {
-    const int Dx = iD % S - nsr, Dy = (iD / S) % S - nsr, Dz = iD / (S * S) - nsr;
+  for (int j = 0; j < MG; ++j) acc[j] = 0.0;
+  for (int a0 = 0; a0 < NA; a0 += AC) {
     __syncthreads();
-    for (int i = threadIdx.x; i < kBT * NA; i += blockDim.x) {
-      const int t = i / NA, a = i % NA;
-      const int ex = bx * kBX + t % kBX, ey = by * kBY + (t / kBX) % kBY, ez = bz * kBZ + t / (kBX * kBY);
+    for (int i = tid; i < AC * LX * LY * LZ; i += S::THREADS) {
+      const int aa = i % AC, h = i / AC;
+      const int lx = h % LX, ly = (h / LX) % LY, lz = h / (LX * LY);
+      int sx = hx0 + lx, sy = hy0 + ly, sz = hz0 + lz;
+      const bool in = sx >= 0 && sx < n && sy >= 0 && sy < n && sz >= 0 && sz < n;
+      if (!box) {
+        sx = wrapn(sx, n);
+        sy = wrapn(sy, n);
+        sz = wrapn(sz, n);
+      }
       double v = 0.0;
-      if (ex < n && ey < n && ez < n) {
-        int sx = ex - Dx, sy = ey - Dy, sz = ez - Dz;
-        const bool in = sx >= 0 && sx < n && sy >= 0 && sy < n && sz >= 0 && sz < n;
-        if (!box) {
-          sx = wrapn(sx, n);
-          sy = wrapn(sy, n);
-          sz = wrapn(sz, n);
-        }
-        if (!box || in) v = C[(size_t(sx) + size_t(n) * (sy + size_t(n) * sz)) * NA + a];
-      }
-      Cs[i] = v;
+      if ((!box || in) && a0 + aa < NA) v = C[(size_t(sx) + size_t(n) * (sy + size_t(n) * sz)) * NA + a0 + aa];
+      Cs[aa * NH + (lz * HY + ly) * HX + lx] = v;
     }
     __syncthreads();
-    if (m < NM) {
-      const double *Tm = T + size_t(iD) * NM + m;
-      for (int a = 0; a < NA; ++a) {
-        const double tv = Tm[size_t(a) * ND * NM];
+    for (int dz = 0; dz < S1; ++dz)
+      for (int dy = 0; dy < S1; ++dy) {
+        const int hrow = hbase - (dz * HY + dy) * HX;
+        const int iD0 = (dz * S1 + dy) * S1;
+        for (int dx = 0; dx < S1; ++dx) {
+          const double *Td = T + (size_t(a0) * ND + iD0 + dx) * NM + g * MG;
 #pragma unroll
-        for (int t = 0; t < kBT; ++t) acc[t] += tv * Cs[t * NA + a];
+          for (int aa = 0; aa < AC; ++aa) {
+            if (a0 + aa >= NA) break;
+            const double cv = Cs[aa * NH + hrow - dx];
+            const double *Ta = Td + size_t(aa) * ND * NM;
+#pragma unroll
+            for (int j = 0; j < MG; ++j) acc[j] += cv * Ta[j];
+          }
+        }
       }
-    }
   }
-  if (m >= NM) return;
-  const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
+  const int ex = bx * S::BX + tx, ey = by * S::BY + ty, ez = bz * S::BZ + tz;
+  if (ex >= n || ey >= n || ez >= n) return;
+  const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
+  double *dst = W + E * NM + g * MG;
 #pragma unroll
-  for (int t = 0; t < kBT; ++t) {
-    const int ex = bx * kBX + t % kBX, ey = by * kBY + (t / kBX) % kBY, ez = bz * kBZ + t / (kBX * kBY);
-    if (ex >= n || ey >= n || ez >= n) continue;
-    const int gx = wrapn(PO * ex + mx, P), gy = wrapn(PO * ey + my, P), gz = wrapn(PO * ez + mz, P);
-    const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
-    W[E * NM + m] = (phi ? phi[(size_t(gz) * P + gy) * P + gx] : 0.0) - acc[t];
+  for (int j = 0; j < MG; ++j) {
+    const int m = g * MG + j;
+    const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
+    double ph = 0.0;
+    if (phi) {
+      const int gx = wrapn(PO * ex + mx, P), gy = wrapn(PO * ey + my, P), gz = wrapn(PO * ez + mz, P);
+      ph = phi[(size_t(gz) * P + gy) * P + gx];
+    }
+    dst[j] = ph - acc[j];
   }
 }
 
@@ -333,11 +368,6 @@ inline int grid_for_count(int64_t count) {
   return int(g > 65536 ? 65536 : g);
 }
 
-inline int psi_threads(int po) {
-  const int nm = (po + 1) * (po + 1) * (po + 1);
-  return ((nm + 63) / 64) * 64;
-}
-
 }  // namespace
 
 // ----------------------------------------------------------------- launchers
@@ -400,10 +430,14 @@ int launch_load_g(hipStream_t s, int nb, int n, int p, int span, int nl, int box
 template <int PO>
 static int psi_g_nl(hipStream_t s, int nb, int n, int nsr, int nl, int box, const double *C, const double *T,
                     const double *phi, double *W) {
-  const int bricks = ((n + kBX - 1) / kBX) * ((n + kBY - 1) / kBY) * ((n + kBZ - 1) / kBZ);
-#define CALL(NL)                                                                                              \
-  hipLaunchKernelGGL((k_psi_g<PO, NL>), dim3(nb * bricks), dim3(psi_threads(PO)), 0, s, n, nsr, box, C, T, phi, \
-                     W)
+  if (nsr < 1 || nsr > 3) return -1;
+#define CALL(NL)                                                                                            \
+  {                                                                                                         \
+    using S = PsiShape<PO, NL>;                                                                             \
+    const int bricks = ((n + S::BX - 1) / S::BX) * ((n + S::BY - 1) / S::BY) * ((n + S::BZ - 1) / S::BZ); \
+    hipLaunchKernelGGL((k_psi_g<PO, NL>), dim3(nb * bricks), dim3(S::THREADS), 0, s, n, nsr, box, C, T,  \
+                       phi, W);                                                                             \
+  }
   FEP3M_NL_SWITCH(nl, CALL)
 #undef CALL
   return 0;
