@@ -388,7 +388,7 @@ struct fep3m_ctx {
   void build_fdm();
   void build_box();
   void box_apply(const double *v, double *y);
-  void box_solve(const double *rhs, double *sol, int which);
+  void box_solve(const double *rhs, double *sol, int which, bool zero_boundary = false);
   void box_solve_neumann(double *f, double *sol, int which);
   void forward_box(double *Phi, double *U, bool pair_forces);
   void reverse_box(double *F, double *dUdQ);
@@ -918,22 +918,35 @@ void fep3m_ctx::build_box() {
   bxlam = alloc<double>(nv, "box adjoint potential");
   Mat K1, M1;
   assemble_1d(p, n, false, K1, M1);
-  // bands of half-width p: row o holds A(o, o - p .. o + p); every entry
-  // outside the band must be zero (elements couple nodes at most p apart)
+  // class rows of the bands of half-width p: row o holds A(o, o - p .. o + p)
+  // and equals the row of its class (o mod p inside, p for o = 0, p + 1 for
+  // o = P - 1); every entry outside the band must be zero (elements couple
+  // nodes at most p apart) and every row must equal its class row
   const int W = 2 * p + 1;
-  std::vector<double> kb(size_t(Pb) * W, 0.0), mb(size_t(Pb) * W, 0.0);
-  for (int i = 0; i < Pb; ++i)
+  std::vector<double> kb(size_t(p + 2) * W, 0.0), mb(size_t(p + 2) * W, 0.0);
+  auto cls = [&](int o) { return o == 0 ? p : (o == Pb - 1 ? p + 1 : o % p); };
+  std::vector<char> seen(p + 2, 0);
+  for (int i = 0; i < Pb; ++i) {
+    const int c = cls(i);
     for (int j = 0; j < Pb; ++j) {
       const int d = j - i + p;
-      if (d >= 0 && d < W) {
-        kb[size_t(i) * W + d] = K1(i, j);
-        mb[size_t(i) * W + d] = M1(i, j);
-      } else if (K1(i, j) != 0.0 || M1(i, j) != 0.0) {
-        throw Status(FEP3M_ERR_UNSUPPORTED, "box matrices wider than their band");
+      if (d < 0 || d >= W) {
+        if (K1(i, j) != 0.0 || M1(i, j) != 0.0) throw Status(FEP3M_ERR_UNSUPPORTED, "box matrices wider than their band");
+        continue;
+      }
+      double &kc = kb[size_t(c) * W + d], &mc = mb[size_t(c) * W + d];
+      if (!seen[c]) {
+        kc = K1(i, j);
+        mc = M1(i, j);
+      } else if (std::fabs(kc - K1(i, j)) > 1e-12 * std::fabs(K1(i, i)) ||
+                 std::fabs(mc - M1(i, j)) > 1e-12 * std::fabs(M1(i, i))) {
+        throw Status(FEP3M_ERR_UNSUPPORTED, "box matrix rows differ within a class");
       }
     }
-  bxKb = alloc<double>(kb.size(), "box stiffness band");
-  bxMb = alloc<double>(mb.size(), "box mass band");
+    seen[c] = 1;
+  }
+  bxKb = alloc<double>(kb.size(), "box stiffness class rows");
+  bxMb = alloc<double>(mb.size(), "box mass class rows");
   hip_check(hipMemcpy(bxKb, kb.data(), kb.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
   hip_check(hipMemcpy(bxMb, mb.data(), mb.size() * sizeof(double), hipMemcpyHostToDevice), "upload");
   Mat Ki(Pi, Pi), Mi(Pi, Pi);
@@ -1050,14 +1063,22 @@ void fep3m_ctx::box_apply(const double *v, double *y) {
 // interior equations (against the norm of their right side) is measured
 // with one more operator apply; above 1e-9 the call fails.  which: 0 the
 // forward solve, 1 the adjoint one (their statistics slots).
-void fep3m_ctx::box_solve(const double *rhs, double *sol, int which) {
+// zero_boundary: sol is zero on the boundary too (K_IB phi_B = 0, no apply).
+void fep3m_ctx::box_solve(const double *rhs, double *sol, int which, bool zero_boundary) {
   const int Pi = Pb - 2;
   const size_t nv = size_t(Pb) * Pb * Pb * nb, ni = size_t(Pi) * Pi * Pi * nb;
-  box_apply(sol, bxy);                                      // K phi_B
-  int K = launch_box_resid(stream, Pb, nb, true, false, rhs, bxy, partial);
-  launch_sum_partials(stream, K, partial, pcs.bn2, nb);     // |rhs_I - K_IB phi_B|^2
-  launch_box_axpby(stream, nv, 1.0, rhs, -1.0, bxy);        // r = rhs - K phi_B
-  launch_box_interior(stream, Pb, nb, true, bxy, bxt1);
+  int K;
+  if (zero_boundary) {
+    K = launch_box_resid(stream, Pb, nb, true, false, rhs, nullptr, partial);
+    launch_sum_partials(stream, K, partial, pcs.bn2, nb);   // |rhs_I|^2
+    launch_box_interior(stream, Pb, nb, true, rhs, bxt1);
+  } else {
+    box_apply(sol, bxy);                                      // K phi_B
+    K = launch_box_resid(stream, Pb, nb, true, false, rhs, bxy, partial);
+    launch_sum_partials(stream, K, partial, pcs.bn2, nb);     // |rhs_I - K_IB phi_B|^2
+    launch_box_axpby(stream, nv, 1.0, rhs, -1.0, bxy);        // r = rhs - K phi_B
+    launch_box_interior(stream, Pb, nb, true, bxy, bxt1);
+  }
   launch_axis_transform(stream, Pi, 0, nb, bxV, true, bxt1, bxt2);
   launch_axis_transform(stream, Pi, 1, nb, bxV, true, bxt2, bxt1);
   launch_axis_transform(stream, Pi, 2, nb, bxV, true, bxt1, bxt2);
@@ -1170,7 +1191,7 @@ void fep3m_ctx::reverse_box(double *F, double *dUdQ) {
   }
   const size_t nv = size_t(Pb) * Pb * Pb * nb;
   launch_box_fill(stream, nv, 0.0, bxlam);
-  box_solve(bxg, bxlam, 1);
+  box_solve(bxg, bxlam, 1, true);
   box_apply(bxlam, bxy);
   launch_box_axpby(stream, nv, 1.0, bxg, -1.0, bxy);   // mu = G - K lambda (read on the boundary nodes)
   stage_mark(FEP3M_PROF_ADJ_SOLVE, false);

@@ -268,10 +268,29 @@ __global__ __launch_bounds__(256) void k_box_mu_slots(int n, int nb, const doubl
   }
 }
 
+// Sum of four values over the 64 lanes of a wave (every lane gets the sum).
+__device__ __forceinline__ void wave_sum4(double &a, double &b, double &c, double &d) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+    c += __shfl_xor(c, o, 64);
+    d += __shfl_xor(d, o, 64);
+  }
+}
+
+// True for an element within nsr elements of no face (no boundary term).
+__device__ __forceinline__ bool far_from_faces(const int (&Ec)[3], int n, int nsr) {
+  return Ec[0] > nsr && Ec[1] > nsr && Ec[2] > nsr && n - 1 - Ec[0] > nsr && n - 1 - Ec[1] > nsr &&
+         n - 1 - Ec[2] > nsr;
+}
+
 // Boundary part of the per-charge gradients: for a sorted charge s near a
 // face, bp = sum_B mu_B (x_B - x_s) / r^3 and bq = sum_B mu_B / r over the
-// boundary nodes whose element's near block holds it; F += s2 Q bp / 2 and
-// dU/dQ -= inv_h bq / 2 (physical units), in caller order.
+// boundary nodes whose element's near block holds it (each visited once, as
+// in for_near_boundary); F += s2 Q bp / 2 and dU/dQ -= inv_h bq / 2 (physical
+// units), in caller order.  One wave per charge: the lanes split the nodes
+// of each face's range and the wave sums them.
 template <int PO>
 __global__ __launch_bounds__(256) void k_box_charge_bnd(int n, int nsr, int nb, int64_t N, const int *__restrict__ off,
                                                         double inv_h, BoxNodes nodes, const double *__restrict__ sg,
@@ -280,36 +299,67 @@ __global__ __launch_bounds__(256) void k_box_charge_bnd(int n, int nsr, int nb, 
                                                         double *__restrict__ dUdQ) {
   const int P = PO * n + 1;
   const size_t per = size_t(P) * P * P;
-  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < N; s += int64_t(gridDim.x) * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = int64_t(gridDim.x) * (blockDim.x >> 6);
+  for (int64_t s = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); s < N; s += waves) {
     const double xs[3] = {sg[s], sg[N + s], sg[2 * N + s]};
     int Ec[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) Ec[c] = min(int(floor(xs[c])), n - 1);
-    if (Ec[0] > nsr && Ec[1] > nsr && Ec[2] > nsr && n - 1 - Ec[0] > nsr && n - 1 - Ec[1] > nsr &&
-        n - 1 - Ec[2] > nsr)
-      continue;
+    if (far_from_faces(Ec, n, nsr)) continue;
     const double *muc = mu + size_t(cfg_of(off, nb, s)) * per;
-    double bx = 0.0, by = 0.0, bz = 0.0, bq = 0.0;
-    for_near_boundary<PO>(Ec, n, nsr, [&](const int (&g)[3], const int (&e)[3], const int (&k)[3]) {
-      const double mv = muc[(size_t(g[2]) * P + g[1]) * P + g[0]];
-      const double dx = e[0] + 0.5 + nodes.x[k[0]] - xs[0];
-      const double dy = e[1] + 0.5 + nodes.x[k[1]] - xs[1];
-      const double dz = e[2] + 0.5 + nodes.x[k[2]] - xs[2];
-      const double ri = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-      const double w = mv * ri * ri * ri;
-      bx += w * dx;
-      by += w * dy;
-      bz += w * dz;
-      bq += mv * ri;
-    });
-    const int i = perm[s];
-    const double q = sQ[s], c = 0.5 * inv_h * inv_h * q;
-    if (F) {
-      F[3 * size_t(i) + 0] += c * bx;
-      F[3 * size_t(i) + 1] += c * by;
-      F[3 * size_t(i) + 2] += c * bz;
+    int lo[3], hi[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int el = max(Ec[c] - nsr, 0), eh = min(Ec[c] + nsr, n - 1);
+      lo[c] = PO * el;
+      hi[c] = eh == n - 1 ? P - 1 : PO * eh + PO - 1;
     }
-    if (dUdQ) dUdQ[i] -= 0.5 * inv_h * bq;
+    double bx = 0.0, by = 0.0, bz = 0.0, bq = 0.0;
+    for (int face = 0; face < 6; ++face) {
+      const int ax = face >> 1, side = face & 1;
+      if (side == 0 ? Ec[ax] > nsr : (n - 1 - Ec[ax]) > nsr) continue;
+      int a0[3], len[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        int u0 = lo[c], u1 = hi[c];
+        if (c < ax) {   // nodes on the faces of a lower axis were visited there
+          u0 = max(u0, 1);
+          u1 = min(u1, P - 2);
+        }
+        if (c == ax) u0 = u1 = side ? P - 1 : 0;
+        a0[c] = u0;
+        len[c] = u1 - u0 + 1;
+      }
+      const int count = len[0] * len[1] * len[2];
+      for (int idx = lane; idx < count; idx += 64) {
+        const int g[3] = {a0[0] + idx % len[0], a0[1] + (idx / len[0]) % len[1], a0[2] + idx / (len[0] * len[1])};
+        double d[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int e = node_elem(g[c], PO, n);
+          d[c] = e + 0.5 + nodes.x[g[c] - PO * e] - xs[c];
+        }
+        const double mv = muc[(size_t(g[2]) * P + g[1]) * P + g[0]];
+        const double ri = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double w = mv * ri * ri * ri;
+        bx += w * d[0];
+        by += w * d[1];
+        bz += w * d[2];
+        bq += mv * ri;
+      }
+    }
+    wave_sum4(bx, by, bz, bq);
+    if (lane == 0) {
+      const int i = perm[s];
+      const double q = sQ[s], c = 0.5 * inv_h * inv_h * q;
+      if (F) {
+        F[3 * size_t(i) + 0] += c * bx;
+        F[3 * size_t(i) + 1] += c * by;
+        F[3 * size_t(i) + 2] += c * bz;
+      }
+      if (dUdQ) dUdQ[i] -= 0.5 * inv_h * bq;
+    }
   }
 }
 
@@ -463,23 +513,25 @@ __global__ __launch_bounds__(256) void k_box_h_slots(int n, int nb, const double
 // charge whose element lies in the near block of a boundary face's element,
 // sum over the face's Gauss points of Lw (-n / r^3 + 3 (n.d) d / r^5) and of
 // Lw (n.d) / r^3 (d = x_q - x_s); F -= Q s2 / 2 times the first, dU/dQ +=
-// inv_h / 2 times the second (physical units, caller order).
+// inv_h / 2 times the second (physical units, caller order).  One wave per
+// charge: the lanes split the (face element, Gauss point) pairs of each
+// near face and the wave sums them.
 template <int PO>
 __global__ __launch_bounds__(256) void k_box_flux_charge(int n, int nsr, int nb, int64_t N,
                                                          const int *__restrict__ off, double inv_h, BoxQuad qd,
                                                          const double *__restrict__ sg, const double *__restrict__ sQ,
                                                          const double *__restrict__ Lw, const int *__restrict__ perm,
                                                          double *__restrict__ F, double *__restrict__ dUdQ) {
-  constexpr int NQ = kBoxNQ;
+  constexpr int NQ = kBoxNQ, NQ2 = NQ * NQ;
   const size_t nf = size_t(6) * n * n;
-  for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < N; s += int64_t(gridDim.x) * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = int64_t(gridDim.x) * (blockDim.x >> 6);
+  for (int64_t s = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); s < N; s += waves) {
     const double xs[3] = {sg[s], sg[N + s], sg[2 * N + s]};
     int Ec[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) Ec[c] = min(int(floor(xs[c])), n - 1);
-    if (Ec[0] > nsr && Ec[1] > nsr && Ec[2] > nsr && n - 1 - Ec[0] > nsr && n - 1 - Ec[1] > nsr &&
-        n - 1 - Ec[2] > nsr)
-      continue;
+    if (far_from_faces(Ec, n, nsr)) continue;
     const int cfg = cfg_of(off, nb, s);
     double gx = 0.0, gy = 0.0, gz = 0.0, dq = 0.0;
     for (int a = 0; a < 3; ++a) {
@@ -487,40 +539,42 @@ __global__ __launch_bounds__(256) void k_box_flux_charge(int n, int nsr, int nb,
       for (int side = 0; side < 2; ++side) {
         if (side == 0 ? Ec[a] > nsr : (n - 1 - Ec[a]) > nsr) continue;
         const double sgn = side ? 1.0 : -1.0;
-        const double xa = side ? double(n) : 0.0;
+        const double da = (side ? double(n) : 0.0) - xs[a];   // normal offset, the same at every point
         const int i0 = max(Ec[t0] - nsr, 0), i1 = min(Ec[t0] + nsr, n - 1);
         const int j0 = max(Ec[t1] - nsr, 0), j1 = min(Ec[t1] + nsr, n - 1);
-        for (int j = j0; j <= j1; ++j)
-          for (int i = i0; i <= i1; ++i) {
-            const size_t face = size_t(a) * 2 * n * n + size_t(side) * n * n + size_t(j) * n + i;
-            const double *lw = Lw + (size_t(cfg) * nf + face) * NQ * NQ;
-            for (int qi = 0; qi < NQ; ++qi)
-              for (int qj = 0; qj < NQ; ++qj) {
-                double d[3];
-                d[a] = xa - xs[a];
-                d[t0] = i + 0.5 + qd.xq[qj] - xs[t0];
-                d[t1] = j + 0.5 + qd.xq[qi] - xs[t1];
-                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                const double ri = 1.0 / sqrt(r2), ri3 = ri * ri * ri;
-                const double w = lw[qi * NQ + qj];
-                const double nd = sgn * d[a];
-                const double c5 = 3.0 * nd * ri3 * ri * ri;
-                gx += w * (c5 * d[0] - (a == 0 ? sgn : 0.0) * ri3);
-                gy += w * (c5 * d[1] - (a == 1 ? sgn : 0.0) * ri3);
-                gz += w * (c5 * d[2] - (a == 2 ? sgn : 0.0) * ri3);
-                dq += w * nd * ri3;
-              }
-          }
+        const int ni = i1 - i0 + 1, count = ni * (j1 - j0 + 1) * NQ2;
+        const double *lwp = Lw + (size_t(cfg) * nf + size_t(a) * 2 * n * n + size_t(side) * n * n) * NQ2;
+        for (int idx = lane; idx < count; idx += 64) {
+          const int q = idx % NQ2, el = idx / NQ2;
+          const int i = i0 + el % ni, j = j0 + el / ni;
+          const int qi = q / NQ, qj = q % NQ;
+          double d[3];
+          d[a] = da;
+          d[t0] = i + 0.5 + qd.xq[qj] - xs[t0];
+          d[t1] = j + 0.5 + qd.xq[qi] - xs[t1];
+          const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+          const double ri = 1.0 / sqrt(r2), ri3 = ri * ri * ri;
+          const double w = lwp[(size_t(j) * n + i) * NQ2 + q];
+          const double nd = sgn * da;
+          const double c5 = 3.0 * nd * ri3 * ri * ri;
+          gx += w * (c5 * d[0] - (a == 0 ? sgn : 0.0) * ri3);
+          gy += w * (c5 * d[1] - (a == 1 ? sgn : 0.0) * ri3);
+          gz += w * (c5 * d[2] - (a == 2 ? sgn : 0.0) * ri3);
+          dq += w * nd * ri3;
+        }
       }
     }
-    const int idx = perm[s];
-    const double qv = sQ[s], c = 0.5 * inv_h * inv_h * qv;
-    if (F) {
-      F[3 * size_t(idx) + 0] -= c * gx;
-      F[3 * size_t(idx) + 1] -= c * gy;
-      F[3 * size_t(idx) + 2] -= c * gz;
+    wave_sum4(gx, gy, gz, dq);
+    if (lane == 0) {
+      const int idx = perm[s];
+      const double qv = sQ[s], c = 0.5 * inv_h * inv_h * qv;
+      if (F) {
+        F[3 * size_t(idx) + 0] -= c * gx;
+        F[3 * size_t(idx) + 1] -= c * gy;
+        F[3 * size_t(idx) + 2] -= c * gz;
+      }
+      if (dUdQ) dUdQ[idx] += 0.5 * inv_h * dq;
     }
-    if (dUdQ) dUdQ[idx] += 0.5 * inv_h * dq;
   }
 }
 
@@ -576,32 +630,41 @@ __global__ __launch_bounds__(256) void k_box_sub_mass(int P, int nb, double invV
   }
 }
 
-// One pass of the box operator K = Kx My Mz + Mx Ky Mz + Mx My Kz along one
+// Passes of the box operator K = Kx My Mz + Mx Ky Mz + Mx My Kz along one
 // axis of nb P^3 blocks.  The 1-D element-assembled matrices are banded (node
-// o couples to nodes o - HB .. o + HB, HB = p), stored row by row as
-// band[o (2 HB + 1) + d] = A(o, o - HB + d), zero outside the matrix:
-// out0 = Ba in0 (+ Bb in1 when in1 is given), and out1 = Bc in0 when out1 is
-// given.  A thread owns R consecutive outputs of one line and holds the
-// R + 2 HB inputs they need in registers; along x (R = 1) the lanes run over
-// the outputs themselves, along y and z over x, so every load and store of a
-// wave covers consecutive x.
+// o couples to nodes o - HB .. o + HB, HB = p) and, on the uniform mesh, row o
+// depends only on its class: o mod p inside, p for o = 0, p + 1 for
+// o = P - 1.  They come as compact tables of p + 2 class rows,
+// row[c (2 HB + 1) + d] = A(o, o - HB + d), staged in LDS.
+template <int HB>
+__device__ __forceinline__ int band_class(int o, int P) {
+  return o == 0 ? HB : (o == P - 1 ? HB + 1 : o % HB);
+}
+
+// Along y (axis 1) or z (axis 2): out0 = A in0 (+ B in1 when in1 is given),
+// out1 = C in0 when out1 is given.  A thread owns R consecutive outputs of
+// one line with the R + 2 HB inputs they need in registers; the lanes run
+// over x, so every load and store of a wave covers consecutive x.
 template <int HB, int R>
-__global__ __launch_bounds__(256) void k_box_band(int P, int axis, int nb, const double *__restrict__ Ba,
-                                                  const double *__restrict__ Bb, const double *__restrict__ Bc,
+__global__ __launch_bounds__(256) void k_box_band(int P, int axis, int nb, const double *__restrict__ Ac,
+                                                  const double *__restrict__ Bc, const double *__restrict__ Cc,
                                                   const double *__restrict__ in0, const double *__restrict__ in1,
                                                   double *__restrict__ out0, double *__restrict__ out1) {
-  constexpr int W = 2 * HB + 1, NV = R + 2 * HB;
+  constexpr int W = 2 * HB + 1, NV = R + 2 * HB, NC = HB + 2;
+  __shared__ double tab[3][NC * W];
+  for (int i = threadIdx.x; i < NC * W; i += blockDim.x) {
+    tab[0][i] = Ac[i];
+    tab[1][i] = Bc[i];
+    tab[2][i] = Cc[i];
+  }
+  __syncthreads();
   const size_t P2 = size_t(P) * P, per = P2 * P;
   const int nrun = (P + R - 1) / R;
   const size_t total = size_t(nb) * P2 * nrun;
   for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += size_t(gridDim.x) * blockDim.x) {
     size_t base, stride;
     int o0;
-    if (axis == 0) {            // t = (line, run), lanes along x
-      o0 = int(t % nrun) * R;
-      base = (t / nrun) * P;
-      stride = 1;
-    } else if (axis == 1) {     // t = ((sys, z), run, x)
+    if (axis == 1) {            // t = ((sys, z), run, x)
       const int x = int(t % P);
       const size_t r = t / P;
       o0 = int(r % nrun) * R;
@@ -626,20 +689,63 @@ __global__ __launch_bounds__(256) void k_box_band(int P, int axis, int nb, const
     for (int r = 0; r < R; ++r) {
       const int o = o0 + r;
       if (o >= P) break;
-      const double *ba = Ba + size_t(o) * W, *bb = Bb + size_t(o) * W, *bc = Bc + size_t(o) * W;
+      const int c = band_class<HB>(o, P) * W;
       double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-      for (int d = 0; d < W; ++d) s0 += ba[d] * v0[r + d];
+      for (int d = 0; d < W; ++d) s0 += tab[0][c + d] * v0[r + d];
       if (in1) {
 #pragma unroll
-        for (int d = 0; d < W; ++d) s0 += bb[d] * v1[r + d];
+        for (int d = 0; d < W; ++d) s0 += tab[1][c + d] * v1[r + d];
       }
       out0[base + size_t(o) * stride] = s0;
       if (out1) {
 #pragma unroll
-        for (int d = 0; d < W; ++d) s1 += bc[d] * v0[r + d];
+        for (int d = 0; d < W; ++d) s1 += tab[2][c + d] * v0[r + d];
         out1[base + size_t(o) * stride] = s1;
       }
+    }
+  }
+}
+
+// Along x: out = A in0 + B in1.  A block stages LPB whole x-lines of both
+// inputs in LDS (zero padded by HB on each side) and writes the lines'
+// outputs, one per thread, coalesced.
+constexpr int kBandLines = 4;
+
+template <int HB>
+__global__ __launch_bounds__(256) void k_box_band_x(int P, size_t lines, const double *__restrict__ Ac,
+                                                    const double *__restrict__ Bc, const double *__restrict__ in0,
+                                                    const double *__restrict__ in1, double *__restrict__ out) {
+  constexpr int W = 2 * HB + 1, NC = HB + 2, LPB = kBandLines;
+  extern __shared__ double sh[];
+  const int L = P + 2 * HB;
+  double *s0 = sh, *s1 = sh + LPB * L, *ta = s1 + LPB * L, *tb = ta + NC * W;
+  for (int i = threadIdx.x; i < NC * W; i += blockDim.x) {
+    ta[i] = Ac[i];
+    tb[i] = Bc[i];
+  }
+  for (size_t lb = size_t(blockIdx.x) * LPB; lb < lines; lb += size_t(gridDim.x) * LPB) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < LPB * L; i += blockDim.x) {
+      const int li = i / L, x = i % L - HB;
+      const size_t l = lb + li;
+      const bool ok = l < lines && x >= 0 && x < P;
+      s0[i] = ok ? in0[l * P + x] : 0.0;
+      s1[i] = ok ? in1[l * P + x] : 0.0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < LPB * P; i += blockDim.x) {
+      const int li = i / P, o = i % P;
+      const size_t l = lb + li;
+      if (l >= lines) break;
+      const int c = band_class<HB>(o, P) * W;
+      const double *v0 = s0 + li * L + o, *v1 = s1 + li * L + o;   // v[d] = in[o - HB + d]
+      double acc = 0.0;
+#pragma unroll
+      for (int d = 0; d < W; ++d) acc += ta[c + d] * v0[d];
+#pragma unroll
+      for (int d = 0; d < W; ++d) acc += tb[c + d] * v1[d];
+      out[l * P + o] = acc;
     }
   }
 }
@@ -651,27 +757,30 @@ inline int grid_of(size_t count) {
 }
 
 template <int HB>
-void box_apply_impl(hipStream_t s, int P, int nb, const double *Kb, const double *Mb, const double *v, double *t1,
+void box_apply_impl(hipStream_t s, int P, int nb, const double *Kc, const double *Mc, const double *v, double *t1,
                     double *t2, double *t3, double *t4, double *y) {
   constexpr int RYZ = 8;
   const size_t lines = size_t(nb) * P * P;
-  const int gyz = grid_of(lines * ((P + RYZ - 1) / RYZ)), gx = grid_of(lines * P);
+  const int gyz = grid_of(lines * ((P + RYZ - 1) / RYZ));
+  const int gx = int(std::min<size_t>((lines + kBandLines - 1) / kBandLines, 65536));
+  const size_t shx = (size_t(2) * kBandLines * (P + 2 * HB) + size_t(2) * (HB + 2) * (2 * HB + 1)) * sizeof(double);
   // t1 = Mz v, t3 = Kz v
-  hipLaunchKernelGGL((k_box_band<HB, RYZ>), dim3(gyz), dim3(256), 0, s, P, 2, nb, Mb, Mb, Kb, v, nullptr, t1, t3);
+  hipLaunchKernelGGL((k_box_band<HB, RYZ>), dim3(gyz), dim3(256), 0, s, P, 2, nb, Mc, Mc, Kc, v, nullptr, t1, t3);
   // t2 = Ky t1 + My t3, t4 = My t1
-  hipLaunchKernelGGL((k_box_band<HB, RYZ>), dim3(gyz), dim3(256), 0, s, P, 1, nb, Kb, Mb, Mb, t1, t3, t2, t4);
+  hipLaunchKernelGGL((k_box_band<HB, RYZ>), dim3(gyz), dim3(256), 0, s, P, 1, nb, Kc, Mc, Mc, t1, t3, t2, t4);
   // y = Kx t4 + Mx t2
-  hipLaunchKernelGGL((k_box_band<HB, 1>), dim3(gx), dim3(256), 0, s, P, 0, nb, Kb, Mb, Kb, t4, t2, y, nullptr);
+  hipLaunchKernelGGL((k_box_band_x<HB>), dim3(gx), dim3(256), shx, s, P, lines, Kc, Mc, t4, t2, y);
 }
 
 }  // namespace
 
-int launch_box_apply(hipStream_t s, int P, int nb, int p, const double *Kb, const double *Mb, const double *v,
+int launch_box_apply(hipStream_t s, int P, int nb, int p, const double *Kc, const double *Mc, const double *v,
                      double *t1, double *t2, double *t3, double *t4, double *y) {
+  if (P < 2 * p + 1) return -1;   // the class rows need two elements
   switch (p) {
-    case 4: box_apply_impl<4>(s, P, nb, Kb, Mb, v, t1, t2, t3, t4, y); return 0;
-    case 5: box_apply_impl<5>(s, P, nb, Kb, Mb, v, t1, t2, t3, t4, y); return 0;
-    case 6: box_apply_impl<6>(s, P, nb, Kb, Mb, v, t1, t2, t3, t4, y); return 0;
+    case 4: box_apply_impl<4>(s, P, nb, Kc, Mc, v, t1, t2, t3, t4, y); return 0;
+    case 5: box_apply_impl<5>(s, P, nb, Kc, Mc, v, t1, t2, t3, t4, y); return 0;
+    case 6: box_apply_impl<6>(s, P, nb, Kc, Mc, v, t1, t2, t3, t4, y); return 0;
     default: return -1;
   }
 }
@@ -736,7 +845,7 @@ int launch_box_assemble(hipStream_t s, int nb, int n, int p, const double *gE, d
 int launch_box_charge_bnd(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const int *off, double inv_h,
                           const BoxNodes &nodes, const double *sg, const double *sQ, const double *mu, const int *perm,
                           double *F, double *dUdQ) {
-  const int g = grid_of(size_t(N));
+  const int g = int(std::min<int64_t>((N + 3) / 4, 65535));   // one wave per charge, four per block
   switch (p) {
     case 4: hipLaunchKernelGGL(k_box_charge_bnd<4>, dim3(g), dim3(256), 0, s, n, nsr, nb, N, off, inv_h, nodes, sg, sQ, mu, perm, F, dUdQ); return 0;
     case 5: hipLaunchKernelGGL(k_box_charge_bnd<5>, dim3(g), dim3(256), 0, s, n, nsr, nb, N, off, inv_h, nodes, sg, sQ, mu, perm, F, dUdQ); return 0;
@@ -806,7 +915,7 @@ int launch_box_h_slots(hipStream_t s, int nb, int n, int p, const double *hF, do
 int launch_box_flux_charge(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const int *off, double inv_h,
                            const BoxQuad &qd, const double *sg, const double *sQ, const double *Lw, const int *perm,
                            double *F, double *dUdQ) {
-  const int g = grid_of(size_t(N));
+  const int g = int(std::min<int64_t>((N + 3) / 4, 65535));   // one wave per charge, four per block
   switch (p) {
     case 4: hipLaunchKernelGGL(k_box_flux_charge<4>, dim3(g), dim3(256), 0, s, n, nsr, nb, N, off, inv_h, qd, sg, sQ, Lw, perm, F, dUdQ); return 0;
     case 5: hipLaunchKernelGGL(k_box_flux_charge<5>, dim3(g), dim3(256), 0, s, n, nsr, nb, N, off, inv_h, qd, sg, sQ, Lw, perm, F, dUdQ); return 0;

@@ -138,23 +138,26 @@ __global__ __launch_bounds__(256) void k_fs_solve(int n, const double2 *__restri
 // out[line][o] = sum_k A(o, k) in[line][k], A(o, k) = V[k + o P] (TRANS:
 // V^T, the forward transform into modes) or V[o + k P] (back), V the
 // column-major eigenvector matrix.  A block covers 64 outputs x 64 lines,
-// k in chunks of 16 staged in LDS; each of its four waves owns 32 x 32 of
-// them as 2 x 2 float64 matrix-core tiles (16 x 16 x 4 steps: lane l
-// supplies row l % 16, k l / 16 of the left operand and k l / 16, column
-// l % 16 of the right one; accumulator value v of lane l is row l / 16 + 4 v,
-// column l % 16).  LR: the tile rows are lines and the columns outputs
-// (along x, where outputs are contiguous, so a store covers 16 consecutive
-// outputs); otherwise rows are outputs and columns lines (along y and z,
-// where consecutive lines are consecutive x).  The steps accumulate in k
-// order like fused multiply-adds, so every output equals a sequential loop
-// over k.
+// k in chunks of KC staged in LDS, the next chunk's operands fetched into
+// registers while the current one is multiplied; each of the four waves
+// owns 32 x 32 of the block as 2 x 2 float64 matrix-core tiles (16 x 16 x 4
+// steps: lane l supplies row l % 16, k l / 16 of the left operand and
+// k l / 16, column l % 16 of the right one; accumulator value v of lane l is
+// row l / 16 + 4 v, column l % 16).  LR: the tile rows are lines and the
+// columns outputs (along x, where outputs are contiguous, so a store covers
+// 16 consecutive outputs); otherwise rows are outputs and columns lines
+// (along y and z, where consecutive lines are consecutive x).  Line
+// addresses are formed once per block (no division in the k loop).  The
+// steps accumulate in k order like fused multiply-adds, so every output
+// equals a sequential loop over k.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <bool TRANS, bool LR>
 __global__ __launch_bounds__(256) void k_axis_transform(int P, int axis, int nsys, const double *__restrict__ V,
                                                         const double *__restrict__ in, double *__restrict__ out) {
-  __shared__ double As[16][65];   // [k][o]
-  __shared__ double Xs[16][65];   // [k][line]
+  constexpr int KC = 16, NR = KC * 64 / 256;   // operands per thread and chunk, for each matrix
+  __shared__ double As[KC][65];   // [k][o]
+  __shared__ double Xs[KC][65];   // [k][line]
   const size_t P2 = size_t(P) * P, per = P2 * P;
   const int otiles = (P + 63) / 64;
   const size_t lines = P2 * nsys;
@@ -164,36 +167,60 @@ __global__ __launch_bounds__(256) void k_axis_transform(int P, int axis, int nsy
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
   const int wo = (w & 1) * 32, wl = (w >> 1) * 32;
-  // element k of line l: line l = (system, a, b) with a, b the other two axes
-  auto addr = [&](size_t l, int k) -> size_t {
+  const size_t kstride = axis == 0 ? 1 : (axis == 1 ? size_t(P) : P2);
+  // address of element 0 of line l = (system, a, b), a, b the other two axes
+  auto line_base = [&](size_t l) -> size_t {
     const size_t sys = l / P2, r = l % P2;
-    const size_t a = r / P, b = r % P;   // axis 0: (z, y); axis 1: (z, x); axis 2: (y, x)
-    if (axis == 0) return sys * per + r * P + k;
-    if (axis == 1) return sys * per + a * P2 + size_t(k) * P + b;
-    return sys * per + size_t(k) * P2 + r;
+    if (axis == 0) return sys * per + r * P;
+    if (axis == 1) return sys * per + (r / P) * P2 + (r % P);
+    return sys * per + r;
+  };
+  // this thread's staging slots: (k in chunk, line or output) and the line
+  // or matrix addresses at k = 0
+  int xk[NR], ak[NR], ao[NR];
+  size_t xb[NR];
+  bool xok[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = tid + 256 * r;
+    int kk, ll;
+    if (axis == 0) { kk = i % KC; ll = i / KC; } else { ll = i % 64; kk = i / 64; }
+    xk[r] = kk;
+    xok[r] = l0 + ll < lines;
+    xb[r] = xok[r] ? line_base(l0 + ll) : 0;
+    int k2, oo;
+    if (TRANS) { k2 = i % KC; oo = i / KC; } else { oo = i % 64; k2 = i / 64; }
+    ak[r] = k2;
+    ao[r] = o0 + oo;
+  }
+  double xv[NR], av[NR];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int k = k0 + xk[r];
+      xv[r] = (k < P && xok[r]) ? in[xb[r] + size_t(k) * kstride] : 0.0;
+      const int ka = k0 + ak[r], o = ao[r];
+      av[r] = (ka < P && o < P) ? (TRANS ? V[ka + size_t(o) * P] : V[o + size_t(ka) * P]) : 0.0;
+    }
   };
   f64x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < P; k0 += 16) {
-    for (int i = tid; i < 16 * 64; i += 256) {
-      int kk, oo;
-      if (TRANS) { kk = i % 16; oo = i / 16; } else { oo = i % 64; kk = i / 64; }
-      const int k = k0 + kk, o = o0 + oo;
-      As[kk][oo] = (k < P && o < P) ? (TRANS ? V[k + size_t(o) * P] : V[o + size_t(k) * P]) : 0.0;
-    }
-    for (int i = tid; i < 16 * 64; i += 256) {
-      int kk, ll;
-      if (axis == 0) { kk = i % 16; ll = i / 16; } else { ll = i % 64; kk = i / 64; }
-      const int k = k0 + kk;
-      const size_t l = l0 + ll;
-      Xs[kk][ll] = (k < P && l < lines) ? in[addr(l, k)] : 0.0;
+  fetch(0);
+  for (int k0 = 0; k0 < P; k0 += KC) {
+    __syncthreads();   // the previous chunk is consumed
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int i = tid + 256 * r;
+      if (axis == 0) Xs[i % KC][i / KC] = xv[r]; else Xs[i / 64][i % 64] = xv[r];
+      if (TRANS) As[i % KC][i / KC] = av[r]; else As[i / 64][i % 64] = av[r];
     }
     __syncthreads();
+    if (k0 + KC < P) fetch(k0 + KC);
 #pragma unroll
-    for (int ks = 0; ks < 16; ks += 4) {
+    for (int ks = 0; ks < KC; ks += 4) {
       double xa[2], ob[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) xa[i] = Xs[ks + kq][wl + 16 * i + r16];
@@ -206,18 +233,36 @@ __global__ __launch_bounds__(256) void k_axis_transform(int P, int axis, int nsy
           acc[i][j] = LR ? __builtin_amdgcn_mfma_f64_16x16x4f64(xa[i], ob[j], acc[i][j], 0, 0, 0)
                          : __builtin_amdgcn_mfma_f64_16x16x4f64(ob[j], xa[i], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();
   }
+  if (LR) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const size_t l = l0 + wl + 16 * i + (LR ? kq + 4 * v : r16);
-        const int o = o0 + wo + 16 * j + (LR ? r16 : kq + 4 * v);
-        if (l < lines && o < P) out[addr(l, o)] = acc[i][j][v];
+        const size_t l = l0 + wl + 16 * i + kq + 4 * v;
+        if (l >= lines) continue;
+        const size_t b = line_base(l);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int o = o0 + wo + 16 * j + r16;
+          if (o < P) out[b + size_t(o) * kstride] = acc[i][j][v];
+        }
       }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const size_t l = l0 + wl + 16 * i + r16;
+      if (l >= lines) continue;
+      const size_t b = line_base(l);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int o = o0 + wo + 16 * j + kq + 4 * v;
+          if (o < P) out[b + size_t(o) * kstride] = acc[i][j][v];
+        }
+    }
+  }
 }
 
 inline int grid_of(size_t count) {

@@ -310,7 +310,29 @@ __global__ __launch_bounds__(AdjNearShape<NL * NL * NL>::THREADS) void k_adj_nea
       for (int dy = 0; dy < S1; ++dy) {
         const int hrow = hbase + (dz * HY + dy) * HX;
         const double *Trow = Tt + (size_t((dz * S1 + dy) * S1) * NM + m0) * NA + g * AG;
-        for (int dx = 0; dx < S1; ++dx) {
+        // offsets two at a time: both offsets' table values are requested
+        // before the first is used (S1 is odd: the last offset alone)
+        int dx = 0;
+        for (; dx + 1 < S1; dx += 2) {
+          const double *Td = Trow + size_t(dx) * NM * NA;
+          double tv[2][MC][AG], gv[2][MC];
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int mm = 0; mm < MC; ++mm) {
+              const bool ok = m0 + mm < NM;
+              gv[u][mm] = ok ? Gs[mm * NH + hrow + dx + u] : 0.0;
+#pragma unroll
+              for (int j = 0; j < AG; ++j) tv[u][mm][j] = ok ? Td[size_t(u) * NM * NA + mm * NA + j] : 0.0;
+            }
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int mm = 0; mm < MC; ++mm)
+#pragma unroll
+              for (int j = 0; j < AG; ++j) acc[j] += gv[u][mm] * tv[u][mm][j];
+        }
+        {
           const double *Td = Trow + size_t(dx) * NM * NA;
 #pragma unroll
           for (int mm = 0; mm < MC; ++mm) {

@@ -121,9 +121,10 @@ struct BoxQuad {
 int launch_box_bvals(hipStream_t s, int nb, int n, int nsr, int p, int64_t N, const BoxNodes &nodes, const int *start,
                      const double *sg, const double *sQ, const double *Wneg, double *phiB);
 // y = K v on every node of the box (K = Kx My Mz + Mx Ky Mz + Mx My Kz) by
-// three banded 1-D passes; Kb, Mb the 1-D matrices as P x (2 p + 1) bands,
-// t1..t4 work vectors of nb P^3
-int launch_box_apply(hipStream_t s, int P, int nb, int p, const double *Kb, const double *Mb, const double *v,
+// three banded 1-D passes; Kc, Mc the 1-D matrices as (p + 2) x (2 p + 1)
+// tables of class rows (row o: class o mod p inside, p for o = 0, p + 1 for
+// o = P - 1; entry d is column o - p + d); t1..t4 work vectors of nb P^3
+int launch_box_apply(hipStream_t s, int P, int nb, int p, const double *Kc, const double *Mc, const double *v,
                      double *t1, double *t2, double *t3, double *t4, double *y);
 // interior nodes of the box <-> contiguous (P - 2)^3 blocks
 void launch_box_interior(hipStream_t s, int P, int nb, bool to_interior, const double *src, double *dst);
