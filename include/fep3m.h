@@ -377,9 +377,15 @@ int fep3m_backward(fep3m_ctx *ctx, int64_t generation, double *F, double *dUdQ);
  * of `out_bytes` bytes (test and diagnostic use).  Stages:
  *   0 perm     int32  [N]        caller index of each sorted slot
  *   1 start    int32  [n^3 + 1]  first sorted slot of each element
- *   2 C        double [n^3 * 8]  element screen moments (element units)
- *   3 b        double [(p n)^3]  load vector after projection ([z][y][x])
- *   4 phi      double [(p n)^3]  mesh potential, zero mean (element units)
+ *   2 C        double [n^3 * (d + 1)^3]  element screen moments (element
+ *                                units; (d + 1)^3 = 8 for the default screen)
+ *   3 b        double [(p n)^3]  load vector after projection ([z][y][x]);
+ *                                in a box [(p n + 1)^3]: the volume load
+ *                                (insulating box: plus the surface load,
+ *                                projected on the compatible subspace)
+ *   4 phi      double [(p n)^3]  mesh potential, zero mean (element units);
+ *                                in a box [(p n + 1)^3] with its boundary
+ *                                values (grounded) or int phi = 0 (insulating)
  *   5 Phi_p    double [N]        near pair sum, caller order, physical units
  *   6 Phi_m    double [N]        mesh minus near-screen term, caller order
  *   7 T        double [8 * (2 n_sr + 1)^3 * (p + 1)^3]  tables (element units)

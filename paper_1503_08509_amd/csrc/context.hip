@@ -389,6 +389,14 @@ struct fep3m_ctx {
   void build_box();
   void box_apply(const double *v, double *y);
   void box_solve(const double *rhs, double *sol, int which, bool zero_boundary = false);
+  // the one-element q = 3 screen (p = 5, 2 moments per axis), which has
+  // kernels of its own for the near field and the moment adjoint
+  bool std_screen() const { return p == 5 && nl == 2 && span == 1; }
+  // moment adjoint in a box (near part from the deposit gE, mesh part from bxlam)
+  int box_adjoint_moments() {
+    return std_screen() ? launch_adj_moments(stream, nb, p, n, nsr, 1, gE, Tt, bxlam, gw, Aadj)
+                        : launch_adj_g(stream, nb, n, nsr, p, span, nl, 1, gE, Tt, bxlam, gw, Aadj);
+  }
   void box_solve_neumann(double *f, double *sol, int which);
   void forward_box(double *Phi, double *U, bool pair_forces);
   void reverse_box(double *F, double *dUdQ);
@@ -1124,7 +1132,9 @@ void fep3m_ctx::forward_box(double *Phi, double *U, bool pair_forces) {
   stage_mark(FEP3M_PROF_LOAD, false);
   stage_mark(FEP3M_PROF_ASSIGN, false);
   stage_mark(FEP3M_PROF_NEAR, true);
-  if (launch_psi_g(stream, nb, n, nsr, p, nl, 1, C, T, nullptr, Wel) != 0)
+  // the default screen (one element, q = 3) on the matrix cores, the others by the generic table sums
+  if ((std_screen() ? launch_psi<double>(stream, nb, n, nsr, p, 1, C, T, nullptr, Wel)
+                    : launch_psi_g(stream, nb, n, nsr, p, nl, 1, C, T, nullptr, Wel)) != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
   stage_mark(FEP3M_PROF_NEAR, false);
   pair_pass(pair_forces);
@@ -1178,7 +1188,7 @@ void fep3m_ctx::reverse_box(double *F, double *dUdQ) {
     stage_mark(FEP3M_PROF_ADJ_NEAR, true);
     if (launch_box_flux_adj(stream, nb, n, p, bxquad, bxlam, bxLw, bxhF) != 0 ||
         launch_box_h_slots(stream, nb, n, p, bxhF, gE) != 0 ||
-        launch_adj_g(stream, nb, n, nsr, p, span, nl, 1, gE, Tt, bxlam, gw, Aadj) != 0)
+        box_adjoint_moments() != 0)
       throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
     stage_mark(FEP3M_PROF_ADJ_NEAR, false);
     stage_mark(FEP3M_PROF_FORCES, true);
@@ -1199,7 +1209,7 @@ void fep3m_ctx::reverse_box(double *F, double *dUdQ) {
   // the boundary term of the moment adjoint as -mu in the deposit's
   // canonical slots (the deposit is rebuilt by every reverse pass)
   if (launch_box_mu_slots(stream, nb, n, p, bxy, gE) != 0 ||
-      launch_adj_g(stream, nb, n, nsr, p, span, nl, 1, gE, Tt, bxlam, gw, Aadj) != 0)
+      box_adjoint_moments() != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
   stage_mark(FEP3M_PROF_ADJ_NEAR, false);
   stage_mark(FEP3M_PROF_FORCES, true);
@@ -1423,8 +1433,8 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   } else if (generic) {
     ps = launch_psi_g(stream, nb, n, nsr, p, nl, 0, C, T, sol, Wel);
   } else
-    ps = mixed ? launch_psi<float>(stream, nb, n, nsr, p, C, Tf, sol, Welf)
-               : launch_psi<double>(stream, nb, n, nsr, p, C, T, sol, Wel);
+    ps = mixed ? launch_psi<float>(stream, nb, n, nsr, p, 0, C, Tf, sol, Welf)
+               : launch_psi<double>(stream, nb, n, nsr, p, 0, C, T, sol, Wel);
   if (ps != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
   stage_mark(FEP3M_PROF_NEAR, false);
   if (overlap) join.now();
@@ -1563,7 +1573,7 @@ void fep3m_ctx::reverse(double *F, double *dUdQ) {
   } else if (generic) {
     as = launch_adj_g(stream, nb, n, nsr, p, span, nl, 0, gE, Tt, lam, gw, Aadj);
   } else {
-    as = launch_adj_moments(stream, nb, p, n, nsr, gE, Tt, lam, gw, Aadj);
+    as = launch_adj_moments(stream, nb, p, n, nsr, 0, gE, Tt, lam, gw, Aadj);
   }
   if (as != 0) throw Status(FEP3M_ERR_UNSUPPORTED, "adjoint variant");
   stage_mark(FEP3M_PROF_ADJ_NEAR, false);
@@ -1993,7 +2003,8 @@ int fep3m_backward(fep3m_ctx *ctx, int64_t generation, double *F, double *dUdQ) 
 int64_t fep3m_stage_bytes(const fep3m_ctx *ctx, int32_t stage) {
   if (!ctx) return 0;
   const int64_t M = int64_t(ctx->n) * ctx->n * ctx->n * ctx->nb;
-  const int64_t P3 = int64_t(ctx->lv.empty() ? 0 : ctx->lv[0].ndof) * ctx->nb;
+  const int64_t P3 = ctx->box ? int64_t(ctx->Pb) * ctx->Pb * ctx->Pb * ctx->nb
+                              : int64_t(ctx->lv.empty() ? 0 : ctx->lv[0].ndof) * ctx->nb;
   switch (stage) {
     case 0: return ctx->N * 4;
     case 1: return (M + 1) * 4;
@@ -2018,8 +2029,8 @@ int fep3m_debug_stage(fep3m_ctx *ctx, int32_t stage, void *out, int64_t out_byte
       case 0: hip_check(hipMemcpyAsync(out, ctx->perm, need, k, ctx->stream), "stage"); break;
       case 1: hip_check(hipMemcpyAsync(out, ctx->start, need, k, ctx->stream), "stage"); break;
       case 2: hip_check(hipMemcpyAsync(out, ctx->C, need, k, ctx->stream), "stage"); break;
-      case 3: hip_check(hipMemcpyAsync(out, ctx->b, need, k, ctx->stream), "stage"); break;
-      case 4: hip_check(hipMemcpyAsync(out, ctx->sol, need, k, ctx->stream), "stage"); break;
+      case 3: hip_check(hipMemcpyAsync(out, ctx->box ? ctx->bxb : ctx->b, need, k, ctx->stream), "stage"); break;
+      case 4: hip_check(hipMemcpyAsync(out, ctx->box ? ctx->bxphi : ctx->sol, need, k, ctx->stream), "stage"); break;
       case 5: launch_unpermute(ctx->stream, ctx->N, 1.0 / ctx->h, ctx->perm, ctx->phip_s, static_cast<double *>(out)); break;
       case 6: launch_unpermute(ctx->stream, ctx->N, 1.0, ctx->perm, ctx->phim_s, static_cast<double *>(out)); break;
       case 7: hip_check(hipMemcpyAsync(out, ctx->T_host.data(), need, hipMemcpyHostToDevice, ctx->stream), "stage"); break;

@@ -152,7 +152,7 @@ __device__ __forceinline__ int wrap3(int v, int n) {
 }
 
 template <int NSR, int PO>
-__global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__restrict__ gE,
+__global__ __launch_bounds__(256, 2) void k_adj_moments(int n, int box, const double *__restrict__ gE,
                                                      const double *__restrict__ Tt, const double *__restrict__ lam,
                                                      const double *__restrict__ gw, double *__restrict__ Aout) {
   constexpr int BX = 8, BY = 4, BZ = 4;
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__r
   const int bx_n = (n + BX - 1) / BX, by_n = (n + BY - 1) / BY, bz_n = (n + BZ - 1) / BZ;
   {  // configuration of this brick
     const int cfg = blockIdx.x / (bx_n * by_n * bz_n);
-    const size_t M = size_t(n) * n * n, P = size_t(PO) * n;
+    const size_t M = size_t(n) * n * n, P = size_t(PO) * n + (box ? 1 : 0);
     gE += size_t(cfg) * M * NM;
     lam += size_t(cfg) * P * P * P;
     Aout += size_t(cfg) * M * 8;
@@ -203,9 +203,11 @@ __global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__r
       const int mm = i % MC, h = i / MC;
       const int m = ch * MC + mm;
       const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
-      const int ex = wrap3(x0 - NSR + hx, n), ey = wrap3(y0 - NSR + hy, n);
-      const int ez = wrap3(z0 + hz + Dz, n);
-      gpf[r] = (i < MC * SLAB && m < NM) ? gE[(size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NM + m] : 0.0;
+      const int sx = x0 - NSR + hx, sy = y0 - NSR + hy, sz = z0 + hz + Dz;
+      const bool in = sx >= 0 && sx < n && sy >= 0 && sy < n && sz >= 0 && sz < n;   // box: no source outside
+      const int ex = wrap3(sx, n), ey = wrap3(sy, n), ez = wrap3(sz, n);
+      gpf[r] = (i < MC * SLAB && m < NM && (in || !box)) ? gE[(size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NM + m]
+                                                        : 0.0;
     }
   };
   fetch(0);
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(256, 2) void k_adj_moments(int n, const double *__r
   if (tid >= BX * BY * BZ) return;
   const int ex = x0 + tid % BX, ey = y0 + (tid / BX) % BY, ez = z0 + tid / (BX * BY);
   if (ex >= n || ey >= n || ez >= n) return;
-  const int P = PO * n;
+  const int P = PO * n + (box ? 1 : 0);   // box: (PO n + 1)^3 nodes, no index leaves it
   double a1[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int mm = 0; mm < NM; ++mm) {
     const int mx = mm % Q1, my = (mm / Q1) % Q1, mz = mm / (Q1 * Q1);
@@ -423,15 +425,15 @@ int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, doubl
     default: return -1;
   }
 }
-int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, const double *gE, const double *Tt,
+int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, int box, const double *gE, const double *Tt,
                        const double *lam, const double *gw, double *A) {
   if (p != 5) return -1;
   const int bxn = (n + 7) / 8, byn = (n + 3) / 4, bzn = (n + 3) / 4;
   dim3 g(nb * bxn * byn * bzn);
   switch (nsr) {
-    case 1: hipLaunchKernelGGL((k_adj_moments<1, 5>), g, dim3(256), 0, s, n, gE, Tt, lam, gw, A); return 0;
-    case 2: hipLaunchKernelGGL((k_adj_moments<2, 5>), g, dim3(256), 0, s, n, gE, Tt, lam, gw, A); return 0;
-    case 3: hipLaunchKernelGGL((k_adj_moments<3, 5>), g, dim3(256), 0, s, n, gE, Tt, lam, gw, A); return 0;
+    case 1: hipLaunchKernelGGL((k_adj_moments<1, 5>), g, dim3(256), 0, s, n, box, gE, Tt, lam, gw, A); return 0;
+    case 2: hipLaunchKernelGGL((k_adj_moments<2, 5>), g, dim3(256), 0, s, n, box, gE, Tt, lam, gw, A); return 0;
+    case 3: hipLaunchKernelGGL((k_adj_moments<3, 5>), g, dim3(256), 0, s, n, box, gE, Tt, lam, gw, A); return 0;
     default: return -1;
   }
 }

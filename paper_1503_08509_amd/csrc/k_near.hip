@@ -59,7 +59,7 @@ constexpr int kPsiBZ = 8;    // brick depth in z
 constexpr int kPsiThreads = 64 * kPsiBZ;
 
 template <int NSR, int PO, class T>
-__global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, const double *__restrict__ C,
+__global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, int box, const double *__restrict__ C,
                                                         const T *__restrict__ Tab, const double *__restrict__ phi,
                                                         T *__restrict__ Wel) {
   using M = Mfma16<T>;
@@ -86,9 +86,9 @@ __global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, const double *__r
   const int lin = xcd_linear(blockIdx.x, gridDim.x);
   {  // configuration of this brick
     const int cfg = lin / per;
-    const size_t Mn = size_t(n) * n * n, P = size_t(PO) * n;
+    const size_t Mn = size_t(n) * n * n, P = size_t(PO) * n + (box ? 1 : 0);
     C += size_t(cfg) * Mn * 8;
-    phi += size_t(cfg) * P * P * P;
+    if (phi) phi += size_t(cfg) * P * P * P;
     Wel += size_t(cfg) * Mn * NM;
   }
   int b = lin % per;
@@ -122,8 +122,13 @@ __global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, const double *__r
     __syncthreads();
     for (int h = tid; h < SLAB; h += NTH) {
       const int hx = h % H, hy = (h / H) % H, lz = h / (H * H);
-      const int ex = (x0 - NSR + hx + 2 * n) % n, ey = (y0 - NSR + hy + 2 * n) % n;
-      const int ez = (z0 + lz - Dz + 2 * n) % n;
+      const int sx = x0 - NSR + hx, sy = y0 - NSR + hy, sz = z0 + lz - Dz;
+      if (box && (sx < 0 || sx >= n || sy < 0 || sy >= n || sz < 0 || sz >= n)) {   // no source outside the box
+#pragma unroll
+        for (int a = 0; a < 8; ++a) Cs[a * SLAB + h] = T(0);
+        continue;
+      }
+      const int ex = (sx + 2 * n) % n, ey = (sy + 2 * n) % n, ez = (sz + 2 * n) % n;
       const double *c = C + (size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * 8;
 #pragma unroll
       for (int a = 0; a < 8; ++a) Cs[a * SLAB + h] = T(c[a]);
@@ -186,7 +191,7 @@ __global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, const double *__r
         }
     }
   }
-  const int P = PO * n;
+  const int P = PO * n + (box ? 1 : 0);
 #pragma unroll
   for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
@@ -203,26 +208,27 @@ __global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, const double *__r
         const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
         const int gx = (PO * ex + mx) % P, gy = (PO * ey + my) % P, gz = (PO * ez + mz) % P;
         const double psi = kComp ? double(tot[ti][v]) - double(cmp[ti][v]) : double(acc[ti][v]);
-        Wel[E * NM + m] = T(phi[(size_t(gz) * P + gy) * P + gx] - psi);
+        Wel[E * NM + m] = T((phi ? phi[(size_t(gz) * P + gy) * P + gx] : 0.0) - psi);
       }
     }
 }
 
 template <class T>
-int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, const double *C, const T *Tab, const double *phi, T *Wel) {
+int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, int box, const double *C, const T *Tab, const double *phi,
+               T *Wel) {
   if (p != 5) return -1;
   const int bricks = (n + kPsiBS - 1) / kPsiBS, bricksz = (n + kPsiBZ - 1) / kPsiBZ;
   dim3 g(nb * bricks * bricks * bricksz);
   switch (nsr) {
-    case 1: hipLaunchKernelGGL((k_psi<1, 5, T>), g, dim3(kPsiThreads), 0, s, n, C, Tab, phi, Wel); return 0;
-    case 2: hipLaunchKernelGGL((k_psi<2, 5, T>), g, dim3(kPsiThreads), 0, s, n, C, Tab, phi, Wel); return 0;
-    case 3: hipLaunchKernelGGL((k_psi<3, 5, T>), g, dim3(kPsiThreads), 0, s, n, C, Tab, phi, Wel); return 0;
+    case 1: hipLaunchKernelGGL((k_psi<1, 5, T>), g, dim3(kPsiThreads), 0, s, n, box, C, Tab, phi, Wel); return 0;
+    case 2: hipLaunchKernelGGL((k_psi<2, 5, T>), g, dim3(kPsiThreads), 0, s, n, box, C, Tab, phi, Wel); return 0;
+    case 3: hipLaunchKernelGGL((k_psi<3, 5, T>), g, dim3(kPsiThreads), 0, s, n, box, C, Tab, phi, Wel); return 0;
     default: return -1;
   }
 }
-template int launch_psi<double>(hipStream_t, int, int, int, int, const double *, const double *, const double *,
+template int launch_psi<double>(hipStream_t, int, int, int, int, int, const double *, const double *, const double *,
                                 double *);
-template int launch_psi<float>(hipStream_t, int, int, int, int, const double *, const float *, const double *,
+template int launch_psi<float>(hipStream_t, int, int, int, int, int, const double *, const float *, const double *,
                                float *);
 
 }  // namespace fep3m

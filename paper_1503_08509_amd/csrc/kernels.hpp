@@ -77,7 +77,10 @@ int launch_deposit(hipStream_t s, int nb, int p, int n, int64_t N, const GllBasi
                    const double *sg, const double *sQ, double *gE);
 // returns the partial count K per configuration (-1: unsupported order)
 int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, double *G, double *partial);
-int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, const double *gE, const double *Tt,
+// box = 1: no source outside [0, n)^3 and lam on the (p n + 1)^3 nodes of the
+// box (launch_psi likewise: no source outside, phi on the box's nodes; a null
+// phi gives W = -Psi)
+int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, int box, const double *gE, const double *Tt,
                        const double *lam, const double *gw, double *A);
 // W of the forward pass in float64, or float32 on the mixed-precision path
 // (nl moments per axis; the screen families' (p, nl) pairs are instantiated)
@@ -164,7 +167,8 @@ int launch_box_flux_charge(hipStream_t s, int nb, int n, int nsr, int p, int64_t
 // near field (k_near.hip)
 // T = double, or float (float32 tables, compensated slab sums, float32 W)
 template <class T>
-int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, const double *C, const T *Tab, const double *phi, T *Wel);
+int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, int box, const double *C, const T *Tab, const double *phi,
+               T *Wel);
 
 // near field and its transpose by 3-D FFTs of the element lattice (k_fft.hip);
 // n a power of two in [8, 64], p = 5.  S: table spectrum at the

@@ -218,3 +218,62 @@ def test_insulated_box_forces_match_oracle(torch, N, n, q, seed):
         e = _rel(out["F"].cpu().numpy(), img)
         print(f"insulated box forces vs image sum: {e:.3e}")
         assert e < 1e-2
+
+
+def _box_fixture(kind):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"box_{kind}_uniform-1M-n64.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("kind", ["grounded", "insulated"])
+def test_box_full_size_against_oracle(torch, kind):
+    """The benchmark's box runs (uniform-1M-n64: 10^6 charges, 64^3 elements,
+    default options) against the oracle's box form: Phi on 512 sampled
+    charges and the mesh potential on 512 sampled nodes, stored by
+    tests/golden/make_box_fixtures.py; U through its definition
+    U = 1/2 sum Q Phi on the GPU's own Phi (pinned on the sample); forces
+    against central differences of the GPU energy on four charges (step
+    1e-6, the energy smooth inside an element)."""
+    import math
+    import workloads
+    ref = _box_fixture(kind)
+    x, Q = workloads.make(ref["workload"])
+    n = ref["n"]
+    bc = fp.BOUNDARY_GROUNDED if kind == "grounded" else fp.BOUNDARY_INSULATED
+    print(f"box full size: {kind} N={len(Q)} n={n}", flush=True)
+    ctx = fp.Context(1.0, len(Q), n, boundary=bc, solver=fp.SOLVER_FDM)
+    tx, tQ = torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda()
+    ctx.energy_forces(tx, tQ, Phi=True)                 # first call: tuning
+    out = ctx.energy_forces(tx, tQ, Phi=True)
+    torch.cuda.synchronize()
+    Phi = out["Phi"].cpu().numpy()
+    t = np.array(ref["targets"])
+    e_Phi = _rel(Phi[t], np.array(ref["Phi"]))
+    phi = ctx.stage("phi").cpu().numpy()
+    e_phi = float(np.abs(phi[np.array(ref["nodes"])] - np.array(ref["phi"])).max() / ref["phi_absmax"])
+    U = float(out["U"].item())
+    Uq = 0.5 * math.fsum(Q * Phi)
+    e_U = abs(U - Uq) / abs(Uq)
+    print(f"box full size {kind}: Phi {e_Phi:.2e} (sample), phi {e_phi:.2e} (nodes), U {e_U:.2e}", flush=True)
+    assert e_Phi < 1e-9 and e_phi < 1e-9 and e_U < 1e-12
+    F = out["F"].cpu().numpy()
+    hstep = 1e-6
+    g = x * n
+    frac = g - np.floor(g)
+    ok = np.nonzero(np.all((frac > 1e-4 + hstep * n) & (frac < 1 - 1e-4 - hstep * n), axis=1))[0]
+    pick = np.random.default_rng(4006).choice(ok, 4, replace=False)
+    fd = np.zeros((4, 3))
+    for r, i in enumerate(pick):
+        for k in range(3):
+            xp = tx.clone()
+            xp[i, k] += hstep
+            xm = tx.clone()
+            xm[i, k] -= hstep
+            fd[r, k] = -(float(ctx.energy(xp, tQ)[1].item()) - float(ctx.energy(xm, tQ)[1].item())) / (2 * hstep)
+    err = np.abs(fd - F[pick]).max()
+    scale = np.abs(F[pick]).max()
+    print(f"box full size {kind}: forces against central differences {err / scale:.2e}", flush=True)
+    assert err < 1e-5 * scale
