@@ -550,6 +550,9 @@ def main():
         op["flop_peak"] = PEAK_FP64_TFLOPS   # the PCG operator is float64 in both precisions
         op["flop_frac"] = tf / op["flop_peak"]
         op["flop_unit"] = "TFLOP/s (98 FLOP per DOF)"
+    if not mixed:   # counter-measured HBM bytes per launch where a current summary exists
+        for k in kernels:
+            kernels[k]["traffic"] = traffic_for(k, r["workload"])
     dominant = max(kernels, key=lambda k: kernels[k]["avg_launch_ms"] * kernels[k]["launches_per_step"])
     roof = dict(kernels[dominant])
     roof["kernel"] = dominant
