@@ -212,9 +212,8 @@ __global__ __launch_bounds__(256) void k_moments(int n, int MT, int64_t N, const
     const int El = E % M;
     const int ex = El % n, ey = (El / n) % n, ez = El / (n * n);
     double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int s = start[E]; s < start[E + 1]; ++s) {
-      const double q = sQ[s];
-      const double ux = sg[s] - ex - 0.5, uy = sg[N + s] - ey - 0.5, uz = sg[2 * N + s] - ez - 0.5;
+    auto add = [&](double q, double gx, double gy, double gz) {
+      const double ux = gx - ex - 0.5, uy = gy - ey - 0.5, uz = gz - ez - 0.5;
       c[0] += q;
       c[1] += q * ux;
       c[2] += q * uy;
@@ -223,7 +222,25 @@ __global__ __launch_bounds__(256) void k_moments(int n, int MT, int64_t N, const
       c[5] += q * ux * uz;
       c[6] += q * uy * uz;
       c[7] += q * ux * uy * uz;
+    };
+    // four charges' loads in flight before they are summed (a heavy
+    // element's chain of dependent loads sets the kernel's time); the sum
+    // runs over the charges in order either way
+    const int s1 = start[E + 1];
+    int s = start[E];
+    for (; s + 4 <= s1; s += 4) {
+      double q[4], gx[4], gy[4], gz[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        q[u] = sQ[s + u];
+        gx[u] = sg[s + u];
+        gy[u] = sg[N + s + u];
+        gz[u] = sg[2 * N + s + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) add(q[u], gx[u], gy[u], gz[u]);
     }
+    for (; s < s1; ++s) add(sQ[s], sg[s], sg[N + s], sg[2 * N + s]);
     for (int a = 0; a < 8; ++a) C[size_t(E) * 8 + a] = c[a];
   }
 }

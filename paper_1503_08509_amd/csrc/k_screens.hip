@@ -52,14 +52,30 @@ __global__ __launch_bounds__(256) void k_moments_g(int n, int MT, int64_t N, con
     const int El = E % M;
     const int ex = El % n, ey = (El / n) % n, ez = El / (n * n);
     double c = 0.0;
-    for (int s = start[E]; s < start[E + 1]; ++s) {
-      const double ux = sg[s] - ex - 0.5, uy = sg[N + s] - ey - 0.5, uz = sg[2 * N + s] - ez - 0.5;
-      double m = sQ[s];
+    auto add = [&](double q, double gx, double gy, double gz) {
+      const double ux = gx - ex - 0.5, uy = gy - ey - 0.5, uz = gz - ez - 0.5;
+      double m = q;
       for (int k = 0; k < ax; ++k) m *= ux;
       for (int k = 0; k < ay; ++k) m *= uy;
       for (int k = 0; k < az; ++k) m *= uz;
       c += m;
+    };
+    // four charges' loads in flight before they are summed, in order
+    const int s1 = start[E + 1];
+    int s = start[E];
+    for (; s + 4 <= s1; s += 4) {
+      double q[4], gx[4], gy[4], gz[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        q[u] = sQ[s + u];
+        gx[u] = sg[s + u];
+        gy[u] = sg[N + s + u];
+        gz[u] = sg[2 * N + s + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) add(q[u], gx[u], gy[u], gz[u]);
     }
+    for (; s < s1; ++s) add(sQ[s], sg[s], sg[N + s], sg[2 * N + s]);
     C[t] = c;
   }
 }
