@@ -168,8 +168,12 @@ struct PsiShape {
   static constexpr int NM = (PO + 1) * (PO + 1) * (PO + 1), NA = NL * NL * NL;
   static constexpr int MG = NM == 64 ? 16 : (NM == 125 ? 25 : (NM == 216 ? 27 : 49));
   static constexpr int NG = NM / MG;
-  static constexpr int BX = 4, BY = 4, BZ = 4, TB = BX * BY * BZ;
-  static constexpr int AC = NA < 8 ? NA : 8;      // moments per LDS stage
+  // TT targets per thread, 4 elements apart along x: with many moments the
+  // table values (read once per thread) dominate, and a second target
+  // halves their reads per result
+  static constexpr int TT = (NA >= 27 && MG <= 27) ? 2 : 1;
+  static constexpr int BX = 4 * TT, BY = 4, BZ = 4, TB = 64;   // TB threads per node group: one wave
+  static constexpr int AC = NA < 8 ? NA : (TT == 2 ? 4 : 8);   // moments per LDS stage
   static constexpr int HX = BX + 6, HY = BY + 6, HZ = BZ + 6, NH = HX * HY * HZ;
   static constexpr int THREADS = NG * TB;
   static_assert(NG * MG == NM && THREADS <= 1024, "near-field brick shape");
@@ -195,16 +199,19 @@ __global__ __launch_bounds__((PsiShape<PO, NL>::THREADS)) void k_psi_g(int n, in
   const double *phi = phiall ? phiall + size_t(cfg) * P * P * P : nullptr;
   double *W = Wall + size_t(cfg) * M * NM;
   const int S1 = 2 * nsr + 1, ND = S1 * S1 * S1;
+  constexpr int TT = S::TT;
   const int tid = threadIdx.x, t = tid % S::TB;
   const int g = __builtin_amdgcn_readfirstlane(tid / S::TB);
-  const int tx = t % S::BX, ty = (t / S::BX) % S::BY, tz = t / (S::BX * S::BY);
+  const int tx = t % 4, ty = (t / 4) % S::BY, tz = t / (4 * S::BY);   // targets tx + 4 u, u < TT
   const int hx0 = bx * S::BX - nsr, hy0 = by * S::BY - nsr, hz0 = bz * S::BZ - nsr;
   const int LX = S::BX + 2 * nsr, LY = S::BY + 2 * nsr, LZ = S::BZ + 2 * nsr;   // halo in use
   // the source of offset D sits at halo (t + nsr - D): index hbase - (D + nsr) . (1, HX, HX HY)
   const int hbase = ((tz + 2 * nsr) * HY + ty + 2 * nsr) * HX + tx + 2 * nsr;
-  double acc[MG];
+  double acc[TT][MG];
 #pragma unroll
-  for (int j = 0; j < MG; ++j) acc[j] = 0.0;
+  for (int u = 0; u < TT; ++u)
+#pragma unroll
+    for (int j = 0; j < MG; ++j) acc[u][j] = 0.0;
   for (int a0 = 0; a0 < NA; a0 += AC) {
     __syncthreads();
     for (int i = tid; i < AC * LX * LY * LZ; i += S::THREADS) {
@@ -231,28 +238,37 @@ __global__ __launch_bounds__((PsiShape<PO, NL>::THREADS)) void k_psi_g(int n, in
 #pragma unroll
           for (int aa = 0; aa < AC; ++aa) {
             if (a0 + aa >= NA) break;
-            const double cv = Cs[aa * NH + hrow - dx];
+            double cv[TT];
+#pragma unroll
+            for (int u = 0; u < TT; ++u) cv[u] = Cs[aa * NH + hrow - dx + 4 * u];
             const double *Ta = Td + size_t(aa) * ND * NM;
 #pragma unroll
-            for (int j = 0; j < MG; ++j) acc[j] += cv * Ta[j];
+            for (int j = 0; j < MG; ++j) {
+              const double tv = Ta[j];
+#pragma unroll
+              for (int u = 0; u < TT; ++u) acc[u][j] += cv[u] * tv;
+            }
           }
         }
       }
   }
-  const int ex = bx * S::BX + tx, ey = by * S::BY + ty, ez = bz * S::BZ + tz;
-  if (ex >= n || ey >= n || ez >= n) return;
-  const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
-  double *dst = W + E * NM + g * MG;
 #pragma unroll
-  for (int j = 0; j < MG; ++j) {
-    const int m = g * MG + j;
-    const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
-    double ph = 0.0;
-    if (phi) {
-      const int gx = wrapn(PO * ex + mx, P), gy = wrapn(PO * ey + my, P), gz = wrapn(PO * ez + mz, P);
-      ph = phi[(size_t(gz) * P + gy) * P + gx];
+  for (int u = 0; u < TT; ++u) {
+    const int ex = bx * S::BX + tx + 4 * u, ey = by * S::BY + ty, ez = bz * S::BZ + tz;
+    if (ex >= n || ey >= n || ez >= n) continue;
+    const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
+    double *dst = W + E * NM + g * MG;
+#pragma unroll
+    for (int j = 0; j < MG; ++j) {
+      const int m = g * MG + j;
+      const int mx = m % Q1, my = (m / Q1) % Q1, mz = m / (Q1 * Q1);
+      double ph = 0.0;
+      if (phi) {
+        const int gx = wrapn(PO * ex + mx, P), gy = wrapn(PO * ey + my, P), gz = wrapn(PO * ez + mz, P);
+        ph = phi[(size_t(gz) * P + gy) * P + gx];
+      }
+      dst[j] = ph - acc[u][j];
     }
-    dst[j] = ph - acc[j];
   }
 }
 
@@ -270,13 +286,16 @@ template <int NA>
 struct AdjNearShape {
   static constexpr int AG = NA == 27 ? 9 : (NA == 125 ? 25 : (NA >= 8 ? 8 : NA));
   static constexpr int NG = NA / AG;
-  static constexpr int TB = NG == 1 ? 256 : 64;   // targets per block (a multiple of the wave)
-  static constexpr int BX = TB == 256 ? 8 : 4, BY = BX, BZ = 4;
+  static constexpr int TB = NG == 1 ? 256 : 64;   // threads per moment group (a multiple of the wave)
+  // targets per thread, XT elements apart along x: with several groups each
+  // thread takes two targets, halving the table reads per result
+  static constexpr int TPT = NG == 1 ? 1 : 2;
+  static constexpr int BX = 8, BY = TB == 256 ? 8 : 4, BZ = 4, XT = BX / TPT;
   static constexpr int MC = 2;                    // deposit nodes per LDS stage
   static constexpr int HX = BX + 6, HY = BY + 6, HZ = BZ + 6;
   static constexpr int NH = HX * HY * HZ;
   static constexpr int THREADS = NG * TB;
-  static_assert(NG * AG == NA && BX * BY * BZ == TB && TB % 64 == 0, "adjoint brick shape");
+  static_assert(NG * AG == NA && BX * BY * BZ == TB * TPT && TB % 64 == 0, "adjoint brick shape");
 };
 
 template <int PO, int NL>
@@ -298,13 +317,16 @@ __global__ __launch_bounds__(AdjNearShape<NL * NL * NL>::THREADS) void k_adj_nea
   const int S1 = 2 * nsr + 1, ND = S1 * S1 * S1;
   const int tid = threadIdx.x, t = tid % TB;
   const int g = __builtin_amdgcn_readfirstlane(tid / TB);
-  const int tx = t % S::BX, ty = (t / S::BX) % S::BY, tz = t / (S::BX * S::BY);
+  constexpr int TPT = S::TPT, XT = S::XT;
+  const int tx = t % XT, ty = (t / XT) % S::BY, tz = t / (XT * S::BY);   // targets tx + XT u, u < TPT
   const int hx0 = bx * S::BX - nsr, hy0 = by * S::BY - nsr, hz0 = bz * S::BZ - nsr;
   const int LX = S::BX + 2 * nsr, LY = S::BY + 2 * nsr, LZ = S::BZ + 2 * nsr;   // halo in use
   const int hbase = (tz * HY + ty) * HX + tx;   // halo index of the source at D = (-nsr, -nsr, -nsr)
-  double acc[AG];
+  double acc[TPT][AG];
 #pragma unroll
-  for (int j = 0; j < AG; ++j) acc[j] = 0.0;
+  for (int u = 0; u < TPT; ++u)
+#pragma unroll
+    for (int j = 0; j < AG; ++j) acc[u][j] = 0.0;
   for (int m0 = 0; m0 < NM; m0 += MC) {
     __syncthreads();
     for (int i = tid; i < MC * LX * LY * LZ; i += S::THREADS) {
@@ -326,6 +348,25 @@ __global__ __launch_bounds__(AdjNearShape<NL * NL * NL>::THREADS) void k_adj_nea
       for (int dy = 0; dy < S1; ++dy) {
         const int hrow = hbase + (dz * HY + dy) * HX;
         const double *Trow = Tt + (size_t((dz * S1 + dy) * S1) * NM + m0) * NA + g * AG;
+        if constexpr (TPT > 1) {
+          for (int dx = 0; dx < S1; ++dx) {
+            const double *Td = Trow + size_t(dx) * NM * NA;
+#pragma unroll
+            for (int mm = 0; mm < MC; ++mm) {
+              if (m0 + mm >= NM) break;
+              double gv[TPT];
+#pragma unroll
+              for (int u = 0; u < TPT; ++u) gv[u] = Gs[mm * NH + hrow + dx + XT * u];
+#pragma unroll
+              for (int j = 0; j < AG; ++j) {
+                const double tv = Td[mm * NA + j];
+#pragma unroll
+                for (int u = 0; u < TPT; ++u) acc[u][j] += gv[u] * tv;
+              }
+            }
+          }
+          continue;
+        }
         // offsets two at a time: both offsets' table values are requested
         // before the first is used (S1 is odd: the last offset alone)
         int dx = 0;
@@ -346,7 +387,7 @@ __global__ __launch_bounds__(AdjNearShape<NL * NL * NL>::THREADS) void k_adj_nea
 #pragma unroll
             for (int mm = 0; mm < MC; ++mm)
 #pragma unroll
-              for (int j = 0; j < AG; ++j) acc[j] += gv[u][mm] * tv[u][mm][j];
+              for (int j = 0; j < AG; ++j) acc[0][j] += gv[u][mm] * tv[u][mm][j];
         }
         {
           const double *Td = Trow + size_t(dx) * NM * NA;
@@ -355,16 +396,19 @@ __global__ __launch_bounds__(AdjNearShape<NL * NL * NL>::THREADS) void k_adj_nea
             if (m0 + mm >= NM) break;
             const double gv = Gs[mm * NH + hrow + dx];
 #pragma unroll
-            for (int j = 0; j < AG; ++j) acc[j] += gv * Td[mm * NA + j];
+            for (int j = 0; j < AG; ++j) acc[0][j] += gv * Td[mm * NA + j];
           }
         }
       }
   }
-  const int ex = bx * S::BX + tx, ey = by * S::BY + ty, ez = bz * S::BZ + tz;
-  if (ex >= n || ey >= n || ez >= n) return;
-  double *dst = A + (size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NA + g * AG;
 #pragma unroll
-  for (int j = 0; j < AG; ++j) dst[j] = -acc[j];
+  for (int u = 0; u < TPT; ++u) {
+    const int ex = bx * S::BX + tx + XT * u, ey = by * S::BY + ty, ez = bz * S::BZ + tz;
+    if (ex >= n || ey >= n || ez >= n) continue;
+    double *dst = A + (size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NA + g * AG;
+#pragma unroll
+    for (int j = 0; j < AG; ++j) dst[j] = -acc[u][j];
+  }
 }
 
 // Mesh part of the moment adjoint: A[E][a] += 4 pi sum over the support's
