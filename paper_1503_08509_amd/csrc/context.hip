@@ -1132,9 +1132,9 @@ void fep3m_ctx::forward_box(double *Phi, double *U, bool pair_forces) {
   stage_mark(FEP3M_PROF_LOAD, false);
   stage_mark(FEP3M_PROF_ASSIGN, false);
   stage_mark(FEP3M_PROF_NEAR, true);
-  // the default screen (one element, q = 3) on the matrix cores, the others by the generic table sums
-  if ((std_screen() ? launch_psi<double>(stream, nb, n, nsr, p, 1, C, T, nullptr, Wel)
-                    : launch_psi_g(stream, nb, n, nsr, p, nl, 1, C, T, nullptr, Wel)) != 0)
+  // on the matrix cores where the screen family has a kernel there, else by the generic table sums
+  if (launch_psi_mfma_g(stream, nb, n, nsr, p, nl, 1, C, T, nullptr, Wel) != 0 &&
+      launch_psi_g(stream, nb, n, nsr, p, nl, 1, C, T, nullptr, Wel) != 0)
     throw Status(FEP3M_ERR_UNSUPPORTED, "near field variant");
   stage_mark(FEP3M_PROF_NEAR, false);
   pair_pass(pair_forces);
@@ -1430,8 +1430,9 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
                  : launch_psi_fft_finish<double>(stream, nb, n, p, twd, sol, zpsi, Wel);
     adj_near_ready = pair_forces;
     prof.near_both = pair_forces;
-  } else if (generic) {
-    ps = launch_psi_g(stream, nb, n, nsr, p, nl, 0, C, T, sol, Wel);
+  } else if (generic) {   // the matrix cores where the family has a kernel there, else the table sums
+    ps = launch_psi_mfma_g(stream, nb, n, nsr, p, nl, 0, C, T, sol, Wel);
+    if (ps != 0) ps = launch_psi_g(stream, nb, n, nsr, p, nl, 0, C, T, sol, Wel);
   } else
     ps = mixed ? launch_psi<float>(stream, nb, n, nsr, p, 0, C, Tf, sol, Welf)
                : launch_psi<double>(stream, nb, n, nsr, p, 0, C, T, sol, Wel);

@@ -58,7 +58,12 @@ constexpr int kPsiBS = 4;    // brick edge in x and y (elements)
 constexpr int kPsiBZ = 8;    // brick depth in z
 constexpr int kPsiThreads = 64 * kPsiBZ;
 
-template <int NSR, int PO, class T>
+// NA moments per element (8 for the default screen; the other screen
+// families: 1, 8, 27 or 64), taken 8 at a time: for each chunk of 8 the
+// offsets are walked again (the missing moments of the last chunk read as
+// zero), with the chunk's moments of each source slab and its tables of
+// each offset staged as for 8.
+template <int NSR, int PO, class T, int NA = 8>
 __global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, int box, const double *__restrict__ C,
                                                         const T *__restrict__ Tab, const double *__restrict__ phi,
                                                         T *__restrict__ Wel) {
@@ -74,7 +79,9 @@ __global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, int box, const do
   constexpr int NT = (NM + 15) / 16;          // 16-node tiles
   constexpr int NTW = NT / 2;                 // node tiles per wave
   constexpr int NMP = NT * 16;                // padded table row
-  constexpr int TV = 8 * NM;                  // table values per offset
+  constexpr int TV = 8 * NM;                  // table values per offset and chunk of 8 moments
+  constexpr int NCH = (NA + 7) / 8;           // moment chunks
+  constexpr int NST = NCH * ND;               // table stages: (chunk, offset)
   constexpr int TPF = (TV + NTH - 1) / NTH;   // prefetch registers per thread
   constexpr int SLAB = BZ * H * H;            // one z-slab of the halo
   static_assert(NT % 2 == 0 && BZ % 2 == 0, "wave tiling");
@@ -87,7 +94,7 @@ __global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, int box, const do
   {  // configuration of this brick
     const int cfg = lin / per;
     const size_t Mn = size_t(n) * n * n, P = size_t(PO) * n + (box ? 1 : 0);
-    C += size_t(cfg) * Mn * 8;
+    C += size_t(cfg) * Mn * NA;
     if (phi) phi += size_t(cfg) * P * P * P;
     Wel += size_t(cfg) * Mn * NM;
   }
@@ -111,14 +118,18 @@ __global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, int box, const do
   }
   for (int i = tid; i < 2 * 8 * NMP; i += NTH) (&Ts[0][0])[i] = T(0);   // padding stays zero
   __syncthreads();
-  for (int i = tid; i < TV; i += NTH) {   // table values of offset 0 into buffer 0
-    const int a = i / NM, m = i % NM;
-    Ts[0][a * NMP + m] = Tab[(size_t(a) * ND + 0) * NM + m];
-  }
-  int iD = 0;
+  // table value i of stage st (chunk st / ND, offset st % ND); zero past the last moment
+  auto table = [&](int st, int i) -> T {
+    const int ch = NCH == 1 ? 0 : st / ND, iD = NCH == 1 ? st : st - ch * ND;
+    const int a = ch * 8 + i / NM, m = i % NM;
+    return (NA % 8 == 0 || a < NA) ? Tab[(size_t(a) * ND + iD) * NM + m] : T(0);
+  };
+  for (int i = tid; i < TV; i += NTH) Ts[0][(i / NM) * NMP + i % NM] = table(0, i);   // stage 0 into buffer 0
+  int st = 0;
+  for (int a0 = 0; a0 < NA; a0 += 8)
   for (int Dz = -NSR; Dz <= NSR; ++Dz) {
-    // stage the moments of the source slab for this D_z: target layer lz
-    // reads halo layer lz - Dz + NSR
+    // stage moments a0 .. a0 + 7 of the source slab for this D_z: target
+    // layer lz reads halo layer lz - Dz + NSR
     __syncthreads();
     for (int h = tid; h < SLAB; h += NTH) {
       const int hx = h % H, hy = (h / H) % H, lz = h / (H * H);
@@ -129,34 +140,32 @@ __global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, int box, const do
         continue;
       }
       const int ex = (sx + 2 * n) % n, ey = (sy + 2 * n) % n, ez = (sz + 2 * n) % n;
-      const double *c = C + (size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * 8;
+      const double *c = C + (size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NA + a0;
 #pragma unroll
-      for (int a = 0; a < 8; ++a) Cs[a * SLAB + h] = T(c[a]);
+      for (int a = 0; a < 8; ++a) Cs[a * SLAB + h] = (NA % 8 == 0 || a0 + a < NA) ? T(c[a]) : T(0);
     }
     __syncthreads();
-    for (int Dyx = 0; Dyx < S * S; ++Dyx, ++iD) {
+    for (int Dyx = 0; Dyx < S * S; ++Dyx, ++st) {
       const int Dx = Dyx % S - NSR, Dy = Dyx / S - NSR;
-      const int cur = iD & 1;
-      // prefetch the next offset's tables into registers
+      const int cur = st & 1;
+      // prefetch the next stage's tables into registers
       T tp[TPF];
-      const bool more = iD + 1 < ND;
+      const bool more = st + 1 < NST;
       if (more) {
 #pragma unroll
         for (int q = 0; q < TPF; ++q) {
           const int i = tid + NTH * q;
-          if (i < TV) {
-            const int a = i / NM, m = i % NM;
-            tp[q] = Tab[(size_t(a) * ND + iD + 1) * NM + m];
-          }
+          if (i < TV) tp[q] = table(st + 1, i);
         }
       }
       const T *tb = Ts[cur];
       const int cb = ((2 * mh) * H + (aly - Dy + NSR)) * H + (alx - Dx + NSR);
 #pragma unroll
-      for (int a0 = 0; a0 < 8; a0 += 4) {
-        const T av0 = Cs[(a0 + kq) * SLAB + cb];           // layer 2 mh
-        const T av1 = Cs[(a0 + kq) * SLAB + cb + H * H];   // layer 2 mh + 1
-        const T *brow = tb + (a0 + kq) * NMP + 16 * NTW * nh + r;
+      for (int k0 = 0; k0 < 8; k0 += 4) {
+        if (NA < 8 && k0 >= NA) break;                     // fewer than 8 moments: the zero half is skipped
+        const T av0 = Cs[(k0 + kq) * SLAB + cb];           // layer 2 mh
+        const T av1 = Cs[(k0 + kq) * SLAB + cb + H * H];   // layer 2 mh + 1
+        const T *brow = tb + (k0 + kq) * NMP + 16 * NTW * nh + r;
         T bv[NTW];
 #pragma unroll
         for (int t = 0; t < NTW; ++t) bv[t] = brow[16 * t];
@@ -228,6 +237,30 @@ int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, int box, const doub
 }
 template int launch_psi<double>(hipStream_t, int, int, int, int, int, const double *, const double *, const double *,
                                 double *);
+
+template <int PO, int NA>
+static int psi_mfma_nsr(hipStream_t s, dim3 g, int n, int nsr, int box, const double *C, const double *Tab,
+                        const double *phi, double *Wel) {
+  switch (nsr) {
+    case 1: hipLaunchKernelGGL((k_psi<1, PO, double, NA>), g, dim3(kPsiThreads), 0, s, n, box, C, Tab, phi, Wel); return 0;
+    case 2: hipLaunchKernelGGL((k_psi<2, PO, double, NA>), g, dim3(kPsiThreads), 0, s, n, box, C, Tab, phi, Wel); return 0;
+    case 3: hipLaunchKernelGGL((k_psi<3, PO, double, NA>), g, dim3(kPsiThreads), 0, s, n, box, C, Tab, phi, Wel); return 0;
+    default: return -1;
+  }
+}
+
+int launch_psi_mfma_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, int box, const double *C, const double *Tab,
+                      const double *phi, double *Wel) {
+  const int bricks = (n + kPsiBS - 1) / kPsiBS, bricksz = (n + kPsiBZ - 1) / kPsiBZ;
+  dim3 g(nb * bricks * bricks * bricksz);
+  switch (10 * p + nl) {   // (order, moments per axis) of the screen families up to order 5
+    case 52: return psi_mfma_nsr<5, 8>(s, g, n, nsr, box, C, Tab, phi, Wel);
+    case 32: return psi_mfma_nsr<3, 8>(s, g, n, nsr, box, C, Tab, phi, Wel);
+    case 43: return psi_mfma_nsr<4, 27>(s, g, n, nsr, box, C, Tab, phi, Wel);
+    case 54: return psi_mfma_nsr<5, 64>(s, g, n, nsr, box, C, Tab, phi, Wel);
+    default: return -1;   // one moment (one-element q = 2) or order 6: the table sums are faster or fit
+  }
+}
 template int launch_psi<float>(hipStream_t, int, int, int, int, int, const double *, const float *, const double *,
                                float *);
 

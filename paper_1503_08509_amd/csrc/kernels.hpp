@@ -169,6 +169,10 @@ int launch_box_flux_charge(hipStream_t s, int nb, int n, int nsr, int p, int64_t
 template <class T>
 int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, int box, const double *C, const T *Tab, const double *phi,
                T *Wel);
+// the same on the matrix cores for the other screen families of order <= 5
+// (nl moments per axis; -1 for (p, nl) it does not cover), float64
+int launch_psi_mfma_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, int box, const double *C, const double *Tab,
+                      const double *phi, double *Wel);
 
 // near field and its transpose by 3-D FFTs of the element lattice (k_fft.hip);
 // n a power of two in [8, 64], p = 5.  S: table spectrum at the
