@@ -258,7 +258,9 @@ int launch_psi_mfma_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, int 
     case 32: return psi_mfma_nsr<3, 8>(s, g, n, nsr, box, C, Tab, phi, Wel);
     case 43: return psi_mfma_nsr<4, 27>(s, g, n, nsr, box, C, Tab, phi, Wel);
     case 54: return psi_mfma_nsr<5, 64>(s, g, n, nsr, box, C, Tab, phi, Wel);
-    default: return -1;   // one moment (one-element q = 2) or order 6: the table sums are faster or fit
+    case 63: return psi_mfma_nsr<6, 27>(s, g, n, nsr, box, C, Tab, phi, Wel);
+    case 65: return psi_mfma_nsr<6, 125>(s, g, n, nsr, box, C, Tab, phi, Wel);
+    default: return -1;   // one moment (one-element q = 2): the table sums are faster
   }
 }
 template int launch_psi<float>(hipStream_t, int, int, int, int, int, const double *, const float *, const double *,
