@@ -222,6 +222,174 @@ __global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, int box, const do
     }
 }
 
+// Near part of the moment adjoint on the matrix cores, for the screen
+// families with many moments (NA = 27, 64, 125):
+//
+//   A[E][a] = - sum_D sum_m g_{E+D}[m] T[a][D][m]
+//
+// a contraction over k = (D, m) with a gathered left operand (the deposits
+// of the sources E + D) and the tables, transposed to Tt[D][m][a], on the
+// right:
+//   block  = a 4 x 4 x 8 brick of target elements, 4 waves,
+//   wave   = two 4 x 4 element layers (two 16-row tiles) x every 16-moment
+//            column tile of a (NAT = ceil(NA / 16) of them),
+//   k-step = one offset D and four nodes m: one 16 x 16 x 4 float64 MFMA
+//            per tile,
+//   stages = (node chunk of 8, offset D): the chunk's deposits of one z-slab
+//            of sources per D_z in LDS, the chunk's tables of one offset
+//            (8 x NA values, contiguous in Tt) in a double LDS buffer
+//            prefetched one stage ahead into registers.
+// Missing nodes of the last chunk and moments past NA read as zero.
+constexpr int kAdjThreads = 256;
+
+template <int NSR, int PO, int NA>
+__global__ __launch_bounds__(kAdjThreads) void k_adj_mfma(int n, int box, const double *__restrict__ gE,
+                                                        const double *__restrict__ Tt, double *__restrict__ Aout) {
+  using M = Mfma16<double>;
+  using V = typename M::V;
+  constexpr int BS = kPsiBS, BZ = kPsiBZ, NTH = kAdjThreads;
+  constexpr int H = BS + 2 * NSR;             // halo edge in x and y
+  constexpr int S = 2 * NSR + 1, ND = S * S * S;
+  constexpr int Q1 = PO + 1, NM = Q1 * Q1 * Q1;
+  constexpr int NCH = (NM + 7) / 8;           // node chunks
+  constexpr int NAT = (NA + 15) / 16;         // 16-moment column tiles
+  constexpr int NAP = NAT * 16;               // padded table row
+  constexpr int TV = 8 * NA;                  // table values per stage
+  constexpr int TPF = (TV + NTH - 1) / NTH;   // prefetch registers per thread
+  constexpr int SLAB = BZ * H * H;            // one z-slab of the halo
+  constexpr int NST = NCH * ND;               // stages
+  static_assert(BZ == 2 * (NTH / 64), "two element layers per wave");
+  __shared__ __align__(16) double Ts[2][8 * NAP];
+  __shared__ __align__(16) double Gs[8 * SLAB];
+
+  const int bricks = (n + BS - 1) / BS, bricksz = (n + BZ - 1) / BZ;
+  const int per = bricks * bricks * bricksz;
+  const int lin = xcd_linear(blockIdx.x, gridDim.x);
+  {  // configuration of this brick
+    const int cfg = lin / per;
+    const size_t Mn = size_t(n) * n * n;
+    gE += size_t(cfg) * Mn * NM;
+    Aout += size_t(cfg) * Mn * NA;
+  }
+  int b = lin % per;
+  const int bx = b % bricks;
+  b /= bricks;
+  const int by = b % bricks;
+  const int bz = b / bricks;
+  const int x0 = bx * BS, y0 = by * BS, z0 = bz * BZ;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;   // layers 2 w, 2 w + 1
+  const int r = lane & 15, kq = lane >> 4;                       // A row (element of the layer) and k (node)
+  const int alx = r & 3, aly = r >> 2;
+
+  V acc[2][NAT];
+#pragma unroll
+  for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+    for (int t = 0; t < NAT; ++t) acc[hh][t] = V{0, 0, 0, 0};
+  for (int i = tid; i < 2 * 8 * NAP; i += NTH) (&Ts[0][0])[i] = 0.0;   // padding stays zero
+  __syncthreads();
+  // table value i of stage st (chunk st / ND, offset st % ND): Tt[D][m][a] with m = 8 chunk + i / NA
+  auto table = [&](int st, int i) -> double {
+    const int ch = st / ND, iD = st - ch * ND;
+    const int m = ch * 8 + i / NA;
+    return m < NM ? Tt[(size_t(iD) * NM + m) * NA + i % NA] : 0.0;
+  };
+  for (int i = tid; i < TV; i += NTH) Ts[0][(i / NA) * NAP + i % NA] = table(0, i);
+  int st = 0;
+  for (int m0 = 0; m0 < NM; m0 += 8)
+  for (int Dz = -NSR; Dz <= NSR; ++Dz) {
+    // deposits of nodes m0 .. m0 + 7 of the source slab for this D_z: target
+    // layer lz reads halo layer lz (sources at z + D_z)
+    __syncthreads();
+    for (int h = tid; h < SLAB; h += NTH) {
+      const int hx = h % H, hy = (h / H) % H, lz = h / (H * H);
+      const int sx = x0 - NSR + hx, sy = y0 - NSR + hy, sz = z0 + lz + Dz;
+      if (box && (sx < 0 || sx >= n || sy < 0 || sy >= n || sz < 0 || sz >= n)) {   // no source outside the box
+#pragma unroll
+        for (int mm = 0; mm < 8; ++mm) Gs[mm * SLAB + h] = 0.0;
+        continue;
+      }
+      const int ex = (sx + 2 * n) % n, ey = (sy + 2 * n) % n, ez = (sz + 2 * n) % n;
+      const double *g = gE + (size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NM + m0;
+#pragma unroll
+      for (int mm = 0; mm < 8; ++mm) Gs[mm * SLAB + h] = (NM % 8 == 0 || m0 + mm < NM) ? g[mm] : 0.0;
+    }
+    __syncthreads();
+    for (int Dyx = 0; Dyx < S * S; ++Dyx, ++st) {
+      const int Dx = Dyx % S - NSR, Dy = Dyx / S - NSR;
+      const int cur = st & 1;
+      double tp[TPF];
+      const bool more = st + 1 < NST;
+      if (more) {
+#pragma unroll
+        for (int q = 0; q < TPF; ++q) {
+          const int i = tid + NTH * q;
+          if (i < TV) tp[q] = table(st + 1, i);
+        }
+      }
+      const double *tb = Ts[cur];
+      const int cb = ((2 * w) * H + (aly + Dy + NSR)) * H + (alx + Dx + NSR);
+#pragma unroll
+      for (int k0 = 0; k0 < 8; k0 += 4) {
+        const double av0 = Gs[(k0 + kq) * SLAB + cb];           // layer 2 w
+        const double av1 = Gs[(k0 + kq) * SLAB + cb + H * H];   // layer 2 w + 1
+        const double *brow = tb + (k0 + kq) * NAP + r;
+#pragma unroll
+        for (int t = 0; t < NAT; ++t) {
+          const double bv = brow[16 * t];
+          acc[0][t] = M::step(av0, bv, acc[0][t]);
+          acc[1][t] = M::step(av1, bv, acc[1][t]);
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int q = 0; q < TPF; ++q) {
+          const int i = tid + NTH * q;
+          if (i < TV) Ts[cur ^ 1][(i / NA) * NAP + i % NA] = tp[q];
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+    for (int t = 0; t < NAT; ++t) {
+      const int a = 16 * t + r;
+      if (a >= NA) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int e = M::row(lane, v);
+        const int ex = x0 + (e & 3), ey = y0 + (e >> 2), ez = z0 + 2 * w + hh;
+        if (ex >= n || ey >= n || ez >= n) continue;
+        Aout[(size_t(ex) + size_t(n) * (ey + size_t(n) * ez)) * NA + a] = -acc[hh][t][v];
+      }
+    }
+}
+
+template <int PO, int NA>
+static int adj_mfma_nsr(hipStream_t s, dim3 g, int n, int nsr, int box, const double *gE, const double *Tt, double *A) {
+  switch (nsr) {
+    case 1: hipLaunchKernelGGL((k_adj_mfma<1, PO, NA>), g, dim3(kAdjThreads), 0, s, n, box, gE, Tt, A); return 0;
+    case 2: hipLaunchKernelGGL((k_adj_mfma<2, PO, NA>), g, dim3(kAdjThreads), 0, s, n, box, gE, Tt, A); return 0;
+    case 3: hipLaunchKernelGGL((k_adj_mfma<3, PO, NA>), g, dim3(kAdjThreads), 0, s, n, box, gE, Tt, A); return 0;
+    default: return -1;
+  }
+}
+
+int launch_adj_near_mfma(hipStream_t s, int nb, int n, int nsr, int p, int nl, int box, const double *gE,
+                         const double *Tt, double *A) {
+  const int bricks = (n + kPsiBS - 1) / kPsiBS, bricksz = (n + kPsiBZ - 1) / kPsiBZ;
+  dim3 g(nb * bricks * bricks * bricksz);
+  switch (10 * p + nl) {   // the families with 27 or more moments
+    case 43: return adj_mfma_nsr<4, 27>(s, g, n, nsr, box, gE, Tt, A);
+    case 54: return adj_mfma_nsr<5, 64>(s, g, n, nsr, box, gE, Tt, A);
+    case 63: return adj_mfma_nsr<6, 27>(s, g, n, nsr, box, gE, Tt, A);
+    case 65: return adj_mfma_nsr<6, 125>(s, g, n, nsr, box, gE, Tt, A);
+    default: return -1;
+  }
+}
+
 template <class T>
 int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, int box, const double *C, const T *Tab, const double *phi,
                T *Wel) {

@@ -173,6 +173,10 @@ int launch_psi(hipStream_t s, int nb, int n, int nsr, int p, int box, const doub
 // (nl moments per axis; -1 for (p, nl) it does not cover), float64
 int launch_psi_mfma_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, int box, const double *C, const double *Tab,
                       const double *phi, double *Wel);
+// near part of the moment adjoint (A = -sum_D <g_{E+D}, T[.][D]>) on the
+// matrix cores for the families with 27 or more moments (-1 otherwise)
+int launch_adj_near_mfma(hipStream_t s, int nb, int n, int nsr, int p, int nl, int box, const double *gE,
+                         const double *Tt, double *A);
 
 // near field and its transpose by 3-D FFTs of the element lattice (k_fft.hip);
 // n a power of two in [8, 64], p = 5.  S: table spectrum at the
