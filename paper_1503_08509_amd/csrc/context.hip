@@ -141,10 +141,11 @@ struct fep3m_ctx {
   // q = 3 screen (their float64 kernels are in k_screens.hip)
   int nl = 2, na = 8, span = 1;
   bool generic = false;
-  // grounded box (boundary = FEP3M_BOUNDARY_GROUNDED, Section 2.6): mesh
-  // vectors of Pb = p n + 1 nodes per axis ([z][y][x] per configuration),
-  // the dense 1-D stiffness and mass of the box and the eigenbasis of the
-  // interior pencil (K1_II V = M1_II V Lambda, V^T M1_II V = I)
+  // boxes (boundary = FEP3M_BOUNDARY_GROUNDED or _INSULATED, Section 2.6):
+  // mesh vectors of Pb = p n + 1 nodes per axis ([z][y][x] per
+  // configuration), the 1-D stiffness and mass of the box as class-row band
+  // tables, and the eigenbasis of the interior pencil
+  // (K1_II V = M1_II V Lambda, V^T M1_II V = I)
   bool box = false;
   bool insulated = false;   // boundary = FEP3M_BOUNDARY_INSULATED (else grounded)
   int Pb = 0;
@@ -908,9 +909,10 @@ int fep3m_ctx::vcycle(int l, const T *f, double *dot_part) {
   return cheb_smooth<T>(l, f, false, dot_part);
 }
 
-// Grounded box: the dense 1-D stiffness and mass on the p n + 1 nodes of
-// an axis (non-periodic assembly), the generalised eigenbasis of the
-// interior pencil, the GLL nodes, and the box vectors.
+// Boxes: the 1-D stiffness and mass on the p n + 1 nodes of an axis
+// (non-periodic assembly) as class-row band tables for the operator, the
+// generalised eigenbasis of the interior pencil (and, insulating box, of the
+// whole pencil), the GLL nodes, the face quadrature and the box vectors.
 void fep3m_ctx::build_box() {
   Pb = p * n + 1;
   const int Pi = Pb - 2;
