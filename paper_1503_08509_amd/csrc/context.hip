@@ -1253,7 +1253,7 @@ void fep3m_ctx::solve(const double *rhs, double *sol, int which) {
     if (!mixed) {   // z . r from the V-cycle's last smoothing step
       launch_sum_partials(stream, vcycle<double>(0, rcur, partial), partial, pcs.rzn, nbs);
     } else {
-      launch_to_f32(stream, nd, rcur, L0.vf.f);
+      if (!q) launch_to_f32(stream, nd, rcur, L0.vf.f);   // later residuals come with their float copy
       vcycle<float>(0, L0.vf.f);
       const int K = launch_dot2_f32(stream, nbs, per, L0.vf.x, rcur, q, dot_scr);
       launch_sum_partials(stream, K, dot_scr, pcs.rzn, nbs);
@@ -1281,8 +1281,8 @@ void fep3m_ctx::solve(const double *rhs, double *sol, int which) {
     const int Ka = apply0<double>(pv, nullptr, qv, nullptr, nullptr, 0.0, 0.0, kApplyDot, partial);
     launch_sum_partials(stream, Ka, partial, pcs.pq, nbs);
     launch_pcg_scalars(stream, nbs, kPcgAlpha, 0.0, pcs);
-    launch_sum_partials(stream, launch_r_update(stream, nbs, per, pcs.alpha, qv, rcur, rr, partial), partial,
-                        pcs.rr, nbs);
+    launch_sum_partials(stream, launch_r_update(stream, nbs, per, pcs.alpha, qv, rcur, rr, partial,
+                                                mixed ? L0.vf.f : nullptr), partial, pcs.rr, nbs);
     rcur = rr;
     launch_pcg_scalars(stream, nbs, kPcgResid, opt.mg_rtol, pcs);
     if (capturing) {

@@ -801,13 +801,17 @@ __global__ __launch_bounds__(256) void k_dot(size_t per, int K, const double *__
 // x += alpha_b p; r -= alpha_b q; partial of r.r
 // r_out = r_in - alpha_b q and block partials of r_out . r_out (r_in may be
 // r_out, or the right side in the first iteration).
+// r_out = r_in - alpha q, block partials of |r_out|^2; with rf, also a
+// float32 copy of r_out (the mixed-precision V-cycle's right side)
 __global__ __launch_bounds__(256) void k_r_update(size_t per, int K, const double *__restrict__ alphas,
                                                   const double *__restrict__ q, const double *r_in,
-                                                  double *r_out, double *__restrict__ partial) {
+                                                  double *r_out, float *__restrict__ rf,
+                                                  double *__restrict__ partial) {
   __shared__ double red[256];
   const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
   const size_t o = size_t(cfg) * per;
   q += o; r_in += o; r_out += o;
+  if (rf) rf += o;
   const double alpha = alphas[cfg];
   double acc = 0.0;
   // four elements per thread and pass: every load first, then the stores
@@ -830,7 +834,10 @@ __global__ __launch_bounds__(256) void k_r_update(size_t per, int K, const doubl
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const size_t i = i0 + u * stride;
-      if (i < per) r_out[i] = rv[u];
+      if (i < per) {
+        r_out[i] = rv[u];
+        if (rf) rf[i] = float(rv[u]);
+      }
     }
   }
   double t = block_sum(acc, red);
@@ -1216,9 +1223,9 @@ int launch_dot(hipStream_t s, int nb, size_t per, const double *a, const double 
   return K;
 }
 int launch_r_update(hipStream_t s, int nb, size_t per, const double *alphas, const double *q, const double *r_in,
-                    double *r_out, double *partial) {
+                    double *r_out, double *partial, float *rf) {
   const int K = seg_blocks(nb, per);
-  hipLaunchKernelGGL(k_r_update, dim3(nb * K), dim3(256), 0, s, per, K, alphas, q, r_in, r_out, partial);
+  hipLaunchKernelGGL(k_r_update, dim3(nb * K), dim3(256), 0, s, per, K, alphas, q, r_in, r_out, rf, partial);
   return K;
 }
 template <class ZT>

@@ -261,7 +261,7 @@ int launch_dot(hipStream_t s, int nb, size_t per, const double *a, const double 
 // (returns K); x += alpha p (x = alpha p unless xinit) fused with the next
 // direction p = z + beta p; p = z; the last x update after the loop.
 int launch_r_update(hipStream_t s, int nb, size_t per, const double *alphas, const double *q, const double *r_in,
-                    double *r_out, double *partial);
+                    double *r_out, double *partial, float *rf = nullptr);   // rf: float32 copy of r_out (or null)
 template <class ZT>
 void launch_xp_update(hipStream_t s, int nb, size_t per, const double *alphas, const double *betas, const ZT *z,
                       double *p, double *x, bool xinit);
