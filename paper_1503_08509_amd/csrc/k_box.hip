@@ -1,4 +1,4 @@
-// The grounded box (Section 2.6, eq. bcadjust with g = 0): the mesh
+// The boxes of Section 2.6.  Grounded (eq. bcadjust with g = 0): the mesh
 // potential of the box [0, n]^3 (element units) takes on the boundary the
 // values -Phi_sr, the short-range potential of the charges of the near
 // block; its interior solves K_II phi_I = b_I - K_IB phi_B.  Mesh vectors of
@@ -16,6 +16,16 @@
 //   element field     W_E[m] += phi at node (p e + k) of the box
 //   residual          block partials of sum_I (b - K phi)^2 and sum_I b^2
 //                     over the interior nodes
+//   operator          y = K v on every node by three banded 1-D passes
+//                     (class-row band tables in LDS)
+//   reverse pass      box assembly of the deposit, the boundary terms of the
+//                     moment adjoint (mu = G - K lambda in the deposit's
+//                     boundary slots) and of the per-charge gradients (one
+//                     wave per charge)
+//   insulating box    (zero normal field) the surface load of -dPhi_sr/dn by
+//                     a Gauss rule per boundary element face, the
+//                     compatibility projection, and the reverse pass's face
+//                     weights and per-charge face terms
 #include <algorithm>
 
 #include "kernels.hpp"
