@@ -50,8 +50,9 @@ def test_batch_matches_single_configurations(torch, precision):
         ctx = fp.Context(1.0, N, n, mg_rtol=1e-12, precision=precision)
         ref = ctx.energy_forces(torch.from_numpy(xs[b]).cuda(), torch.from_numpy(Qs[b]).cuda(), dUdQ=True, Phi=True)
         sl = slice(off[b], off[b + 1])
-        # FP64: the survey's bar of 1e-12 (measured: <= 3e-13; the batch's
-        # per-configuration reductions use other block counts than a single run)
+        # FP64: a batch must equal its single runs to 1e-12 (measured: <= 3e-13;
+        # the batch's per-configuration reductions use other block counts than
+        # a single run)
         tol = 1e-12 if precision == fp.PRECISION_FP64 else 1e-10
         for k in ("Phi", "F", "dUdQ"):
             assert _rel(out[k][sl].cpu().numpy(), ref[k].cpu().numpy()) < tol, (b, k)
