@@ -97,11 +97,12 @@ def test_family_ragged_and_batch(torch, q, support):
             assert _rel(out[k][sl].cpu().numpy(), one[k].cpu().numpy()) < 1e-12, (b_, k)
 
 
-@pytest.mark.parametrize("q", [2, 3])
-def test_family_full_size_against_oracle(torch, q):
-    """27-element screens of degree q at the benchmark's full size
-    (uniform-1M-n64, 7^3 near block, default options: multigrid at 1e-7,
-    the matrix-core near field and moment adjoint): Phi, F and dU/dQ on 256
+@pytest.mark.parametrize("q,support", [(2, "27"), (3, "27"), (4, "one")])
+def test_family_full_size_against_oracle(torch, q, support):
+    """Screen families at the benchmark's full size (uniform-1M-n64, 7^3
+    near block, default options: multigrid at 1e-7, the matrix-core near
+    field and moment adjoint): 27-element q = 2, 3 and one-element q = 4
+    (order-6 mesh); Phi, F and dU/dQ on 256
     sampled charges and the mesh potential on 512 sampled nodes against the
     oracle's values stored by tests/golden/make_family_fixtures.py; U
     through its definition on the GPU's own Phi.  Gate 1e-6 (the solver
@@ -109,13 +110,14 @@ def test_family_full_size_against_oracle(torch, q):
     import json
     import math
     import os
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"family_q{q}_27_uniform-1M-n64.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        f"family_q{q}_{support}_uniform-1M-n64.json")
     with open(path) as f:
         ref = json.load(f)
     x, Q = workloads.make(ref["workload"])
     n = ref["n"]
-    print(f"family full size: 27-element q={q} N={len(Q)} n={n}", flush=True)
-    ctx = fp.Context(1.0, len(Q), n, q=q, support=fp.SUPPORT_27)
+    print(f"family full size: support {support} q={q} N={len(Q)} n={n}", flush=True)
+    ctx = fp.Context(1.0, len(Q), n, q=q, support=SUP[support])
     tx, tQ = torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda()
     ctx.energy_forces(tx, tQ, dUdQ=True, Phi=True)          # first call: tuning
     out = ctx.energy_forces(tx, tQ, dUdQ=True, Phi=True)
@@ -129,6 +131,6 @@ def test_family_full_size_against_oracle(torch, q):
     errs["phi"] = float(np.abs(phi[np.array(ref["nodes"])] - np.array(ref["phi"])).max() / ref["phi_absmax"])
     Uq = 0.5 * math.fsum(Q * Phi)
     errs["U"] = abs(float(out["U"].item()) - Uq) / abs(Uq)
-    print(f"family full size q={q}:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    print(f"family full size {support} q={q}:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     for k, v in errs.items():
         assert v < 1e-6, (k, v)
