@@ -274,6 +274,12 @@ __global__ __launch_bounds__(256, 2) void k_adj_moments(int n, int box, const do
   if (tid >= BX * BY * BZ) return;
   const int ex = x0 + tid % BX, ey = y0 + (tid / BX) % BY, ez = z0 + tid / (BX * BY);
   if (ex >= n || ey >= n || ez >= n) return;
+  if (!lam) {   // the near part alone (screens whose mesh part spans more elements add it after)
+    const size_t E = size_t(ex) + size_t(n) * (ey + size_t(n) * ez);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) Aout[E * 8 + a] = -red[tid * 8 + a];
+    return;
+  }
   const int P = PO * n + (box ? 1 : 0);   // box: (PO n + 1)^3 nodes, no index leaves it
   double a1[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int mm = 0; mm < NM; ++mm) {
@@ -427,6 +433,17 @@ int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, doubl
 }
 int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, int box, const double *gE, const double *Tt,
                        const double *lam, const double *gw, double *A) {
+  if (p == 3) {   // 27-element q = 1 (8 moments, order 3): the near part alone
+    if (lam) return -1;
+    const int bxn = (n + 7) / 8, byn = (n + 3) / 4, bzn = (n + 3) / 4;
+    dim3 g(nb * bxn * byn * bzn);
+    switch (nsr) {
+      case 1: hipLaunchKernelGGL((k_adj_moments<1, 3>), g, dim3(256), 0, s, n, box, gE, Tt, lam, gw, A); return 0;
+      case 2: hipLaunchKernelGGL((k_adj_moments<2, 3>), g, dim3(256), 0, s, n, box, gE, Tt, lam, gw, A); return 0;
+      case 3: hipLaunchKernelGGL((k_adj_moments<3, 3>), g, dim3(256), 0, s, n, box, gE, Tt, lam, gw, A); return 0;
+      default: return -1;
+    }
+  }
   if (p != 5) return -1;
   const int bxn = (n + 7) / 8, byn = (n + 3) / 4, bzn = (n + 3) / 4;
   dim3 g(nb * bxn * byn * bzn);

@@ -540,6 +540,7 @@ template <int PO, int NL>
 static void adj_near_launch(hipStream_t s, int nb, int n, int nsr, int box, const double *gE, const double *Tt,
                             double *A) {
   if (launch_adj_near_mfma(s, nb, n, nsr, PO, NL, box, gE, Tt, A) == 0) return;   // matrix cores
+  if (NL == 2 && launch_adj_moments(s, nb, PO, n, nsr, box, gE, Tt, nullptr, nullptr, A) == 0) return;   // 8 moments
   using S = AdjNearShape<NL * NL * NL>;
   const int bricks = ((n + S::BX - 1) / S::BX) * ((n + S::BY - 1) / S::BY) * ((n + S::BZ - 1) / S::BZ);
   hipLaunchKernelGGL((k_adj_near_g<PO, NL>), dim3(nb * bricks), dim3(S::THREADS), 0, s, n, nsr, box, gE, Tt, A);

@@ -79,7 +79,8 @@ int launch_deposit(hipStream_t s, int nb, int p, int n, int64_t N, const GllBasi
 int launch_assemble(hipStream_t s, int nb, int p, int n, const double *gE, double *G, double *partial);
 // box = 1: no source outside [0, n)^3 and lam on the (p n + 1)^3 nodes of the
 // box (launch_psi likewise: no source outside, phi on the box's nodes; a null
-// phi gives W = -Psi)
+// phi gives W = -Psi).  A null lam writes the near part alone (A = -B); p = 3
+// (the 27-element q = 1 screen) takes only that form.
 int launch_adj_moments(hipStream_t s, int nb, int p, int n, int nsr, int box, const double *gE, const double *Tt,
                        const double *lam, const double *gw, double *A);
 // W of the forward pass in float64, or float32 on the mixed-precision path
