@@ -194,6 +194,7 @@ struct fep3m_ctx {
   int *flags = nullptr, *maxcount = nullptr;
   unsigned long long *paircount = nullptr;
   double *C = nullptr, *Wel = nullptr, *phip_s = nullptr, *phim_s = nullptr, *phi_s = nullptr;
+  double *lsep = nullptr;   // separable-load scratch of the 27-element screens (periodic)
   // mixed precision: float32 tables, element field, local coordinates
   float *Tf = nullptr, *Welf = nullptr;
   float4 *su = nullptr;
@@ -510,6 +511,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   maxcount = alloc<int>(4, "max count");
   paircount = alloc<unsigned long long>(2, "pair count");
   C = alloc<double>(size_t(nb) * M * na, "moments");
+  if (generic && !box && span == 3) lsep = alloc<double>(load_sep_scratch(nb, n, p, nl), "load passes");
   if (!mixed) {
     Wel = alloc<double>(size_t(nb) * M * (p + 1) * (p + 1) * (p + 1), "element field");
   } else {
@@ -1400,7 +1402,7 @@ void fep3m_ctx::forward(const double *x, const double *Qc, double *Phi, double *
   }
   stage_mark(FEP3M_PROF_MOMENTS, false);
   stage_mark(FEP3M_PROF_LOAD, true);
-  const int Kl = generic ? launch_load_g(stream, nb, n, p, span, nl, 0, C, gw, b, partial)
+  const int Kl = generic ? launch_load_g(stream, nb, n, p, span, nl, 0, C, gw, b, partial, lsep)
                          : launch_load(stream, nb, n, p, C, gw, b, partial);
   stage_mark(FEP3M_PROF_LOAD, false);
   if (Kl < 0) throw Status(FEP3M_ERR_UNSUPPORTED, "load variant");

@@ -17,6 +17,8 @@
 //
 // Element ids are configuration-major (b n^3 + e); mesh vectors are nb
 // consecutive (PO n)^3 blocks [z][y][x].
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace fep3m {
@@ -415,6 +417,113 @@ __global__ __launch_bounds__(AdjNearShape<NL * NL * NL>::THREADS) void k_adj_nea
 // nodes of lambda * gw[ax][jx] gw[ay][jy] gw[az][jz], one thread per
 // (element, moment), contracted along x, then y, then z.  box: lambda on the
 // (PO n + 1)^3 nodes of the box (SPAN 1, so no index leaves it).
+// The same load for the 27-element screens (SPAN 3, periodic), separably:
+// b = 4 pi (W_z (x) W_y (x) W_x) C, W mapping (source element s, moment
+// index a) of one axis to the nodes g of the source's support with weight
+// gw[a][g - p (s - 1)].  Three passes, each a 1-D gather over the 3 or 4
+// sources of a node (every moment of a source element is read once per
+// pass instead of once per node of its support):
+//   x:  T1[c][sz][sy][az][ay][gx] = sum_{sx, ax} W_x C[c][sz][sy][sx][az][ay][ax]
+//   y:  T2[c][sz][az][gy][gx]     = sum_{sy, ay} W_y T1
+//   z:  b[c][gz][gy][gx]          = 4 pi sum_{sz, az} W_z T2  (with block partials of b)
+template <int PO, int NL>
+__global__ __launch_bounds__(256) void k_load_sx(int nb, int n, const double *__restrict__ C,
+                                                 const double *__restrict__ gw, double *__restrict__ T1) {
+  constexpr int NA = NL * NL * NL, NL2 = NL * NL, KS = 3 * PO + 1;
+  const int P = PO * n;
+  const size_t rows = size_t(nb) * n * n;   // (c, sz, sy)
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < rows * P; t += size_t(gridDim.x) * blockDim.x) {
+    const int gx = int(t % P);
+    const size_t row = t / P;
+    int sx[4], jx[4];
+    const int cx = axis_sources<PO, 3>(gx, n, false, sx, jx);
+    double acc[NL2];
+#pragma unroll
+    for (int q = 0; q < NL2; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i >= cx) break;
+      double w[NL];
+#pragma unroll
+      for (int ax = 0; ax < NL; ++ax) w[ax] = gw[ax * KS + jx[i]];
+      const double *c = C + (row * n + sx[i]) * NA;
+#pragma unroll
+      for (int q = 0; q < NL2; ++q) {
+        double v = 0.0;
+#pragma unroll
+        for (int ax = 0; ax < NL; ++ax) v += w[ax] * c[q * NL + ax];
+        acc[q] += v;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NL2; ++q) T1[(row * NL2 + q) * P + gx] = acc[q];
+  }
+}
+
+template <int PO, int NL>
+__global__ __launch_bounds__(256) void k_load_sy(int nb, int n, const double *__restrict__ gw,
+                                                 const double *__restrict__ T1, double *__restrict__ T2) {
+  constexpr int NL2 = NL * NL, KS = 3 * PO + 1;
+  const int P = PO * n;
+  const size_t P2 = size_t(P) * P;
+  const size_t total = size_t(nb) * n * P2;   // (c, sz, gy, gx)
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += size_t(gridDim.x) * blockDim.x) {
+    const int gx = int(t % P), gy = int((t / P) % P);
+    const size_t csz = t / P2;   // c n + sz
+    int sy[4], jy[4];
+    const int cy = axis_sources<PO, 3>(gy, n, false, sy, jy);
+    double acc[NL];
+#pragma unroll
+    for (int az = 0; az < NL; ++az) acc[az] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i >= cy) break;
+      const double *r = T1 + ((csz * n + sy[i]) * NL2) * P + gx;
+#pragma unroll
+      for (int az = 0; az < NL; ++az) {
+        double v = 0.0;
+#pragma unroll
+        for (int ay = 0; ay < NL; ++ay) v += gw[ay * KS + jy[i]] * r[size_t(az * NL + ay) * P];
+        acc[az] += v;
+      }
+    }
+#pragma unroll
+    for (int az = 0; az < NL; ++az) T2[((csz * NL + az) * P + gy) * P + gx] = acc[az];
+  }
+}
+
+template <int PO, int NL>
+__global__ __launch_bounds__(256) void k_load_sz(int n, int K, const double *__restrict__ gw,
+                                                 const double *__restrict__ T2all, double *__restrict__ ball,
+                                                 double *__restrict__ partial) {
+  constexpr int KS = 3 * PO + 1;
+  __shared__ double red[8];
+  const int P = PO * n;
+  const size_t P2 = size_t(P) * P, per = P2 * P;
+  const int cfg = blockIdx.x / K, kb = blockIdx.x % K;
+  const double *T2 = T2all + size_t(cfg) * n * NL * P2;
+  double *b = ball + size_t(cfg) * per;
+  double acc = 0.0;
+  for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < per; g += size_t(K) * blockDim.x) {
+    const size_t gxy = g % P2;
+    const int gz = int(g / P2);
+    int sz[4], jz[4];
+    const int cz = axis_sources<PO, 3>(gz, n, false, sz, jz);
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i >= cz) break;
+#pragma unroll
+      for (int az = 0; az < NL; ++az) v += gw[az * KS + jz[i]] * T2[(size_t(sz[i]) * NL + az) * P2 + gxy];
+    }
+    v *= 4.0 * M_PI;
+    b[g] = v;
+    acc += v;
+  }
+  const double s = block_sum_s(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
 template <int PO, int SPAN, int NL>
 __global__ __launch_bounds__(256) void k_adj_lam_g(int n, int MT, int box, const double *__restrict__ lamall,
                                                    const double *__restrict__ gw, double *__restrict__ A) {
@@ -484,11 +593,43 @@ static int load_g_nl(hipStream_t s, int nb, int n, int nl, int K, int box, const
   return 0;
 }
 
+template <int PO>
+static int load_sep_nl(hipStream_t s, int nb, int n, int nl, int K, const double *C, const double *gw, double *t1,
+                       double *t2, double *b, double *partial) {
+  const size_t P = size_t(PO) * n;
+  auto grid = [](size_t count) { return int(std::min<size_t>((count + 255) / 256, 65536)); };
+  const int g1 = grid(size_t(nb) * n * n * P), g2 = grid(size_t(nb) * n * P * P);
+#define CALL(NL)                                                                                         \
+  hipLaunchKernelGGL((k_load_sx<PO, NL>), dim3(g1), dim3(256), 0, s, nb, n, C, gw, t1);                \
+  hipLaunchKernelGGL((k_load_sy<PO, NL>), dim3(g2), dim3(256), 0, s, nb, n, gw, t1, t2);               \
+  hipLaunchKernelGGL((k_load_sz<PO, NL>), dim3(nb * K), dim3(256), 0, s, n, K, gw, t2, b, partial)
+  FEP3M_NL_SWITCH(nl, CALL)
+#undef CALL
+  return 0;
+}
+
+size_t load_sep_scratch(int nb, int n, int p, int nl) {
+  const size_t P = size_t(p) * n;
+  return size_t(nb) * n * n * P * nl * nl + size_t(nb) * n * P * P * nl;   // T1, then T2
+}
+
 int launch_load_g(hipStream_t s, int nb, int n, int p, int span, int nl, int box, const double *C, const double *gw,
-                  double *b, double *partial) {
+                  double *b, double *partial, double *sep) {
   if (box && span != 1) return -1;   // a box holds the one-element screens only
   const int P = p * n + (box ? 1 : 0);
   const int K = seg_blocks(nb, size_t(P) * P * P);
+  if (span == 3 && sep) {   // separable passes through the scratch T1, T2
+    double *t1 = sep, *t2 = sep + size_t(nb) * n * n * size_t(P) * nl * nl;
+    int r = -1;
+    switch (p) {
+      case 3: r = load_sep_nl<3>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
+      case 4: r = load_sep_nl<4>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
+      case 5: r = load_sep_nl<5>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
+      case 6: r = load_sep_nl<6>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
+      default: return -1;
+    }
+    return r < 0 ? -1 : K;
+  }
   int r = -1;
   if (span == 1) {
     switch (p) {
