@@ -194,7 +194,7 @@ struct fep3m_ctx {
   int *flags = nullptr, *maxcount = nullptr;
   unsigned long long *paircount = nullptr;
   double *C = nullptr, *Wel = nullptr, *phip_s = nullptr, *phim_s = nullptr, *phi_s = nullptr;
-  double *lsep = nullptr;   // separable-load scratch of the 27-element screens (periodic)
+  double *lsep = nullptr;   // scratch of the separable load and adjoint of the 27-element screens (periodic)
   // mixed precision: float32 tables, element field, local coordinates
   float *Tf = nullptr, *Welf = nullptr;
   float4 *su = nullptr;
@@ -1576,7 +1576,7 @@ void fep3m_ctx::reverse(double *F, double *dUdQ) {
     if (as == 0) as = launch_adj_fft_finish(stream, nb, n, p, lam, gw, za, Aadj);
     adj_near_ready = false;
   } else if (generic) {
-    as = launch_adj_g(stream, nb, n, nsr, p, span, nl, 0, gE, Tt, lam, gw, Aadj);
+    as = launch_adj_g(stream, nb, n, nsr, p, span, nl, 0, gE, Tt, lam, gw, Aadj, lsep);
   } else {
     as = launch_adj_moments(stream, nb, p, n, nsr, 0, gE, Tt, lam, gw, Aadj);
   }

@@ -553,6 +553,99 @@ __global__ __launch_bounds__(256) void k_adj_lam_g(int n, int MT, int box, const
   }
 }
 
+// The lambda part of the moment adjoint of the 27-element screens, the
+// transpose of the separable load (periodic): A += 4 pi (W_z (x) W_y (x) W_x)^T
+// lam, one axis at a time through the load's scratch:
+//   z:  U1[c][sz][az][gy][gx]     = sum_kz gw[az][kz] lam[p (sz - 1) + kz][gy][gx]
+//   y:  U2[c][sz][sy][az][ay][gx] = sum_ky gw[ay][ky] U1[c][sz][az][p (sy - 1) + ky][gx]
+//   x:  A[c][sz][sy][sx][az][ay][ax] += 4 pi sum_kx gw[ax][kx] U2[c][sz][sy][az][ay][p (sx - 1) + kx]
+// (node indices wrap modulo P = p n).
+template <int PO, int NL>
+__global__ __launch_bounds__(256) void k_adjl_z(int nb, int n, const double *__restrict__ lamall,
+                                                const double *__restrict__ gw, double *__restrict__ U1) {
+  constexpr int KS = 3 * PO + 1;
+  const int P = PO * n;
+  const size_t P2 = size_t(P) * P;
+  const size_t total = size_t(nb) * n * P2;   // (c, sz, gy, gx)
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += size_t(gridDim.x) * blockDim.x) {
+    const size_t gxy = t % P2, csz = t / P2;
+    const int sz = int(csz % n);
+    const size_t c = csz / n;
+    const double *lam = lamall + c * P2 * P + gxy;
+    const int z0 = PO * (sz - 1);
+    double acc[NL];
+#pragma unroll
+    for (int az = 0; az < NL; ++az) acc[az] = 0.0;
+#pragma unroll
+    for (int kz = 0; kz < KS; ++kz) {
+      const double v = lam[size_t(((z0 + kz) % P + P) % P) * P2];
+#pragma unroll
+      for (int az = 0; az < NL; ++az) acc[az] += gw[az * KS + kz] * v;
+    }
+#pragma unroll
+    for (int az = 0; az < NL; ++az) U1[(csz * NL + az) * P2 + gxy] = acc[az];
+  }
+}
+
+template <int PO, int NL>
+__global__ __launch_bounds__(256) void k_adjl_y(int nb, int n, const double *__restrict__ gw,
+                                                const double *__restrict__ U1, double *__restrict__ U2) {
+  constexpr int KS = 3 * PO + 1, NL2 = NL * NL;
+  const int P = PO * n;
+  const size_t P2 = size_t(P) * P;
+  const size_t total = size_t(nb) * n * n * P;   // (c, sz, sy, gx)
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += size_t(gridDim.x) * blockDim.x) {
+    const int gx = int(t % P);
+    const size_t row = t / P;   // (c n + sz) n + sy
+    const int sy = int(row % n);
+    const size_t csz = row / n;
+    const int y0 = PO * (sy - 1);
+#pragma unroll
+    for (int az = 0; az < NL; ++az) {
+      const double *u = U1 + (csz * NL + az) * P2 + gx;
+      double acc[NL];
+#pragma unroll
+      for (int ay = 0; ay < NL; ++ay) acc[ay] = 0.0;
+#pragma unroll
+      for (int ky = 0; ky < KS; ++ky) {
+        const double v = u[size_t(((y0 + ky) % P + P) % P) * P];
+#pragma unroll
+        for (int ay = 0; ay < NL; ++ay) acc[ay] += gw[ay * KS + ky] * v;
+      }
+#pragma unroll
+      for (int ay = 0; ay < NL; ++ay) U2[(row * NL2 + az * NL + ay) * P + gx] = acc[ay];
+    }
+  }
+}
+
+template <int PO, int NL>
+__global__ __launch_bounds__(256) void k_adjl_x(int nb, int n, const double *__restrict__ gw,
+                                                const double *__restrict__ U2, double *__restrict__ A) {
+  constexpr int KS = 3 * PO + 1, NL2 = NL * NL, NA = NL2 * NL;
+  const int P = PO * n;
+  const size_t total = size_t(nb) * n * n * n * NL2;   // (c, sz, sy, q = (az, ay), sx)
+  for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += size_t(gridDim.x) * blockDim.x) {
+    const int sx = int(t % n);
+    const size_t rq = t / n;   // row NL2 + q
+    const int q = int(rq % NL2);
+    const size_t row = rq / NL2;
+    const double *u = U2 + rq * P;
+    const int x0 = PO * (sx - 1);
+    double acc[NL];
+#pragma unroll
+    for (int ax = 0; ax < NL; ++ax) acc[ax] = 0.0;
+#pragma unroll
+    for (int kx = 0; kx < KS; ++kx) {
+      const double v = u[((x0 + kx) % P + P) % P];
+#pragma unroll
+      for (int ax = 0; ax < NL; ++ax) acc[ax] += gw[ax * KS + kx] * v;
+    }
+    double *a = A + (row * n + sx) * NA + q * NL;
+#pragma unroll
+    for (int ax = 0; ax < NL; ++ax) a[ax] += 4.0 * M_PI * acc[ax];
+  }
+}
+
 inline int grid_for_count(int64_t count) {
   int64_t g = (count + 255) / 256;
   if (g < 1) g = 1;
@@ -689,9 +782,23 @@ static void adj_near_launch(hipStream_t s, int nb, int n, int nsr, int box, cons
 
 template <int PO, int SPAN>
 static int adj_g_nl(hipStream_t s, int nb, int n, int nsr, int nl, int box, const double *gE, const double *Tt,
-                    const double *lam, const double *gw, double *A) {
+                    const double *lam, const double *gw, double *A, double *sep) {
   if (nsr < 1 || nsr > 3) return -1;
   const int MT = nb * n * n * n;
+  if (SPAN == 3 && sep && !box) {   // separable lambda part through the load's scratch
+    const size_t P = size_t(PO) * n;
+    double *u2 = sep, *u1 = sep + size_t(nb) * n * n * P * nl * nl;
+    const int gz = grid_for_count(int64_t(nb) * n * P * P), gy = grid_for_count(int64_t(nb) * n * n * P);
+    const int gx = grid_for_count(int64_t(MT) * nl * nl);
+#define CALL(NL)                                                                                  \
+  adj_near_launch<PO, NL>(s, nb, n, nsr, box, gE, Tt, A);                                         \
+  hipLaunchKernelGGL((k_adjl_z<PO, NL>), dim3(gz), dim3(256), 0, s, nb, n, lam, gw, u1);         \
+  hipLaunchKernelGGL((k_adjl_y<PO, NL>), dim3(gy), dim3(256), 0, s, nb, n, gw, u1, u2);          \
+  hipLaunchKernelGGL((k_adjl_x<PO, NL>), dim3(gx), dim3(256), 0, s, nb, n, gw, u2, A)
+    FEP3M_NL_SWITCH(nl, CALL)
+#undef CALL
+    return 0;
+  }
   const int g = grid_for_count(int64_t(MT) * nl * nl * nl);
 #define CALL(NL)                                             \
   adj_near_launch<PO, NL>(s, nb, n, nsr, box, gE, Tt, A); \
@@ -702,22 +809,22 @@ static int adj_g_nl(hipStream_t s, int nb, int n, int nsr, int nl, int box, cons
 }
 
 int launch_adj_g(hipStream_t s, int nb, int n, int nsr, int p, int span, int nl, int box, const double *gE,
-                 const double *T, const double *lam, const double *gw, double *A) {
+                 const double *T, const double *lam, const double *gw, double *A, double *sep) {
   if (box && span != 1) return -1;
   if (span == 1) {
     switch (p) {
-      case 4: return adj_g_nl<4, 1>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
-      case 5: return adj_g_nl<5, 1>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
-      case 6: return adj_g_nl<6, 1>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
+      case 4: return adj_g_nl<4, 1>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A, sep);
+      case 5: return adj_g_nl<5, 1>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A, sep);
+      case 6: return adj_g_nl<6, 1>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A, sep);
       default: return -1;
     }
   }
   if (span == 3) {
     switch (p) {
-      case 3: return adj_g_nl<3, 3>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
-      case 4: return adj_g_nl<4, 3>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
-      case 5: return adj_g_nl<5, 3>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
-      case 6: return adj_g_nl<6, 3>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A);
+      case 3: return adj_g_nl<3, 3>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A, sep);
+      case 4: return adj_g_nl<4, 3>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A, sep);
+      case 5: return adj_g_nl<5, 3>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A, sep);
+      case 6: return adj_g_nl<6, 3>(s, nb, n, nsr, nl, box, gE, T, lam, gw, A, sep);
       default: return -1;
     }
   }

@@ -106,7 +106,7 @@ size_t load_sep_scratch(int nb, int n, int p, int nl);
 int launch_psi_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, int box, const double *C, const double *T,
                  const double *phi, double *W);
 int launch_adj_g(hipStream_t s, int nb, int n, int nsr, int p, int span, int nl, int box, const double *gE,
-                 const double *Tt, const double *lam, const double *gw, double *A);   // Tt: tables as [D][m][a]
+                 const double *Tt, const double *lam, const double *gw, double *A, double *sep = nullptr);   // Tt: tables as [D][m][a]
 
 // grounded box (k_box.hip): mesh vectors of (p n + 1)^3 nodes per
 // configuration, P = p n + 1.
