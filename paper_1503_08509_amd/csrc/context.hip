@@ -658,6 +658,24 @@ void fep3m_ctx::build_mg() {
         L_.vf.r = alloc<float>(nv, "mg r (f32)");
       }
     }
+    if (L_.op.p == 6) {   // the order-6 operator reads its band coefficients from device memory
+      constexpr int Q2 = 49;
+      std::vector<double> cd(2 * Q2);
+      for (int k = 0; k < Q2; ++k) {
+        cd[k] = L_.op.me[k];
+        cd[Q2 + k] = L_.op.ke[k];
+      }
+      double *g = alloc<double>(cd.size(), "order-6 operator coefficients");
+      hip_check(hipMemcpy(g, cd.data(), cd.size() * sizeof(double), hipMemcpyHostToDevice), "upload coefficients");
+      L_.op.cg = g;
+      if (mixed) {
+        std::vector<float> cf(cd.size());
+        for (size_t k = 0; k < cf.size(); ++k) cf[k] = k < Q2 ? L_.opf.me[k] : L_.opf.ke[k - Q2];
+        float *gf = alloc<float>(cf.size(), "order-6 operator coefficients (f32)");
+        hip_check(hipMemcpy(gf, cf.data(), cf.size() * sizeof(float), hipMemcpyHostToDevice), "upload coefficients");
+        L_.opf.cg = gf;
+      }
+    }
   }
   fuse_rr = lv.size() > 1 && lv[0].op.p == 5 && lv[1].op.p == 3 && n % 2 == 0;
   if (fuse_rr) {

@@ -23,6 +23,7 @@ struct LevelOpT {
   T me[(kMaxP + 1) * (kMaxP + 1)];  // element mass
   T dk[kMaxP];           // diagonal of assembled K1 at local index k (k = 0: vertex)
   T dm[kMaxP];           // diagonal of assembled M1
+  const T *cg = nullptr; // device copy of me then ke (p = 6 levels: read through scalar loads)
 
   template <class U>
   LevelOpT<U> cast() const {

@@ -197,7 +197,7 @@ __device__ __forceinline__ T pick(const T (&v)[kMaxP], int k) {
   return r;
 }
 
-template <int PO, int TE>
+template <int PO, int TE, int NT = 256>
 struct ApplyShape {
   static constexpr int O = TE * PO;          // owned nodes per axis
   static constexpr int I = O + PO + 1;       // input nodes per axis (with halo)
@@ -209,7 +209,7 @@ struct ApplyShape {
   static constexpr int LDS_C = 2 * O * SC;
   static constexpr int LDS_Y = O * O * YS;
   static constexpr int LDS = LDS_AB > LDS_C + LDS_Y ? LDS_AB : LDS_C + LDS_Y;
-  static_assert(I * I <= 256 && O * I <= 256 && O * O <= 256, "tile columns must fit one pass of 256 threads");
+  static_assert(I * I <= NT && O * I <= NT && O * O <= NT, "tile columns must fit one pass of the block");
 };
 
 // Banded 1-D element-assembled operator on a column held in registers:
@@ -287,22 +287,29 @@ __device__ __forceinline__ void restrict_partial(const T *__restrict__ w, const 
 // gives y = Kx C1 + Mx C2; the epilogue then walks the owned nodes x-fastest.
 // With RR (kResidual, PO = 5, TE = 2, whole tiles) the residual is not
 // stored: the tile restricts it to 7^3 partial coarse values (RestrictArgs).
-template <class T, int PO, int TE, bool RR>
-__global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restrict__ x, const T *__restrict__ f,
+// NT threads per block (one per input column of the z pass: 384 for the
+// 19^2 columns of a p = 6 tile of 2^3 elements).
+template <class T, int PO, int TE, bool RR, int NT = 256>
+__global__ __launch_bounds__(NT) void k_apply(LevelOpT<T> op, const T *__restrict__ x, const T *__restrict__ f,
                                                T *__restrict__ out, const T *xprev, T *xo, T c1, T c2, int mode,
-                                               double *__restrict__ partial, T s0, RestrictArgs<T> ra) {
+                                               double *__restrict__ partial, T s0, RestrictArgs<T> ra,
+                                               const T *__restrict__ cg) {
   static_assert(!RR || (PO == 5 && TE == 2), "the fused restriction covers p = 5 tiles of 2^3 elements");
-  using S = ApplyShape<PO, TE>;
+  using S = ApplyShape<PO, TE, NT>;
   constexpr int O = S::O, I = S::I;
   static_assert(S::LDS * sizeof(T) >= 256 * sizeof(double), "the dot-product tree reuses the tile");
   __shared__ __align__(16) T lds[S::LDS];  // A, B; then C1, C2, Y; last the dot-product tree
   __shared__ T invd[PO * PO * PO];         // 1 / diag(K) by local node index
-  __shared__ T Xo[O * O * O];              // x on the owned nodes (from the z-pass columns)
-  // p = 6: the band coefficients (2 x 49 values) in LDS; read through the
-  // by-value argument they make the compiler copy the whole operator to
-  // scratch memory
-  constexpr bool kLdsCoef = PO == 6;
-  __shared__ T coef[kLdsCoef ? 2 * (PO + 1) * (PO + 1) : 1];
+  // x on the owned nodes, from the z-pass columns; p = 6 reads it from global
+  // memory in the epilogue instead (a tile then needs little enough LDS for
+  // two blocks per compute unit)
+  constexpr bool kXoLds = PO != 6;
+  __shared__ T Xo[kXoLds ? O * O * O : 1];
+  // p = 6: the band coefficients (2 x 49 values) come from the device copy
+  // op.cg at wave-uniform addresses (scalar loads); read through the by-value
+  // argument they make the compiler copy the whole operator to scratch
+  // memory, and held in vector registers they spill
+  constexpr bool kGlobalCoef = PO == 6;
   T *A = lds;
   T *B = lds + O * S::SA;
   T *C1 = lds;
@@ -327,40 +334,36 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
 
   // Epilogue operands of this thread's owned nodes, fetched now so their
   // latency hides behind the three passes.
-  constexpr int NIT = (O * O * O + 255) / 256;
+  constexpr int NIT = (O * O * O + NT - 1) / NT;
   const bool zstart = (mode == kChebZ2);   // input columns are s0 D^-1 f
   const bool cheb = (mode == kCheb) || (mode == kChebDot);
   const bool need_f = (mode == kResidual) || cheb || zstart || (mode == kChebZ3);
   const bool need_d = cheb && (c1 != T(0)) && (xprev != nullptr);   // null x_prev reads as zero
-  for (int i = tid; i < PO * PO * PO; i += 256) {
+  const bool need_x = !kXoLds && !zstart && (cheb || mode == kChebZ3 || mode == kApplyDot);
+  for (int i = tid; i < PO * PO * PO; i += NT) {
     const int kx = i % PO, ky = (i / PO) % PO, kz = i / (PO * PO);
     const T dkx = pick<PO>(op.dk, kx), dky = pick<PO>(op.dk, ky), dkz = pick<PO>(op.dk, kz);
     const T dmx = pick<PO>(op.dm, kx), dmy = pick<PO>(op.dm, ky), dmz = pick<PO>(op.dm, kz);
     invd[i] = T(1) / (dkx * dmy * dmz + dmx * dky * dmz + dmx * dmy * dkz);
   }
   const T *cme = op.me, *cke = op.ke;
-  if constexpr (kLdsCoef) {
-    constexpr int Q2 = (PO + 1) * (PO + 1);
-    if (tid < Q2) {
-      coef[tid] = op.me[tid];
-      coef[Q2 + tid] = op.ke[tid];
-    }
-    __syncthreads();
-    cme = coef;
-    cke = coef + Q2;
+  if constexpr (kGlobalCoef) {
+    cme = cg;
+    cke = cg + (PO + 1) * (PO + 1);
   }
   // Addresses: a block-uniform 64-bit tile base plus 32-bit offsets inside
   // the tile (at most O P^2 + O P + O < 2^31 for every supported n).
   const size_t tbase = (size_t(oz0) * P + oy0) * P + ox0;
-  T pf_f[NIT], pf_d[NIT];
+  T pf_f[NIT], pf_d[NIT], pf_x[kXoLds ? 1 : NIT];
 #pragma unroll
   for (int r = 0; r < NIT; ++r) {
-    const int li = tid + 256 * r;
+    const int li = tid + NT * r;
     const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
     const bool ok = li < O * O * O && ox0 + ox < P && oy0 + oy < P && oz0 + oz < P;
     const size_t g = tbase + unsigned(ok ? (oz * P + oy) * P + ox : 0);
     pf_f[r] = (ok && need_f) ? f[g] : T(0);
     pf_d[r] = (ok && need_d) ? xprev[g] : T(0);
+    if constexpr (!kXoLds) pf_x[r] = (ok && need_x) ? x[g] : T(0);
   }
 
   // pass z
@@ -380,7 +383,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
 #pragma unroll
       for (int z = 0; z < I; ++z) v[z] *= s0 * id[PO * PO * (z % PO)];
     }
-    if (lx >= PO && lx < PO + O && ly >= PO && ly < PO + O) {
+    if (kXoLds && lx >= PO && lx < PO + O && ly >= PO && ly < PO + O) {
 #pragma unroll
       for (int oz = 0; oz < O; ++oz) Xo[(oz * O + (ly - PO)) * O + (lx - PO)] = v[oz + PO];
     }
@@ -435,7 +438,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
     // separable partial restrictions: x rows, y columns, z columns.
 #pragma unroll
     for (int r = 0; r < NIT; ++r) {
-      const int li = tid + 256 * r;
+      const int li = tid + NT * r;
       if (li < O * O * O) {
         const int cx = li % O, cy = (li / O) % O, cz = li / (O * O);
         Xo[li] = pf_f[r] - Y[(cz * O + cy) * S::YS + cx];
@@ -483,14 +486,16 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
   T *const base = (cheb || zstart || mode == kChebZ3) ? xo : out;   // xo may overwrite x_prev
 #pragma unroll
   for (int r = 0; r < NIT; ++r) {
-    const int li = tid + 256 * r;
+    const int li = tid + NT * r;
     const int ox = li % O, oy = (li / O) % O, oz = li / (O * O);
     const bool ok = li < O * O * O && ox0 + ox < P && oy0 + oy < P && oz0 + oz < P;
     const int lc = ok ? li : 0;
     const int cx = lc % O, cy = (lc / O) % O, cz = lc / (O * O);
     const T y = Y[(cz * O + cy) * S::YS + cx];
-    const T xv = Xo[lc];
     const T id = invd[(ox % PO) + PO * ((oy % PO) + PO * (oz % PO))];
+    T xv;
+    if constexpr (kXoLds) xv = Xo[lc];
+    else xv = zstart ? pf_f[r] * (s0 * id) : pf_x[r];   // the z pass's input: s0 D^-1 f, else x
     const T rr = (pf_f[r] - y) * id;
     T v;
     if (mode == kApply || mode == kApplyDot) v = y;
@@ -509,7 +514,9 @@ __global__ __launch_bounds__(256) void k_apply(LevelOpT<T> op, const T *__restri
     if (dst[r]) *dst[r] = res[r];
   if (mode == kApplyDot || mode == kChebDot) {
     __syncthreads();  // every thread is done with Y before the tree reuses it
-    double s = block_sum(acc, reinterpret_cast<double *>(lds));
+    double s;
+    if constexpr (NT == 256) s = block_sum(acc, reinterpret_cast<double *>(lds));
+    else s = block_sum_waves(acc, reinterpret_cast<double *>(lds));   // whole waves, not a power of two
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
   }
 }
@@ -1056,13 +1063,14 @@ void launch_sub_const(hipStream_t s, int nb, size_t per, double invV, const doub
   hipLaunchKernelGGL(k_sub_const, dim3(nb * K), dim3(256), 0, s, per, K, invV, scal, v);
 }
 
-template <class T, int PO, int TE>
+template <class T, int PO, int TE, int NT = 256>
 static int apply_impl(hipStream_t s, int nb, const LevelOpT<T> &op, const T *x, const T *f, T *out, const T *d, T *xo,
                       T c1, T c2, int mode, double *partial, T s0) {
   const int tiles = (op.n + TE - 1) / TE;
   const int K = tiles * tiles * tiles;
-  hipLaunchKernelGGL((k_apply<T, PO, TE, false>), dim3(nb * K), dim3(256), 0, s, op, x, f, out, d, xo, c1, c2, mode,
-                     partial, s0, RestrictArgs<T>{});
+  if (PO == 6 && !op.cg) return -1;   // the order-6 operator reads its coefficients from op.cg
+  hipLaunchKernelGGL((k_apply<T, PO, TE, false, NT>), dim3(nb * K), dim3(NT), 0, s, op, x, f, out, d, xo, c1, c2,
+                     mode, partial, s0, RestrictArgs<T>{}, op.cg);
   return K;
 }
 
@@ -1112,7 +1120,7 @@ int launch_apply_restrict(hipStream_t s, int nb, const LevelOpT<T> &op, const Tr
   const int tiles = op.n / 2;
   const int K = tiles * tiles * tiles;
   hipLaunchKernelGGL((k_apply<T, 5, 2, true>), dim3(nb * K), dim3(256), 0, s, op, x, f, nullptr, nullptr, nullptr,
-                     T(0), T(0), int(kResidual), nullptr, T(0), ra);
+                     T(0), T(0), int(kResidual), nullptr, T(0), ra, op.cg);
   return K;
 }
 
@@ -1132,13 +1140,13 @@ int launch_apply(hipStream_t s, int nb, const LevelOpT<T> &op, const T *x, const
     case 3: return apply_impl<T, 3, 4>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
     case 4: return apply_impl<T, 4, 2>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
     case 5: return apply_impl<T, 5, 2>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
-    case 6: return apply_impl<T, 6, 1>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
+    case 6: return apply_impl<T, 6, 2, 384>(s, nb, op, x, f, out, d, xo, c1, c2, mode, partial, s0);
     default: return -1;
   }
 }
 
 int apply_blocks(const LevelOp &op) {
-  int TE = op.p == 1 ? 8 : op.p == 2 ? 4 : op.p == 3 ? 4 : op.p == 6 ? 1 : 2;
+  int TE = op.p == 1 ? 8 : op.p == 2 ? 4 : op.p == 3 ? 4 : 2;
   int tiles = (op.n + TE - 1) / TE;
   return tiles * tiles * tiles;
 }
