@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kPsiThreads, 1) void k_psi(int n, int box, const do
 constexpr int kAdjThreads = 256;
 
 template <int NSR, int PO, int NA>
-__global__ __launch_bounds__(kAdjThreads) void k_adj_mfma(int n, int box, const double *__restrict__ gE,
+__global__ __launch_bounds__(kAdjThreads, 2) void k_adj_mfma(int n, int box, const double *__restrict__ gE,
                                                         const double *__restrict__ Tt, double *__restrict__ Aout) {
   using M = Mfma16<double>;
   using V = typename M::V;
