@@ -573,11 +573,13 @@ __device__ __forceinline__ void restrict_col(const T *__restrict__ w, const T (&
   }
 }
 
-template <class T, int PF, int PC, int R, int TE>
-__global__ __launch_bounds__(256) void k_restrict(TransferT<T> tr, const T *__restrict__ rf, T *__restrict__ fc) {
+// NT threads per block, one per fine input column of the z pass (384 for the
+// 18^2 columns of a p = 6 tile of 2^3 coarse elements).
+template <class T, int PF, int PC, int R, int TE, int NT = 256>
+__global__ __launch_bounds__(NT) void k_restrict(TransferT<T> tr, const T *__restrict__ rf, T *__restrict__ fc) {
   using S = XferShape<PF, PC, R, TE>;
   constexpr int NS = S::NS, CO = S::CO, NF = S::NF;
-  static_assert(NF * NF <= 256 && NF * CO <= 256 && CO * CO <= 256, "restriction tile too large");
+  static_assert(NF * NF <= NT && NF * CO <= NT && CO * CO <= NT, "restriction tile too large");
   __shared__ T G1[CO * NF * (NF + 1)];   // [cz][fy][fx]
   __shared__ T G2[CO * CO * (NF + 1)];   // [cz][cy][fx]
   __shared__ T Out[CO * CO * CO];        // [cz][cy][cx]
@@ -624,7 +626,7 @@ __global__ __launch_bounds__(256) void k_restrict(TransferT<T> tr, const T *__re
     for (int c = 0; c < CO; ++c) Out[(cz * CO + cy) * CO + c] = o[c];
   }
   __syncthreads();
-  for (int li = tid; li < CO * CO * CO; li += 256) {
+  for (int li = tid; li < CO * CO * CO; li += NT) {
     const int cx = li % CO, cy = (li / CO) % CO, cz = li / (CO * CO);
     const int gx = tx * CO + cx, gy = ty * CO + cy, gz = tz * CO + cz;
     if (gx < Pc && gy < Pc && gz < Pc) fc[(size_t(gz) * Pc + gy) * Pc + gx] = Out[li];
@@ -1157,10 +1159,11 @@ void launch_cheb_first(hipStream_t s, int nb, const LevelOpT<T> &op, const T *f,
   const int K = seg_blocks(nb, per);
   hipLaunchKernelGGL(k_cheb_first<T>, dim3(nb * K), dim3(256), 0, s, op, K, f, x, c2);
 }
-template <class T, int PF, int PC, int R, int TE>
+template <class T, int PF, int PC, int R, int TE, int NT = 256>
 static void restrict_impl(hipStream_t s, int nb, const TransferT<T> &tr, const T *in, T *out) {
   const int tiles = (tr.nc + TE - 1) / TE;
-  hipLaunchKernelGGL((k_restrict<T, PF, PC, R, TE>), dim3(nb * tiles * tiles * tiles), dim3(256), 0, s, tr, in, out);
+  hipLaunchKernelGGL((k_restrict<T, PF, PC, R, TE, NT>), dim3(nb * tiles * tiles * tiles), dim3(NT), 0, s, tr, in,
+                     out);
 }
 template <class T, int PF, int PC, int R, int TE>
 static void prolong_impl(hipStream_t s, int nb, const TransferT<T> &tr, const T *in, T *out) {
@@ -1179,7 +1182,7 @@ int launch_transfer(hipStream_t s, int nb, const TransferT<T> &tr, const T *in, 
     if (restrict_) restrict_impl<T, 4, 3, 1, 2>(s, nb, tr, in, out);
     else prolong_impl<T, 4, 3, 1, 3>(s, nb, tr, in, out);
   } else if (tr.pf == 6 && tr.pc == 3 && tr.r == 1) {
-    if (restrict_) restrict_impl<T, 6, 3, 1, 1>(s, nb, tr, in, out);
+    if (restrict_) restrict_impl<T, 6, 3, 1, 2, 384>(s, nb, tr, in, out);
     else prolong_impl<T, 6, 3, 1, 2>(s, nb, tr, in, out);
   } else if (tr.pf == 3 && tr.pc == 1 && tr.r == 1) {
     if (restrict_) restrict_impl<T, 3, 1, 1, 4>(s, nb, tr, in, out);
