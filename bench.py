@@ -30,6 +30,11 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 OPERATOR_FLOP_PER_DOF = 98.0
 
 
+# screen family -> (support, degree q); mesh order p = q + 2
+SCREENS = {"one-q2": ("one", 2), "one-q3": ("one", 3), "one-q4": ("one", 4),
+           "27-q1": ("27", 1), "27-q2": ("27", 2), "27-q3": ("27", 3), "27-q4": ("27", 4)}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +56,11 @@ def parse():
                     help="mesh solve: multigrid PCG (the method's default) or the exact periodic solve")
     ap.add_argument("--boundary", choices=["periodic", "grounded", "insulated"], default="periodic",
                     help="the periodic cube, or the boxes of Section 2.6 (with --solver exact)")
+    ap.add_argument("--screen", choices=sorted(SCREENS), default="one-q3",
+                    help="screen family: the one-element screens of degree 2..4 or the 27-element screens of degree "
+                         "1..4 (one-q3 is the method's default; the others skip the variants and the CPU baseline)")
+    ap.add_argument("--n-sr", type=int, choices=[1, 2, 3], default=3, help="near block radius (block of 2 n_sr + 1 "
+                    "elements per axis)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mixed-precision, clustered and batched measurements reported beside the FP64 line")
@@ -274,7 +284,7 @@ def stream_copy_gbs():
     return 2 * 2**30 / (best * 1e-3) / 1e9
 
 
-def kernel_rooflines(prof, steps, mixed, near_fft=False):
+def kernel_rooflines(prof, steps, mixed, near_fft=False, p=5, moments=8, default_screen=True):
     def kern(slot, bound):
         s = prof[slot]
         if s["count"] == 0 or s["ms"] <= 0:
@@ -298,13 +308,18 @@ def kernel_rooflines(prof, steps, mixed, near_fft=False):
                    "k_pair (near-pair sum)": kern("pair", "alu"),
                    "k_apply p=5 (fine-level operator)": kern("fine_apply", "hbm"),
                    "transposed near field (FFTs + spectrum product)": kern("adj_near", "hbm")}
-    else:
+    elif default_screen:
         kernels = {"k_psi (near-screen field)": kern("near", "mfma"),
                    "k_pair (near-pair sum)": kern("pair", "alu"),
                    "k_apply p=5 (fine-level operator)": kern("fine_apply", "hbm"),
                    "k_adj_moments (transposed near field)": kern("adj_near", "alu")}
+    else:   # the other screen families: near field on the matrix cores from 8 moments, adjoint from 27
+        kernels = {f"near-screen field, {moments} moments": kern("near", "mfma" if moments >= 8 else "alu"),
+                   "k_pair (near-pair sum)": kern("pair", "alu"),
+                   f"k_apply p={p} (fine-level operator)": kern("fine_apply", "hbm"),
+                   f"moment adjoint, {moments} moments": kern("adj_near", "mfma" if moments >= 27 else "alu")}
     if mixed:
-        kernels["k_apply<float> p=5 (fine-level preconditioner operator)"] = kern("fine_apply_f32", "hbm")
+        kernels[f"k_apply<float> p={p} (fine-level preconditioner operator)"] = kern("fine_apply_f32", "hbm")
     return {k: v for k, v in kernels.items() if v}
 
 
@@ -323,6 +338,9 @@ def measure(name, precision, steps, warmup, forces=True, graph=False, solver=0, 
     tx = torch.from_numpy(x).to(dev)
     tQ = torch.from_numpy(Q).to(dev)
     q = opts.pop("q", 3)
+    sup = opts.get("support", fp.SUPPORT_ONE)
+    nsr = opts.get("n_sr", 3)
+    moments = (q + 1 if sup == fp.SUPPORT_27 else q - 1) ** 3
     ctx = fp.Context(L, counts if len(counts) > 1 else counts[0], n, q=q,
                      precision=fp.PRECISION_MIXED if mixed else fp.PRECISION_FP64, use_graph=1 if graph else 0,
                      solver=solver, near_field=near_field, **opts)
@@ -350,7 +368,8 @@ def measure(name, precision, steps, warmup, forces=True, graph=False, solver=0, 
     res = {
         "workload": label, "precision": precision, "counts": counts, "n": n, "L": L, "ms_per_step": ms,
         "pairs": st["near_pairs"], "value": st["near_pairs"] / (ms * 1e-3), "stats": st,
-        "kernels": kernel_rooflines(prof, steps, mixed, bool(st["near_fft"])),
+        "kernels": kernel_rooflines(prof, steps, mixed, bool(st["near_fft"]), p=q + 2, moments=moments,
+                                    default_screen=(sup == fp.SUPPORT_ONE and q == 3)),
         "stages_ms_per_step": {k: v["ms"] / steps for k, v in prof.items() if not k.startswith("fine_apply")},
         "out": {k: v.detach().cpu().numpy() for k, v in out.items()},
         "x": x, "Q": Q, "mg_rtol": ctx.options.mg_rtol, "prof": prof, "steps": steps,
@@ -528,9 +547,13 @@ def main():
     if bc and args.solver != "exact":
         print(json.dumps({"error": "the boxes of Section 2.6 need --solver exact"}))
         sys.exit(2)
+    support, q = SCREENS[args.screen]
+    default_screen = args.screen == "one-q3" and args.n_sr == 3
+    screen_opts = {} if default_screen else {"q": q, "support": 1 if support == "27" else 0, "n_sr": args.n_sr,
+                                             "table_box": 2 * args.n_sr + 9}
     r = measure(args.workload, args.precision, args.steps, args.warmup, forces,
                 solver={"mg": 0, "exact": 1}[args.solver], near_field={"auto": 0, "direct": 1, "fft": 2}[args.near],
-                boundary=bc)
+                boundary=bc, **screen_opts)
     mixed = args.precision == "mixed"
     kernels = r["kernels"]
     practical = stream_copy_gbs() if not args.no_variants else None   # kept out of profiled runs
@@ -538,13 +561,13 @@ def main():
         if v["bound"] == "hbm" and practical:
             v["practical_peak"] = practical
             v["frac_practical"] = v["achieved"] / practical
-    op = kernels.get("k_apply p=5 (fine-level operator)")
+    op = kernels.get(f"k_apply p={q + 2} (fine-level operator)")
     if op:
         # the operator's own arithmetic: sum-factorised Kronecker-sum apply,
         # 7 one-dimensional band passes of 7 multiply-adds per node on average
         # (6 taps inside an element, 11 at a vertex) = 98 FLOP per DOF
         # with forces every fine-level launch covers the forward and the adjoint system
-        dofs = (5 * r["n"]) ** 3 * len(r["counts"]) * (2 if forces else 1)
+        dofs = ((q + 2) * r["n"]) ** 3 * len(r["counts"]) * (2 if forces else 1)
         tf = OPERATOR_FLOP_PER_DOF * dofs / (op["avg_launch_ms"] * 1e-3) / 1e12
         op["flop_achieved"] = tf
         op["flop_peak"] = PEAK_FP64_TFLOPS   # the PCG operator is float64 in both precisions
@@ -575,8 +598,9 @@ def main():
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": r["workload"], "N": int(sum(r["counts"])), "configurations": len(r["counts"]),
-                   "elements": f"{r['n']}^3", "L": r["L"], "screen": "one-element q=3", "mesh_order": 5,
-                   "near_block": "7^3", "outputs": "U, F" if forces else "Phi, U", "precision": args.precision,
+                   "elements": f"{r['n']}^3", "L": r["L"],
+                   "screen": f"{'27-element' if support == '27' else 'one-element'} q={q}", "mesh_order": q + 2,
+                   "near_block": f"{2 * args.n_sr + 1}^3", "outputs": "U, F" if forces else "Phi, U", "precision": args.precision,
                    "mg_rtol": r["mg_rtol"], "solver": "multigrid PCG" if args.solver == "mg" else "exact",
                    "boundary": args.boundary,
                    "near_pairs_per_step": r["pairs"]},
@@ -591,7 +615,8 @@ def main():
         "pair_variant": variant_summary(r)["pair_variant"],
         "U": [float(u) for u in np.atleast_1d(r["out"]["U"])][:4],
     }
-    if not args.no_variants and forces and args.workload == "uniform-1M-n64" and not mixed and not bc:
+    if not args.no_variants and forces and args.workload == "uniform-1M-n64" and not mixed and not bc \
+            and default_screen:
         variants = {}
         m = measure("uniform-1M-n64", "mixed", 3, 1)
         variants["mixed uniform-1M-n64"] = variant_summary(m, r)
@@ -645,7 +670,10 @@ def main():
         out["hbm_stages"] = hbm_stage_rooflines()
         if not args.no_sweep:
             out["screen_sweep"] = screen_sweep()
-    if not args.no_cpu_baseline and args.boundary == "periodic":
+    if not default_screen and args.boundary == "periodic" and forces and not mixed \
+            and args.workload in ("uniform-1M-n64", "clustered-1M-n64"):
+        out["method_error_vs_ewald_full_size"] = ewald_error_full_size(r, support, q, args.n_sr)
+    if not args.no_cpu_baseline and args.boundary == "periodic" and default_screen:
         out["method_error_vs_ewald"] = method_error_vs_ewald()
         if args.workload in ("uniform-1M-n64", "clustered-1M-n64") and forces and not mixed:
             out["method_error_vs_ewald_full_size"] = ewald_error_full_size(r)
