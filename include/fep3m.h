@@ -205,7 +205,8 @@ typedef struct {
                             solve; 0: every launch on the caller's stream      */
   int32_t support;       /* FEP3M_SUPPORT_* (default ONE).  Every family but the
                             one-element q = 3 screen runs in float64 with the
-                            direct near field (vector units); create returns
+                            direct near field (matrix cores from 8 moments per
+                            element, vector units for one); create returns
                             FEP3M_ERR_UNSUPPORTED for precision = MIXED or
                             near_field = FFT there, and for element orders
                             above 6 (one-element q = 5, 6)                     */
