@@ -97,17 +97,23 @@ def test_family_ragged_and_batch(torch, q, support):
             assert _rel(out[k][sl].cpu().numpy(), one[k].cpu().numpy()) < 1e-12, (b_, k)
 
 
-@pytest.mark.parametrize("q,support", [(1, "27"), (2, "27"), (3, "27"), (4, "one")])
+@pytest.mark.parametrize("q,support", [(1, "27"), (2, "27"), (3, "27"), (4, "27"), (4, "one")])
 def test_family_full_size_against_oracle(torch, q, support):
     """Screen families at the benchmark's full size (uniform-1M-n64, 7^3
     near block, default options: multigrid at 1e-7, the matrix-core near
     field and moment adjoint, the separable load and lambda passes of the
     27-element screens): 27-element q = 1 (order-3 mesh, the direct
-    8-moment adjoint), q = 2, 3 and one-element q = 4 (order-6 mesh); Phi, F and dU/dQ on 256
+    8-moment adjoint), q = 2, 3, 4 (q = 4: 125 moments, order-6 mesh) and
+    one-element q = 4 (order-6 mesh); Phi, F and dU/dQ on 256
     sampled charges and the mesh potential on 512 sampled nodes against the
     oracle's values stored by tests/golden/make_family_fixtures.py; U
     through its definition on the GPU's own Phi.  Gate 1e-6 (the solver
-    tolerance moves the results by about 1e-8)."""
+    tolerance moves the results by about 1e-8).  The 27-element q = 4
+    screens' mesh potential is about 100 times larger than the others'
+    (max |phi| 9e3 against 70-90) and cancels against the near-screen
+    field, so the default tolerance moves their Phi by about 3e-7; that
+    family is solved to 1e-11 here and gated at 1e-9 (measured 2e-11),
+    which shows the difference is the solver's and not the kernels'."""
     import json
     import math
     import os
@@ -118,7 +124,8 @@ def test_family_full_size_against_oracle(torch, q, support):
     x, Q = workloads.make(ref["workload"])
     n = ref["n"]
     print(f"family full size: support {support} q={q} N={len(Q)} n={n}", flush=True)
-    ctx = fp.Context(1.0, len(Q), n, q=q, support=SUP[support])
+    tight = (q, support) == (4, "27")
+    ctx = fp.Context(1.0, len(Q), n, q=q, support=SUP[support], **({"mg_rtol": 1e-11} if tight else {}))
     tx, tQ = torch.from_numpy(x).cuda(), torch.from_numpy(Q).cuda()
     ctx.energy_forces(tx, tQ, dUdQ=True, Phi=True)          # first call: tuning
     out = ctx.energy_forces(tx, tQ, dUdQ=True, Phi=True)
@@ -134,4 +141,4 @@ def test_family_full_size_against_oracle(torch, q, support):
     errs["U"] = abs(float(out["U"].item()) - Uq) / abs(Uq)
     print(f"family full size {support} q={q}:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     for k, v in errs.items():
-        assert v < 1e-6, (k, v)
+        assert v < (1e-9 if tight else 1e-6), (k, v)
