@@ -2,16 +2,16 @@
 charges, and its mesh potential at sampled nodes, for the uniform-1M-n64
 workload (10^6 charges, 64^3 elements, 7^3 near block) with the
 27-element screens of Section 2.1 of degree q = 1 to 4 and the
-one-element screen of degree 4 (Section 5), to
+one-element screens of degree 2 and 4 (Section 5), to
 tests/golden/family_q<q>_<support>_uniform-1M-n64.json, for the full-size
 GPU parity tests of the screen families.  Calls only the oracle
 (oracle.adjoint.energy_forces with targets, pinned in
 tests/test_oracle_screens27.py and tests/test_oracle_adjoint.py) on the
 seeded inputs of workloads.py.
 
-    python tests/golden/make_family_fixtures.py [q:support ...]   (default 1:27 2:27 3:27 4:27 4:one)
+    python tests/golden/make_family_fixtures.py [q:support ...]   (default 1:27 2:27 3:27 4:27 2:one 4:one)
 
-About 0.5, 1, 2, 3.5 and 3 minutes on 8 cores."""
+About 0.5, 1, 2, 3.5, 0.2 and 3 minutes on 8 cores."""
 from __future__ import annotations
 
 import json
@@ -53,6 +53,6 @@ def make(q, support):
 
 
 if __name__ == "__main__":
-    for spec in (sys.argv[1:] or ["1:27", "2:27", "3:27", "4:27", "4:one"]):
+    for spec in (sys.argv[1:] or ["1:27", "2:27", "3:27", "4:27", "2:one", "4:one"]):
         q, support = spec.split(":")
         make(int(q), support)

@@ -97,14 +97,15 @@ def test_family_ragged_and_batch(torch, q, support):
             assert _rel(out[k][sl].cpu().numpy(), one[k].cpu().numpy()) < 1e-12, (b_, k)
 
 
-@pytest.mark.parametrize("q,support", [(1, "27"), (2, "27"), (3, "27"), (4, "27"), (4, "one")])
+@pytest.mark.parametrize("q,support", [(1, "27"), (2, "27"), (3, "27"), (4, "27"), (2, "one"), (4, "one")])
 def test_family_full_size_against_oracle(torch, q, support):
     """Screen families at the benchmark's full size (uniform-1M-n64, 7^3
     near block, default options: multigrid at 1e-7, the matrix-core near
     field and moment adjoint, the separable load and lambda passes of the
     27-element screens): 27-element q = 1 (order-3 mesh, the direct
-    8-moment adjoint), q = 2, 3, 4 (q = 4: 125 moments, order-6 mesh) and
-    one-element q = 4 (order-6 mesh); Phi, F and dU/dQ on 256
+    8-moment adjoint), q = 2, 3, 4 (q = 4: 125 moments, order-6 mesh),
+    one-element q = 2 (one moment: the table sums on the vector units) and
+    q = 4 (order-6 mesh); Phi, F and dU/dQ on 256
     sampled charges and the mesh potential on 512 sampled nodes against the
     oracle's values stored by tests/golden/make_family_fixtures.py; U
     through its definition on the GPU's own Phi.  Gate 1e-6 (the solver
