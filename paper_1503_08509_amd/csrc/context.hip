@@ -194,7 +194,7 @@ struct fep3m_ctx {
   int *flags = nullptr, *maxcount = nullptr;
   unsigned long long *paircount = nullptr;
   double *C = nullptr, *Wel = nullptr, *phip_s = nullptr, *phim_s = nullptr, *phi_s = nullptr;
-  double *lsep = nullptr;   // scratch of the separable load and adjoint of the 27-element screens (periodic)
+  double *lsep = nullptr;   // scratch of the separable load and adjoint passes (periodic screen families)
   // mixed precision: float32 tables, element field, local coordinates
   float *Tf = nullptr, *Welf = nullptr;
   float4 *su = nullptr;
@@ -511,7 +511,7 @@ void fep3m_ctx::build(double L_, const std::vector<int64_t> &Ns, int n_, int q_,
   maxcount = alloc<int>(4, "max count");
   paircount = alloc<unsigned long long>(2, "pair count");
   C = alloc<double>(size_t(nb) * M * na, "moments");
-  if (generic && !box && span == 3) lsep = alloc<double>(load_sep_scratch(nb, n, p, nl), "load passes");
+  if (generic && !box && (span == 3 || nl > 1)) lsep = alloc<double>(load_sep_scratch(nb, n, p, nl), "load passes");
   if (!mixed) {
     Wel = alloc<double>(size_t(nb) * M * (p + 1) * (p + 1) * (p + 1), "element field");
   } else {

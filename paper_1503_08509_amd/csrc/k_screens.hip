@@ -417,31 +417,32 @@ __global__ __launch_bounds__(AdjNearShape<NL * NL * NL>::THREADS) void k_adj_nea
 // nodes of lambda * gw[ax][jx] gw[ay][jy] gw[az][jz], one thread per
 // (element, moment), contracted along x, then y, then z.  box: lambda on the
 // (PO n + 1)^3 nodes of the box (SPAN 1, so no index leaves it).
-// The same load for the 27-element screens (SPAN 3, periodic), separably:
-// b = 4 pi (W_z (x) W_y (x) W_x) C, W mapping (source element s, moment
-// index a) of one axis to the nodes g of the source's support with weight
-// gw[a][g - p (s - 1)].  Three passes, each a 1-D gather over the 3 or 4
-// sources of a node (every moment of a source element is read once per
-// pass instead of once per node of its support):
+// The same load separably (periodic; SPAN 3: the 27-element screens, SPAN
+// 1: the one-element screens): b = 4 pi (W_z (x) W_y (x) W_x) C, W mapping
+// (source element s, moment index a) of one axis to the nodes g of the
+// source's support with weight gw[a][g - p (s - H)], H = (SPAN - 1) / 2.
+// Three passes, each a 1-D gather over the SPAN or SPAN + 1 sources of a
+// node (every moment of a source element is read once per pass instead of
+// once per node of its support):
 //   x:  T1[c][sz][sy][az][ay][gx] = sum_{sx, ax} W_x C[c][sz][sy][sx][az][ay][ax]
 //   y:  T2[c][sz][az][gy][gx]     = sum_{sy, ay} W_y T1
 //   z:  b[c][gz][gy][gx]          = 4 pi sum_{sz, az} W_z T2  (with block partials of b)
-template <int PO, int NL>
+template <int PO, int SPAN, int NL>
 __global__ __launch_bounds__(256) void k_load_sx(int nb, int n, const double *__restrict__ C,
                                                  const double *__restrict__ gw, double *__restrict__ T1) {
-  constexpr int NA = NL * NL * NL, NL2 = NL * NL, KS = 3 * PO + 1;
+  constexpr int NA = NL * NL * NL, NL2 = NL * NL, KS = SPAN * PO + 1;
   const int P = PO * n;
   const size_t rows = size_t(nb) * n * n;   // (c, sz, sy)
   for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < rows * P; t += size_t(gridDim.x) * blockDim.x) {
     const int gx = int(t % P);
     const size_t row = t / P;
-    int sx[4], jx[4];
-    const int cx = axis_sources<PO, 3>(gx, n, false, sx, jx);
+    int sx[SPAN + 1], jx[SPAN + 1];
+    const int cx = axis_sources<PO, SPAN>(gx, n, false, sx, jx);
     double acc[NL2];
 #pragma unroll
     for (int q = 0; q < NL2; ++q) acc[q] = 0.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < SPAN + 1; ++i) {
       if (i >= cx) break;
       double w[NL];
 #pragma unroll
@@ -460,23 +461,23 @@ __global__ __launch_bounds__(256) void k_load_sx(int nb, int n, const double *__
   }
 }
 
-template <int PO, int NL>
+template <int PO, int SPAN, int NL>
 __global__ __launch_bounds__(256) void k_load_sy(int nb, int n, const double *__restrict__ gw,
                                                  const double *__restrict__ T1, double *__restrict__ T2) {
-  constexpr int NL2 = NL * NL, KS = 3 * PO + 1;
+  constexpr int NL2 = NL * NL, KS = SPAN * PO + 1;
   const int P = PO * n;
   const size_t P2 = size_t(P) * P;
   const size_t total = size_t(nb) * n * P2;   // (c, sz, gy, gx)
   for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += size_t(gridDim.x) * blockDim.x) {
     const int gx = int(t % P), gy = int((t / P) % P);
     const size_t csz = t / P2;   // c n + sz
-    int sy[4], jy[4];
-    const int cy = axis_sources<PO, 3>(gy, n, false, sy, jy);
+    int sy[SPAN + 1], jy[SPAN + 1];
+    const int cy = axis_sources<PO, SPAN>(gy, n, false, sy, jy);
     double acc[NL];
 #pragma unroll
     for (int az = 0; az < NL; ++az) acc[az] = 0.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < SPAN + 1; ++i) {
       if (i >= cy) break;
       const double *r = T1 + ((csz * n + sy[i]) * NL2) * P + gx;
 #pragma unroll
@@ -492,11 +493,11 @@ __global__ __launch_bounds__(256) void k_load_sy(int nb, int n, const double *__
   }
 }
 
-template <int PO, int NL>
+template <int PO, int SPAN, int NL>
 __global__ __launch_bounds__(256) void k_load_sz(int n, int K, const double *__restrict__ gw,
                                                  const double *__restrict__ T2all, double *__restrict__ ball,
                                                  double *__restrict__ partial) {
-  constexpr int KS = 3 * PO + 1;
+  constexpr int KS = SPAN * PO + 1;
   __shared__ double red[8];
   const int P = PO * n;
   const size_t P2 = size_t(P) * P, per = P2 * P;
@@ -507,11 +508,11 @@ __global__ __launch_bounds__(256) void k_load_sz(int n, int K, const double *__r
   for (size_t g = size_t(kb) * blockDim.x + threadIdx.x; g < per; g += size_t(K) * blockDim.x) {
     const size_t gxy = g % P2;
     const int gz = int(g / P2);
-    int sz[4], jz[4];
-    const int cz = axis_sources<PO, 3>(gz, n, false, sz, jz);
+    int sz[SPAN + 1], jz[SPAN + 1];
+    const int cz = axis_sources<PO, SPAN>(gz, n, false, sz, jz);
     double v = 0.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < SPAN + 1; ++i) {
       if (i >= cz) break;
 #pragma unroll
       for (int az = 0; az < NL; ++az) v += gw[az * KS + jz[i]] * T2[(size_t(sz[i]) * NL + az) * P2 + gxy];
@@ -553,17 +554,17 @@ __global__ __launch_bounds__(256) void k_adj_lam_g(int n, int MT, int box, const
   }
 }
 
-// The lambda part of the moment adjoint of the 27-element screens, the
-// transpose of the separable load (periodic): A += 4 pi (W_z (x) W_y (x) W_x)^T
-// lam, one axis at a time through the load's scratch:
-//   z:  U1[c][sz][az][gy][gx]     = sum_kz gw[az][kz] lam[p (sz - 1) + kz][gy][gx]
-//   y:  U2[c][sz][sy][az][ay][gx] = sum_ky gw[ay][ky] U1[c][sz][az][p (sy - 1) + ky][gx]
-//   x:  A[c][sz][sy][sx][az][ay][ax] += 4 pi sum_kx gw[ax][kx] U2[c][sz][sy][az][ay][p (sx - 1) + kx]
+// The lambda part of the moment adjoint, the transpose of the separable
+// load (periodic): A += 4 pi (W_z (x) W_y (x) W_x)^T lam, one axis at a time
+// through the load's scratch:
+//   z:  U1[c][sz][az][gy][gx]     = sum_kz gw[az][kz] lam[p (sz - H) + kz][gy][gx]
+//   y:  U2[c][sz][sy][az][ay][gx] = sum_ky gw[ay][ky] U1[c][sz][az][p (sy - H) + ky][gx]
+//   x:  A[c][sz][sy][sx][az][ay][ax] += 4 pi sum_kx gw[ax][kx] U2[c][sz][sy][az][ay][p (sx - H) + kx]
 // (node indices wrap modulo P = p n).
-template <int PO, int NL>
+template <int PO, int SPAN, int NL>
 __global__ __launch_bounds__(256) void k_adjl_z(int nb, int n, const double *__restrict__ lamall,
                                                 const double *__restrict__ gw, double *__restrict__ U1) {
-  constexpr int KS = 3 * PO + 1;
+  constexpr int KS = SPAN * PO + 1;
   const int P = PO * n;
   const size_t P2 = size_t(P) * P;
   const size_t total = size_t(nb) * n * P2;   // (c, sz, gy, gx)
@@ -572,7 +573,7 @@ __global__ __launch_bounds__(256) void k_adjl_z(int nb, int n, const double *__r
     const int sz = int(csz % n);
     const size_t c = csz / n;
     const double *lam = lamall + c * P2 * P + gxy;
-    const int z0 = PO * (sz - 1);
+    const int z0 = PO * (sz - (SPAN - 1) / 2);
     double acc[NL];
 #pragma unroll
     for (int az = 0; az < NL; ++az) acc[az] = 0.0;
@@ -587,10 +588,10 @@ __global__ __launch_bounds__(256) void k_adjl_z(int nb, int n, const double *__r
   }
 }
 
-template <int PO, int NL>
+template <int PO, int SPAN, int NL>
 __global__ __launch_bounds__(256) void k_adjl_y(int nb, int n, const double *__restrict__ gw,
                                                 const double *__restrict__ U1, double *__restrict__ U2) {
-  constexpr int KS = 3 * PO + 1, NL2 = NL * NL;
+  constexpr int KS = SPAN * PO + 1, NL2 = NL * NL;
   const int P = PO * n;
   const size_t P2 = size_t(P) * P;
   const size_t total = size_t(nb) * n * n * P;   // (c, sz, sy, gx)
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(256) void k_adjl_y(int nb, int n, const double *__r
     const size_t row = t / P;   // (c n + sz) n + sy
     const int sy = int(row % n);
     const size_t csz = row / n;
-    const int y0 = PO * (sy - 1);
+    const int y0 = PO * (sy - (SPAN - 1) / 2);
 #pragma unroll
     for (int az = 0; az < NL; ++az) {
       const double *u = U1 + (csz * NL + az) * P2 + gx;
@@ -618,10 +619,10 @@ __global__ __launch_bounds__(256) void k_adjl_y(int nb, int n, const double *__r
   }
 }
 
-template <int PO, int NL>
+template <int PO, int SPAN, int NL>
 __global__ __launch_bounds__(256) void k_adjl_x(int nb, int n, const double *__restrict__ gw,
                                                 const double *__restrict__ U2, double *__restrict__ A) {
-  constexpr int KS = 3 * PO + 1, NL2 = NL * NL, NA = NL2 * NL;
+  constexpr int KS = SPAN * PO + 1, NL2 = NL * NL, NA = NL2 * NL;
   const int P = PO * n;
   const size_t total = size_t(nb) * n * n * n * NL2;   // (c, sz, sy, q = (az, ay), sx)
   for (size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += size_t(gridDim.x) * blockDim.x) {
@@ -630,7 +631,7 @@ __global__ __launch_bounds__(256) void k_adjl_x(int nb, int n, const double *__r
     const int q = int(rq % NL2);
     const size_t row = rq / NL2;
     const double *u = U2 + rq * P;
-    const int x0 = PO * (sx - 1);
+    const int x0 = PO * (sx - (SPAN - 1) / 2);
     double acc[NL];
 #pragma unroll
     for (int ax = 0; ax < NL; ++ax) acc[ax] = 0.0;
@@ -686,16 +687,16 @@ static int load_g_nl(hipStream_t s, int nb, int n, int nl, int K, int box, const
   return 0;
 }
 
-template <int PO>
+template <int PO, int SPAN>
 static int load_sep_nl(hipStream_t s, int nb, int n, int nl, int K, const double *C, const double *gw, double *t1,
                        double *t2, double *b, double *partial) {
   const size_t P = size_t(PO) * n;
   auto grid = [](size_t count) { return int(std::min<size_t>((count + 255) / 256, 65536)); };
   const int g1 = grid(size_t(nb) * n * n * P), g2 = grid(size_t(nb) * n * P * P);
 #define CALL(NL)                                                                                         \
-  hipLaunchKernelGGL((k_load_sx<PO, NL>), dim3(g1), dim3(256), 0, s, nb, n, C, gw, t1);                \
-  hipLaunchKernelGGL((k_load_sy<PO, NL>), dim3(g2), dim3(256), 0, s, nb, n, gw, t1, t2);               \
-  hipLaunchKernelGGL((k_load_sz<PO, NL>), dim3(nb * K), dim3(256), 0, s, n, K, gw, t2, b, partial)
+  hipLaunchKernelGGL((k_load_sx<PO, SPAN, NL>), dim3(g1), dim3(256), 0, s, nb, n, C, gw, t1);          \
+  hipLaunchKernelGGL((k_load_sy<PO, SPAN, NL>), dim3(g2), dim3(256), 0, s, nb, n, gw, t1, t2);         \
+  hipLaunchKernelGGL((k_load_sz<PO, SPAN, NL>), dim3(nb * K), dim3(256), 0, s, n, K, gw, t2, b, partial)
   FEP3M_NL_SWITCH(nl, CALL)
 #undef CALL
   return 0;
@@ -711,14 +712,19 @@ int launch_load_g(hipStream_t s, int nb, int n, int p, int span, int nl, int box
   if (box && span != 1) return -1;   // a box holds the one-element screens only
   const int P = p * n + (box ? 1 : 0);
   const int K = seg_blocks(nb, size_t(P) * P * P);
-  if (span == 3 && sep) {   // separable passes through the scratch T1, T2
+  // separable passes through the scratch T1, T2 (one moment per element: the gather reads one value per source)
+  if ((span == 3 || (span == 1 && nl > 1)) && sep && !box) {
     double *t1 = sep, *t2 = sep + size_t(nb) * n * n * size_t(P) * nl * nl;
     int r = -1;
-    switch (p) {
-      case 3: r = load_sep_nl<3>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
-      case 4: r = load_sep_nl<4>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
-      case 5: r = load_sep_nl<5>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
-      case 6: r = load_sep_nl<6>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
+    switch (10 * p + span) {
+      case 31: r = load_sep_nl<3, 1>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
+      case 41: r = load_sep_nl<4, 1>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
+      case 51: r = load_sep_nl<5, 1>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
+      case 61: r = load_sep_nl<6, 1>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
+      case 33: r = load_sep_nl<3, 3>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
+      case 43: r = load_sep_nl<4, 3>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
+      case 53: r = load_sep_nl<5, 3>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
+      case 63: r = load_sep_nl<6, 3>(s, nb, n, nl, K, C, gw, t1, t2, b, partial); break;
       default: return -1;
     }
     return r < 0 ? -1 : K;
@@ -785,16 +791,16 @@ static int adj_g_nl(hipStream_t s, int nb, int n, int nsr, int nl, int box, cons
                     const double *lam, const double *gw, double *A, double *sep) {
   if (nsr < 1 || nsr > 3) return -1;
   const int MT = nb * n * n * n;
-  if (SPAN == 3 && sep && !box) {   // separable lambda part through the load's scratch
+  if (sep && !box && (SPAN == 3 || nl > 1)) {   // separable lambda part through the load's scratch
     const size_t P = size_t(PO) * n;
     double *u2 = sep, *u1 = sep + size_t(nb) * n * n * P * nl * nl;
     const int gz = grid_for_count(int64_t(nb) * n * P * P), gy = grid_for_count(int64_t(nb) * n * n * P);
     const int gx = grid_for_count(int64_t(MT) * nl * nl);
 #define CALL(NL)                                                                                  \
   adj_near_launch<PO, NL>(s, nb, n, nsr, box, gE, Tt, A);                                         \
-  hipLaunchKernelGGL((k_adjl_z<PO, NL>), dim3(gz), dim3(256), 0, s, nb, n, lam, gw, u1);         \
-  hipLaunchKernelGGL((k_adjl_y<PO, NL>), dim3(gy), dim3(256), 0, s, nb, n, gw, u1, u2);          \
-  hipLaunchKernelGGL((k_adjl_x<PO, NL>), dim3(gx), dim3(256), 0, s, nb, n, gw, u2, A)
+  hipLaunchKernelGGL((k_adjl_z<PO, SPAN, NL>), dim3(gz), dim3(256), 0, s, nb, n, lam, gw, u1);   \
+  hipLaunchKernelGGL((k_adjl_y<PO, SPAN, NL>), dim3(gy), dim3(256), 0, s, nb, n, gw, u1, u2);    \
+  hipLaunchKernelGGL((k_adjl_x<PO, SPAN, NL>), dim3(gx), dim3(256), 0, s, nb, n, gw, u2, A)
     FEP3M_NL_SWITCH(nl, CALL)
 #undef CALL
     return 0;

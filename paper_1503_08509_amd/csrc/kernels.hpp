@@ -101,7 +101,7 @@ int launch_moments_g(hipStream_t s, int nb, int n, int nl, int64_t N, const int 
 // configuration; span 1 only); a null phi makes the near field W = -Psi.
 int launch_load_g(hipStream_t s, int nb, int n, int p, int span, int nl, int box, const double *C, const double *gw,
                   double *b, double *partial, double *sep = nullptr);
-// scratch (doubles) of the separable load of the 27-element screens (sep above)
+// scratch (doubles) of the separable load and lambda passes (periodic screen families; sep above)
 size_t load_sep_scratch(int nb, int n, int p, int nl);
 int launch_psi_g(hipStream_t s, int nb, int n, int nsr, int p, int nl, int box, const double *C, const double *T,
                  const double *phi, double *W);
